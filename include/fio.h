@@ -1,0 +1,177 @@
+/*
+ * fio.h -- C ABI of the MI355X (gfx950) approximate-inverse library for discrete
+ * Fourier integral operators (Feliu-Faba and Ying, "Approximate inversion of
+ * discrete Fourier integral operators").
+ *
+ * Problem (section 1, equations eq:X_domain, eq:freq_domain, eq3, eq6): grids
+ *   X     = { x = (k_1..k_d)/n : 0 <= k_i < n },
+ *   Omega = { xi = (j_1..j_d)   : -n/2 <= j_i < n/2 },   n even, N = n^d,
+ * and the dense N x N matrix K with K_ij = a(x_i, xi_j) exp(2 pi i Phi(x_i, xi_j)),
+ * so that u = K fhat with fhat = F f the normalised DFT.  Points are numbered
+ * lexicographically with the first coordinate slowest ("natural order").
+ *
+ * The library builds, on the host in FP64, the butterfly factorization
+ * Kd = U_L C_{L-1}..C_{lm} D H*_{lm}..H*_{1} V*_L of K (section 2, eq_BFF_fact),
+ * a hierarchical representation Sd of S = Kd^* Kd by peeling (section 3), and the
+ * inverse factors Gd = R_L..R_1 A_0^{-1} R_1^*..R_L^* of Sd (section 4,
+ * eqAinv_1d / eqAinv_2d).  The factors are uploaded to one GPU, and every apply
+ * (Kd, Kd^*, Gd Kd^* ~ K^{-1}, eq:pseudoinv, section 5) runs in HIP kernels.
+ *
+ * Conventions shared by every entry point:
+ *  - Vectors are complex, interleaved (re, im): FIO_C64 = two floats, FIO_C128 =
+ *    two doubles.  A block of nrhs vectors is column-major N x nrhs with leading
+ *    dimension ld >= N (in elements), in natural order.  Vector buffers are
+ *    device pointers owned by the caller.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Applies are
+ *    asynchronous on that stream; they may use library-owned device workspace
+ *    that is sized for the largest nrhs seen (grown on demand), so calls on one
+ *    plan must not run concurrently on different streams.
+ *  - Every call returns an fio_status; nothing throws across the ABI.  On error
+ *    the outputs are unspecified, fio_last_error() gives a message (thread
+ *    local), and the plan stays valid unless the status is FIO_ERR_DEVICE.
+ */
+#ifndef FIO_H
+#define FIO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fio_plan_s *fio_plan;
+
+typedef enum {
+    FIO_OK = 0,
+    FIO_ERR_ARG = 1,            /* invalid argument                               */
+    FIO_ERR_NOMEM = 2,          /* host or device allocation failed               */
+    FIO_ERR_DEVICE = 3,         /* HIP runtime error                              */
+    FIO_ERR_NOT_HPD = 4,        /* a pivot block of the inverse was not HPD       */
+    FIO_ERR_NOT_CONVERGED = 5,  /* iterative solve did not reach its tolerance    */
+    FIO_ERR_UNSUPPORTED = 6,    /* request not supported by this plan             */
+    FIO_ERR_IO = 7              /* save/load failure                              */
+} fio_status;
+
+typedef enum { FIO_C64 = 0, FIO_C128 = 1 } fio_dtype;
+
+/* Operator selector of fio_apply: Kd (frequency -> space) or its adjoint. */
+typedef enum { FIO_OP_K = 0, FIO_OP_KH = 1 } fio_op;
+
+/* Phase functions of the paper's numerical section (section 6), a = 1. */
+typedef enum {
+    FIO_PHASE_LINEAR = 0,   /* Phi = x.xi (K = N F^*: exact identity checks)                */
+    FIO_PHASE_1D_EX1 = 1,   /* Phi = x xi + c(x)|xi|, c(x) = (2 + sin 2 pi x)/c_div  (Ex. 1) */
+    FIO_PHASE_2D_RADON = 2  /* Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),          (Ex. 3)
+                               c1 = (2 + sin 2pi x1 sin 2pi x2)/c_div,
+                               c2 = (2 + cos 2pi x1 cos 2pi x2)/c_div                     */
+} fio_phase_id;
+
+/* Build description.  Zero means "default" for every tuning field. */
+typedef struct {
+    int d;                  /* dimension, 1 or 2                                       */
+    int n;                  /* points per dimension: even power of two, N = n^d        */
+    fio_phase_id phase;
+    double c_div;           /* divisor of c(x) (Examples 1 and 3); 0 -> 16             */
+    double eps;             /* tolerance: peeling and inverse tolerances default to it */
+    double eps_bf;          /* butterfly tolerance; 0 -> eps/10                        */
+    double eps_peel;        /* peeling tolerance;   0 -> eps                           */
+    double eps_hif;         /* skeletonization tolerance; 0 -> eps                     */
+    int leaf_bf;            /* butterfly leaf side (points per dim); 0 -> 8 (1D), 4 (2D) */
+    int leaf_h;             /* hierarchical-matrix leaf side; 0 -> 64 (1D), 8 (2D)     */
+    int oversample;         /* peeling oversampling c; 0 -> 10                         */
+    uint64_t seed;          /* seed of the peeling probes                              */
+    int device;             /* HIP device ordinal, or -1 for a host-only plan that can
+                               be saved and loaded later but not applied              */
+    int nthreads;           /* host threads for the build; 0 -> hardware concurrency  */
+} fio_problem;
+
+/* Build the factors of K and of the approximate inverse (Algorithm "alg",
+ * section 5: butterfly factorization, peeling, hierarchical inversion).
+ * Synchronous.  On success *out is a library-owned plan (free with fio_destroy).
+ * Errors: FIO_ERR_ARG (d, n, eps out of range), FIO_ERR_NOT_HPD, FIO_ERR_NOMEM,
+ * FIO_ERR_DEVICE. */
+fio_status fio_build(const fio_problem *p, fio_plan *out);
+
+/* y = Kd x (op = FIO_OP_K, eq_BFF_fact) or y = Kd^* x (op = FIO_OP_KH).
+ * x, y: device buffers of dtype, N x nrhs, leading dimension ld; x and y must
+ * not overlap.  Asynchronous on hip_stream. */
+fio_status fio_apply(fio_plan plan, fio_op op, fio_dtype dtype, const void *x, void *y,
+                     int64_t nrhs, int64_t ld, void *hip_stream);
+
+/* fhat = Gd Kd^* u, the approximate inverse of K (section 5, eq:pseudoinv).
+ * The small top-level block A_0^{-1} is applied in FP64 for both dtypes.
+ * u, fhat: device buffers of dtype, N x nrhs, leading dimension ld, no overlap.
+ * Asynchronous. */
+fio_status fio_inverse_apply(fio_plan plan, fio_dtype dtype, const void *u, void *fhat,
+                             int64_t nrhs, int64_t ld, void *hip_stream);
+
+/* y = Gd x, the approximate inverse of Kd^* Kd alone (section 4). */
+fio_status fio_gd_apply(fio_plan plan, fio_dtype dtype, const void *x, void *y,
+                        int64_t nrhs, int64_t ld, void *hip_stream);
+
+typedef enum {
+    FIO_SOLVE_DIRECT = 0,   /* fhat = Gd Kd^* u                                        */
+    FIO_SOLVE_REFINE = 1,   /* direct solve, then x += Gd Kd^*(u - Kd x) with the
+                               residual in FP64 (complex128 factors)                  */
+    FIO_SOLVE_PCG = 2       /* CG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5) */
+} fio_solve_mode;
+
+typedef struct {
+    fio_solve_mode mode;
+    double tol;             /* REFINE: stop when ||dx|| <= tol ||x|| for every column;
+                               PCG: stop when ||r|| <= tol ||Kd^* u||; 0 -> run maxit */
+    int maxit;              /* iteration cap (REFINE steps or PCG iterations)          */
+    int precondition;       /* PCG only: 1 -> Gd, 0 -> none (the paper's "Kd^* only") */
+} fio_solve_opts;
+
+typedef struct {
+    int iters;              /* iterations performed                                    */
+    double rel_resid;       /* max over columns of the last relative residual/correction */
+} fio_solve_info;
+
+/* Solve K fhat = u for nrhs columns.  u and out are complex128 device buffers
+ * (N x nrhs, leading dimension ld) for every mode; dtype selects the precision
+ * of the bulk factor applies: FIO_C64 (complex FP32 with FP32 accumulation,
+ * accuracy won back by the FP64 residual of REFINE) or FIO_C128 (FP64 throughout).
+ * If info is non-NULL the call synchronises hip_stream and fills it; with
+ * tol > 0 the call synchronises once per iteration to test convergence.
+ * Returns FIO_ERR_NOT_CONVERGED if tol > 0 was not met within maxit. */
+fio_status fio_solve(fio_plan plan, const fio_solve_opts *opts, fio_dtype dtype,
+                     const void *u, void *out, int64_t nrhs, int64_t ld,
+                     fio_solve_info *info, void *hip_stream);
+
+typedef struct {
+    int d, n, L, L_mid;            /* butterfly depth and middle level                 */
+    int n_stages;                  /* butterfly stages of one apply (L + 3)            */
+    int64_t bf_nnz;                /* nonzeros of all butterfly factors of Kd          */
+    int max_rank_bf;               /* largest butterfly rank                           */
+    int hif_levels;                /* skeletonization steps of Gd                      */
+    int64_t hif_nnz;               /* nonzeros of all T, L^{-1}, M blocks of Gd        */
+    int root_size;                 /* DOFs of the top-level block A_0                  */
+    int max_rank_h;                /* largest off-diagonal rank of Sd                  */
+    int64_t device_bytes;          /* device memory held by the factors                */
+    int64_t workspace_bytes;       /* device workspace per right-hand side             */
+    double build_seconds;          /* wall time of fio_build                           */
+} fio_plan_stats_t;
+
+fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);
+
+/* Per-stage layout of the butterfly apply (for measurement): for stage s of the
+ * forward apply, nnz of its blocks and the number of output blocks. */
+fio_status fio_stage_info(fio_plan plan, int stage, int64_t *nnz, int64_t *n_out_blocks,
+                          int *r_out, int *r_in, int *fan);
+
+/* Save the factors to a file / load them onto a device (device = -1: host only). */
+fio_status fio_save(fio_plan plan, const char *path);
+fio_status fio_load(const char *path, int device, fio_plan *out);
+
+void fio_destroy(fio_plan plan);
+
+/* Message of the last error on this thread ("" if none). */
+const char *fio_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIO_H */

@@ -1,0 +1,214 @@
+// Host construction of all factors (Algorithm "alg", section 5) and their file format.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+
+#include "plan.hpp"
+
+namespace fio {
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+fio_problem normalized_problem(const fio_problem &in) {
+    fio_problem p = in;
+    if (p.d != 1 && p.d != 2) fail(FIO_ERR_ARG, "d must be 1 or 2");
+    if (!is_pow2(p.n) || p.n % 2) fail(FIO_ERR_ARG, "n must be an even power of two");
+    if (!(p.eps > 0 && p.eps < 1)) fail(FIO_ERR_ARG, "eps must lie in (0, 1)");
+    if (p.phase == FIO_PHASE_1D_EX1 && p.d != 1) fail(FIO_ERR_ARG, "phase 1D_EX1 needs d = 1");
+    if (p.phase == FIO_PHASE_2D_RADON && p.d != 2) fail(FIO_ERR_ARG, "phase 2D_RADON needs d = 2");
+    if (p.phase < FIO_PHASE_LINEAR || p.phase > FIO_PHASE_2D_RADON) fail(FIO_ERR_ARG, "unknown phase");
+    if (p.c_div == 0) p.c_div = 16.0;
+    if (!(p.c_div > 0)) fail(FIO_ERR_ARG, "c_div must be positive");
+    if (p.eps_bf == 0) p.eps_bf = p.eps / 10;
+    if (p.eps_peel == 0) p.eps_peel = p.eps;
+    if (p.eps_hif == 0) p.eps_hif = p.eps;
+    if (!(p.eps_bf > 0 && p.eps_peel > 0 && p.eps_hif > 0)) fail(FIO_ERR_ARG, "tolerances must be positive");
+    if (p.leaf_bf == 0) p.leaf_bf = (p.d == 1) ? 8 : 4;
+    if (p.leaf_h == 0) p.leaf_h = (p.d == 1) ? 64 : 8;
+    if (p.oversample == 0) p.oversample = 10;
+    if (!is_pow2(p.leaf_bf) || p.leaf_bf > p.n / 2) fail(FIO_ERR_ARG, "leaf_bf must be a power of two <= n/2");
+    if (!is_pow2(p.leaf_h)) fail(FIO_ERR_ARG, "leaf_h must be a power of two");
+    if (p.d == 1 && p.leaf_h > p.n / 2) p.leaf_h = p.n / 2;
+    if (p.d == 2 && p.leaf_h > p.n / 2) p.leaf_h = p.n / 2;
+    if (p.oversample < 1) fail(FIO_ERR_ARG, "oversample must be positive");
+    return p;
+}
+
+void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu) {
+    auto t0 = std::chrono::steady_clock::now();
+    fio_problem p = normalized_problem(pin);
+    if (p.d == 2) fail(FIO_ERR_UNSUPPORTED, "2D inverse factors are not available in this build");
+    FioKernel K;
+    K.init(p.d, p.n, p.phase, p.c_div);
+    ButterflyOptions bo;
+    bo.eps = p.eps_bf;
+    bo.leaf = p.leaf_bf;
+    bo.nthreads = p.nthreads;
+    bo.seed = p.seed ^ 0xB0F1ULL;
+    Butterfly B = build_butterfly(K, bo);
+    out.d = p.d; out.n = p.n; out.N = B.N; out.L = B.L; out.Lm = B.Lm; out.m = B.m;
+    out.perm = K.to_nat;
+    out.prob = p;
+    std::vector<Stage> adj;
+    for (int s = (int)B.fwd.size() - 1; s >= 0; --s) adj.push_back(adjoint_stage(B.fwd[s]));
+    // Peeling needs products with A = Kd^* Kd (section 5): on the GPU when available.
+    BlockApply A;
+    if (gpu) {
+        A = gpu(B.fwd, adj);
+    } else {
+        const int64_t N = B.N;
+        const int nt = p.nthreads;
+        A = [&](const cd *x, cd *y, int nr) {
+            std::vector<cd> t((size_t)N * nr);
+            host_chain_apply(B.fwd, x, t.data(), nr, nt);
+            host_chain_apply(adj, t.data(), y, nr, nt);
+        };
+    }
+    PeelOptions po;
+    po.eps = p.eps_peel;
+    po.leaf = p.leaf_h;
+    po.oversample = p.oversample;
+    po.seed = p.seed ^ 0x9EE1ULL;
+    po.nthreads = p.nthreads;
+    out.hif = build_hif_1d(A, B.N, po, p.eps_hif);
+    out.fwd = std::move(B.fwd);
+    out.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- file format
+namespace {
+const char MAGIC[8] = {'F', 'I', 'O', 'P', 'L', 'A', 'N', '1'};
+
+struct W {
+    std::ofstream f;
+    template <class T> void v(const T &x) { f.write((const char *)&x, sizeof(T)); }
+    template <class T> void arr(const std::vector<T> &a) {
+        int64_t n = (int64_t)a.size();
+        v(n);
+        if (n) f.write((const char *)a.data(), sizeof(T) * n);
+    }
+    void mat(const Mat &M) {
+        v(M.m); v(M.n);
+        if (!M.a.empty()) f.write((const char *)M.a.data(), sizeof(cd) * M.a.size());
+    }
+};
+struct R {
+    std::ifstream f;
+    template <class T> void v(T &x) {
+        f.read((char *)&x, sizeof(T));
+        if (!f) fail(FIO_ERR_IO, "truncated plan file");
+    }
+    template <class T> void arr(std::vector<T> &a) {
+        int64_t n = 0;
+        v(n);
+        if (n < 0 || n > (int64_t)1 << 40) fail(FIO_ERR_IO, "corrupt plan file");
+        a.resize(n);
+        if (n) f.read((char *)a.data(), sizeof(T) * n);
+        if (!f) fail(FIO_ERR_IO, "truncated plan file");
+    }
+    void mat(Mat &M) {
+        int m = 0, n = 0;
+        v(m); v(n);
+        if (m < 0 || n < 0) fail(FIO_ERR_IO, "corrupt plan file");
+        M = Mat(m, n);
+        if (!M.a.empty()) f.read((char *)M.a.data(), sizeof(cd) * M.a.size());
+        if (!f) fail(FIO_ERR_IO, "truncated plan file");
+    }
+};
+}  // namespace
+
+void save_factors(const HostFactors &h, const std::string &path) {
+    W w;
+    w.f.open(path, std::ios::binary);
+    if (!w.f) fail(FIO_ERR_IO, "cannot open " + path + " for writing");
+    w.f.write(MAGIC, 8);
+    const fio_problem &p = h.prob;
+    w.v(p.d); w.v(p.n); w.v((int)p.phase); w.v(p.c_div); w.v(p.eps); w.v(p.eps_bf);
+    w.v(p.eps_peel); w.v(p.eps_hif); w.v(p.leaf_bf); w.v(p.leaf_h); w.v(p.oversample);
+    w.v(p.seed);
+    w.v(h.N); w.v(h.L); w.v(h.Lm); w.v(h.m);
+    w.arr(h.perm);
+    w.v((int)h.fwd.size());
+    for (const Stage &s : h.fwd) {
+        w.v(s.n_out); w.v(s.n_in); w.v(s.r_out); w.v(s.r_in); w.v(s.fan);
+        w.arr(s.in_idx);
+        w.arr(s.A);
+    }
+    w.v(h.hif.N);
+    w.v((int)h.hif.steps.size());
+    for (const HifStep &st : h.hif.steps) {
+        w.v((int)st.nodes.size());
+        for (const HifNode &nd : st.nodes) {
+            w.arr(nd.idx_r); w.arr(nd.idx_s);
+            w.mat(nd.T); w.mat(nd.Linv); w.mat(nd.M);
+        }
+    }
+    w.arr(h.hif.root_idx);
+    w.mat(h.hif.A0inv);
+    w.v(h.hif.max_rank_h);
+    w.v(h.build_seconds);
+    if (!w.f) fail(FIO_ERR_IO, "write failed: " + path);
+}
+
+void load_factors(const std::string &path, HostFactors &h) {
+    R r;
+    r.f.open(path, std::ios::binary);
+    if (!r.f) fail(FIO_ERR_IO, "cannot open " + path);
+    char mg[8];
+    r.f.read(mg, 8);
+    if (!r.f || std::memcmp(mg, MAGIC, 8) != 0) fail(FIO_ERR_IO, "not a plan file: " + path);
+    fio_problem &p = h.prob;
+    std::memset(&p, 0, sizeof(p));
+    int ph = 0;
+    r.v(p.d); r.v(p.n); r.v(ph); p.phase = (fio_phase_id)ph;
+    r.v(p.c_div); r.v(p.eps); r.v(p.eps_bf); r.v(p.eps_peel); r.v(p.eps_hif);
+    r.v(p.leaf_bf); r.v(p.leaf_h); r.v(p.oversample); r.v(p.seed);
+    h.d = p.d; h.n = p.n;
+    r.v(h.N); r.v(h.L); r.v(h.Lm); r.v(h.m);
+    r.arr(h.perm);
+    if ((int64_t)h.perm.size() != h.N) fail(FIO_ERR_IO, "corrupt plan file (perm)");
+    int ns = 0;
+    r.v(ns);
+    if (ns < 0 || ns > 4096) fail(FIO_ERR_IO, "corrupt plan file (stages)");
+    h.fwd.resize(ns);
+    for (Stage &s : h.fwd) {
+        r.v(s.n_out); r.v(s.n_in); r.v(s.r_out); r.v(s.r_in); r.v(s.fan);
+        r.arr(s.in_idx);
+        r.arr(s.A);
+        if ((int64_t)s.in_idx.size() != s.n_out * s.fan || (int64_t)s.A.size() != s.nnz())
+            fail(FIO_ERR_IO, "corrupt plan file (stage sizes)");
+        for (int32_t v : s.in_idx)
+            if (v < 0 || v >= s.n_in) fail(FIO_ERR_IO, "corrupt plan file (stage index)");
+    }
+    r.v(h.hif.N);
+    int nst = 0;
+    r.v(nst);
+    if (nst < 0 || nst > 4096) fail(FIO_ERR_IO, "corrupt plan file (hif)");
+    h.hif.steps.resize(nst);
+    for (HifStep &st : h.hif.steps) {
+        int nn = 0;
+        r.v(nn);
+        if (nn < 0) fail(FIO_ERR_IO, "corrupt plan file (hif nodes)");
+        st.nodes.resize(nn);
+        for (HifNode &nd : st.nodes) {
+            r.arr(nd.idx_r); r.arr(nd.idx_s);
+            r.mat(nd.T); r.mat(nd.Linv); r.mat(nd.M);
+            const int nr = (int)nd.idx_r.size(), nsk = (int)nd.idx_s.size();
+            if (nd.T.m != nsk || nd.T.n != nr || nd.Linv.m != nr || nd.Linv.n != nr ||
+                nd.M.m != nsk || nd.M.n != nr)
+                fail(FIO_ERR_IO, "corrupt plan file (hif blocks)");
+            for (int v : nd.idx_r) if (v < 0 || v >= h.N) fail(FIO_ERR_IO, "corrupt plan file (idx)");
+            for (int v : nd.idx_s) if (v < 0 || v >= h.N) fail(FIO_ERR_IO, "corrupt plan file (idx)");
+        }
+    }
+    r.arr(h.hif.root_idx);
+    r.mat(h.hif.A0inv);
+    for (int v : h.hif.root_idx) if (v < 0 || v >= h.N) fail(FIO_ERR_IO, "corrupt plan file (root)");
+    if (h.hif.A0inv.m != (int)h.hif.root_idx.size()) fail(FIO_ERR_IO, "corrupt plan file (root)");
+    r.v(h.hif.max_rank_h);
+    r.v(h.build_seconds);
+}
+
+}  // namespace fio

@@ -1,0 +1,243 @@
+#include "butterfly.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+#include "la.hpp"
+
+namespace fio {
+
+static int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+
+// Sorted distinct sample of `count` positions of [lo, lo + size): one uniformly
+// random position per equal stratum (all positions if count >= size).
+static std::vector<int> stratified(int64_t lo, int64_t size, int count, uint64_t seed) {
+    std::vector<int> out;
+    if (count >= size) {
+        out.resize(size);
+        for (int64_t i = 0; i < size; ++i) out[i] = (int)(lo + i);
+        return out;
+    }
+    out.resize(count);
+    for (int s = 0; s < count; ++s) {
+        int64_t a = size * s / count, b = size * (s + 1) / count;
+        uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)s + 0x51ED27ULL));
+        out[s] = (int)(lo + a + (int64_t)(h % (uint64_t)(b - a)));
+    }
+    return out;
+}
+
+static int n_samples(int ncand, int64_t size) {
+    return (int)std::min<int64_t>(size, std::max(2 * ncand + 16, 32));
+}
+
+Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
+    Butterfly B;
+    B.d = K.d;
+    B.F = 1 << K.d;
+    B.N = K.N;
+    const int F = B.F;
+    B.m = (int)ipow(opt.leaf, K.d);
+    if (B.m > B.N || B.N % B.m) fail(FIO_ERR_ARG, "butterfly leaf larger than the grid");
+    int L = 0;
+    while (ipow(F, L) * B.m < B.N) ++L;
+    if (ipow(F, L) * B.m != B.N) fail(FIO_ERR_ARG, "grid is not a power of the tree fan");
+    B.L = L;
+    B.Lm = L / 2;
+    const int Lm = B.Lm;
+    const int64_t N = B.N;
+    const int64_t npairs = ipow(F, L);
+    B.rU.assign(L + 1, 0);
+    B.rV.assign(L + 1, 0);
+    B.fwd.assign(L + 3, Stage());
+    const int nt = opt.nthreads;
+
+    // ---------------- X side: row skeletons, levels L down to Lm ----------------
+    std::vector<std::vector<int>> skelU(L + 1);
+    for (int l = L; l >= Lm; --l) {
+        const int64_t nOm = ipow(F, L - l);       // Omega nodes at level L - l
+        const int64_t szX = N / ipow(F, l);
+        const int64_t szOm = N / nOm;
+        const int rnext = (l < L) ? B.rU[l + 1] : 0;
+        const int ncand = (l == L) ? (int)szX : F * rnext;
+        auto candidates = [&](int64_t pr) {
+            int64_t i = pr / nOm, j = pr % nOm;
+            std::vector<int> c(ncand);
+            if (l == L) {
+                for (int t = 0; t < ncand; ++t) c[t] = (int)(i * szX + t);
+            } else {
+                const int64_t nOmN = nOm / F;
+                for (int q = 0; q < F; ++q) {
+                    const int *s = &skelU[l + 1][((F * i + q) * nOmN + j / F) * rnext];
+                    std::copy(s, s + rnext, c.begin() + q * rnext);
+                }
+            }
+            return c;
+        };
+        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand) {
+            int64_t j = pr % nOm;
+            std::vector<int> cols = stratified(j * szOm, szOm, n_samples(ncand, szOm),
+                                               opt.seed ^ splitmix64(0xA000 + l) ^ (uint64_t)pr * 7919ULL);
+            Mat MT((int)cols.size(), ncand);  // transpose of K(cand, cols)
+            for (int c = 0; c < ncand; ++c)
+                for (size_t s = 0; s < cols.size(); ++s) MT((int)s, c) = K.entry(cand[c], cols[s]);
+            return MT;
+        };
+        std::vector<int> ranks(npairs);
+        parallel_for(npairs, nt, [&](int64_t pr) {
+            auto cand = candidates(pr);
+            ranks[pr] = id_rank(sample_matrix(pr, cand), opt.eps, ncand);
+        });
+        const int r = std::max(1, *std::max_element(ranks.begin(), ranks.end()));
+        B.rU[l] = r;
+        skelU[l].assign((size_t)npairs * r, 0);
+        std::vector<Mat> Q(npairs);
+        parallel_for(npairs, nt, [&](int64_t pr) {
+            auto cand = candidates(pr);
+            ColumnID id = column_id(sample_matrix(pr, cand), opt.eps, r, ncand);
+            // K(cand, :) ~= Q K(skel, :) with Q(skel_k, k) = 1 and Q(redund_t, k) = T(k, t).
+            Mat q(ncand, r);
+            for (int k = 0; k < r; ++k) {
+                q(id.skel[k], k) = 1.0;
+                skelU[l][pr * r + k] = cand[id.skel[k]];
+            }
+            for (size_t t = 0; t < id.redund.size(); ++t)
+                for (int k = 0; k < r; ++k) q(id.redund[t], k) = id.T(k, (int)t);
+            Q[pr] = std::move(q);
+        });
+        if (l < L) skelU[l + 1].clear();
+        Stage st;
+        if (l == L) {
+            // U_L: X leaf i <- pair (i, 0), an m x r block.
+            st.n_out = npairs; st.n_in = npairs;
+            st.r_out = (int)szX; st.r_in = r; st.fan = 1;
+            st.in_idx.resize(npairs);
+            st.A.resize((size_t)npairs * szX * r);
+            for (int64_t i = 0; i < npairs; ++i) {
+                st.in_idx[i] = (int32_t)i;
+                std::copy(Q[i].a.begin(), Q[i].a.end(), st.A.begin() + (size_t)i * szX * r);
+            }
+            B.fwd[L + 2] = std::move(st);
+        } else {
+            // C_l: pair (ih, jh) at level l+1 <- pairs (ih/F, F jh + q) at level l.
+            const int64_t nOmN = nOm / F;
+            st.n_out = npairs; st.n_in = npairs;
+            st.r_out = rnext; st.r_in = r; st.fan = F;
+            st.in_idx.resize(npairs * F);
+            st.A.assign((size_t)npairs * rnext * F * r, cd(0));
+            parallel_for(npairs, nt, [&](int64_t o) {
+                int64_t ih = o / nOmN, jh = o % nOmN;
+                int64_t i = ih / F, c = ih % F;
+                cd *blk = st.A.data() + (size_t)o * rnext * F * r;
+                for (int q = 0; q < F; ++q) {
+                    int64_t in = i * nOm + F * jh + q;
+                    st.in_idx[o * F + q] = (int32_t)in;
+                    const Mat &Qi = Q[in];
+                    for (int k = 0; k < r; ++k)
+                        for (int a = 0; a < rnext; ++a)
+                            blk[a + (size_t)(q * r + k) * rnext] = Qi((int)(c * rnext + a), k);
+                }
+            });
+            B.fwd[l + 2] = std::move(st);
+        }
+    }
+
+    // ---------------- Omega side: column skeletons, levels 0 up to Lm ----------------
+    std::vector<std::vector<int>> skelV(L + 1);
+    for (int l = 0; l <= Lm; ++l) {
+        const int64_t nOm = ipow(F, L - l);
+        const int64_t szX = N / ipow(F, l);
+        const int rprev = (l > 0) ? B.rV[l - 1] : 0;
+        const int ncand = (l == 0) ? B.m : F * rprev;
+        auto candidates = [&](int64_t pr) {
+            int64_t i = pr / nOm, j = pr % nOm;
+            std::vector<int> c(ncand);
+            if (l == 0) {
+                for (int t = 0; t < ncand; ++t) c[t] = (int)(j * B.m + t);
+            } else {
+                const int64_t nOmP = nOm * F;
+                for (int q = 0; q < F; ++q) {
+                    const int *s = &skelV[l - 1][((i / F) * nOmP + F * j + q) * rprev];
+                    std::copy(s, s + rprev, c.begin() + q * rprev);
+                }
+            }
+            return c;
+        };
+        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand) {
+            int64_t i = pr / nOm;
+            std::vector<int> rows = stratified(i * szX, szX, n_samples(ncand, szX),
+                                               opt.seed ^ splitmix64(0xB000 + l) ^ (uint64_t)pr * 104729ULL);
+            Mat M((int)rows.size(), ncand);
+            for (int c = 0; c < ncand; ++c)
+                for (size_t s = 0; s < rows.size(); ++s) M((int)s, c) = K.entry(rows[s], cand[c]);
+            return M;
+        };
+        std::vector<int> ranks(npairs);
+        parallel_for(npairs, nt, [&](int64_t pr) {
+            auto cand = candidates(pr);
+            ranks[pr] = id_rank(sample_matrix(pr, cand), opt.eps, ncand);
+        });
+        const int r = std::max(1, *std::max_element(ranks.begin(), ranks.end()));
+        B.rV[l] = r;
+        skelV[l].assign((size_t)npairs * r, 0);
+        std::vector<Mat> G(npairs);
+        parallel_for(npairs, nt, [&](int64_t pr) {
+            auto cand = candidates(pr);
+            ColumnID id = column_id(sample_matrix(pr, cand), opt.eps, r, ncand);
+            // K(:, cand) ~= K(:, skel) G with G(k, skel_k) = 1 and G(k, redund_t) = T(k, t).
+            Mat g(r, ncand);
+            for (int k = 0; k < r; ++k) {
+                g(k, id.skel[k]) = 1.0;
+                skelV[l][pr * r + k] = cand[id.skel[k]];
+            }
+            for (size_t t = 0; t < id.redund.size(); ++t)
+                for (int k = 0; k < r; ++k) g(k, id.redund[t]) = id.T(k, (int)t);
+            G[pr] = std::move(g);
+        });
+        if (l > 0) skelV[l - 1].clear();
+        Stage st;
+        st.n_out = npairs; st.n_in = npairs;
+        st.r_out = r;
+        st.fan = (l == 0) ? 1 : F;
+        st.r_in = (l == 0) ? B.m : rprev;
+        st.in_idx.resize(npairs * st.fan);
+        st.A.resize((size_t)npairs * r * ncand);
+        const int64_t nOmP = nOm * F;
+        parallel_for(npairs, nt, [&](int64_t o) {
+            int64_t i = o / nOm, j = o % nOm;
+            if (l == 0) {
+                st.in_idx[o] = (int32_t)j;  // Omega leaf j
+            } else {
+                for (int q = 0; q < F; ++q)
+                    st.in_idx[o * F + q] = (int32_t)((i / F) * nOmP + F * j + q);
+            }
+            std::copy(G[o].a.begin(), G[o].a.end(), st.A.begin() + (size_t)o * r * ncand);
+        });
+        B.fwd[l] = std::move(st);
+    }
+
+    // ---------------- middle level: D_ij = K(s_ij, t_ij) ----------------
+    {
+        const int ru = B.rU[Lm], rv = B.rV[Lm];
+        Stage st;
+        st.n_out = npairs; st.n_in = npairs;
+        st.r_out = ru; st.r_in = rv; st.fan = 1;
+        st.in_idx.resize(npairs);
+        st.A.resize((size_t)npairs * ru * rv);
+        parallel_for(npairs, nt, [&](int64_t o) {
+            st.in_idx[o] = (int32_t)o;
+            cd *blk = st.A.data() + (size_t)o * ru * rv;
+            for (int b = 0; b < rv; ++b)
+                for (int a = 0; a < ru; ++a)
+                    blk[a + (size_t)b * ru] = K.entry(skelU[Lm][o * ru + a], skelV[Lm][o * rv + b]);
+        });
+        B.fwd[Lm + 1] = std::move(st);
+    }
+    return B;
+}
+
+}  // namespace fio

@@ -1,0 +1,41 @@
+// Butterfly factorization of K (section 2), built on the host in FP64.
+//
+// Trees T_X and T_Omega of depth L (fan F = 2^d, leaves of m points).  At level l
+// the pairs (i, j) couple X node i at level l with Omega node j at level L - l
+// (the complementary low-rank blocks K_{l;ij}).  This construction uses
+// interpolative decompositions: on the X side, K_{l;ij} ~= P_{l;ij} K(s_{l;ij}, Omega_j)
+// with skeleton rows s chosen among the children's skeletons, so P is nested
+// (U_l = U_{l+1} C_l of eq_BFF_nested); on the Omega side, K_{l;ij} ~= K(X_i, t_{l;ij}) W_{l;ij}
+// with W nested across levels (V_l = V_{l+1} H_l).  At the middle level lm the
+// coupling block is D_{ij} = K(s_ij, t_ij), so
+//     Kd = U_L C_{L-1} .. C_lm D H^*_lm .. H^*_1 V^*_L
+// has L + 3 block-sparse factors, each with O(N) nonzeros (eq_BFF_fact).
+#pragma once
+
+#include "fio_kernel.hpp"
+#include "stages.hpp"
+
+namespace fio {
+
+struct ButterflyOptions {
+    double eps = 1e-7;    // relative tolerance of every interpolative decomposition
+    int leaf = 8;         // leaf side (points per dimension)
+    int nthreads = 0;
+    uint64_t seed = 1;    // column/row sampling
+};
+
+struct Butterfly {
+    int d = 1, F = 2, L = 0, Lm = 0, m = 0;
+    int64_t N = 0;
+    std::vector<int> rU, rV;       // ranks per level (X side l = Lm..L, Omega side l = 0..Lm)
+    std::vector<Stage> fwd;        // L + 3 stages: Omega tree order in -> X tree order out
+    int64_t nnz() const {
+        int64_t s = 0;
+        for (auto &st : fwd) s += st.nnz();
+        return s;
+    }
+};
+
+Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt);
+
+}  // namespace fio

@@ -1,0 +1,533 @@
+// C ABI: plan lifetime, device images of the factors, and the apply/solve drivers.
+// Every floating-point step of an apply runs in the kernels of kernels.hip; the
+// host only enqueues work on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fio.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace fio;
+
+namespace {
+
+thread_local std::string g_err;
+
+#define HIPC(x)                                                                          \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            fail(e_ == hipErrorOutOfMemory ? FIO_ERR_NOMEM : FIO_ERR_DEVICE,             \
+                 std::string(#x) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+// Device allocation owned by a plan.
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DBuf() {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t b) {
+        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        if (b == 0) return;
+        HIPC(hipMalloc(&p, b));
+        bytes = b;
+    }
+    void upload(const void *src, size_t b) {
+        alloc(b);
+        if (b) HIPC(hipMemcpy(p, src, b, hipMemcpyHostToDevice));
+    }
+};
+
+template <class T> struct DStageStore {
+    DBuf idx, A64, A128;
+    StageDev view(bool dbl, const Stage &s) const {
+        StageDev v;
+        v.n_out = s.n_out; v.n_in = s.n_in; v.r_out = s.r_out; v.r_in = s.r_in; v.fan = s.fan;
+        v.idx = (const int32_t *)idx.p;
+        v.A = dbl ? A128.p : A64.p;
+        return v;
+    }
+};
+
+struct DHifStore {
+    DBuf desc, idx, m64, m128;
+    HifStepDev view(bool dbl) const {
+        HifStepDev v = base;
+        v.desc = (const int64_t *)desc.p;
+        v.idx = (const int32_t *)idx.p;
+        v.mat = dbl ? m128.p : m64.p;
+        return v;
+    }
+    HifStepDev base;
+};
+
+void upload_complex(DBuf &b64, DBuf &b128, const std::vector<cd> &a) {
+    std::vector<float> f(2 * a.size());
+    for (size_t i = 0; i < a.size(); ++i) {
+        f[2 * i] = (float)a[i].real();
+        f[2 * i + 1] = (float)a[i].imag();
+    }
+    b64.upload(f.data(), f.size() * sizeof(float));
+    b128.upload(a.data(), a.size() * sizeof(cd));
+}
+
+}  // namespace
+
+struct fio_plan_s {
+    HostFactors host;
+    int device = -1;
+    std::vector<Stage> adj;                   // host adjoint stages (Kd^*)
+    std::vector<DStageStore<int>> dfwd, dadj;
+    std::vector<DHifStore> dhif;
+    DBuf root_idx, A0inv, perm;
+    int s0 = 0;
+    int64_t max_coef = 0;                     // longest coefficient vector between stages
+    int64_t device_bytes = 0;
+    // workspace (grown on demand)
+    int ws_nrhs = 0;
+    DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal;
+    std::mutex mu;
+};
+
+namespace {
+
+void count_bytes(fio_plan p) {
+    int64_t b = 0;
+    for (auto &s : p->dfwd) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
+    for (auto &s : p->dadj) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
+    for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes;
+    b += p->root_idx.bytes + p->A0inv.bytes + p->perm.bytes;
+    p->device_bytes = b;
+}
+
+void upload_stages(const std::vector<Stage> &st, std::vector<DStageStore<int>> &d) {
+    d.resize(st.size());
+    for (size_t i = 0; i < st.size(); ++i) {
+        d[i].idx.upload(st[i].in_idx.data(), st[i].in_idx.size() * sizeof(int32_t));
+        upload_complex(d[i].A64, d[i].A128, st[i].A);
+    }
+}
+
+void upload_plan(fio_plan p) {
+    HIPC(hipSetDevice(p->device));
+    const HostFactors &h = p->host;
+    upload_stages(h.fwd, p->dfwd);
+    upload_stages(p->adj, p->dadj);
+    p->max_coef = h.N;
+    for (auto &s : h.fwd) {
+        p->max_coef = std::max<int64_t>(p->max_coef, s.n_out * s.r_out);
+        p->max_coef = std::max<int64_t>(p->max_coef, s.n_in * s.r_in);
+    }
+    p->dhif.resize(h.hif.steps.size());
+    for (size_t k = 0; k < h.hif.steps.size(); ++k) {
+        const HifStep &st = h.hif.steps[k];
+        std::vector<int64_t> desc;
+        std::vector<int32_t> idx;
+        std::vector<cd> mat;
+        int mr = 0, ms = 0;
+        for (const HifNode &nd : st.nodes) {
+            const int nr = (int)nd.idx_r.size(), ns = (int)nd.idx_s.size();
+            mr = std::max(mr, nr);
+            ms = std::max(ms, ns);
+            desc.push_back(nr);
+            desc.push_back(ns);
+            desc.push_back((int64_t)idx.size());
+            desc.push_back((int64_t)mat.size());
+            idx.insert(idx.end(), nd.idx_r.begin(), nd.idx_r.end());
+            idx.insert(idx.end(), nd.idx_s.begin(), nd.idx_s.end());
+            mat.insert(mat.end(), nd.T.a.begin(), nd.T.a.end());
+            mat.insert(mat.end(), nd.Linv.a.begin(), nd.Linv.a.end());
+            mat.insert(mat.end(), nd.M.a.begin(), nd.M.a.end());
+        }
+        DHifStore &d = p->dhif[k];
+        d.base.n_nodes = (int64_t)st.nodes.size();
+        d.base.max_nr = mr;
+        d.base.max_ns = ms;
+        d.desc.upload(desc.data(), desc.size() * sizeof(int64_t));
+        d.idx.upload(idx.data(), idx.size() * sizeof(int32_t));
+        upload_complex(d.m64, d.m128, mat);
+    }
+    p->s0 = (int)h.hif.root_idx.size();
+    p->root_idx.upload(h.hif.root_idx.data(), h.hif.root_idx.size() * sizeof(int32_t));
+    p->A0inv.upload(h.hif.A0inv.a.data(), h.hif.A0inv.a.size() * sizeof(cd));
+    p->perm.upload(h.perm.data(), h.perm.size() * sizeof(int32_t));
+    count_bytes(p);
+}
+
+void ensure_ws(fio_plan p, int nrhs) {
+    if (nrhs <= p->ws_nrhs) return;
+    const size_t coef = (size_t)p->max_coef * nrhs * 16;
+    const size_t vec = (size_t)p->host.N * nrhs * 16;
+    p->P.alloc(coef); p->Q.alloc(coef);
+    p->V1.alloc(vec); p->V2.alloc(vec); p->V3.alloc(vec); p->W.alloc(vec);
+    p->U.alloc(vec); p->X.alloc(vec); p->R.alloc(vec); p->Z.alloc(vec); p->Pv.alloc(vec);
+    p->red.alloc((size_t)reduce_partial_cap(p->host.N, nrhs) * sizeof(double));
+    p->scal.alloc((size_t)nrhs * 8 * sizeof(double));
+    p->ws_nrhs = nrhs;
+}
+
+// Run a stage chain: in (first stage's input) -> out (last stage's output).
+void run_chain(fio_plan p, const std::vector<Stage> &host, const std::vector<DStageStore<int>> &dev,
+               bool dbl, const void *in, void *out, int nrhs, hipStream_t st) {
+    const size_t S = dev.size();
+    const void *cur = in;
+    for (size_t s = 0; s < S; ++s) {
+        void *dst = (s + 1 == S) ? out : ((s % 2 == 0) ? p->P.p : p->Q.p);
+        launch_stage(dev[s].view(dbl, host[s]), dbl, cur, dst, nrhs, st);
+        cur = dst;
+    }
+}
+
+void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
+    for (size_t k = 0; k < p->dhif.size(); ++k) launch_hif_step(p->dhif[k].view(dbl), dbl, true, x, nrhs, st);
+    launch_root((const int32_t *)p->root_idx.p, p->A0inv.p, p->s0, dbl, x, nrhs, st);
+    for (size_t k = p->dhif.size(); k-- > 0;) launch_hif_step(p->dhif[k].view(dbl), dbl, false, x, nrhs, st);
+}
+
+void check_apply_args(fio_plan p, int64_t nrhs, int64_t ld, const void *a, const void *b) {
+    if (!p) fail(FIO_ERR_ARG, "null plan");
+    if (p->device < 0) fail(FIO_ERR_UNSUPPORTED, "plan is host-only (built or loaded with device = -1)");
+    if (nrhs < 0 || nrhs > (1 << 20)) fail(FIO_ERR_ARG, "nrhs out of range");
+    if (nrhs > 0 && ld < p->host.N) fail(FIO_ERR_ARG, "ld must be >= N");
+    if (nrhs > 0 && (!a || !b)) fail(FIO_ERR_ARG, "null vector buffer");
+}
+
+template <class F> fio_status guard(F &&f) {
+    try {
+        f();
+        return FIO_OK;
+    } catch (const Error &e) {
+        g_err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return FIO_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return FIO_ERR_DEVICE;
+    }
+}
+
+// Builder hook: products with Kd^* Kd for the peeling step on the plan's GPU (FP64).
+PeelApplyFactory gpu_peel_factory(int device) {
+    return [device](const std::vector<Stage> &fwd, const std::vector<Stage> &adj) -> BlockApply {
+        auto df = std::make_shared<std::vector<DStageStore<int>>>();
+        auto da = std::make_shared<std::vector<DStageStore<int>>>();
+        HIPC(hipSetDevice(device));
+        upload_stages(fwd, *df);
+        upload_stages(adj, *da);
+        int64_t maxc = 0;
+        for (auto &s : fwd) maxc = std::max<int64_t>(maxc, std::max(s.n_out * s.r_out, s.n_in * s.r_in));
+        const int64_t N = fwd.front().n_in * fwd.front().r_in;
+        return [df, da, maxc, N, device, &fwd, &adj](const cd *x, cd *y, int nr) {
+            HIPC(hipSetDevice(device));
+            DBuf in, out, P, Q;
+            in.alloc((size_t)N * nr * 16);
+            out.alloc((size_t)N * nr * 16);
+            P.alloc((size_t)maxc * nr * 16);
+            Q.alloc((size_t)maxc * nr * 16);
+            HIPC(hipMemcpy(in.p, x, (size_t)N * nr * 16, hipMemcpyHostToDevice));
+            auto chain = [&](const std::vector<Stage> &h, const std::vector<DStageStore<int>> &d,
+                             const void *src, void *dst) {
+                const void *cur = src;
+                for (size_t s = 0; s < d.size(); ++s) {
+                    void *t = (s + 1 == d.size()) ? dst : ((s % 2 == 0) ? P.p : Q.p);
+                    launch_stage(d[s].view(true, h[s]), true, cur, t, nr, 0);
+                    cur = t;
+                }
+            };
+            chain(fwd, *df, in.p, out.p);
+            chain(adj, *da, out.p, in.p);
+            HIPC(hipMemcpy(y, in.p, (size_t)N * nr * 16, hipMemcpyDeviceToHost));
+        };
+    };
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char *fio_last_error(void) { return g_err.c_str(); }
+
+fio_status fio_build(const fio_problem *prob, fio_plan *out) {
+    return guard([&] {
+        if (!prob || !out) fail(FIO_ERR_ARG, "null argument");
+        *out = nullptr;
+        std::unique_ptr<fio_plan_s> p(new fio_plan_s());
+        p->device = prob->device;
+        if (p->device >= 0) {
+            int cnt = 0;
+            HIPC(hipGetDeviceCount(&cnt));
+            if (p->device >= cnt) fail(FIO_ERR_ARG, "device ordinal out of range");
+            HIPC(hipSetDevice(p->device));
+        }
+        // Peeling products on the GPU when the plan has one (host otherwise).
+        PeelApplyFactory f;
+        if (p->device >= 0) f = gpu_peel_factory(p->device);
+        build_host_factors(*prob, p->host, f);
+        for (int s = (int)p->host.fwd.size() - 1; s >= 0; --s) p->adj.push_back(adjoint_stage(p->host.fwd[s]));
+        if (p->device >= 0) upload_plan(p.get());
+        *out = p.release();
+    });
+}
+
+fio_status fio_load(const char *path, int device, fio_plan *out) {
+    return guard([&] {
+        if (!path || !out) fail(FIO_ERR_ARG, "null argument");
+        *out = nullptr;
+        std::unique_ptr<fio_plan_s> p(new fio_plan_s());
+        load_factors(path, p->host);
+        p->host.prob.device = device;
+        p->device = device;
+        for (int s = (int)p->host.fwd.size() - 1; s >= 0; --s) p->adj.push_back(adjoint_stage(p->host.fwd[s]));
+        if (device >= 0) upload_plan(p.get());
+        *out = p.release();
+    });
+}
+
+fio_status fio_save(fio_plan p, const char *path) {
+    return guard([&] {
+        if (!p || !path) fail(FIO_ERR_ARG, "null argument");
+        save_factors(p->host, path);
+    });
+}
+
+void fio_destroy(fio_plan p) { delete p; }
+
+fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
+    return guard([&] {
+        if (!p || !o) fail(FIO_ERR_ARG, "null argument");
+        std::memset(o, 0, sizeof(*o));
+        const HostFactors &h = p->host;
+        o->d = h.d; o->n = h.n; o->L = h.L; o->L_mid = h.Lm;
+        o->n_stages = (int)h.fwd.size();
+        for (auto &s : h.fwd) {
+            o->bf_nnz += s.nnz();
+            o->max_rank_bf = std::max({o->max_rank_bf, s.fan > 1 ? s.r_out : 0, s.fan > 1 ? s.r_in : 0});
+        }
+        o->hif_levels = (int)h.hif.steps.size();
+        for (auto &st : h.hif.steps)
+            for (auto &nd : st.nodes) o->hif_nnz += (int64_t)nd.T.a.size() + nd.Linv.a.size() + nd.M.a.size();
+        o->root_size = (int)h.hif.root_idx.size();
+        o->max_rank_h = h.hif.max_rank_h;
+        o->device_bytes = p->device_bytes;
+        o->workspace_bytes = (int64_t)(2 * p->max_coef + 11 * h.N) * 16;
+        o->build_seconds = h.build_seconds;
+    });
+}
+
+fio_status fio_stage_info(fio_plan p, int stage, int64_t *nnz, int64_t *nob, int *r_out, int *r_in, int *fan) {
+    return guard([&] {
+        if (!p) fail(FIO_ERR_ARG, "null plan");
+        if (stage < 0 || stage >= (int)p->host.fwd.size()) fail(FIO_ERR_ARG, "stage out of range");
+        const Stage &s = p->host.fwd[stage];
+        if (nnz) *nnz = s.nnz();
+        if (nob) *nob = s.n_out;
+        if (r_out) *r_out = s.r_out;
+        if (r_in) *r_in = s.r_in;
+        if (fan) *fan = s.fan;
+    });
+}
+
+fio_status fio_apply(fio_plan p, fio_op op, fio_dtype dt, const void *x, void *y, int64_t nrhs, int64_t ld,
+                     void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, ld, x, y);
+        if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (nrhs == 0) return;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        hipStream_t st = (hipStream_t)stream;
+        const bool dbl = dt == FIO_C128;
+        const int nr = (int)nrhs;
+        ensure_ws(p, nr);
+        const int32_t *perm = (const int32_t *)p->perm.p;
+        const int64_t N = p->host.N;
+        launch_gather(x, dbl, ld, perm, p->V1.p, dbl, N, nr, st);
+        if (op == FIO_OP_K) run_chain(p, p->host.fwd, p->dfwd, dbl, p->V1.p, p->V2.p, nr, st);
+        else run_chain(p, p->adj, p->dadj, dbl, p->V1.p, p->V2.p, nr, st);
+        launch_scatter(p->V2.p, dbl, perm, y, dbl, ld, N, nr, st);
+    });
+}
+
+fio_status fio_gd_apply(fio_plan p, fio_dtype dt, const void *x, void *y, int64_t nrhs, int64_t ld, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, ld, x, y);
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (nrhs == 0) return;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        hipStream_t st = (hipStream_t)stream;
+        const bool dbl = dt == FIO_C128;
+        const int nr = (int)nrhs;
+        ensure_ws(p, nr);
+        const int32_t *perm = (const int32_t *)p->perm.p;
+        launch_gather(x, dbl, ld, perm, p->V2.p, dbl, p->host.N, nr, st);
+        gd_inplace(p, dbl, p->V2.p, nr, st);
+        launch_scatter(p->V2.p, dbl, perm, y, dbl, ld, p->host.N, nr, st);
+    });
+}
+
+fio_status fio_inverse_apply(fio_plan p, fio_dtype dt, const void *u, void *fh, int64_t nrhs, int64_t ld,
+                             void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, ld, u, fh);
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (nrhs == 0) return;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        hipStream_t st = (hipStream_t)stream;
+        const bool dbl = dt == FIO_C128;
+        const int nr = (int)nrhs;
+        ensure_ws(p, nr);
+        const int32_t *perm = (const int32_t *)p->perm.p;
+        const int64_t N = p->host.N;
+        launch_gather(u, dbl, ld, perm, p->V1.p, dbl, N, nr, st);
+        run_chain(p, p->adj, p->dadj, dbl, p->V1.p, p->V2.p, nr, st);
+        gd_inplace(p, dbl, p->V2.p, nr, st);
+        launch_scatter(p->V2.p, dbl, perm, fh, dbl, ld, N, nr, st);
+    });
+}
+
+fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const void *u, void *out,
+                     int64_t nrhs, int64_t ld, fio_solve_info *info, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, ld, u, out);
+        if (!opts) fail(FIO_ERR_ARG, "null options");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (opts->mode < FIO_SOLVE_DIRECT || opts->mode > FIO_SOLVE_PCG) fail(FIO_ERR_ARG, "bad mode");
+        if (opts->maxit < 0 || opts->tol < 0) fail(FIO_ERR_ARG, "bad iteration settings");
+        if (nrhs == 0) return;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        hipStream_t st = (hipStream_t)stream;
+        const bool dbl = dt == FIO_C128;
+        const int nr = (int)nrhs;
+        ensure_ws(p, nr);
+        const int32_t *perm = (const int32_t *)p->perm.p;
+        const int64_t N = p->host.N;
+        const int64_t cnt = N * nr;
+        double *scal = (double *)p->scal.p;
+        std::vector<double> hs(8 * (size_t)nr);
+        int iters = 0;
+        double worst = 0;
+        bool converged = true;
+        // U: u in X tree order (complex128).  X: solution in Omega tree order (complex128).
+        launch_gather(u, true, ld, perm, p->U.p, true, N, nr, st);
+        auto gd_kh = [&](const void *r128, void *d_out) {
+            // d_out (dtype) = Gd Kd^* r
+            const void *src = r128;
+            if (!dbl) {
+                launch_convert(r128, true, p->V3.p, false, cnt, st);
+                src = p->V3.p;
+            }
+            run_chain(p, p->adj, p->dadj, dbl, src, d_out, nr, st);
+            gd_inplace(p, dbl, d_out, nr, st);
+        };
+        if (opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_REFINE) {
+            gd_kh(p->U.p, p->V2.p);
+            launch_convert(p->V2.p, dbl, p->X.p, true, cnt, st);  // x0 = Gd Kd^* u
+            if (opts->mode == FIO_SOLVE_REFINE) {
+                for (int it = 0; it < opts->maxit; ++it) {
+                    // r = u - Kd x with complex128 factors and FP64 accumulation
+                    run_chain(p, p->host.fwd, p->dfwd, true, p->X.p, p->V1.p, nr, st);
+                    launch_residual(p->U.p, p->V1.p, p->R.p, true, cnt, st);
+                    gd_kh(p->R.p, p->V2.p);
+                    launch_axpy_update(p->X.p, p->V2.p, dbl, cnt, st);
+                    ++iters;
+                    if (opts->tol > 0 || (info && it + 1 == opts->maxit)) {
+                        // ||dx|| / ||x|| per column
+                        if (!dbl) launch_convert(p->V2.p, false, p->V1.p, true, cnt, st);
+                        const void *dx = dbl ? p->V2.p : p->V1.p;
+                        launch_colnorm2(dx, N, nr, (double *)p->red.p, reduce_partial_cap(N, nr), scal, st);
+                        launch_colnorm2(p->X.p, N, nr, (double *)p->red.p, reduce_partial_cap(N, nr), scal + nr, st);
+                        HIPC(hipMemcpyAsync(hs.data(), scal, 2 * nr * sizeof(double), hipMemcpyDeviceToHost, st));
+                        HIPC(hipStreamSynchronize(st));
+                        worst = 0;
+                        for (int b = 0; b < nr; ++b)
+                            worst = std::max(worst, std::sqrt(hs[b] / std::max(hs[nr + b], 1e-300)));
+                        if (opts->tol > 0 && worst <= opts->tol) break;
+                    }
+                }
+                if (opts->tol > 0 && worst > opts->tol) converged = false;
+            }
+        } else {
+            // PCG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5).  Vectors are
+            // complex128; the operator applies run in dtype.
+            auto apply_chain = [&](const std::vector<Stage> &h, const std::vector<DStageStore<int>> &d,
+                                   const void *in128, void *out128) {
+                if (dbl) {
+                    run_chain(p, h, d, true, in128, out128, nr, st);
+                } else {
+                    launch_convert(in128, true, p->V3.p, false, cnt, st);
+                    run_chain(p, h, d, false, p->V3.p, p->W.p, nr, st);
+                    launch_convert(p->W.p, false, out128, true, cnt, st);
+                }
+            };
+            auto precond = [&](const void *r128, void *z128) {
+                if (!opts->precondition) {
+                    HIPC(hipMemcpyAsync(z128, r128, cnt * 16, hipMemcpyDeviceToDevice, st));
+                    return;
+                }
+                if (dbl) {
+                    HIPC(hipMemcpyAsync(z128, r128, cnt * 16, hipMemcpyDeviceToDevice, st));
+                    gd_inplace(p, true, z128, nr, st);
+                } else {
+                    launch_convert(r128, true, p->V3.p, false, cnt, st);
+                    gd_inplace(p, false, p->V3.p, nr, st);
+                    launch_convert(p->V3.p, false, z128, true, cnt, st);
+                }
+            };
+            double *rz = scal, *rzn = scal + 2 * nr, *pAp = scal + 4 * nr, *nrm = scal + 6 * nr;
+            const int64_t cap = reduce_partial_cap(N, nr);
+            apply_chain(p->adj, p->dadj, p->U.p, p->R.p);  // r = b = Kd^* u (x0 = 0)
+            launch_colnorm2(p->R.p, N, nr, (double *)p->red.p, cap, nrm, st);
+            std::vector<double> bnorm(nr);
+            HIPC(hipMemcpyAsync(bnorm.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+            launch_scale_zero(p->X.p, cnt, st);
+            precond(p->R.p, p->Z.p);
+            HIPC(hipMemcpyAsync(p->Pv.p, p->Z.p, cnt * 16, hipMemcpyDeviceToDevice, st));
+            launch_coldot(p->R.p, p->Z.p, N, nr, (double *)p->red.p, cap, rz, st);
+            HIPC(hipStreamSynchronize(st));
+            converged = false;
+            for (int it = 0; it < std::max(1, opts->maxit); ++it) {
+                apply_chain(p->host.fwd, p->dfwd, p->Pv.p, p->V2.p);
+                apply_chain(p->adj, p->dadj, p->V2.p, p->V1.p);  // Ap (complex128 in V1)
+                launch_coldot(p->Pv.p, p->V1.p, N, nr, (double *)p->red.p, cap, pAp, st);
+                launch_pcg_xr(p->X.p, p->R.p, p->Pv.p, p->V1.p, rz, pAp, N, nr, st);
+                ++iters;
+                launch_colnorm2(p->R.p, N, nr, (double *)p->red.p, cap, nrm, st);
+                HIPC(hipMemcpyAsync(hs.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+                HIPC(hipStreamSynchronize(st));
+                worst = 0;
+                for (int b = 0; b < nr; ++b) worst = std::max(worst, std::sqrt(hs[b] / std::max(bnorm[b], 1e-300)));
+                if (opts->tol > 0 && worst <= opts->tol) { converged = true; break; }
+                if (opts->tol == 0 && it + 1 == opts->maxit) { converged = true; break; }
+                precond(p->R.p, p->Z.p);
+                launch_coldot(p->R.p, p->Z.p, N, nr, (double *)p->red.p, cap, rzn, st);
+                launch_pcg_p(p->Pv.p, p->Z.p, rzn, rz, N, nr, st);
+                HIPC(hipMemcpyAsync(rz, rzn, 2 * nr * sizeof(double), hipMemcpyDeviceToDevice, st));
+            }
+        }
+        launch_scatter(p->X.p, true, perm, out, true, ld, N, nr, st);
+        if (info) {
+            HIPC(hipStreamSynchronize(st));
+            info->iters = iters;
+            info->rel_resid = worst;
+        }
+        if (!converged) fail(FIO_ERR_NOT_CONVERGED, "tolerance not reached within maxit");
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Shared host utilities: complex type, error reporting, a small thread pool loop.
+#pragma once
+
+#include <atomic>
+#include <complex>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fio.h"
+
+namespace fio {
+
+using cd = std::complex<double>;
+
+// Error carried from deep inside the build to the C ABI boundary.
+struct Error : std::runtime_error {
+    fio_status status;
+    Error(fio_status s, const std::string &msg) : std::runtime_error(msg), status(s) {}
+};
+
+[[noreturn]] inline void fail(fio_status s, const std::string &msg) { throw Error(s, msg); }
+
+inline int hw_threads(int requested) {
+    if (requested > 0) return requested;
+    unsigned h = std::thread::hardware_concurrency();
+    return h ? (int)h : 4;
+}
+
+// Run fn(i) for i in [0, n) on nthreads threads (dynamic scheduling).
+template <class Fn>
+void parallel_for(int64_t n, int nthreads, Fn &&fn) {
+    if (n <= 0) return;
+    int nt = (int)std::min<int64_t>(hw_threads(nthreads), n);
+    if (nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int64_t> next(0);
+    std::exception_ptr err = nullptr;
+    std::atomic<bool> failed(false);
+    auto work = [&]() {
+        try {
+            for (;;) {
+                int64_t i = next.fetch_add(1);
+                if (i >= n || failed.load()) break;
+                fn(i);
+            }
+        } catch (...) {
+            if (!failed.exchange(true)) err = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int t = 0; t < nt - 1; ++t) th.emplace_back(work);
+    work();
+    for (auto &t : th) t.join();
+    if (err) std::rethrow_exception(err);
+}
+
+// splitmix64: the builder's own counter-based generator for random probes.
+inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+}
+
+// Standard normal from two counter values (Box-Muller), deterministic in (seed, k).
+inline double gauss(uint64_t seed, uint64_t k) {
+    uint64_t a = splitmix64(seed ^ splitmix64(2 * k + 1));
+    uint64_t b = splitmix64(seed ^ splitmix64(2 * k + 2));
+    double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+    double u2 = (b >> 11) * (1.0 / 9007199254740992.0);           // [0, 1)
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+}
+
+}  // namespace fio

@@ -1,0 +1,62 @@
+// Hierarchical representation of S = Kd^* Kd and its inverse factors.
+//
+// 1D (section 3, "peeling algorithm for 1D HODLR matrices"; section 4, "1D case"):
+//   Sd = D + sum_l Ahat_l, each Ahat_l made of sibling blocks
+//   A_{l;(2p+1)(2p)} ~= U_{l;2p+1} B_{l;p} U_{l;2p}^* (0-based node numbers),
+//   and Gd = R_L .. R_1 A_0^{-1} R_1^* .. R_L^* (eqAinv_1d) from recursive
+//   skeletonization: per node, an interpolative decomposition of the stacked
+//   bases (eq_id, eq:ID_1d), the zeroing matrix Z (eq_sk) and a block
+//   Gaussian elimination E (eq_sk_3).
+//
+// One node factor Z_I E_I acts on the redundant DOFs r (I-tilde) and skeleton
+// DOFs s (I-hat) of a node:
+//   apply of (Z E)^*:  x_r -= T^* x_s;  x_r = Linv x_r;  x_s -= M x_r
+//   apply of  Z E   :  x_r = Linv^* (x_r - M^* x_s);  x_s -= T x_r
+// with Atilde_rr = L L^* (Cholesky), Linv = L^{-1} and M = Atilde_sr L^{-*}.
+#pragma once
+
+#include <functional>
+
+#include "la.hpp"
+
+namespace fio {
+
+struct HifNode {
+    std::vector<int> idx_r, idx_s;  // global DOF indices (Omega tree order)
+    Mat T;                          // ns x nr
+    Mat Linv;                       // nr x nr, lower triangular
+    Mat M;                          // ns x nr
+};
+
+struct HifStep {
+    std::vector<HifNode> nodes;     // disjoint index sets: factors commute
+};
+
+struct HifFactors {
+    int64_t N = 0;
+    std::vector<HifStep> steps;     // R_L first (the order of the upward sweep)
+    std::vector<int> root_idx;      // S_0
+    Mat A0inv;                      // inverse of the top-level block on S_0 (FP64)
+    int max_rank_h = 0;             // largest off-diagonal rank of Sd
+};
+
+// y = A x for nrhs vectors stored point-major (entry (e, b) at e*nrhs + b).
+using BlockApply = std::function<void(const cd *x, cd *y, int nrhs)>;
+
+struct PeelOptions {
+    double eps = 1e-6;      // relative tolerance (to ||S||_2) of the low-rank blocks
+    int leaf = 64;          // leaf size (1D points) / leaf side (2D)
+    int oversample = 10;    // c
+    int k0 = 16;            // initial rank guess k
+    uint64_t seed = 7;
+    int nthreads = 0;
+};
+
+// 1D HODLR peeling of a Hermitian operator given only by products (section 3),
+// followed by recursive skeletonization (section 4) with tolerance eps_hif.
+HifFactors build_hif_1d(const BlockApply &A, int64_t N, const PeelOptions &po, double eps_hif);
+
+// Largest eigenvalue estimate of a Hermitian positive operator by power iteration.
+double power_norm(const BlockApply &A, int64_t N, int iters, uint64_t seed);
+
+}  // namespace fio

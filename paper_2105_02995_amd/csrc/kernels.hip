@@ -1,0 +1,494 @@
+// gfx950 kernels of the factor applies: butterfly stages, skeletonization steps,
+// the top-level FP64 block, layout conversions and the FP64 vector updates of
+// iterative refinement and preconditioned CG.
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <stdexcept>
+#include <string>
+
+namespace fio {
+
+// ------------------------------------------------------------------ complex helpers
+__device__ __forceinline__ float2 cz(float2) { return make_float2(0.f, 0.f); }
+__device__ __forceinline__ double2 cz(double2) { return make_double2(0.0, 0.0); }
+
+// acc + a*b
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+    return acc;
+}
+__device__ __forceinline__ double2 cfma(double2 acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+// acc + conj(a)*b
+__device__ __forceinline__ float2 cfmac(float2 acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(-a.y, b.x, acc.y);
+    return acc;
+}
+__device__ __forceinline__ double2 cfmac(double2 acc, double2 a, double2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+template <class T> __device__ __forceinline__ T csub(T a, T b) {
+    a.x -= b.x;
+    a.y -= b.y;
+    return a;
+}
+template <class To, class Ti> __device__ __forceinline__ To cvt(Ti v);
+template <> __device__ __forceinline__ float2 cvt<float2, float2>(float2 v) { return v; }
+template <> __device__ __forceinline__ double2 cvt<double2, double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float2 cvt<float2, double2>(double2 v) {
+    return make_float2((float)v.x, (float)v.y);
+}
+template <> __device__ __forceinline__ double2 cvt<double2, float2>(float2 v) {
+    return make_double2((double)v.x, (double)v.y);
+}
+
+static void check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static unsigned grid_for(int64_t work, int block) {
+    int64_t g = (work + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 30));
+}
+
+// ------------------------------------------------------------------ butterfly stage
+// One thread per output entry (o, a, b), b fastest: the factor entry is shared by
+// the nrhs lanes of one row and the gathered input is read coalesced across b.
+template <class T>
+__global__ void __launch_bounds__(256) k_stage(int64_t n_out, int r_out, int r_in, int fan,
+                                               const int32_t *__restrict__ idx,
+                                               const T *__restrict__ A, const T *__restrict__ x,
+                                               T *__restrict__ y, int nrhs) {
+    const int64_t total = n_out * r_out * (int64_t)nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const int64_t t2 = t / nrhs;
+        const int a = (int)(t2 % r_out);
+        const int64_t o = t2 / r_out;
+        const T *Ao = A + o * (int64_t)r_out * fan * r_in + a;
+        T acc = cz(T());
+        for (int q = 0; q < fan; ++q) {
+            const T *xin = x + (int64_t)idx[o * fan + q] * r_in * nrhs + b;
+            const T *Aq = Ao + (int64_t)q * r_in * r_out;
+            for (int e = 0; e < r_in; ++e) acc = cfma(acc, Aq[(int64_t)e * r_out], xin[(int64_t)e * nrhs]);
+        }
+        y[t] = acc;
+    }
+}
+
+void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st) {
+    const int64_t work = s.n_out * s.r_out * (int64_t)nrhs;
+    const unsigned g = grid_for(work, 256);
+    if (dbl)
+        hipLaunchKernelGGL(k_stage<double2>, dim3(g), dim3(256), 0, st, s.n_out, s.r_out, s.r_in,
+                           s.fan, s.idx, (const double2 *)s.A, (const double2 *)x, (double2 *)y, nrhs);
+    else
+        hipLaunchKernelGGL(k_stage<float2>, dim3(g), dim3(256), 0, st, s.n_out, s.r_out, s.r_in,
+                           s.fan, s.idx, (const float2 *)s.A, (const float2 *)x, (float2 *)y, nrhs);
+    check_launch("stage");
+}
+
+// ------------------------------------------------------------------ skeletonization steps
+// One workgroup per node; the node's entries of x are gathered into LDS for a
+// chunk of right-hand sides, transformed, and scattered back.  Nodes of one step
+// own disjoint index sets, so workgroups never touch the same entries.
+template <class T, bool UP>
+__global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
+                                             const int32_t *__restrict__ idx,
+                                             const T *__restrict__ mat, T *__restrict__ x,
+                                             int nrhs, int bchunk) {
+    extern __shared__ char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
+    const int64_t v = blockIdx.x;
+    const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
+    const int32_t *ir = idx + desc[4 * v + 2];
+    const int32_t *is = ir + nr;
+    const T *Tm = mat + desc[4 * v + 3];        // ns x nr
+    const T *Li = Tm + (int64_t)ns * nr;        // nr x nr (lower)
+    const T *Mm = Li + (int64_t)nr * nr;        // ns x nr
+    for (int b0 = 0; b0 < nrhs; b0 += bchunk) {
+        const int bc = min(bchunk, nrhs - b0);
+        T *xr = sm, *xs = sm + nr * bc, *y = xs + ns * bc;
+        for (int e = threadIdx.x; e < (nr + ns) * bc; e += blockDim.x) {
+            const int i = e / bc, b = e % bc;
+            const int64_t g = (i < nr) ? ir[i] : is[i - nr];
+            xr[e] = x[g * nrhs + b0 + b];  // xr and xs are contiguous in LDS
+        }
+        __syncthreads();
+        if (UP) {
+            // x_r -= T^* x_s
+            for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
+                const int i = e / bc, b = e % bc;
+                T acc = cz(T());
+                for (int k = 0; k < ns; ++k) acc = cfmac(acc, Tm[k + (int64_t)i * ns], xs[k * bc + b]);
+                xr[e] = csub(xr[e], acc);
+            }
+            __syncthreads();
+            // y = Linv x_r
+            for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
+                const int i = e / bc, b = e % bc;
+                T acc = cz(T());
+                for (int k = 0; k <= i; ++k) acc = cfma(acc, Li[i + (int64_t)k * nr], xr[k * bc + b]);
+                y[e] = acc;
+            }
+            __syncthreads();
+            // x_s -= M y
+            for (int e = threadIdx.x; e < ns * bc; e += blockDim.x) {
+                const int k = e / bc, b = e % bc;
+                T acc = cz(T());
+                for (int i = 0; i < nr; ++i) acc = cfma(acc, Mm[k + (int64_t)i * ns], y[i * bc + b]);
+                xs[e] = csub(xs[e], acc);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < (nr + ns) * bc; e += blockDim.x) {
+                const int i = e / bc, b = e % bc;
+                if (i < nr) x[(int64_t)ir[i] * nrhs + b0 + b] = y[e];
+                else x[(int64_t)is[i - nr] * nrhs + b0 + b] = xs[e - nr * bc];
+            }
+        } else {
+            // y = x_r - M^* x_s
+            for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
+                const int i = e / bc, b = e % bc;
+                T acc = cz(T());
+                for (int k = 0; k < ns; ++k) acc = cfmac(acc, Mm[k + (int64_t)i * ns], xs[k * bc + b]);
+                y[e] = csub(xr[e], acc);
+            }
+            __syncthreads();
+            // x_r = Linv^* y
+            for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
+                const int i = e / bc, b = e % bc;
+                T acc = cz(T());
+                for (int k = i; k < nr; ++k) acc = cfmac(acc, Li[k + (int64_t)i * nr], y[k * bc + b]);
+                xr[e] = acc;
+            }
+            __syncthreads();
+            // x_s -= T x_r
+            for (int e = threadIdx.x; e < ns * bc; e += blockDim.x) {
+                const int k = e / bc, b = e % bc;
+                T acc = cz(T());
+                for (int i = 0; i < nr; ++i) acc = cfma(acc, Tm[k + (int64_t)i * ns], xr[i * bc + b]);
+                xs[e] = csub(xs[e], acc);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < (nr + ns) * bc; e += blockDim.x) {
+                const int i = e / bc, b = e % bc;
+                if (i < nr) x[(int64_t)ir[i] * nrhs + b0 + b] = xr[e];
+                else x[(int64_t)is[i - nr] * nrhs + b0 + b] = xs[e - nr * bc];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+static const int HIF_LDS = 64 * 1024;
+
+void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
+    if (h.n_nodes == 0) return;
+    const int elt = dbl ? 16 : 8;
+    const int per = 2 * h.max_nr + h.max_ns;
+    int bchunk = per > 0 ? HIF_LDS / (per * elt) : nrhs;
+    bchunk = std::max(1, std::min(bchunk, nrhs));
+    if (per * elt * bchunk > HIF_LDS) throw std::runtime_error("skeletonization node exceeds LDS");
+    const size_t lds = (size_t)std::max(1, per) * elt * bchunk;
+    const dim3 g((unsigned)h.n_nodes), b(256);
+    if (dbl) {
+        if (up) hipLaunchKernelGGL((k_hif<double2, true>), g, b, lds, st, h.desc, h.idx, (const double2 *)h.mat, (double2 *)x, nrhs, bchunk);
+        else hipLaunchKernelGGL((k_hif<double2, false>), g, b, lds, st, h.desc, h.idx, (const double2 *)h.mat, (double2 *)x, nrhs, bchunk);
+    } else {
+        if (up) hipLaunchKernelGGL((k_hif<float2, true>), g, b, lds, st, h.desc, h.idx, (const float2 *)h.mat, (float2 *)x, nrhs, bchunk);
+        else hipLaunchKernelGGL((k_hif<float2, false>), g, b, lds, st, h.desc, h.idx, (const float2 *)h.mat, (float2 *)x, nrhs, bchunk);
+    }
+    check_launch("hif step");
+}
+
+// ------------------------------------------------------------------ top-level block (FP64)
+template <class T>
+__global__ void __launch_bounds__(256) k_root(const int32_t *__restrict__ idx,
+                                              const double2 *__restrict__ A, int s0,
+                                              T *__restrict__ x, int nrhs) {
+    extern __shared__ char smem_raw[];
+    double2 *v = reinterpret_cast<double2 *>(smem_raw);
+    const int b = blockIdx.x;
+    for (int i = threadIdx.x; i < s0; i += blockDim.x) v[i] = cvt<double2, T>(x[(int64_t)idx[i] * nrhs + b]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < s0; i += blockDim.x) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = 0; k < s0; ++k) acc = cfma(acc, A[i + (int64_t)k * s0], v[k]);
+        x[(int64_t)idx[i] * nrhs + b] = cvt<T, double2>(acc);
+    }
+}
+
+void launch_root(const int32_t *idx, const void *A0inv, int s0, bool dbl, void *x, int nrhs,
+                 hipStream_t st) {
+    if (s0 == 0) return;
+    if ((size_t)s0 * 16 > 64 * 1024) throw std::runtime_error("top-level block exceeds LDS");
+    const size_t lds = (size_t)s0 * 16;
+    if (dbl) hipLaunchKernelGGL(k_root<double2>, dim3(nrhs), dim3(256), lds, st, idx, (const double2 *)A0inv, s0, (double2 *)x, nrhs);
+    else hipLaunchKernelGGL(k_root<float2>, dim3(nrhs), dim3(256), lds, st, idx, (const double2 *)A0inv, s0, (float2 *)x, nrhs);
+    check_launch("root");
+}
+
+// ------------------------------------------------------------------ layout conversion
+template <class Tu, class Ti>
+__global__ void __launch_bounds__(256) k_gather(const Tu *__restrict__ user, int64_t ld,
+                                                const int32_t *__restrict__ perm,
+                                                Ti *__restrict__ out, int64_t n, int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const int64_t p = t / nrhs;
+        const int64_t src = perm ? perm[p] : p;
+        out[t] = cvt<Ti, Tu>(user[src + b * ld]);
+    }
+}
+template <class Ti, class Tu>
+__global__ void __launch_bounds__(256) k_scatter(const Ti *__restrict__ in,
+                                                 const int32_t *__restrict__ perm,
+                                                 Tu *__restrict__ user, int64_t ld, int64_t n,
+                                                 int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const int64_t p = t / nrhs;
+        const int64_t dst = perm ? perm[p] : p;
+        user[dst + b * ld] = cvt<Tu, Ti>(in[t]);
+    }
+}
+
+void launch_gather(const void *user, bool ud, int64_t ld, const int32_t *perm, void *internal,
+                   bool id, int64_t n, int nrhs, hipStream_t st) {
+    const unsigned g = grid_for(n * nrhs, 256);
+    if (ud && id) hipLaunchKernelGGL((k_gather<double2, double2>), dim3(g), dim3(256), 0, st, (const double2 *)user, ld, perm, (double2 *)internal, n, nrhs);
+    else if (ud && !id) hipLaunchKernelGGL((k_gather<double2, float2>), dim3(g), dim3(256), 0, st, (const double2 *)user, ld, perm, (float2 *)internal, n, nrhs);
+    else if (!ud && id) hipLaunchKernelGGL((k_gather<float2, double2>), dim3(g), dim3(256), 0, st, (const float2 *)user, ld, perm, (double2 *)internal, n, nrhs);
+    else hipLaunchKernelGGL((k_gather<float2, float2>), dim3(g), dim3(256), 0, st, (const float2 *)user, ld, perm, (float2 *)internal, n, nrhs);
+    check_launch("gather");
+}
+
+void launch_scatter(const void *internal, bool id, const int32_t *perm, void *user, bool ud,
+                    int64_t ld, int64_t n, int nrhs, hipStream_t st) {
+    const unsigned g = grid_for(n * nrhs, 256);
+    if (ud && id) hipLaunchKernelGGL((k_scatter<double2, double2>), dim3(g), dim3(256), 0, st, (const double2 *)internal, perm, (double2 *)user, ld, n, nrhs);
+    else if (ud && !id) hipLaunchKernelGGL((k_scatter<float2, double2>), dim3(g), dim3(256), 0, st, (const float2 *)internal, perm, (double2 *)user, ld, n, nrhs);
+    else if (!ud && id) hipLaunchKernelGGL((k_scatter<double2, float2>), dim3(g), dim3(256), 0, st, (const double2 *)internal, perm, (float2 *)user, ld, n, nrhs);
+    else hipLaunchKernelGGL((k_scatter<float2, float2>), dim3(g), dim3(256), 0, st, (const float2 *)internal, perm, (float2 *)user, ld, n, nrhs);
+    check_launch("scatter");
+}
+
+template <class Ts, class Td>
+__global__ void __launch_bounds__(256) k_convert(const Ts *__restrict__ s, Td *__restrict__ d, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        d[t] = cvt<Td, Ts>(s[t]);
+}
+
+void launch_convert(const void *src, bool sd, void *dst, bool dd, int64_t count, hipStream_t st) {
+    const unsigned g = grid_for(count, 256);
+    if (sd && dd) hipLaunchKernelGGL((k_convert<double2, double2>), dim3(g), dim3(256), 0, st, (const double2 *)src, (double2 *)dst, count);
+    else if (sd) hipLaunchKernelGGL((k_convert<double2, float2>), dim3(g), dim3(256), 0, st, (const double2 *)src, (float2 *)dst, count);
+    else if (dd) hipLaunchKernelGGL((k_convert<float2, double2>), dim3(g), dim3(256), 0, st, (const float2 *)src, (double2 *)dst, count);
+    else hipLaunchKernelGGL((k_convert<float2, float2>), dim3(g), dim3(256), 0, st, (const float2 *)src, (float2 *)dst, count);
+    check_launch("convert");
+}
+
+// ------------------------------------------------------------------ FP64 vector updates
+template <class Td>
+__global__ void __launch_bounds__(256) k_residual(const double2 *__restrict__ u, const double2 *__restrict__ y,
+                                                  Td *__restrict__ d, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        d[t] = cvt<Td, double2>(csub(u[t], y[t]));
+}
+
+void launch_residual(const void *u, const void *y, void *dst, bool dd, int64_t count, hipStream_t st) {
+    const unsigned g = grid_for(count, 256);
+    if (dd) hipLaunchKernelGGL(k_residual<double2>, dim3(g), dim3(256), 0, st, (const double2 *)u, (const double2 *)y, (double2 *)dst, count);
+    else hipLaunchKernelGGL(k_residual<float2>, dim3(g), dim3(256), 0, st, (const double2 *)u, (const double2 *)y, (float2 *)dst, count);
+    check_launch("residual");
+}
+
+template <class Ts>
+__global__ void __launch_bounds__(256) k_axpy(double2 *__restrict__ x, const Ts *__restrict__ d, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        double2 v = cvt<double2, Ts>(d[t]);
+        double2 a = x[t];
+        a.x += v.x;
+        a.y += v.y;
+        x[t] = a;
+    }
+}
+
+void launch_axpy_update(void *x, const void *d, bool dd, int64_t count, hipStream_t st) {
+    const unsigned g = grid_for(count, 256);
+    if (dd) hipLaunchKernelGGL(k_axpy<double2>, dim3(g), dim3(256), 0, st, (double2 *)x, (const double2 *)d, count);
+    else hipLaunchKernelGGL(k_axpy<float2>, dim3(g), dim3(256), 0, st, (double2 *)x, (const float2 *)d, count);
+    check_launch("axpy");
+}
+
+// Deterministic two-pass per-column reductions.  Pass 1: workgroup (g, bt) sums
+// rows [g*chunk, (g+1)*chunk) for columns [bt*bw, bt*bw + bw) into partial[col][g];
+// pass 2 adds the partials of each column in a fixed order.
+static const int RED_G = 64;
+
+int64_t reduce_partial_cap(int64_t n, int nrhs) { return (int64_t)RED_G * nrhs * 2; }
+
+template <bool DOT>
+__global__ void __launch_bounds__(256) k_colred1(const double2 *__restrict__ a, const double2 *__restrict__ c,
+                                                 int64_t n, int nrhs, double *__restrict__ partial) {
+    __shared__ double sre[256], sim[256];
+    const int bw = min(nrhs, 256);
+    const int col0 = blockIdx.y * bw;
+    const int lanes = min(bw, nrhs - col0);
+    const int rows_per = 256 / bw;
+    const int tb = threadIdx.x % bw, tr = threadIdx.x / bw;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+    double s_re = 0, s_im = 0;
+    if (tb < lanes && tr < rows_per) {
+        const int col = col0 + tb;
+        for (int64_t r = r0 + tr; r < r1; r += rows_per) {
+            const double2 va = a[r * nrhs + col];
+            if (DOT) {
+                const double2 vc = c[r * nrhs + col];
+                s_re += va.x * vc.x + va.y * vc.y;
+                s_im += va.x * vc.y - va.y * vc.x;
+            } else {
+                s_re += va.x * va.x + va.y * va.y;
+            }
+        }
+    }
+    sre[threadIdx.x] = s_re;
+    sim[threadIdx.x] = s_im;
+    __syncthreads();
+    if (tr == 0 && tb < lanes) {
+        double tre = 0, tim = 0;
+        for (int q = 0; q < rows_per; ++q) {
+            tre += sre[q * bw + tb];
+            tim += sim[q * bw + tb];
+        }
+        const int col = col0 + tb;
+        partial[((int64_t)col * gridDim.x + blockIdx.x) * 2] = tre;
+        partial[((int64_t)col * gridDim.x + blockIdx.x) * 2 + 1] = tim;
+    }
+}
+
+template <bool DOT>
+__global__ void k_colred2(const double *__restrict__ partial, int G, int nrhs, double *__restrict__ out) {
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= nrhs) return;
+    double re = 0, im = 0;
+    for (int g = 0; g < G; ++g) {
+        re += partial[((int64_t)col * G + g) * 2];
+        im += partial[((int64_t)col * G + g) * 2 + 1];
+    }
+    if (DOT) {
+        out[2 * col] = re;
+        out[2 * col + 1] = im;
+    } else {
+        out[col] = re;
+    }
+}
+
+static void colred(bool dot, const void *a, const void *c, int64_t n, int nrhs, double *partial,
+                   int64_t cap, double *out, hipStream_t st) {
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(RED_G, (n + 1023) / 1024));
+    if ((int64_t)G * nrhs * 2 > cap) throw std::runtime_error("reduction workspace too small");
+    const int bw = std::min(nrhs, 256);
+    const dim3 g1(G, (nrhs + bw - 1) / bw);
+    if (dot) hipLaunchKernelGGL(k_colred1<true>, g1, dim3(256), 0, st, (const double2 *)a, (const double2 *)c, n, nrhs, partial);
+    else hipLaunchKernelGGL(k_colred1<false>, g1, dim3(256), 0, st, (const double2 *)a, (const double2 *)a, n, nrhs, partial);
+    const dim3 g2((nrhs + 63) / 64);
+    if (dot) hipLaunchKernelGGL(k_colred2<true>, g2, dim3(64), 0, st, partial, G, nrhs, out);
+    else hipLaunchKernelGGL(k_colred2<false>, g2, dim3(64), 0, st, partial, G, nrhs, out);
+    check_launch("column reduction");
+}
+
+void launch_colnorm2(const void *v, int64_t n, int nrhs, double *partial, int64_t cap, double *out,
+                     hipStream_t st) {
+    colred(false, v, v, n, nrhs, partial, cap, out, st);
+}
+
+void launch_coldot(const void *a, const void *c, int64_t n, int nrhs, double *partial, int64_t cap,
+                   double *out, hipStream_t st) {
+    colred(true, a, c, n, nrhs, partial, cap, out, st);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double den = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
+}
+
+__global__ void __launch_bounds__(256) k_pcg_xr(double2 *__restrict__ x, double2 *__restrict__ r,
+                                                const double2 *__restrict__ p, const double2 *__restrict__ Ap,
+                                                const double *__restrict__ rz, const double *__restrict__ pAp,
+                                                int64_t n, int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const double2 al = cdiv(make_double2(rz[2 * b], rz[2 * b + 1]), make_double2(pAp[2 * b], pAp[2 * b + 1]));
+        const double2 pv = p[t], av = Ap[t];
+        double2 xv = x[t], rv = r[t];
+        xv.x += al.x * pv.x - al.y * pv.y;
+        xv.y += al.x * pv.y + al.y * pv.x;
+        rv.x -= al.x * av.x - al.y * av.y;
+        rv.y -= al.x * av.y + al.y * av.x;
+        x[t] = xv;
+        r[t] = rv;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pcg_p(double2 *__restrict__ p, const double2 *__restrict__ z,
+                                               const double *__restrict__ rzn, const double *__restrict__ rzo,
+                                               int64_t n, int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const double2 be = cdiv(make_double2(rzn[2 * b], rzn[2 * b + 1]), make_double2(rzo[2 * b], rzo[2 * b + 1]));
+        const double2 pv = p[t], zv = z[t];
+        p[t] = make_double2(zv.x + be.x * pv.x - be.y * pv.y, zv.y + be.x * pv.y + be.y * pv.x);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero(double2 *__restrict__ x, int64_t n) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        x[t] = make_double2(0.0, 0.0);
+}
+
+void launch_scale_zero(void *x, int64_t count, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(count, 256)), dim3(256), 0, st, (double2 *)x, count);
+    check_launch("zero");
+}
+
+void launch_pcg_xr(void *x, void *r, const void *p, const void *Ap, const double *rz, const double *pAp,
+                   int64_t n, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_xr, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, st, (double2 *)x, (double2 *)r,
+                       (const double2 *)p, (const double2 *)Ap, rz, pAp, n, nrhs);
+    check_launch("pcg x/r update");
+}
+
+void launch_pcg_p(void *p, const void *z, const double *rzn, const double *rzo, int64_t n, int nrhs,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_p, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, st, (double2 *)p,
+                       (const double2 *)z, rzn, rzo, n, nrhs);
+    check_launch("pcg p update");
+}
+
+}  // namespace fio

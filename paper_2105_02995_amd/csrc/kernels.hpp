@@ -1,0 +1,63 @@
+// Device kernels (gfx950) of the factor applies and their launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fio {
+
+// One butterfly stage on nrhs vectors stored point-major ([block][row][rhs]):
+//   y_o = sum_t A_{o,t} x_{in_idx[o*fan+t]}   (blocks column-major r_out x fan*r_in).
+struct StageDev {
+    int64_t n_out = 0, n_in = 0;
+    int r_out = 0, r_in = 0, fan = 0;
+    const int32_t *idx = nullptr;
+    const void *A = nullptr;   // float2 (c64) or double2 (c128)
+};
+
+// Node factor table of one skeletonization step: per node
+// {nr, ns, idx_off, mat_off}; idx holds idx_r then idx_s; mat holds T (ns x nr),
+// Linv (nr x nr), M (ns x nr), column-major, one after the other.
+struct HifStepDev {
+    int64_t n_nodes = 0;
+    int max_nr = 0, max_ns = 0;
+    const int64_t *desc = nullptr;
+    const int32_t *idx = nullptr;
+    const void *mat = nullptr;
+};
+
+void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st);
+void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st);
+void launch_root(const int32_t *idx, const void *A0inv, int s0, bool dbl, void *x, int nrhs,
+                 hipStream_t st);
+// internal[t*nrhs + b] = user[perm[t] + b*ld] (perm may be null), with conversion.
+void launch_gather(const void *user, bool user_dbl, int64_t ld, const int32_t *perm, void *internal,
+                   bool int_dbl, int64_t n, int nrhs, hipStream_t st);
+void launch_scatter(const void *internal, bool int_dbl, const int32_t *perm, void *user,
+                    bool user_dbl, int64_t ld, int64_t n, int nrhs, hipStream_t st);
+// dst = src (contiguous), with conversion.
+void launch_convert(const void *src, bool src_dbl, void *dst, bool dst_dbl, int64_t count,
+                    hipStream_t st);
+// r = u - y (complex128 u, y) written as dst dtype.
+void launch_residual(const void *u, const void *y, void *dst, bool dst_dbl, int64_t count,
+                     hipStream_t st);
+// x += d (x complex128, d of dtype).
+void launch_axpy_update(void *x, const void *d, bool d_dbl, int64_t count, hipStream_t st);
+// Per-column squared norms of an n x nrhs point-major complex128 block: out[b] (double).
+void launch_colnorm2(const void *v, int64_t n, int nrhs, double *partial, int64_t partial_cap,
+                     double *out, hipStream_t st);
+// Per-column dots <a_b, c_b> (conj(a) c) of complex128 blocks: out[2b], out[2b+1] = re, im.
+void launch_coldot(const void *a, const void *c, int64_t n, int nrhs, double *partial,
+                   int64_t partial_cap, double *out, hipStream_t st);
+// PCG vector updates (complex128, per-column scalars on the device).
+void launch_pcg_xr(void *x, void *r, const void *p, const void *Ap, const double *rz,
+                   const double *pAp, int64_t n, int nrhs, hipStream_t st);
+void launch_pcg_p(void *p, const void *z, const double *rz_new, const double *rz_old, int64_t n,
+                  int nrhs, hipStream_t st);
+
+int64_t reduce_partial_cap(int64_t n, int nrhs);
+// x = 0 (complex128), by a fill kernel (no memset node if the stream is captured).
+void launch_scale_zero(void *x, int64_t count, hipStream_t st);
+
+}  // namespace fio

@@ -1,0 +1,35 @@
+// The plan: host copies of the factors (for save/load) and their device images.
+#pragma once
+
+#include <string>
+
+#include "butterfly.hpp"
+#include "hif.hpp"
+
+namespace fio {
+
+// Host-side factor set: everything needed to reproduce the device images.
+struct HostFactors {
+    int d = 1, n = 0;
+    int64_t N = 0;
+    int L = 0, Lm = 0, m = 0;
+    std::vector<int> perm;          // tree position -> natural index (X and Omega)
+    std::vector<Stage> fwd;         // Kd stages (Omega tree order -> X tree order)
+    HifFactors hif;                 // Gd factors (Omega tree order)
+    fio_problem prob{};             // build description
+    double build_seconds = 0;
+};
+
+// Builds the factors on the host; `gpu_apply` (may be empty) replaces the host
+// product Kd^* Kd of the peeling step.
+using PeelApplyFactory = std::function<BlockApply(const std::vector<Stage> &fwd,
+                                                  const std::vector<Stage> &adj)>;
+void build_host_factors(const fio_problem &p, HostFactors &out, const PeelApplyFactory &gpu);
+
+void save_factors(const HostFactors &f, const std::string &path);
+void load_factors(const std::string &path, HostFactors &f);
+
+// Fills defaults of a problem description and validates it.
+fio_problem normalized_problem(const fio_problem &p);
+
+}  // namespace fio

@@ -1,0 +1,204 @@
+"""ctypes binding of libfio.so: the C ABI of include/fio.h with the same names.
+
+Argument marshalling only.  Vector arguments may be torch tensors (their device
+pointer is passed) or raw integer device addresses.  Every computation happens
+in the library's HIP kernels; if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfio.so")
+
+FIO_OK = 0
+STATUS = {0: "FIO_OK", 1: "FIO_ERR_ARG", 2: "FIO_ERR_NOMEM", 3: "FIO_ERR_DEVICE",
+          4: "FIO_ERR_NOT_HPD", 5: "FIO_ERR_NOT_CONVERGED", 6: "FIO_ERR_UNSUPPORTED",
+          7: "FIO_ERR_IO"}
+FIO_C64, FIO_C128 = 0, 1
+FIO_OP_K, FIO_OP_KH = 0, 1
+FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON = 0, 1, 2
+FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG = 0, 1, 2
+PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON}
+
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
+           "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
+           "fio_last_error"]
+
+
+class FioError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class fio_problem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("phase", ctypes.c_int),
+                ("c_div", ctypes.c_double), ("eps", ctypes.c_double),
+                ("eps_bf", ctypes.c_double), ("eps_peel", ctypes.c_double),
+                ("eps_hif", ctypes.c_double), ("leaf_bf", ctypes.c_int),
+                ("leaf_h", ctypes.c_int), ("oversample", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("device", ctypes.c_int), ("nthreads", ctypes.c_int)]
+
+
+class fio_solve_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("precondition", ctypes.c_int)]
+
+
+class fio_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_resid", ctypes.c_double)]
+
+
+class fio_plan_stats_t(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("L", ctypes.c_int),
+                ("L_mid", ctypes.c_int), ("n_stages", ctypes.c_int),
+                ("bf_nnz", ctypes.c_int64), ("max_rank_bf", ctypes.c_int),
+                ("hif_levels", ctypes.c_int), ("hif_nnz", ctypes.c_int64),
+                ("root_size", ctypes.c_int), ("max_rank_h", ctypes.c_int),
+                ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("build_seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfio.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfio.so is not built; run paper_2105_02995_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, VP = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+    lib.fio_build.argtypes = [ctypes.POINTER(fio_problem), ctypes.POINTER(P)]
+    lib.fio_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_inverse_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_gd_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_solve.argtypes = [P, ctypes.POINTER(fio_solve_opts), ctypes.c_int, VP, VP, I64, I64,
+                              ctypes.POINTER(fio_solve_info), VP]
+    lib.fio_plan_stats.argtypes = [P, ctypes.POINTER(fio_plan_stats_t)]
+    lib.fio_stage_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_int)]
+    lib.fio_save.argtypes = [P, ctypes.c_char_p]
+    lib.fio_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P)]
+    lib.fio_destroy.argtypes = [P]
+    lib.fio_destroy.restype = None
+    lib.fio_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("fio_destroy", "fio_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != FIO_OK:
+        raise FioError(rc, load_library().fio_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+class Plan:
+    """Owner of a fio_plan handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            load_library().fio_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_problem(d, n, phase="1d_ex1", eps=1e-6, c_div=16.0, device=0, **kw) -> fio_problem:
+    p = fio_problem()
+    p.d, p.n = d, n
+    p.phase = PHASES[phase] if isinstance(phase, str) else int(phase)
+    p.c_div, p.eps, p.device = c_div, eps, device
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def fio_build(problem: fio_problem) -> Plan:
+    h = ctypes.c_void_p()
+    _check(load_library().fio_build(ctypes.byref(problem), ctypes.byref(h)))
+    return Plan(h)
+
+
+def fio_load(path: str, device: int = 0) -> Plan:
+    h = ctypes.c_void_p()
+    _check(load_library().fio_load(path.encode(), device, ctypes.byref(h)))
+    return Plan(h)
+
+
+def fio_save(plan: Plan, path: str):
+    _check(load_library().fio_save(plan.handle, path.encode()))
+
+
+def fio_destroy(plan: Plan):
+    plan.close()
+
+
+def fio_apply(plan: Plan, op: int, dtype: int, x, y, nrhs: int, ld: int, stream=None):
+    _check(load_library().fio_apply(plan.handle, op, dtype, _ptr(x), _ptr(y), nrhs, ld,
+                                    _stream(stream)))
+
+
+def fio_inverse_apply(plan: Plan, dtype: int, u, fhat, nrhs: int, ld: int, stream=None):
+    _check(load_library().fio_inverse_apply(plan.handle, dtype, _ptr(u), _ptr(fhat), nrhs, ld,
+                                            _stream(stream)))
+
+
+def fio_gd_apply(plan: Plan, dtype: int, x, y, nrhs: int, ld: int, stream=None):
+    _check(load_library().fio_gd_apply(plan.handle, dtype, _ptr(x), _ptr(y), nrhs, ld,
+                                       _stream(stream)))
+
+
+def fio_solve(plan: Plan, mode: int, dtype: int, u, out, nrhs: int, ld: int, tol: float = 0.0,
+              maxit: int = 0, precondition: int = 1, stream=None, want_info: bool = True):
+    o = fio_solve_opts(mode, tol, maxit, precondition)
+    info = fio_solve_info()
+    _check(load_library().fio_solve(plan.handle, ctypes.byref(o), dtype, _ptr(u), _ptr(out), nrhs,
+                                    ld, ctypes.byref(info) if want_info else None,
+                                    _stream(stream)))
+    return (info.iters, info.rel_resid) if want_info else None
+
+
+def fio_plan_stats(plan: Plan) -> dict:
+    s = fio_plan_stats_t()
+    _check(load_library().fio_plan_stats(plan.handle, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in s._fields_}
+
+
+def fio_stage_info(plan: Plan, stage: int) -> dict:
+    nnz, nob = ctypes.c_int64(), ctypes.c_int64()
+    ro, ri, fan = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load_library().fio_stage_info(plan.handle, stage, ctypes.byref(nnz), ctypes.byref(nob),
+                                         ctypes.byref(ro), ctypes.byref(ri), ctypes.byref(fan)))
+    return {"nnz": nnz.value, "n_out": nob.value, "r_out": ro.value, "r_in": ri.value,
+            "fan": fan.value}

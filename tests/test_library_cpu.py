@@ -1,0 +1,124 @@
+"""CPU tests of the C ABI library: symbols, argument checks and the host-side
+factor construction (plans built with device = -1 are never applied on the CPU;
+their saved factors are multiplied out with NumPy here).
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fio_synth import gaussian_complex
+from paper_2105_02995_amd import fio as F
+
+from . import factor_file as FF
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return F.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "fio.h")).read()
+    declared = set(re.findall(r"\b(fio_[a-z_]+)\s*\(", hdr))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(F.EXPORTS)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(d=3, n=64), 1),
+    (dict(d=1, n=100), 1),
+    (dict(d=1, n=256, eps=1.5), 1),
+    (dict(d=1, n=256, eps=0.0), 1),
+    (dict(d=2, n=64, phase="1d_ex1"), 1),
+    (dict(d=1, n=256, phase="2d_radon"), 1),
+])
+def test_build_rejects_bad_arguments(lib, kw, status):
+    args = dict(d=1, n=256, phase="1d_ex1", eps=1e-6, device=-1)
+    args.update(kw)
+    with pytest.raises(F.FioError) as e:
+        F.fio_build(F.make_problem(**args))
+    assert e.value.status == status
+
+
+def _host_plan(tmp_path, n=256, phase="1d_ex1", eps=1e-6, **kw):
+    plan = F.fio_build(F.make_problem(1, n, phase, eps=eps, device=-1, **kw))
+    path = str(tmp_path / "plan.fio")
+    F.fio_save(plan, path)
+    return plan, FF.read(path), path
+
+
+def test_host_only_plan_refuses_applies(tmp_path):
+    plan, _, _ = _host_plan(tmp_path)
+    with pytest.raises(F.FioError) as e:
+        F.fio_apply(plan, F.FIO_OP_K, F.FIO_C128, 1, 1, 1, 256)
+    assert e.value.status == 6
+    with pytest.raises(F.FioError):
+        F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C64, 1, 1, 1, 256)
+
+
+def test_butterfly_accuracy_against_oracle(tmp_path):
+    """e_a = ||K - Kd|| / ||K|| (section 6) on random vectors, eps_bf = eps/10."""
+    eps = 1e-6
+    plan, f, _ = _host_plan(tmp_path, eps=eps)
+    st = F.fio_plan_stats(plan)
+    assert st["n_stages"] == st["L"] + 3
+    p = O.OracleProblem(1, 256, "1d_ex1", 16.0)
+    K = O.dense_K(p)
+    x = gaussian_complex((256, 4), 11)
+    assert O.rel_err(FF.apply_K(f, x), K @ x).max() < eps
+    assert O.rel_err(FF.apply_KH(f, x), K.conj().T @ x).max() < eps
+
+
+def test_direct_inverse_within_ten_eps(tmp_path):
+    """Gd Kd^* u against the oracle's LU solve: <= 10 eps (section 5, eq:pseudoinv)."""
+    eps = 1e-6
+    _, f, _ = _host_plan(tmp_path, eps=eps)
+    p = O.OracleProblem(1, 256, "1d_ex1", 16.0)
+    K = O.dense_K(p)
+    fs = gaussian_complex((256, 3), 1000)
+    u = K @ O.dft(fs, 1, 256)
+    ref = O.solve_dense(p, u, K)
+    assert O.rel_err(FF.inverse(f, u), ref).max() < 10 * eps
+
+
+def test_gd_is_hermitian_positive(tmp_path):
+    _, f, _ = _host_plan(tmp_path)
+    x = gaussian_complex(256, 3)
+    y = gaussian_complex(256, 4)
+    a = np.vdot(y, FF.gd(f, x))
+    b = np.vdot(FF.gd(f, y), x)
+    assert abs(a - b) < 1e-10 * abs(a)
+    assert np.vdot(x, FF.gd(f, x)).real > 0
+
+
+def test_identity_phase_gives_rank_zero_hierarchy(tmp_path):
+    """Phi = x.xi: S = N I, every off-diagonal block is empty and Gd Kd^* = F."""
+    _, f, _ = _host_plan(tmp_path, phase="linear")
+    assert f["max_rank_h"] == 0
+    assert f["root"].size == 0
+    u = gaussian_complex(256, 5)
+    ref = O.dft(u, 1, 256)  # K^{-1} = F when K = N F^*
+    assert O.rel_err(FF.inverse(f, u), ref).max() < 1e-6
+
+
+def test_save_load_roundtrip(tmp_path):
+    plan, f, path = _host_plan(tmp_path)
+    plan2 = F.fio_load(path, device=-1)
+    path2 = str(tmp_path / "plan2.fio")
+    F.fio_save(plan2, path2)
+    assert open(path, "rb").read() == open(path2, "rb").read()
+
+
+def test_load_rejects_garbage(tmp_path):
+    bad = tmp_path / "bad.fio"
+    bad.write_bytes(b"not a plan")
+    with pytest.raises(F.FioError) as e:
+        F.fio_load(str(bad), device=-1)
+    assert e.value.status == 7
