@@ -1,0 +1,221 @@
+"""Throughput of the factored FIO inverse solve on one MI355X.
+
+A step is one pass of the whole hot path over one batch of right-hand sides:
+layout in, Kd^* (butterfly adjoint, complex64), Gd (skeletonization sweeps and
+the FP64 top-level block), one FP64 refinement step r = u - Kd x (complex128
+factors) followed by the complex64 correction Gd Kd^* r, and layout out.
+
+Prints one JSON line (see the keys below).  Inputs are synthetic (seeded
+Gaussian right-hand sides) and resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from fio_synth import WORKLOADS, gaussian_complex, uniform_indices  # noqa: E402
+
+PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # MI355X dense MFMA FP32 / FP64
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="1d_n65536", choices=sorted(WORKLOADS))
+    ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps per solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
+    return ap.parse_args()
+
+
+def stage_timing(F, plan, torch, dtype, op, nrhs, reps=5):
+    """Average duration (ms) and algorithmic flops of every launch of the stage
+    kernel over one chain (op = K or KH), timed with events on the launch stream."""
+    st = F.fio_plan_stats(plan)
+    S = st["n_stages"]
+    infos = [F.fio_stage_info(plan, s) for s in range(S)]
+    order = list(range(S)) if op == F.FIO_OP_K else list(range(S - 1, -1, -1))
+    maxlen = max(max(i["n_out"] * i["r_out"], 1) for i in infos)
+    maxlen = max(maxlen, st["n"] ** st["d"], max(i["nnz"] // max(i["r_out"] * i["fan"], 1) for i in infos))
+    ctype = torch.complex64 if dtype == F.FIO_C64 else torch.complex128
+    a = torch.randn(maxlen * nrhs, dtype=ctype, device="cuda")
+    b = torch.zeros_like(a)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(S)]
+    tot_ms = np.zeros(S)
+    for r in range(reps):
+        for k in range(S):
+            ev[k][0].record(stream)
+            F.fio_stage_apply(plan, op, k, dtype, a, b, nrhs, stream)
+            ev[k][1].record(stream)
+            a, b = b, a
+        torch.cuda.synchronize()
+        if r > 0:
+            tot_ms += np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    tot_ms /= max(reps - 1, 1)
+    flops = np.array([8.0 * infos[order[k]]["nnz"] * nrhs for k in range(S)])
+    return tot_ms, flops
+
+
+def cpu_baseline(wl, x_gpu, u):
+    """The FP64 oracle on a bounded sample of the same workload (CPU, all cores):
+    its solve is CG on K^*K x = K^*u with direct-summation products (section 6,
+    eq_NR_1).  Timed: one K^*K product on one right-hand side at full N; the
+    iteration count comes from the oracle's own CG at N = 4096 (same phase).
+    Also checks the GPU solution's residual on sampled rows."""
+    import oracle as O
+    p_small = O.OracleProblem(1, 4096, wl.phase, wl.c_div)
+    K = O.dense_K(p_small)
+    _, iters = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v,
+                           gaussian_complex(4096, 99), tol=1e-8)
+    del K
+    p = O.OracleProblem(wl.d, wl.n, wl.phase, wl.c_div)
+    v = gaussian_complex(wl.N, 98)
+    t0 = time.perf_counter()
+    w = O.apply_direct(p, v)
+    O.apply_direct(p, w, adjoint=True)
+    t_pair = time.perf_counter() - t0
+    per_rhs = (iters + 0.5) * t_pair          # iterations plus the initial K^* u
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rows = uniform_indices(32, wl.N, 7)
+    cols = np.array([0, wl.nrhs - 1])
+    r = O.apply_direct(p, x_gpu[:, cols], out_idx=rows) - u[rows][:, cols]
+    resid = float((np.linalg.norm(r, axis=0) / np.linalg.norm(u[rows][:, cols], axis=0)).max())
+    return {"value": wl.N / per_rhs, "unit": "RHS*N/s", "cores": cores, "kind": "oracle",
+            "sample": "one K^*K product by direct summation on 1 RHS at N=%d (%.1f s), "
+                      "times %d CG iterations (oracle CG count at N=4096) + 0.5" % (wl.N, t_pair, iters),
+            "oracle_residual_sampled_rows": resid}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the factored solve is measured on a single "
+              "MI355X (multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2105_02995_amd import fio as F
+
+    wl = WORKLOADS[args.workload]
+    N, B = wl.N, wl.nrhs
+    log("workload %s: d=%d n=%d N=%d nrhs=%d eps=%g" % (wl.name, wl.d, wl.n, N, B, wl.eps))
+    t0 = time.perf_counter()
+    plan = F.fio_build(F.make_problem(wl.d, wl.n, wl.phase, eps=wl.eps, c_div=wl.c_div, device=0))
+    build_s = time.perf_counter() - t0
+    stats = F.fio_plan_stats(plan)
+    log("built in %.1f s: bf_nnz=%d hif_nnz=%d root=%d device_bytes=%.2f GB" % (
+        build_s, stats["bf_nnz"], stats["hif_nnz"], stats["root_size"], stats["device_bytes"] / 1e9))
+
+    u = gaussian_complex((N, B), wl.seed)
+    U = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()
+    X = torch.zeros_like(U)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0, maxit=args.refine,
+                    stream=stream, want_info=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        step()
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    ms = 1000.0 * elapsed / args.steps
+    value = B * N / (elapsed / args.steps)
+    log("timed %d steps: %.3f ms/step, %.3e RHS*N/s" % (args.steps, ms, value))
+    its, corr = F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0,
+                            maxit=args.refine, stream=stream)
+    x = X.cpu().numpy().T
+
+    # dominant kernel: the butterfly stage kernel (complex64 adjoint chain runs twice
+    # per step, the complex128 forward chain once)
+    t64, f64 = stage_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
+    t128, f128 = stage_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
+    if 2 * t64.sum() >= args.refine * t128.sum():
+        name, tms, fl, pk = "k_stage<float2> (complex64 butterfly stage)", t64, f64, PEAK_TFLOPS["c64"]
+    else:
+        name, tms, fl, pk = "k_stage<double2> (complex128 butterfly stage)", t128, f128, PEAK_TFLOPS["c128"]
+    achieved = fl.sum() / (tms.sum() * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": pk, "unit": "TFLOP/s",
+            "frac": round(achieved / pk, 4), "traffic": None, "kernel": name,
+            "avg_launch_ms": round(float(tms.mean()), 5),
+            "flops_per_launch": float(fl.mean()),
+            "chain_ms": {"c64_KH": round(float(t64.sum()), 4), "c128_K": round(float(t128.sum()), 4)}}
+    log("roofline: %s avg %.4f ms/launch, %.2f TFLOP/s (%.1f%% of %.1f)" % (
+        name, tms.mean(), achieved, 100 * achieved / pk, pk))
+
+    plain = None
+    if not args.no_plain:
+        # plain FP64 path: complex128 factors, one right-hand side per call, direct solve
+        ncols = 16
+        Uc = [U[j:j + 1].contiguous() for j in range(ncols)]
+        Xc = [torch.zeros_like(Uc[0]) for _ in range(ncols)]
+        for j in range(2):
+            F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream,
+                        want_info=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(ncols):
+            F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream,
+                        want_info=False)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        plain = {"value": ncols * N / tp, "ms_per_rhs": 1000 * tp / ncols, "dtype": "c128",
+                 "nrhs_per_call": 1}
+        log("plain FP64 single-RHS: %.3f ms/RHS, %.3e RHS*N/s" % (1000 * tp / ncols, plain["value"]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(wl, x, u)
+        log("cpu baseline: %.3e RHS*N/s on %d cores" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": "RHS*N/s of factored FIO inverse solve at rel err <= 10 eps; p50/p99 latency",
+        "value": value, "unit": "RHS*N/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "%s: 1D FIO Example 1 phase c(x)=(2+sin 2pi x)/16, N=%d, %d RHS, "
+                               "eps=%g, complex64 applies + %d FP64 refinement step(s)"
+                               % (wl.name, N, B, wl.eps, args.refine),
+                   "N": N, "nrhs": B, "eps": wl.eps},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "last_correction_rel": corr,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_fp64_single_rhs": plain,
+        "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "build_seconds": build_s,
+        "plan": {k: stats[k] for k in ("bf_nnz", "hif_nnz", "root_size", "max_rank_bf",
+                                       "max_rank_h", "device_bytes", "L")},
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,16 @@ fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);
 fio_status fio_stage_info(fio_plan plan, int stage, int64_t *nnz, int64_t *n_out_blocks,
                           int *r_out, int *r_in, int *fan);
 
+/* Apply the single factor `stage` of Kd (op = FIO_OP_K: stage s of eq_BFF_fact,
+ * counted from V_L^* = 0 to U_L = L + 2) or of Kd^* (op = FIO_OP_KH: the adjoint
+ * chain, V_L^*'s adjoint last) to coefficient vectors.  x and y are device
+ * buffers in the library's internal layout: point-major, entry (e, b) of the
+ * stage's input (n_in*r_in entries) or output (n_out*r_out entries) at
+ * e*nrhs + b.  This is the kernel every apply runs, exposed for measurement.
+ * Asynchronous; errors: FIO_ERR_ARG (stage or op out of range). */
+fio_status fio_stage_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x,
+                           void *y, int64_t nrhs, void *hip_stream);
+
 /* Save the factors to a file / load them onto a device (device = -1: host only). */
 fio_status fio_save(fio_plan plan, const char *path);
 fio_status fio_load(const char *path, int device, fio_plan *out);

@@ -361,6 +361,22 @@ fio_status fio_apply(fio_plan p, fio_op op, fio_dtype dt, const void *x, void *y
     });
 }
 
+fio_status fio_stage_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const void *x, void *y,
+                           int64_t nrhs, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, p ? p->host.N : 0, x, y);
+        if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        const auto &hs = (op == FIO_OP_K) ? p->host.fwd : p->adj;
+        const auto &ds = (op == FIO_OP_K) ? p->dfwd : p->dadj;
+        if (stage < 0 || stage >= (int)hs.size()) fail(FIO_ERR_ARG, "stage out of range");
+        if (nrhs == 0) return;
+        HIPC(hipSetDevice(p->device));
+        const bool dbl = dt == FIO_C128;
+        launch_stage(ds[stage].view(dbl, hs[stage]), dbl, x, y, (int)nrhs, (hipStream_t)stream);
+    });
+}
+
 fio_status fio_gd_apply(fio_plan p, fio_dtype dt, const void *x, void *y, int64_t nrhs, int64_t ld, void *stream) {
     return guard([&] {
         check_apply_args(p, nrhs, ld, x, y);
