@@ -94,7 +94,134 @@ __global__ void __launch_bounds__(256) k_stage(int64_t n_out, int r_out, int r_i
     }
 }
 
+// Batched stage on matrix cores.  One wave computes 16*MT rows of one output
+// block for a chunk of 64 right-hand sides as four 16x16 tiles; the complex
+// product uses four real MFMAs per k-step (Yr += Ar Xr - Ai Xi, Yi += Ar Xi + Ai Xr),
+// accumulating in the working precision (FP32 for complex64, FP64 for complex128).
+// MFMA 16x16x4 lane layout: A[l%16][l/16], B[l/16][l%16]; the accumulator entry v
+// of lane l is D[4*(l/16)+v][l%16] for FP32 and D[l/16+4*v][l%16] for FP64.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <class R> struct MF;
+template <> struct MF<float> {
+    using C = float2;
+    using V4 = floatx4;
+    static __device__ __forceinline__ V4 mma(float a, float b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct MF<double> {
+    using C = double2;
+    using V4 = doublex4;
+    static __device__ __forceinline__ V4 mma(double a, double b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int drow(int lk, int v) { return lk + 4 * v; }
+};
+
+template <class R, int MT>
+__global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
+                                                    const int32_t *__restrict__ idx,
+                                                    const typename MF<R>::C *__restrict__ A,
+                                                    const typename MF<R>::C *__restrict__ x,
+                                                    typename MF<R>::C *__restrict__ y, int nrhs,
+                                                    int mchunks) {
+    using C = typename MF<R>::C;
+    using V4 = typename MF<R>::V4;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= n_out * mchunks) return;  // wave-uniform
+    const int64_t o = wave / mchunks;
+    const int mc = (int)(wave % mchunks);
+    const int n0 = blockIdx.y * 64;
+    const int K = fan * r_in;
+    const int li = lane & 15, lk = lane >> 4;
+    V4 accR[MT][4], accI[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            accR[mt][nt] = V4{0, 0, 0, 0};
+            accI[mt][nt] = V4{0, 0, 0, 0};
+        }
+    const C *Ao = A + o * (int64_t)r_out * K;
+    const int32_t *io = idx + o * fan;
+    int q = 0, e = lk;  // (input block, entry) of this lane's k = k0 + lk
+    while (e >= r_in) { e -= r_in; ++q; }
+    const C zero = C{0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        const bool kv = k < K;
+        C xv[4];
+        if (kv) {
+            const C *xrow = x + ((int64_t)io[q] * r_in + e) * nrhs;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int col = n0 + nt * 16 + li;
+                xv[nt] = (col < nrhs) ? xrow[col] : zero;
+            }
+        } else {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) xv[nt] = zero;
+        }
+        C av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int row = (mc * MT + mt) * 16 + li;
+            av[mt] = (kv && row < r_out) ? Ao[row + (int64_t)k * r_out] : zero;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const R ar = av[mt].x, ai = av[mt].y, nai = -av[mt].y;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                accR[mt][nt] = MF<R>::mma(ar, xv[nt].x, accR[mt][nt]);
+                accR[mt][nt] = MF<R>::mma(nai, xv[nt].y, accR[mt][nt]);
+                accI[mt][nt] = MF<R>::mma(ar, xv[nt].y, accI[mt][nt]);
+                accI[mt][nt] = MF<R>::mma(ai, xv[nt].x, accI[mt][nt]);
+            }
+        }
+        e += 4;
+        while (e >= r_in) { e -= r_in; ++q; }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = (mc * MT + mt) * 16 + MF<R>::drow(lk, v);
+                const int col = n0 + nt * 16 + li;
+                if (row < r_out && col < nrhs)
+                    y[(o * r_out + row) * (int64_t)nrhs + col] = C{accR[mt][nt][v], accI[mt][nt][v]};
+            }
+}
+
+template <class R, int MT>
+static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    const int mtiles = (s.r_out + 15) / 16;
+    const int mchunks = (mtiles + MT - 1) / MT;
+    const int64_t waves = s.n_out * mchunks;
+    const dim3 g((unsigned)((waves + 3) / 4), (unsigned)((nrhs + 63) / 64));
+    hipLaunchKernelGGL((k_stage_mfma<R, MT>), g, dim3(256), 0, st, s.n_out, s.r_out, s.r_in, s.fan,
+                       s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks);
+}
+
+// Right-hand-side counts from which the matrix-core path is used.
+static const int MFMA_MIN_RHS = 16;
+
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st) {
+    if (nrhs >= MFMA_MIN_RHS) {
+        const int mtiles = (s.r_out + 15) / 16;
+        if (dbl) launch_mfma<double, 1>(s, x, y, nrhs, st);
+        else if (mtiles >= 2) launch_mfma<float, 2>(s, x, y, nrhs, st);
+        else launch_mfma<float, 1>(s, x, y, nrhs, st);
+        check_launch("stage (matrix cores)");
+        return;
+    }
     const int64_t work = s.n_out * s.r_out * (int64_t)nrhs;
     const unsigned g = grid_for(work, 256);
     if (dbl)

@@ -82,6 +82,25 @@ def test_apply_matches_saved_factors_tightly(tmp_path):
     assert O.rel_err(z, FF.inverse(f, x)).max() < 1e-12
 
 
+@pytest.mark.parametrize("n,B", [(256, 64), (256, 70), (4096, 17)])
+def test_batched_matrix_core_path_tight(tmp_path, n, B):
+    """Batches of >= 16 right-hand sides run on matrix cores (complex products as
+    four real MFMAs, 64-column tiles with a ragged tail): complex128 must equal the
+    host product of the same factors to FP64 rounding, complex64 to FP32 rounding."""
+    plan = plan_for(n)
+    path = str(tmp_path / "p.fio")
+    F.fio_save(plan, path)
+    f = FF.read(path)
+    x = gaussian_complex((n, B), 8 + B)
+    ref = FF.apply_K(f, x)
+    refh = FF.apply_KH(f, x)
+    log("matrix-core apply n=%d B=%d" % (n, B))
+    assert O.rel_err(G.apply(plan, F.FIO_OP_K, F.FIO_C128, x), ref).max() < 1e-13
+    assert O.rel_err(G.apply(plan, F.FIO_OP_KH, F.FIO_C128, x), refh).max() < 1e-13
+    assert O.rel_err(G.apply(plan, F.FIO_OP_K, F.FIO_C64, x), ref).max() < 2e-6
+    assert O.rel_err(G.apply(plan, F.FIO_OP_KH, F.FIO_C64, x), refh).max() < 2e-6
+
+
 def test_leading_dimension_and_ragged_batch():
     plan = plan_for(256)
     x = gaussian_complex((256, 37), 9)
