@@ -133,11 +133,13 @@ void upload_plan(fio_plan p) {
         std::vector<int64_t> desc;
         std::vector<int32_t> idx;
         std::vector<cd> mat;
-        int mr = 0, ms = 0;
+        int mr = 0, ms = 0, mv = 0, mm = 0;
         for (const HifNode &nd : st.nodes) {
             const int nr = (int)nd.idx_r.size(), ns = (int)nd.idx_s.size();
             mr = std::max(mr, nr);
             ms = std::max(ms, ns);
+            mv = std::max(mv, 2 * nr + ns);
+            mm = std::max(mm, 2 * ns * nr + nr * nr);
             desc.push_back(nr);
             desc.push_back(ns);
             desc.push_back((int64_t)idx.size());
@@ -152,6 +154,8 @@ void upload_plan(fio_plan p) {
         d.base.n_nodes = (int64_t)st.nodes.size();
         d.base.max_nr = mr;
         d.base.max_ns = ms;
+        d.base.max_vec = mv;
+        d.base.max_mat = mm;
         d.desc.upload(desc.data(), desc.size() * sizeof(int64_t));
         d.idx.upload(idx.data(), idx.size() * sizeof(int32_t));
         upload_complex(d.m64, d.m128, mat);

@@ -234,10 +234,12 @@ void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs,
 }
 
 // ------------------------------------------------------------------ skeletonization steps
-// One workgroup per node; the node's entries of x are gathered into LDS for a
-// chunk of right-hand sides, transformed, and scattered back.  Nodes of one step
-// own disjoint index sets, so workgroups never touch the same entries.
-template <class T, bool UP>
+// One workgroup per node.  The node's blocks T (ns x nr), Linv (nr x nr) and
+// M (ns x nr) are first copied into LDS with coalesced loads (when they fit),
+// then its entries of x are gathered into LDS for a chunk of right-hand sides,
+// transformed, and scattered back.  Nodes of one step own disjoint index sets,
+// so workgroups never touch the same entries of x.
+template <class T, bool UP, bool STAGED>
 __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
                                              const int32_t *__restrict__ idx,
                                              const T *__restrict__ mat, T *__restrict__ x,
@@ -248,12 +250,22 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
     const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
     const int32_t *ir = idx + desc[4 * v + 2];
     const int32_t *is = ir + nr;
-    const T *Tm = mat + desc[4 * v + 3];        // ns x nr
-    const T *Li = Tm + (int64_t)ns * nr;        // nr x nr (lower)
-    const T *Mm = Li + (int64_t)nr * nr;        // ns x nr
+    const T *gm = mat + desc[4 * v + 3];
+    const int nmat = 2 * ns * nr + nr * nr;
+    const T *Tm, *Li, *Mm;
+    T *work = sm;
+    if (STAGED) {
+        for (int e = threadIdx.x; e < nmat; e += blockDim.x) sm[e] = gm[e];
+        Tm = sm;
+        work = sm + nmat;
+    } else {
+        Tm = gm;
+    }
+    Li = Tm + (int64_t)ns * nr;  // nr x nr (lower)
+    Mm = Li + (int64_t)nr * nr;  // ns x nr
     for (int b0 = 0; b0 < nrhs; b0 += bchunk) {
         const int bc = min(bchunk, nrhs - b0);
-        T *xr = sm, *xs = sm + nr * bc, *y = xs + ns * bc;
+        T *xr = work, *xs = work + nr * bc, *y = xs + ns * bc;
         for (int e = threadIdx.x; e < (nr + ns) * bc; e += blockDim.x) {
             const int i = e / bc, b = e % bc;
             const int64_t g = (i < nr) ? ir[i] : is[i - nr];
@@ -265,7 +277,8 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
             for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
                 const int i = e / bc, b = e % bc;
                 T acc = cz(T());
-                for (int k = 0; k < ns; ++k) acc = cfmac(acc, Tm[k + (int64_t)i * ns], xs[k * bc + b]);
+                const T *tc = Tm + (int64_t)i * ns;
+                for (int k = 0; k < ns; ++k) acc = cfmac(acc, tc[k], xs[k * bc + b]);
                 xr[e] = csub(xr[e], acc);
             }
             __syncthreads();
@@ -295,7 +308,8 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
             for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
                 const int i = e / bc, b = e % bc;
                 T acc = cz(T());
-                for (int k = 0; k < ns; ++k) acc = cfmac(acc, Mm[k + (int64_t)i * ns], xs[k * bc + b]);
+                const T *mc = Mm + (int64_t)i * ns;
+                for (int k = 0; k < ns; ++k) acc = cfmac(acc, mc[k], xs[k * bc + b]);
                 y[e] = csub(xr[e], acc);
             }
             __syncthreads();
@@ -303,7 +317,8 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
             for (int e = threadIdx.x; e < nr * bc; e += blockDim.x) {
                 const int i = e / bc, b = e % bc;
                 T acc = cz(T());
-                for (int k = i; k < nr; ++k) acc = cfmac(acc, Li[k + (int64_t)i * nr], y[k * bc + b]);
+                const T *lc = Li + (int64_t)i * nr;
+                for (int k = i; k < nr; ++k) acc = cfmac(acc, lc[k], y[k * bc + b]);
                 xr[e] = acc;
             }
             __syncthreads();
@@ -325,23 +340,51 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
     }
 }
 
-static const int HIF_LDS = 64 * 1024;
+// LDS one workgroup may use: the device's opt-in limit (160 KiB per CU on
+// gfx950), capped with a margin; 64 KiB if the runtime does not report it.
+static int hif_lds_budget() {
+    static int budget = -1;
+    if (budget < 0) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        budget = std::min(v, 144 * 1024);
+        (void)hipGetLastError();
+    }
+    return budget;
+}
+
+template <class T, bool UP, bool ST>
+static void hif_go(const HifStepDev &h, size_t lds, void *x, int nrhs, int bchunk, hipStream_t st) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_hif<T, UP, ST>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_hif<T, UP, ST>), dim3((unsigned)h.n_nodes), dim3(256), lds, st, h.desc,
+                       h.idx, (const T *)h.mat, (T *)x, nrhs, bchunk);
+}
 
 void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
     if (h.n_nodes == 0) return;
     const int elt = dbl ? 16 : 8;
-    const int per = 2 * h.max_nr + h.max_ns;
-    int bchunk = per > 0 ? HIF_LDS / (per * elt) : nrhs;
-    bchunk = std::max(1, std::min(bchunk, nrhs));
-    if (per * elt * bchunk > HIF_LDS) throw std::runtime_error("skeletonization node exceeds LDS");
-    const size_t lds = (size_t)std::max(1, per) * elt * bchunk;
-    const dim3 g((unsigned)h.n_nodes), b(256);
+    const int64_t HIF_LDS = hif_lds_budget();
+    const int per = std::max(1, h.max_vec);         // max over nodes of 2*nr + ns
+    const int64_t matb = (int64_t)h.max_mat * elt;   // max over nodes of 2*ns*nr + nr*nr
+    const bool staged = matb + (int64_t)per * elt <= HIF_LDS;
+    const int64_t avail = staged ? HIF_LDS - matb : HIF_LDS;
+    int bchunk = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, avail / ((int64_t)per * elt)));
+    if (bchunk >= 64) bchunk = (bchunk / 64) * 64;
+    const size_t lds = (size_t)(staged ? matb : 0) + (size_t)per * elt * bchunk;
+    if ((int64_t)lds > HIF_LDS) throw std::runtime_error("skeletonization node exceeds LDS");
     if (dbl) {
-        if (up) hipLaunchKernelGGL((k_hif<double2, true>), g, b, lds, st, h.desc, h.idx, (const double2 *)h.mat, (double2 *)x, nrhs, bchunk);
-        else hipLaunchKernelGGL((k_hif<double2, false>), g, b, lds, st, h.desc, h.idx, (const double2 *)h.mat, (double2 *)x, nrhs, bchunk);
+        if (staged) { if (up) hif_go<double2, true, true>(h, lds, x, nrhs, bchunk, st); else hif_go<double2, false, true>(h, lds, x, nrhs, bchunk, st); }
+        else { if (up) hif_go<double2, true, false>(h, lds, x, nrhs, bchunk, st); else hif_go<double2, false, false>(h, lds, x, nrhs, bchunk, st); }
     } else {
-        if (up) hipLaunchKernelGGL((k_hif<float2, true>), g, b, lds, st, h.desc, h.idx, (const float2 *)h.mat, (float2 *)x, nrhs, bchunk);
-        else hipLaunchKernelGGL((k_hif<float2, false>), g, b, lds, st, h.desc, h.idx, (const float2 *)h.mat, (float2 *)x, nrhs, bchunk);
+        if (staged) { if (up) hif_go<float2, true, true>(h, lds, x, nrhs, bchunk, st); else hif_go<float2, false, true>(h, lds, x, nrhs, bchunk, st); }
+        else { if (up) hif_go<float2, true, false>(h, lds, x, nrhs, bchunk, st); else hif_go<float2, false, false>(h, lds, x, nrhs, bchunk, st); }
     }
     check_launch("hif step");
 }

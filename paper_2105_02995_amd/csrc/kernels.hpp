@@ -22,6 +22,8 @@ struct StageDev {
 struct HifStepDev {
     int64_t n_nodes = 0;
     int max_nr = 0, max_ns = 0;
+    int max_vec = 0;   // max over nodes of 2*nr + ns (LDS entries per right-hand side)
+    int max_mat = 0;   // max over nodes of 2*ns*nr + nr*nr (entries of the node's blocks)
     const int64_t *desc = nullptr;
     const int32_t *idx = nullptr;
     const void *mat = nullptr;
