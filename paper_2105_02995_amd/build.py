@@ -53,6 +53,11 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
+    # measurement aid (copy kernel of known size, MFMA rates)
+    cal = os.path.join(HERE, "fio_calibrate")
+    _run([HIPCC, "-O3", "-std=c++17", *HIP_FLAGS, os.path.join(CSRC, "calibrate.hip"),
+          "-o", cal + ".tmp"])
+    os.replace(cal + ".tmp", cal)
     return LIB
 
 

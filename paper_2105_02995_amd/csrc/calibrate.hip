@@ -1,0 +1,92 @@
+// fio_calibrate: measurement aid for the roofline figures of the library.
+//   fio_calibrate copy   1 GiB device-to-device copy kernel (known bytes), used to
+//                        scale the FETCH_SIZE / WRITE_SIZE counters of rocprofv3;
+//   fio_calibrate mfma   sustained 16x16x4 FP32 and FP64 MFMA rates (registers only).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) calib_copy(const float4 *__restrict__ a, float4 *__restrict__ b, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+template <int NACC>
+__global__ void __launch_bounds__(256) calib_mfma32(float *out, int iters, float a0) {
+    floatx4 acc[NACC];
+    for (int i = 0; i < NACC; ++i) acc[i] = floatx4{0, 0, 0, 0};
+    float a = a0 + threadIdx.x * 1e-6f, b = a0 - threadIdx.x * 1e-6f;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[i], 0, 0, 0);
+    float s = 0;
+    for (int i = 0; i < NACC; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+    if (s == 12345.f) out[threadIdx.x] = s;
+}
+
+template <int NACC>
+__global__ void __launch_bounds__(256) calib_mfma64(double *out, int iters, double a0) {
+    doublex4 acc[NACC];
+    for (int i = 0; i < NACC; ++i) acc[i] = doublex4{0, 0, 0, 0};
+    double a = a0 + threadIdx.x * 1e-6, b = a0 - threadIdx.x * 1e-6;
+    for (int it = 0; it < iters; ++it)
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+    double s = 0;
+    for (int i = 0; i < NACC; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+    if (s == 12345.0) out[threadIdx.x] = s;
+}
+
+#define CK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { fprintf(stderr, "%s: %s\n", #x, hipGetErrorString(e_)); return 1; } } while (0)
+
+int main(int argc, char **argv) {
+    const char *mode = argc > 1 ? argv[1] : "copy";
+    hipEvent_t e0, e1;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    float ms = 0;
+    if (!strcmp(mode, "copy")) {
+        const long n = 1L << 26;  // float4 elements: 1 GiB per buffer
+        float4 *a, *b;
+        CK(hipMalloc(&a, n * 16));
+        CK(hipMalloc(&b, n * 16));
+        CK(hipMemset(a, 0, n * 16));
+        hipLaunchKernelGGL(calib_copy, dim3(4096), dim3(256), 0, 0, a, b, n);
+        CK(hipDeviceSynchronize());
+        const int reps = 5;
+        CK(hipEventRecord(e0));
+        for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(calib_copy, dim3(4096), dim3(256), 0, 0, a, b, n);
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        printf("copy: 1 GiB read + 1 GiB write per dispatch, %.2f TB/s\n", 2.0 * n * 16 * reps / ms / 1e9);
+        CK(hipFree(a));
+        CK(hipFree(b));
+    } else {
+        float *o;
+        double *od;
+        CK(hipMalloc(&o, 4096));
+        CK(hipMalloc(&od, 8192));
+        const int iters = 2000, blocks = 2048;
+        hipLaunchKernelGGL(calib_mfma32<8>, dim3(blocks), dim3(256), 0, 0, o, 10, 1.0f);
+        CK(hipDeviceSynchronize());
+        CK(hipEventRecord(e0));
+        hipLaunchKernelGGL(calib_mfma32<8>, dim3(blocks), dim3(256), 0, 0, o, iters, 1.0f);
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        printf("mfma f32 16x16x4: %.1f TFLOP/s\n", 2048.0 * 8 * iters * blocks * 4 / ms / 1e9);
+        hipLaunchKernelGGL(calib_mfma64<8>, dim3(blocks), dim3(256), 0, 0, od, 10, 1.0);
+        CK(hipDeviceSynchronize());
+        CK(hipEventRecord(e0));
+        hipLaunchKernelGGL(calib_mfma64<8>, dim3(blocks), dim3(256), 0, 0, od, iters, 1.0);
+        CK(hipEventRecord(e1));
+        CK(hipEventSynchronize(e1));
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        printf("mfma f64 16x16x4: %.1f TFLOP/s\n", 2048.0 * 8 * iters * blocks * 4 / ms / 1e9);
+    }
+    return 0;
+}

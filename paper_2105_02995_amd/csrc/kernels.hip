@@ -258,12 +258,14 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
         for (int e = threadIdx.x; e < nmat; e += blockDim.x) sm[e] = gm[e];
         Tm = sm;
         work = sm + nmat;
+        __syncthreads();
     } else {
         Tm = gm;
     }
     Li = Tm + (int64_t)ns * nr;  // nr x nr (lower)
     Mm = Li + (int64_t)nr * nr;  // ns x nr
-    for (int b0 = 0; b0 < nrhs; b0 += bchunk) {
+    {
+        const int b0 = blockIdx.y * bchunk;
         const int bc = min(bchunk, nrhs - b0);
         T *xr = work, *xs = work + nr * bc, *y = xs + ns * bc;
         for (int e = threadIdx.x; e < (nr + ns) * bc; e += blockDim.x) {
@@ -363,7 +365,8 @@ static void hif_go(const HifStepDev &h, size_t lds, void *x, int nrhs, int bchun
                                   hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_hif<T, UP, ST>), dim3((unsigned)h.n_nodes), dim3(256), lds, st, h.desc,
+    const unsigned nch = (unsigned)((nrhs + bchunk - 1) / bchunk);
+    hipLaunchKernelGGL((k_hif<T, UP, ST>), dim3((unsigned)h.n_nodes, nch), dim3(256), lds, st, h.desc,
                        h.idx, (const T *)h.mat, (T *)x, nrhs, bchunk);
 }
 
@@ -377,6 +380,9 @@ void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, 
     const int64_t avail = staged ? HIF_LDS - matb : HIF_LDS;
     int bchunk = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs, avail / ((int64_t)per * elt)));
     if (bchunk >= 64) bchunk = (bchunk / 64) * 64;
+    // spread steps with few nodes over right-hand-side chunks (at least 16 columns each)
+    const int64_t want = (int64_t)nrhs * h.n_nodes / 1024;
+    if (want < bchunk) bchunk = (int)std::max<int64_t>(std::min<int64_t>(16, bchunk), want);
     const size_t lds = (size_t)(staged ? matb : 0) + (size_t)per * elt * bchunk;
     if ((int64_t)lds > HIF_LDS) throw std::runtime_error("skeletonization node exceeds LDS");
     if (dbl) {
