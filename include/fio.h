@@ -83,6 +83,8 @@ typedef struct {
     int device;             /* HIP device ordinal, or -1 for a host-only plan that can
                                be saved and loaded later but not applied              */
     int nthreads;           /* host threads for the build; 0 -> hardware concurrency  */
+    int verbose;            /* nonzero: fio_build prints one progress line per phase
+                               and per tree level to stderr                           */
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",

@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
-CXX_SOURCES = ["la.cpp", "stages.cpp", "butterfly.cpp", "hif1d.cpp", "build.cpp"]
+CXX_SOURCES = ["la.cpp", "stages.cpp", "butterfly.cpp", "hif1d.cpp", "hif2d.cpp", "build.cpp"]
 HIP_SOURCES = ["kernels.hip", "capi.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

@@ -1,6 +1,7 @@
 // Host construction of all factors (Algorithm "alg", section 5) and their file format.
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -8,6 +9,17 @@
 #include "plan.hpp"
 
 namespace fio {
+
+void progress(bool on, const char *fmt, ...) {
+    if (!on) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fprintf(stderr, "[fio_build] ");
+    std::vfprintf(stderr, fmt, ap);
+    std::fprintf(stderr, "\n");
+    std::fflush(stderr);
+    va_end(ap);
+}
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -39,7 +51,6 @@ fio_problem normalized_problem(const fio_problem &in) {
 void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu) {
     auto t0 = std::chrono::steady_clock::now();
     fio_problem p = normalized_problem(pin);
-    if (p.d == 2) fail(FIO_ERR_UNSUPPORTED, "2D inverse factors are not available in this build");
     FioKernel K;
     K.init(p.d, p.n, p.phase, p.c_div);
     ButterflyOptions bo;
@@ -47,7 +58,12 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     bo.leaf = p.leaf_bf;
     bo.nthreads = p.nthreads;
     bo.seed = p.seed ^ 0xB0F1ULL;
+    const bool vb = p.verbose != 0;
+    bo.verbose = vb;
+    progress(vb, "d=%d n=%d: butterfly (eps_bf=%.1e)", p.d, p.n, p.eps_bf);
     Butterfly B = build_butterfly(K, bo);
+    progress(vb, "butterfly done: L=%d nnz=%lld (%.1fs)", B.L, (long long)B.nnz(),
+             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     out.d = p.d; out.n = p.n; out.N = B.N; out.L = B.L; out.Lm = B.Lm; out.m = B.m;
     out.perm = K.to_nat;
     out.prob = p;
@@ -72,7 +88,11 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     po.oversample = p.oversample;
     po.seed = p.seed ^ 0x9EE1ULL;
     po.nthreads = p.nthreads;
-    out.hif = build_hif_1d(A, B.N, po, p.eps_hif);
+    po.verbose = vb;
+    out.hif = (p.d == 1) ? build_hif_1d(A, B.N, po, p.eps_hif) : build_hif_2d(A, p.n, po, p.eps_hif);
+    progress(vb, "inverse factors done: %zu steps, root %zu (%.1fs)", out.hif.steps.size(),
+             out.hif.root_idx.size(),
+             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     out.fwd = std::move(B.fwd);
     out.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }

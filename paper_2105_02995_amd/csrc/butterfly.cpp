@@ -32,7 +32,27 @@ static std::vector<int> stratified(int64_t lo, int64_t size, int count, uint64_t
 }
 
 static int n_samples(int ncand, int64_t size) {
-    return (int)std::min<int64_t>(size, std::max(2 * ncand + 16, 32));
+    return (int)std::min<int64_t>(size, std::max(ncand + ncand / 2 + 16, 32));
+}
+
+// Pairs whose interpolative decompositions set the rank of a level: a stratified
+// subset of all pairs, plus every pair whose Omega node holds xi = 0 (where the
+// phase |xi| or sqrt(...) has its kink and ranks peak).
+static std::vector<int64_t> rank_probe_pairs(int64_t npairs, int64_t nOm, int64_t j0, uint64_t seed) {
+    const int64_t want = 256;
+    std::vector<int64_t> out;
+    if (npairs <= 2 * want) {
+        for (int64_t p = 0; p < npairs; ++p) out.push_back(p);
+        return out;
+    }
+    for (int64_t s = 0; s < want; ++s) {
+        int64_t a = npairs * s / want, b = npairs * (s + 1) / want;
+        out.push_back(a + (int64_t)(splitmix64(seed + s) % (uint64_t)(b - a)));
+    }
+    for (int64_t i = 0; i < npairs / nOm; ++i) out.push_back(i * nOm + j0);
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
 }
 
 Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
@@ -55,6 +75,8 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
     B.rV.assign(L + 1, 0);
     B.fwd.assign(L + 3, Stage());
     const int nt = opt.nthreads;
+    // tree position of xi = 0 (the Omega point with j = 0 in every coordinate)
+    const int64_t xi0 = K.to_tree[(K.d == 1) ? K.n / 2 : (int64_t)(K.n / 2) * K.n + K.n / 2];
 
     // ---------------- X side: row skeletons, levels L down to Lm ----------------
     std::vector<std::vector<int>> skelU(L + 1);
@@ -78,27 +100,28 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
             }
             return c;
         };
-        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand) {
+        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand, int ns) {
             int64_t j = pr % nOm;
-            std::vector<int> cols = stratified(j * szOm, szOm, n_samples(ncand, szOm),
+            std::vector<int> cols = stratified(j * szOm, szOm, std::min<int64_t>(ns, szOm),
                                                opt.seed ^ splitmix64(0xA000 + l) ^ (uint64_t)pr * 7919ULL);
             Mat MT((int)cols.size(), ncand);  // transpose of K(cand, cols)
             for (int c = 0; c < ncand; ++c)
                 for (size_t s = 0; s < cols.size(); ++s) MT((int)s, c) = K.entry(cand[c], cols[s]);
             return MT;
         };
-        std::vector<int> ranks(npairs);
-        parallel_for(npairs, nt, [&](int64_t pr) {
-            auto cand = candidates(pr);
-            ranks[pr] = id_rank(sample_matrix(pr, cand), opt.eps, ncand);
+        const std::vector<int64_t> probe = rank_probe_pairs(npairs, nOm, xi0 / szOm, opt.seed ^ (0xC00 + l));
+        std::vector<int> ranks(probe.size());
+        parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
+            auto cand = candidates(probe[t]);
+            ranks[t] = id_rank(sample_matrix(probe[t], cand, n_samples(ncand, N)), opt.eps, ncand);
         });
-        const int r = std::max(1, *std::max_element(ranks.begin(), ranks.end()));
+        const int r = std::min(ncand, std::max(1, *std::max_element(ranks.begin(), ranks.end())));
         B.rU[l] = r;
         skelU[l].assign((size_t)npairs * r, 0);
         std::vector<Mat> Q(npairs);
         parallel_for(npairs, nt, [&](int64_t pr) {
             auto cand = candidates(pr);
-            ColumnID id = column_id(sample_matrix(pr, cand), opt.eps, r, ncand);
+            ColumnID id = column_id(sample_matrix(pr, cand, n_samples(ncand, N)), opt.eps, r, ncand);
             // K(cand, :) ~= Q K(skel, :) with Q(skel_k, k) = 1 and Q(redund_t, k) = T(k, t).
             Mat q(ncand, r);
             for (int k = 0; k < r; ++k) {
@@ -109,6 +132,7 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
                 for (int k = 0; k < r; ++k) q(id.redund[t], k) = id.T(k, (int)t);
             Q[pr] = std::move(q);
         });
+        progress(opt.verbose, "butterfly X side level %d: rank %d", l, r);
         if (l < L) skelU[l + 1].clear();
         Stage st;
         if (l == L) {
@@ -167,27 +191,29 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
             }
             return c;
         };
-        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand) {
+        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand, int ns) {
             int64_t i = pr / nOm;
-            std::vector<int> rows = stratified(i * szX, szX, n_samples(ncand, szX),
+            std::vector<int> rows = stratified(i * szX, szX, std::min<int64_t>(ns, szX),
                                                opt.seed ^ splitmix64(0xB000 + l) ^ (uint64_t)pr * 104729ULL);
             Mat M((int)rows.size(), ncand);
             for (int c = 0; c < ncand; ++c)
                 for (size_t s = 0; s < rows.size(); ++s) M((int)s, c) = K.entry(rows[s], cand[c]);
             return M;
         };
-        std::vector<int> ranks(npairs);
-        parallel_for(npairs, nt, [&](int64_t pr) {
-            auto cand = candidates(pr);
-            ranks[pr] = id_rank(sample_matrix(pr, cand), opt.eps, ncand);
+        const int64_t szOmV = N / nOm;
+        const std::vector<int64_t> probe = rank_probe_pairs(npairs, nOm, xi0 / szOmV, opt.seed ^ (0xD00 + l));
+        std::vector<int> ranks(probe.size());
+        parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
+            auto cand = candidates(probe[t]);
+            ranks[t] = id_rank(sample_matrix(probe[t], cand, n_samples(ncand, N)), opt.eps, ncand);
         });
-        const int r = std::max(1, *std::max_element(ranks.begin(), ranks.end()));
+        const int r = std::min(ncand, std::max(1, *std::max_element(ranks.begin(), ranks.end())));
         B.rV[l] = r;
         skelV[l].assign((size_t)npairs * r, 0);
         std::vector<Mat> G(npairs);
         parallel_for(npairs, nt, [&](int64_t pr) {
             auto cand = candidates(pr);
-            ColumnID id = column_id(sample_matrix(pr, cand), opt.eps, r, ncand);
+            ColumnID id = column_id(sample_matrix(pr, cand, n_samples(ncand, N)), opt.eps, r, ncand);
             // K(:, cand) ~= K(:, skel) G with G(k, skel_k) = 1 and G(k, redund_t) = T(k, t).
             Mat g(r, ncand);
             for (int k = 0; k < r; ++k) {
@@ -198,6 +224,7 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
                 for (int k = 0; k < r; ++k) g(k, id.redund[t]) = id.T(k, (int)t);
             G[pr] = std::move(g);
         });
+        progress(opt.verbose, "butterfly Omega side level %d: rank %d", l, r);
         if (l > 0) skelV[l - 1].clear();
         Stage st;
         st.n_out = npairs; st.n_in = npairs;

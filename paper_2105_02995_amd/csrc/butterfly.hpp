@@ -22,6 +22,7 @@ struct ButterflyOptions {
     int leaf = 8;         // leaf side (points per dimension)
     int nthreads = 0;
     uint64_t seed = 1;    // column/row sampling
+    bool verbose = false;
 };
 
 struct Butterfly {

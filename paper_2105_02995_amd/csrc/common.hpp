@@ -60,6 +60,9 @@ void parallel_for(int64_t n, int nthreads, Fn &&fn) {
     if (err) std::rethrow_exception(err);
 }
 
+// Progress line on stderr (build phases); flushed so a watcher sees it at once.
+void progress(bool on, const char *fmt, ...);
+
 // splitmix64: the builder's own counter-based generator for random probes.
 inline uint64_t splitmix64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ULL;

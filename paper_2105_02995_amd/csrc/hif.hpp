@@ -50,11 +50,17 @@ struct PeelOptions {
     int k0 = 16;            // initial rank guess k
     uint64_t seed = 7;
     int nthreads = 0;
+    bool verbose = false;
 };
 
 // 1D HODLR peeling of a Hermitian operator given only by products (section 3),
 // followed by recursive skeletonization (section 4) with tolerance eps_hif.
 HifFactors build_hif_1d(const BlockApply &A, int64_t N, const PeelOptions &po, double eps_hif);
+
+// 2D H-matrix peeling with strong admissibility and periodic neighbour lists
+// (section 3) followed by cell and edge skeletonization (section 4, 2D case).
+// n points per side; po.leaf is the side of the leaf cells.
+HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, double eps_hif);
 
 // Largest eigenvalue estimate of a Hermitian positive operator by power iteration.
 double power_norm(const BlockApply &A, int64_t N, int iters, uint64_t seed);

@@ -110,6 +110,7 @@ Hodlr1D peel_1d(const BlockApply &A, int64_t N, const PeelOptions &po, double no
                 k = (int)std::min<int64_t>(2 * k, sz);
                 continue;
             }
+            progress(po.verbose, "peeling level %d: rank <= %d", l, k + c);
             H.U[l].resize(2 * np);
             H.B[l] = std::move(Bp);
             for (int64_t p = 0; p < np; ++p) {

@@ -39,7 +39,8 @@ class fio_problem(ctypes.Structure):
                 ("eps_bf", ctypes.c_double), ("eps_peel", ctypes.c_double),
                 ("eps_hif", ctypes.c_double), ("leaf_bf", ctypes.c_int),
                 ("leaf_h", ctypes.c_int), ("oversample", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("device", ctypes.c_int), ("nthreads", ctypes.c_int)]
+                ("seed", ctypes.c_uint64), ("device", ctypes.c_int), ("nthreads", ctypes.c_int),
+                ("verbose", ctypes.c_int)]
 
 
 class fio_solve_opts(ctypes.Structure):

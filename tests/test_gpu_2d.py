@@ -1,0 +1,111 @@
+"""GPU parity for the 2D generalized Radon example (section 6, Example 3):
+H-matrix inverse with cell and edge skeletonization, used directly and as the
+CG preconditioner on the normal equations (section 5), against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fio_synth import gaussian_complex
+from paper_2105_02995_amd import fio as F
+
+from . import factor_file as FF
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from . import gpu_util as G  # noqa: E402
+
+EPS = 1e-4
+_plans = {}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def plan2d(n):
+    if n not in _plans:
+        log("building 2D plan n=%d eps=%g" % (n, EPS))
+        _plans[n] = F.fio_build(F.make_problem(2, n, "2d_radon", eps=EPS, device=0, verbose=1))
+    return _plans[n]
+
+
+@pytest.fixture(scope="module")
+def case64():
+    n = 64
+    p = O.OracleProblem(2, n, "2d_radon", 16.0)
+    K = O.dense_K(p)
+    f = gaussian_complex((n * n, 16), 1002)
+    u = K @ O.dft(f, 2, n)
+    return p, K, f, u, O.solve_dense(p, u, K)
+
+
+@pytest.mark.parametrize("dtype", [F.FIO_C128, F.FIO_C64])
+def test_2d_apply_vs_oracle(case64, dtype):
+    p, K, f, u, ref = case64
+    plan = plan2d(64)
+    x = gaussian_complex((4096, 17), 5)
+    assert O.rel_err(G.apply(plan, F.FIO_OP_K, dtype, x), K @ x).max() < 10 * EPS
+    assert O.rel_err(G.apply(plan, F.FIO_OP_KH, dtype, x), K.conj().T @ x).max() < 10 * EPS
+
+
+def test_2d_apply_matches_saved_factors(tmp_path):
+    plan = plan2d(64)
+    path = str(tmp_path / "p.fio")
+    F.fio_save(plan, path)
+    f = FF.read(path)
+    x = gaussian_complex((4096, 20), 6)
+    assert O.rel_err(G.apply(plan, F.FIO_OP_K, F.FIO_C128, x), FF.apply_K(f, x)).max() < 1e-12
+    assert O.rel_err(G.inverse(plan, F.FIO_C128, x), FF.inverse(f, x)).max() < 1e-11
+
+
+@pytest.mark.parametrize("dtype", [F.FIO_C128, F.FIO_C64])
+def test_2d_direct_inverse_vs_lu(case64, dtype):
+    """fhat = Gd Kd^* u within 10 eps of the dense LU solve (n=64, eps=1e-4)."""
+    p, K, f, u, ref = case64
+    x = G.inverse(plan2d(64), dtype, u)
+    err = O.rel_err(x, ref)
+    log("2D direct inverse dtype=%d max rel err %.2e" % (dtype, err.max()))
+    assert err.max() < 10 * EPS
+
+
+@pytest.mark.parametrize("precondition,lo,hi", [(1, 1, 4), (0, 17, 23)])
+def test_2d_pcg_iteration_counts(case64, precondition, lo, hi):
+    """pcg(Kd^*Kd, Kd^*u, Gd) to 1e-8 (config: 16 RHS): the paper reports 3
+    iterations with Gd and 20 with Kd^* alone at n=64 (Table 2d_FIO)."""
+    p, K, f, u, ref = case64
+    x, (its, rr) = G.solve(plan2d(64), F.FIO_SOLVE_PCG, F.FIO_C128, u, tol=1e-8, maxit=200,
+                           precondition=precondition)
+    log("2D PCG precondition=%d its=%d resid=%.2e" % (precondition, its, rr))
+    assert lo <= its <= hi
+    assert O.rel_err(x, ref).max() < 10 * EPS
+
+
+def test_2d_refine_c64_vs_lu(case64):
+    p, K, f, u, ref = case64
+    x, (its, rr) = G.solve(plan2d(64), F.FIO_SOLVE_REFINE, F.FIO_C64, u, maxit=2)
+    assert O.rel_err(x, ref).max() < 10 * EPS
+    assert O.rel_err(O.idft(x, 2, 64), f).max() < 10 * EPS
+
+
+def test_2d_n128_batch256_sampled_columns():
+    """n=128 (N=16384), 256 right-hand sides, complex64 applies + FP64 refinement:
+    four columns carry u = K fhat from the oracle's direct summation."""
+    n, B = 128, 256
+    plan = plan2d(n)
+    p = O.OracleProblem(2, n, "2d_radon", 16.0)
+    fh = gaussian_complex((n * n, 4), 3003)
+    log("oracle direct summation n=128, 4 columns")
+    u = gaussian_complex((n * n, B), 3004)
+    cols = np.array([0, 99, 200, 255])
+    u[:, cols] = O.apply_direct(p, fh)
+    x, (its, rr) = G.solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, u, maxit=1)
+    err = O.rel_err(x[:, cols], fh)
+    log("2D n=128 refine rel err %s" % err)
+    assert err.max() < 10 * EPS

@@ -122,3 +122,30 @@ def test_load_rejects_garbage(tmp_path):
     with pytest.raises(F.FioError) as e:
         F.fio_load(str(bad), device=-1)
     assert e.value.status == 7
+
+
+def test_2d_host_construction_n32(tmp_path):
+    """2D generalized Radon example (section 6, Example 3) at n=32, eps=1e-4: the
+    H-matrix peeling (strong admissibility, periodic neighbours) and the cell/edge
+    skeletonization inverse give a direct solve within 10 eps, and Gd makes CG on
+    the normal equations converge in a few iterations (section 5)."""
+    eps = 1e-4
+    plan = F.fio_build(F.make_problem(2, 32, "2d_radon", eps=eps, device=-1))
+    path = str(tmp_path / "p2.fio")
+    F.fio_save(plan, path)
+    f = FF.read(path)
+    p = O.OracleProblem(2, 32, "2d_radon", 16.0)
+    K = O.dense_K(p)
+    x = gaussian_complex((1024, 2), 3)
+    assert O.rel_err(FF.apply_K(f, x), K @ x).max() < eps
+    fs = gaussian_complex((1024, 2), 1002)
+    u = K @ O.dft(fs, 2, 32)
+    ref = O.solve_dense(p, u, K)
+    assert O.rel_err(FF.inverse(f, u), ref).max() < 10 * eps
+    pre = lambda r: FF.from_tree(f, FF.gd(f, FF.to_tree(f, r)))
+    _, its = O.cg_normal(lambda v: FF.apply_K(f, v), lambda v: FF.apply_KH(f, v), u[:, 0],
+                         tol=1e-8, precond=pre)
+    assert its <= 4
+    # every DOF is eliminated exactly once or kept in the root
+    seen = np.concatenate([nd["r"] for st in f["steps"] for nd in st] + [f["root"]])
+    assert np.array_equal(np.sort(seen), np.arange(1024))
