@@ -1,0 +1,339 @@
+"""Continuous-batching server for factored FIO solves.
+
+Requests (a right-hand-side block for one factor key: dimension, n, phase, eps)
+arrive over time.  Factors of every key stay resident on the GPU.  The scheduler
+keeps one queue per key; whenever a key has no batch on the device, all its
+queued requests (up to ``max_batch_rhs`` columns) are merged into one batch and
+started on a free stream, if the batch's buffers fit the HBM budget.  Batches of
+different keys run concurrently on different streams, so requests that arrive
+while others are on the GPU are admitted as soon as their key's slot and the
+memory free up.  Every request's latency (arrival to result in host memory) is
+recorded.
+
+The scheduler talks to an executor with three calls (``footprint``, ``start``,
+``poll``); ``GpuExecutor`` runs batches through the C ABI (``fio_solve``), and
+``MockExecutor`` completes them after a modelled duration so the scheduling,
+admission and accounting logic can be tested on a CPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import heapq
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    rid: int
+    key: tuple            # (d, n, phase, eps)
+    arrival: float        # seconds, on the server clock
+    u: np.ndarray         # (N, nrhs) complex128
+    result: np.ndarray | None = None
+    start: float | None = None
+    done: float | None = None
+
+    @property
+    def nrhs(self) -> int:
+        return self.u.shape[1]
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class Batch:
+    key: tuple
+    requests: list
+    nrhs: int
+    bytes: int
+    handle: object = None
+
+
+class Scheduler:
+    """Continuous batching with HBM-footprint admission over an executor."""
+
+    def __init__(self, executor, hbm_budget: int, max_batch_rhs: int = 256,
+                 max_inflight: int = 8):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_batch_rhs = max_batch_rhs
+        self.max_inflight = max_inflight
+        self.queues = collections.defaultdict(collections.deque)
+        self.running = {}           # key -> Batch
+        self.resident = 0           # bytes of resident factors and workspaces
+        self.inflight_bytes = 0
+        self.finished = []
+        self.batches_started = 0
+        self.peak_inflight = 0
+        self.rejected_keys = []
+
+    # ---------------------------------------------------------------- keys
+    def register(self, key) -> bool:
+        """Make a key's factors resident if they fit the budget (else refuse it)."""
+        need = self.ex.resident_bytes(key)
+        if self.resident + need > self.budget:
+            self.rejected_keys.append(key)
+            return False
+        self.ex.load(key)
+        self.resident += need
+        return True
+
+    # ---------------------------------------------------------------- loop
+    def submit(self, req: ServeRequest):
+        self.queues[req.key].append(req)
+
+    def _form_batch(self, key):
+        q = self.queues[key]
+        reqs, cols = [], 0
+        while q and (cols + q[0].nrhs <= self.max_batch_rhs or not reqs):
+            r = q.popleft()
+            reqs.append(r)
+            cols += r.nrhs
+        return Batch(key, reqs, cols, self.ex.footprint(key, cols))
+
+    def step(self, now: float):
+        """Start every admissible batch, then collect the finished ones."""
+        for key in list(self.queues):
+            if not self.queues[key] or key in self.running:
+                continue
+            if len(self.running) >= self.max_inflight:
+                break
+            b = self._form_batch(key)
+            if self.resident + self.inflight_bytes + b.bytes > self.budget:
+                for r in reversed(b.requests):  # not admitted: back to the queue head
+                    self.queues[key].appendleft(r)
+                continue
+            for r in b.requests:
+                r.start = now
+            b.handle = self.ex.start(b, now)
+            self.running[key] = b
+            self.inflight_bytes += b.bytes
+            self.batches_started += 1
+            self.peak_inflight = max(self.peak_inflight, len(self.running))
+        for key, b in list(self.running.items()):
+            res = self.ex.poll(b.handle, now)
+            if res is None:
+                continue
+            t = self.ex.clock()
+            c0 = 0
+            for r in b.requests:
+                r.result = res[:, c0:c0 + r.nrhs]
+                r.done = t
+                c0 += r.nrhs
+                self.finished.append(r)
+            del self.running[key]
+            self.inflight_bytes -= b.bytes
+
+    def idle(self) -> bool:
+        return not self.running and not any(self.queues.values())
+
+    def run(self, requests, time_scale: float = 1.0, timeout: float = 600.0):
+        """Replay requests at their arrival times (seconds * time_scale) until all finish."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.ex.clock()
+        i = 0
+        while True:
+            now = self.ex.clock() - t0
+            while i < len(pending) and pending[i].arrival * time_scale <= now:
+                r = pending[i]
+                r.arrival = t0 + r.arrival * time_scale
+                self.submit(r)
+                i += 1
+            self.step(self.ex.clock())
+            if i == len(pending) and self.idle():
+                break
+            if now > timeout:
+                raise TimeoutError("serving run exceeded %.0f s" % timeout)
+            self.ex.wait()
+        return self.finished
+
+
+def latency_stats(finished) -> dict:
+    lat = np.array([r.latency for r in finished])
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3), "count": int(lat.size)}
+
+
+def throughput(finished) -> float:
+    """RHS * N per second over the span from the first arrival to the last completion."""
+    t0 = min(r.arrival for r in finished)
+    t1 = max(r.done for r in finished)
+    work = sum(r.nrhs * r.u.shape[0] for r in finished)
+    return work / max(t1 - t0, 1e-9)
+
+
+# ====================================================================== executors
+class MockExecutor:
+    """CPU stand-in: a batch takes ``cost(key, nrhs)`` seconds of modelled time and
+    returns ``transform(key, u)``; clock and waiting are virtual."""
+
+    def __init__(self, cost, transform=None, factor_bytes=None, ws_bytes_per_rhs=None):
+        self.cost = cost
+        self.transform = transform or (lambda key, u: u.copy())
+        self.factor_bytes = factor_bytes or (lambda key: 0)
+        self.ws_bytes_per_rhs = ws_bytes_per_rhs or (lambda key: 0)
+        self.t = 0.0
+        self.events = []
+        self.loaded = []
+
+    def clock(self):
+        return self.t
+
+    def wait(self):
+        self.t += 1e-4
+
+    def resident_bytes(self, key):
+        return self.factor_bytes(key)
+
+    def load(self, key):
+        self.loaded.append(key)
+
+    def footprint(self, key, nrhs):
+        return self.ws_bytes_per_rhs(key) * nrhs
+
+    def start(self, batch, now):
+        u = np.concatenate([r.u for r in batch.requests], axis=1)
+        return (self.t + self.cost(batch.key, batch.nrhs), self.transform(batch.key, u))
+
+    def poll(self, handle, now):
+        t_done, res = handle
+        return res if self.t >= t_done else None
+
+
+class GpuExecutor:
+    """Runs batches through the C ABI on a pool of HIP streams (default priority).
+
+    Loading a key sizes its plan's workspace for ``max_batch_rhs`` columns and
+    allocates pinned host staging for it, so nothing is allocated inside the
+    library while serving.  A batch copies its right-hand sides to the device,
+    runs ``fio_solve`` (complex64 applies + ``refine`` FP64 refinement steps),
+    copies the result back and records an event.
+
+    With ``use_graphs`` the solve of each key is captured once per batch-size
+    bucket (a HIP graph of all its kernel launches, on static device buffers) and
+    replayed; a batch is padded up to its bucket.  Columns are independent, so
+    padding does not change the results.
+    """
+
+    BUCKETS = (16, 32, 64, 128, 256, 512, 1024)
+
+    def __init__(self, plans: dict, max_batch_rhs: int = 256, refine: int = 1, nstreams: int = 4,
+                 use_graphs: bool = False):
+        import torch
+        from . import fio as F
+        self.torch, self.F = torch, F
+        self.plans = plans            # key -> Plan
+        self.max_batch_rhs = max_batch_rhs
+        self.refine = refine
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.busy = {}
+        self.stats = {k: F.fio_plan_stats(p) for k, p in plans.items()}
+        self.use_graphs = use_graphs
+        self.graphs = {}              # (key, bucket) -> (graph, U, X)
+        self.stage = {}               # key -> (pinned u, pinned x)
+
+    def clock(self):
+        return time.perf_counter()
+
+    def wait(self):
+        time.sleep(5e-5)
+
+    def _N(self, key):
+        return self.stats[key]["n"] ** self.stats[key]["d"]
+
+    def _bucket(self, nrhs):
+        for b in self.BUCKETS:
+            if nrhs <= b:
+                return b
+        return nrhs
+
+    def resident_bytes(self, key):
+        s = self.stats[key]
+        static = 0
+        if self.use_graphs:
+            static = sum(2 * self._N(key) * b * 16 for b in self.BUCKETS if b <= self._bucket(self.max_batch_rhs))
+        return s["device_bytes"] + s["workspace_bytes"] * self._bucket(self.max_batch_rhs) + static
+
+    def _solve(self, key, U, X, B, stream):
+        F = self.F
+        F.fio_solve(self.plans[key], F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, self._N(key), tol=0.0,
+                    maxit=self.refine, stream=stream, want_info=False)
+
+    def load(self, key):
+        torch = self.torch
+        N = self._N(key)
+        top = self._bucket(self.max_batch_rhs)
+        U = torch.zeros((top, N), dtype=torch.complex128, device="cuda")
+        X = torch.zeros_like(U)
+        self._solve(key, U, X, top, torch.cuda.current_stream())  # sizes the plan's workspace
+        torch.cuda.synchronize()
+        self.stage[key] = (torch.empty((top, N), dtype=torch.complex128).pin_memory(),
+                           torch.empty((top, N), dtype=torch.complex128).pin_memory())
+        if self.use_graphs:
+            s = self.streams[0]
+            for b in self.BUCKETS:
+                if b > top:
+                    break
+                Ub = torch.zeros((b, N), dtype=torch.complex128, device="cuda")
+                Xb = torch.zeros_like(Ub)
+                with torch.cuda.stream(s):
+                    self._solve(key, Ub, Xb, b, s)  # eager warm-up on the capture stream
+                s.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=s):
+                    self._solve(key, Ub, Xb, b, s)
+                self.graphs[(key, b)] = (g, Ub, Xb)
+            torch.cuda.synchronize()
+
+    def footprint(self, key, nrhs):
+        if self.use_graphs:
+            return 0  # static per-bucket buffers are counted as resident
+        return 2 * self._N(key) * nrhs * 16
+
+    def _stream(self):
+        used = set(id(s) for s in self.busy.values())
+        for s in self.streams:
+            if id(s) not in used:
+                return s
+        return self.streams[0]
+
+    def start(self, batch, now):
+        torch = self.torch
+        key = batch.key
+        N = self._N(key)
+        B = batch.nrhs
+        s = self._stream()
+        hu, hx = self.stage[key]
+        c0 = 0
+        for r in batch.requests:
+            hu[c0:c0 + r.nrhs].copy_(torch.from_numpy(np.ascontiguousarray(r.u.T)))
+            c0 += r.nrhs
+        with torch.cuda.stream(s):
+            if self.use_graphs:
+                g, U, X = self.graphs[(key, self._bucket(B))]
+                U[:B].copy_(hu[:B], non_blocking=True)
+                g.replay()
+                hx[:B].copy_(X[:B], non_blocking=True)
+                keep = None
+            else:
+                U = torch.empty((B, N), dtype=torch.complex128, device="cuda")
+                X = torch.empty_like(U)
+                U.copy_(hu[:B], non_blocking=True)
+                self._solve(key, U, X, B, s)
+                hx[:B].copy_(X, non_blocking=True)
+                keep = (U, X)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self.busy[id(batch)] = s
+        return (batch, ev, B, keep)
+
+    def poll(self, handle, now):
+        batch, ev, B, keep = handle
+        if not ev.query():
+            return None
+        self.busy.pop(id(batch), None)
+        return self.stage[batch.key][1][:B].numpy().T.copy()

@@ -1,0 +1,141 @@
+"""Serving on the GPU: continuous batching of mixed 1D/2D solves with resident
+factors; every result must be the same alone and in the mix, and correct."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fio_synth import gaussian_complex
+from paper_2105_02995_amd import fio as F
+from paper_2105_02995_amd.serve import (GpuExecutor, Scheduler, ServeRequest, latency_stats,
+                                        throughput)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+KEYS = [(1, 1024, "1d_ex1", 1e-6), (1, 4096, "1d_ex1", 1e-4), (2, 32, "2d_radon", 1e-4)]
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def plans():
+    out = {}
+    for k in KEYS:
+        log("building plan %s" % (k,))
+        out[k] = F.fio_build(F.make_problem(k[0], k[1], k[2], eps=k[3], device=0))
+    return out
+
+
+def _mix(count, rate, seed):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    reqs = []
+    for j in range(count):
+        k = KEYS[int(rng.integers(len(KEYS)))]
+        N = k[1] ** k[0]
+        reqs.append(ServeRequest(j, k, float(t[j]), gaussian_complex((N, int(rng.integers(1, 17))), 500 + j)))
+    return reqs
+
+
+def test_results_alone_equal_results_in_the_mix(plans):
+    ex = GpuExecutor(plans, max_batch_rhs=64, refine=1)
+    sched = Scheduler(ex, hbm_budget=64 << 30, max_batch_rhs=64)
+    for k in KEYS:
+        assert sched.register(k)
+    reqs = _mix(60, rate=3000.0, seed=7)
+    log("serving 60 mixed requests")
+    done = sched.run(reqs)
+    assert len(done) == 60
+    st = latency_stats(done)
+    log("mix: batches=%d peak_inflight=%d p50=%.2f ms p99=%.2f ms RHS*N/s=%.3e" % (
+        sched.batches_started, sched.peak_inflight, st["p50_ms"], st["p99_ms"], throughput(done)))
+    assert sched.batches_started < 60  # continuous batching merged requests
+    # the same requests one at a time
+    worst = 0.0
+    for r in sorted(done, key=lambda r: r.rid)[:12]:
+        ex1 = GpuExecutor({r.key: plans[r.key]}, max_batch_rhs=64, refine=1)
+        s1 = Scheduler(ex1, hbm_budget=64 << 30, max_batch_rhs=64)
+        assert s1.register(r.key)
+        alone = ServeRequest(r.rid, r.key, 0.0, r.u)
+        s1.run([alone])
+        rel = O.rel_err(alone.result, r.result).max()
+        worst = max(worst, rel)
+        assert rel < 10 * r.key[3], (r.key, rel)
+    log("alone vs mix: worst relative difference %.2e" % worst)
+
+
+def test_mix_results_match_the_oracle(plans):
+    ex = GpuExecutor(plans, max_batch_rhs=64, refine=1)
+    sched = Scheduler(ex, hbm_budget=64 << 30, max_batch_rhs=64)
+    for k in KEYS:
+        sched.register(k)
+    reqs = []
+    t = 0.0
+    truth = {}
+    for j, k in enumerate(KEYS * 3):
+        d, n, phase, eps = k
+        p = O.OracleProblem(d, n, phase, 16.0)
+        fh = gaussian_complex((n ** d, 3), 900 + j)
+        u = O.forward(p, fh)
+        truth[j] = fh
+        reqs.append(ServeRequest(j, k, t, u))
+        t += 0.0005
+    done = sched.run(reqs)
+    for r in done:
+        assert O.rel_err(r.result, truth[r.rid]).max() < 10 * r.key[3]
+
+
+def test_graph_replays_match_eager_solve(plans):
+    """A HIP graph of one whole solve (all kernel launches of fio_solve, captured
+    on a stream) replayed several times, with eager library work and host
+    synchronisation in between: every replay equals the eager result bitwise."""
+    key = (1, 4096, "1d_ex1", 1e-4)
+    plan = plans[key]
+    N, B = 4096, 64
+    u = gaussian_complex((N, B), 4242)
+    U = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()
+    X = torch.zeros_like(U)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, maxit=1, stream=s, want_info=False)
+    s.synchronize()
+    eager = X.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, maxit=1, stream=s, want_info=False)
+    other = torch.zeros_like(U)
+    for rep in range(4):
+        X.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        s.synchronize()
+        assert torch.equal(X, eager), rep
+        # eager work of the program between replays (same plan, other buffers)
+        F.fio_apply(plan, F.FIO_OP_K, F.FIO_C128, U, other, B, N, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+
+
+def test_serving_with_graphs_matches_eager_serving(plans):
+    reqs_a = _mix(40, rate=800.0, seed=11)
+    reqs_b = [ServeRequest(r.rid, r.key, r.arrival, r.u) for r in reqs_a]
+    out = []
+    for reqs, graphs in ((reqs_a, False), (reqs_b, True)):
+        ex = GpuExecutor(plans, max_batch_rhs=64, refine=1, use_graphs=graphs)
+        sch = Scheduler(ex, hbm_budget=64 << 30, max_batch_rhs=64)
+        for k in KEYS:
+            assert sch.register(k)
+        done = sch.run(reqs)
+        st = latency_stats(done)
+        log("graphs=%s: p50=%.2f ms p99=%.2f ms" % (graphs, st["p50_ms"], st["p99_ms"]))
+        out.append({r.rid: r for r in done})
+    for rid, r in out[0].items():
+        assert O.rel_err(out[1][rid].result, r.result).max() < 10 * r.key[3]

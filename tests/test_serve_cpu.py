@@ -1,0 +1,111 @@
+"""Serving loop on the CPU: scheduling, continuous batching, HBM admission and
+latency accounting, with a mock executor standing in for the GPU."""
+import numpy as np
+import pytest
+
+from fio_synth import gaussian_complex, serving_mix
+from paper_2105_02995_amd.serve import (MockExecutor, Scheduler, ServeRequest, latency_stats,
+                                        throughput)
+
+
+def _key(i):
+    return (1, 1024 * (1 + i % 3), "1d_ex1", 1e-6)
+
+
+def _requests(count, rate, seed=0, max_rhs=8, keys=3):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    out = []
+    for j in range(count):
+        k = _key(int(rng.integers(keys)))
+        nr = int(rng.integers(1, max_rhs + 1))
+        out.append(ServeRequest(j, k, float(t[j]), gaussian_complex((16, nr), 100 + j)))
+    return out
+
+
+def _transform(key, u):
+    return u * (1.0 + key[1] / 1024.0)  # a per-key linear map, columnwise
+
+
+def test_every_request_gets_its_own_columns_back():
+    ex = MockExecutor(cost=lambda key, nr: 0.01 + 1e-4 * nr, transform=_transform)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=32)
+    for k in {_key(i) for i in range(3)}:
+        assert s.register(k)
+    reqs = _requests(200, rate=500.0)
+    done = s.run(reqs)
+    assert len(done) == 200
+    for r in done:
+        np.testing.assert_array_equal(r.result, _transform(r.key, r.u))
+        assert r.done >= r.start >= r.arrival
+
+
+def test_requests_arriving_during_a_batch_are_merged_into_the_next():
+    ex = MockExecutor(cost=lambda key, nr: 0.05)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=1024)
+    s.register(_key(0))
+    reqs = [ServeRequest(j, _key(0), 0.001 * j, gaussian_complex((8, 2), j)) for j in range(100)]
+    s.run(reqs)
+    # 100 requests over 0.1 s with 50 ms batches: a handful of batches, not 100
+    assert s.batches_started <= 5
+    assert len(s.finished) == 100
+
+
+def test_batch_never_exceeds_max_columns_unless_a_single_request_does():
+    sizes = []
+
+    class Ex(MockExecutor):
+        def start(self, batch, now):
+            sizes.append((batch.nrhs, len(batch.requests)))
+            return super().start(batch, now)
+
+    ex = Ex(cost=lambda key, nr: 0.01)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=10)
+    s.register(_key(0))
+    reqs = [ServeRequest(j, _key(0), 0.0, gaussian_complex((4, 3 if j != 5 else 25), j)) for j in range(12)]
+    s.run(reqs)
+    assert all(n <= 10 or k == 1 for n, k in sizes)
+    assert any(n == 25 for n, _ in sizes)
+
+
+def test_hbm_admission_bounds_inflight_bytes_and_refuses_oversized_keys():
+    inflight = []
+    per_rhs = 1000
+
+    class Ex(MockExecutor):
+        def start(self, batch, now):
+            inflight.append(sched.inflight_bytes + batch.bytes)
+            return super().start(batch, now)
+
+    ex = Ex(cost=lambda key, nr: 0.02, factor_bytes=lambda key: 100_000 if key[0] == 2 else 10_000,
+            ws_bytes_per_rhs=lambda key: per_rhs)
+    sched = Scheduler(ex, hbm_budget=10_000 * 3 + 40 * per_rhs, max_batch_rhs=16)
+    for i in range(3):
+        assert sched.register(_key(i))
+    assert not sched.register((2, 256, "2d_radon", 1e-4))  # would exceed the budget
+    sched.run(_requests(300, rate=2000.0, max_rhs=8))
+    assert len(sched.finished) == 300
+    assert max(inflight) <= 40 * per_rhs
+    assert sched.rejected_keys == [(2, 256, "2d_radon", 1e-4)]
+
+
+def test_different_keys_overlap_and_latency_accounting():
+    ex = MockExecutor(cost=lambda key, nr: 0.03)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=64)
+    for i in range(3):
+        s.register(_key(i))
+    done = s.run(_requests(150, rate=1000.0, keys=3))
+    assert s.peak_inflight >= 2
+    st = latency_stats(done)
+    assert st["p50_ms"] >= 30.0 - 1e-6  # at least one batch duration
+    assert st["p99_ms"] >= st["p50_ms"]
+    assert throughput(done) > 0
+
+
+def test_serving_mix_generator_shapes():
+    mix = serving_mix(50, rate=10.0, seed=2000)
+    assert len(mix) == 50
+    assert all(m.nrhs >= 1 and m.nrhs <= 32 for m in mix)
+    assert {m.d for m in mix} <= {1, 2}
+    arr = [m.arrival for m in mix]
+    assert arr == sorted(arr)
