@@ -63,7 +63,81 @@ def parse():
     ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
+    ap.add_argument("--no-serve", action="store_true", help="skip the small serving leg")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving mix (Poisson arrivals over many keys) instead of the solve bench")
+    ap.add_argument("--serve-requests", type=int, default=200)
     return ap.parse_args()
+
+
+SERVE_KEYS_FULL = ([(1, n, "1d_ex1", e) for n in (1024, 2048, 4096, 8192, 16384, 32768, 65536)
+                    for e in (1e-4, 1e-6)] + [(2, n, "2d_radon", 1e-4) for n in (32, 64, 128)])
+SERVE_KEYS_SMALL = [(1, 4096, "1d_ex1", 1e-6), (1, 65536, "1d_ex1", 1e-6), (2, 64, "2d_radon", 1e-4)]
+
+
+def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True):
+    """Poisson arrivals (seeded) of solves over the given resident keys, 1..32
+    right-hand sides each; the rate is a fraction of the measured saturation rate
+    (all requests at t=0).  Returns p50/p99 latency and RHS*N/s per rate."""
+    from paper_2105_02995_amd.serve import (GpuExecutor, Scheduler, ServeRequest, latency_stats,
+                                            throughput)
+    rng = np.random.default_rng(seed)
+    pools = {k: gaussian_complex((k[1] ** k[0], 32), 7000 + i) for i, k in enumerate(keys)}
+    kidx = rng.integers(len(keys), size=nreq)
+    nrhs = rng.integers(1, 33, size=nreq)
+    ex = GpuExecutor({k: plans[k] for k in keys}, max_batch_rhs=max_batch, refine=1, use_graphs=graphs)
+
+    def make(times):
+        return [ServeRequest(j, keys[kidx[j]], float(times[j]), pools[keys[kidx[j]]][:, :nrhs[j]])
+                for j in range(nreq)]
+
+    sch = Scheduler(ex, hbm_budget=200 << 30, max_batch_rhs=max_batch)
+    for k in keys:
+        if not sch.register(k):
+            raise RuntimeError("key %s does not fit the HBM budget" % (k,))
+    log("serving: saturation burst of %d requests" % nreq)
+    t0 = time.perf_counter()
+    sch.run(make(np.zeros(nreq)))
+    sat = nreq / (time.perf_counter() - t0)
+    out = {"saturation_req_per_s": sat, "keys": len(keys), "requests": nreq, "graphs": graphs, "rates": []}
+    for frac in fracs:
+        sch.finished = []
+        times = np.cumsum(rng.exponential(1.0 / (frac * sat), nreq))
+        done = sch.run(make(times))
+        st = latency_stats(done)
+        rec = {"rate_frac": frac, "req_per_s": frac * sat, "p50_ms": st["p50_ms"],
+               "p99_ms": st["p99_ms"], "rhs_n_per_s": throughput(done)}
+        log("serving at %.2f x saturation: p50 %.2f ms, p99 %.2f ms, %.3e RHS*N/s" % (
+            frac, st["p50_ms"], st["p99_ms"], rec["rhs_n_per_s"]))
+        out["rates"].append(rec)
+    return out
+
+
+def build_plans(F, keys, have=None):
+    plans = dict(have or {})
+    for k in keys:
+        if k in plans:
+            continue
+        t0 = time.perf_counter()
+        plans[k] = F.fio_build(F.make_problem(k[0], k[1], k[2], eps=k[3], device=0))
+        log("built %s in %.1f s" % (k, time.perf_counter() - t0))
+    return plans
+
+
+def serve_main(args):
+    import torch  # noqa: F401
+    from paper_2105_02995_amd import fio as F
+    plans = build_plans(F, SERVE_KEYS_FULL)
+    res = serving_run(F, plans, SERVE_KEYS_FULL, args.serve_requests, (0.5, 0.8, 0.95), 2000)
+    head = res["rates"][1]
+    out = {"metric": "serving mix: p50/p99 latency and RHS*N/s of factored FIO solves",
+           "value": head["rhs_n_per_s"], "unit": "RHS*N/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "Poisson arrivals over %d resident keys (1D N=1024..65536 at eps 1e-4/1e-6, "
+                                  "2D n=32,64,128 at eps 1e-4), 1-32 RHS per request, complex64 + 1 FP64 "
+                                  "refinement step, HIP-graph replay" % len(SERVE_KEYS_FULL)},
+           "serving": res}
+    print(json.dumps(out), flush=True)
 
 
 def stage_timing(F, plan, torch, dtype, op, nrhs, reps=5):
@@ -102,7 +176,7 @@ def cpu_baseline(wl, x_gpu, u):
     iteration count comes from the oracle's own CG at N = 4096 (same phase).
     Also checks the GPU solution's residual on sampled rows."""
     import oracle as O
-    p_small = O.OracleProblem(1, 4096, wl.phase, wl.c_div)
+    p_small = O.OracleProblem(wl.d, 4096 if wl.d == 1 else 64, wl.phase, wl.c_div)
     K = O.dense_K(p_small)
     _, iters = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v,
                            gaussian_complex(4096, 99), tol=1e-8)
@@ -131,6 +205,8 @@ def main():
         print("bench.py runs on one GPU only: the factored solve is measured on a single "
               "MI355X (multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve_main(args)
     import torch
     from paper_2105_02995_amd import fio as F
 
@@ -224,6 +300,14 @@ def main():
                  "nrhs_per_call": 1}
         log("plain FP64 single-RHS: %.3f ms/RHS, %.3e RHS*N/s" % (1000 * tp / ncols, plain["value"]))
 
+    serving = None
+    if not args.no_serve and wl.d == 1 and wl.n == 65536:
+        plans = build_plans(F, SERVE_KEYS_SMALL, {SERVE_KEYS_SMALL[1]: plan})
+        serving = serving_run(F, plans, SERVE_KEYS_SMALL, 100, (0.8,), 2000)
+        for k, pl in plans.items():
+            if pl is not plan:
+                pl.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -239,7 +323,9 @@ def main():
                                "eps=%g, complex64 applies + %d FP64 refinement step(s)"
                                % (wl.name, N, B, wl.eps, args.refine),
                    "N": N, "nrhs": B, "eps": wl.eps},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "what": "per-step (64-RHS batch) latency, HIP events"},
+        "serving": serving,
         "last_correction_rel": corr,
         "roofline": roof,
         "cpu_baseline": cpu,
