@@ -59,12 +59,14 @@ template <class T> struct DStageStore {
 };
 
 struct DHifStore {
-    DBuf desc, idx, m64, m128;
+    DBuf desc, idx, m64, m128, tr, ts;
     HifStepDev view(bool dbl) const {
         HifStepDev v = base;
         v.desc = (const int64_t *)desc.p;
         v.idx = (const int32_t *)idx.p;
         v.mat = dbl ? m128.p : m64.p;
+        v.tiles_r = (const int32_t *)tr.p;
+        v.tiles_s = (const int32_t *)ts.p;
         return v;
     }
     HifStepDev base;
@@ -88,13 +90,13 @@ struct fio_plan_s {
     std::vector<Stage> adj;                   // host adjoint stages (Kd^*)
     std::vector<DStageStore<int>> dfwd, dadj;
     std::vector<DHifStore> dhif;
-    DBuf root_idx, A0inv, perm;
+    DBuf root_idx, A0inv, perm, root_stage_idx;
     int s0 = 0;
     int64_t max_coef = 0;                     // longest coefficient vector between stages
     int64_t device_bytes = 0;
     // workspace (grown on demand)
     int ws_nrhs = 0;
-    DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal;
+    DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal, HT, RI, RO;
     std::mutex mu;
 };
 
@@ -104,7 +106,7 @@ void count_bytes(fio_plan p) {
     int64_t b = 0;
     for (auto &s : p->dfwd) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
     for (auto &s : p->dadj) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
-    for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes;
+    for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes + h.tr.bytes + h.ts.bytes;
     b += p->root_idx.bytes + p->A0inv.bytes + p->perm.bytes;
     p->device_bytes = b;
 }
@@ -134,6 +136,12 @@ void upload_plan(fio_plan p) {
         std::vector<int32_t> idx;
         std::vector<cd> mat;
         int mr = 0, ms = 0, mv = 0, mm = 0;
+        std::vector<int32_t> tr, ts;
+        for (size_t v = 0; v < st.nodes.size(); ++v) {
+            const int nr = (int)st.nodes[v].idx_r.size(), ns = (int)st.nodes[v].idx_s.size();
+            for (int r0 = 0; r0 < nr; r0 += 16) { tr.push_back((int32_t)v); tr.push_back(r0); }
+            for (int r0 = 0; r0 < ns; r0 += 16) { ts.push_back((int32_t)v); ts.push_back(r0); }
+        }
         for (const HifNode &nd : st.nodes) {
             const int nr = (int)nd.idx_r.size(), ns = (int)nd.idx_s.size();
             mr = std::max(mr, nr);
@@ -156,6 +164,10 @@ void upload_plan(fio_plan p) {
         d.base.max_ns = ms;
         d.base.max_vec = mv;
         d.base.max_mat = mm;
+        d.tr.upload(tr.data(), tr.size() * sizeof(int32_t));
+        d.ts.upload(ts.data(), ts.size() * sizeof(int32_t));
+        d.base.n_tiles_r = (int64_t)tr.size() / 2;
+        d.base.n_tiles_s = (int64_t)ts.size() / 2;
         d.desc.upload(desc.data(), desc.size() * sizeof(int64_t));
         d.idx.upload(idx.data(), idx.size() * sizeof(int32_t));
         upload_complex(d.m64, d.m128, mat);
@@ -164,6 +176,8 @@ void upload_plan(fio_plan p) {
     p->root_idx.upload(h.hif.root_idx.data(), h.hif.root_idx.size() * sizeof(int32_t));
     p->A0inv.upload(h.hif.A0inv.a.data(), h.hif.A0inv.a.size() * sizeof(cd));
     p->perm.upload(h.perm.data(), h.perm.size() * sizeof(int32_t));
+    const int32_t zero = 0;
+    p->root_stage_idx.upload(&zero, sizeof(int32_t));
     count_bytes(p);
 }
 
@@ -176,6 +190,9 @@ void ensure_ws(fio_plan p, int nrhs) {
     p->U.alloc(vec); p->X.alloc(vec); p->R.alloc(vec); p->Z.alloc(vec); p->Pv.alloc(vec);
     p->red.alloc((size_t)reduce_partial_cap(p->host.N, nrhs) * sizeof(double));
     p->scal.alloc((size_t)nrhs * 8 * sizeof(double));
+    p->HT.alloc(vec);
+    p->RI.alloc((size_t)std::max(1, p->s0) * nrhs * 16);
+    p->RO.alloc((size_t)std::max(1, p->s0) * nrhs * 16);
     p->ws_nrhs = nrhs;
 }
 
@@ -191,10 +208,35 @@ void run_chain(fio_plan p, const std::vector<Stage> &host, const std::vector<DSt
     }
 }
 
+// One skeletonization step: LDS-staged kernel for small nodes, gathered GEMMs on
+// matrix cores when a node's blocks exceed LDS (large 2D cells and edges).
+void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
+    const HifStepDev h = p->dhif[k].view(dbl);
+    if (hif_step_fits_lds(h, dbl) || nrhs < 16) launch_hif_step(h, dbl, up, x, nrhs, st);
+    else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, st);
+}
+
+// A_0^{-1} on the remaining DOFs, always in FP64: as a one-block FP64 stage on
+// matrix cores for batches, else the direct kernel.
+void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
+    if (p->s0 == 0) return;
+    if (nrhs < 16 || p->s0 < 64) {
+        launch_root((const int32_t *)p->root_idx.p, p->A0inv.p, p->s0, dbl, x, nrhs, st);
+        return;
+    }
+    launch_rows_gather(x, dbl, (const int32_t *)p->root_idx.p, p->s0, nrhs, p->RI.p, true, st);
+    StageDev s;
+    s.n_out = 1; s.n_in = 1; s.r_out = p->s0; s.r_in = p->s0; s.fan = 1;
+    s.idx = (const int32_t *)p->root_stage_idx.p;
+    s.A = p->A0inv.p;
+    launch_stage(s, true, p->RI.p, p->RO.p, nrhs, st);
+    launch_rows_scatter(p->RO.p, true, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
+}
+
 void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
-    for (size_t k = 0; k < p->dhif.size(); ++k) launch_hif_step(p->dhif[k].view(dbl), dbl, true, x, nrhs, st);
-    launch_root((const int32_t *)p->root_idx.p, p->A0inv.p, p->s0, dbl, x, nrhs, st);
-    for (size_t k = p->dhif.size(); k-- > 0;) launch_hif_step(p->dhif[k].view(dbl), dbl, false, x, nrhs, st);
+    for (size_t k = 0; k < p->dhif.size(); ++k) hif_step(p, k, dbl, true, x, nrhs, st);
+    root_apply(p, dbl, x, nrhs, st);
+    for (size_t k = p->dhif.size(); k-- > 0;) hif_step(p, k, dbl, false, x, nrhs, st);
 }
 
 void check_apply_args(fio_plan p, int64_t nrhs, int64_t ld, const void *a, const void *b) {
@@ -325,7 +367,7 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
         o->root_size = (int)h.hif.root_idx.size();
         o->max_rank_h = h.hif.max_rank_h;
         o->device_bytes = p->device_bytes;
-        o->workspace_bytes = (int64_t)(2 * p->max_coef + 11 * h.N) * 16;
+        o->workspace_bytes = (int64_t)(2 * p->max_coef + 12 * h.N + 2 * (int64_t)h.hif.root_idx.size()) * 16;
         o->build_seconds = h.build_seconds;
     });
 }

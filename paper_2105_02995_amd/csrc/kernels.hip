@@ -395,6 +395,207 @@ void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, 
     check_launch("hif step");
 }
 
+// ------------------------------------------------------------------ large skeletonization nodes
+// Nodes whose blocks do not fit LDS run as gathered complex GEMMs on matrix
+// cores, all nodes of a step in one launch per phase.  A tile is 16*MT rows of
+// one node's output times 64 right-hand sides; its input rows are gathered from
+// x (or the temporary t) through the node's index lists.
+//   up:   1) x_r -= T^* x_s      2) t_r = Linv x_r      3) x_s -= M t_r; x_r = t_r
+//   down: 1) t_r = x_r - M^* x_s 2) x_r = Linv^* t_r    3) x_s -= T x_r
+// PH selects the phase: 0..2 up, 3..5 down.
+template <class R, int PH, int MT>
+__global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
+                                               const int32_t *__restrict__ idx,
+                                               const int32_t *__restrict__ tiles,
+                                               int64_t ntiles,
+                                               const typename MF<R>::C *__restrict__ mat,
+                                               typename MF<R>::C *__restrict__ x,
+                                               typename MF<R>::C *__restrict__ t, int nrhs) {
+    using C = typename MF<R>::C;
+    using V4 = typename MF<R>::V4;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= ntiles) return;  // wave-uniform
+    const int v = tiles[2 * wave], row0 = tiles[2 * wave + 1];
+    const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
+    const int32_t *ir = idx + desc[4 * v + 2];
+    const int32_t *is = ir + nr;
+    const C *Tm = mat + desc[4 * v + 3];
+    const C *Li = Tm + (int64_t)ns * nr;
+    const C *Mm = Li + (int64_t)nr * nr;
+    // phase configuration
+    constexpr bool CONJT = (PH == 0 || PH == 3 || PH == 4);   // A(i,k) = conj(S[k + i*ld])
+    constexpr bool SUB = (PH == 0 || PH == 2 || PH == 3 || PH == 5);
+    const int m = (PH == 2 || PH == 5) ? ns : nr;
+    const int K = (PH == 0 || PH == 3) ? ns : nr;
+    const C *S = (PH == 0 || PH == 5) ? Tm : ((PH == 1 || PH == 4) ? Li : Mm);
+    const int ld = (PH == 1 || PH == 4) ? nr : ns;
+    const int32_t *kin = (PH == 0 || PH == 3) ? is : ir;      // input rows
+    const C *src = (PH == 2 || PH == 4) ? t : x;              // input vector
+    const int32_t *oout = (PH == 2 || PH == 5) ? is : ir;     // output rows
+    C *dst = (PH == 1 || PH == 3) ? t : x;                    // output vector
+    const C *yin = (PH == 3) ? x : dst;                       // subtracted-from vector
+    const int n0 = blockIdx.y * 64;
+    const int li = lane & 15, lk = lane >> 4;
+    V4 accR[MT][4], accI[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            accR[mt][nt] = V4{0, 0, 0, 0};
+            accI[mt][nt] = V4{0, 0, 0, 0};
+        }
+    const C zero = C{0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        const bool kv = k < K;
+        C xv[4];
+        if (kv) {
+            const C *xrow = src + (int64_t)kin[k] * nrhs;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int col = n0 + nt * 16 + li;
+                xv[nt] = (col < nrhs) ? xrow[col] : zero;
+            }
+        } else {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) xv[nt] = zero;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int row = row0 + mt * 16 + li;
+            C av = zero;
+            if (kv && row < m) {
+                if (CONJT) {
+                    av = S[k + (int64_t)row * ld];
+                    av.y = -av.y;
+                } else {
+                    av = S[row + (int64_t)k * ld];
+                }
+            }
+            const R ar = av.x, ai = av.y, nai = -av.y;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                accR[mt][nt] = MF<R>::mma(ar, xv[nt].x, accR[mt][nt]);
+                accR[mt][nt] = MF<R>::mma(nai, xv[nt].y, accR[mt][nt]);
+                accI[mt][nt] = MF<R>::mma(ar, xv[nt].y, accI[mt][nt]);
+                accI[mt][nt] = MF<R>::mma(ai, xv[nt].x, accI[mt][nt]);
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+            const int row = row0 + mt * 16 + MF<R>::drow(lk, vv);
+            if (row >= m) continue;
+            const int64_t orow = (int64_t)oout[row] * nrhs;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int col = n0 + nt * 16 + li;
+                if (col >= nrhs) continue;
+                C a = C{accR[mt][nt][vv], accI[mt][nt][vv]};
+                if (SUB) {
+                    const C b = yin[orow + col];
+                    a = C{b.x - a.x, b.y - a.y};
+                }
+                dst[orow + col] = a;
+            }
+        }
+}
+
+// x_r = t_r for every node of a step (end of the upward phase 3).
+template <class C>
+__global__ void __launch_bounds__(256) k_hcopy(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                               const C *__restrict__ t, C *__restrict__ x, int nrhs) {
+    const int64_t v = blockIdx.x;
+    const int nr = (int)desc[4 * v];
+    const int32_t *ir = idx + desc[4 * v + 2];
+    for (int e = threadIdx.x; e < nr * nrhs; e += blockDim.x) {
+        const int64_t g = (int64_t)ir[e / nrhs] * nrhs + e % nrhs;
+        x[g] = t[g];
+    }
+}
+
+template <class R>
+static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, void *x, void *t,
+                        int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    if (ntiles == 0) return;
+    const dim3 g((unsigned)((ntiles + 3) / 4), (unsigned)((nrhs + 63) / 64));
+    const C *mat = (const C *)h.mat;
+#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1>), g, dim3(256), 0, st, h.desc, h.idx, tiles, ntiles, mat, (C *)x, (C *)t, nrhs)
+    switch (ph) {
+        case 0: HG(0); break;
+        case 1: HG(1); break;
+        case 2: HG(2); break;
+        case 3: HG(3); break;
+        case 4: HG(4); break;
+        default: HG(5); break;
+    }
+#undef HG
+}
+
+void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, hipStream_t st) {
+    if (h.n_nodes == 0) return;
+    const int p0 = up ? 0 : 3;
+    for (int k = 0; k < 3; ++k) {
+        const int ph = p0 + k;
+        // phases 2 and 5 produce the skeleton rows (ns), the others the redundant rows (nr)
+        const bool srows = (ph == 2 || ph == 5);
+        const int32_t *tiles = srows ? h.tiles_s : h.tiles_r;
+        const int64_t nt = srows ? h.n_tiles_s : h.n_tiles_r;
+        if (dbl) hgemm_phase<double>(ph, h, tiles, nt, x, t, nrhs, st);
+        else hgemm_phase<float>(ph, h, tiles, nt, x, t, nrhs, st);
+        check_launch("hif step (matrix cores)");
+    }
+    if (up) {
+        if (dbl) hipLaunchKernelGGL(k_hcopy<double2>, dim3((unsigned)h.n_nodes), dim3(256), 0, st, h.desc, h.idx, (const double2 *)t, (double2 *)x, nrhs);
+        else hipLaunchKernelGGL(k_hcopy<float2>, dim3((unsigned)h.n_nodes), dim3(256), 0, st, h.desc, h.idx, (const float2 *)t, (float2 *)x, nrhs);
+        check_launch("hif copy");
+    }
+}
+
+bool hif_step_fits_lds(const HifStepDev &h, bool dbl) {
+    const int elt = dbl ? 16 : 8;
+    const int64_t budget = hif_lds_budget();
+    return (int64_t)h.max_mat * elt + (int64_t)std::max(1, h.max_vec) * elt <= budget;
+}
+
+// Rows of a point-major block: out[i*nrhs + b] = x[idx[i]*nrhs + b] (with conversion), and back.
+template <class Ti, class To>
+__global__ void __launch_bounds__(256) k_rows_gather(const Ti *__restrict__ x, const int32_t *__restrict__ idx,
+                                                     int64_t rows, int nrhs, To *__restrict__ out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * nrhs; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = cvt<To, Ti>(x[(int64_t)idx[e / nrhs] * nrhs + e % nrhs]);
+}
+template <class Ti, class To>
+__global__ void __launch_bounds__(256) k_rows_scatter(const Ti *__restrict__ in, const int32_t *__restrict__ idx,
+                                                      int64_t rows, int nrhs, To *__restrict__ x) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * nrhs; e += (int64_t)gridDim.x * blockDim.x)
+        x[(int64_t)idx[e / nrhs] * nrhs + e % nrhs] = cvt<To, Ti>(in[e]);
+}
+
+void launch_rows_gather(const void *x, bool xd, const int32_t *idx, int64_t rows, int nrhs, void *out, bool od,
+                        hipStream_t st) {
+    const unsigned g = grid_for(rows * nrhs, 256);
+    if (xd && od) hipLaunchKernelGGL((k_rows_gather<double2, double2>), dim3(g), dim3(256), 0, st, (const double2 *)x, idx, rows, nrhs, (double2 *)out);
+    else if (xd) hipLaunchKernelGGL((k_rows_gather<double2, float2>), dim3(g), dim3(256), 0, st, (const double2 *)x, idx, rows, nrhs, (float2 *)out);
+    else if (od) hipLaunchKernelGGL((k_rows_gather<float2, double2>), dim3(g), dim3(256), 0, st, (const float2 *)x, idx, rows, nrhs, (double2 *)out);
+    else hipLaunchKernelGGL((k_rows_gather<float2, float2>), dim3(g), dim3(256), 0, st, (const float2 *)x, idx, rows, nrhs, (float2 *)out);
+    check_launch("rows gather");
+}
+
+void launch_rows_scatter(const void *in, bool id, const int32_t *idx, int64_t rows, int nrhs, void *x, bool xd,
+                         hipStream_t st) {
+    const unsigned g = grid_for(rows * nrhs, 256);
+    if (id && xd) hipLaunchKernelGGL((k_rows_scatter<double2, double2>), dim3(g), dim3(256), 0, st, (const double2 *)in, idx, rows, nrhs, (double2 *)x);
+    else if (id) hipLaunchKernelGGL((k_rows_scatter<double2, float2>), dim3(g), dim3(256), 0, st, (const double2 *)in, idx, rows, nrhs, (float2 *)x);
+    else if (xd) hipLaunchKernelGGL((k_rows_scatter<float2, double2>), dim3(g), dim3(256), 0, st, (const float2 *)in, idx, rows, nrhs, (double2 *)x);
+    else hipLaunchKernelGGL((k_rows_scatter<float2, float2>), dim3(g), dim3(256), 0, st, (const float2 *)in, idx, rows, nrhs, (float2 *)x);
+    check_launch("rows scatter");
+}
+
 // ------------------------------------------------------------------ top-level block (FP64)
 template <class T>
 __global__ void __launch_bounds__(256) k_root(const int32_t *__restrict__ idx,

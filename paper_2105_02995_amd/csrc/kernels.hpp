@@ -24,6 +24,10 @@ struct HifStepDev {
     int max_nr = 0, max_ns = 0;
     int max_vec = 0;   // max over nodes of 2*nr + ns (LDS entries per right-hand side)
     int max_mat = 0;   // max over nodes of 2*ns*nr + nr*nr (entries of the node's blocks)
+    // Tiles of 16 output rows for the matrix-core path: pairs (node, first row)
+    // over the redundant rows (nr) and over the skeleton rows (ns).
+    const int32_t *tiles_r = nullptr, *tiles_s = nullptr;
+    int64_t n_tiles_r = 0, n_tiles_s = 0;
     const int64_t *desc = nullptr;
     const int32_t *idx = nullptr;
     const void *mat = nullptr;
@@ -31,6 +35,15 @@ struct HifStepDev {
 
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st);
 void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st);
+// Large-node variant of launch_hif_step (gathered GEMMs on matrix cores); t is an
+// N x nrhs temporary of the same dtype.
+void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, hipStream_t st);
+// Whether a step's largest node fits the LDS-staged kernel.
+bool hif_step_fits_lds(const HifStepDev &h, bool dbl);
+void launch_rows_gather(const void *x, bool xd, const int32_t *idx, int64_t rows, int nrhs, void *out, bool od,
+                        hipStream_t st);
+void launch_rows_scatter(const void *in, bool id, const int32_t *idx, int64_t rows, int nrhs, void *x, bool xd,
+                         hipStream_t st);
 void launch_root(const int32_t *idx, const void *A0inv, int s0, bool dbl, void *x, int nrhs,
                  hipStream_t st);
 // internal[t*nrhs + b] = user[perm[t] + b*ld] (perm may be null), with conversion.
