@@ -30,7 +30,7 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE (x2) and WRITE_SIZE (x1) scaled by a 1 GiB copy kernel (summaries under
 # profiles/), valid only for the kernel source they were measured on.
 TRAFFIC = {
-    "k_stage_mfma<float, 2>": {
+    "k_stage_mfma<float, 2, 4>": {
         "bytes": (84319.99 * 2 + 99421.09) * 1024,
         "kernels_sha256": "7510381283a0dc19cea5914d9536e5b4d6ee4758d146b67435bc45bb01e9ca27",
     },
@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
     ap.add_argument("--no-serve", action="store_true", help="skip the small serving leg")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in kernel heuristics")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving mix (Poisson arrivals over many keys) instead of the solve bench")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -225,6 +226,12 @@ def main():
     X = torch.zeros_like(U)
     stream = torch.cuda.current_stream()
 
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        F.fio_autotune(plan, F.FIO_C64, B, 3, stream)
+        F.fio_autotune(plan, F.FIO_C128, B, 3, stream)
+        log("autotuned stage kernels for %d RHS in %.1f s" % (B, time.perf_counter() - t0))
+
     def step():
         F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0, maxit=args.refine,
                     stream=stream, want_info=False)
@@ -250,35 +257,43 @@ def main():
                             maxit=args.refine, stream=stream)
     x = X.cpu().numpy().T
 
-    # Dominant kernel: the butterfly stage kernel instance with the largest time per
-    # step.  Instances: complex64 with one or two 16-row tiles per wave (r_out <= 16
-    # or > 16) and complex128 (one tile); the complex64 adjoint chain runs twice per
-    # step, the complex128 forward chain once per refinement step.
+    # Dominant kernel: the butterfly stage kernel instance (template instantiation,
+    # chosen per stage by the autotuner) with the largest time per step.  The
+    # complex64 adjoint chain runs twice per step, the complex128 forward chain
+    # once per refinement step.
     S = stats["n_stages"]
-    infos = [F.fio_stage_info(plan, s) for s in range(S)]
-    r_out_kh = [infos[S - 1 - k]["r_in"] for k in range(S)]   # adjoint stage k outputs
+    VNAME = {0: None, 1: (1, 4), 2: (2, 4), 3: (1, 2), 4: (2, 2), 5: (1, 1), 6: (2, 1)}
+
+    def inst_name(dtype, v):
+        r = "float" if dtype == F.FIO_C64 else "double"
+        if v == 0:
+            return "k_stage<%s2>" % r
+        return "k_stage_mfma<%s, %d, %d>" % ((r,) + VNAME[v])
+
     t64, f64 = stage_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
     t128, f128 = stage_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
-    inst = {
-        "k_stage_mfma<float, 2> (complex64 stage, r_out > 16)":
-            ([k for k in range(S) if r_out_kh[k] > 16], t64, f64, 2, PEAK_TFLOPS["c64"]),
-        "k_stage_mfma<float, 1> (complex64 stage, r_out <= 16)":
-            ([k for k in range(S) if r_out_kh[k] <= 16], t64, f64, 2, PEAK_TFLOPS["c64"]),
-        "k_stage_mfma<double, 1> (complex128 stage)":
-            (list(range(S)), t128, f128, args.refine, PEAK_TFLOPS["c128"]),
-    }
-    best = max(inst, key=lambda k: inst[k][3] * inst[k][1][inst[k][0]].sum() if inst[k][0] else 0)
-    ks, tms_all, fl_all, _, pk = inst[best]
-    tms, fl = tms_all[ks], fl_all[ks]
+    inst = {}
+    for dtype, op, tms_all, fl_all, weight, pk in ((F.FIO_C64, F.FIO_OP_KH, t64, f64, 2, PEAK_TFLOPS["c64"]),
+                                                   (F.FIO_C128, F.FIO_OP_K, t128, f128, args.refine,
+                                                    PEAK_TFLOPS["c128"])):
+        for k in range(S):
+            name = inst_name(dtype, F.fio_tune_query(plan, op, k, dtype, B))
+            e = inst.setdefault(name, {"ks": [], "t": tms_all, "f": fl_all, "w": weight, "pk": pk})
+            e["ks"].append(k)
+    best = max(inst, key=lambda n: inst[n]["w"] * inst[n]["t"][inst[n]["ks"]].sum())
+    e = inst[best]
+    tms, fl, pk = e["t"][e["ks"]], e["f"][e["ks"]], e["pk"]
     achieved = fl.sum() / (tms.sum() * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": pk, "unit": "TFLOP/s",
             "frac": round(achieved / pk, 4), "traffic": traffic_for(best), "kernel": best,
-            "launches_per_chain": len(ks),
+            "launches_per_chain": len(e["ks"]),
             "avg_launch_ms": round(float(tms.mean()), 5),
             "flops_per_launch": float(fl.mean()),
-            "chain_ms": {"c64_KH": round(float(t64.sum()), 4), "c128_K": round(float(t128.sum()), 4)}}
+            "chain_ms": {"c64_KH": round(float(t64.sum()), 4), "c128_K": round(float(t128.sum()), 4)},
+            "instances": {n: {"launches": len(v["ks"]), "ms_per_chain": round(float(v["t"][v["ks"]].sum()), 4)}
+                          for n, v in inst.items()}}
     log("roofline: %s avg %.4f ms/launch over %d launches, %.2f TFLOP/s (%.1f%% of %.1f)" % (
-        best, tms.mean(), len(ks), achieved, 100 * achieved / pk, pk))
+        best, tms.mean(), len(e["ks"]), achieved, 100 * achieved / pk, pk))
 
     plain = None
     if not args.no_plain:

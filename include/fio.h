@@ -173,6 +173,23 @@ fio_status fio_stage_info(fio_plan plan, int stage, int64_t *nnz, int64_t *n_out
 fio_status fio_stage_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x,
                            void *y, int64_t nrhs, void *hip_stream);
 
+/* Autotuner: for this dtype and batch width, time every kernel variant of every
+ * butterfly stage (vector kernel; matrix-core tiles of 16 or 32 rows by 16, 32 or
+ * 64 columns) and, per skeletonization step, the LDS-staged kernel against the
+ * matrix-core GEMM path, with `reps` timed repetitions each (HIP events on
+ * hip_stream), and keep the fastest choices in the plan.  Later applies with the
+ * same dtype and nrhs use them (other widths use built-in heuristics).
+ * Synchronous; the plan's workspace is used as scratch, so no other call on the
+ * plan may run concurrently.  Errors: FIO_ERR_ARG, FIO_ERR_UNSUPPORTED (host-only). */
+fio_status fio_autotune(fio_plan plan, fio_dtype dtype, int64_t nrhs, int reps, void *hip_stream);
+
+/* Kernel variant used for stage `stage` of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) at
+ * this dtype and nrhs: 0 vector kernel, 1..6 matrix-core tilings (16*MT rows x
+ * 16*NT columns per wave: 1 MT1xNT4, 2 MT2xNT4, 3 MT1xNT2, 4 MT2xNT2, 5 MT1xNT1,
+ * 6 MT2xNT1). */
+fio_status fio_tune_query(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int64_t nrhs,
+                          int *variant);
+
 /* Save the factors to a file / load them onto a device (device = -1: host only). */
 fio_status fio_save(fio_plan plan, const char *path);
 fio_status fio_load(const char *path, int device, fio_plan *out);

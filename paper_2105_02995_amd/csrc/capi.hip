@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <map>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -98,6 +99,17 @@ struct fio_plan_s {
     int ws_nrhs = 0;
     DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal, HT, RI, RO;
     std::mutex mu;
+    // Autotuned choices keyed by (dtype, nrhs): stage kernel variant per stage of the
+    // forward and adjoint chains, and per skeletonization step 0 = LDS kernel,
+    // 1 = matrix-core GEMMs.
+    struct Tune {
+        std::vector<int> fwd, adj, hif;
+    };
+    std::map<std::pair<int, int>, Tune> tune;
+    const Tune *tuned(bool dbl, int nrhs) const {
+        auto it = tune.find({dbl ? 1 : 0, nrhs});
+        return it == tune.end() ? nullptr : &it->second;
+    }
 };
 
 namespace {
@@ -200,19 +212,30 @@ void ensure_ws(fio_plan p, int nrhs) {
 void run_chain(fio_plan p, const std::vector<Stage> &host, const std::vector<DStageStore<int>> &dev,
                bool dbl, const void *in, void *out, int nrhs, hipStream_t st) {
     const size_t S = dev.size();
+    const auto *t = p->tuned(dbl, nrhs);
+    const std::vector<int> *var = t ? ((&dev == &p->dfwd) ? &t->fwd : &t->adj) : nullptr;
     const void *cur = in;
     for (size_t s = 0; s < S; ++s) {
         void *dst = (s + 1 == S) ? out : ((s % 2 == 0) ? p->P.p : p->Q.p);
-        launch_stage(dev[s].view(dbl, host[s]), dbl, cur, dst, nrhs, st);
+        StageDev v = dev[s].view(dbl, host[s]);
+        if (var && s < var->size()) v.variant = (*var)[s];
+        launch_stage(v, dbl, cur, dst, nrhs, st);
         cur = dst;
     }
 }
 
 // One skeletonization step: LDS-staged kernel for small nodes, gathered GEMMs on
 // matrix cores when a node's blocks exceed LDS (large 2D cells and edges).
-void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
+void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int force = -1) {
     const HifStepDev h = p->dhif[k].view(dbl);
-    if (hif_step_fits_lds(h, dbl) || nrhs < 16) launch_hif_step(h, dbl, up, x, nrhs, st);
+    int choice = force;
+    if (choice < 0) {
+        const auto *t = p->tuned(dbl, nrhs);
+        if (t && k < t->hif.size()) choice = t->hif[k];
+    }
+    if (choice < 0) choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
+    if (choice == 1 && nrhs < 16) choice = 0;
+    if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
     else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, st);
 }
 
@@ -419,7 +442,99 @@ fio_status fio_stage_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const
         if (nrhs == 0) return;
         HIPC(hipSetDevice(p->device));
         const bool dbl = dt == FIO_C128;
-        launch_stage(ds[stage].view(dbl, hs[stage]), dbl, x, y, (int)nrhs, (hipStream_t)stream);
+        StageDev v = ds[stage].view(dbl, hs[stage]);
+        const auto *t = p->tuned(dbl, (int)nrhs);
+        if (t) v.variant = (op == FIO_OP_K) ? t->fwd[stage] : t->adj[stage];
+        launch_stage(v, dbl, x, y, (int)nrhs, (hipStream_t)stream);
+    });
+}
+
+fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *stream) {
+    return guard([&] {
+        if (!p) fail(FIO_ERR_ARG, "null plan");
+        if (p->device < 0) fail(FIO_ERR_UNSUPPORTED, "plan is host-only");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (nrhs < 1 || nrhs > (1 << 16)) fail(FIO_ERR_ARG, "nrhs out of range");
+        if (reps < 1) reps = 3;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        hipStream_t st = (hipStream_t)stream;
+        const bool dbl = dt == FIO_C128;
+        const int nr = (int)nrhs;
+        ensure_ws(p, nr);
+        launch_scale_zero(p->P.p, p->max_coef * nr, st);
+        launch_scale_zero(p->Q.p, p->max_coef * nr, st);
+        launch_scale_zero(p->V2.p, p->host.N * nr, st);
+        hipEvent_t e0, e1;
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        auto timeit = [&](auto &&fn) {
+            fn();  // warm-up (also sets kernel attributes outside the timed region)
+            HIPC(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) fn();
+            HIPC(hipEventRecord(e1, st));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            return ms;
+        };
+        fio_plan_s::Tune t;
+        for (int chain = 0; chain < 2; ++chain) {
+            const auto &hs = chain == 0 ? p->host.fwd : p->adj;
+            const auto &ds = chain == 0 ? p->dfwd : p->dadj;
+            std::vector<int> &out = chain == 0 ? t.fwd : t.adj;
+            for (size_t s = 0; s < ds.size(); ++s) {
+                int best = -1;
+                float best_ms = 1e30f;
+                for (int v = 0; v < STAGE_VARIANTS; ++v) {
+                    if (v > 0 && nr < 8) continue;  // matrix cores need a few columns
+                    StageDev sd = ds[s].view(dbl, hs[s]);
+                    sd.variant = v;
+                    const float ms = timeit([&] { launch_stage(sd, dbl, p->P.p, p->Q.p, nr, st); });
+                    if (ms < best_ms) { best_ms = ms; best = v; }
+                }
+                out.push_back(best);
+            }
+        }
+        for (size_t k = 0; k < p->dhif.size(); ++k) {
+            const HifStepDev h = p->dhif[k].view(dbl);
+            int best = 0;
+            if (nr >= 16) {
+                float ms0 = 1e30f;
+                if (hif_step_fits_lds(h, dbl)) {
+                    ms0 = timeit([&] {
+                        launch_hif_step(h, dbl, true, p->V2.p, nr, st);
+                        launch_hif_step(h, dbl, false, p->V2.p, nr, st);
+                    });
+                }
+                const float ms1 = timeit([&] {
+                    launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, st);
+                    launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, st);
+                });
+                best = ms1 < ms0 ? 1 : 0;
+            }
+            t.hif.push_back(best);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        p->tune[{dbl ? 1 : 0, nr}] = std::move(t);
+    });
+}
+
+fio_status fio_tune_query(fio_plan p, fio_op op, int stage, fio_dtype dt, int64_t nrhs, int *variant) {
+    return guard([&] {
+        if (!p || !variant) fail(FIO_ERR_ARG, "null argument");
+        const bool dbl = dt == FIO_C128;
+        const auto &hs = (op == FIO_OP_K) ? p->host.fwd : p->adj;
+        if (stage < 0 || stage >= (int)hs.size()) fail(FIO_ERR_ARG, "stage out of range");
+        const auto *t = p->tuned(dbl, (int)nrhs);
+        if (t) {
+            *variant = (op == FIO_OP_K) ? t->fwd[stage] : t->adj[stage];
+        } else {
+            StageDev sd;
+            sd.r_out = hs[stage].r_out;
+            *variant = stage_default_variant(sd, dbl, (int)nrhs);
+        }
     });
 }
 

@@ -121,7 +121,7 @@ template <> struct MF<double> {
     static __device__ __forceinline__ int drow(int lk, int v) { return lk + 4 * v; }
 };
 
-template <class R, int MT>
+template <class R, int MT, int NT>
 __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
                                                     const int32_t *__restrict__ idx,
                                                     const typename MF<R>::C *__restrict__ A,
@@ -135,14 +135,14 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
     if (wave >= n_out * mchunks) return;  // wave-uniform
     const int64_t o = wave / mchunks;
     const int mc = (int)(wave % mchunks);
-    const int n0 = blockIdx.y * 64;
+    const int n0 = blockIdx.y * (16 * NT);
     const int K = fan * r_in;
     const int li = lane & 15, lk = lane >> 4;
-    V4 accR[MT][4], accI[MT][4];
+    V4 accR[MT][NT], accI[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
+        for (int nt = 0; nt < NT; ++nt) {
             accR[mt][nt] = V4{0, 0, 0, 0};
             accI[mt][nt] = V4{0, 0, 0, 0};
         }
@@ -154,17 +154,17 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
     for (int k0 = 0; k0 < K; k0 += 4) {
         const int k = k0 + lk;
         const bool kv = k < K;
-        C xv[4];
+        C xv[NT];
         if (kv) {
             const C *xrow = x + ((int64_t)io[q] * r_in + e) * nrhs;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < NT; ++nt) {
                 const int col = n0 + nt * 16 + li;
                 xv[nt] = (col < nrhs) ? xrow[col] : zero;
             }
         } else {
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) xv[nt] = zero;
+            for (int nt = 0; nt < NT; ++nt) xv[nt] = zero;
         }
         C av[MT];
 #pragma unroll
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
         for (int mt = 0; mt < MT; ++mt) {
             const R ar = av[mt].x, ai = av[mt].y, nai = -av[mt].y;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < NT; ++nt) {
                 accR[mt][nt] = MF<R>::mma(ar, xv[nt].x, accR[mt][nt]);
                 accR[mt][nt] = MF<R>::mma(nai, xv[nt].y, accR[mt][nt]);
                 accI[mt][nt] = MF<R>::mma(ar, xv[nt].y, accI[mt][nt]);
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = (mc * MT + mt) * 16 + MF<R>::drow(lk, v);
@@ -199,26 +199,48 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
             }
 }
 
-template <class R, int MT>
+template <class R, int MT, int NT>
 static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
     const int mtiles = (s.r_out + 15) / 16;
     const int mchunks = (mtiles + MT - 1) / MT;
     const int64_t waves = s.n_out * mchunks;
-    const dim3 g((unsigned)((waves + 3) / 4), (unsigned)((nrhs + 63) / 64));
-    hipLaunchKernelGGL((k_stage_mfma<R, MT>), g, dim3(256), 0, st, s.n_out, s.r_out, s.r_in, s.fan,
+    const dim3 g((unsigned)((waves + 3) / 4), (unsigned)((nrhs + 16 * NT - 1) / (16 * NT)));
+    hipLaunchKernelGGL((k_stage_mfma<R, MT, NT>), g, dim3(256), 0, st, s.n_out, s.r_out, s.r_in, s.fan,
                        s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks);
 }
 
-// Right-hand-side counts from which the matrix-core path is used.
+// Right-hand-side counts from which the matrix-core path is used by default.
 static const int MFMA_MIN_RHS = 16;
 
+// Kernel variants of a stage launch (chosen by heuristics or by the autotuner):
+//   0 vector kernel; 1..6 matrix cores with MT row tiles and NT 16-column tiles
+//   (1: MT1 NT4, 2: MT2 NT4, 3: MT1 NT2, 4: MT2 NT2, 5: MT1 NT1, 6: MT2 NT1).
+int stage_default_variant(const StageDev &s, bool dbl, int nrhs) {
+    if (nrhs < MFMA_MIN_RHS) return 0;
+    const int mtiles = (s.r_out + 15) / 16;
+    if (dbl || mtiles < 2) return 1;
+    return 2;
+}
+
+template <class R>
+static void launch_variant(int v, const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+    switch (v) {
+        case 1: launch_mfma<R, 1, 4>(s, x, y, nrhs, st); break;
+        case 2: launch_mfma<R, 2, 4>(s, x, y, nrhs, st); break;
+        case 3: launch_mfma<R, 1, 2>(s, x, y, nrhs, st); break;
+        case 4: launch_mfma<R, 2, 2>(s, x, y, nrhs, st); break;
+        case 5: launch_mfma<R, 1, 1>(s, x, y, nrhs, st); break;
+        default: launch_mfma<R, 2, 1>(s, x, y, nrhs, st); break;
+    }
+}
+
+
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st) {
-    if (nrhs >= MFMA_MIN_RHS) {
-        const int mtiles = (s.r_out + 15) / 16;
-        if (dbl) launch_mfma<double, 1>(s, x, y, nrhs, st);
-        else if (mtiles >= 2) launch_mfma<float, 2>(s, x, y, nrhs, st);
-        else launch_mfma<float, 1>(s, x, y, nrhs, st);
+    const int v = (s.variant >= 0) ? s.variant : stage_default_variant(s, dbl, nrhs);
+    if (v > 0) {
+        if (dbl) launch_variant<double>(v, s, x, y, nrhs, st);
+        else launch_variant<float>(v, s, x, y, nrhs, st);
         check_launch("stage (matrix cores)");
         return;
     }

@@ -14,7 +14,12 @@ struct StageDev {
     int r_out = 0, r_in = 0, fan = 0;
     const int32_t *idx = nullptr;
     const void *A = nullptr;   // float2 (c64) or double2 (c128)
+    int variant = -1;          // kernel variant (see stage_default_variant); -1: heuristic
 };
+
+// Number of stage kernel variants and the heuristic choice for a launch.
+constexpr int STAGE_VARIANTS = 7;
+int stage_default_variant(const StageDev &s, bool dbl, int nrhs);
 
 // Node factor table of one skeletonization step: per node
 // {nr, ns, idx_off, mat_off}; idx holds idx_r then idx_s; mat holds T (ns x nr),

@@ -23,6 +23,7 @@ FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG = 0, 1, 2
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON}
 
 EXPORTS = ["fio_build", "fio_apply", "fio_stage_apply", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
+           "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error"]
 
@@ -77,6 +78,9 @@ def load_library():
     lib.fio_build.argtypes = [ctypes.POINTER(fio_problem), ctypes.POINTER(P)]
     lib.fio_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_stage_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
+    lib.fio_autotune.argtypes = [P, ctypes.c_int, I64, ctypes.c_int, VP]
+    lib.fio_tune_query.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64,
+                                   ctypes.POINTER(ctypes.c_int)]
     lib.fio_inverse_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_gd_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_solve.argtypes = [P, ctypes.POINTER(fio_solve_opts), ctypes.c_int, VP, VP, I64, I64,
@@ -174,6 +178,16 @@ def fio_apply(plan: Plan, op: int, dtype: int, x, y, nrhs: int, ld: int, stream=
 def fio_stage_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
     _check(load_library().fio_stage_apply(plan.handle, op, stage, dtype, _ptr(x), _ptr(y), nrhs,
                                           _stream(stream)))
+
+
+def fio_autotune(plan: Plan, dtype: int, nrhs: int, reps: int = 3, stream=None):
+    _check(load_library().fio_autotune(plan.handle, dtype, nrhs, reps, _stream(stream)))
+
+
+def fio_tune_query(plan: Plan, op: int, stage: int, dtype: int, nrhs: int) -> int:
+    v = ctypes.c_int()
+    _check(load_library().fio_tune_query(plan.handle, op, stage, dtype, nrhs, ctypes.byref(v)))
+    return v.value
 
 
 def fio_inverse_apply(plan: Plan, dtype: int, u, fhat, nrhs: int, ld: int, stream=None):

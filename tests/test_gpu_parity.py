@@ -209,3 +209,20 @@ def test_identity_phase_n65536_fft_pin():
     x = G.inverse(plan, F.FIO_C64, u)
     ref = np.fft.fft(((-1.0) ** np.arange(n))[:, None] * u, axis=0) / n
     assert O.rel_err(x, ref).max() < 1e-5
+
+
+def test_autotuned_variants_give_the_same_results():
+    """fio_autotune picks a kernel variant per stage; results stay within FP32
+    rounding of the built-in choice (complex64) and FP64 rounding (complex128)."""
+    plan = plan_for(4096)
+    x = gaussian_complex((4096, 64), 31)
+    before64 = G.apply(plan, F.FIO_OP_K, F.FIO_C64, x)
+    before128 = G.apply(plan, F.FIO_OP_KH, F.FIO_C128, x)
+    F.fio_autotune(plan, F.FIO_C64, 64, 2, G.stream())
+    F.fio_autotune(plan, F.FIO_C128, 64, 2, G.stream())
+    st = F.fio_plan_stats(plan)
+    vs = [F.fio_tune_query(plan, F.FIO_OP_K, s, F.FIO_C64, 64) for s in range(st["n_stages"])]
+    log("tuned complex64 variants: %s" % vs)
+    assert all(0 <= v <= 6 for v in vs)
+    assert O.rel_err(G.apply(plan, F.FIO_OP_K, F.FIO_C64, x), before64).max() < 1e-5
+    assert O.rel_err(G.apply(plan, F.FIO_OP_KH, F.FIO_C128, x), before128).max() < 1e-12
