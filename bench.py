@@ -141,33 +141,68 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
-def stage_timing(F, plan, torch, dtype, op, nrhs, reps=5):
-    """Average duration (ms) and algorithmic flops of every launch of the stage
-    kernel over one chain (op = K or KH), timed with events on the launch stream."""
+VNAME = {1: (1, 4), 2: (2, 4), 3: (1, 2), 4: (2, 2), 5: (1, 1), 6: (2, 1)}
+PAIR_NT = {1: 1, 2: 2, 3: 4}
+
+
+def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
+    """Every launch of one chain apply (op = K or KH) as the library schedules it
+    (single stages and fused stage pairs), timed with HIP events on the launch
+    stream.  Returns one dict per launch: kernel instance name, average ms,
+    algorithmic flops (8 per complex multiply-add of the block products) and
+    algorithmic HBM bytes (factor blocks and input indices read once, the
+    launch's input coefficients read once, its output written once)."""
     st = F.fio_plan_stats(plan)
     S = st["n_stages"]
-    infos = [F.fio_stage_info(plan, s) for s in range(S)]
-    order = list(range(S)) if op == F.FIO_OP_K else list(range(S - 1, -1, -1))
-    maxlen = max(max(i["n_out"] * i["r_out"], 1) for i in infos)
-    maxlen = max(maxlen, st["n"] ** st["d"], max(i["nnz"] // max(i["r_out"] * i["fan"], 1) for i in infos))
+    N = st["n"] ** st["d"]
+    fwd_info = [F.fio_stage_info(plan, s) for s in range(S)]
+    # stage k of the chain of op: its factor, input and output entry counts
+    def io(k):
+        f = k if op == F.FIO_OP_K else S - 1 - k
+        i = fwd_info[f]
+        rows_o = i["n_out"] * i["r_out"]
+        rows_i = N if f == 0 else fwd_info[f - 1]["n_out"] * fwd_info[f - 1]["r_out"]
+        nb_idx = i["n_out"] * i["fan"]
+        return (i, rows_i, rows_o, nb_idx) if op == F.FIO_OP_K else (i, rows_o, rows_i, nb_idx)
+    csize = 8 if dtype == F.FIO_C64 else 16
+    r = "float" if dtype == F.FIO_C64 else "double"
+    sched = F.fio_chain_schedule(plan, op, dtype, nrhs)
+    maxlen = max(max(max(io(k)[1], io(k)[2]) for k in range(S)), N)
     ctype = torch.complex64 if dtype == F.FIO_C64 else torch.complex128
     a = torch.randn(maxlen * nrhs, dtype=ctype, device="cuda")
     b = torch.zeros_like(a)
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(S)]
-    tot_ms = np.zeros(S)
-    for r in range(reps):
-        for k in range(S):
-            ev[k][0].record(stream)
-            F.fio_stage_apply(plan, op, k, dtype, a, b, nrhs, stream)
-            ev[k][1].record(stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in sched]
+    tot = np.zeros(len(sched))
+    for rep in range(reps):
+        for j, (first, count, v) in enumerate(sched):
+            ev[j][0].record(stream)
+            if count == 2:
+                F.fio_stage_pair_apply(plan, op, first, dtype, a, b, nrhs, stream)
+            else:
+                F.fio_stage_apply(plan, op, first, dtype, a, b, nrhs, stream)
+            ev[j][1].record(stream)
             a, b = b, a
         torch.cuda.synchronize()
-        if r > 0:
-            tot_ms += np.array([e0.elapsed_time(e1) for e0, e1 in ev])
-    tot_ms /= max(reps - 1, 1)
-    flops = np.array([8.0 * infos[order[k]]["nnz"] * nrhs for k in range(S)])
-    return tot_ms, flops
+        if rep > 0:
+            tot += np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    tot /= max(reps - 1, 1)
+    out = []
+    for j, (first, count, v) in enumerate(sched):
+        ks = list(range(first, first + count))
+        flops = sum(8.0 * io(k)[0]["nnz"] * nrhs for k in ks)
+        byts = sum(io(k)[0]["nnz"] * csize + 4 * io(k)[3] for k in ks)
+        byts += (io(ks[0])[1] + io(ks[-1])[2]) * nrhs * csize
+        if count == 2:
+            mt = 2 if max(io(k)[0]["r_out"] if op == F.FIO_OP_K else io(k)[0]["r_in"] for k in ks) > 16 else 1
+            name = "k_stage2_mfma<%s, %d, %d>" % (r, mt, PAIR_NT[v])
+        elif v == 0:
+            name = "k_stage<%s2>" % r
+        else:
+            name = "k_stage_mfma<%s, %d, %d>" % ((r,) + VNAME[v])
+        out.append({"name": name, "ms": float(tot[j]), "flops": flops, "bytes": float(byts),
+                    "stages": ks})
+    return out
 
 
 def cpu_baseline(wl, x_gpu, u):
@@ -257,43 +292,47 @@ def main():
                             maxit=args.refine, stream=stream)
     x = X.cpu().numpy().T
 
-    # Dominant kernel: the butterfly stage kernel instance (template instantiation,
-    # chosen per stage by the autotuner) with the largest time per step.  The
-    # complex64 adjoint chain runs twice per step, the complex128 forward chain
-    # once per refinement step.
-    S = stats["n_stages"]
-    VNAME = {0: None, 1: (1, 4), 2: (2, 4), 3: (1, 2), 4: (2, 2), 5: (1, 1), 6: (2, 1)}
-
-    def inst_name(dtype, v):
-        r = "float" if dtype == F.FIO_C64 else "double"
-        if v == 0:
-            return "k_stage<%s2>" % r
-        return "k_stage_mfma<%s, %d, %d>" % ((r,) + VNAME[v])
-
-    t64, f64 = stage_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
-    t128, f128 = stage_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
+    # Dominant kernel: the butterfly kernel instance (template instantiation, chosen
+    # per launch by the autotuner) with the largest time per step.  The complex64
+    # adjoint chain runs twice per step, the complex128 forward chain once per
+    # refinement step.  Its bound is the roof it would reach first: HBM if its
+    # algorithmic bytes take longer at 8 TB/s than its flops at the MFMA peak.
+    l64 = chain_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
+    l128 = chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
     inst = {}
-    for dtype, op, tms_all, fl_all, weight, pk in ((F.FIO_C64, F.FIO_OP_KH, t64, f64, 2, PEAK_TFLOPS["c64"]),
-                                                   (F.FIO_C128, F.FIO_OP_K, t128, f128, args.refine,
-                                                    PEAK_TFLOPS["c128"])):
-        for k in range(S):
-            name = inst_name(dtype, F.fio_tune_query(plan, op, k, dtype, B))
-            e = inst.setdefault(name, {"ks": [], "t": tms_all, "f": fl_all, "w": weight, "pk": pk})
-            e["ks"].append(k)
-    best = max(inst, key=lambda n: inst[n]["w"] * inst[n]["t"][inst[n]["ks"]].sum())
+    for launches, weight, pk in ((l64, 2, PEAK_TFLOPS["c64"]), (l128, args.refine, PEAK_TFLOPS["c128"])):
+        for ln in launches:
+            e = inst.setdefault(ln["name"], {"l": [], "w": weight, "pk": pk})
+            e["l"].append(ln)
+    best = max(inst, key=lambda n: inst[n]["w"] * sum(x["ms"] for x in inst[n]["l"]))
     e = inst[best]
-    tms, fl, pk = e["t"][e["ks"]], e["f"][e["ks"]], e["pk"]
-    achieved = fl.sum() / (tms.sum() * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": pk, "unit": "TFLOP/s",
-            "frac": round(achieved / pk, 4), "traffic": traffic_for(best), "kernel": best,
-            "launches_per_chain": len(e["ks"]),
+    tms = np.array([x["ms"] for x in e["l"]])
+    fl = np.array([x["flops"] for x in e["l"]])
+    by = np.array([x["bytes"] for x in e["l"]])
+    pk = e["pk"]
+    tf = fl.sum() / (tms.sum() * 1e-3) / 1e12
+    gbs = by.sum() / (tms.sum() * 1e-3) / 1e9
+    hbm_bound = by.sum() / (PEAK_HBM_GBS * 1e9) >= fl.sum() / (pk * 1e12)
+    roof = {"bound": "hbm" if hbm_bound else "mfma",
+            "achieved": round(gbs if hbm_bound else tf, 3),
+            "peak": PEAK_HBM_GBS if hbm_bound else pk,
+            "unit": "GB/s" if hbm_bound else "TFLOP/s",
+            "frac": round((gbs / PEAK_HBM_GBS) if hbm_bound else (tf / pk), 4),
+            "traffic": traffic_for(best), "kernel": best,
+            "launches_per_chain": len(e["l"]),
             "avg_launch_ms": round(float(tms.mean()), 5),
-            "flops_per_launch": float(fl.mean()),
-            "chain_ms": {"c64_KH": round(float(t64.sum()), 4), "c128_K": round(float(t128.sum()), 4)},
-            "instances": {n: {"launches": len(v["ks"]), "ms_per_chain": round(float(v["t"][v["ks"]].sum()), 4)}
+            "flops_per_launch": float(fl.mean()), "bytes_per_launch": float(by.mean()),
+            "intensity_flop_per_byte": round(float(fl.sum() / by.sum()), 2),
+            "other_roof": {"mfma_tflops": round(tf, 3), "mfma_frac": round(tf / pk, 4),
+                           "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)},
+            "chain_ms": {"c64_KH": round(sum(x["ms"] for x in l64), 4),
+                         "c128_K": round(sum(x["ms"] for x in l128), 4)},
+            "instances": {n: {"launches": len(v["l"]), "ms_per_chain": round(sum(x["ms"] for x in v["l"]), 4)}
                           for n, v in inst.items()}}
-    log("roofline: %s avg %.4f ms/launch over %d launches, %.2f TFLOP/s (%.1f%% of %.1f)" % (
-        best, tms.mean(), len(e["ks"]), achieved, 100 * achieved / pk, pk))
+    log("roofline: %s avg %.4f ms/launch over %d launches: %.2f TFLOP/s (%.1f%% of %.1f), "
+        "%.0f GB/s (%.1f%% of HBM), bound %s" % (best, tms.mean(), len(e["l"]), tf, 100 * tf / pk, pk,
+                                                 gbs, 100 * gbs / PEAK_HBM_GBS, roof["bound"]))
+    log("chains: c64 KH %.4f ms, c128 K %.4f ms" % (roof["chain_ms"]["c64_KH"], roof["chain_ms"]["c128_K"]))
 
     plain = None
     if not args.no_plain:

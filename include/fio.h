@@ -173,6 +173,28 @@ fio_status fio_stage_info(fio_plan plan, int stage, int64_t *nnz, int64_t *n_out
 fio_status fio_stage_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x,
                            void *y, int64_t nrhs, void *hip_stream);
 
+/* Apply the factors `stage` and `stage + 1` of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH)
+ * in one fused launch: consecutive butterfly factors of eq_BFF_fact couple closed
+ * groups of at most fan^2 blocks, so one workgroup computes a group's
+ * intermediate coefficients in LDS and applies the next factor to them.  x is
+ * stage `stage`'s input and y stage `stage + 1`'s output, in the layout of
+ * fio_stage_apply.  Uses the tuned column tiling for (dtype, nrhs) if there is
+ * one.  Asynchronous.  Errors: FIO_ERR_ARG (stage out of range),
+ * FIO_ERR_UNSUPPORTED (the pair's ranks exceed 32, the second factor's fan
+ * exceeds 2, or its blocks do not form closed groups of at most four). */
+fio_status fio_stage_pair_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x,
+                                void *y, int64_t nrhs, void *hip_stream);
+
+/* The launches that an apply of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) makes at this
+ * dtype and nrhs: launch j runs n_stages[j] (1 or 2) consecutive factors from
+ * first_stage[j] with kernel variant variant[j] (single factor: the codes of
+ * fio_tune_query; fused pair: 1, 2, 3 for 16, 32, 64 columns per wave).
+ * *n_launch is always set; with cap = 0 only the count is returned, otherwise
+ * the arrays (cap entries each, host memory) are filled.  Errors: FIO_ERR_ARG
+ * (cap too small, null pointers). */
+fio_status fio_chain_schedule(fio_plan plan, fio_op op, fio_dtype dtype, int64_t nrhs, int cap,
+                              int *n_launch, int *first_stage, int *n_stages, int *variant);
+
 /* Autotuner: for this dtype and batch width, time every kernel variant of every
  * butterfly stage (vector kernel; matrix-core tiles of 16 or 32 rows by 16, 32 or
  * 64 columns) and, per skeletonization step, the LDS-staged kernel against the

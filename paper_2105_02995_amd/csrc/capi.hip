@@ -3,6 +3,7 @@
 // host only enqueues work on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <map>
 #include <cstring>
@@ -73,6 +74,76 @@ struct DHifStore {
     HifStepDev base;
 };
 
+// Workgroup table of a fused stage pair (a, b), or nothing when the pair cannot
+// be fused.  Stage-a blocks are grouped with the stage-b blocks that read them and
+// with the stage-a blocks that share their inputs; in a butterfly these closed
+// groups hold at most fan^2 blocks.  Whole groups are packed into workgroups of at
+// most four stage-a and four stage-b blocks.
+struct DPair {
+    DBuf tab;
+    int64_t n_wg = 0;
+    bool ok = false;
+};
+
+bool build_pair_table(const Stage &a, const Stage &b, std::vector<int32_t> &tab) {
+    tab.clear();
+    if (b.n_in != a.n_out || b.r_in != a.r_out || !stage_pair_fusable(a.r_out, b.r_out, b.fan)) return false;
+    const int64_t nm = a.n_out;
+    std::vector<int64_t> par(nm);
+    for (int64_t i = 0; i < nm; ++i) par[i] = i;
+    auto find = [&](int64_t x) {
+        while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+        return x;
+    };
+    auto unite = [&](int64_t x, int64_t y) { x = find(x); y = find(y); if (x != y) par[x] = y; };
+    for (int64_t o = 0; o < b.n_out; ++o)
+        for (int q = 1; q < b.fan; ++q) unite(b.in_idx[o * b.fan], b.in_idx[o * b.fan + q]);
+    std::vector<int64_t> first_user(a.n_in, -1);
+    for (int64_t o = 0; o < nm; ++o)
+        for (int q = 0; q < a.fan; ++q) {
+            const int32_t i = a.in_idx[o * a.fan + q];
+            if (first_user[i] < 0) first_user[i] = o;
+            else unite(first_user[i], o);
+        }
+    // members of each group, in block order
+    std::map<int64_t, std::pair<std::vector<int32_t>, std::vector<int32_t>>> groups;
+    for (int64_t m = 0; m < nm; ++m) groups[find(m)].first.push_back((int32_t)m);
+    for (int64_t o = 0; o < b.n_out; ++o) groups[find(b.in_idx[o * b.fan])].second.push_back((int32_t)o);
+    std::vector<std::pair<std::vector<int32_t>, std::vector<int32_t>>> ordered;
+    for (auto &g : groups) {
+        if (g.second.first.size() > 4 || g.second.second.size() > 4) return false;
+        ordered.push_back(std::move(g.second));
+    }
+    std::sort(ordered.begin(), ordered.end(),
+              [](const auto &x, const auto &y) { return x.first[0] < y.first[0]; });
+    std::vector<int32_t> mids, outs;
+    auto flush = [&] {
+        if (mids.empty() && outs.empty()) return;
+        int32_t w[16];
+        for (int i = 0; i < 16; ++i) w[i] = -1;
+        for (size_t i = 0; i < mids.size(); ++i) w[i] = mids[i];
+        for (size_t i = 0; i < outs.size(); ++i) {
+            w[4 + i] = outs[i];
+            for (int q = 0; q < b.fan; ++q) {
+                const int32_t m = b.in_idx[(int64_t)outs[i] * b.fan + q];
+                const auto it = std::find(mids.begin(), mids.end(), m);
+                if (it == mids.end()) fail(FIO_ERR_DEVICE, "fused stage table: group is not closed");
+                w[8 + 2 * i + q] = (int32_t)(it - mids.begin());
+            }
+        }
+        tab.insert(tab.end(), w, w + 16);
+        mids.clear();
+        outs.clear();
+    };
+    for (auto &g : ordered) {
+        if (mids.size() + g.first.size() > 4 || outs.size() + g.second.size() > 4) flush();
+        mids.insert(mids.end(), g.first.begin(), g.first.end());
+        outs.insert(outs.end(), g.second.begin(), g.second.end());
+    }
+    flush();
+    return true;
+}
+
 void upload_complex(DBuf &b64, DBuf &b128, const std::vector<cd> &a) {
     std::vector<float> f(2 * a.size());
     for (size_t i = 0; i < a.size(); ++i) {
@@ -90,6 +161,7 @@ struct fio_plan_s {
     int device = -1;
     std::vector<Stage> adj;                   // host adjoint stages (Kd^*)
     std::vector<DStageStore<int>> dfwd, dadj;
+    std::vector<DPair> pfwd, padj;            // fused pairs (s, s+1) of each chain
     std::vector<DHifStore> dhif;
     DBuf root_idx, A0inv, perm, root_stage_idx;
     int s0 = 0;
@@ -100,10 +172,11 @@ struct fio_plan_s {
     DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal, HT, RI, RO;
     std::mutex mu;
     // Autotuned choices keyed by (dtype, nrhs): stage kernel variant per stage of the
-    // forward and adjoint chains, and per skeletonization step 0 = LDS kernel,
-    // 1 = matrix-core GEMMs.
+    // forward and adjoint chains, which consecutive stages run fused, and per
+    // skeletonization step 0 = LDS kernel, 1 = matrix-core GEMMs.
+    // fwd_pair/adj_pair[s] > 0: stages s and s+1 run fused with that variant.
     struct Tune {
-        std::vector<int> fwd, adj, hif;
+        std::vector<int> fwd, adj, hif, fwd_pair, adj_pair;
     };
     std::map<std::pair<int, int>, Tune> tune;
     const Tune *tuned(bool dbl, int nrhs) const {
@@ -118,6 +191,8 @@ void count_bytes(fio_plan p) {
     int64_t b = 0;
     for (auto &s : p->dfwd) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
     for (auto &s : p->dadj) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
+    for (auto &q : p->pfwd) b += q.tab.bytes;
+    for (auto &q : p->padj) b += q.tab.bytes;
     for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes + h.tr.bytes + h.ts.bytes;
     b += p->root_idx.bytes + p->A0inv.bytes + p->perm.bytes;
     p->device_bytes = b;
@@ -131,11 +206,24 @@ void upload_stages(const std::vector<Stage> &st, std::vector<DStageStore<int>> &
     }
 }
 
+void upload_pairs(const std::vector<Stage> &st, std::vector<DPair> &d) {
+    d.assign(st.empty() ? 0 : st.size() - 1, DPair());
+    std::vector<int32_t> tab;
+    for (size_t s = 0; s + 1 < st.size(); ++s) {
+        if (!build_pair_table(st[s], st[s + 1], tab)) continue;
+        d[s].tab.upload(tab.data(), tab.size() * sizeof(int32_t));
+        d[s].n_wg = (int64_t)tab.size() / 16;
+        d[s].ok = true;
+    }
+}
+
 void upload_plan(fio_plan p) {
     HIPC(hipSetDevice(p->device));
     const HostFactors &h = p->host;
     upload_stages(h.fwd, p->dfwd);
     upload_stages(p->adj, p->dadj);
+    upload_pairs(h.fwd, p->pfwd);
+    upload_pairs(p->adj, p->padj);
     p->max_coef = h.N;
     for (auto &s : h.fwd) {
         p->max_coef = std::max<int64_t>(p->max_coef, s.n_out * s.r_out);
@@ -208,18 +296,66 @@ void ensure_ws(fio_plan p, int nrhs) {
     p->ws_nrhs = nrhs;
 }
 
-// Run a stage chain: in (first stage's input) -> out (last stage's output).
-void run_chain(fio_plan p, const std::vector<Stage> &host, const std::vector<DStageStore<int>> &dev,
-               bool dbl, const void *in, void *out, int nrhs, hipStream_t st) {
-    const size_t S = dev.size();
+// Launch schedule of a chain: (first stage, number of stages, variant) per launch.
+// Tuned choices when the plan has them for (dtype, nrhs); otherwise consecutive
+// fusable stages run in pairs for batches of 16 or more columns.
+struct Launch {
+    int first, count, variant;
+};
+
+std::vector<Launch> chain_schedule(fio_plan p, bool fwd, bool dbl, int nrhs) {
+    const auto &ds = fwd ? p->dfwd : p->dadj;
+    const auto &pr = fwd ? p->pfwd : p->padj;
     const auto *t = p->tuned(dbl, nrhs);
-    const std::vector<int> *var = t ? ((&dev == &p->dfwd) ? &t->fwd : &t->adj) : nullptr;
+    const std::vector<int> *var = t ? (fwd ? &t->fwd : &t->adj) : nullptr;
+    const std::vector<int> *pv = t ? (fwd ? &t->fwd_pair : &t->adj_pair) : nullptr;
+    std::vector<Launch> out;
+    const int S = (int)ds.size();
+    for (int s = 0; s < S;) {
+        int fuse = 0;
+        if (s + 1 < S && pr[s].ok) {
+            if (pv && (size_t)s < pv->size()) fuse = (*pv)[s];
+            else if (!pv && nrhs >= 16) fuse = 2;
+        }
+        if (fuse > 0) {
+            out.push_back({s, 2, fuse});
+            s += 2;
+        } else {
+            out.push_back({s, 1, (var && (size_t)s < var->size()) ? (*var)[s] : -1});
+            s += 1;
+        }
+    }
+    return out;
+}
+
+StagePairDev pair_view(fio_plan p, bool fwd, bool dbl, int s) {
+    const auto &hs = fwd ? p->host.fwd : p->adj;
+    const auto &ds = fwd ? p->dfwd : p->dadj;
+    const auto &pr = fwd ? p->pfwd : p->padj;
+    StagePairDev v;
+    v.a = ds[s].view(dbl, hs[s]);
+    v.b = ds[s + 1].view(dbl, hs[s + 1]);
+    v.tab = (const int32_t *)pr[s].tab.p;
+    v.n_wg = pr[s].n_wg;
+    return v;
+}
+
+// Run a stage chain: in (first stage's input) -> out (last stage's output).
+void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nrhs, hipStream_t st) {
+    const auto &hs = fwd ? p->host.fwd : p->adj;
+    const auto &ds = fwd ? p->dfwd : p->dadj;
+    const std::vector<Launch> sched = chain_schedule(p, fwd, dbl, nrhs);
     const void *cur = in;
-    for (size_t s = 0; s < S; ++s) {
-        void *dst = (s + 1 == S) ? out : ((s % 2 == 0) ? p->P.p : p->Q.p);
-        StageDev v = dev[s].view(dbl, host[s]);
-        if (var && s < var->size()) v.variant = (*var)[s];
-        launch_stage(v, dbl, cur, dst, nrhs, st);
+    for (size_t j = 0; j < sched.size(); ++j) {
+        void *dst = (j + 1 == sched.size()) ? out : ((j % 2 == 0) ? p->P.p : p->Q.p);
+        const Launch &l = sched[j];
+        if (l.count == 2) {
+            launch_stage_pair(pair_view(p, fwd, dbl, l.first), dbl, l.variant, cur, dst, nrhs, st);
+        } else {
+            StageDev v = ds[l.first].view(dbl, hs[l.first]);
+            v.variant = l.variant;
+            launch_stage(v, dbl, cur, dst, nrhs, st);
+        }
         cur = dst;
     }
 }
@@ -424,8 +560,8 @@ fio_status fio_apply(fio_plan p, fio_op op, fio_dtype dt, const void *x, void *y
         const int32_t *perm = (const int32_t *)p->perm.p;
         const int64_t N = p->host.N;
         launch_gather(x, dbl, ld, perm, p->V1.p, dbl, N, nr, st);
-        if (op == FIO_OP_K) run_chain(p, p->host.fwd, p->dfwd, dbl, p->V1.p, p->V2.p, nr, st);
-        else run_chain(p, p->adj, p->dadj, dbl, p->V1.p, p->V2.p, nr, st);
+        if (op == FIO_OP_K) run_chain(p, true, dbl, p->V1.p, p->V2.p, nr, st);
+        else run_chain(p, false, dbl, p->V1.p, p->V2.p, nr, st);
         launch_scatter(p->V2.p, dbl, perm, y, dbl, ld, N, nr, st);
     });
 }
@@ -446,6 +582,54 @@ fio_status fio_stage_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const
         const auto *t = p->tuned(dbl, (int)nrhs);
         if (t) v.variant = (op == FIO_OP_K) ? t->fwd[stage] : t->adj[stage];
         launch_stage(v, dbl, x, y, (int)nrhs, (hipStream_t)stream);
+    });
+}
+
+fio_status fio_stage_pair_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const void *x, void *y,
+                                int64_t nrhs, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, p ? p->host.N : 0, x, y);
+        if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        const bool fwd = op == FIO_OP_K;
+        const auto &pr = fwd ? p->pfwd : p->padj;
+        if (stage < 0 || stage >= (int)pr.size()) fail(FIO_ERR_ARG, "stage out of range");
+        if (!pr[stage].ok) fail(FIO_ERR_UNSUPPORTED, "these two stages cannot run fused");
+        if (nrhs == 0) return;
+        HIPC(hipSetDevice(p->device));
+        const bool dbl = dt == FIO_C128;
+        int v = 2;
+        for (const Launch &l : chain_schedule(p, fwd, dbl, (int)nrhs))
+            if (l.first == stage && l.count == 2) v = l.variant;
+        launch_stage_pair(pair_view(p, fwd, dbl, stage), dbl, v, x, y, (int)nrhs, (hipStream_t)stream);
+    });
+}
+
+fio_status fio_chain_schedule(fio_plan p, fio_op op, fio_dtype dt, int64_t nrhs, int cap, int *n_launch,
+                              int *first_stage, int *n_stages, int *variant) {
+    return guard([&] {
+        if (!p || !n_launch) fail(FIO_ERR_ARG, "null argument");
+        if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (nrhs < 1) fail(FIO_ERR_ARG, "nrhs must be positive");
+        const bool dbl = dt == FIO_C128;
+        const std::vector<Launch> s = chain_schedule(p, op == FIO_OP_K, dbl, (int)nrhs);
+        *n_launch = (int)s.size();
+        if (cap < (int)s.size()) {
+            if (cap > 0) fail(FIO_ERR_ARG, "cap smaller than the number of launches");
+            return;
+        }
+        if (!first_stage || !n_stages || !variant) fail(FIO_ERR_ARG, "null output arrays");
+        for (size_t j = 0; j < s.size(); ++j) {
+            first_stage[j] = s[j].first;
+            n_stages[j] = s[j].count;
+            const int v = s[j].variant;
+            variant[j] = (s[j].count == 1 && v < 0)
+                             ? stage_default_variant((op == FIO_OP_K ? p->dfwd : p->dadj)[s[j].first].view(
+                                                         dbl, (op == FIO_OP_K ? p->host.fwd : p->adj)[s[j].first]),
+                                                     dbl, (int)nrhs)
+                             : v;
+        }
     });
 }
 
@@ -478,12 +662,19 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             HIPC(hipEventElapsedTime(&ms, e0, e1));
             return ms;
         };
+        const bool vb = p->host.prob.verbose != 0;
         fio_plan_s::Tune t;
         for (int chain = 0; chain < 2; ++chain) {
-            const auto &hs = chain == 0 ? p->host.fwd : p->adj;
-            const auto &ds = chain == 0 ? p->dfwd : p->dadj;
-            std::vector<int> &out = chain == 0 ? t.fwd : t.adj;
-            for (size_t s = 0; s < ds.size(); ++s) {
+            const bool fwd = chain == 0;
+            const auto &hs = fwd ? p->host.fwd : p->adj;
+            const auto &ds = fwd ? p->dfwd : p->dadj;
+            const auto &pr = fwd ? p->pfwd : p->padj;
+            std::vector<int> &out = fwd ? t.fwd : t.adj;
+            std::vector<int> &pout = fwd ? t.fwd_pair : t.adj_pair;
+            const int S = (int)ds.size();
+            std::vector<float> one_ms(S, 0.f), two_ms(S, 1e30f);
+            std::vector<int> two_v(S, 0);
+            for (int s = 0; s < S; ++s) {
                 int best = -1;
                 float best_ms = 1e30f;
                 for (int v = 0; v < STAGE_VARIANTS; ++v) {
@@ -494,6 +685,34 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                     if (ms < best_ms) { best_ms = ms; best = v; }
                 }
                 out.push_back(best);
+                one_ms[s] = best_ms;
+                if (s + 1 < S && pr[s].ok && nr >= 8) {
+                    const StagePairDev pv = pair_view(p, fwd, dbl, s);
+                    for (int v = 1; v <= stage_pair_variants(dbl); ++v) {
+                        const float ms = timeit([&] { launch_stage_pair(pv, dbl, v, p->P.p, p->Q.p, nr, st); });
+                        progress(vb, "tune %s %s pair (%d,%d) variant %d: %.4f ms", dbl ? "c128" : "c64",
+                                 fwd ? "K" : "KH", s, s + 1, v, ms / reps);
+                        if (ms < two_ms[s]) { two_ms[s] = ms; two_v[s] = v; }
+                    }
+                }
+                progress(vb, "tune %s %s stage %d (r_out %d, r_in %d, fan %d): variant %d %.4f ms",
+                         dbl ? "c128" : "c64", fwd ? "K" : "KH", s, hs[s].r_out, hs[s].r_in, hs[s].fan,
+                         best, best_ms / reps);
+            }
+            // fastest split of the chain into single and fused launches
+            std::vector<float> best(S + 1, 0.f);
+            std::vector<int> take(S, 1);
+            for (int s = S - 1; s >= 0; --s) {
+                best[s] = one_ms[s] + best[s + 1];
+                if (s + 1 < S && two_v[s] > 0 && two_ms[s] + best[s + 2] < best[s]) {
+                    best[s] = two_ms[s] + best[s + 2];
+                    take[s] = 2;
+                }
+            }
+            pout.assign(S, 0);
+            for (int s = 0; s < S;) {
+                if (take[s] == 2) { pout[s] = two_v[s]; s += 2; }
+                else s += 1;
             }
         }
         for (size_t k = 0; k < p->dhif.size(); ++k) {
@@ -571,7 +790,7 @@ fio_status fio_inverse_apply(fio_plan p, fio_dtype dt, const void *u, void *fh, 
         const int32_t *perm = (const int32_t *)p->perm.p;
         const int64_t N = p->host.N;
         launch_gather(u, dbl, ld, perm, p->V1.p, dbl, N, nr, st);
-        run_chain(p, p->adj, p->dadj, dbl, p->V1.p, p->V2.p, nr, st);
+        run_chain(p, false, dbl, p->V1.p, p->V2.p, nr, st);
         gd_inplace(p, dbl, p->V2.p, nr, st);
         launch_scatter(p->V2.p, dbl, perm, fh, dbl, ld, N, nr, st);
     });
@@ -609,7 +828,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
                 launch_convert(r128, true, p->V3.p, false, cnt, st);
                 src = p->V3.p;
             }
-            run_chain(p, p->adj, p->dadj, dbl, src, d_out, nr, st);
+            run_chain(p, false, dbl, src, d_out, nr, st);
             gd_inplace(p, dbl, d_out, nr, st);
         };
         if (opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_REFINE) {
@@ -618,7 +837,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             if (opts->mode == FIO_SOLVE_REFINE) {
                 for (int it = 0; it < opts->maxit; ++it) {
                     // r = u - Kd x with complex128 factors and FP64 accumulation
-                    run_chain(p, p->host.fwd, p->dfwd, true, p->X.p, p->V1.p, nr, st);
+                    run_chain(p, true, true, p->X.p, p->V1.p, nr, st);
                     launch_residual(p->U.p, p->V1.p, p->R.p, true, cnt, st);
                     gd_kh(p->R.p, p->V2.p);
                     launch_axpy_update(p->X.p, p->V2.p, dbl, cnt, st);
@@ -642,13 +861,12 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
         } else {
             // PCG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5).  Vectors are
             // complex128; the operator applies run in dtype.
-            auto apply_chain = [&](const std::vector<Stage> &h, const std::vector<DStageStore<int>> &d,
-                                   const void *in128, void *out128) {
+            auto apply_chain = [&](bool fwd, const void *in128, void *out128) {
                 if (dbl) {
-                    run_chain(p, h, d, true, in128, out128, nr, st);
+                    run_chain(p, fwd, true, in128, out128, nr, st);
                 } else {
                     launch_convert(in128, true, p->V3.p, false, cnt, st);
-                    run_chain(p, h, d, false, p->V3.p, p->W.p, nr, st);
+                    run_chain(p, fwd, false, p->V3.p, p->W.p, nr, st);
                     launch_convert(p->W.p, false, out128, true, cnt, st);
                 }
             };
@@ -668,7 +886,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             };
             double *rz = scal, *rzn = scal + 2 * nr, *pAp = scal + 4 * nr, *nrm = scal + 6 * nr;
             const int64_t cap = reduce_partial_cap(N, nr);
-            apply_chain(p->adj, p->dadj, p->U.p, p->R.p);  // r = b = Kd^* u (x0 = 0)
+            apply_chain(false, p->U.p, p->R.p);  // r = b = Kd^* u (x0 = 0)
             launch_colnorm2(p->R.p, N, nr, (double *)p->red.p, cap, nrm, st);
             std::vector<double> bnorm(nr);
             HIPC(hipMemcpyAsync(bnorm.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -679,8 +897,8 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             HIPC(hipStreamSynchronize(st));
             converged = false;
             for (int it = 0; it < std::max(1, opts->maxit); ++it) {
-                apply_chain(p->host.fwd, p->dfwd, p->Pv.p, p->V2.p);
-                apply_chain(p->adj, p->dadj, p->V2.p, p->V1.p);  // Ap (complex128 in V1)
+                apply_chain(true, p->Pv.p, p->V2.p);
+                apply_chain(false, p->V2.p, p->V1.p);  // Ap (complex128 in V1)
                 launch_coldot(p->Pv.p, p->V1.p, N, nr, (double *)p->red.p, cap, pAp, st);
                 launch_pcg_xr(p->X.p, p->R.p, p->Pv.p, p->V1.p, rz, pAp, N, nr, st);
                 ++iters;

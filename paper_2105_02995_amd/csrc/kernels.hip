@@ -121,6 +121,104 @@ template <> struct MF<double> {
     static __device__ __forceinline__ int drow(int lk, int v) { return lk + 4 * v; }
 };
 
+// Product of one block's factor A (r_out x K, column-major) with its gathered
+// input, for the wave's 16*MT rows (first row mrow0) and 16*NT columns.  Input
+// block q (q < fan <= 4) starts at xb + off[q] and its row e at + e*ld; this
+// lane reads columns 16*nt + (lane % 16) of it, zero at or beyond ncols.
+// The k loop is software-pipelined: the loads of k-step i + STAGE_PF - 1 are
+// issued before the MFMAs of k-step i, into STAGE_PF register buffers used in
+// turn, so every wave keeps loads in flight while its matrix cores run.
+#ifndef FIO_STAGE_PF
+#define FIO_STAGE_PF 2
+#endif
+constexpr int STAGE_PF = FIO_STAGE_PF;  // k-steps of loads in flight per wave, plus one
+
+template <class R, int MT, int NT> struct Frag {
+    typename MF<R>::C x[NT], a[MT];
+};
+
+// Loads are unconditional, from clamped (always valid) addresses, with the
+// out-of-range entries replaced by zero afterwards: loads under a branch would
+// make the compiler wait for every load in flight before the next MFMAs.
+template <class R, int MT, int NT, class P>
+__device__ __forceinline__ void frag_load(Frag<R, MT, NT> &f, int k, int &q, int &e, int K, int r_in,
+                                          const P *__restrict__ xb, const int64_t (&off)[4], int64_t ld,
+                                          const typename MF<R>::C *__restrict__ Ao, int r_out, int mrow0,
+                                          int ncols) {
+    using C = typename MF<R>::C;
+    const int li = threadIdx.x & 15;
+    const C zero = C{0, 0};
+    const bool kv = k < K;
+    // past the last k, (q, e) may run beyond the blocks: read block 0's row 0 instead
+    const int64_t o = !kv ? off[0] : q == 0 ? off[0] : q == 1 ? off[1] : q == 2 ? off[2] : off[3];
+    const P *xrow = xb + o + (kv ? (int64_t)e * ld : 0);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int col = nt * 16 + li;
+        const C v = xrow[min(col, ncols - 1)];
+        f.x[nt] = (kv && col < ncols) ? v : zero;
+    }
+    const int kc = min(k, K - 1);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int row = mrow0 + mt * 16 + li;
+        const C v = Ao[min(row, r_out - 1) + (int64_t)kc * r_out];
+        f.a[mt] = (kv && row < r_out) ? v : zero;
+    }
+    e += 4;
+    while (e >= r_in) { e -= r_in; ++q; }
+}
+
+template <class R, int MT, int NT>
+__device__ __forceinline__ void frag_mma(const Frag<R, MT, NT> &f, typename MF<R>::V4 (&accR)[MT][NT],
+                                         typename MF<R>::V4 (&accI)[MT][NT]) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const R ar = f.a[mt].x, ai = f.a[mt].y, nai = -f.a[mt].y;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            accR[mt][nt] = MF<R>::mma(ar, f.x[nt].x, accR[mt][nt]);
+            accI[mt][nt] = MF<R>::mma(ar, f.x[nt].y, accI[mt][nt]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            accR[mt][nt] = MF<R>::mma(nai, f.x[nt].y, accR[mt][nt]);
+            accI[mt][nt] = MF<R>::mma(ai, f.x[nt].x, accI[mt][nt]);
+        }
+    }
+}
+
+template <class R, int MT, int NT, class P>
+__device__ __forceinline__ void mfma_block(typename MF<R>::V4 (&accR)[MT][NT],
+                                           typename MF<R>::V4 (&accI)[MT][NT],
+                                           const typename MF<R>::C *__restrict__ Ao, int r_out,
+                                           int r_in, int K, int mrow0, int ncols, const P *__restrict__ xb,
+                                           const int64_t (&off)[4], int64_t ld) {
+    using V4 = typename MF<R>::V4;
+    const int lk = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            accR[mt][nt] = V4{0, 0, 0, 0};
+            accI[mt][nt] = V4{0, 0, 0, 0};
+        }
+    int q = 0, e = lk;  // (input block, entry) of this lane's next k
+    while (e >= r_in) { e -= r_in; ++q; }
+    Frag<R, MT, NT> f[STAGE_PF];
+#pragma unroll
+    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], 4 * j + lk, q, e, K, r_in, xb, off, ld, Ao, r_out, mrow0, ncols);
+    for (int k0 = 0; k0 < K; k0 += 4 * STAGE_PF) {
+#pragma unroll
+        for (int j = 0; j < STAGE_PF; ++j) {
+            if (k0 + 4 * j >= K) break;  // wave-uniform
+            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], k0 + 4 * (j + STAGE_PF - 1) + lk, q, e, K, r_in, xb, off,
+                      ld, Ao, r_out, mrow0, ncols);
+            frag_mma(f[j], accR, accI);
+        }
+    }
+}
+
 template <class R, int MT, int NT>
 __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
                                                     const int32_t *__restrict__ idx,
@@ -139,53 +237,12 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
     const int K = fan * r_in;
     const int li = lane & 15, lk = lane >> 4;
     V4 accR[MT][NT], accI[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            accR[mt][nt] = V4{0, 0, 0, 0};
-            accI[mt][nt] = V4{0, 0, 0, 0};
-        }
-    const C *Ao = A + o * (int64_t)r_out * K;
     const int32_t *io = idx + o * fan;
-    int q = 0, e = lk;  // (input block, entry) of this lane's k = k0 + lk
-    while (e >= r_in) { e -= r_in; ++q; }
-    const C zero = C{0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + lk;
-        const bool kv = k < K;
-        C xv[NT];
-        if (kv) {
-            const C *xrow = x + ((int64_t)io[q] * r_in + e) * nrhs;
+    int64_t off[4];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int col = n0 + nt * 16 + li;
-                xv[nt] = (col < nrhs) ? xrow[col] : zero;
-            }
-        } else {
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) xv[nt] = zero;
-        }
-        C av[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int row = (mc * MT + mt) * 16 + li;
-            av[mt] = (kv && row < r_out) ? Ao[row + (int64_t)k * r_out] : zero;
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const R ar = av[mt].x, ai = av[mt].y, nai = -av[mt].y;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                accR[mt][nt] = MF<R>::mma(ar, xv[nt].x, accR[mt][nt]);
-                accR[mt][nt] = MF<R>::mma(nai, xv[nt].y, accR[mt][nt]);
-                accI[mt][nt] = MF<R>::mma(ar, xv[nt].y, accI[mt][nt]);
-                accI[mt][nt] = MF<R>::mma(ai, xv[nt].x, accI[mt][nt]);
-            }
-        }
-        e += 4;
-        while (e >= r_in) { e -= r_in; ++q; }
-    }
+    for (int f = 0; f < 4; ++f) off[f] = (f < fan) ? (int64_t)io[f] * r_in * nrhs : 0;
+    mfma_block<R, MT, NT>(accR, accI, A + o * (int64_t)r_out * K, r_out, r_in, K, mc * MT * 16, nrhs - n0,
+                          x + n0, off, (int64_t)nrhs);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -196,6 +253,71 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
                 const int col = n0 + nt * 16 + li;
                 if (row < r_out && col < nrhs)
                     y[(o * r_out + row) * (int64_t)nrhs + col] = C{accR[mt][nt][v], accI[mt][nt][v]};
+            }
+}
+
+// Two consecutive stages a, b in one launch.  The blocks of two consecutive
+// butterfly stages fall into closed groups: the stage-b outputs of a group read
+// only stage-a outputs of that group.  A workgroup of four waves owns up to four
+// stage-a blocks and four stage-b blocks of whole groups (table tab, 16 entries
+// per workgroup: stage-a blocks, stage-b blocks, then for each stage-b block the
+// workgroup slot of each of its fan_b <= 2 inputs; -1 pads).  Wave w computes
+// stage-a block w of the workgroup into LDS, then stage-b block w from LDS, so
+// the intermediate coefficients never leave the compute unit.
+template <class R, int MT, int NT>
+__global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__ tab, int r_mid,
+                                                     int r_in_a, int fan_a,
+                                                     const int32_t *__restrict__ idx_a,
+                                                     const typename MF<R>::C *__restrict__ A_a,
+                                                     int r_out_b, int fan_b,
+                                                     const typename MF<R>::C *__restrict__ A_b,
+                                                     const typename MF<R>::C *__restrict__ x,
+                                                     typename MF<R>::C *__restrict__ y, int nrhs) {
+    using C = typename MF<R>::C;
+    using V4 = typename MF<R>::V4;
+    constexpr int ROWS = 16 * MT, COLS = 16 * NT;
+    __shared__ C mid[4][ROWS][COLS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int32_t *t = tab + (int64_t)blockIdx.x * 16;
+    const int n0 = blockIdx.y * COLS;
+    const int ncols = nrhs - n0;
+    V4 accR[MT][NT], accI[MT][NT];
+    const int ba = t[w];
+    if (ba >= 0) {  // wave-uniform
+        const int Ka = fan_a * r_in_a;
+        const int32_t *io = idx_a + (int64_t)ba * fan_a;
+        int64_t off[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) off[f] = (f < fan_a) ? (int64_t)io[f] * r_in_a * nrhs : 0;
+        mfma_block<R, MT, NT>(accR, accI, A_a + (int64_t)ba * r_mid * Ka, r_mid, r_in_a, Ka, 0, ncols, x + n0,
+                              off, (int64_t)nrhs);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    mid[w][mt * 16 + MF<R>::drow(lk, v)][nt * 16 + li] = C{accR[mt][nt][v], accI[mt][nt][v]};
+    }
+    __syncthreads();
+    const int bb = t[4 + w];
+    if (bb < 0) return;  // wave-uniform, after the only barrier
+    const int Kb = fan_b * r_mid;
+    int64_t off[4] = {(int64_t)t[8 + 2 * w] * ROWS * COLS,
+                      fan_b > 1 ? (int64_t)t[9 + 2 * w] * ROWS * COLS : 0, 0, 0};
+    mfma_block<R, MT, NT>(accR, accI, A_b + (int64_t)bb * r_out_b * Kb, r_out_b, r_mid, Kb, 0, ncols,
+                          &mid[0][0][0], off, (int64_t)COLS);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = mt * 16 + MF<R>::drow(lk, v);
+                const int col = n0 + nt * 16 + li;
+                if (row < r_out_b && col < nrhs)
+                    y[((int64_t)bb * r_out_b + row) * nrhs + col] = C{accR[mt][nt][v], accI[mt][nt][v]};
             }
 }
 
@@ -253,6 +375,39 @@ void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs,
         hipLaunchKernelGGL(k_stage<float2>, dim3(g), dim3(256), 0, st, s.n_out, s.r_out, s.r_in,
                            s.fan, s.idx, (const float2 *)s.A, (const float2 *)x, (float2 *)y, nrhs);
     check_launch("stage");
+}
+
+template <class R, int MT, int NT>
+static void launch_pair(const StagePairDev &p, const void *x, void *y, int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    const dim3 g((unsigned)p.n_wg, (unsigned)((nrhs + 16 * NT - 1) / (16 * NT)));
+    hipLaunchKernelGGL((k_stage2_mfma<R, MT, NT>), g, dim3(256), 0, st, p.tab, p.a.r_out, p.a.r_in,
+                       p.a.fan, p.a.idx, (const C *)p.a.A, p.b.r_out, p.b.fan, (const C *)p.b.A,
+                       (const C *)x, (C *)y, nrhs);
+}
+
+bool stage_pair_fusable(int r_mid, int r_out_b, int fan_b) {
+    return r_mid <= 32 && r_out_b <= 32 && fan_b <= 2;
+}
+
+int stage_pair_variants(bool dbl) { return dbl ? 2 : 3; }
+
+void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void *x, void *y, int nrhs,
+                       hipStream_t st) {
+    if (!stage_pair_fusable(p.a.r_out, p.b.r_out, p.b.fan) || p.b.r_in != p.a.r_out)
+        throw std::runtime_error("stage pair cannot be fused");
+    const bool m2 = std::max(p.a.r_out, p.b.r_out) > 16;
+    if (variant < 1 || variant > stage_pair_variants(dbl)) variant = 2;
+    if (dbl) {
+        // FP64 tiles of 16 x 64 columns would need 128 KiB of LDS: up to 32 columns.
+        if (variant == 1) { if (m2) launch_pair<double, 2, 1>(p, x, y, nrhs, st); else launch_pair<double, 1, 1>(p, x, y, nrhs, st); }
+        else { if (m2) launch_pair<double, 2, 2>(p, x, y, nrhs, st); else launch_pair<double, 1, 2>(p, x, y, nrhs, st); }
+    } else {
+        if (variant == 1) { if (m2) launch_pair<float, 2, 1>(p, x, y, nrhs, st); else launch_pair<float, 1, 1>(p, x, y, nrhs, st); }
+        else if (variant == 2) { if (m2) launch_pair<float, 2, 2>(p, x, y, nrhs, st); else launch_pair<float, 1, 2>(p, x, y, nrhs, st); }
+        else { if (m2) launch_pair<float, 2, 4>(p, x, y, nrhs, st); else launch_pair<float, 1, 4>(p, x, y, nrhs, st); }
+    }
+    check_launch("fused stage pair");
 }
 
 // ------------------------------------------------------------------ skeletonization steps

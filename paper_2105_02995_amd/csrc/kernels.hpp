@@ -21,6 +21,21 @@ struct StageDev {
 constexpr int STAGE_VARIANTS = 7;
 int stage_default_variant(const StageDev &s, bool dbl, int nrhs);
 
+// Two consecutive stages a, b fused in one launch (the intermediate stays in LDS).
+// tab: 16 int32 per workgroup (4 stage-a blocks, 4 stage-b blocks, 2 input slots
+// per stage-b block; -1 pads), built from the closed groups of the two stages.
+struct StagePairDev {
+    StageDev a, b;
+    const int32_t *tab = nullptr;
+    int64_t n_wg = 0;
+};
+// Whether two stages with these shapes can run fused (ranks <= 32, fan of b <= 2).
+bool stage_pair_fusable(int r_mid, int r_out_b, int fan_b);
+// Fused kernel variants: 1: 16 columns per wave, 2: 32, 3: 64 (complex64 only).
+int stage_pair_variants(bool dbl);
+void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void *x, void *y, int nrhs,
+                       hipStream_t st);
+
 // Node factor table of one skeletonization step: per node
 // {nr, ns, idx_off, mat_off}; idx holds idx_r then idx_s; mat holds T (ns x nr),
 // Linv (nr x nr), M (ns x nr), column-major, one after the other.

@@ -22,7 +22,7 @@ FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON = 0, 1, 2
 FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG = 0, 1, 2
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON}
 
-EXPORTS = ["fio_build", "fio_apply", "fio_stage_apply", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error"]
@@ -78,6 +78,9 @@ def load_library():
     lib.fio_build.argtypes = [ctypes.POINTER(fio_problem), ctypes.POINTER(P)]
     lib.fio_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_stage_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
+    lib.fio_stage_pair_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
+    IP = ctypes.POINTER(ctypes.c_int)
+    lib.fio_chain_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, I64, ctypes.c_int, IP, IP, IP, IP]
     lib.fio_autotune.argtypes = [P, ctypes.c_int, I64, ctypes.c_int, VP]
     lib.fio_tune_query.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64,
                                    ctypes.POINTER(ctypes.c_int)]
@@ -178,6 +181,21 @@ def fio_apply(plan: Plan, op: int, dtype: int, x, y, nrhs: int, ld: int, stream=
 def fio_stage_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
     _check(load_library().fio_stage_apply(plan.handle, op, stage, dtype, _ptr(x), _ptr(y), nrhs,
                                           _stream(stream)))
+
+
+def fio_stage_pair_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
+    _check(load_library().fio_stage_pair_apply(plan.handle, op, stage, dtype, _ptr(x), _ptr(y), nrhs,
+                                               _stream(stream)))
+
+
+def fio_chain_schedule(plan: Plan, op: int, dtype: int, nrhs: int) -> list:
+    """Launches of a chain apply: list of (first_stage, n_stages, variant)."""
+    lib = load_library()
+    n = ctypes.c_int()
+    _check(lib.fio_chain_schedule(plan.handle, op, dtype, nrhs, 0, ctypes.byref(n), None, None, None))
+    a, b, c = (ctypes.c_int * max(1, n.value))(), (ctypes.c_int * max(1, n.value))(), (ctypes.c_int * max(1, n.value))()
+    _check(lib.fio_chain_schedule(plan.handle, op, dtype, nrhs, n.value, ctypes.byref(n), a, b, c))
+    return [(a[j], b[j], c[j]) for j in range(n.value)]
 
 
 def fio_autotune(plan: Plan, dtype: int, nrhs: int, reps: int = 3, stream=None):
