@@ -87,7 +87,9 @@ struct DPair {
 
 bool build_pair_table(const Stage &a, const Stage &b, std::vector<int32_t> &tab) {
     tab.clear();
-    if (b.n_in != a.n_out || b.r_in != a.r_out || !stage_pair_fusable(a.r_out, b.r_out, b.fan)) return false;
+    if (b.n_in != a.n_out || b.r_in != a.r_out || !stage_pair_fusable(a.r_out, b.r_out, b.fan) || a.fan > 4 ||
+        a.r_in < 1)
+        return false;
     const int64_t nm = a.n_out;
     std::vector<int64_t> par(nm);
     for (int64_t i = 0; i < nm; ++i) par[i] = i;

@@ -124,10 +124,16 @@ template <> struct MF<double> {
 // Product of one block's factor A (r_out x K, column-major) with its gathered
 // input, for the wave's 16*MT rows (first row mrow0) and 16*NT columns.  Input
 // block q (q < fan <= 4) starts at xb + off[q] and its row e at + e*ld; this
-// lane reads columns 16*nt + (lane % 16) of it, zero at or beyond ncols.
+// lane reads columns 16*nt + (lane % 16) of it.
 // The k loop is software-pipelined: the loads of k-step i + STAGE_PF - 1 are
 // issued before the MFMAs of k-step i, into STAGE_PF register buffers used in
 // turn, so every wave keeps loads in flight while its matrix cores run.
+// Loads are unconditional, from clamped (always valid) addresses: loads under a
+// branch make the compiler wait for every load in flight before the next MFMAs.
+// Rows at or beyond r_out and columns at or beyond ncols then hold finite
+// duplicates of valid entries; they only feed output rows and columns that are
+// never stored (each output column depends on its own input column only).  Past
+// the last k the factor entry is replaced by zero, so those steps add nothing.
 #ifndef FIO_STAGE_PF
 #define FIO_STAGE_PF 2
 #endif
@@ -137,36 +143,49 @@ template <class R, int MT, int NT> struct Frag {
     typename MF<R>::C x[NT], a[MT];
 };
 
-// Loads are unconditional, from clamped (always valid) addresses, with the
-// out-of-range entries replaced by zero afterwards: loads under a branch would
-// make the compiler wait for every load in flight before the next MFMAs.
-template <class R, int MT, int NT, class P>
-__device__ __forceinline__ void frag_load(Frag<R, MT, NT> &f, int k, int &q, int &e, int K, int r_in,
-                                          const P *__restrict__ xb, const int64_t (&off)[4], int64_t ld,
-                                          const typename MF<R>::C *__restrict__ Ao, int r_out, int mrow0,
-                                          int ncols) {
-    using C = typename MF<R>::C;
-    const int li = threadIdx.x & 15;
-    const C zero = C{0, 0};
-    const bool kv = k < K;
-    // past the last k, (q, e) may run beyond the blocks: read block 0's row 0 instead
-    const int64_t o = !kv ? off[0] : q == 0 ? off[0] : q == 1 ? off[1] : q == 2 ? off[2] : off[3];
-    const P *xrow = xb + o + (kv ? (int64_t)e * ld : 0);
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int col = nt * 16 + li;
-        const C v = xrow[min(col, ncols - 1)];
-        f.x[nt] = (kv && col < ncols) ? v : zero;
+// Start offsets of the (up to four) input blocks of one output block.  Four named
+// members rather than an array: a lane-dependent index into an array would be
+// lowered to a private-memory load.
+struct Off4 {
+    int64_t o0, o1, o2, o3;
+    __device__ __forceinline__ int64_t operator()(int q) const {
+        return q <= 0 ? o0 : q == 1 ? o1 : q == 2 ? o2 : o3;
     }
-    const int kc = min(k, K - 1);
+};
+
+// Per-lane walk over k = lk, lk + 4, ...: input row pointer, factor column
+// pointer and (block, entry) of the lane's next k.
+template <class R, class P> struct KWalk {
+    const P *xp;
+    const typename MF<R>::C *ap;
+    int q, e, k;
+};
+
+template <class R, int MT, int NT, class P>
+__device__ __forceinline__ void frag_load(Frag<R, MT, NT> &f, KWalk<R, P> &w, int K, int r_in,
+                                          const P *__restrict__ xb, const Off4 &off, int64_t ld,
+                                          const typename MF<R>::C *__restrict__ Ao, int r_out,
+                                          const int (&colc)[NT], const int (&rowc)[MT]) {
+    using C = typename MF<R>::C;
+    const C zero = C{0, 0};
+    const bool kv = w.k < K;
+    const P *xrow = kv ? w.xp : xb + off.o0;
+    const C *acol = kv ? w.ap : Ao;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) f.x[nt] = xrow[colc[nt]];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        const int row = mrow0 + mt * 16 + li;
-        const C v = Ao[min(row, r_out - 1) + (int64_t)kc * r_out];
-        f.a[mt] = (kv && row < r_out) ? v : zero;
+        const C v = acol[rowc[mt]];
+        f.a[mt] = kv ? v : zero;
     }
-    e += 4;
-    while (e >= r_in) { e -= r_in; ++q; }
+    w.k += 4;
+    w.ap += 4 * (int64_t)r_out;
+    w.e += 4;
+    w.xp += 4 * ld;
+    if (w.e >= r_in) {
+        do { w.e -= r_in; ++w.q; } while (w.e >= r_in);
+        w.xp = xb + off(w.q) + (int64_t)w.e * ld;
+    }
 }
 
 template <class R, int MT, int NT>
@@ -193,9 +212,10 @@ __device__ __forceinline__ void mfma_block(typename MF<R>::V4 (&accR)[MT][NT],
                                            typename MF<R>::V4 (&accI)[MT][NT],
                                            const typename MF<R>::C *__restrict__ Ao, int r_out,
                                            int r_in, int K, int mrow0, int ncols, const P *__restrict__ xb,
-                                           const int64_t (&off)[4], int64_t ld) {
+                                           const Off4 &off, int64_t ld) {
     using V4 = typename MF<R>::V4;
-    const int lk = (threadIdx.x & 63) >> 4;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -203,17 +223,26 @@ __device__ __forceinline__ void mfma_block(typename MF<R>::V4 (&accR)[MT][NT],
             accR[mt][nt] = V4{0, 0, 0, 0};
             accI[mt][nt] = V4{0, 0, 0, 0};
         }
-    int q = 0, e = lk;  // (input block, entry) of this lane's next k
-    while (e >= r_in) { e -= r_in; ++q; }
+    int colc[NT], rowc[MT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) colc[nt] = min(nt * 16 + li, ncols - 1);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) rowc[mt] = min(mrow0 + mt * 16 + li, r_out - 1);
+    KWalk<R, P> w;
+    w.q = 0;
+    w.e = lk;
+    while (w.e >= r_in) { w.e -= r_in; ++w.q; }
+    w.k = lk;
+    w.ap = Ao + (int64_t)lk * r_out;
+    w.xp = xb + off(w.q) + (int64_t)w.e * ld;
     Frag<R, MT, NT> f[STAGE_PF];
 #pragma unroll
-    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], 4 * j + lk, q, e, K, r_in, xb, off, ld, Ao, r_out, mrow0, ncols);
+    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, Ao, r_out, colc, rowc);
     for (int k0 = 0; k0 < K; k0 += 4 * STAGE_PF) {
 #pragma unroll
         for (int j = 0; j < STAGE_PF; ++j) {
             if (k0 + 4 * j >= K) break;  // wave-uniform
-            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], k0 + 4 * (j + STAGE_PF - 1) + lk, q, e, K, r_in, xb, off,
-                      ld, Ao, r_out, mrow0, ncols);
+            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, Ao, r_out, colc, rowc);
             frag_mma(f[j], accR, accI);
         }
     }
@@ -238,9 +267,8 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
     const int li = lane & 15, lk = lane >> 4;
     V4 accR[MT][NT], accI[MT][NT];
     const int32_t *io = idx + o * fan;
-    int64_t off[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f) off[f] = (f < fan) ? (int64_t)io[f] * r_in * nrhs : 0;
+    const int64_t bs = (int64_t)r_in * nrhs;
+    const Off4 off{io[0] * bs, fan > 1 ? io[1] * bs : 0, fan > 2 ? io[2] * bs : 0, fan > 3 ? io[3] * bs : 0};
     mfma_block<R, MT, NT>(accR, accI, A + o * (int64_t)r_out * K, r_out, r_in, K, mc * MT * 16, nrhs - n0,
                           x + n0, off, (int64_t)nrhs);
 #pragma unroll
@@ -287,9 +315,9 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
     if (ba >= 0) {  // wave-uniform
         const int Ka = fan_a * r_in_a;
         const int32_t *io = idx_a + (int64_t)ba * fan_a;
-        int64_t off[4];
-#pragma unroll
-        for (int f = 0; f < 4; ++f) off[f] = (f < fan_a) ? (int64_t)io[f] * r_in_a * nrhs : 0;
+        const int64_t bs = (int64_t)r_in_a * nrhs;
+        const Off4 off{io[0] * bs, fan_a > 1 ? io[1] * bs : 0, fan_a > 2 ? io[2] * bs : 0,
+                       fan_a > 3 ? io[3] * bs : 0};
         mfma_block<R, MT, NT>(accR, accI, A_a + (int64_t)ba * r_mid * Ka, r_mid, r_in_a, Ka, 0, ncols, x + n0,
                               off, (int64_t)nrhs);
 #pragma unroll
@@ -304,8 +332,7 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
     const int bb = t[4 + w];
     if (bb < 0) return;  // wave-uniform, after the only barrier
     const int Kb = fan_b * r_mid;
-    int64_t off[4] = {(int64_t)t[8 + 2 * w] * ROWS * COLS,
-                      fan_b > 1 ? (int64_t)t[9 + 2 * w] * ROWS * COLS : 0, 0, 0};
+    const Off4 off{(int64_t)t[8 + 2 * w] * ROWS * COLS, fan_b > 1 ? (int64_t)t[9 + 2 * w] * ROWS * COLS : 0, 0, 0};
     mfma_block<R, MT, NT>(accR, accI, A_b + (int64_t)bb * r_out_b * Kb, r_out_b, r_mid, Kb, 0, ncols,
                           &mid[0][0][0], off, (int64_t)COLS);
 #pragma unroll
@@ -359,7 +386,9 @@ static void launch_variant(int v, const StageDev &s, const void *x, void *y, int
 
 
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st) {
-    const int v = (s.variant >= 0) ? s.variant : stage_default_variant(s, dbl, nrhs);
+    int v = (s.variant >= 0) ? s.variant : stage_default_variant(s, dbl, nrhs);
+    // the matrix-core kernels walk at most four input blocks of at least one row
+    if (s.fan > 4 || s.r_in < 1 || s.r_out < 1) v = 0;
     if (v > 0) {
         if (dbl) launch_variant<double>(v, s, x, y, nrhs, st);
         else launch_variant<float>(v, s, x, y, nrhs, st);
@@ -387,14 +416,15 @@ static void launch_pair(const StagePairDev &p, const void *x, void *y, int nrhs,
 }
 
 bool stage_pair_fusable(int r_mid, int r_out_b, int fan_b) {
-    return r_mid <= 32 && r_out_b <= 32 && fan_b <= 2;
+    return r_mid >= 1 && r_mid <= 32 && r_out_b >= 1 && r_out_b <= 32 && fan_b >= 1 && fan_b <= 2;
 }
 
 int stage_pair_variants(bool dbl) { return dbl ? 2 : 3; }
 
 void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void *x, void *y, int nrhs,
                        hipStream_t st) {
-    if (!stage_pair_fusable(p.a.r_out, p.b.r_out, p.b.fan) || p.b.r_in != p.a.r_out)
+    if (!stage_pair_fusable(p.a.r_out, p.b.r_out, p.b.fan) || p.b.r_in != p.a.r_out || p.a.fan > 4 ||
+        p.a.r_in < 1)
         throw std::runtime_error("stage pair cannot be fused");
     const bool m2 = std::max(p.a.r_out, p.b.r_out) > 16;
     if (variant < 1 || variant > stage_pair_variants(dbl)) variant = 2;
