@@ -248,21 +248,45 @@ __device__ __forceinline__ void mfma_block(typename MF<R>::V4 (&accR)[MT][NT],
     }
 }
 
+// XCD-aware workgroup order.  Workgroups of a launch are dispatched to the eight
+// XCDs in turn (id % 8), each XCD with its own L2.  Logical id xcd*per + id/8
+// gives every XCD a contiguous range of (block row, column chunk) pairs, chunk
+// fastest, so the chunks of one block row run on one XCD one after the other
+// and the factor blocks they share are read from HBM once.  The grid has
+// 8*per >= nb*nch workgroups; those past the end get b >= nb.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ void xcd_order(int64_t nb, int nch, int64_t &b, int &c) {
+    const int64_t per = (nb * nch + N_XCD - 1) / N_XCD;
+    const int64_t id = blockIdx.x;
+    const int64_t lid = (id % N_XCD) * per + id / N_XCD;
+    b = lid / nch;
+    c = (int)(lid % nch);
+}
+static unsigned xcd_grid(int64_t nb, int nch) {
+    const int64_t per = (nb * nch + N_XCD - 1) / N_XCD;
+    if (per * N_XCD * 256 >= (int64_t(1) << 32))
+        throw std::runtime_error("stage launch exceeds the grid limit (too many blocks x right-hand sides)");
+    return (unsigned)(per * N_XCD);
+}
+
 template <class R, int MT, int NT>
 __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
                                                     const int32_t *__restrict__ idx,
                                                     const typename MF<R>::C *__restrict__ A,
                                                     const typename MF<R>::C *__restrict__ x,
                                                     typename MF<R>::C *__restrict__ y, int nrhs,
-                                                    int mchunks) {
+                                                    int mchunks, int nchunks) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t wg;
+    int chunk;
+    xcd_order((n_out * mchunks + 3) / 4, nchunks, wg, chunk);
+    const int64_t wave = wg * 4 + (threadIdx.x >> 6);
     if (wave >= n_out * mchunks) return;  // wave-uniform
     const int64_t o = wave / mchunks;
     const int mc = (int)(wave % mchunks);
-    const int n0 = blockIdx.y * (16 * NT);
+    const int n0 = chunk * (16 * NT);
     const int K = fan * r_in;
     const int li = lane & 15, lk = lane >> 4;
     V4 accR[MT][NT], accI[MT][NT];
@@ -300,15 +324,20 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
                                                      int r_out_b, int fan_b,
                                                      const typename MF<R>::C *__restrict__ A_b,
                                                      const typename MF<R>::C *__restrict__ x,
-                                                     typename MF<R>::C *__restrict__ y, int nrhs) {
+                                                     typename MF<R>::C *__restrict__ y, int nrhs,
+                                                     int64_t n_wg, int nchunks) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
     constexpr int ROWS = 16 * MT, COLS = 16 * NT;
     __shared__ C mid[4][ROWS][COLS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int32_t *t = tab + (int64_t)blockIdx.x * 16;
-    const int n0 = blockIdx.y * COLS;
+    int64_t g;
+    int chunk;
+    xcd_order(n_wg, nchunks, g, chunk);
+    if (g >= n_wg) return;  // workgroup-uniform, before the barrier
+    const int32_t *t = tab + g * 16;
+    const int n0 = chunk * COLS;
     const int ncols = nrhs - n0;
     V4 accR[MT][NT], accI[MT][NT];
     const int ba = t[w];
@@ -354,9 +383,9 @@ static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hip
     const int mtiles = (s.r_out + 15) / 16;
     const int mchunks = (mtiles + MT - 1) / MT;
     const int64_t waves = s.n_out * mchunks;
-    const dim3 g((unsigned)((waves + 3) / 4), (unsigned)((nrhs + 16 * NT - 1) / (16 * NT)));
-    hipLaunchKernelGGL((k_stage_mfma<R, MT, NT>), g, dim3(256), 0, st, s.n_out, s.r_out, s.r_in, s.fan,
-                       s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks);
+    const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
+    hipLaunchKernelGGL((k_stage_mfma<R, MT, NT>), dim3(xcd_grid((waves + 3) / 4, nch)), dim3(256), 0, st, s.n_out,
+                       s.r_out, s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks, nch);
 }
 
 // Right-hand-side counts from which the matrix-core path is used by default.
@@ -409,10 +438,10 @@ void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs,
 template <class R, int MT, int NT>
 static void launch_pair(const StagePairDev &p, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
-    const dim3 g((unsigned)p.n_wg, (unsigned)((nrhs + 16 * NT - 1) / (16 * NT)));
-    hipLaunchKernelGGL((k_stage2_mfma<R, MT, NT>), g, dim3(256), 0, st, p.tab, p.a.r_out, p.a.r_in,
-                       p.a.fan, p.a.idx, (const C *)p.a.A, p.b.r_out, p.b.fan, (const C *)p.b.A,
-                       (const C *)x, (C *)y, nrhs);
+    const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
+    hipLaunchKernelGGL((k_stage2_mfma<R, MT, NT>), dim3(xcd_grid(p.n_wg, nch)), dim3(256), 0, st, p.tab,
+                       p.a.r_out, p.a.r_in, p.a.fan, p.a.idx, (const C *)p.a.A, p.b.r_out, p.b.fan,
+                       (const C *)p.b.A, (const C *)x, (C *)y, nrhs, p.n_wg, nch);
 }
 
 bool stage_pair_fusable(int r_mid, int r_out_b, int fan_b) {
