@@ -30,9 +30,9 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE (x2) and WRITE_SIZE (x1) scaled by a 1 GiB copy kernel (summaries under
 # profiles/), valid only for the kernel source they were measured on.
 TRAFFIC = {
-    "k_stage_mfma<float, 2, 4>": {
-        "bytes": (84319.99 * 2 + 99421.09) * 1024,
-        "kernels_sha256": "7510381283a0dc19cea5914d9536e5b4d6ee4758d146b67435bc45bb01e9ca27",
+    "k_stage2_mfma<float, 2, 2>": {
+        "bytes": (114177.61 * 2 + 100352.00) * 1024,
+        "kernels_sha256": "4374f1a4aaf09e0432b94da07c2529c35c6dd4e0bbd81eefa67e0387a2e711f0",
     },
 }
 
