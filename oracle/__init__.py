@@ -8,7 +8,7 @@ product library: the two share no code.
 It computes what the method approximates, from the paper's definitions:
 
 * the grids X and Omega and the discrete FIO matrix K (section 1, eq3/eq6);
-* the normalised DFT F (section 1);
+* the normalised DFT F and its inverse (section 1), dense or row by row;
 * u = K fhat by dense products (small N) or by direct summation in C (any N);
 * the exact solve fhat = K^{-1} u by dense LU, cross-checked by Cholesky on
   the normal equations K^*K fhat = K^* u (section 5, eq:pseudoinv);

@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "OracleProblem", "grid", "phase_mod1", "dense_K", "dft_matrix", "dft",
-    "idft", "apply_direct", "forward", "adjoint", "solve_dense",
+    "idft", "idft_rows", "apply_direct", "forward", "adjoint", "solve_dense",
     "solve_normal_cholesky", "cg_normal", "rel_err", "build_c", "PHASE_IDS",
 ]
 
@@ -117,6 +117,16 @@ def dft(f: np.ndarray, d: int, n: int) -> np.ndarray:
 def idft(fhat: np.ndarray, d: int, n: int) -> np.ndarray:
     """f = F^{-1} fhat = n^d F^* fhat (the normalised DFT has F^{-1} = n^d F^*)."""
     return float(n ** d) * (dft_matrix(d, n).conj().T @ fhat)
+
+
+def idft_rows(fhat: np.ndarray, d: int, n: int, rows) -> np.ndarray:
+    """Selected entries f[rows] of f = n^d F^* fhat, each summed by the definition
+    f_k = sum_j exp(2 pi i x_k . xi_j) fhat_j (section 1); for sizes where the dense
+    F does not fit.  The exponent is reduced exactly in integers, as in dft_matrix."""
+    k, xi = grid(d, n)
+    kk = k[np.asarray(rows)]
+    t = np.mod((kk[:, None, :] * xi[None, :, :]).sum(axis=-1), n) / n
+    return np.exp(2j * np.pi * t) @ fhat
 
 
 def build_c(force: bool = False) -> str:

@@ -58,6 +58,32 @@ def test_dft_matches_library_fft_2d():
     assert np.abs(O.idft(O.dft(f, 2, n), 2, n) - f).max() < 1e-12
 
 
+def test_idft_matches_library_ifft():
+    """f = n^d F^* fhat = (-1)^(sum k) N ifft(fhat) (section 1 grids), dense and by rows."""
+    n = 128
+    fh = gaussian_complex(n, 8)
+    ref = _shift(1, n) * n * np.fft.ifft(fh)
+    assert np.abs(O.idft(fh, 1, n) - ref).max() < 1e-12
+    m = 16
+    fh2 = gaussian_complex(m * m, 9)
+    ref2 = _shift(2, m) * (m * m) * np.fft.ifft2(fh2.reshape(m, m)).ravel()
+    assert np.abs(O.idft(fh2, 2, m) - ref2).max() < 1e-12
+
+
+@pytest.mark.parametrize("d,n", [(1, 65536), (2, 256)])
+def test_idft_rows_at_full_size(d, n):
+    """The row-by-row inverse DFT at N = 65536 against the library FFT closed form."""
+    N = n ** d
+    fh = gaussian_complex((N, 2), 10 + d)
+    rows = np.array([0, 1, 777, N // 2, N - 1])
+    got = O.idft_rows(fh, d, n, rows)
+    if d == 1:
+        full = _shift(1, n)[:, None] * N * np.fft.ifft(fh, axis=0)
+    else:
+        full = _shift(2, n)[:, None] * N * np.fft.ifft2(fh.reshape(n, n, 2), axes=(0, 1)).reshape(N, 2)
+    assert np.abs(got - full[rows]).max() / np.abs(full[rows]).max() < 1e-11
+
+
 def _row_closed_form_1d(n, c, fhat, i):
     """(K fhat)_i when row i has constant c: N F^*(e^{2 pi i c|xi|} fhat) via ifft."""
     xi = np.arange(n) - n // 2
