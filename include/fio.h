@@ -124,6 +124,7 @@ typedef struct {
                                PCG: stop when ||r|| <= tol ||Kd^* u||; 0 -> run maxit */
     int maxit;              /* iteration cap (REFINE steps or PCG iterations)          */
     int precondition;       /* PCG only: 1 -> Gd, 0 -> none (the paper's "Kd^* only") */
+    int spatial;            /* 1 -> return f = F^{-1} fhat (see fio_inverse_dft) instead of fhat */
 } fio_solve_opts;
 
 typedef struct {
@@ -157,6 +158,16 @@ typedef struct {
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);
+
+/* f = F^{-1} fhat = n^d F^* fhat (section 1: the normalised DFT F_jk =
+ * n^{-d} exp(-2 pi i x_k . xi_j) with x_k = k/n and xi_j = j - n/2 per coordinate),
+ * i.e. the spatial function whose Fourier coefficients a solve returns.  fhat and f
+ * are device buffers of complex128, column-major N x nrhs with leading dimension ld,
+ * natural lexicographic order of Omega (fhat) and X (f); f may alias fhat.  Computed
+ * in FP64 by radix-4/2 passes on the GPU; the plan supplies d, n and workspace.
+ * Asynchronous.  Errors: FIO_ERR_ARG, FIO_ERR_UNSUPPORTED (host-only plan). */
+fio_status fio_inverse_dft(fio_plan plan, const void *fhat, void *f, int64_t nrhs, int64_t ld,
+                           void *hip_stream);
 
 /* Per-stage layout of the butterfly apply (for measurement): for stage s of the
  * forward apply, nnz of its blocks and the number of output blocks. */

@@ -918,12 +918,25 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             }
         }
         launch_scatter(p->X.p, true, perm, out, true, ld, N, nr, st);
+        if (opts->spatial)
+            launch_inverse_dft(out, ld, out, p->host.d, p->host.n, nr, p->V1.p, p->V2.p, st);
         if (info) {
             HIPC(hipStreamSynchronize(st));
             info->iters = iters;
             info->rel_resid = worst;
         }
         if (!converged) fail(FIO_ERR_NOT_CONVERGED, "tolerance not reached within maxit");
+    });
+}
+
+fio_status fio_inverse_dft(fio_plan p, const void *fhat, void *f, int64_t nrhs, int64_t ld, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, ld, fhat, f);
+        if (nrhs == 0) return;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        ensure_ws(p, (int)nrhs);
+        launch_inverse_dft(fhat, ld, f, p->host.d, p->host.n, (int)nrhs, p->V1.p, p->V2.p, (hipStream_t)stream);
     });
 }
 

@@ -1104,4 +1104,114 @@ void launch_pcg_p(void *p, const void *z, const double *rzn, const double *rzo, 
     check_launch("pcg p update");
 }
 
+
+// ------------------------------------------------------------------ inverse DFT (layout out)
+// f = F^-1 fhat = n^d F* fhat (section 1: F_jk = n^-d exp(-2 pi i x_k . xi_j)).  With
+// x_k = k/n and xi_j = j - n/2 per coordinate,
+//   f_k = sum_j exp(2 pi i k (j - n/2) / n) fhat_j = sum_j' exp(2 pi i k j' / n) fhat_{j' + n/2},
+// j' = j - n/2 mod n: an unnormalised inverse DFT of fhat rotated by n/2 in every
+// coordinate.  k_dft_in gathers the user's column-major block into the point-major
+// layout with that rotation; Stockham passes (radix 4, and radix 2 once when log2 n is
+// odd) transform one coordinate at a time with the right-hand sides as the contiguous
+// batch, so every load and store is coalesced; the plain scatter writes the result.
+// Everything runs in FP64.
+__global__ void __launch_bounds__(256) k_dft_in(const double2 *__restrict__ user, int64_t ld,
+                                                double2 *__restrict__ x, int d, int n, int nrhs) {
+    const int64_t N = d == 1 ? (int64_t)n : (int64_t)n * n;
+    const int64_t total = N * nrhs;
+    const int h = n / 2;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const int64_t p = t / nrhs;
+        int64_t src;
+        if (d == 1) {
+            src = (p + h) % n;
+        } else {
+            const int64_t k1 = p / n, k2 = p % n;
+            src = ((k1 + h) % n) * n + (k2 + h) % n;
+        }
+        x[t] = user[src + b * ld];
+    }
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+// One Stockham pass of radix R (2 or 4) over a length-n transform (sign +).  Element
+// (o, p, i) of the data sits at (o*n + p)*inner + i; Ns is the length of the
+// sub-transforms already done.  One thread per (o, j, i), j < n/R.
+template <int R>
+__global__ void __launch_bounds__(256) k_dft_pass(const double2 *__restrict__ in, double2 *__restrict__ out,
+                                                  int64_t n, int64_t inner, int64_t outer, int64_t Ns) {
+    const int64_t m = n / R;
+    const int64_t total = outer * m * inner;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t % inner;
+        const int64_t t2 = t / inner;
+        const int64_t j = t2 % m, o = t2 / m;
+        const int64_t k = j % Ns;
+        const double2 *src = in + (o * n + j) * inner + i;
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[(int64_t)r * m * inner];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            double sn, cs;
+            sincospi(2.0 * (double)(r * k) / (double)(Ns * R), &sn, &cs);
+            v[r] = cmul(v[r], make_double2(cs, sn));
+        }
+        double2 w[R];
+        if (R == 2) {
+            w[0] = make_double2(v[0].x + v[1].x, v[0].y + v[1].y);
+            w[1] = make_double2(v[0].x - v[1].x, v[0].y - v[1].y);
+        } else {
+            const double2 a0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+            const double2 a1 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+            const double2 a2 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+            const double2 a3 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+            w[0] = make_double2(a0.x + a2.x, a0.y + a2.y);
+            w[2] = make_double2(a0.x - a2.x, a0.y - a2.y);
+            w[1] = make_double2(a1.x - a3.y, a1.y + a3.x);  // a1 + i a3
+            w[3] = make_double2(a1.x + a3.y, a1.y - a3.x);  // a1 - i a3
+        }
+        double2 *dst = out + (o * n + (j / Ns) * Ns * R + k) * inner + i;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[(int64_t)r * Ns * inner] = w[r];
+    }
+}
+
+void launch_inverse_dft(const void *fhat, int64_t ld, void *f, int d, int n, int nrhs, void *w0, void *w1,
+                        hipStream_t st) {
+    if (n < 2 || (n & (n - 1))) throw std::runtime_error("inverse DFT needs n a power of two");
+    const int64_t N = d == 1 ? (int64_t)n : (int64_t)n * n;
+    double2 *a = (double2 *)w0, *b = (double2 *)w1;
+    hipLaunchKernelGGL(k_dft_in, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, st, (const double2 *)fhat, ld, a,
+                       d, n, nrhs);
+    check_launch("inverse DFT gather");
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    for (int dim = d - 1; dim >= 0; --dim) {
+        // dim = d-1: the last (fastest) coordinate; dim 0 in 2D: the first
+        const int64_t inner = (d == 2 && dim == 0) ? (int64_t)n * nrhs : nrhs;
+        const int64_t outer = (d == 2 && dim == 1) ? n : 1;
+        int64_t Ns = 1;
+        for (int pass = 0; pass < lg / 2; ++pass) {
+            hipLaunchKernelGGL(k_dft_pass<4>, dim3(grid_for(N * nrhs / 4, 256)), dim3(256), 0, st, a, b, (int64_t)n,
+                               inner, outer, Ns);
+            std::swap(a, b);
+            Ns *= 4;
+        }
+        if (lg % 2) {
+            hipLaunchKernelGGL(k_dft_pass<2>, dim3(grid_for(N * nrhs / 2, 256)), dim3(256), 0, st, a, b, (int64_t)n,
+                               inner, outer, Ns);
+            std::swap(a, b);
+        }
+        check_launch("inverse DFT pass");
+    }
+    launch_scatter(a, true, nullptr, f, true, ld, N, nrhs, st);
+}
+
 }  // namespace fio

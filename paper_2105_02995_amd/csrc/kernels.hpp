@@ -92,6 +92,10 @@ void launch_pcg_p(void *p, const void *z, const double *rz_new, const double *rz
                   int nrhs, hipStream_t st);
 
 int64_t reduce_partial_cap(int64_t n, int nrhs);
+// f = n^d F* fhat (section 1) for user-layout complex128 blocks (column-major N x nrhs,
+// leading dimension ld; f may alias fhat).  w0, w1: N x nrhs complex128 temporaries.
+void launch_inverse_dft(const void *fhat, int64_t ld, void *f, int d, int n, int nrhs, void *w0, void *w1,
+                        hipStream_t st);
 // x = 0 (complex128), by a fill kernel (no memset node if the stream is captured).
 void launch_scale_zero(void *x, int64_t count, hipStream_t st);
 

@@ -22,7 +22,7 @@ FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON = 0, 1, 2
 FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG = 0, 1, 2
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON}
 
-EXPORTS = ["fio_build", "fio_apply", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error"]
@@ -46,7 +46,7 @@ class fio_problem(ctypes.Structure):
 
 class fio_solve_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
-                ("precondition", ctypes.c_int)]
+                ("precondition", ctypes.c_int), ("spatial", ctypes.c_int)]
 
 
 class fio_solve_info(ctypes.Structure):
@@ -86,6 +86,7 @@ def load_library():
                                    ctypes.POINTER(ctypes.c_int)]
     lib.fio_inverse_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_gd_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_inverse_dft.argtypes = [P, VP, VP, I64, I64, VP]
     lib.fio_solve.argtypes = [P, ctypes.POINTER(fio_solve_opts), ctypes.c_int, VP, VP, I64, I64,
                               ctypes.POINTER(fio_solve_info), VP]
     lib.fio_plan_stats.argtypes = [P, ctypes.POINTER(fio_plan_stats_t)]
@@ -213,14 +214,19 @@ def fio_inverse_apply(plan: Plan, dtype: int, u, fhat, nrhs: int, ld: int, strea
                                             _stream(stream)))
 
 
+def fio_inverse_dft(plan: Plan, fhat, f, nrhs: int, ld: int, stream=None):
+    _check(load_library().fio_inverse_dft(plan.handle, _ptr(fhat), _ptr(f), nrhs, ld, _stream(stream)))
+
+
 def fio_gd_apply(plan: Plan, dtype: int, x, y, nrhs: int, ld: int, stream=None):
     _check(load_library().fio_gd_apply(plan.handle, dtype, _ptr(x), _ptr(y), nrhs, ld,
                                        _stream(stream)))
 
 
 def fio_solve(plan: Plan, mode: int, dtype: int, u, out, nrhs: int, ld: int, tol: float = 0.0,
-              maxit: int = 0, precondition: int = 1, stream=None, want_info: bool = True):
-    o = fio_solve_opts(mode, tol, maxit, precondition)
+              maxit: int = 0, precondition: int = 1, stream=None, want_info: bool = True,
+              spatial: int = 0):
+    o = fio_solve_opts(mode, tol, maxit, precondition, spatial)
     info = fio_solve_info()
     _check(load_library().fio_solve(plan.handle, ctypes.byref(o), dtype, _ptr(u), _ptr(out), nrhs,
                                     ld, ctypes.byref(info) if want_info else None,

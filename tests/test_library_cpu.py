@@ -61,6 +61,12 @@ def test_host_only_plan_refuses_applies(tmp_path):
     assert e.value.status == 6
     with pytest.raises(F.FioError):
         F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C64, 1, 1, 1, 256)
+    for call in (lambda: F.fio_inverse_dft(plan, 1, 1, 1, 256),
+                 lambda: F.fio_stage_pair_apply(plan, F.FIO_OP_K, 0, F.FIO_C64, 1, 1, 16),
+                 lambda: F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C64, 1, 1, 1, 256, spatial=1)):
+        with pytest.raises(F.FioError) as e:
+            call()
+        assert e.value.status == 6
 
 
 def test_butterfly_accuracy_against_oracle(tmp_path):
