@@ -292,6 +292,19 @@ def main():
                             maxit=args.refine, stream=stream)
     x = X.cpu().numpy().T
 
+    # optional spatial output f = n^d F* fhat of the batch (not part of the step)
+    Fs = torch.empty_like(X)
+    F.fio_inverse_dft(plan, X, Fs, B, N, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        F.fio_inverse_dft(plan, X, Fs, B, N, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    spatial_ms = e0.elapsed_time(e1) / 5
+    del Fs
+    log("spatial output (inverse DFT of the batch): %.4f ms" % spatial_ms)
+
     # Dominant kernel: the butterfly kernel instance (template instantiation, chosen
     # per launch by the autotuner) with the largest time per step.  The complex64
     # adjoint chain runs twice per step, the complex128 forward chain once per
@@ -373,14 +386,17 @@ def main():
         "value": value, "unit": "RHS*N/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
-        "config": {"workload": "%s: 1D FIO Example 1 phase c(x)=(2+sin 2pi x)/16, N=%d, %d RHS, "
-                               "eps=%g, complex64 applies + %d FP64 refinement step(s)"
-                               % (wl.name, N, B, wl.eps, args.refine),
+        "config": {"workload": "%s: %s, N=%d, %d RHS, eps=%g, complex64 applies + %d FP64 "
+                               "refinement step(s)"
+                               % (wl.name, "1D FIO Example 1 phase c(x)=(2+sin 2pi x)/16" if wl.d == 1 else
+                                  "2D FIO Example 3 (generalized Radon phase), n=%d" % wl.n,
+                                  N, B, wl.eps, args.refine),
                    "N": N, "nrhs": B, "eps": wl.eps},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "per-step (64-RHS batch) latency, HIP events"},
         "serving": serving,
         "last_correction_rel": corr,
+        "spatial_output_ms": spatial_ms,
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain_fp64_single_rhs": plain,

@@ -208,10 +208,13 @@ fio_status fio_chain_schedule(fio_plan plan, fio_op op, fio_dtype dtype, int64_t
 
 /* Autotuner: for this dtype and batch width, time every kernel variant of every
  * butterfly stage (vector kernel; matrix-core tiles of 16 or 32 rows by 16, 32 or
- * 64 columns) and, per skeletonization step, the LDS-staged kernel against the
- * matrix-core GEMM path, with `reps` timed repetitions each (HIP events on
- * hip_stream), and keep the fastest choices in the plan.  Later applies with the
- * same dtype and nrhs use them (other widths use built-in heuristics).
+ * 64 columns), of every fusable pair of consecutive stages, per skeletonization
+ * step the LDS-staged kernel against the matrix-core GEMM path (16, 32 or 64
+ * columns per tile), and the tiling of the FP64 top-level block, with `reps` timed
+ * repetitions each (HIP events on hip_stream); keep the fastest choices in the
+ * plan, with the chain split into single and fused launches that minimises the
+ * summed time.  Later applies with the same dtype and nrhs use them (other widths
+ * use built-in heuristics).
  * Synchronous; the plan's workspace is used as scratch, so no other call on the
  * plan may run concurrently.  Errors: FIO_ERR_ARG, FIO_ERR_UNSUPPORTED (host-only). */
 fio_status fio_autotune(fio_plan plan, fio_dtype dtype, int64_t nrhs, int reps, void *hip_stream);

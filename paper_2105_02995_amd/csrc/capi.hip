@@ -61,12 +61,13 @@ template <class T> struct DStageStore {
 };
 
 struct DHifStore {
-    DBuf desc, idx, m64, m128, tr, ts;
+    DBuf desc, idx, m64, m128, h64, h128, tr, ts;
     HifStepDev view(bool dbl) const {
         HifStepDev v = base;
         v.desc = (const int64_t *)desc.p;
         v.idx = (const int32_t *)idx.p;
         v.mat = dbl ? m128.p : m64.p;
+        v.matH = dbl ? h128.p : h64.p;
         v.tiles_r = (const int32_t *)tr.p;
         v.tiles_s = (const int32_t *)ts.p;
         return v;
@@ -176,9 +177,11 @@ struct fio_plan_s {
     // Autotuned choices keyed by (dtype, nrhs): stage kernel variant per stage of the
     // forward and adjoint chains, which consecutive stages run fused, and per
     // skeletonization step 0 = LDS kernel, 1 = matrix-core GEMMs.
-    // fwd_pair/adj_pair[s] > 0: stages s and s+1 run fused with that variant.
+    // fwd_pair/adj_pair[s] > 0: stages s and s+1 run fused with that variant; hif[k]:
+    // the choice of hif_step.
     struct Tune {
         std::vector<int> fwd, adj, hif, fwd_pair, adj_pair;
+        int root = -1;  // stage variant of the FP64 top-level block
     };
     std::map<std::pair<int, int>, Tune> tune;
     const Tune *tuned(bool dbl, int nrhs) const {
@@ -195,7 +198,8 @@ void count_bytes(fio_plan p) {
     for (auto &s : p->dadj) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
     for (auto &q : p->pfwd) b += q.tab.bytes;
     for (auto &q : p->padj) b += q.tab.bytes;
-    for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes + h.tr.bytes + h.ts.bytes;
+    for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes + h.h64.bytes + h.h128.bytes +
+                                   h.tr.bytes + h.ts.bytes;
     b += p->root_idx.bytes + p->A0inv.bytes + p->perm.bytes;
     p->device_bytes = b;
 }
@@ -236,7 +240,7 @@ void upload_plan(fio_plan p) {
         const HifStep &st = h.hif.steps[k];
         std::vector<int64_t> desc;
         std::vector<int32_t> idx;
-        std::vector<cd> mat;
+        std::vector<cd> mat, matH;
         int mr = 0, ms = 0, mv = 0, mm = 0;
         std::vector<int32_t> tr, ts;
         for (size_t v = 0; v < st.nodes.size(); ++v) {
@@ -259,6 +263,10 @@ void upload_plan(fio_plan p) {
             mat.insert(mat.end(), nd.T.a.begin(), nd.T.a.end());
             mat.insert(mat.end(), nd.Linv.a.begin(), nd.Linv.a.end());
             mat.insert(mat.end(), nd.M.a.begin(), nd.M.a.end());
+            // conjugate transposes, same offsets: T^* and M^* are nr x ns, Linv^* nr x nr
+            for (const Mat *B : {&nd.T, &nd.Linv, &nd.M})
+                for (int j = 0; j < B->m; ++j)
+                    for (int i = 0; i < B->n; ++i) matH.push_back(std::conj((*B)(j, i)));
         }
         DHifStore &d = p->dhif[k];
         d.base.n_nodes = (int64_t)st.nodes.size();
@@ -273,6 +281,7 @@ void upload_plan(fio_plan p) {
         d.desc.upload(desc.data(), desc.size() * sizeof(int64_t));
         d.idx.upload(idx.data(), idx.size() * sizeof(int32_t));
         upload_complex(d.m64, d.m128, mat);
+        upload_complex(d.h64, d.h128, matH);
     }
     p->s0 = (int)h.hif.root_idx.size();
     p->root_idx.upload(h.hif.root_idx.data(), h.hif.root_idx.size() * sizeof(int32_t));
@@ -362,8 +371,9 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
     }
 }
 
-// One skeletonization step: LDS-staged kernel for small nodes, gathered GEMMs on
-// matrix cores when a node's blocks exceed LDS (large 2D cells and edges).
+// One skeletonization step: LDS-staged kernel for small nodes (choice 0), gathered
+// GEMMs on matrix cores when a node's blocks exceed LDS (large 2D cells and edges),
+// in tiles of 64, 32 or 16 right-hand sides (choices 1, 2, 3).
 void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int force = -1) {
     const HifStepDev h = p->dhif[k].view(dbl);
     int choice = force;
@@ -372,9 +382,9 @@ void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStr
         if (t && k < t->hif.size()) choice = t->hif[k];
     }
     if (choice < 0) choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
-    if (choice == 1 && nrhs < 16) choice = 0;
+    if (choice >= 1 && nrhs < 16) choice = 0;
     if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
-    else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, st);
+    else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, 64 >> (choice - 1), st);
 }
 
 // A_0^{-1} on the remaining DOFs, always in FP64: as a one-block FP64 stage on
@@ -390,6 +400,8 @@ void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
     s.n_out = 1; s.n_in = 1; s.r_out = p->s0; s.r_in = p->s0; s.fan = 1;
     s.idx = (const int32_t *)p->root_stage_idx.p;
     s.A = p->A0inv.p;
+    const auto *t = p->tuned(dbl, nrhs);
+    if (t) s.variant = t->root;
     launch_stage(s, true, p->RI.p, p->RO.p, nrhs, st);
     launch_rows_scatter(p->RO.p, true, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
 }
@@ -721,20 +733,38 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             const HifStepDev h = p->dhif[k].view(dbl);
             int best = 0;
             if (nr >= 16) {
-                float ms0 = 1e30f;
+                float best_ms = 1e30f;
                 if (hif_step_fits_lds(h, dbl)) {
-                    ms0 = timeit([&] {
+                    best_ms = timeit([&] {
                         launch_hif_step(h, dbl, true, p->V2.p, nr, st);
                         launch_hif_step(h, dbl, false, p->V2.p, nr, st);
                     });
                 }
-                const float ms1 = timeit([&] {
-                    launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, st);
-                    launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, st);
-                });
-                best = ms1 < ms0 ? 1 : 0;
+                for (int c = 1; c <= 3; ++c) {
+                    const float ms = timeit([&] {
+                        launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, 64 >> (c - 1), st);
+                        launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, 64 >> (c - 1), st);
+                    });
+                    if (ms < best_ms) { best_ms = ms; best = c; }
+                }
+                progress(vb, "tune %s skeletonization step %zu (%lld nodes): choice %d %.4f ms",
+                         dbl ? "c128" : "c64", k, (long long)h.n_nodes, best, best_ms / reps);
             }
             t.hif.push_back(best);
+        }
+        if (nr >= 16 && p->s0 >= 64) {
+            StageDev sr;
+            sr.n_out = 1; sr.n_in = 1; sr.r_out = p->s0; sr.r_in = p->s0; sr.fan = 1;
+            sr.idx = (const int32_t *)p->root_stage_idx.p;
+            sr.A = p->A0inv.p;
+            float best_ms = 1e30f;
+            launch_scale_zero(p->RI.p, (int64_t)p->s0 * nr, st);
+            for (int v = 1; v < STAGE_VARIANTS; ++v) {
+                sr.variant = v;
+                const float ms = timeit([&] { launch_stage(sr, true, p->RI.p, p->RO.p, nr, st); });
+                if (ms < best_ms) { best_ms = ms; t.root = v; }
+            }
+            progress(vb, "tune top-level block (%d DOFs): variant %d %.4f ms", p->s0, t.root, best_ms / reps);
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

@@ -188,41 +188,49 @@ __device__ __forceinline__ void frag_load(Frag<R, MT, NT> &f, KWalk<R, P> &w, in
     }
 }
 
-template <class R, int MT, int NT>
-__device__ __forceinline__ void frag_mma(const Frag<R, MT, NT> &f, typename MF<R>::V4 (&accR)[MT][NT],
-                                         typename MF<R>::V4 (&accI)[MT][NT]) {
+// Accumulators of a wave's 16*MT x 16*NT complex tile: Yr = Ar Xr - Ai Xi and
+// Yi = Ar Xi + Ai Xr as four real products per k-step.  (The three-product form
+// measured slower: its third accumulator set costs occupancy.)
+template <class R, int MT, int NT> struct Acc {
+    using V4 = typename MF<R>::V4;
+    using C = typename MF<R>::C;
+    V4 re[MT][NT], im[MT][NT];
+    __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const R ar = f.a[mt].x, ai = f.a[mt].y, nai = -f.a[mt].y;
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            accR[mt][nt] = MF<R>::mma(ar, f.x[nt].x, accR[mt][nt]);
-            accI[mt][nt] = MF<R>::mma(ar, f.x[nt].y, accI[mt][nt]);
-        }
+            for (int nt = 0; nt < NT; ++nt) {
+                re[mt][nt] = V4{0, 0, 0, 0};
+                im[mt][nt] = V4{0, 0, 0, 0};
+            }
+    }
+    __device__ __forceinline__ void mma(const Frag<R, MT, NT> &f) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            accR[mt][nt] = MF<R>::mma(nai, f.x[nt].y, accR[mt][nt]);
-            accI[mt][nt] = MF<R>::mma(ai, f.x[nt].x, accI[mt][nt]);
+        for (int mt = 0; mt < MT; ++mt) {
+            const R ar = f.a[mt].x, ai = f.a[mt].y, nai = -f.a[mt].y;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                re[mt][nt] = MF<R>::mma(ar, f.x[nt].x, re[mt][nt]);
+                im[mt][nt] = MF<R>::mma(ar, f.x[nt].y, im[mt][nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                re[mt][nt] = MF<R>::mma(nai, f.x[nt].y, re[mt][nt]);
+                im[mt][nt] = MF<R>::mma(ai, f.x[nt].x, im[mt][nt]);
+            }
         }
     }
-}
+    // entry v of this lane's part of tile (mt, nt)
+    __device__ __forceinline__ C get(int mt, int nt, int v) const { return C{re[mt][nt][v], im[mt][nt][v]}; }
+};
 
 template <class R, int MT, int NT, class P>
-__device__ __forceinline__ void mfma_block(typename MF<R>::V4 (&accR)[MT][NT],
-                                           typename MF<R>::V4 (&accI)[MT][NT],
-                                           const typename MF<R>::C *__restrict__ Ao, int r_out,
+__device__ __forceinline__ void mfma_block(Acc<R, MT, NT> &acc, const typename MF<R>::C *__restrict__ Ao, int r_out,
                                            int r_in, int K, int mrow0, int ncols, const P *__restrict__ xb,
                                            const Off4 &off, int64_t ld) {
-    using V4 = typename MF<R>::V4;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            accR[mt][nt] = V4{0, 0, 0, 0};
-            accI[mt][nt] = V4{0, 0, 0, 0};
-        }
+    acc.zero();
     int colc[NT], rowc[MT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) colc[nt] = min(nt * 16 + li, ncols - 1);
@@ -243,7 +251,7 @@ __device__ __forceinline__ void mfma_block(typename MF<R>::V4 (&accR)[MT][NT],
         for (int j = 0; j < STAGE_PF; ++j) {
             if (k0 + 4 * j >= K) break;  // wave-uniform
             frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, Ao, r_out, colc, rowc);
-            frag_mma(f[j], accR, accI);
+            acc.mma(f[j]);
         }
     }
 }
@@ -289,11 +297,11 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
     const int n0 = chunk * (16 * NT);
     const int K = fan * r_in;
     const int li = lane & 15, lk = lane >> 4;
-    V4 accR[MT][NT], accI[MT][NT];
+    Acc<R, MT, NT> acc;
     const int32_t *io = idx + o * fan;
     const int64_t bs = (int64_t)r_in * nrhs;
     const Off4 off{io[0] * bs, fan > 1 ? io[1] * bs : 0, fan > 2 ? io[2] * bs : 0, fan > 3 ? io[3] * bs : 0};
-    mfma_block<R, MT, NT>(accR, accI, A + o * (int64_t)r_out * K, r_out, r_in, K, mc * MT * 16, nrhs - n0,
+    mfma_block<R, MT, NT>(acc, A + o * (int64_t)r_out * K, r_out, r_in, K, mc * MT * 16, nrhs - n0,
                           x + n0, off, (int64_t)nrhs);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -304,7 +312,7 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
                 const int row = (mc * MT + mt) * 16 + MF<R>::drow(lk, v);
                 const int col = n0 + nt * 16 + li;
                 if (row < r_out && col < nrhs)
-                    y[(o * r_out + row) * (int64_t)nrhs + col] = C{accR[mt][nt][v], accI[mt][nt][v]};
+                    y[(o * r_out + row) * (int64_t)nrhs + col] = acc.get(mt, nt, v);
             }
 }
 
@@ -339,7 +347,7 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
     const int32_t *t = tab + g * 16;
     const int n0 = chunk * COLS;
     const int ncols = nrhs - n0;
-    V4 accR[MT][NT], accI[MT][NT];
+    Acc<R, MT, NT> acc;
     const int ba = t[w];
     if (ba >= 0) {  // wave-uniform
         const int Ka = fan_a * r_in_a;
@@ -347,7 +355,7 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
         const int64_t bs = (int64_t)r_in_a * nrhs;
         const Off4 off{io[0] * bs, fan_a > 1 ? io[1] * bs : 0, fan_a > 2 ? io[2] * bs : 0,
                        fan_a > 3 ? io[3] * bs : 0};
-        mfma_block<R, MT, NT>(accR, accI, A_a + (int64_t)ba * r_mid * Ka, r_mid, r_in_a, Ka, 0, ncols, x + n0,
+        mfma_block<R, MT, NT>(acc, A_a + (int64_t)ba * r_mid * Ka, r_mid, r_in_a, Ka, 0, ncols, x + n0,
                               off, (int64_t)nrhs);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -355,14 +363,14 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    mid[w][mt * 16 + MF<R>::drow(lk, v)][nt * 16 + li] = C{accR[mt][nt][v], accI[mt][nt][v]};
+                    mid[w][mt * 16 + MF<R>::drow(lk, v)][nt * 16 + li] = acc.get(mt, nt, v);
     }
     __syncthreads();
     const int bb = t[4 + w];
     if (bb < 0) return;  // wave-uniform, after the only barrier
     const int Kb = fan_b * r_mid;
     const Off4 off{(int64_t)t[8 + 2 * w] * ROWS * COLS, fan_b > 1 ? (int64_t)t[9 + 2 * w] * ROWS * COLS : 0, 0, 0};
-    mfma_block<R, MT, NT>(accR, accI, A_b + (int64_t)bb * r_out_b * Kb, r_out_b, r_mid, Kb, 0, ncols,
+    mfma_block<R, MT, NT>(acc, A_b + (int64_t)bb * r_out_b * Kb, r_out_b, r_mid, Kb, 0, ncols,
                           &mid[0][0][0], off, (int64_t)COLS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -373,7 +381,7 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
                 const int row = mt * 16 + MF<R>::drow(lk, v);
                 const int col = n0 + nt * 16 + li;
                 if (row < r_out_b && col < nrhs)
-                    y[((int64_t)bb * r_out_b + row) * nrhs + col] = C{accR[mt][nt][v], accI[mt][nt][v]};
+                    y[((int64_t)bb * r_out_b + row) * nrhs + col] = acc.get(mt, nt, v);
             }
 }
 
@@ -634,88 +642,103 @@ void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, 
 // ------------------------------------------------------------------ large skeletonization nodes
 // Nodes whose blocks do not fit LDS run as gathered complex GEMMs on matrix
 // cores, all nodes of a step in one launch per phase.  A tile is 16*MT rows of
-// one node's output times 64 right-hand sides; its input rows are gathered from
-// x (or the temporary t) through the node's index lists.
-//   up:   1) x_r -= T^* x_s      2) t_r = Linv x_r      3) x_s -= M t_r; x_r = t_r
-//   down: 1) t_r = x_r - M^* x_s 2) x_r = Linv^* t_r    3) x_s -= T x_r
-// PH selects the phase: 0..2 up, 3..5 down.
-template <class R, int PH, int MT>
+// one node's output times 16*NT right-hand sides; its input rows are gathered
+// from x (or the temporary t) through the node's index lists.
+//   up:   0) x_r -= T^* x_s      1) t_r = Linv x_r      2) x_s -= M t_r; x_r = t_r
+//   down: 3) t_r = x_r - M^* x_s 4) x_r = Linv^* t_r    5) x_s -= T x_r
+// Every phase reads its factor column-major (the conjugate transposes are stored),
+// so the loads of a tile's rows are coalesced.  Linv is lower triangular: phase 1
+// stops at the tile's last row, phase 4 starts at its first.  The k loop is the
+// pipelined one of the stage kernels, with the gathered row index of the next
+// k-step loaded one step ahead.
+template <class R, int MT, int NT> struct GWalk {
+    const typename MF<R>::C *ap;
+    int k, gnext;  // this lane's next k; gathered row of that k (already loaded)
+};
+
+template <class R, int MT, int NT>
+__device__ __forceinline__ void gfrag_load(Frag<R, MT, NT> &f, GWalk<R, MT, NT> &w, int kend,
+                                           const typename MF<R>::C *__restrict__ xb, int64_t ldx,
+                                           const int32_t *__restrict__ kin,
+                                           const typename MF<R>::C *__restrict__ Ao, int ld,
+                                           const int (&colc)[NT], const int (&rowc)[MT]) {
+    using C = typename MF<R>::C;
+    const C zero = C{0, 0};
+    const bool kv = w.k < kend;
+    const C *xrow = xb + (int64_t)w.gnext * ldx;
+    const C *acol = kv ? w.ap : Ao;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) f.x[nt] = xrow[colc[nt]];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const C v = acol[rowc[mt]];
+        f.a[mt] = kv ? v : zero;
+    }
+    w.k += 4;
+    w.ap += 4 * (int64_t)ld;
+    w.gnext = kin[min(w.k, kend - 1)];
+}
+
+template <class R, int PH, int MT, int NT>
 __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
                                                const int32_t *__restrict__ idx,
                                                const int32_t *__restrict__ tiles,
                                                int64_t ntiles,
                                                const typename MF<R>::C *__restrict__ mat,
+                                               const typename MF<R>::C *__restrict__ matH,
                                                typename MF<R>::C *__restrict__ x,
-                                               typename MF<R>::C *__restrict__ t, int nrhs) {
+                                               typename MF<R>::C *__restrict__ t, int nrhs, int nchunks) {
     using C = typename MF<R>::C;
-    using V4 = typename MF<R>::V4;
     const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int64_t wg;
+    int chunk;
+    xcd_order((ntiles + 3) / 4, nchunks, wg, chunk);
+    const int64_t wave = wg * 4 + (threadIdx.x >> 6);
     if (wave >= ntiles) return;  // wave-uniform
     const int v = tiles[2 * wave], row0 = tiles[2 * wave + 1];
     const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
     const int32_t *ir = idx + desc[4 * v + 2];
     const int32_t *is = ir + nr;
-    const C *Tm = mat + desc[4 * v + 3];
-    const C *Li = Tm + (int64_t)ns * nr;
-    const C *Mm = Li + (int64_t)nr * nr;
-    // phase configuration
-    constexpr bool CONJT = (PH == 0 || PH == 3 || PH == 4);   // A(i,k) = conj(S[k + i*ld])
+    const int64_t mo = desc[4 * v + 3];
+    // factor block of the phase, column-major m x K with leading dimension ld
     constexpr bool SUB = (PH == 0 || PH == 2 || PH == 3 || PH == 5);
     const int m = (PH == 2 || PH == 5) ? ns : nr;
     const int K = (PH == 0 || PH == 3) ? ns : nr;
-    const C *S = (PH == 0 || PH == 5) ? Tm : ((PH == 1 || PH == 4) ? Li : Mm);
-    const int ld = (PH == 1 || PH == 4) ? nr : ns;
+    const int ld = (PH == 2 || PH == 5) ? ns : nr;
+    const int64_t off = (PH == 0 || PH == 5) ? 0 : ((PH == 1 || PH == 4) ? (int64_t)ns * nr : (int64_t)ns * nr + (int64_t)nr * nr);
+    const C *S = ((PH == 0 || PH == 3 || PH == 4) ? matH : mat) + mo + off;
     const int32_t *kin = (PH == 0 || PH == 3) ? is : ir;      // input rows
     const C *src = (PH == 2 || PH == 4) ? t : x;              // input vector
     const int32_t *oout = (PH == 2 || PH == 5) ? is : ir;     // output rows
     C *dst = (PH == 1 || PH == 3) ? t : x;                    // output vector
     const C *yin = (PH == 3) ? x : dst;                       // subtracted-from vector
-    const int n0 = blockIdx.y * 64;
+    const int kbeg = (PH == 4) ? row0 : 0;
+    const int kend = (PH == 1) ? min(K, row0 + 16 * MT) : K;
+    const int n0 = chunk * (16 * NT);
+    const int ncols = nrhs - n0;
     const int li = lane & 15, lk = lane >> 4;
-    V4 accR[MT][4], accI[MT][4];
+    Acc<R, MT, NT> acc;
+    acc.zero();
+    if (kbeg < kend && m > 0) {  // wave-uniform
+        int colc[NT], rowc[MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+        for (int nt = 0; nt < NT; ++nt) colc[nt] = min(nt * 16 + li, ncols - 1);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            accR[mt][nt] = V4{0, 0, 0, 0};
-            accI[mt][nt] = V4{0, 0, 0, 0};
-        }
-    const C zero = C{0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-        const int k = k0 + lk;
-        const bool kv = k < K;
-        C xv[4];
-        if (kv) {
-            const C *xrow = src + (int64_t)kin[k] * nrhs;
+        for (int mt = 0; mt < MT; ++mt) rowc[mt] = min(row0 + mt * 16 + li, m - 1);
+        const C *xb = src + n0;
+        GWalk<R, MT, NT> w;
+        w.k = kbeg + lk;
+        w.ap = S + (int64_t)w.k * ld;
+        w.gnext = kin[min(w.k, kend - 1)];
+        Frag<R, MT, NT> f[STAGE_PF];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int col = n0 + nt * 16 + li;
-                xv[nt] = (col < nrhs) ? xrow[col] : zero;
-            }
-        } else {
+        for (int j = 0; j + 1 < STAGE_PF; ++j) gfrag_load(f[j], w, kend, xb, nrhs, kin, S, ld, colc, rowc);
+        for (int k0 = kbeg; k0 < kend; k0 += 4 * STAGE_PF) {
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) xv[nt] = zero;
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int row = row0 + mt * 16 + li;
-            C av = zero;
-            if (kv && row < m) {
-                if (CONJT) {
-                    av = S[k + (int64_t)row * ld];
-                    av.y = -av.y;
-                } else {
-                    av = S[row + (int64_t)k * ld];
-                }
-            }
-            const R ar = av.x, ai = av.y, nai = -av.y;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                accR[mt][nt] = MF<R>::mma(ar, xv[nt].x, accR[mt][nt]);
-                accR[mt][nt] = MF<R>::mma(nai, xv[nt].y, accR[mt][nt]);
-                accI[mt][nt] = MF<R>::mma(ar, xv[nt].y, accI[mt][nt]);
-                accI[mt][nt] = MF<R>::mma(ai, xv[nt].x, accI[mt][nt]);
+            for (int j = 0; j < STAGE_PF; ++j) {
+                if (k0 + 4 * j >= kend) break;  // wave-uniform
+                gfrag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, kend, xb, nrhs, kin, S, ld, colc, rowc);
+                acc.mma(f[j]);
             }
         }
     }
@@ -727,10 +750,10 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
             if (row >= m) continue;
             const int64_t orow = (int64_t)oout[row] * nrhs;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
+            for (int nt = 0; nt < NT; ++nt) {
                 const int col = n0 + nt * 16 + li;
                 if (col >= nrhs) continue;
-                C a = C{accR[mt][nt][vv], accI[mt][nt][vv]};
+                C a = acc.get(mt, nt, vv);
                 if (SUB) {
                     const C b = yin[orow + col];
                     a = C{b.x - a.x, b.y - a.y};
@@ -740,27 +763,33 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
         }
 }
 
-// x_r = t_r for every node of a step (end of the upward phase 3).
+// x_r = t_r for every node of a step (end of the upward pass): one workgroup per
+// tile of 16 redundant rows, all right-hand sides.
 template <class C>
 __global__ void __launch_bounds__(256) k_hcopy(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
-                                               const C *__restrict__ t, C *__restrict__ x, int nrhs) {
-    const int64_t v = blockIdx.x;
+                                               const int32_t *__restrict__ tiles, const C *__restrict__ t,
+                                               C *__restrict__ x, int nrhs) {
+    const int64_t tile = blockIdx.x;
+    const int v = tiles[2 * tile], row0 = tiles[2 * tile + 1];
     const int nr = (int)desc[4 * v];
     const int32_t *ir = idx + desc[4 * v + 2];
-    for (int e = threadIdx.x; e < nr * nrhs; e += blockDim.x) {
-        const int64_t g = (int64_t)ir[e / nrhs] * nrhs + e % nrhs;
+    const int rows = min(16, nr - row0);
+    for (int e = threadIdx.x; e < rows * nrhs; e += blockDim.x) {
+        const int64_t g = (int64_t)ir[row0 + e / nrhs] * nrhs + e % nrhs;
         x[g] = t[g];
     }
 }
 
-template <class R>
+template <class R, int NT>
 static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, void *x, void *t,
                         int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
     if (ntiles == 0) return;
-    const dim3 g((unsigned)((ntiles + 3) / 4), (unsigned)((nrhs + 63) / 64));
-    const C *mat = (const C *)h.mat;
-#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1>), g, dim3(256), 0, st, h.desc, h.idx, tiles, ntiles, mat, (C *)x, (C *)t, nrhs)
+    const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
+    const dim3 g(xcd_grid((ntiles + 3) / 4, nch));
+    const C *mat = (const C *)h.mat, *matH = (const C *)h.matH;
+#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1, NT>), g, dim3(256), 0, st, h.desc, h.idx, tiles, ntiles, mat, matH, \
+                                 (C *)x, (C *)t, nrhs, nch)
     switch (ph) {
         case 0: HG(0); break;
         case 1: HG(1); break;
@@ -772,22 +801,33 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
 #undef HG
 }
 
-void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, hipStream_t st) {
+template <class R>
+static void hgemm_phase_nt(int nt, int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, void *x,
+                           void *t, int nrhs, hipStream_t st) {
+    if (nt == 1) hgemm_phase<R, 1>(ph, h, tiles, ntiles, x, t, nrhs, st);
+    else if (nt == 2) hgemm_phase<R, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
+    else hgemm_phase<R, 4>(ph, h, tiles, ntiles, x, t, nrhs, st);
+}
+
+void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
+                          hipStream_t st) {
     if (h.n_nodes == 0) return;
+    const int nt = cols <= 16 ? 1 : (cols <= 32 ? 2 : 4);
     const int p0 = up ? 0 : 3;
     for (int k = 0; k < 3; ++k) {
         const int ph = p0 + k;
         // phases 2 and 5 produce the skeleton rows (ns), the others the redundant rows (nr)
         const bool srows = (ph == 2 || ph == 5);
         const int32_t *tiles = srows ? h.tiles_s : h.tiles_r;
-        const int64_t nt = srows ? h.n_tiles_s : h.n_tiles_r;
-        if (dbl) hgemm_phase<double>(ph, h, tiles, nt, x, t, nrhs, st);
-        else hgemm_phase<float>(ph, h, tiles, nt, x, t, nrhs, st);
+        const int64_t ntl = srows ? h.n_tiles_s : h.n_tiles_r;
+        if (dbl) hgemm_phase_nt<double>(nt, ph, h, tiles, ntl, x, t, nrhs, st);
+        else hgemm_phase_nt<float>(nt, ph, h, tiles, ntl, x, t, nrhs, st);
         check_launch("hif step (matrix cores)");
     }
-    if (up) {
-        if (dbl) hipLaunchKernelGGL(k_hcopy<double2>, dim3((unsigned)h.n_nodes), dim3(256), 0, st, h.desc, h.idx, (const double2 *)t, (double2 *)x, nrhs);
-        else hipLaunchKernelGGL(k_hcopy<float2>, dim3((unsigned)h.n_nodes), dim3(256), 0, st, h.desc, h.idx, (const float2 *)t, (float2 *)x, nrhs);
+    if (up && h.n_tiles_r > 0) {
+        const dim3 g((unsigned)h.n_tiles_r);
+        if (dbl) hipLaunchKernelGGL(k_hcopy<double2>, g, dim3(256), 0, st, h.desc, h.idx, h.tiles_r, (const double2 *)t, (double2 *)x, nrhs);
+        else hipLaunchKernelGGL(k_hcopy<float2>, g, dim3(256), 0, st, h.desc, h.idx, h.tiles_r, (const float2 *)t, (float2 *)x, nrhs);
         check_launch("hif copy");
     }
 }

@@ -51,13 +51,18 @@ struct HifStepDev {
     const int64_t *desc = nullptr;
     const int32_t *idx = nullptr;
     const void *mat = nullptr;
+    // Conjugate transposes T^* (nr x ns), Linv^* (nr x nr), M^* (nr x ns) at the
+    // offsets of T, Linv, M, column-major (read by the matrix-core path).
+    const void *matH = nullptr;
 };
 
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st);
 void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st);
-// Large-node variant of launch_hif_step (gathered GEMMs on matrix cores); t is an
-// N x nrhs temporary of the same dtype.
-void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, hipStream_t st);
+// Large-node variant of launch_hif_step (gathered GEMMs on matrix cores, tiles of
+// 16 rows by `cols` = 16, 32 or 64 right-hand sides); t is an N x nrhs temporary of
+// the same dtype.
+void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
+                          hipStream_t st);
 // Whether a step's largest node fits the LDS-staged kernel.
 bool hif_step_fits_lds(const HifStepDev &h, bool dbl);
 void launch_rows_gather(const void *x, bool xd, const int32_t *idx, int64_t rows, int nrhs, void *out, bool od,
