@@ -115,16 +115,22 @@ typedef enum {
     FIO_SOLVE_DIRECT = 0,   /* fhat = Gd Kd^* u                                        */
     FIO_SOLVE_REFINE = 1,   /* direct solve, then x += Gd Kd^*(u - Kd x) with the
                                residual in FP64 (complex128 factors)                  */
-    FIO_SOLVE_PCG = 2       /* CG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5) */
+    FIO_SOLVE_PCG = 2,      /* CG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5) */
+    FIO_SOLVE_GMRES = 3     /* restarted GMRES on Kd fhat = u with the right preconditioner
+                               Gd Kd^* (section 7: avoids the squared condition number of
+                               the normal equations); vectors and Gram-Schmidt in FP64,
+                               operator applies in dtype                                  */
 } fio_solve_mode;
 
 typedef struct {
     fio_solve_mode mode;
     double tol;             /* REFINE: stop when ||dx|| <= tol ||x|| for every column;
-                               PCG: stop when ||r|| <= tol ||Kd^* u||; 0 -> run maxit */
-    int maxit;              /* iteration cap (REFINE steps or PCG iterations)          */
+                               PCG: stop when ||r|| <= tol ||Kd^* u||;
+                               GMRES: stop when ||u - Kd x|| <= tol ||u||; 0 -> run maxit */
+    int maxit;              /* iteration cap (REFINE steps, PCG or GMRES iterations)   */
     int precondition;       /* PCG only: 1 -> Gd, 0 -> none (the paper's "Kd^* only") */
     int spatial;            /* 1 -> return f = F^{-1} fhat (see fio_inverse_dft) instead of fhat */
+    int restart;            /* GMRES only: Krylov dimension per cycle (0 -> 20, at most 64) */
 } fio_solve_opts;
 
 typedef struct {

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
+#include <cmath>
 #include <map>
 #include <cstring>
 #include <memory>
@@ -173,6 +175,8 @@ struct fio_plan_s {
     // workspace (grown on demand)
     int ws_nrhs = 0;
     DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal, HT, RI, RO;
+    DBuf GV, GH;                              // GMRES basis ((m+1) vectors) and Hessenberg entries
+    int64_t gv_vecs = 0, gv_cnt = 0;
     std::mutex mu;
     // Autotuned choices keyed by (dtype, nrhs): stage kernel variant per stage of the
     // forward and adjoint chains, which consecutive stages run fused, and per
@@ -828,13 +832,169 @@ fio_status fio_inverse_apply(fio_plan p, fio_dtype dt, const void *u, void *fh, 
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Restarted GMRES on Kd x = u with the right preconditioner M = Gd Kd^* (or M = I),
+// one Krylov space per column: x = M V y minimises ||u - Kd x|| over the space.
+// Arnoldi with modified Gram-Schmidt runs on the device with per-column scalars;
+// the Hessenberg columns come to the host after every step, where complex Givens
+// rotations keep the least-squares residual |g_{j+1}| of every column.  At the end
+// of a cycle y solves the triangular system, x += M (V y), and the next cycle
+// starts from the true residual.  Expects p->U = u, leaves x in p->X (complex128).
+template <class AC, class GD>
+int gmres(fio_plan p, const fio_solve_opts *opts, int nr, AC &apply_chain, GD &gd128, hipStream_t st,
+          double &worst, bool &converged) {
+    using cdd = std::complex<double>;
+    const int64_t N = p->host.N, cnt = N * nr;
+    const int m = opts->restart > 0 ? std::min(opts->restart, 64) : 20;
+    if (p->gv_vecs < m + 1 || p->gv_cnt < cnt) {
+        p->GV.alloc((size_t)(m + 1) * cnt * 16);
+        p->GH.alloc((size_t)(m + 1) * m * 2 * nr * sizeof(double) + (size_t)(m + 1) * 2 * nr * sizeof(double));
+        p->gv_vecs = m + 1;
+        p->gv_cnt = cnt;
+    }
+    auto V = [&](int j) { return (void *)((char *)p->GV.p + (size_t)j * cnt * 16); };
+    double *H = (double *)p->GH.p;                        // column j of the Hessenberg: H + j*(m+1)*2*nr
+    double *Yd = H + (size_t)(m + 1) * m * 2 * nr;       // y per column
+    auto Hc = [&](int j, int i) { return H + ((size_t)j * (m + 1) + i) * 2 * nr; };
+    double *scal = (double *)p->scal.p;
+    double *nrm = scal + 6 * nr;
+    double *red = (double *)p->red.p;
+    const int64_t cap = reduce_partial_cap(N, nr);
+    const bool pre = opts->precondition != 0;
+    auto applyM = [&](const void *in128, void *out128) {  // out = Gd Kd^* in (complex128)
+        apply_chain(false, in128, out128);
+        gd128(out128, out128);
+    };
+    // unorm
+    std::vector<double> hb(2 * (size_t)(m + 1) * nr), h2(nr), unorm(nr), beta(nr);
+    launch_colnorm2(p->U.p, N, nr, red, cap, nrm, st);
+    HIPC(hipMemcpyAsync(h2.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    for (int b = 0; b < nr; ++b) unorm[b] = std::max(std::sqrt(h2[b]), 1e-300);
+    launch_scale_zero(p->X.p, cnt, st);
+    std::vector<cdd> R((size_t)m * m * nr), g((size_t)(m + 1) * nr), cs((size_t)m * nr), sn((size_t)m * nr);
+    std::vector<double> yh(2 * (size_t)m * nr);
+    const int maxit = std::max(1, opts->maxit);
+    int total = 0;
+    converged = false;
+    worst = 1.0;
+    bool first = true;
+    while (total < maxit) {
+        // r = u - Kd x (x = 0 in the first cycle)
+        if (first) {
+            HIPC(hipMemcpyAsync(p->R.p, p->U.p, cnt * 16, hipMemcpyDeviceToDevice, st));
+        } else {
+            apply_chain(true, p->X.p, p->V1.p);
+            launch_residual(p->U.p, p->V1.p, p->R.p, true, cnt, st);
+        }
+        first = false;
+        launch_colnorm2(p->R.p, N, nr, red, cap, nrm, st);
+        launch_col_unit(V(0), p->R.p, nrm, N, nr, st);
+        HIPC(hipMemcpyAsync(h2.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+        worst = 0;
+        for (int b = 0; b < nr; ++b) {
+            beta[b] = std::sqrt(h2[b]);
+            worst = std::max(worst, beta[b] / unorm[b]);
+        }
+        if (opts->tol > 0 && worst <= opts->tol) { converged = true; break; }
+        std::fill(g.begin(), g.end(), cdd(0));
+        for (int b = 0; b < nr; ++b) g[b] = beta[b];
+        int j = 0;
+        for (; j < m && total < maxit; ++j) {
+            ++total;
+            // w = Kd M v_j
+            if (pre) {
+                applyM(V(j), p->Z.p);
+            } else {
+                HIPC(hipMemcpyAsync(p->Z.p, V(j), cnt * 16, hipMemcpyDeviceToDevice, st));
+            }
+            apply_chain(true, p->Z.p, p->V1.p);
+            for (int i = 0; i <= j; ++i) {
+                launch_coldot(V(i), p->V1.p, N, nr, red, cap, Hc(j, i), st);
+                launch_col_axpy(p->V1.p, V(i), Hc(j, i), -1.0, N, nr, st);
+            }
+            launch_colnorm2(p->V1.p, N, nr, red, cap, nrm, st);
+            launch_col_unit(V(j + 1), p->V1.p, nrm, N, nr, st);
+            HIPC(hipMemcpyAsync(hb.data(), Hc(j, 0), (size_t)(j + 1) * 2 * nr * sizeof(double),
+                                hipMemcpyDeviceToHost, st));
+            HIPC(hipMemcpyAsync(h2.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPC(hipStreamSynchronize(st));
+            worst = 0;
+            for (int b = 0; b < nr; ++b) {
+                std::vector<cdd> h(j + 2);
+                for (int i = 0; i <= j; ++i) h[i] = cdd(hb[(size_t)i * 2 * nr + 2 * b], hb[(size_t)i * 2 * nr + 2 * b + 1]);
+                h[j + 1] = std::sqrt(h2[b]);
+                for (int i = 0; i < j; ++i) {  // earlier rotations
+                    const cdd c = cs[(size_t)i * nr + b], s = sn[(size_t)i * nr + b];
+                    const cdd a0 = h[i], a1 = h[i + 1];
+                    h[i] = c * a0 + s * a1;
+                    h[i + 1] = -std::conj(s) * a0 + c * a1;
+                }
+                const double aa = std::abs(h[j]), bb = std::abs(h[j + 1]);
+                const double t = std::hypot(aa, bb);
+                cdd c = 1.0, s = 0.0;
+                if (t > 0) {
+                    if (aa == 0) { c = 0.0; s = std::conj(h[j + 1]) / bb; }
+                    else { c = aa / t; s = (h[j] / aa) * std::conj(h[j + 1]) / t; }
+                }
+                cs[(size_t)j * nr + b] = c;
+                sn[(size_t)j * nr + b] = s;
+                h[j] = c * h[j] + s * h[j + 1];
+                for (int i = 0; i <= j; ++i) R[((size_t)j * m + i) * nr + b] = h[i];
+                const cdd gj = g[(size_t)j * nr + b];
+                g[(size_t)j * nr + b] = c * gj;
+                g[(size_t)(j + 1) * nr + b] = -std::conj(s) * gj;
+                worst = std::max(worst, std::abs(g[(size_t)(j + 1) * nr + b]) / unorm[b]);
+            }
+            if (opts->tol > 0 && worst <= opts->tol) { ++j; break; }
+        }
+        // y = R^{-1} g (upper triangular, j x j) per column; x += M (V y)
+        for (int b = 0; b < nr; ++b) {
+            std::vector<cdd> y(j);
+            for (int i = j - 1; i >= 0; --i) {
+                cdd acc = g[(size_t)i * nr + b];
+                for (int k = i + 1; k < j; ++k) acc -= R[((size_t)k * m + i) * nr + b] * y[k];
+                const cdd d = R[((size_t)i * m + i) * nr + b];
+                y[i] = std::abs(d) > 0 ? acc / d : cdd(0);
+            }
+            for (int i = 0; i < j; ++i) {
+                yh[(size_t)i * 2 * nr + 2 * b] = y[i].real();
+                yh[(size_t)i * 2 * nr + 2 * b + 1] = y[i].imag();
+            }
+        }
+        HIPC(hipMemcpyAsync(Yd, yh.data(), (size_t)j * 2 * nr * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_scale_zero(p->Pv.p, cnt, st);
+        for (int i = 0; i < j; ++i) launch_col_axpy(p->Pv.p, V(i), Yd + (size_t)i * 2 * nr, 1.0, N, nr, st);
+        if (pre) {
+            applyM(p->Pv.p, p->Z.p);
+            launch_axpy_update(p->X.p, p->Z.p, true, cnt, st);
+        } else {
+            launch_axpy_update(p->X.p, p->Pv.p, true, cnt, st);
+        }
+        HIPC(hipStreamSynchronize(st));  // the host copy of y is reused by the next cycle
+        if (opts->tol > 0 && worst <= opts->tol) { converged = true; break; }
+        if (opts->tol == 0 && total >= maxit) { converged = true; break; }
+    }
+    if (opts->tol == 0) converged = true;
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
 fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const void *u, void *out,
                      int64_t nrhs, int64_t ld, fio_solve_info *info, void *stream) {
     return guard([&] {
         check_apply_args(p, nrhs, ld, u, out);
         if (!opts) fail(FIO_ERR_ARG, "null options");
         if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
-        if (opts->mode < FIO_SOLVE_DIRECT || opts->mode > FIO_SOLVE_PCG) fail(FIO_ERR_ARG, "bad mode");
+        if (opts->mode < FIO_SOLVE_DIRECT || opts->mode > FIO_SOLVE_GMRES) fail(FIO_ERR_ARG, "bad mode");
+        if (opts->restart < 0) fail(FIO_ERR_ARG, "bad restart length");
         if (opts->maxit < 0 || opts->tol < 0) fail(FIO_ERR_ARG, "bad iteration settings");
         if (nrhs == 0) return;
         std::lock_guard<std::mutex> lk(p->mu);
@@ -863,7 +1023,35 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             run_chain(p, false, dbl, src, d_out, nr, st);
             gd_inplace(p, dbl, d_out, nr, st);
         };
-        if (opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_REFINE) {
+        // Operator applies on complex128 vectors, computed in dtype (V3, W: conversions).
+        auto apply_chain = [&](bool fwd, const void *in128, void *out128) {
+            if (dbl) {
+                run_chain(p, fwd, true, in128, out128, nr, st);
+            } else {
+                launch_convert(in128, true, p->V3.p, false, cnt, st);
+                run_chain(p, fwd, false, p->V3.p, p->W.p, nr, st);
+                launch_convert(p->W.p, false, out128, true, cnt, st);
+            }
+        };
+        // z = Gd r on complex128 vectors, computed in dtype (z may alias r).
+        auto gd128 = [&](const void *r128, void *z128) {
+            if (dbl) {
+                if (z128 != r128) HIPC(hipMemcpyAsync(z128, r128, cnt * 16, hipMemcpyDeviceToDevice, st));
+                gd_inplace(p, true, z128, nr, st);
+            } else {
+                launch_convert(r128, true, p->V3.p, false, cnt, st);
+                gd_inplace(p, false, p->V3.p, nr, st);
+                launch_convert(p->V3.p, false, z128, true, cnt, st);
+            }
+        };
+        // PCG preconditioner: Gd, or the identity without preconditioning.
+        auto precond = [&](const void *r128, void *z128) {
+            if (!opts->precondition) HIPC(hipMemcpyAsync(z128, r128, cnt * 16, hipMemcpyDeviceToDevice, st));
+            else gd128(r128, z128);
+        };
+        if (opts->mode == FIO_SOLVE_GMRES) {
+            iters = gmres(p, opts, nr, apply_chain, gd128, st, worst, converged);
+        } else if (opts->mode == FIO_SOLVE_DIRECT || opts->mode == FIO_SOLVE_REFINE) {
             gd_kh(p->U.p, p->V2.p);
             launch_convert(p->V2.p, dbl, p->X.p, true, cnt, st);  // x0 = Gd Kd^* u
             if (opts->mode == FIO_SOLVE_REFINE) {
@@ -893,29 +1081,6 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
         } else {
             // PCG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5).  Vectors are
             // complex128; the operator applies run in dtype.
-            auto apply_chain = [&](bool fwd, const void *in128, void *out128) {
-                if (dbl) {
-                    run_chain(p, fwd, true, in128, out128, nr, st);
-                } else {
-                    launch_convert(in128, true, p->V3.p, false, cnt, st);
-                    run_chain(p, fwd, false, p->V3.p, p->W.p, nr, st);
-                    launch_convert(p->W.p, false, out128, true, cnt, st);
-                }
-            };
-            auto precond = [&](const void *r128, void *z128) {
-                if (!opts->precondition) {
-                    HIPC(hipMemcpyAsync(z128, r128, cnt * 16, hipMemcpyDeviceToDevice, st));
-                    return;
-                }
-                if (dbl) {
-                    HIPC(hipMemcpyAsync(z128, r128, cnt * 16, hipMemcpyDeviceToDevice, st));
-                    gd_inplace(p, true, z128, nr, st);
-                } else {
-                    launch_convert(r128, true, p->V3.p, false, cnt, st);
-                    gd_inplace(p, false, p->V3.p, nr, st);
-                    launch_convert(p->V3.p, false, z128, true, cnt, st);
-                }
-            };
             double *rz = scal, *rzn = scal + 2 * nr, *pAp = scal + 4 * nr, *nrm = scal + 6 * nr;
             const int64_t cap = reduce_partial_cap(N, nr);
             apply_chain(false, p->U.p, p->R.p);  // r = b = Kd^* u (x0 = 0)

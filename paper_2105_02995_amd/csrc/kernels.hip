@@ -1144,6 +1144,45 @@ void launch_pcg_p(void *p, const void *z, const double *rzn, const double *rzo, 
     check_launch("pcg p update");
 }
 
+// y_b += sign * alpha_b * x_b per column b (complex128, alpha on the device as re, im pairs).
+__global__ void __launch_bounds__(256) k_col_axpy(double2 *__restrict__ y, const double2 *__restrict__ x,
+                                                  const double *__restrict__ alpha, double sign, int64_t n,
+                                                  int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const double ar = sign * alpha[2 * b], ai = sign * alpha[2 * b + 1];
+        const double2 xv = x[t];
+        double2 yv = y[t];
+        yv.x += ar * xv.x - ai * xv.y;
+        yv.y += ar * xv.y + ai * xv.x;
+        y[t] = yv;
+    }
+}
+
+// y_b = x_b / sqrt(nrm2_b) per column (zero where nrm2_b is zero).
+__global__ void __launch_bounds__(256) k_col_unit(double2 *__restrict__ y, const double2 *__restrict__ x,
+                                                  const double *__restrict__ nrm2, int64_t n, int nrhs) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t % nrhs);
+        const double s = nrm2[b] > 0 ? 1.0 / sqrt(nrm2[b]) : 0.0;
+        const double2 xv = x[t];
+        y[t] = make_double2(s * xv.x, s * xv.y);
+    }
+}
+
+void launch_col_axpy(void *y, const void *x, const double *alpha, double sign, int64_t n, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_axpy, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, st, (double2 *)y, (const double2 *)x,
+                       alpha, sign, n, nrhs);
+    check_launch("column axpy");
+}
+
+void launch_col_unit(void *y, const void *x, const double *nrm2, int64_t n, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_unit, dim3(grid_for(n * nrhs, 256)), dim3(256), 0, st, (double2 *)y, (const double2 *)x,
+                       nrm2, n, nrhs);
+    check_launch("column normalise");
+}
 
 // ------------------------------------------------------------------ inverse DFT (layout out)
 // f = F^-1 fhat = n^d F* fhat (section 1: F_jk = n^-d exp(-2 pi i x_k . xi_j)).  With

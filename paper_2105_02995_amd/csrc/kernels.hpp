@@ -96,6 +96,12 @@ void launch_pcg_xr(void *x, void *r, const void *p, const void *Ap, const double
 void launch_pcg_p(void *p, const void *z, const double *rz_new, const double *rz_old, int64_t n,
                   int nrhs, hipStream_t st);
 
+// GMRES vector updates (complex128, per-column scalars on the device):
+// y_b += sign * alpha_b x_b (alpha as re, im pairs); y_b = x_b / sqrt(nrm2_b).
+void launch_col_axpy(void *y, const void *x, const double *alpha, double sign, int64_t n, int nrhs,
+                     hipStream_t st);
+void launch_col_unit(void *y, const void *x, const double *nrm2, int64_t n, int nrhs, hipStream_t st);
+
 int64_t reduce_partial_cap(int64_t n, int nrhs);
 // f = n^d F* fhat (section 1) for user-layout complex128 blocks (column-major N x nrhs,
 // leading dimension ld; f may alias fhat).  w0, w1: N x nrhs complex128 temporaries.

@@ -19,7 +19,7 @@ STATUS = {0: "FIO_OK", 1: "FIO_ERR_ARG", 2: "FIO_ERR_NOMEM", 3: "FIO_ERR_DEVICE"
 FIO_C64, FIO_C128 = 0, 1
 FIO_OP_K, FIO_OP_KH = 0, 1
 FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON = 0, 1, 2
-FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG = 0, 1, 2
+FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG, FIO_SOLVE_GMRES = 0, 1, 2, 3
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON}
 
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
@@ -46,7 +46,7 @@ class fio_problem(ctypes.Structure):
 
 class fio_solve_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
-                ("precondition", ctypes.c_int), ("spatial", ctypes.c_int)]
+                ("precondition", ctypes.c_int), ("spatial", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class fio_solve_info(ctypes.Structure):
@@ -225,8 +225,8 @@ def fio_gd_apply(plan: Plan, dtype: int, x, y, nrhs: int, ld: int, stream=None):
 
 def fio_solve(plan: Plan, mode: int, dtype: int, u, out, nrhs: int, ld: int, tol: float = 0.0,
               maxit: int = 0, precondition: int = 1, stream=None, want_info: bool = True,
-              spatial: int = 0):
-    o = fio_solve_opts(mode, tol, maxit, precondition, spatial)
+              spatial: int = 0, restart: int = 0):
+    o = fio_solve_opts(mode, tol, maxit, precondition, spatial, restart)
     info = fio_solve_info()
     _check(load_library().fio_solve(plan.handle, ctypes.byref(o), dtype, _ptr(u), _ptr(out), nrhs,
                                     ld, ctypes.byref(info) if want_info else None,

@@ -49,10 +49,10 @@ def inverse(plan, dtype, u: np.ndarray, ld=None):
     return from_dev(Y, N)
 
 
-def solve(plan, mode, dtype, u: np.ndarray, tol=0.0, maxit=0, precondition=1, ld=None, spatial=0):
+def solve(plan, mode, dtype, u: np.ndarray, tol=0.0, maxit=0, precondition=1, ld=None, spatial=0, restart=0):
     N = u.shape[0]
     U = to_dev(u, F.FIO_C128, ld)
     Y = empty(N, U.shape[0], F.FIO_C128, ld)
     info = F.fio_solve(plan, mode, dtype, U, Y, U.shape[0], U.shape[1], tol=tol, maxit=maxit,
-                       precondition=precondition, stream=stream(), spatial=spatial)
+                       precondition=precondition, stream=stream(), spatial=spatial, restart=restart)
     return from_dev(Y, N), info
