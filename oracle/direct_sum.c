@@ -11,7 +11,7 @@
  *   forward:  u(x_i)  = sum_j  a(x_i, xi_j) exp(2 pi i Phi(x_i, xi_j)) fhat(xi_j)
  *   adjoint:  v(xi_j) = sum_i  conj(a) exp(-2 pi i Phi(x_i, xi_j)) u(x_i)
  *
- * with a = 1, x = (k_1..k_d)/n for 0 <= k < n and xi = (j_1..j_d) for
+ * with a = 1 except for Example 2, x = (k_1..k_d)/n for 0 <= k < n and xi = (j_1..j_d) for
  * -n/2 <= j < n/2, points in lexicographic order with the first coordinate
  * slowest.  Phi = x.xi + phi(x, xi); the linear part is reduced exactly in
  * integers, ((sum_d k_d xi_d) mod n)/n, and phi is evaluated in double and
@@ -25,6 +25,9 @@
  *                 c2 = (2 + cos 2pi x1 cos 2pi x2)/param
  *   3  1d_const   phi = param |xi|   (constant c: K = N F^* diag(e^{2 pi i c|xi|}),
  *                 used only to pin this code against an FFT closed form)
+ *   4  1d_ex2     Example 1's phi with the real amplitude (Example 2)
+ *                 a(x, xi) = sum_k exp(-(d(x, x_k)^2 + (xi/n - eta_k)^2) / sigma2),
+ *                 d the distance on the unit circle; amp = (x_0, eta_0, x_1, eta_1, ...)
  *
  * Vectors are complex, stored as interleaved (re, im) doubles, column-major
  * with leading dimension N for inputs and n_out for outputs.
@@ -47,7 +50,7 @@ static double phi_nonlinear(int d, int n, int phase, double param, long long p, 
     if (d == 1) {
         double x = (double)p / (double)n;
         double xi = (double)(q - n / 2);
-        if (phase == 1) return (2.0 + sin(TWO_PI * x)) / param * fabs(xi);
+        if (phase == 1 || phase == 4) return (2.0 + sin(TWO_PI * x)) / param * fabs(xi);
         if (phase == 3) return param * fabs(xi);
         return 0.0;
     }
@@ -75,14 +78,29 @@ static long long linear_mod(int d, int n, long long p, long long q)
     return s;
 }
 
+/* Example 2's amplitude at X point p, Omega point q (1D). */
+static double amplitude(int n, long long p, long long q, int nterms, const double *amp, double sigma2)
+{
+    double x = (double)p / (double)n, nu = (double)(q - n / 2) / (double)n, a = 0.0;
+    for (int k = 0; k < nterms; ++k) {
+        double dx = fmod(fabs(x - amp[2 * k]), 1.0);
+        if (dx > 0.5) dx = 1.0 - dx;
+        double de = nu - amp[2 * k + 1];
+        a += exp(-(dx * dx + de * de) / sigma2);
+    }
+    return a;
+}
+
 /* Returns 0 on success, -1 on bad arguments. */
 int oracle_fio_apply(int d, int n, int phase, double param, int adjoint, int nrhs,
                      const double *in, double *out, const long long *out_idx,
-                     long long n_out, int nthreads)
+                     long long n_out, int nthreads, int amp_terms, const double *amp,
+                     double sigma2)
 {
     if ((d != 1 && d != 2) || n < 2 || (n % 2) || nrhs < 1) return -1;
-    if (phase < 0 || phase > 3 || ((phase == 1 || phase == 3) && d != 1) ||
+    if (phase < 0 || phase > 4 || ((phase == 1 || phase == 3 || phase == 4) && d != 1) ||
         (phase == 2 && d != 2)) return -1;
+    if (phase == 4 && (amp_terms < 1 || !amp || !(sigma2 > 0))) return -1;
     long long N = (d == 1) ? n : (long long)n * n;
     if (!out_idx) n_out = N;
     /* Input transposed to point-major (all right-hand sides of one point together). */
@@ -112,6 +130,11 @@ int oracle_fio_apply(int d, int n, int phase, double param, int adjoint, int nrh
                                frac(phi_nonlinear(d, n, phase, param, p, q));
                 theta = frac(theta);
                 double c = cos(TWO_PI * theta), s = sin(TWO_PI * theta);
+                if (phase == 4) {
+                    double a = amplitude(n, p, q, amp_terms, amp, sigma2);
+                    c *= a;
+                    s *= a;
+                }
                 if (adjoint) s = -s;
                 const double *v = tin + 2 * b * nrhs;
                 for (int r = 0; r < nrhs; ++r) {

@@ -13,12 +13,12 @@ import subprocess
 import numpy as np
 
 __all__ = [
-    "OracleProblem", "grid", "phase_mod1", "dense_K", "dft_matrix", "dft",
+    "OracleProblem", "grid", "phase_mod1", "amplitude", "dense_K", "dft_matrix", "dft",
     "idft", "idft_rows", "apply_direct", "forward", "adjoint", "solve_dense",
     "solve_normal_cholesky", "cg_normal", "rel_err", "build_c", "PHASE_IDS",
 ]
 
-PHASE_IDS = {"linear": 0, "1d_ex1": 1, "2d_radon": 2, "1d_const": 3}
+PHASE_IDS = {"linear": 0, "1d_ex1": 1, "2d_radon": 2, "1d_const": 3, "1d_ex2": 4}
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_direct_sum.so")
 _lib = None
@@ -26,18 +26,26 @@ _lib = None
 
 @dataclasses.dataclass(frozen=True)
 class OracleProblem:
-    """A discrete FIO with amplitude a = 1 (section 6 examples).
+    """A discrete FIO of the section 6 examples.
 
     phase:  "linear"   Phi = x.xi                              (identity checks)
             "1d_ex1"   Phi = x xi + c(x)|xi|, c = (2 + sin 2 pi x)/param  (Example 1)
+            "1d_ex2"   Example 1's phase with the amplitude below          (Example 2)
             "2d_radon" Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2)       (Example 3)
             "1d_const" Phi = x xi + param |xi|                  (closed-form pin)
     param:  the divisor of c (Examples 1 and 3) or the constant c of "1d_const".
+    amp, sigma2: Example 2's amplitude, a Gaussian mixture periodic in x,
+            a(x, xi) = sum_k exp(-(d(x, x_k)^2 + (xi/n - eta_k)^2) / sigma2),
+            d the distance on the unit circle, amp = ((x_k, eta_k), ...).  The
+            paper gives neither the centres nor their number; these defaults are
+            this build's choice.  a = 1 for the other phases.
     """
     d: int
     n: int
     phase: str
     param: float = 16.0
+    amp: tuple = ((0.2, -0.2), (0.5, 0.2), (0.8, 0.0))
+    sigma2: float = 0.1
 
     @property
     def N(self) -> int:
@@ -63,11 +71,27 @@ def grid(d: int, n: int):
     return k, xi
 
 
+def amplitude(prob: OracleProblem, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+    """a(x_rows, xi_cols) as a (len(rows), len(cols)) array (Example 2; 1 otherwise)."""
+    rows, cols = np.asarray(rows), np.asarray(cols)
+    if prob.phase != "1d_ex2":
+        return np.ones((rows.size, cols.size))
+    k, xi = grid(prob.d, prob.n)
+    x = k[rows, 0] / prob.n
+    nu = xi[cols, 0] / prob.n
+    a = np.zeros((rows.size, cols.size))
+    for xk, ek in prob.amp:
+        dx = np.abs(x - xk) % 1.0
+        dx = np.minimum(dx, 1.0 - dx)
+        a += np.exp(-(dx[:, None] ** 2 + (nu[None, :] - ek) ** 2) / prob.sigma2)
+    return a
+
+
 def _nonlinear(prob: OracleProblem, x: np.ndarray, xi: np.ndarray) -> np.ndarray:
     """phi(x, xi) of the examples in section 6 (x, xi broadcast against each other)."""
     if prob.phase == "linear":
         return np.zeros(np.broadcast_shapes(x.shape[:-1], xi.shape[:-1]))
-    if prob.phase == "1d_ex1":
+    if prob.phase in ("1d_ex1", "1d_ex2"):
         c = (2.0 + np.sin(2 * np.pi * x[..., 0])) / prob.param
         return c * np.abs(xi[..., 0])
     if prob.phase == "1d_const":
@@ -97,9 +121,9 @@ def phase_mod1(prob: OracleProblem, rows: np.ndarray, cols: np.ndarray) -> np.nd
 
 
 def dense_K(prob: OracleProblem) -> np.ndarray:
-    """K_ij = a(x_i, xi_j) exp(2 pi i Phi(x_i, xi_j)) with a = 1 (section 1, eq6)."""
+    """K_ij = a(x_i, xi_j) exp(2 pi i Phi(x_i, xi_j)) (section 1, eq6)."""
     idx = np.arange(prob.N)
-    return np.exp(2j * np.pi * phase_mod1(prob, idx, idx))
+    return amplitude(prob, idx, idx) * np.exp(2j * np.pi * phase_mod1(prob, idx, idx))
 
 
 def dft_matrix(d: int, n: int) -> np.ndarray:
@@ -151,7 +175,7 @@ def _load():
         lib.oracle_fio_apply.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_longlong, ctypes.c_int]
+            ctypes.c_longlong, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_double]
         _lib = lib
     return _lib
 
@@ -173,9 +197,11 @@ def apply_direct(prob: OracleProblem, v: np.ndarray, adjoint: bool = False,
         idx = np.ascontiguousarray(np.asarray(out_idx, dtype=np.int64))
         n_out, idx_ptr = idx.size, idx.ctypes.data
     out = np.zeros((n_out, B), dtype=np.complex128, order="F")
+    amp = np.ascontiguousarray(np.asarray(prob.amp, dtype=np.float64).reshape(-1, 2))
     rc = lib.oracle_fio_apply(prob.d, prob.n, PHASE_IDS[prob.phase], float(prob.param),
                               1 if adjoint else 0, B, V.ctypes.data, out.ctypes.data,
-                              idx_ptr, n_out, int(nthreads))
+                              idx_ptr, n_out, int(nthreads), amp.shape[0], amp.ctypes.data,
+                              float(prob.sigma2))
     if rc != 0:
         raise ValueError("oracle_fio_apply rejected its arguments")
     return out[:, 0] if vec else out

@@ -151,7 +151,7 @@ def test_normal_matrix_hermitian_positive_definite(phase, d, n):
     assert np.linalg.eigvalsh(S).min() > 0.1 * K.shape[0]
 
 
-@pytest.mark.parametrize("phase,d,n", [("1d_ex1", 1, 512), ("2d_radon", 2, 16)])
+@pytest.mark.parametrize("phase,d,n", [("1d_ex1", 1, 512), ("1d_ex2", 1, 512), ("2d_radon", 2, 16)])
 def test_direct_sum_adjoint_identity(phase, d, n):
     """<K x, y> = <x, K^* y> for the direct-summation forward and adjoint."""
     p = O.OracleProblem(d, n, phase, 16.0)
@@ -209,3 +209,54 @@ def test_cg_count_distinguishes_config_phase():
     _, its = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v,
                          gaussian_complex(1024, 20), tol=1e-8)
     assert its < 20
+
+
+def test_example2_single_term_is_separable():
+    """One Gaussian term factors, a(x, xi) = g(x) h(xi), so K = diag(g) K_1 diag(h)
+    with K_1 Example 1's operator: rows reduce to the FFT closed form.  Pins the
+    periodic distance in x, the xi/n scaling and sigma2."""
+    n, x0, e0, s2 = 256, 0.9, 0.15, 0.07
+    p = O.OracleProblem(1, n, "1d_ex2", 16.0, amp=((x0, e0),), sigma2=s2)
+    fh = gaussian_complex(n, 12)
+    nu = (np.arange(n) - n // 2) / n
+    h = np.exp(-(nu - e0) ** 2 / s2)
+    rows = np.array([0, 3, 100, 128, 230, 255])
+    dense = O.dense_K(p) @ fh
+    direct = O.apply_direct(p, fh, out_idx=rows)
+    for t, i in enumerate(rows):
+        x = i / n
+        dx = min(abs(x - x0), 1 - abs(x - x0))
+        g = np.exp(-dx ** 2 / s2)
+        ci = (2.0 + np.sin(2 * np.pi * x)) / 16.0
+        ref = g * _row_closed_form_1d(n, ci, h * fh, i)
+        assert abs(dense[i] - ref) < 1e-10 * max(1.0, abs(ref))
+        assert abs(direct[t] - ref) < 1e-10 * max(1.0, abs(ref))
+
+
+def test_example2_mixture_is_additive_and_real():
+    """The mixture is a sum over its terms, and a is real: K(A u B) = K(A) + K(B)
+    and |K_ij| = a(x_i, xi_j)."""
+    n = 128
+    A, B = ((0.2, -0.2),), ((0.5, 0.2), (0.8, 0.0))
+    pa = O.OracleProblem(1, n, "1d_ex2", 16.0, amp=A, sigma2=0.1)
+    pb = O.OracleProblem(1, n, "1d_ex2", 16.0, amp=B, sigma2=0.1)
+    pab = O.OracleProblem(1, n, "1d_ex2", 16.0, amp=A + B, sigma2=0.1)
+    Kab = O.dense_K(pab)
+    assert np.abs(Kab - O.dense_K(pa) - O.dense_K(pb)).max() < 1e-12
+    idx = np.arange(n)
+    assert np.abs(np.abs(Kab) - O.amplitude(pab, idx, idx)).max() < 1e-12
+
+
+def test_example2_adjoint_is_a_poor_preconditioner():
+    """Section 6, Example 2: with a variable amplitude K^* no longer approximates
+    K^{-1}; CG on K^*K needs on the order of a hundred iterations (sigma2 = 0.1)
+    and more than a thousand (sigma2 = 0.05) at N = 1024, against 12 for a = 1."""
+    counts = []
+    for s2 in (0.1, 0.05):
+        p = O.OracleProblem(1, 1024, "1d_ex2", 16.0, sigma2=s2)
+        K = O.dense_K(p)
+        _, its = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v,
+                             gaussian_complex(1024, 20), tol=1e-8, maxit=5000)
+        counts.append(its)
+    assert 100 <= counts[0] <= 400, counts
+    assert counts[1] > 1000, counts
