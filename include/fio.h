@@ -57,14 +57,21 @@ typedef enum { FIO_C64 = 0, FIO_C128 = 1 } fio_dtype;
 /* Operator selector of fio_apply: Kd (frequency -> space) or its adjoint. */
 typedef enum { FIO_OP_K = 0, FIO_OP_KH = 1 } fio_op;
 
-/* Phase functions of the paper's numerical section (section 6), a = 1. */
+/* Phase functions (and amplitudes) of the paper's numerical section (section 6);
+ * a = 1 except for Example 2. */
 typedef enum {
     FIO_PHASE_LINEAR = 0,   /* Phi = x.xi (K = N F^*: exact identity checks)                */
     FIO_PHASE_1D_EX1 = 1,   /* Phi = x xi + c(x)|xi|, c(x) = (2 + sin 2 pi x)/c_div  (Ex. 1) */
-    FIO_PHASE_2D_RADON = 2  /* Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),          (Ex. 3)
+    FIO_PHASE_2D_RADON = 2, /* Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),          (Ex. 3)
                                c1 = (2 + sin 2pi x1 sin 2pi x2)/c_div,
                                c2 = (2 + cos 2pi x1 cos 2pi x2)/c_div                     */
+    FIO_PHASE_1D_EX2 = 3    /* Example 1's phase with the variable amplitude of Ex. 2:
+                               a(x, xi) = sum_k exp(-(d(x, x_k)^2 + (xi/n - eta_k)^2)/sigma2),
+                               d the distance on the unit circle (periodic in x); the
+                               centres come from amp_x/amp_eta (see fio_problem)          */
 } fio_phase_id;
+
+#define FIO_MAX_AMP_TERMS 8
 
 /* Build description.  Zero means "default" for every tuning field. */
 typedef struct {
@@ -85,6 +92,13 @@ typedef struct {
     int nthreads;           /* host threads for the build; 0 -> hardware concurrency  */
     int verbose;            /* nonzero: fio_build prints one progress line per phase
                                and per tree level to stderr                           */
+    /* Example 2 amplitude (FIO_PHASE_1D_EX2 only; not stored by fio_save).  The paper
+     * gives neither the number of Gaussian terms nor their centres; amp_terms = 0
+     * selects three terms at (x, xi/n) = (0.2, -0.2), (0.5, 0.2), (0.8, 0.0).     */
+    double amp_sigma2;      /* width sigma^2 of every term; 0 -> 0.1                   */
+    int amp_terms;          /* number of terms, 0..FIO_MAX_AMP_TERMS                   */
+    double amp_x[FIO_MAX_AMP_TERMS];    /* centres in x, in [0, 1)                     */
+    double amp_eta[FIO_MAX_AMP_TERMS];  /* centres in xi/n, in [-1/2, 1/2)             */
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",

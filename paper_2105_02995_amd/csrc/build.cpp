@@ -30,7 +30,16 @@ fio_problem normalized_problem(const fio_problem &in) {
     if (!(p.eps > 0 && p.eps < 1)) fail(FIO_ERR_ARG, "eps must lie in (0, 1)");
     if (p.phase == FIO_PHASE_1D_EX1 && p.d != 1) fail(FIO_ERR_ARG, "phase 1D_EX1 needs d = 1");
     if (p.phase == FIO_PHASE_2D_RADON && p.d != 2) fail(FIO_ERR_ARG, "phase 2D_RADON needs d = 2");
-    if (p.phase < FIO_PHASE_LINEAR || p.phase > FIO_PHASE_2D_RADON) fail(FIO_ERR_ARG, "unknown phase");
+    if (p.phase == FIO_PHASE_1D_EX2 && p.d != 1) fail(FIO_ERR_ARG, "phase 1D_EX2 needs d = 1");
+    if (p.phase < FIO_PHASE_LINEAR || p.phase > FIO_PHASE_1D_EX2) fail(FIO_ERR_ARG, "unknown phase");
+    if (p.amp_terms < 0 || p.amp_terms > FIO_MAX_AMP_TERMS) fail(FIO_ERR_ARG, "amp_terms out of range");
+    if (p.amp_sigma2 == 0) p.amp_sigma2 = 0.1;
+    if (!(p.amp_sigma2 > 0)) fail(FIO_ERR_ARG, "amp_sigma2 must be positive");
+    if (p.phase == FIO_PHASE_1D_EX2 && p.amp_terms == 0) {
+        const double cx[3] = {0.2, 0.5, 0.8}, ce[3] = {-0.2, 0.2, 0.0};
+        p.amp_terms = 3;
+        for (int k = 0; k < 3; ++k) { p.amp_x[k] = cx[k]; p.amp_eta[k] = ce[k]; }
+    }
     if (p.c_div == 0) p.c_div = 16.0;
     if (!(p.c_div > 0)) fail(FIO_ERR_ARG, "c_div must be positive");
     if (p.eps_bf == 0) p.eps_bf = p.eps / 10;
@@ -52,7 +61,7 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     auto t0 = std::chrono::steady_clock::now();
     fio_problem p = normalized_problem(pin);
     FioKernel K;
-    K.init(p.d, p.n, p.phase, p.c_div);
+    K.init(p);
     ButterflyOptions bo;
     bo.eps = p.eps_bf;
     bo.leaf = p.leaf_bf;

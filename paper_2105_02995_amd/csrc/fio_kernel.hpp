@@ -31,6 +31,24 @@ struct FioKernel {
     std::vector<double> c1, c2; // per X point (tree order): c(x) (1D) or c1, c2 (2D)
     std::vector<int> k1, k2;    // per X point: integer coordinates
     std::vector<int> j1, j2;    // per Omega point: frequencies xi (-n/2 .. n/2-1)
+    // Example 2's amplitude: each Gaussian term factors into g_k(x) h_k(xi), so
+    // a(x_p, xi_q) = sum_k gx[k][p] hq[k][q] (tree order).
+    std::vector<std::vector<double>> gx, hq;
+
+    void init(const fio_problem &pr) {
+        init(pr.d, pr.n, pr.phase, pr.c_div);
+        if (pr.phase != FIO_PHASE_1D_EX2) return;
+        gx.assign(pr.amp_terms, std::vector<double>(N));
+        hq.assign(pr.amp_terms, std::vector<double>(N));
+        for (int k = 0; k < pr.amp_terms; ++k)
+            for (int64_t t = 0; t < N; ++t) {
+                double dx = std::fmod(std::fabs((double)k1[t] / n - pr.amp_x[k]), 1.0);
+                if (dx > 0.5) dx = 1.0 - dx;
+                const double de = (double)j1[t] / n - pr.amp_eta[k];
+                gx[k][t] = std::exp(-dx * dx / pr.amp_sigma2);
+                hq[k][t] = std::exp(-de * de / pr.amp_sigma2);
+            }
+    }
 
     void init(int d_, int n_, fio_phase_id ph, double cdiv) {
         d = d_; n = n_; phase = ph; c_div = cdiv;
@@ -53,7 +71,7 @@ struct FioKernel {
             k1[t] = a; k2[t] = b;
             j1[t] = a - n / 2; j2[t] = (d == 1) ? 0 : b - n / 2;
             double x1 = (double)a / n, x2 = (double)b / n;
-            if (ph == FIO_PHASE_1D_EX1) {
+            if (ph == FIO_PHASE_1D_EX1 || ph == FIO_PHASE_1D_EX2) {
                 c1[t] = (2.0 + std::sin(tp * x1)) / cdiv;
             } else if (ph == FIO_PHASE_2D_RADON) {
                 c1[t] = (2.0 + std::sin(tp * x1) * std::sin(tp * x2)) / cdiv;
@@ -69,7 +87,7 @@ struct FioKernel {
         s %= n;
         if (s < 0) s += n;
         double nl = 0.0;
-        if (phase == FIO_PHASE_1D_EX1) {
+        if (phase == FIO_PHASE_1D_EX1 || phase == FIO_PHASE_1D_EX2) {
             nl = c1[p] * std::fabs((double)j1[q]);
         } else if (phase == FIO_PHASE_2D_RADON) {
             double a = c1[p] * j1[q], b = c2[p] * j2[q];
@@ -79,9 +97,16 @@ struct FioKernel {
         return t - std::floor(t);
     }
 
+    double amplitude(int64_t p, int64_t q) const {
+        if (gx.empty()) return 1.0;
+        double a = 0.0;
+        for (size_t k = 0; k < gx.size(); ++k) a += gx[k][p] * hq[k][q];
+        return a;
+    }
+
     cd entry(int64_t p, int64_t q) const {
         double t = 6.283185307179586476925286766559 * phase_mod1(p, q);
-        return cd(std::cos(t), std::sin(t));
+        return amplitude(p, q) * cd(std::cos(t), std::sin(t));
     }
 };
 

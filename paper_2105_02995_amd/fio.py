@@ -18,9 +18,11 @@ STATUS = {0: "FIO_OK", 1: "FIO_ERR_ARG", 2: "FIO_ERR_NOMEM", 3: "FIO_ERR_DEVICE"
           7: "FIO_ERR_IO"}
 FIO_C64, FIO_C128 = 0, 1
 FIO_OP_K, FIO_OP_KH = 0, 1
-FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON = 0, 1, 2
+FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON, FIO_PHASE_1D_EX2 = 0, 1, 2, 3
+FIO_MAX_AMP_TERMS = 8
 FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG, FIO_SOLVE_GMRES = 0, 1, 2, 3
-PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON}
+PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON,
+          "1d_ex2": FIO_PHASE_1D_EX2}
 
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
            "fio_autotune", "fio_tune_query",
@@ -41,7 +43,8 @@ class fio_problem(ctypes.Structure):
                 ("eps_hif", ctypes.c_double), ("leaf_bf", ctypes.c_int),
                 ("leaf_h", ctypes.c_int), ("oversample", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("device", ctypes.c_int), ("nthreads", ctypes.c_int),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("amp_sigma2", ctypes.c_double), ("amp_terms", ctypes.c_int),
+                ("amp_x", ctypes.c_double * FIO_MAX_AMP_TERMS), ("amp_eta", ctypes.c_double * FIO_MAX_AMP_TERMS)]
 
 
 class fio_solve_opts(ctypes.Structure):
@@ -149,6 +152,13 @@ def make_problem(d, n, phase="1d_ex1", eps=1e-6, c_div=16.0, device=0, **kw) -> 
     p.d, p.n = d, n
     p.phase = PHASES[phase] if isinstance(phase, str) else int(phase)
     p.c_div, p.eps, p.device = c_div, eps, device
+    amp = kw.pop("amp", None)
+    if amp is not None:  # Example 2 centres [(x_k, eta_k), ...]
+        if len(amp) > FIO_MAX_AMP_TERMS:
+            raise ValueError("at most %d amplitude terms" % FIO_MAX_AMP_TERMS)
+        p.amp_terms = len(amp)
+        for k, (x, e) in enumerate(amp):
+            p.amp_x[k], p.amp_eta[k] = x, e
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -1,0 +1,82 @@
+"""Example 2 (section 6): 1D FIO with a variable amplitude.  K^* alone is a poor
+preconditioner for CG on the normal equations (hundreds to thousands of
+iterations), while the approximate inverse Gd Kd^* needs a few; GMRES with the
+right preconditioner Gd Kd^* likewise.  Against the oracle (dense K, N = 4096)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fio_synth import gaussian_complex
+from paper_2105_02995_amd import fio as F
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from . import gpu_util as G  # noqa: E402
+
+MIX = ((0.2, -0.2), (0.5, 0.2), (0.8, 0.0))
+N = 4096
+_cases = {}
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def case(s2, eps):
+    key = (s2, eps)
+    if key not in _cases:
+        log("building Example 2 plan N=%d sigma2=%g eps=%g" % (N, s2, eps))
+        plan = F.fio_build(F.make_problem(1, N, "1d_ex2", eps=eps, device=0, amp=MIX, amp_sigma2=s2))
+        p = O.OracleProblem(1, N, "1d_ex2", 16.0, amp=MIX, sigma2=s2)
+        K = O.dense_K(p)
+        fh = gaussian_complex((N, 4), 700)
+        _cases[key] = (plan, K, fh, K @ fh)
+    return _cases[key]
+
+
+# sigma2 = 0.05 makes cond(S) = cond(K)^2 about 1e5 here: with tolerances relative to
+# ||S|| the peeled Sd stays positive definite only for eps below 1e-5 (at 1e-4 the
+# build stops with FIO_ERR_NOT_HPD, see test_example2_ill_conditioned_build_fails_cleanly).
+@pytest.mark.parametrize("s2,eps", [(0.1, 1e-5), (0.05, 1e-6)])
+def test_example2_apply_matches_oracle(s2, eps):
+    plan, K, fh, u = case(s2, eps)
+    y = G.apply(plan, F.FIO_OP_K, F.FIO_C128, fh)
+    assert O.rel_err(y, u).max() < eps
+
+
+@pytest.mark.parametrize("s2,eps,max_pre,min_plain", [(0.1, 1e-5, 6, 100), (0.05, 1e-6, 12, 1000)])
+def test_example2_pcg_counts(s2, eps, max_pre, min_plain):
+    plan, K, fh, u = case(s2, eps)
+    x, (its_pre, rr) = G.solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, u, tol=1e-8, maxit=200)
+    err = O.rel_err(x, fh).max()
+    _, (its_plain, rr_plain) = G.solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, u, tol=1e-8, maxit=5000,
+                                       precondition=0)
+    log("Example 2 sigma2=%g eps=%g: PCG with Gd %d iterations (error %.2e), with K^* only %d"
+        % (s2, eps, its_pre, err, its_plain))
+    assert its_pre <= max_pre
+    assert its_plain >= min_plain
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("s2,eps", [(0.1, 1e-5), (0.05, 1e-6)])
+def test_example2_gmres(s2, eps):
+    plan, K, fh, u = case(s2, eps)
+    x, (its, rr) = G.solve(plan, F.FIO_SOLVE_GMRES, F.FIO_C128, u, tol=1e-10, maxit=60)
+    err = O.rel_err(x, fh).max()
+    log("Example 2 sigma2=%g: GMRES with Gd Kd^* %d iterations, residual %.2e, error %.2e" % (s2, its, rr, err))
+    assert rr <= 1e-10
+    assert its <= 15
+    assert err < 1e-6
+
+
+def test_example2_ill_conditioned_build_fails_cleanly():
+    with pytest.raises(F.FioError) as e:
+        F.fio_build(F.make_problem(1, N, "1d_ex2", eps=1e-4, device=0, amp=MIX, amp_sigma2=0.05))
+    assert e.value.status == 4  # FIO_ERR_NOT_HPD

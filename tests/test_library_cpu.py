@@ -155,3 +155,40 @@ def test_2d_host_construction_n32(tmp_path):
     # every DOF is eliminated exactly once or kept in the root
     seen = np.concatenate([nd["r"] for st in f["steps"] for nd in st] + [f["root"]])
     assert np.array_equal(np.sort(seen), np.arange(1024))
+
+
+MIX = ((0.2, -0.2), (0.5, 0.2), (0.8, 0.0))
+
+
+@pytest.mark.parametrize("s2", [0.1, 0.05])
+def test_example2_host_factors(tmp_path, s2):
+    """Example 2 (variable amplitude): the butterfly reaches e_a <= eps, and Gd Kd^*
+    solves within the accuracy the conditioning allows: the peeling and
+    skeletonization tolerances are relative to ||S||, S = Kd^* Kd, so the error of
+    Gd S is about eps cond(S) = eps cond(K)^2 (against the oracle's LU solve)."""
+    n, eps = 512, 1e-6
+    plan, f, _ = _host_plan(tmp_path, n=n, phase="1d_ex2", eps=eps, amp=MIX, amp_sigma2=s2)
+    p = O.OracleProblem(1, n, "1d_ex2", 16.0, amp=MIX, sigma2=s2)
+    K = O.dense_K(p)
+    x = gaussian_complex((n, 4), 13)
+    ea = O.rel_err(FF.apply_K(f, x), K @ x).max()
+    assert ea < eps
+    assert O.rel_err(FF.apply_KH(f, x), K.conj().T @ x).max() < eps
+    fs = gaussian_complex((n, 3), 1001)
+    u = K @ O.dft(fs, 1, n)
+    ref = O.solve_dense(p, u, K)
+    es = O.rel_err(FF.inverse(f, u), ref).max()
+    cond = np.linalg.cond(K)
+    print("sigma2 %.2f: e_a %.2e, e_s %.2e, cond(K) %.1f" % (s2, ea, es, cond))
+    assert es < 10 * eps * cond ** 2, (es, cond)
+
+
+def test_example2_rejects_bad_amplitude_arguments():
+    with pytest.raises(F.FioError):
+        F.fio_build(F.make_problem(1, 256, "1d_ex2", eps=1e-6, device=-1, amp_sigma2=-1.0))
+    with pytest.raises(F.FioError):
+        F.fio_build(F.make_problem(2, 64, "1d_ex2", eps=1e-4, device=-1))
+    p = F.make_problem(1, 256, "1d_ex2", eps=1e-6, device=-1)
+    p.amp_terms = 9
+    with pytest.raises(F.FioError):
+        F.fio_build(p)
