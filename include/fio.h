@@ -131,8 +131,9 @@ typedef enum {
                                residual in FP64 (complex128 factors)                  */
     FIO_SOLVE_PCG = 2,      /* CG on Kd^* Kd x = Kd^* u preconditioned by Gd (section 5) */
     FIO_SOLVE_GMRES = 3     /* restarted GMRES on Kd fhat = u with the right preconditioner
-                               Gd Kd^* (section 7: avoids the squared condition number of
-                               the normal equations); vectors and Gram-Schmidt in FP64,
+                               Gd Kd^* (sections 1 and 7 name GMRES with the factorization
+                               as preconditioner; unlike CG on the normal equations it
+                               does not square cond(K)); vectors and Gram-Schmidt in FP64,
                                operator applies in dtype                                  */
 } fio_solve_mode;
 
