@@ -250,7 +250,9 @@ def main():
     N, B = wl.N, wl.nrhs
     log("workload %s: d=%d n=%d N=%d nrhs=%d eps=%g" % (wl.name, wl.d, wl.n, N, B, wl.eps))
     t0 = time.perf_counter()
-    plan = F.fio_build(F.make_problem(wl.d, wl.n, wl.phase, eps=wl.eps, c_div=wl.c_div, device=0))
+    # large 2D builds take minutes on the host: print their progress
+    plan = F.fio_build(F.make_problem(wl.d, wl.n, wl.phase, eps=wl.eps, c_div=wl.c_div, device=0,
+                                      verbose=1 if wl.N * wl.d >= 2 * 65536 else 0))
     build_s = time.perf_counter() - t0
     stats = F.fio_plan_stats(plan)
     log("built in %.1f s: bf_nnz=%d hif_nnz=%d root=%d device_bytes=%.2f GB" % (

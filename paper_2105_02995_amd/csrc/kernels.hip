@@ -161,23 +161,24 @@ template <class R, class P> struct KWalk {
     int q, e, k;
 };
 
+// Zero-filled device memory (static storage is zero-initialised): past the last k
+// the factor operand is loaded from here, so it is exactly zero without any select
+// on a loaded value.  64 double2 cover the 32 rows of the widest tile.
+__device__ double2 g_zero_rows[64];
+
 template <class R, int MT, int NT, class P>
 __device__ __forceinline__ void frag_load(Frag<R, MT, NT> &f, KWalk<R, P> &w, int K, int r_in,
                                           const P *__restrict__ xb, const Off4 &off, int64_t ld,
-                                          const typename MF<R>::C *__restrict__ Ao, int r_out,
-                                          const int (&colc)[NT], const int (&rowc)[MT]) {
+                                          int r_out, const int (&colc)[NT], const int (&rowc)[MT]) {
     using C = typename MF<R>::C;
-    const C zero = C{0, 0};
     const bool kv = w.k < K;
+    // past the last k: input from a valid row (finite values), factor from zeros
     const P *xrow = kv ? w.xp : xb + off.o0;
-    const C *acol = kv ? w.ap : Ao;
+    const C *acol = kv ? w.ap : reinterpret_cast<const C *>(g_zero_rows);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) f.x[nt] = xrow[colc[nt]];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const C v = acol[rowc[mt]];
-        f.a[mt] = kv ? v : zero;
-    }
+    for (int mt = 0; mt < MT; ++mt) f.a[mt] = acol[kv ? rowc[mt] : mt * 16 + (threadIdx.x & 15)];
     w.k += 4;
     w.ap += 4 * (int64_t)r_out;
     w.e += 4;
@@ -237,20 +238,19 @@ __device__ __forceinline__ void mfma_block(Acc<R, MT, NT> &acc, const typename M
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) rowc[mt] = min(mrow0 + mt * 16 + li, r_out - 1);
     KWalk<R, P> w;
-    w.q = 0;
-    w.e = lk;
-    while (w.e >= r_in) { w.e -= r_in; ++w.q; }
     w.k = lk;
+    w.q = lk / r_in;
+    w.e = lk - w.q * r_in;
     w.ap = Ao + (int64_t)lk * r_out;
     w.xp = xb + off(w.q) + (int64_t)w.e * ld;
     Frag<R, MT, NT> f[STAGE_PF];
 #pragma unroll
-    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, Ao, r_out, colc, rowc);
+    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, r_out, colc, rowc);
     for (int k0 = 0; k0 < K; k0 += 4 * STAGE_PF) {
 #pragma unroll
         for (int j = 0; j < STAGE_PF; ++j) {
             if (k0 + 4 * j >= K) break;  // wave-uniform
-            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, Ao, r_out, colc, rowc);
+            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, r_out, colc, rowc);
             acc.mma(f[j]);
         }
     }
@@ -659,21 +659,16 @@ template <class R, int MT, int NT> struct GWalk {
 template <class R, int MT, int NT>
 __device__ __forceinline__ void gfrag_load(Frag<R, MT, NT> &f, GWalk<R, MT, NT> &w, int kend,
                                            const typename MF<R>::C *__restrict__ xb, int64_t ldx,
-                                           const int32_t *__restrict__ kin,
-                                           const typename MF<R>::C *__restrict__ Ao, int ld,
+                                           const int32_t *__restrict__ kin, int ld,
                                            const int (&colc)[NT], const int (&rowc)[MT]) {
     using C = typename MF<R>::C;
-    const C zero = C{0, 0};
     const bool kv = w.k < kend;
     const C *xrow = xb + (int64_t)w.gnext * ldx;
-    const C *acol = kv ? w.ap : Ao;
+    const C *acol = kv ? w.ap : reinterpret_cast<const C *>(g_zero_rows);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) f.x[nt] = xrow[colc[nt]];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const C v = acol[rowc[mt]];
-        f.a[mt] = kv ? v : zero;
-    }
+    for (int mt = 0; mt < MT; ++mt) f.a[mt] = acol[kv ? rowc[mt] : mt * 16 + (threadIdx.x & 15)];
     w.k += 4;
     w.ap += 4 * (int64_t)ld;
     w.gnext = kin[min(w.k, kend - 1)];
@@ -732,12 +727,12 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
         w.gnext = kin[min(w.k, kend - 1)];
         Frag<R, MT, NT> f[STAGE_PF];
 #pragma unroll
-        for (int j = 0; j + 1 < STAGE_PF; ++j) gfrag_load(f[j], w, kend, xb, nrhs, kin, S, ld, colc, rowc);
+        for (int j = 0; j + 1 < STAGE_PF; ++j) gfrag_load(f[j], w, kend, xb, nrhs, kin, ld, colc, rowc);
         for (int k0 = kbeg; k0 < kend; k0 += 4 * STAGE_PF) {
 #pragma unroll
             for (int j = 0; j < STAGE_PF; ++j) {
                 if (k0 + 4 * j >= kend) break;  // wave-uniform
-                gfrag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, kend, xb, nrhs, kin, S, ld, colc, rowc);
+                gfrag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, kend, xb, nrhs, kin, ld, colc, rowc);
                 acc.mma(f[j]);
             }
         }
