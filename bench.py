@@ -30,9 +30,13 @@ PEAK_HBM_GBS = 8000.0
 # FETCH_SIZE (x2) and WRITE_SIZE (x1) scaled by a 1 GiB copy kernel (summaries under
 # profiles/), valid only for the kernel source they were measured on.
 TRAFFIC = {
+    "k_stage2_mfma<float, 2, 4>": {
+        "bytes": (113834.49 * 2 + 92160.00) * 1024,
+        "kernels_sha256": "7abf2e251e379eee70ba675b055c77d44ebe2978238813ba19b27129cce007c5",
+    },
     "k_stage2_mfma<float, 2, 2>": {
-        "bytes": (114177.61 * 2 + 100352.00) * 1024,
-        "kernels_sha256": "4374f1a4aaf09e0432b94da07c2529c35c6dd4e0bbd81eefa67e0387a2e711f0",
+        "bytes": (115624.39 * 2 + 98304.00) * 1024,
+        "kernels_sha256": "7abf2e251e379eee70ba675b055c77d44ebe2978238813ba19b27129cce007c5",
     },
 }
 
