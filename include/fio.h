@@ -89,7 +89,8 @@ typedef struct {
     uint64_t seed;          /* seed of the peeling probes                              */
     int device;             /* HIP device ordinal, or -1 for a host-only plan that can
                                be saved and loaded later but not applied              */
-    int nthreads;           /* host threads for the build; 0 -> hardware concurrency  */
+    int nthreads;           /* host threads for the build; 0 -> OMP_NUM_THREADS, else
+                               the CPUs of the process's affinity mask                */
     int verbose;            /* nonzero: fio_build prints one progress line per phase
                                and per tree level to stderr                           */
     /* Example 2 amplitude (FIO_PHASE_1D_EX2 only; not stored by fio_save).  The paper

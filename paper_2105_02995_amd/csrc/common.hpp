@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <sched.h>
+#include <cstdlib>
 #include <thread>
 #include <vector>
 
@@ -23,10 +25,25 @@ struct Error : std::runtime_error {
 
 [[noreturn]] inline void fail(fio_status s, const std::string &msg) { throw Error(s, msg); }
 
+// Host threads of the build: the request, else OMP_NUM_THREADS, else the CPUs this
+// process may run on (its affinity mask, which follows container CPU sets), else the
+// hardware count.  Computed once.
 inline int hw_threads(int requested) {
     if (requested > 0) return requested;
-    unsigned h = std::thread::hardware_concurrency();
-    return h ? (int)h : 4;
+    static const int dflt = [] {
+        if (const char *e = std::getenv("OMP_NUM_THREADS")) {
+            const int v = std::atoi(e);
+            if (v > 0) return v;
+        }
+        cpu_set_t set;
+        if (sched_getaffinity(0, sizeof(set), &set) == 0) {
+            const int c = CPU_COUNT(&set);
+            if (c > 0) return c;
+        }
+        const unsigned h = std::thread::hardware_concurrency();
+        return h ? (int)h : 4;
+    }();
+    return dflt;
 }
 
 // Run fn(i) for i in [0, n) on nthreads threads (dynamic scheduling).
