@@ -10,11 +10,14 @@
 
 namespace fio {
 
+// Progress line on stderr, prefixed with the seconds since the first line.
 void progress(bool on, const char *fmt, ...) {
     if (!on) return;
+    static const auto t0 = std::chrono::steady_clock::now();
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     va_list ap;
     va_start(ap, fmt);
-    std::fprintf(stderr, "[fio_build] ");
+    std::fprintf(stderr, "[fio_build %8.2fs] ", el);
     std::vfprintf(stderr, fmt, ap);
     std::fprintf(stderr, "\n");
     std::fflush(stderr);

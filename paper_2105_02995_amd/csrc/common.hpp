@@ -46,11 +46,24 @@ inline int hw_threads(int requested) {
     return dflt;
 }
 
+// Threads currently running parallel_for work (callers included), so that a loop
+// nested in another uses only the cores the outer one leaves idle.
+inline std::atomic<int> &pool_active() {
+    static std::atomic<int> n(0);
+    return n;
+}
+inline bool &pool_member() {
+    thread_local bool in = false;
+    return in;
+}
+
 // Run fn(i) for i in [0, n) on nthreads threads (dynamic scheduling).
 template <class Fn>
 void parallel_for(int64_t n, int nthreads, Fn &&fn) {
     if (n <= 0) return;
-    int nt = (int)std::min<int64_t>(hw_threads(nthreads), n);
+    const int hw = hw_threads(nthreads);
+    const int avail = hw - pool_active().load() + (pool_member() ? 1 : 0);
+    int nt = (int)std::min<int64_t>(std::min(hw, std::max(1, avail)), n);
     if (nt <= 1) {
         for (int64_t i = 0; i < n; ++i) fn(i);
         return;
@@ -58,7 +71,10 @@ void parallel_for(int64_t n, int nthreads, Fn &&fn) {
     std::atomic<int64_t> next(0);
     std::exception_ptr err = nullptr;
     std::atomic<bool> failed(false);
-    auto work = [&]() {
+    auto work = [&](bool spawned) {
+        const bool was = pool_member();
+        if (spawned || !was) pool_active().fetch_add(1);
+        pool_member() = true;
         try {
             for (;;) {
                 int64_t i = next.fetch_add(1);
@@ -68,13 +84,26 @@ void parallel_for(int64_t n, int nthreads, Fn &&fn) {
         } catch (...) {
             if (!failed.exchange(true)) err = std::current_exception();
         }
+        pool_member() = was;
+        if (spawned || !was) pool_active().fetch_sub(1);
     };
     std::vector<std::thread> th;
     th.reserve(nt - 1);
-    for (int t = 0; t < nt - 1; ++t) th.emplace_back(work);
-    work();
+    for (int t = 0; t < nt - 1; ++t) th.emplace_back(work, true);
+    work(false);
     for (auto &t : th) t.join();
     if (err) std::rethrow_exception(err);
+}
+
+// parallel_for for the dense kernels of a single large matrix: runs serially when
+// the work (in complex multiply-adds) is too small to pay for the threads.
+template <class Fn>
+void par_cols(int64_t n, double work, Fn &&fn) {
+    if (work < 4.0e5 || n < 2) {
+        for (int64_t i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    parallel_for(n, 0, fn);
 }
 
 // Progress line on stderr (build phases); flushed so a watcher sees it at once.

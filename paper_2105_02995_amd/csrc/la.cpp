@@ -17,35 +17,38 @@ void gemm_acc(Mat &C, const Mat &A, const Mat &B, cd alpha, char opA, char opB) 
     const int n = (opB == 'N') ? B.n : B.m;
     const int kb = (opB == 'N') ? B.m : B.n;
     if (k != kb || C.m != m || C.n != n) fail(FIO_ERR_ARG, "gemm: shape mismatch");
+    const double work = (double)m * n * k;
     if (opA == 'N' && opB == 'N') {
-        for (int j = 0; j < n; ++j) {
-            cd *c = C.col(j);
+        par_cols(n, work, [&](int64_t j) {
+            cd *c = C.col((int)j);
             for (int p = 0; p < k; ++p) {
-                cd b = alpha * B(p, j);
+                cd b = alpha * B(p, (int)j);
                 if (b == cd(0)) continue;
                 const cd *a = A.col(p);
                 for (int i = 0; i < m; ++i) c[i] += a[i] * b;
             }
-        }
+        });
         return;
     }
     if (opA == 'C' && opB == 'N') {
-        for (int j = 0; j < n; ++j)
+        par_cols(n, work, [&](int64_t j) {
             for (int i = 0; i < m; ++i) {
                 const cd *a = A.col(i);
-                const cd *b = B.col(j);
+                const cd *b = B.col((int)j);
                 cd s = 0;
                 for (int p = 0; p < k; ++p) s += std::conj(a[p]) * b[p];
-                C(i, j) += alpha * s;
+                C(i, (int)j) += alpha * s;
             }
+        });
         return;
     }
-    for (int j = 0; j < n; ++j)
+    par_cols(n, work, [&](int64_t j) {
         for (int i = 0; i < m; ++i) {
             cd s = 0;
-            for (int p = 0; p < k; ++p) s += opget(A, opA, i, p) * opget(B, opB, p, j);
-            C(i, j) += alpha * s;
+            for (int p = 0; p < k; ++p) s += opget(A, opA, i, p) * opget(B, opB, p, (int)j);
+            C(i, (int)j) += alpha * s;
         }
+    });
 }
 
 Mat matmul(const Mat &A, const Mat &B, char opA, char opB) {
@@ -120,14 +123,14 @@ QRP cpqr(Mat A, double tol_abs, int max_rank) {
         f.w0.push_back(w0);
         f.wn2.push_back(wn2);
         if (wn2 > 0) {
-            for (int j = k + 1; j < n; ++j) {
-                cd *v = A.col(j) + k;
+            par_cols(n - k - 1, 2.0 * (m - k) * (n - k - 1), [&](int64_t jj) {
+                cd *v = A.col(k + 1 + (int)jj) + k;
                 cd s = std::conj(w0) * v[0];
                 for (int i = 1; i < m - k; ++i) s += std::conj(x[i]) * v[i];
                 cd t = 2.0 * s / wn2;
                 v[0] -= t * w0;
                 for (int i = 1; i < m - k; ++i) v[i] -= t * x[i];
-            }
+            });
         }
         x[0] = -ph * alpha;  // R_kk; x[1:] keeps the reflector tail
         for (int j = k + 1; j < n; ++j) {
@@ -148,18 +151,19 @@ Mat qr_q(const QRP &f, int k) {
     const int m = f.A.m;
     Mat Q(m, k);
     for (int c = 0; c < k; ++c) Q(c, c) = 1.0;
-    for (int r = k - 1; r >= 0; --r) {
-        if (f.wn2[r] == 0) continue;
-        const cd *tail = f.A.col(r) + r;  // tail[1:] are reflector entries
-        for (int c = 0; c < k; ++c) {
-            cd *v = Q.col(c) + r;
+    // columns of Q are independent: each applies the reflectors in turn
+    par_cols(k, 2.0 * m * k * k, [&](int64_t c) {
+        for (int r = k - 1; r >= 0; --r) {
+            if (f.wn2[r] == 0) continue;
+            const cd *tail = f.A.col(r) + r;  // tail[1:] are reflector entries
+            cd *v = Q.col((int)c) + r;
             cd s = std::conj(f.w0[r]) * v[0];
             for (int i = 1; i < m - r; ++i) s += std::conj(tail[i]) * v[i];
             cd t = 2.0 * s / f.wn2[r];
             v[0] -= t * f.w0[r];
             for (int i = 1; i < m - r; ++i) v[i] -= t * tail[i];
         }
-    }
+    });
     return Q;
 }
 
@@ -197,45 +201,61 @@ ColumnID column_id(const Mat &A, double tol_rel, int fixed_rank, int max_rank) {
     out.skel.assign(f.perm.begin(), f.perm.begin() + k);
     out.redund.assign(f.perm.begin() + k, f.perm.end());
     out.T = Mat(k, n - k);
-    // T = R11^{-1} R12 by back substitution.
-    for (int j = 0; j < n - k; ++j) {
-        for (int i = k - 1; i >= 0; --i) {
-            cd s = f.A(i, k + j);
-            for (int p = i + 1; p < k; ++p) s -= f.A(i, p) * out.T(p, j);
-            out.T(i, j) = s / f.A(i, i);
+    // T = R11^{-1} R12 by back substitution, column by column (independent columns;
+    // column operations on R11 are contiguous).
+    par_cols(n - k, (double)k * k * (n - k) / 2.0, [&](int64_t jj) {
+        const int j = (int)jj;
+        cd *t = out.T.col(j);
+        const cd *r12 = f.A.col(k + j);
+        for (int i = 0; i < k; ++i) t[i] = r12[i];
+        for (int p = k - 1; p >= 0; --p) {
+            t[p] /= f.A(p, p);
+            const cd tp = t[p];
+            const cd *rp = f.A.col(p);
+            for (int i = 0; i < p; ++i) t[i] -= rp[i] * tp;
         }
-    }
+    });
     return out;
 }
 
 bool cholesky_lower(Mat &A) {
+    // right-looking, column by column: scale column j, then update the trailing
+    // columns with contiguous column operations (parallel for large matrices)
     const int n = A.n;
     for (int j = 0; j < n; ++j) {
-        double d = A(j, j).real();
-        for (int p = 0; p < j; ++p) d -= std::norm(A(j, p));
-        if (!(d > 0)) return false;
-        d = std::sqrt(d);
-        A(j, j) = d;
-        for (int i = j + 1; i < n; ++i) {
-            cd s = A(i, j);
-            for (int p = 0; p < j; ++p) s -= A(i, p) * std::conj(A(j, p));
-            A(i, j) = s / d;
-        }
-        for (int i = 0; i < j; ++i) A(i, j) = 0;
+        const double d2 = A(j, j).real();
+        if (!(d2 > 0)) return false;
+        const double d = std::sqrt(d2);
+        cd *cj = A.col(j);
+        cj[j] = d;
+        for (int i = j + 1; i < n; ++i) cj[i] /= d;
+        par_cols(n - j - 1, (double)(n - j) * (n - j), [&](int64_t t) {
+            const int c = j + 1 + (int)t;
+            const cd f = std::conj(cj[c]);
+            cd *cc = A.col(c);
+            for (int i = c; i < n; ++i) cc[i] -= cj[i] * f;
+        });
     }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < j; ++i) A(i, j) = 0;
     return true;
 }
 
 Mat tri_lower_inverse(const Mat &L) {
+    // column c of L^{-1} solves L x = e_c; columns are independent
     const int n = L.n;
     Mat X(n, n);
-    for (int c = 0; c < n; ++c) {
-        for (int i = c; i < n; ++i) {
-            cd s = (i == c) ? cd(1.0) : cd(0.0);
-            for (int p = c; p < i; ++p) s -= L(i, p) * X(p, c);
-            X(i, c) = s / L(i, i);
+    par_cols(n, (double)n * n * n / 6.0, [&](int64_t cc) {
+        const int c = (int)cc;
+        cd *x = X.col(c);
+        x[c] = 1.0;
+        for (int p = c; p < n; ++p) {
+            x[p] /= L(p, p);
+            const cd xp = x[p];
+            const cd *lp = L.col(p);
+            for (int i = p + 1; i < n; ++i) x[i] -= lp[i] * xp;
         }
-    }
+    });
     return X;
 }
 
