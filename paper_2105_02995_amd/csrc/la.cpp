@@ -42,6 +42,20 @@ void gemm_acc(Mat &C, const Mat &A, const Mat &B, cd alpha, char opA, char opB) 
         });
         return;
     }
+    if (opA == 'N' && (opB == 'C' || opB == 'T')) {
+        // C(:, j) += alpha * sum_p A(:, p) op(B)(p, j), op(B)(p, j) = (conj) B(j, p)
+        par_cols(n, work, [&](int64_t j) {
+            cd *c = C.col((int)j);
+            for (int p = 0; p < k; ++p) {
+                const cd bj = B((int)j, p);
+                const cd b = alpha * (opB == 'C' ? std::conj(bj) : bj);
+                if (b == cd(0)) continue;
+                const cd *a = A.col(p);
+                for (int i = 0; i < m; ++i) c[i] += a[i] * b;
+            }
+        });
+        return;
+    }
     par_cols(n, work, [&](int64_t j) {
         for (int i = 0; i < m; ++i) {
             cd s = 0;
