@@ -100,6 +100,13 @@ typedef struct {
     int amp_terms;          /* number of terms, 0..FIO_MAX_AMP_TERMS                   */
     double amp_x[FIO_MAX_AMP_TERMS];    /* centres in x, in [0, 1)                     */
     double amp_eta[FIO_MAX_AMP_TERMS];  /* centres in xi/n, in [-1/2, 1/2)             */
+    /* A skeletonization pivot block (or the top-level block) that is not positive
+     * definite, because the approximation error of Sd exceeds its smallest eigenvalue
+     * (ill-conditioned K), is factored with a diagonal shift (from 1e-3 eps_hif ||S||_2,
+     * doubled until it is), which keeps Gd Hermitian positive definite: a
+     * preconditioner-quality inverse on those nodes.  strict_hpd = 1 makes the build
+     * fail with FIO_ERR_NOT_HPD instead.                                           */
+    int strict_hpd;
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",
@@ -177,6 +184,8 @@ typedef struct {
     int64_t device_bytes;          /* device memory held by the factors                */
     int64_t workspace_bytes;       /* device workspace per right-hand side             */
     double build_seconds;          /* wall time of fio_build                           */
+    int hif_shifted;               /* pivot blocks given a diagonal shift (see strict_hpd;
+                                      not stored by fio_save)                          */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

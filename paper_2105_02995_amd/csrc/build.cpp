@@ -101,9 +101,10 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     po.seed = p.seed ^ 0x9EE1ULL;
     po.nthreads = p.nthreads;
     po.verbose = vb;
+    po.allow_shift = p.strict_hpd == 0;
     out.hif = (p.d == 1) ? build_hif_1d(A, B.N, po, p.eps_hif) : build_hif_2d(A, p.n, po, p.eps_hif);
-    progress(vb, "inverse factors done: %zu steps, root %zu (%.1fs)", out.hif.steps.size(),
-             out.hif.root_idx.size(),
+    progress(vb, "inverse factors done: %zu steps, root %zu, %d shifted pivot blocks (%.1fs)", out.hif.steps.size(),
+             out.hif.root_idx.size(), out.hif.shifted,
              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     out.fwd = std::move(B.fwd);
     out.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

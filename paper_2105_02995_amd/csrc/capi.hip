@@ -543,6 +543,7 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
             for (auto &nd : st.nodes) o->hif_nnz += (int64_t)nd.T.a.size() + nd.Linv.a.size() + nd.M.a.size();
         o->root_size = (int)h.hif.root_idx.size();
         o->max_rank_h = h.hif.max_rank_h;
+        o->hif_shifted = h.hif.shifted;
         o->device_bytes = p->device_bytes;
         o->workspace_bytes = (int64_t)(2 * p->max_coef + 12 * h.N + 2 * (int64_t)h.hif.root_idx.size()) * 16;
         o->build_seconds = h.build_seconds;

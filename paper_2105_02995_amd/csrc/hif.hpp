@@ -38,6 +38,7 @@ struct HifFactors {
     std::vector<int> root_idx;      // S_0
     Mat A0inv;                      // inverse of the top-level block on S_0 (FP64)
     int max_rank_h = 0;             // largest off-diagonal rank of Sd
+    int shifted = 0;                // pivot blocks (and root) that needed a diagonal shift
 };
 
 // y = A x for nrhs vectors stored point-major (entry (e, b) at e*nrhs + b).
@@ -51,6 +52,11 @@ struct PeelOptions {
     uint64_t seed = 7;
     int nthreads = 0;
     bool verbose = false;
+    // Pivot blocks that are not positive definite (the approximation error of Sd
+    // exceeds their smallest eigenvalue) get a diagonal shift, from 1e-3 eps_hif ||S||_2
+    // doubled until positive definite, when true; the build fails with
+    // FIO_ERR_NOT_HPD when false.
+    bool allow_shift = true;
 };
 
 // 1D HODLR peeling of a Hermitian operator given only by products (section 3),

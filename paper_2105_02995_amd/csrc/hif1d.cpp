@@ -1,4 +1,5 @@
 // 1D: HODLR peeling (section 3) and recursive-skeletonization inverse (section 4).
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 
@@ -147,7 +148,7 @@ struct Active {
 };
 
 // Skeletonize one node: returns its factor and replaces st by its skeleton part.
-HifNode skeletonize(Active &st, const Mat &Ubar, double eps) {
+HifNode skeletonize(Active &st, const Mat &Ubar, double eps, double shift0, std::atomic<int> &nshift) {
     const int n = (int)st.I.size();
     HifNode nd;
     std::vector<int> sk, rd;
@@ -185,7 +186,9 @@ HifNode skeletonize(Active &st, const Mat &Ubar, double eps) {
     gemm_acc(Ats, Ass, T, -1.0);
     // Gaussian elimination (eq_sk_3) with Atilde_rr = L L^*.
     Mat Lf = Atr;
-    if (!cholesky_lower(Lf)) fail(FIO_ERR_NOT_HPD, "skeletonization pivot block is not HPD");
+    const double sh = cholesky_lower_shifted(Lf, shift0);
+    if (sh < 0) fail(FIO_ERR_NOT_HPD, "skeletonization pivot block is not HPD");
+    if (sh > 0) nshift.fetch_add(1);
     nd.Linv = tri_lower_inverse(Lf);
     nd.M = matmul(Ats, nd.Linv, 'N', 'C');  // Atilde_sr L^{-*}
     Mat Abar = Ass;
@@ -249,6 +252,8 @@ HifFactors build_hif_1d(const BlockApply &A, int64_t N, const PeelOptions &po, d
     F.N = N;
     const double normS = power_norm(A, N, 12, po.seed ^ 0x5EEDULL);
     Hodlr1D H = peel_1d(A, N, po, normS, F.max_rank_h);
+    const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
+    std::atomic<int> nshift(0);
     const int64_t nleaf = N / H.mh;
     std::vector<Active> st(nleaf);
     for (int64_t b = 0; b < nleaf; ++b) {
@@ -276,7 +281,7 @@ HifFactors build_hif_1d(const BlockApply &A, int64_t N, const PeelOptions &po, d
                         Ubar(r0 + k, (int)c) = std::conj(Ua((int)(I[c] - start), k));
                 r0 += Ua.n;
             }
-            step.nodes[v] = skeletonize(st[v], Ubar, eps_hif);
+            step.nodes[v] = skeletonize(st[v], Ubar, eps_hif, shift0, nshift);
         });
         F.steps.push_back(std::move(step));
         std::vector<Active> up(nn / 2);
@@ -290,8 +295,11 @@ HifFactors build_hif_1d(const BlockApply &A, int64_t N, const PeelOptions &po, d
     // Root: the remaining active DOFs S_0 (st has one entry after the merge of level 1).
     F.root_idx = st[0].I;
     if (!F.root_idx.empty()) {
-        if (!hpd_inverse(st[0].A, F.A0inv)) fail(FIO_ERR_NOT_HPD, "top-level block is not HPD");
+        const double sh = hpd_inverse_shifted(st[0].A, F.A0inv, shift0);
+        if (sh < 0) fail(FIO_ERR_NOT_HPD, "top-level block is not HPD");
+        if (sh > 0) nshift.fetch_add(1);
     }
+    F.shifted = nshift.load();
     return F;
 }
 

@@ -5,6 +5,7 @@
 // DOFs are the Omega points in Z-order ("tree order"), so every quadtree cell at
 // level l is a contiguous range and its Morton index is the prefix of the DOF index.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -384,7 +385,8 @@ struct NodeOut {
 
 // Skeletonize the DOFs I given the stacked row block Ubar and the current
 // diagonal block A_II; same algebra as the 1D case (eq_sk, eq_sk_3).
-NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, double eps) {
+NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, double eps, double shift0,
+               std::atomic<int> &nshift) {
     NodeOut out;
     const int n = (int)I.size();
     std::vector<int> sk, rd;
@@ -420,7 +422,9 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
     Mat Ats = Asr;
     gemm_acc(Ats, Ass, T, -1.0);
     Mat Lf = Atr;
-    if (!cholesky_lower(Lf)) fail(FIO_ERR_NOT_HPD, "2D skeletonization pivot block is not HPD");
+    const double sh = cholesky_lower_shifted(Lf, shift0);
+    if (sh < 0) fail(FIO_ERR_NOT_HPD, "2D skeletonization pivot block is not HPD");
+    if (sh > 0) nshift.fetch_add(1);
     out.nd.Linv = tri_lower_inverse(Lf);
     out.nd.M = matmul(Ats, out.nd.Linv, 'N', 'C');
     out.delta = Mat(ns, ns);
@@ -459,6 +463,8 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
     F.N = g.N;
     const double normS = power_norm(A, g.N, 12, po.seed ^ 0x5EEDULL);
     Hmat2D H = peel_2d(A, g, po, normS);
+    const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
+    std::atomic<int> nshift(0);
     F.max_rank_h = H.max_rank;
     Active2D act(H);
     // active DOFs per cell at the current level
@@ -480,7 +486,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                 if (!Bnear.empty()) blocks.push_back(act.sub(Bnear, I));
                 far_rows(H, l, c, I, blocks);
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif);
+                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift);
             });
             HifStep step;
             for (int64_t c = 0; c < ncell; ++c) {
@@ -559,7 +565,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                     if (c1 == c2) break;
                 }
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif);
+                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift);
             });
             HifStep step;
             std::vector<std::vector<int>> remain(ncell);
@@ -595,8 +601,11 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                 A0(i, j) = v;
                 A0(j, i) = std::conj(v);
             }
-        if (!hpd_inverse(A0, F.A0inv)) fail(FIO_ERR_NOT_HPD, "2D top-level block is not HPD");
+        const double sh = hpd_inverse_shifted(A0, F.A0inv, shift0);
+        if (sh < 0) fail(FIO_ERR_NOT_HPD, "2D top-level block is not HPD");
+        if (sh > 0) nshift.fetch_add(1);
     }
+    F.shifted = nshift.load();
     return F;
 }
 

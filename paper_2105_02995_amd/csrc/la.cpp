@@ -299,6 +299,34 @@ Mat pinv(const Mat &A, double tol_rel) {
     return out;
 }
 
+double cholesky_lower_shifted(Mat &A, double delta0) {
+    Mat work = A;
+    if (cholesky_lower(work)) {
+        A = std::move(work);
+        return 0.0;
+    }
+    if (!(delta0 > 0)) return -1.0;
+    double delta = delta0;
+    for (int t = 0; t < 60; ++t, delta *= 2) {
+        work = A;
+        for (int i = 0; i < work.n; ++i) work(i, i) += delta;
+        if (cholesky_lower(work)) {
+            A = std::move(work);
+            return delta;
+        }
+    }
+    return -1.0;
+}
+
+double hpd_inverse_shifted(const Mat &A, Mat &inv, double delta0) {
+    Mat L = A;
+    const double sh = cholesky_lower_shifted(L, delta0);
+    if (sh < 0) return sh;
+    Mat Li = tri_lower_inverse(L);
+    inv = matmul(Li, Li, 'C', 'N');
+    return sh;
+}
+
 bool hpd_inverse(const Mat &A, Mat &inv) {
     Mat L = A;
     if (!cholesky_lower(L)) return false;

@@ -74,5 +74,12 @@ Mat orth(const Mat &Y, double tol_abs, int max_rank);
 Mat pinv(const Mat &A, double tol_rel = 1e-14);
 // Hermitian positive definite inverse via Cholesky; false if not HPD.
 bool hpd_inverse(const Mat &A, Mat &inv);
+// Cholesky (lower, in place) of a Hermitian matrix that should be positive definite
+// but may not be, because its approximation error exceeds its smallest eigenvalue:
+// on failure A + delta I is factored instead, delta doubling from delta0.  Returns
+// the shift used (0 if none) or -1 (failure, or delta0 <= 0 and A not HPD).
+double cholesky_lower_shifted(Mat &A, double delta0);
+// inv = (A + delta I)^{-1} with the shift of cholesky_lower_shifted; returns it (or -1).
+double hpd_inverse_shifted(const Mat &A, Mat &inv, double delta0);
 
 }  // namespace fio

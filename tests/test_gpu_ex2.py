@@ -42,8 +42,8 @@ def case(s2, eps):
 
 
 # sigma2 = 0.05 makes cond(S) = cond(K)^2 about 1e5 here: with tolerances relative to
-# ||S|| the peeled Sd stays positive definite only for eps below 1e-5 (at 1e-4 the
-# build stops with FIO_ERR_NOT_HPD, see test_example2_ill_conditioned_build_fails_cleanly).
+# ||S|| the peeled Sd stays positive definite only for eps below 1e-5 (at 1e-4 pivot
+# blocks need a shift, see test_example2_ill_conditioned_build_shifts_or_fails_cleanly).
 @pytest.mark.parametrize("s2,eps", [(0.1, 1e-5), (0.05, 1e-6)])
 def test_example2_apply_matches_oracle(s2, eps):
     plan, K, fh, u = case(s2, eps)
@@ -76,7 +76,18 @@ def test_example2_gmres(s2, eps):
     assert err < 1e-6
 
 
-def test_example2_ill_conditioned_build_fails_cleanly():
+def test_example2_ill_conditioned_build_shifts_or_fails_cleanly():
+    """sigma2 = 0.05 at eps = 1e-4: with strict_hpd the build stops with
+    FIO_ERR_NOT_HPD; by default the non-positive pivot blocks are shifted and PCG
+    with the resulting Gd still converges in tens of iterations (K^* alone: ~1800)."""
     with pytest.raises(F.FioError) as e:
-        F.fio_build(F.make_problem(1, N, "1d_ex2", eps=1e-4, device=0, amp=MIX, amp_sigma2=0.05))
+        F.fio_build(F.make_problem(1, N, "1d_ex2", eps=1e-4, device=0, amp=MIX, amp_sigma2=0.05, strict_hpd=1))
     assert e.value.status == 4  # FIO_ERR_NOT_HPD
+    plan = F.fio_build(F.make_problem(1, N, "1d_ex2", eps=1e-4, device=0, amp=MIX, amp_sigma2=0.05))
+    assert F.fio_plan_stats(plan)["hif_shifted"] > 0
+    _, K, fh, u = case(0.05, 1e-6)
+    x, (its, rr) = G.solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, u, tol=1e-8, maxit=200)
+    log("Example 2 sigma2=0.05 eps=1e-4 (shifted pivots): PCG with Gd %d iterations, error %.2e"
+        % (its, O.rel_err(x, fh).max()))
+    assert its <= 40
+    assert O.rel_err(x, fh).max() < 1e-5

@@ -192,3 +192,26 @@ def test_example2_rejects_bad_amplitude_arguments():
     p.amp_terms = 9
     with pytest.raises(F.FioError):
         F.fio_build(p)
+
+
+def test_example2_ill_conditioned_pivots_are_shifted(tmp_path):
+    """sigma2 = 0.05, eps = 1e-4: cond(S) = cond(K)^2 is about 1e5, so pivot blocks of
+    the peeled Sd are not positive definite.  With strict_hpd the build stops with
+    FIO_ERR_NOT_HPD; by default those blocks get a small diagonal shift and Gd stays
+    a preconditioner: CG on K^*K with Gd converges in a few tens of iterations (the
+    eps ||S|| truncation bounds its quality at this conditioning), where K^* alone
+    needs well over a thousand (oracle, dense K)."""
+    n, eps, s2 = 4096, 1e-4, 0.05
+    with pytest.raises(F.FioError) as e:
+        F.fio_build(F.make_problem(1, n, "1d_ex2", eps=eps, device=-1, amp=MIX, amp_sigma2=s2, strict_hpd=1))
+    assert e.value.status == 4
+    plan, f, _ = _host_plan(tmp_path, n=n, phase="1d_ex2", eps=eps, amp=MIX, amp_sigma2=s2)
+    shifted = F.fio_plan_stats(plan)["hif_shifted"]
+    assert shifted > 0
+    p = O.OracleProblem(1, n, "1d_ex2", 16.0, amp=MIX, sigma2=s2)
+    K = O.dense_K(p)
+    b = K @ gaussian_complex(n, 1002)
+    gd_nat = lambda r: FF.from_tree(f, FF.gd(f, FF.to_tree(f, r)))  # noqa: E731
+    x, its = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, b, tol=1e-8, maxit=500, precond=gd_nat)
+    print("shifted %d pivot blocks; PCG with Gd: %d iterations" % (shifted, its))
+    assert its <= 40
