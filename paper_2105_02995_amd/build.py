@@ -53,6 +53,13 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, LIB)
+    # the C ABI from plain C: a file-to-file solve (HIP runtime C API for device memory)
+    ex = os.path.join(HERE, "fio_solve_file")
+    _run(["gcc", "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+          "-I" + os.path.join(ROCM, "include"), os.path.join(HERE, "examples", "solve_file.c"),
+          "-L" + HERE, "-lfio", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
+          "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", ex + ".tmp"])
+    os.replace(ex + ".tmp", ex)
     # measurement aid (copy kernel of known size, MFMA rates)
     cal = os.path.join(HERE, "fio_calibrate")
     _run([HIPCC, "-O3", "-std=c++17", *HIP_FLAGS, os.path.join(CSRC, "calibrate.hip"),

@@ -1,0 +1,41 @@
+"""The C ABI from plain C: paper_2105_02995_amd/fio_solve_file (built from
+paper_2105_02995_amd/examples/solve_file.c against include/fio.h and libfio.so, HIP
+runtime C API for device memory) solves from a file, in a child process; its output
+is compared with the oracle's exact solve."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fio_synth import gaussian_complex
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EXE = os.path.join(ROOT, "paper_2105_02995_amd", "fio_solve_file")
+
+
+@pytest.mark.parametrize("d,n,phase,pid,eps,mode", [(1, 1024, "1d_ex1", 1, 1e-6, 1), (1, 1024, "1d_ex1", 1, 1e-6, 2),
+                                                     (1, 1024, "1d_ex1", 1, 1e-6, 3), (2, 32, "2d_radon", 2, 1e-4, 1)])
+def test_c_program_solves_from_file(tmp_path, d, n, phase, pid, eps, mode):
+    B = 3
+    op = O.OracleProblem(d, n, phase, 16.0)
+    K = O.dense_K(op)
+    fh = gaussian_complex((n ** d, B), 1100 + mode)
+    u = K @ fh
+    uf, of = str(tmp_path / "u.bin"), str(tmp_path / "out.bin")
+    np.asfortranarray(u).T.astype(np.complex128).tofile(uf)  # column-major N x B
+    r = subprocess.run([EXE, str(d), str(n), str(pid), repr(eps), str(B), str(mode), uf, of],
+                       capture_output=True, text=True, timeout=120)
+    print(r.stdout, r.stderr, flush=True)
+    sys.stdout.flush()
+    assert r.returncode == 0
+    x = np.fromfile(of, dtype=np.complex128).reshape(B, n ** d).T
+    assert O.rel_err(x, fh).max() < 10 * eps

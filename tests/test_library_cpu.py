@@ -215,3 +215,13 @@ def test_example2_ill_conditioned_pivots_are_shifted(tmp_path):
     x, its = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, b, tol=1e-8, maxit=500, precond=gd_nat)
     print("shifted %d pivot blocks; PCG with Gd: %d iterations" % (shifted, its))
     assert its <= 40
+
+
+def test_c_example_is_built_and_checks_its_arguments():
+    """build() compiles the plain-C user of the ABI; without arguments it prints its
+    usage and exits with status 2 (no GPU call is made)."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2105_02995_amd", "fio_solve_file")
+    assert os.path.exists(exe)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
