@@ -107,6 +107,10 @@ typedef struct {
      * preconditioner-quality inverse on those nodes.  strict_hpd = 1 makes the build
      * fail with FIO_ERR_NOT_HPD instead.                                           */
     int strict_hpd;
+    /* The butterfly's interpolative decompositions (sampling K, pivoted QR, the
+     * interpolation matrices) run on the plan's device unless this is nonzero or the
+     * plan is host-only; both give factors of the same accuracy.                    */
+    int host_construction;
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",
@@ -186,6 +190,8 @@ typedef struct {
     double build_seconds;          /* wall time of fio_build                           */
     int hif_shifted;               /* pivot blocks given a diagonal shift (see strict_hpd;
                                       not stored by fio_save)                          */
+    double bf_seconds;             /* wall time of the butterfly construction (not stored) */
+    int bf_device_levels;          /* butterfly levels decomposed on the device (not stored) */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

@@ -20,7 +20,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
 CXX_SOURCES = ["la.cpp", "stages.cpp", "butterfly.cpp", "hif1d.cpp", "hif2d.cpp", "build.cpp"]
-HIP_SOURCES = ["kernels.hip", "capi.hip"]
+HIP_SOURCES = ["kernels.hip", "construct.hip", "capi.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -60,7 +60,8 @@ fio_problem normalized_problem(const fio_problem &in) {
     return p;
 }
 
-void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu) {
+void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu,
+                        const BatchedIdFactory &ids) {
     auto t0 = std::chrono::steady_clock::now();
     fio_problem p = normalized_problem(pin);
     FioKernel K;
@@ -72,10 +73,14 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     bo.seed = p.seed ^ 0xB0F1ULL;
     const bool vb = p.verbose != 0;
     bo.verbose = vb;
+    if (ids) bo.ids = ids(K);
     progress(vb, "d=%d n=%d: butterfly (eps_bf=%.1e)", p.d, p.n, p.eps_bf);
     Butterfly B = build_butterfly(K, bo);
-    progress(vb, "butterfly done: L=%d nnz=%lld (%.1fs)", B.L, (long long)B.nnz(),
-             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    bo.ids = nullptr;  // frees the engine's device tables
+    out.bf_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out.bf_device_levels = B.device_levels;
+    progress(vb, "butterfly done: L=%d nnz=%lld, %d levels on the device (%.1fs)", B.L, (long long)B.nnz(),
+             B.device_levels, out.bf_seconds);
     out.d = p.d; out.n = p.n; out.N = B.N; out.L = B.L; out.Lm = B.Lm; out.m = B.m;
     out.perm = K.to_nat;
     out.prob = p;

@@ -1,7 +1,9 @@
 #include "butterfly.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <functional>
 
 #include "la.hpp"
 
@@ -55,6 +57,86 @@ static std::vector<int64_t> rank_probe_pairs(int64_t npairs, int64_t nOm, int64_
     return out;
 }
 
+// Sampled block of K: entry (s, c) = K(cand[c], samp[s]) if the candidates are X
+// points (the transpose of the X-side block), else K(samp[s], cand[c]).
+static Mat sample_block(const FioKernel &K, bool cand_is_x, const std::vector<int> &cand,
+                        const std::vector<int> &samp) {
+    Mat M((int)samp.size(), (int)cand.size());
+    for (size_t c = 0; c < cand.size(); ++c)
+        for (size_t s = 0; s < samp.size(); ++s)
+            M((int)s, (int)c) = cand_is_x ? K.entry(cand[c], samp[s]) : K.entry(samp[s], cand[c]);
+    return M;
+}
+
+// Interpolative decompositions of one level: the rank is the largest numerical rank
+// over the probe pairs, then every pair is decomposed at that rank and handed to
+// sink(pair, id).  Runs through the batched engine when there is one (which may
+// decline a shape), else on the host.  on_rank(r) is called once the rank is known,
+// before the first sink call.  Returns the rank; *dev tells where it ran.
+template <class CandFn, class SampFn, class Sink, class RankFn>
+static int level_ids(const FioKernel &K, const ButterflyOptions &opt, bool cand_is_x, int64_t npairs,
+                     int ncand, int ns, const std::vector<int64_t> &probe, CandFn cand_of,
+                     SampFn samp_of, Sink sink, bool *dev, RankFn on_rank) {
+    const int nt = opt.nthreads;
+    auto fill = [&](IdBatch &bt, int64_t nb, const std::function<int64_t(int64_t)> &pair_of) {
+        bt.nb = nb;
+        bt.ns = ns;
+        bt.nc = ncand;
+        bt.cand_is_x = cand_is_x;
+        bt.samp.resize((size_t)nb * ns);
+        bt.cand.resize((size_t)nb * ncand);
+        parallel_for(nb, nt, [&](int64_t t) {
+            const int64_t pr = pair_of(t);
+            std::vector<int> c = cand_of(pr), sp = samp_of(pr);
+            std::copy(c.begin(), c.end(), bt.cand.begin() + t * ncand);
+            std::copy(sp.begin(), sp.end(), bt.samp.begin() + t * ns);
+        });
+    };
+    *dev = false;
+    int r = 0;
+    if (opt.ids) {
+        IdBatch bt;
+        fill(bt, (int64_t)probe.size(), [&](int64_t t) { return probe[t]; });
+        bt.tol_rel = opt.eps;
+        bt.max_rank = ncand;
+        std::atomic<int> mx(0);
+        *dev = opt.ids(bt, [&](int64_t, int k, const int *, const cd *) {
+            int cur = mx.load();
+            while (k > cur && !mx.compare_exchange_weak(cur, k)) {
+            }
+        });
+        r = mx.load();
+    }
+    if (!*dev) {
+        std::vector<int> ranks(probe.size());
+        parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
+            ranks[t] = id_rank(sample_block(K, cand_is_x, cand_of(probe[t]), samp_of(probe[t])), opt.eps, ncand);
+        });
+        r = *std::max_element(ranks.begin(), ranks.end());
+    }
+    r = std::min(ncand, std::max(1, r));
+    on_rank(r);
+    if (*dev) {
+        IdBatch bt;
+        fill(bt, npairs, [](int64_t t) { return t; });
+        bt.fixed_rank = r;
+        bt.max_rank = ncand;
+        *dev = opt.ids(bt, [&](int64_t pr, int k, const int *perm, const cd *T) {
+            ColumnID id;
+            id.skel.assign(perm, perm + k);
+            id.redund.assign(perm + k, perm + ncand);
+            id.T = Mat(k, ncand - k);
+            std::copy(T, T + (size_t)k * (ncand - k), id.T.a.begin());
+            sink(pr, id);
+        });
+        if (*dev) return r;
+    }
+    parallel_for(npairs, nt, [&](int64_t pr) {
+        sink(pr, column_id(sample_block(K, cand_is_x, cand_of(pr), samp_of(pr)), opt.eps, r, ncand));
+    });
+    return r;
+}
+
 Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
     Butterfly B;
     B.d = K.d;
@@ -100,39 +182,32 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
             }
             return c;
         };
-        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand, int ns) {
+        const int ns = (int)std::min<int64_t>(n_samples(ncand, N), szOm);
+        auto samples = [&](int64_t pr) {
             int64_t j = pr % nOm;
-            std::vector<int> cols = stratified(j * szOm, szOm, std::min<int64_t>(ns, szOm),
-                                               opt.seed ^ splitmix64(0xA000 + l) ^ (uint64_t)pr * 7919ULL);
-            Mat MT((int)cols.size(), ncand);  // transpose of K(cand, cols)
-            for (int c = 0; c < ncand; ++c)
-                for (size_t s = 0; s < cols.size(); ++s) MT((int)s, c) = K.entry(cand[c], cols[s]);
-            return MT;
+            return stratified(j * szOm, szOm, ns, opt.seed ^ splitmix64(0xA000 + l) ^ (uint64_t)pr * 7919ULL);
         };
         const std::vector<int64_t> probe = rank_probe_pairs(npairs, nOm, xi0 / szOm, opt.seed ^ (0xC00 + l));
-        std::vector<int> ranks(probe.size());
-        parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
-            auto cand = candidates(probe[t]);
-            ranks[t] = id_rank(sample_matrix(probe[t], cand, n_samples(ncand, N)), opt.eps, ncand);
-        });
-        const int r = std::min(ncand, std::max(1, *std::max_element(ranks.begin(), ranks.end())));
-        B.rU[l] = r;
-        skelU[l].assign((size_t)npairs * r, 0);
         std::vector<Mat> Q(npairs);
-        parallel_for(npairs, nt, [&](int64_t pr) {
-            auto cand = candidates(pr);
-            ColumnID id = column_id(sample_matrix(pr, cand, n_samples(ncand, N)), opt.eps, r, ncand);
+        std::vector<int> &sk = skelU[l];
+        bool dev = false;
+        const int r = level_ids(K, opt, true, npairs, ncand, ns, probe, candidates, samples,
+                                [&](int64_t pr, const ColumnID &id) {
             // K(cand, :) ~= Q K(skel, :) with Q(skel_k, k) = 1 and Q(redund_t, k) = T(k, t).
-            Mat q(ncand, r);
-            for (int k = 0; k < r; ++k) {
+            const int rr = B.rU[l];
+            if ((int)id.skel.size() != rr) fail(FIO_ERR_ARG, "interpolative decomposition below the level rank");
+            const std::vector<int> cand = candidates(pr);
+            Mat q(ncand, rr);
+            for (int k = 0; k < rr; ++k) {
                 q(id.skel[k], k) = 1.0;
-                skelU[l][pr * r + k] = cand[id.skel[k]];
+                sk[pr * rr + k] = cand[id.skel[k]];
             }
             for (size_t t = 0; t < id.redund.size(); ++t)
-                for (int k = 0; k < r; ++k) q(id.redund[t], k) = id.T(k, (int)t);
+                for (int k = 0; k < rr; ++k) q(id.redund[t], k) = id.T(k, (int)t);
             Q[pr] = std::move(q);
-        });
-        progress(opt.verbose, "butterfly X side level %d: rank %d", l, r);
+        }, &dev, [&](int rank) { B.rU[l] = rank; sk.assign((size_t)npairs * rank, 0); });
+        B.device_levels += dev ? 1 : 0;
+        progress(opt.verbose, "butterfly X side level %d: rank %d (%s)", l, r, dev ? "device" : "host");
         if (l < L) skelU[l + 1].clear();
         Stage st;
         if (l == L) {
@@ -191,40 +266,33 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
             }
             return c;
         };
-        auto sample_matrix = [&](int64_t pr, const std::vector<int> &cand, int ns) {
+        const int ns = (int)std::min<int64_t>(n_samples(ncand, N), szX);
+        auto samples = [&](int64_t pr) {
             int64_t i = pr / nOm;
-            std::vector<int> rows = stratified(i * szX, szX, std::min<int64_t>(ns, szX),
-                                               opt.seed ^ splitmix64(0xB000 + l) ^ (uint64_t)pr * 104729ULL);
-            Mat M((int)rows.size(), ncand);
-            for (int c = 0; c < ncand; ++c)
-                for (size_t s = 0; s < rows.size(); ++s) M((int)s, c) = K.entry(rows[s], cand[c]);
-            return M;
+            return stratified(i * szX, szX, ns, opt.seed ^ splitmix64(0xB000 + l) ^ (uint64_t)pr * 104729ULL);
         };
         const int64_t szOmV = N / nOm;
         const std::vector<int64_t> probe = rank_probe_pairs(npairs, nOm, xi0 / szOmV, opt.seed ^ (0xD00 + l));
-        std::vector<int> ranks(probe.size());
-        parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
-            auto cand = candidates(probe[t]);
-            ranks[t] = id_rank(sample_matrix(probe[t], cand, n_samples(ncand, N)), opt.eps, ncand);
-        });
-        const int r = std::min(ncand, std::max(1, *std::max_element(ranks.begin(), ranks.end())));
-        B.rV[l] = r;
-        skelV[l].assign((size_t)npairs * r, 0);
         std::vector<Mat> G(npairs);
-        parallel_for(npairs, nt, [&](int64_t pr) {
-            auto cand = candidates(pr);
-            ColumnID id = column_id(sample_matrix(pr, cand, n_samples(ncand, N)), opt.eps, r, ncand);
+        std::vector<int> &sk = skelV[l];
+        bool dev = false;
+        const int r = level_ids(K, opt, false, npairs, ncand, ns, probe, candidates, samples,
+                                [&](int64_t pr, const ColumnID &id) {
             // K(:, cand) ~= K(:, skel) G with G(k, skel_k) = 1 and G(k, redund_t) = T(k, t).
-            Mat g(r, ncand);
-            for (int k = 0; k < r; ++k) {
+            const int rr = B.rV[l];
+            if ((int)id.skel.size() != rr) fail(FIO_ERR_ARG, "interpolative decomposition below the level rank");
+            const std::vector<int> cand = candidates(pr);
+            Mat g(rr, ncand);
+            for (int k = 0; k < rr; ++k) {
                 g(k, id.skel[k]) = 1.0;
-                skelV[l][pr * r + k] = cand[id.skel[k]];
+                sk[pr * rr + k] = cand[id.skel[k]];
             }
             for (size_t t = 0; t < id.redund.size(); ++t)
-                for (int k = 0; k < r; ++k) g(k, id.redund[t]) = id.T(k, (int)t);
+                for (int k = 0; k < rr; ++k) g(k, id.redund[t]) = id.T(k, (int)t);
             G[pr] = std::move(g);
-        });
-        progress(opt.verbose, "butterfly Omega side level %d: rank %d", l, r);
+        }, &dev, [&](int rank) { B.rV[l] = rank; sk.assign((size_t)npairs * rank, 0); });
+        B.device_levels += dev ? 1 : 0;
+        progress(opt.verbose, "butterfly Omega side level %d: rank %d (%s)", l, r, dev ? "device" : "host");
         if (l > 0) skelV[l - 1].clear();
         Stage st;
         st.n_out = npairs; st.n_in = npairs;

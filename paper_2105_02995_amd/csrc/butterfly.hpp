@@ -12,10 +12,40 @@
 // has L + 3 block-sparse factors, each with O(N) nonzeros (eq_BFF_fact).
 #pragma once
 
+#include <functional>
+
 #include "fio_kernel.hpp"
 #include "stages.hpp"
 
 namespace fio {
+
+// A batch of interpolative decompositions of sampled kernel blocks, all of one shape:
+// matrix b is ns x nc with entry (s, c) = K(cand[b][c], samp[b][s]) when the
+// candidates are X points (row skeletons of the X side, through the transpose), else
+// K(samp[b][s], cand[b][c]) (column skeletons of the Omega side).  Positions are
+// tree positions.  Column-pivoted QR selects the skeleton columns:
+//  * rank mode (fixed_rank = 0): pivots until the next pivot column's norm is at most
+//    tol_rel times the largest column norm, at most max_rank of them;
+//  * ID mode (fixed_rank > 0): exactly min(fixed_rank, ns, nc) pivots, and the
+//    interpolation matrix T = R11^{-1} R12 (k x (nc - k), column-major).
+struct IdBatch {
+    int64_t nb = 0;
+    int ns = 0, nc = 0;
+    bool cand_is_x = true;
+    std::vector<int> samp, cand;   // nb x ns and nb x nc, row-major by matrix
+    double tol_rel = 0;
+    int max_rank = 0;
+    int fixed_rank = 0;
+};
+// Receives matrix b's result: k pivots, perm (nc entries, skeletons first) and, in ID
+// mode, T.  Called from several host threads at once for different b.
+using IdSink = std::function<void(int64_t b, int k, const int *perm, const cd *T)>;
+// Runs a batch; returns false (having called nothing) if the shape is not supported.
+using BatchedId = std::function<bool(const IdBatch &, const IdSink &)>;
+// Makes a batched-ID engine for the entries of one kernel (device tables are built once).
+using BatchedIdFactory = std::function<BatchedId(const FioKernel &)>;
+// The device engine (FP64 on the given HIP device).
+BatchedIdFactory device_id_factory(int device);
 
 struct ButterflyOptions {
     double eps = 1e-7;    // relative tolerance of every interpolative decomposition
@@ -23,6 +53,7 @@ struct ButterflyOptions {
     int nthreads = 0;
     uint64_t seed = 1;    // column/row sampling
     bool verbose = false;
+    BatchedId ids;        // empty: sample and decompose on the host
 };
 
 struct Butterfly {
@@ -30,6 +61,7 @@ struct Butterfly {
     int64_t N = 0;
     std::vector<int> rU, rV;       // ranks per level (X side l = Lm..L, Omega side l = 0..Lm)
     std::vector<Stage> fwd;        // L + 3 stages: Omega tree order in -> X tree order out
+    int device_levels = 0;         // levels whose decompositions ran on the batched engine
     int64_t nnz() const {
         int64_t s = 0;
         for (auto &st : fwd) s += st.nnz();

@@ -496,8 +496,10 @@ fio_status fio_build(const fio_problem *prob, fio_plan *out) {
         }
         // Peeling products on the GPU when the plan has one (host otherwise).
         PeelApplyFactory f;
+        BatchedIdFactory ids;
         if (p->device >= 0) f = gpu_peel_factory(p->device);
-        build_host_factors(*prob, p->host, f);
+        if (p->device >= 0 && !prob->host_construction) ids = device_id_factory(p->device);
+        build_host_factors(*prob, p->host, f, ids);
         for (int s = (int)p->host.fwd.size() - 1; s >= 0; --s) p->adj.push_back(adjoint_stage(p->host.fwd[s]));
         if (p->device >= 0) upload_plan(p.get());
         *out = p.release();
@@ -547,6 +549,8 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
         o->device_bytes = p->device_bytes;
         o->workspace_bytes = (int64_t)(2 * p->max_coef + 12 * h.N + 2 * (int64_t)h.hif.root_idx.size()) * 16;
         o->build_seconds = h.build_seconds;
+        o->bf_seconds = h.bf_seconds;
+        o->bf_device_levels = h.bf_device_levels;
     });
 }
 

@@ -1,0 +1,427 @@
+// Device side of the butterfly construction (section 2): the interpolative
+// decompositions of the sampled low-rank blocks K_{l;ij}, batched over all pairs of
+// a level.  Three FP64 kernels per batch:
+//   k_id_sample  evaluates the sampled entries of K (section 1, eq6; the phases of
+//                section 6) straight into device memory,
+//   k_id_cpqr    column-pivoted Householder QR of each sample matrix, one workgroup
+//                per matrix, until the rank criterion or the fixed rank is reached,
+//   k_id_solve   the interpolation matrix T = R11^{-1} R12 by back substitution.
+// The host keeps the bookkeeping (candidates, samples, assembly of the stages).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "butterfly.hpp"
+
+namespace fio {
+namespace {
+
+#define CHK(x)                                                                           \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess)                                                            \
+            fail(e_ == hipErrorOutOfMemory ? FIO_ERR_NOMEM : FIO_ERR_DEVICE,             \
+                 std::string(#x) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+constexpr int ID_THREADS = 256;   // four waves per matrix
+constexpr int ID_NC_MAX = 1024;   // candidates per matrix (LDS norms and order)
+constexpr int ID_NS_MAX = 1024;   // samples per matrix (16 rows per lane)
+
+// Kernel tables in tree order (the device image of FioKernel).
+struct KTab {
+    int n = 0, phase = 0, amp_terms = 0;
+    int64_t N = 0;
+    const int *k1 = nullptr, *k2 = nullptr, *j1 = nullptr, *j2 = nullptr;
+    const double *c1 = nullptr, *c2 = nullptr;
+    const double *gx = nullptr, *hq = nullptr;   // amp_terms x N
+};
+
+// K(x_p, xi_q): the linear part of the phase reduced exactly in integers, the
+// non-linear part in FP64, then a * exp(2 pi i Phi).
+__device__ double2 k_entry(const KTab &t, int p, int q) {
+    int64_t s = (int64_t)t.k1[p] * t.j1[q] + (int64_t)t.k2[p] * t.j2[q];
+    s %= t.n;
+    if (s < 0) s += t.n;
+    double nl = 0.0;
+    if (t.phase == FIO_PHASE_1D_EX1 || t.phase == FIO_PHASE_1D_EX2) {
+        nl = t.c1[p] * fabs((double)t.j1[q]);
+    } else if (t.phase == FIO_PHASE_2D_RADON) {
+        const double a = t.c1[p] * t.j1[q], b = t.c2[p] * t.j2[q];
+        nl = sqrt(a * a + b * b);
+    }
+    double ph = (double)s / t.n + (nl - floor(nl));
+    ph -= floor(ph);
+    double amp = 1.0;
+    if (t.amp_terms > 0) {
+        amp = 0.0;
+        for (int k = 0; k < t.amp_terms; ++k) amp += t.gx[(int64_t)k * t.N + p] * t.hq[(int64_t)k * t.N + q];
+    }
+    double sn, cs;
+    sincospi(2.0 * ph, &sn, &cs);
+    return make_double2(amp * cs, amp * sn);
+}
+
+// W[b] (ns x nc, column-major): (s, c) = K(cand_c, samp_s) or K(samp_s, cand_c).
+__global__ void k_id_sample(KTab t, const int *samp, const int *cand, int ns, int nc, int64_t nb,
+                            int cand_is_x, double2 *W) {
+    const int64_t per = (int64_t)ns * nc, total = per * nb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / per, rem = e - b * per;
+        const int c = (int)(rem / ns), s = (int)(rem - (int64_t)c * ns);
+        const int pc = cand[b * nc + c], ps = samp[b * ns + s];
+        W[e] = cand_is_x ? k_entry(t, pc, ps) : k_entry(t, ps, pc);
+    }
+}
+
+// Sums over the 64 lanes; the xor butterfly leaves the same bits in every lane.
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cjmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// Column-pivoted Householder QR of W[b] in place, one workgroup per matrix.  Wave w
+// owns the trailing columns j = k+1+w (mod 4); lane l holds rows l + 64c (c < RPL).
+// Column norms of the trailing rows are recomputed exactly after every step.  The
+// pivot is the largest norm, the first position among equals.  Stops before step k
+// if the pivot norm is at most tol_rel times the largest initial column norm
+// (tol_rel > 0), and after kmax steps.  Upper triangle of the first k rows: R.
+template <int RPL>
+__global__ __launch_bounds__(ID_THREADS) void k_id_cpqr(double2 *W, int ns, int nc, int kmax, double tol_rel,
+                                                      int *rank_out, int *perm_out) {
+    __shared__ double nrm[ID_NC_MAX];
+    __shared__ int ord[ID_NC_MAX];
+    __shared__ double red_v[ID_THREADS / 64];
+    __shared__ int red_i[ID_THREADS / 64];
+    __shared__ double s_tol, s_pmax;
+    __shared__ int s_piv;
+    const int b = blockIdx.x;
+    double2 *A = W + (int64_t)b * ns * nc;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NW = ID_THREADS / 64;
+
+    for (int j = wv; j < nc; j += NW) {
+        const double2 *cj = A + (int64_t)j * ns;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) {
+            const int i = lane + 64 * c;
+            if (i < ns) s += cabs2(cj[i]);
+        }
+        s = wsum(s);
+        if (lane == 0) { nrm[j] = s; ord[j] = j; }
+    }
+    __syncthreads();
+
+    int k = 0;
+    for (; k < kmax; ++k) {
+        // pivot: largest remaining norm, first position among equals
+        double bv = -1.0;
+        int bi = nc;
+        for (int j = k + (int)threadIdx.x; j < nc; j += ID_THREADS) {
+            const double v = nrm[j];
+            if (v > bv) { bv = v; bi = j; }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double v = red_v[0];
+            int i = red_i[0];
+            for (int w = 1; w < NW; ++w)
+                if (red_v[w] > v || (red_v[w] == v && red_i[w] < i)) { v = red_v[w]; i = red_i[w]; }
+            s_piv = i;
+            s_pmax = v;
+            if (k == 0) s_tol = (tol_rel > 0) ? tol_rel * sqrt(fmax(v, 0.0)) : -1.0;
+        }
+        __syncthreads();
+        const int p = s_piv;
+        if (sqrt(fmax(s_pmax, 0.0)) <= s_tol) break;   // the same decision in every thread
+        if (p != k) {
+            double2 *ck = A + (int64_t)k * ns, *cp = A + (int64_t)p * ns;
+            for (int i = threadIdx.x; i < ns; i += ID_THREADS) {
+                const double2 t = ck[i];
+                ck[i] = cp[i];
+                cp[i] = t;
+            }
+            if (threadIdx.x == 0) {
+                const double tv = nrm[k]; nrm[k] = nrm[p]; nrm[p] = tv;
+                const int ti = ord[k]; ord[k] = ord[p]; ord[p] = ti;
+            }
+        }
+        __syncthreads();
+
+        // Householder reflector H = I - 2 w w^* / (w^* w) with w = x + e^{i arg x0} |x| e_k,
+        // x = column k below row k - 1; H x = -e^{i arg x0} |x| e_k.
+        const double2 *ck = A + (int64_t)k * ns;
+        double2 w[RPL];
+        double tail = 0.0;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) {
+            const int i = lane + 64 * c;
+            w[c] = (i >= k && i < ns) ? ck[i] : make_double2(0.0, 0.0);
+            if (i > k) tail += cabs2(w[c]);
+        }
+        tail = wsum(tail);
+        const double2 x0 = ck[k];
+        const double ax0 = hypot(x0.x, x0.y);
+        const double alpha = sqrt(ax0 * ax0 + tail);
+        const double2 ph = (ax0 > 0) ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+        const double2 w0 = make_double2(x0.x + ph.x * alpha, x0.y + ph.y * alpha);
+        const double wn2 = cabs2(w0) + tail;
+#pragma unroll
+        for (int c = 0; c < RPL; ++c)
+            if (lane + 64 * c == k) w[c] = w0;
+
+        for (int j = k + 1 + wv; j < nc; j += NW) {
+            double2 *cj = A + (int64_t)j * ns;
+            double2 v[RPL];
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int c = 0; c < RPL; ++c) {
+                const int i = lane + 64 * c;
+                v[c] = (i >= k && i < ns) ? cj[i] : make_double2(0.0, 0.0);
+                const double2 t = cjmul(w[c], v[c]);
+                sr += t.x;
+                si += t.y;
+            }
+            double nn = 0.0;
+            if (wn2 > 0) {
+                sr = wsum(sr);
+                si = wsum(si);
+                const double2 tau = make_double2(2.0 * sr / wn2, 2.0 * si / wn2);
+#pragma unroll
+                for (int c = 0; c < RPL; ++c) {
+                    const int i = lane + 64 * c;
+                    if (i >= k && i < ns) {
+                        const double2 d = cmul(tau, w[c]);
+                        v[c].x -= d.x;
+                        v[c].y -= d.y;
+                        cj[i] = v[c];
+                        if (i > k) nn += cabs2(v[c]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < RPL; ++c)
+                    if (lane + 64 * c > k) nn += cabs2(v[c]);
+            }
+            nn = wsum(nn);
+            if (lane == 0) nrm[j] = nn;
+        }
+        __syncthreads();
+        // R_kk (every wave has read column k; nothing below reads it again)
+        if (threadIdx.x == 0) A[(int64_t)k * ns + k] = make_double2(-ph.x * alpha, -ph.y * alpha);
+    }
+    if (threadIdx.x == 0) rank_out[b] = k;
+    for (int j = threadIdx.x; j < nc; j += ID_THREADS) perm_out[(int64_t)b * nc + j] = ord[j];
+}
+
+// T[b] = R11^{-1} R12 (k x (nc - k), column-major) from the factored W[b]; one wave
+// per column of R12, lane l holding rows l + 64c.  A zero pivot gives a zero row.
+template <int RPL>
+__global__ __launch_bounds__(ID_THREADS) void k_id_solve(const double2 *W, int ns, int nc, int k, double2 *T) {
+    const int b = blockIdx.x;
+    const double2 *A = W + (int64_t)b * ns * nc;
+    double2 *Tb = T + (int64_t)b * k * (nc - k);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j = wv; j < nc - k; j += ID_THREADS / 64) {
+        const double2 *r12 = A + (int64_t)(k + j) * ns;
+        double2 t[RPL];
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) {
+            const int i = lane + 64 * c;
+            t[c] = (i < k) ? r12[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int c = RPL - 1; c >= 0; --c) {
+            for (int l = 63; l >= 0; --l) {
+                const int p = 64 * c + l;
+                if (p >= k) continue;
+                const double2 *rp = A + (int64_t)p * ns;
+                const double2 d = rp[p];
+                const double2 tv = make_double2(__shfl(t[c].x, l, 64), __shfl(t[c].y, l, 64));
+                const double dd = cabs2(d);
+                const double2 tp = (dd > 0) ? make_double2((tv.x * d.x + tv.y * d.y) / dd, (tv.y * d.x - tv.x * d.y) / dd)
+                                            : make_double2(0.0, 0.0);
+                if (lane == l) t[c] = tp;
+#pragma unroll
+                for (int c2 = 0; c2 < RPL; ++c2) {
+                    if (c2 > c) continue;
+                    const int i = lane + 64 * c2;
+                    if (i < p) {
+                        const double2 u = cmul(rp[i], tp);
+                        t[c2].x -= u.x;
+                        t[c2].y -= u.y;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < RPL; ++c) {
+            const int i = lane + 64 * c;
+            if (i < k) Tb[(int64_t)j * k + i] = t[c];
+        }
+    }
+}
+
+template <int RPL>
+void launch_qr(int64_t nb, double2 *W, int ns, int nc, int kmax, double tol, int *rank, int *perm) {
+    hipLaunchKernelGGL(k_id_cpqr<RPL>, dim3((unsigned)nb), dim3(ID_THREADS), 0, 0, W, ns, nc, kmax, tol, rank, perm);
+}
+template <int RPL>
+void launch_solve(int64_t nb, const double2 *W, int ns, int nc, int k, double2 *T) {
+    hipLaunchKernelGGL(k_id_solve<RPL>, dim3((unsigned)nb), dim3(ID_THREADS), 0, 0, W, ns, nc, k, T);
+}
+// Rows per lane for a column of `rows` entries: 1, 2, 4, 8 or 16.
+int rows_per_lane(int rows) {
+    int r = 1;
+    while (64 * r < rows) r *= 2;
+    return r;
+}
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t b) {
+        if (p) { (void)hipFree(p); p = nullptr; }
+        if (b) CHK(hipMalloc(&p, b));
+    }
+};
+
+// Device copies of the kernel tables, alive as long as the engine.
+struct Tables {
+    int device = 0;
+    KTab view;
+    DevMem k1, k2, j1, j2, c1, c2, gx, hq;
+    Tables(int dev, const FioKernel &K) : device(dev) {
+        CHK(hipSetDevice(dev));
+        auto up = [](DevMem &m, const void *src, size_t bytes) {
+            m.alloc(bytes);
+            if (bytes) CHK(hipMemcpy(m.p, src, bytes, hipMemcpyHostToDevice));
+        };
+        const size_t N = (size_t)K.N;
+        up(k1, K.k1.data(), N * 4); up(k2, K.k2.data(), N * 4);
+        up(j1, K.j1.data(), N * 4); up(j2, K.j2.data(), N * 4);
+        up(c1, K.c1.data(), N * 8); up(c2, K.c2.data(), N * 8);
+        const int nt = (int)K.gx.size();
+        if (nt > 0) {
+            std::vector<double> g(N * nt), h(N * nt);
+            for (int k = 0; k < nt; ++k) {
+                std::copy(K.gx[k].begin(), K.gx[k].end(), g.begin() + k * N);
+                std::copy(K.hq[k].begin(), K.hq[k].end(), h.begin() + k * N);
+            }
+            up(gx, g.data(), g.size() * 8);
+            up(hq, h.data(), h.size() * 8);
+        }
+        view.n = K.n; view.phase = (int)K.phase; view.amp_terms = nt; view.N = K.N;
+        view.k1 = (const int *)k1.p; view.k2 = (const int *)k2.p;
+        view.j1 = (const int *)j1.p; view.j2 = (const int *)j2.p;
+        view.c1 = (const double *)c1.p; view.c2 = (const double *)c2.p;
+        view.gx = (const double *)gx.p; view.hq = (const double *)hq.p;
+    }
+};
+
+bool run_batch(const Tables &tb, const IdBatch &bt, const IdSink &sink, int nthreads) {
+    if (bt.nb <= 0) return true;
+    const int ns = bt.ns, nc = bt.nc;
+    if (ns < 1 || nc < 1 || ns > ID_NS_MAX || nc > ID_NC_MAX) return false;
+    if ((int64_t)bt.samp.size() != bt.nb * ns || (int64_t)bt.cand.size() != bt.nb * nc)
+        fail(FIO_ERR_ARG, "batched ID: index arrays do not match the batch shape");
+    for (int v : bt.samp) if (v < 0 || v >= tb.view.N) fail(FIO_ERR_ARG, "batched ID: sample out of range");
+    for (int v : bt.cand) if (v < 0 || v >= tb.view.N) fail(FIO_ERR_ARG, "batched ID: candidate out of range");
+    CHK(hipSetDevice(tb.device));
+    const bool fixed = bt.fixed_rank > 0;
+    const int kfix = fixed ? std::min({bt.fixed_rank, ns, nc}) : 0;
+    const int kmax = fixed ? kfix : std::min({ns, nc, bt.max_rank > 0 ? bt.max_rank : nc});
+    const int64_t nT = (int64_t)kfix * (nc - kfix);
+    const size_t per = (size_t)ns * nc * 16 + (size_t)nT * 16 + (size_t)(ns + 2 * nc + 1) * 4;
+    size_t freeb = 0, totalb = 0;
+    CHK(hipMemGetInfo(&freeb, &totalb));
+    const size_t budget = std::min<size_t>(freeb / 2, (size_t)8 << 30);
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(bt.nb, (int64_t)(budget / per)));
+    DevMem W, T, S, C, R, P;
+    W.alloc((size_t)chunk * ns * nc * 16);
+    if (nT > 0) T.alloc((size_t)chunk * nT * 16);
+    S.alloc((size_t)chunk * ns * 4);
+    C.alloc((size_t)chunk * nc * 4);
+    R.alloc((size_t)chunk * 4);
+    P.alloc((size_t)chunk * nc * 4);
+    std::vector<int> rank(chunk), perm((size_t)chunk * nc);
+    std::vector<cd> Th((size_t)chunk * nT);
+    const int rq = rows_per_lane(ns), rk = rows_per_lane(std::max(kfix, 1));
+    for (int64_t b0 = 0; b0 < bt.nb; b0 += chunk) {
+        const int64_t nbc = std::min(chunk, bt.nb - b0);
+        CHK(hipMemcpy(S.p, bt.samp.data() + b0 * ns, (size_t)nbc * ns * 4, hipMemcpyHostToDevice));
+        CHK(hipMemcpy(C.p, bt.cand.data() + b0 * nc, (size_t)nbc * nc * 4, hipMemcpyHostToDevice));
+        const int64_t total = nbc * ns * nc;
+        const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+        hipLaunchKernelGGL(k_id_sample, dim3(grid), dim3(256), 0, 0, tb.view, (const int *)S.p, (const int *)C.p,
+                           ns, nc, nbc, bt.cand_is_x ? 1 : 0, (double2 *)W.p);
+        CHK(hipGetLastError());
+        double2 *w = (double2 *)W.p;
+        const double tol = fixed ? 0.0 : bt.tol_rel;
+        int *rp = (int *)R.p, *pp = (int *)P.p;
+        switch (rq) {
+            case 1: launch_qr<1>(nbc, w, ns, nc, kmax, tol, rp, pp); break;
+            case 2: launch_qr<2>(nbc, w, ns, nc, kmax, tol, rp, pp); break;
+            case 4: launch_qr<4>(nbc, w, ns, nc, kmax, tol, rp, pp); break;
+            case 8: launch_qr<8>(nbc, w, ns, nc, kmax, tol, rp, pp); break;
+            default: launch_qr<16>(nbc, w, ns, nc, kmax, tol, rp, pp); break;
+        }
+        CHK(hipGetLastError());
+        if (nT > 0) {
+            double2 *t = (double2 *)T.p;
+            switch (rk) {
+                case 1: launch_solve<1>(nbc, w, ns, nc, kfix, t); break;
+                case 2: launch_solve<2>(nbc, w, ns, nc, kfix, t); break;
+                case 4: launch_solve<4>(nbc, w, ns, nc, kfix, t); break;
+                case 8: launch_solve<8>(nbc, w, ns, nc, kfix, t); break;
+                default: launch_solve<16>(nbc, w, ns, nc, kfix, t); break;
+            }
+            CHK(hipGetLastError());
+        }
+        CHK(hipMemcpy(rank.data(), R.p, (size_t)nbc * 4, hipMemcpyDeviceToHost));
+        CHK(hipMemcpy(perm.data(), P.p, (size_t)nbc * nc * 4, hipMemcpyDeviceToHost));
+        if (nT > 0) CHK(hipMemcpy(Th.data(), T.p, (size_t)nbc * nT * 16, hipMemcpyDeviceToHost));
+        for (int64_t t = 0; t < nbc; ++t)
+            if (fixed && rank[t] != kfix) fail(FIO_ERR_DEVICE, "batched ID: pivot count differs from the fixed rank");
+        parallel_for(nbc, nthreads, [&](int64_t t) {
+            sink(b0 + t, rank[t], perm.data() + t * nc, nT > 0 ? Th.data() + t * nT : nullptr);
+        });
+    }
+    return true;
+}
+
+}  // namespace
+
+BatchedIdFactory device_id_factory(int device) {
+    return [device](const FioKernel &K) -> BatchedId {
+        auto tb = std::make_shared<Tables>(device, K);
+        return [tb](const IdBatch &bt, const IdSink &sink) { return run_batch(*tb, bt, sink, 0); };
+    };
+}
+
+}  // namespace fio

@@ -18,13 +18,17 @@ struct HostFactors {
     HifFactors hif;                 // Gd factors (Omega tree order)
     fio_problem prob{};             // build description
     double build_seconds = 0;
+    double bf_seconds = 0;          // butterfly construction (not stored in files)
+    int bf_device_levels = 0;       // butterfly levels decomposed on the device
 };
 
-// Builds the factors on the host; `gpu_apply` (may be empty) replaces the host
-// product Kd^* Kd of the peeling step.
+// Builds the factors; `gpu` (may be empty) replaces the host product Kd^* Kd of the
+// peeling step, `ids` (may be empty) the host interpolative decompositions of the
+// butterfly.
 using PeelApplyFactory = std::function<BlockApply(const std::vector<Stage> &fwd,
                                                   const std::vector<Stage> &adj)>;
-void build_host_factors(const fio_problem &p, HostFactors &out, const PeelApplyFactory &gpu);
+void build_host_factors(const fio_problem &p, HostFactors &out, const PeelApplyFactory &gpu,
+                        const BatchedIdFactory &ids);
 
 void save_factors(const HostFactors &f, const std::string &path);
 void load_factors(const std::string &path, HostFactors &f);

@@ -45,7 +45,7 @@ class fio_problem(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("device", ctypes.c_int), ("nthreads", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("amp_sigma2", ctypes.c_double), ("amp_terms", ctypes.c_int),
                 ("amp_x", ctypes.c_double * FIO_MAX_AMP_TERMS), ("amp_eta", ctypes.c_double * FIO_MAX_AMP_TERMS),
-                ("strict_hpd", ctypes.c_int)]
+                ("strict_hpd", ctypes.c_int), ("host_construction", ctypes.c_int)]
 
 
 class fio_solve_opts(ctypes.Structure):
@@ -64,7 +64,8 @@ class fio_plan_stats_t(ctypes.Structure):
                 ("hif_levels", ctypes.c_int), ("hif_nnz", ctypes.c_int64),
                 ("root_size", ctypes.c_int), ("max_rank_h", ctypes.c_int),
                 ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double), ("hif_shifted", ctypes.c_int)]
+                ("build_seconds", ctypes.c_double), ("hif_shifted", ctypes.c_int),
+                ("bf_seconds", ctypes.c_double), ("bf_device_levels", ctypes.c_int)]
 
 
 _lib = None
