@@ -28,24 +28,29 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of a stage-kernel instance on this workload, from rocprofv3
 # FETCH_SIZE (x2) and WRITE_SIZE (x1) scaled by a 1 GiB copy kernel (summaries under
-# profiles/), valid only for the kernel source they were measured on.
+# profiles/), valid only for the kernel source and the factor set (its nonzero
+# count) they were measured on.
 TRAFFIC = {
     "k_stage2_mfma<float, 2, 4>": {
-        "bytes": (113834.49 * 2 + 92160.00) * 1024,
-        "kernels_sha256": "7abf2e251e379eee70ba675b055c77d44ebe2978238813ba19b27129cce007c5",
+        "bytes": (113965.40 * 2 + 91136.00) * 1024,
+        "kernels_sha256": "b1d9f0cd23f3016ffdb6d00e4e4499af4c3f5bec29601f708bd25dccbbca6ae3",
+        "bf_nnz": 109109248,
     },
     "k_stage2_mfma<float, 2, 2>": {
-        "bytes": (115624.39 * 2 + 98304.00) * 1024,
-        "kernels_sha256": "7abf2e251e379eee70ba675b055c77d44ebe2978238813ba19b27129cce007c5",
+        "bytes": (119066.29 * 2 + 102400.00) * 1024,
+        "kernels_sha256": "b1d9f0cd23f3016ffdb6d00e4e4499af4c3f5bec29601f708bd25dccbbca6ae3",
+        "bf_nnz": 109109248,
     },
 }
 
 
-def traffic_for(name):
+def traffic_for(name, bf_nnz):
+    """HBM bytes per launch from the committed counter runs, or None if the kernel
+    source or the factors (their nonzero count) differ from the ones profiled."""
     import hashlib
     key = name.split(" (")[0]
     t = TRAFFIC.get(key)
-    if not t:
+    if not t or t.get("bf_nnz") != bf_nnz:
         return None
     src = os.path.join(ROOT, "paper_2105_02995_amd", "csrc", "kernels.hip")
     with open(src, "rb") as fh:
@@ -337,7 +342,7 @@ def main():
             "peak": PEAK_HBM_GBS if hbm_bound else pk,
             "unit": "GB/s" if hbm_bound else "TFLOP/s",
             "frac": round((gbs / PEAK_HBM_GBS) if hbm_bound else (tf / pk), 4),
-            "traffic": traffic_for(best), "kernel": best,
+            "traffic": traffic_for(best, stats["bf_nnz"]), "kernel": best,
             "launches_per_chain": len(e["l"]),
             "avg_launch_ms": round(float(tms.mean()), 5),
             "flops_per_launch": float(fl.mean()), "bytes_per_launch": float(by.mean()),

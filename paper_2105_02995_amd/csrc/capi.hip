@@ -377,17 +377,25 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
 
 // One skeletonization step: LDS-staged kernel for small nodes (choice 0), gathered
 // GEMMs on matrix cores when a node's blocks exceed LDS (large 2D cells and edges),
-// in tiles of 64, 32 or 16 right-hand sides (choices 1, 2, 3).
+// in tiles of 64, 32 or 16 right-hand sides (choices 1, 2, 3), or the fused
+// per-node matrix-core kernel for nodes of at most 64 redundant and 64 skeleton
+// DOFs (choice 4).  `force` overrides the tuned choice where it applies.
+constexpr int HIF_CHOICES = 5;
 void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int force = -1) {
     const HifStepDev h = p->dhif[k].view(dbl);
     int choice = force;
+    if (choice == 4 && !hif_fused_fits(h)) choice = -1;
     if (choice < 0) {
         const auto *t = p->tuned(dbl, nrhs);
         if (t && k < t->hif.size()) choice = t->hif[k];
     }
-    if (choice < 0) choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
-    if (choice >= 1 && nrhs < 16) choice = 0;
+    if (choice < 0) {
+        if (nrhs >= 16 && hif_fused_fits(h)) choice = 4;
+        else choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
+    }
+    if (choice >= 1 && choice <= 3 && nrhs < 16) choice = 0;
     if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
+    else if (choice == 4) launch_hif_fused_step(h, dbl, up, x, nrhs, st);
     else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, 64 >> (choice - 1), st);
 }
 
@@ -410,10 +418,10 @@ void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
     launch_rows_scatter(p->RO.p, true, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
 }
 
-void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
-    for (size_t k = 0; k < p->dhif.size(); ++k) hif_step(p, k, dbl, true, x, nrhs, st);
+void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, int force = -1) {
+    for (size_t k = 0; k < p->dhif.size(); ++k) hif_step(p, k, dbl, true, x, nrhs, st, force);
     root_apply(p, dbl, x, nrhs, st);
-    for (size_t k = p->dhif.size(); k-- > 0;) hif_step(p, k, dbl, false, x, nrhs, st);
+    for (size_t k = p->dhif.size(); k-- > 0;) hif_step(p, k, dbl, false, x, nrhs, st, force);
 }
 
 void check_apply_args(fio_plan p, int64_t nrhs, int64_t ld, const void *a, const void *b) {
@@ -756,6 +764,13 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                     });
                     if (ms < best_ms) { best_ms = ms; best = c; }
                 }
+                if (hif_fused_fits(h)) {
+                    const float ms = timeit([&] {
+                        launch_hif_fused_step(h, dbl, true, p->V2.p, nr, st);
+                        launch_hif_fused_step(h, dbl, false, p->V2.p, nr, st);
+                    });
+                    if (ms < best_ms) { best_ms = ms; best = 4; }
+                }
                 progress(vb, "tune %s skeletonization step %zu (%lld nodes): choice %d %.4f ms",
                          dbl ? "c128" : "c64", k, (long long)h.n_nodes, best, best_ms / reps);
             }
@@ -799,9 +814,15 @@ fio_status fio_tune_query(fio_plan p, fio_op op, int stage, fio_dtype dt, int64_
 }
 
 fio_status fio_gd_apply(fio_plan p, fio_dtype dt, const void *x, void *y, int64_t nrhs, int64_t ld, void *stream) {
+    return fio_gd_apply_variant(p, dt, -1, x, y, nrhs, ld, stream);
+}
+
+fio_status fio_gd_apply_variant(fio_plan p, fio_dtype dt, int variant, const void *x, void *y, int64_t nrhs,
+                                int64_t ld, void *stream) {
     return guard([&] {
         check_apply_args(p, nrhs, ld, x, y);
         if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (variant < -1 || variant >= HIF_CHOICES) fail(FIO_ERR_ARG, "skeletonization kernel variant out of range");
         if (nrhs == 0) return;
         std::lock_guard<std::mutex> lk(p->mu);
         HIPC(hipSetDevice(p->device));
@@ -811,7 +832,7 @@ fio_status fio_gd_apply(fio_plan p, fio_dtype dt, const void *x, void *y, int64_
         ensure_ws(p, nr);
         const int32_t *perm = (const int32_t *)p->perm.p;
         launch_gather(x, dbl, ld, perm, p->V2.p, dbl, p->host.N, nr, st);
-        gd_inplace(p, dbl, p->V2.p, nr, st);
+        gd_inplace(p, dbl, p->V2.p, nr, st, variant);
         launch_scatter(p->V2.p, dbl, perm, y, dbl, ld, p->host.N, nr, st);
     });
 }

@@ -833,6 +833,256 @@ bool hif_step_fits_lds(const HifStepDev &h, bool dbl) {
     return (int64_t)h.max_mat * elt + (int64_t)std::max(1, h.max_vec) * elt <= budget;
 }
 
+// ------------------------------------------------------------------ fused skeletonization step
+// Nodes with nr, ns <= 64, one workgroup per (node, 64 right-hand sides): the
+// node's entries of x are staged in LDS once, the step's three products run on
+// matrix cores (factor from global memory as the A operand, the staged vectors as
+// B), and the results are written back once.
+//   up:   x_r -= T^* x_s;  x_r <- Linv x_r;   x_s -= M x_r
+//   down: x_r -= M^* x_s;  x_r <- Linv^* x_r; x_s -= T x_r
+// The two products with nr output rows split their rows over the waves (wave w:
+// rows 16w..16w+15, all 64 columns), so each factor entry is loaded once per
+// workgroup, with a barrier where a wave reads rows another wave wrote.  The
+// product with ns output rows splits its columns (wave w: columns 16w..16w+15).
+// k-steps in which a triangular factor's tile is zero are skipped.  Staged rows
+// past nr (ns) are zero, so clamped factor entries of k beyond the product's K
+// (finite duplicates) add nothing.
+constexpr int HF_LD = 68;   // LDS row stride, complex entries (64 columns + 4)
+constexpr int HF_PF = 4;    // k-steps of loads in flight (register ring)
+
+template <class R> struct HfFragR {   // row split: one factor entry, four vector entries
+    typename MF<R>::C a, b[4];
+};
+template <class R> struct HfFragC {   // column split: four factor entries, one vector entry
+    typename MF<R>::C a[4], b;
+};
+
+template <class R>
+__device__ __forceinline__ void cmma(typename MF<R>::V4 &re, typename MF<R>::V4 &im, typename MF<R>::C a,
+                                     typename MF<R>::C b) {
+    re = MF<R>::mma(a.x, b.x, re);
+    im = MF<R>::mma(a.x, b.y, im);
+    re = MF<R>::mma(-a.y, b.y, re);
+    im = MF<R>::mma(a.y, b.x, im);
+}
+
+// Row split: acc[nt] = A(rows 16mt.., :) B(:, 16nt..) for nt < ntl.
+template <class R>
+__device__ __forceinline__ void hf_rows(typename MF<R>::V4 (&re)[4], typename MF<R>::V4 (&im)[4],
+                                        const typename MF<R>::C *__restrict__ A, int lda, int rows, int K, int tri,
+                                        const typename MF<R>::C *B, int mt, int ntl) {
+    using C = typename MF<R>::C;
+    using V4 = typename MF<R>::V4;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) { re[nt] = V4{0, 0, 0, 0}; im[nt] = V4{0, 0, 0, 0}; }
+    int sb = 0, se = (K + 3) >> 2;
+    if (tri == 1) se = min(se, (16 * mt + 15) / 4 + 1);   // lower: k <= last row of the tile
+    if (tri == 2) sb = (16 * mt) / 4;                      // upper: k >= first row of the tile
+    if (16 * mt >= rows || sb >= se) return;               // wave-uniform
+    const C *arow = A + min(16 * mt + li, rows - 1);
+    // unconditional loads (a clamped k-step past the end loads valid, unused data):
+    // a load under a branch would make the compiler wait for every load in flight
+    auto load = [&](HfFragR<R> &f, int s) {
+        s = min(s, se - 1);
+        const int k = 4 * s + lk;
+        f.a = arow[(int64_t)min(k, K - 1) * lda];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) f.b[nt] = B[k * HF_LD + 16 * nt + li];
+    };
+    HfFragR<R> f[HF_PF];
+#pragma unroll
+    for (int j = 0; j + 1 < HF_PF; ++j) load(f[j], sb + j);
+    for (int s0 = sb; s0 < se; s0 += HF_PF) {
+#pragma unroll
+        for (int j = 0; j < HF_PF; ++j) {
+            if (s0 + j >= se) break;  // wave-uniform
+            load(f[(j + HF_PF - 1) % HF_PF], s0 + j + HF_PF - 1);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) cmma<R>(re[nt], im[nt], f[j].a, f[j].b[nt]);
+        }
+    }
+}
+
+// Column split: acc[mt] = A(rows 16mt.., :) B(:, col0..col0+15) for all row tiles.
+template <class R>
+__device__ __forceinline__ void hf_cols(typename MF<R>::V4 (&re)[4], typename MF<R>::V4 (&im)[4],
+                                        const typename MF<R>::C *__restrict__ A, int lda, int rows, int K,
+                                        const typename MF<R>::C *B, int col0) {
+    using C = typename MF<R>::C;
+    using V4 = typename MF<R>::V4;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) { re[mt] = V4{0, 0, 0, 0}; im[mt] = V4{0, 0, 0, 0}; }
+    const int nks = (K + 3) >> 2;
+    const int mtl = (rows + 15) >> 4;
+    if (nks == 0) return;  // wave-uniform
+    auto load = [&](HfFragC<R> &f, int s) {   // unconditional, clamped (as in hf_rows)
+        s = min(s, nks - 1);
+        const int k = 4 * s + lk;
+        const C *acol = A + (int64_t)min(k, K - 1) * lda;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) f.a[mt] = acol[min(16 * mt + li, rows - 1)];
+        f.b = B[k * HF_LD + col0 + li];
+    };
+    HfFragC<R> f[HF_PF];
+#pragma unroll
+    for (int j = 0; j + 1 < HF_PF; ++j) load(f[j], j);
+    for (int s0 = 0; s0 < nks; s0 += HF_PF) {
+#pragma unroll
+        for (int j = 0; j < HF_PF; ++j) {
+            if (s0 + j >= nks) break;  // wave-uniform
+            load(f[(j + HF_PF - 1) % HF_PF], s0 + j + HF_PF - 1);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                if (mt < mtl) cmma<R>(re[mt], im[mt], f[j].a[mt], f[j].b);
+        }
+    }
+}
+
+// Row-split result into Y (SET) or subtracted from it: rows 16mt.., columns 16nt + li.
+template <class R, bool SET>
+__device__ __forceinline__ void hf_store_rows(const typename MF<R>::V4 (&re)[4], const typename MF<R>::V4 (&im)[4],
+                                              typename MF<R>::C *Y, int rows, int mt, int ntl) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    if (16 * mt >= rows) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int row = 16 * mt + MF<R>::drow(lk, v);
+        if (row >= rows) continue;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            if (nt >= ntl) continue;
+            typename MF<R>::C &y = Y[row * HF_LD + 16 * nt + li];
+            if (SET) y = typename MF<R>::C{re[nt][v], im[nt][v]};
+            else y = typename MF<R>::C{y.x - re[nt][v], y.y - im[nt][v]};
+        }
+    }
+}
+
+// Column-split result subtracted from Y: rows 16mt + .., columns col0 + li.
+template <class R>
+__device__ __forceinline__ void hf_sub_cols(const typename MF<R>::V4 (&re)[4], const typename MF<R>::V4 (&im)[4],
+                                            typename MF<R>::C *Y, int rows, int col0) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        if (16 * mt >= rows) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * mt + MF<R>::drow(lk, v);
+            if (row >= rows) continue;
+            typename MF<R>::C &y = Y[row * HF_LD + col0 + li];
+            y = typename MF<R>::C{y.x - re[mt][v], y.y - im[mt][v]};
+        }
+    }
+}
+
+template <class R, bool UP>
+__global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                                   const typename MF<R>::C *__restrict__ mat,
+                                                   const typename MF<R>::C *__restrict__ matH,
+                                                   typename MF<R>::C *__restrict__ x, int nrhs, int rows_r,
+                                                   int rows_s) {
+    using C = typename MF<R>::C;
+    using V4 = typename MF<R>::V4;
+    extern __shared__ char smem_raw[];
+    C *Xr = reinterpret_cast<C *>(smem_raw);   // rows_r x HF_LD
+    C *Xs = Xr + (int64_t)rows_r * HF_LD;      // rows_s x HF_LD
+    const int64_t v = blockIdx.x;
+    const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
+    const int32_t *ir = idx + desc[4 * v + 2];
+    const int32_t *is = ir + nr;
+    const int64_t mo = desc[4 * v + 3];
+    const C *Tm = mat + mo, *Li = Tm + (int64_t)ns * nr, *Mm = Li + (int64_t)nr * nr;
+    const C *TH = matH + mo, *LH = TH + (int64_t)ns * nr, *MH = LH + (int64_t)nr * nr;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int w = threadIdx.x >> 6, col0 = 16 * w;
+    const int b0 = blockIdx.y * 64;
+    const int bc = min(64, nrhs - b0);
+    const int ntl = (bc + 15) >> 4;   // column tiles holding columns
+    // the node's row indices (x_r rows, then x_s rows) in LDS, one load per thread
+    int32_t *gidx = reinterpret_cast<int32_t *>(Xr + (int64_t)(rows_r + rows_s) * HF_LD);
+    const int32_t g0 = (nr > 0) ? ir[0] : ((ns > 0) ? is[0] : 0);
+    for (int i = threadIdx.x; i < rows_r + rows_s; i += blockDim.x) {
+        const int ii = (i < rows_r) ? i : i - rows_r;
+        const int cnt = (i < rows_r) ? nr : ns;
+        gidx[i] = (ii < cnt) ? ((i < rows_r) ? ir[ii] : is[ii]) : -1;
+    }
+    __syncthreads();
+    // stage: each wave its 16 columns, four rows per instruction; all loads of the
+    // wave are issued (from valid rows and columns) before the first store, and
+    // entries outside the node or the batch are then replaced by zero
+    const bool cv = col0 + li < bc;
+    const int64_t cc = b0 + min(col0 + li, bc - 1);
+    for (int i0 = 0; i0 < rows_r + rows_s; i0 += 64) {
+        C t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = min(i0 + 4 * u + lk, rows_r + rows_s - 1);
+            const int32_t g = gidx[i];
+            t[u] = x[(int64_t)(g >= 0 ? g : g0) * nrhs + cc];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + 4 * u + lk;
+            if (i < rows_r + rows_s) Xr[i * HF_LD + col0 + li] = (cv && gidx[i] >= 0) ? t[u] : C{0, 0};
+        }
+    }
+    __syncthreads();
+    V4 re[4], im[4];
+    // first product: x_r -= (T^* or M^*) x_s, row split
+    if (ns > 0) {
+        hf_rows<R>(re, im, UP ? TH : MH, nr, nr, ns, 0, Xs, w, ntl);
+        hf_store_rows<R, false>(re, im, Xr, nr, w, ntl);
+    }
+    __syncthreads();
+    // x_r <- (Linv or Linv^*) x_r, row split; every wave reads all rows first
+    hf_rows<R>(re, im, UP ? Li : LH, nr, nr, nr, UP ? 1 : 2, Xr, w, ntl);
+    __syncthreads();
+    hf_store_rows<R, true>(re, im, Xr, nr, w, ntl);
+    __syncthreads();
+    // x_s -= (M or T) x_r, column split
+    if (ns > 0 && col0 < bc) {
+        hf_cols<R>(re, im, UP ? Mm : Tm, ns, ns, nr, Xr, col0);
+        hf_sub_cols<R>(re, im, Xs, ns, col0);
+    }
+    // write back this wave's columns (x_s was last written by this wave, x_r before
+    // the last barrier)
+    if (cv) {
+        for (int i = lk; i < nr; i += 4) x[(int64_t)gidx[i] * nrhs + cc] = Xr[i * HF_LD + col0 + li];
+        for (int i = lk; i < ns; i += 4) x[(int64_t)gidx[rows_r + i] * nrhs + cc] = Xs[i * HF_LD + col0 + li];
+    }
+}
+
+bool hif_fused_fits(const HifStepDev &h) { return h.max_nr <= 64 && h.max_ns <= 64; }
+
+template <class R, bool UP>
+static void hif_fused_go(const HifStepDev &h, int rr, int rs, void *x, int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    const size_t lds = (size_t)(rr + rs) * HF_LD * sizeof(C) + (size_t)(rr + rs) * sizeof(int32_t);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_hif_fused<R, UP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  hif_lds_budget());
+        attr_set = true;
+    }
+    if ((int64_t)lds > hif_lds_budget()) throw std::runtime_error("fused skeletonization step exceeds LDS");
+    const dim3 g((unsigned)h.n_nodes, (unsigned)((nrhs + 63) / 64));
+    hipLaunchKernelGGL((k_hif_fused<R, UP>), g, dim3(256), lds, st, h.desc, h.idx, (const C *)h.mat,
+                       (const C *)h.matH, (C *)x, nrhs, rr, rs);
+}
+
+void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
+    if (h.n_nodes == 0) return;
+    if (!hif_fused_fits(h)) throw std::runtime_error("fused skeletonization step needs nr, ns <= 64");
+    // staged rows: whole 16-row tiles (the k loops read up to the next multiple of 4)
+    const int rr = std::max(16, (h.max_nr + 15) / 16 * 16), rs = std::max(16, (h.max_ns + 15) / 16 * 16);
+    if (dbl) { if (up) hif_fused_go<double, true>(h, rr, rs, x, nrhs, st); else hif_fused_go<double, false>(h, rr, rs, x, nrhs, st); }
+    else { if (up) hif_fused_go<float, true>(h, rr, rs, x, nrhs, st); else hif_fused_go<float, false>(h, rr, rs, x, nrhs, st); }
+    check_launch("hif step (fused)");
+}
+
 // Rows of a point-major block: out[i*nrhs + b] = x[idx[i]*nrhs + b] (with conversion), and back.
 template <class Ti, class To>
 __global__ void __launch_bounds__(256) k_rows_gather(const Ti *__restrict__ x, const int32_t *__restrict__ idx,

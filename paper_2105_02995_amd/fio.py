@@ -24,7 +24,7 @@ FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG, FIO_SOLVE_GMRES = 0, 1, 2, 3
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON,
           "1d_ex2": FIO_PHASE_1D_EX2}
 
-EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error"]
@@ -91,6 +91,7 @@ def load_library():
                                    ctypes.POINTER(ctypes.c_int)]
     lib.fio_inverse_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_gd_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_gd_apply_variant.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_inverse_dft.argtypes = [P, VP, VP, I64, I64, VP]
     lib.fio_solve.argtypes = [P, ctypes.POINTER(fio_solve_opts), ctypes.c_int, VP, VP, I64, I64,
                               ctypes.POINTER(fio_solve_info), VP]
@@ -233,6 +234,11 @@ def fio_inverse_dft(plan: Plan, fhat, f, nrhs: int, ld: int, stream=None):
 def fio_gd_apply(plan: Plan, dtype: int, x, y, nrhs: int, ld: int, stream=None):
     _check(load_library().fio_gd_apply(plan.handle, dtype, _ptr(x), _ptr(y), nrhs, ld,
                                        _stream(stream)))
+
+
+def fio_gd_apply_variant(plan: Plan, dtype: int, variant: int, x, y, nrhs: int, ld: int, stream=None):
+    _check(load_library().fio_gd_apply_variant(plan.handle, dtype, variant, _ptr(x), _ptr(y), nrhs, ld,
+                                               _stream(stream)))
 
 
 def fio_solve(plan: Plan, mode: int, dtype: int, u, out, nrhs: int, ld: int, tol: float = 0.0,
