@@ -93,7 +93,8 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     } else {
         const int64_t N = B.N;
         const int nt = p.nthreads;
-        A = [&](const cd *x, cd *y, int nr) {
+        // N and nt by value: the product outlives this block
+        A = [&B, &adj, N, nt](const cd *x, cd *y, int nr) {
             std::vector<cd> t((size_t)N * nr);
             host_chain_apply(B.fwd, x, t.data(), nr, nt);
             host_chain_apply(adj, t.data(), y, nr, nt);
