@@ -1,0 +1,55 @@
+"""Run-to-run determinism: every solve mode, repeated on the same plan and input,
+returns the same bits (no atomics in any reduction; column norms and dots are
+two-pass), and a batch solved in two halves equals the halves of the whole batch
+solved at once (columns are independent, tiles only pad).  A race on shared
+workspace or an order-dependent reduction would show up here."""
+import sys
+
+import numpy as np
+import pytest
+
+from fio_synth import gaussian_complex
+from paper_2105_02995_amd import fio as F
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from . import gpu_util as G  # noqa: E402
+
+_plan = {}
+
+
+def plan():
+    if "p" not in _plan:
+        print("building 1D N=4096 plan", flush=True)
+        _plan["p"] = F.fio_build(F.make_problem(1, 4096, "1d_ex1", eps=1e-6, device=0))
+    return _plan["p"]
+
+
+MODES = [(F.FIO_SOLVE_DIRECT, 0.0, 0), (F.FIO_SOLVE_REFINE, 0.0, 2), (F.FIO_SOLVE_PCG, 1e-8, 50),
+         (F.FIO_SOLVE_GMRES, 1e-8, 50)]
+
+
+@pytest.mark.parametrize("mode,tol,maxit", MODES)
+@pytest.mark.parametrize("dtype", [F.FIO_C64, F.FIO_C128])
+def test_repeated_solves_are_bitwise_equal(mode, tol, maxit, dtype):
+    p = plan()
+    u = gaussian_complex((4096, 40), 77)
+    print("mode %d dtype %d" % (mode, dtype), flush=True)
+    x1, _ = G.solve(p, mode, dtype, u, tol=tol, maxit=maxit)
+    x2, _ = G.solve(p, mode, dtype, u, tol=tol, maxit=maxit)
+    x3, _ = G.solve(p, mode, dtype, u, tol=tol, maxit=maxit)
+    assert np.array_equal(x1, x2) and np.array_equal(x2, x3)
+
+
+@pytest.mark.parametrize("mode,tol,maxit", MODES[:2])
+def test_split_batch_equals_whole_batch(mode, tol, maxit):
+    p = plan()
+    u = gaussian_complex((4096, 64), 78)
+    whole, _ = G.solve(p, mode, F.FIO_C64, u, tol=tol, maxit=maxit)
+    lo, _ = G.solve(p, mode, F.FIO_C64, u[:, :32], tol=tol, maxit=maxit)
+    hi, _ = G.solve(p, mode, F.FIO_C64, u[:, 32:], tol=tol, maxit=maxit)
+    assert np.array_equal(whole, np.concatenate([lo, hi], axis=1))
