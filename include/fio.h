@@ -111,6 +111,14 @@ typedef struct {
      * interpolation matrices) run on the plan's device unless this is nonzero or the
      * plan is host-only; both give factors of the same accuracy.                    */
     int host_construction;
+    /* 1D only (FIO_ERR_ARG for d = 2): Cholesky-prescaled skeletonization, the
+     * paper's alternative to the elimination step (section 4, 1D case): every node is
+     * first scaled by the inverse Cholesky factor of its diagonal block, the ID is
+     * taken on the scaled bases, and the elimination that remains acts on I + T^*T
+     * (always positive definite).  Gd then has two steps per level (the scaling, a
+     * node with redundant DOFs only, then the skeletonization).  Not stored by
+     * fio_save (the factors are).                                                  */
+    int prescale_skel;
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",

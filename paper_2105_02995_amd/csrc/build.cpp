@@ -57,6 +57,7 @@ fio_problem normalized_problem(const fio_problem &in) {
     if (p.d == 1 && p.leaf_h > p.n / 2) p.leaf_h = p.n / 2;
     if (p.d == 2 && p.leaf_h > p.n / 2) p.leaf_h = p.n / 2;
     if (p.oversample < 1) fail(FIO_ERR_ARG, "oversample must be positive");
+    if (p.prescale_skel && p.d != 1) fail(FIO_ERR_ARG, "prescaled skeletonization is built for 1D only");
     return p;
 }
 
@@ -108,6 +109,7 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     po.nthreads = p.nthreads;
     po.verbose = vb;
     po.allow_shift = p.strict_hpd == 0;
+    po.prescale = p.prescale_skel != 0;
     out.hif = (p.d == 1) ? build_hif_1d(A, B.N, po, p.eps_hif) : build_hif_2d(A, p.n, po, p.eps_hif);
     progress(vb, "inverse factors done: %zu steps, root %zu, %d shifted pivot blocks (%.1fs)", out.hif.steps.size(),
              out.hif.root_idx.size(), out.hif.shifted,

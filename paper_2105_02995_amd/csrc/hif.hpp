@@ -57,6 +57,12 @@ struct PeelOptions {
     // doubled until positive definite, when true; the build fails with
     // FIO_ERR_NOT_HPD when false.
     bool allow_shift = true;
+    // 1D only: Cholesky-prescaled skeletonization (section 4, the alternative after
+    // the 1D case): each node's diagonal block is first factored A_II = L L^* and the
+    // node scaled by L^{-1}, the ID is taken on Ubar L^{-*}, and the elimination that
+    // remains acts on I + T^* T.  Each level then has two steps: the scaling (a node
+    // with only redundant DOFs and Linv = L^{-1}) and the skeletonization.
+    bool prescale = false;
 };
 
 // 1D HODLR peeling of a Hermitian operator given only by products (section 3),

@@ -227,6 +227,118 @@ Active merge(const Active &a, const Active &b, const Mat &Ua, const Mat &Ub, con
     return m;
 }
 
+// ---- Cholesky-prescaled variant (section 4, the alternative to eq_sk_3) ----
+// The active state of a node also carries its bases in the scaled coordinates:
+// P[lp] (k_lp x n) stands for U_{lp;I}^* at every ancestor level lp, multiplied on the
+// right by the inverse-adjoint Cholesky factors of the scalings applied so far and
+// restricted to the surviving coordinates.  Coordinates live in the storage slots I.
+struct ActiveP {
+    std::vector<int> I;
+    Mat A;
+    std::vector<Mat> P;  // index lp = 1..l (P[0] unused)
+};
+
+// Scale, decompose, eliminate: returns the two node factors (scaling first).
+void skeletonize_prescaled(ActiveP &st, int l, double eps, double shift0, std::atomic<int> &nshift,
+                           HifNode &pre, HifNode &skn) {
+    const int n = (int)st.I.size();
+    // A_II = L L^* (the scaling); Hermitian part first
+    Mat Lf = st.A;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < j; ++i) {
+            const cd v = 0.5 * (Lf(i, j) + std::conj(Lf(j, i)));
+            Lf(i, j) = v;
+            Lf(j, i) = std::conj(v);
+        }
+    const double sh = cholesky_lower_shifted(Lf, shift0);
+    if (sh < 0) fail(FIO_ERR_NOT_HPD, "prescaled skeletonization: diagonal block is not HPD");
+    if (sh > 0) nshift.fetch_add(1);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < j; ++i) Lf(i, j) = 0.0;
+    const Mat Linv = tri_lower_inverse(Lf);
+    // scaled bases: P[lp] L^{-*}, stacked from level l down to 1 for the ID
+    int rows = 0;
+    for (int lp = l; lp >= 1; --lp) {
+        st.P[lp] = matmul(st.P[lp], Linv, 'N', 'C');
+        rows += st.P[lp].m;
+    }
+    Mat Ubar(rows, n);
+    int r0 = 0;
+    for (int lp = l; lp >= 1; --lp) {
+        for (int c = 0; c < n; ++c)
+            for (int k = 0; k < st.P[lp].m; ++k) Ubar(r0 + k, c) = st.P[lp](k, c);
+        r0 += st.P[lp].m;
+    }
+    std::vector<int> sk, rd;
+    Mat T;
+    if (rows == 0 || n == 0) {
+        for (int i = 0; i < n; ++i) rd.push_back(i);
+        T = Mat(0, n);
+    } else {
+        ColumnID id = column_id(Ubar, eps, 0, -1);
+        sk = id.skel;
+        rd = id.redund;
+        T = std::move(id.T);
+    }
+    const int ns = (int)sk.size(), nr = (int)rd.size();
+    // In the scaled coordinates A_II = I, so Z^* A Z (eq_sk) has Atilde_rr = I + T^* T
+    // (eigenvalues >= 1) and Atilde_sr = -T.
+    Mat Atr = Mat::eye(nr);
+    gemm_acc(Atr, T, T, 1.0, 'C', 'N');
+    Mat L2 = Atr;
+    if (!cholesky_lower(L2)) fail(FIO_ERR_NOT_HPD, "prescaled skeletonization: I + T^*T not HPD");
+    skn.Linv = tri_lower_inverse(L2);
+    Mat Ats(ns, nr);
+    for (int j = 0; j < nr; ++j)
+        for (int i = 0; i < ns; ++i) Ats(i, j) = -T(i, j);
+    skn.M = matmul(Ats, skn.Linv, 'N', 'C');
+    Mat Abar = Mat::eye(ns);
+    gemm_acc(Abar, skn.M, skn.M, -1.0, 'N', 'C');
+    skn.T = std::move(T);
+    for (int i : rd) skn.idx_r.push_back(st.I[i]);
+    for (int i : sk) skn.idx_s.push_back(st.I[i]);
+    pre.idx_r = st.I;
+    pre.T = Mat(0, n);
+    pre.Linv = Linv;
+    pre.M = Mat(0, n);
+    // surviving coordinates: the skeletons, with their scaled bases
+    for (int lp = l; lp >= 1; --lp) st.P[lp] = cols_of(st.P[lp], sk);
+    st.I = skn.idx_s;
+    st.A = std::move(Abar);
+}
+
+// Merge two scaled siblings at level l: the coupling is P_b[l]^* B P_a[l].
+ActiveP merge_prescaled(const ActiveP &a, const ActiveP &b, const Mat &Bp, int l) {
+    ActiveP m;
+    const int na = (int)a.I.size(), nb = (int)b.I.size();
+    m.I = a.I;
+    m.I.insert(m.I.end(), b.I.begin(), b.I.end());
+    m.A = Mat(na + nb, na + nb);
+    for (int j = 0; j < na; ++j)
+        for (int i = 0; i < na; ++i) m.A(i, j) = a.A(i, j);
+    for (int j = 0; j < nb; ++j)
+        for (int i = 0; i < nb; ++i) m.A(na + i, na + j) = b.A(i, j);
+    if (a.P[l].m > 0 && b.P[l].m > 0 && na > 0 && nb > 0) {
+        Mat Sba = matmul(matmul(b.P[l], Bp, 'C', 'N'), a.P[l]);  // nb x na
+        for (int j = 0; j < na; ++j)
+            for (int i = 0; i < nb; ++i) {
+                m.A(na + i, j) = Sba(i, j);
+                m.A(j, na + i) = std::conj(Sba(i, j));
+            }
+    }
+    m.P.assign(l, Mat());
+    for (int lp = 1; lp < l; ++lp) {
+        const Mat &pa = a.P[lp], &pb = b.P[lp];
+        Mat c(std::max(pa.m, pb.m), na + nb);
+        for (int j = 0; j < na; ++j)
+            for (int k = 0; k < pa.m; ++k) c(k, j) = pa(k, j);
+        for (int j = 0; j < nb; ++j)
+            for (int k = 0; k < pb.m; ++k) c(k, na + j) = pb(k, j);
+        m.P[lp] = std::move(c);
+    }
+    return m;
+}
+
 }  // namespace
 
 double power_norm(const BlockApply &A, int64_t N, int iters, uint64_t seed) {
@@ -255,6 +367,49 @@ HifFactors build_hif_1d(const BlockApply &A, int64_t N, const PeelOptions &po, d
     const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
     std::atomic<int> nshift(0);
     const int64_t nleaf = N / H.mh;
+    if (po.prescale) {
+        std::vector<ActiveP> sp(nleaf);
+        for (int64_t b = 0; b < nleaf; ++b) {
+            ActiveP &a = sp[b];
+            a.I.resize(H.mh);
+            for (int64_t i = 0; i < H.mh; ++i) a.I[i] = (int)(b * H.mh + i);
+            a.A = H.D[b];
+            a.P.assign(H.Lh + 1, Mat());
+            for (int lp = 1; lp <= H.Lh; ++lp) {
+                const int64_t an = b >> (H.Lh - lp);
+                const Mat &Ua = H.U[lp][an];
+                const int64_t start = an * (N >> lp);
+                Mat P(Ua.n, (int)H.mh);
+                for (int64_t c = 0; c < H.mh; ++c)
+                    for (int k = 0; k < Ua.n; ++k) P(k, (int)c) = std::conj(Ua((int)(b * H.mh + c - start), k));
+                a.P[lp] = std::move(P);
+            }
+        }
+        for (int l = H.Lh; l >= 1; --l) {
+            const int64_t nn = (int64_t)1 << l;
+            HifStep pre, skl;
+            pre.nodes.resize(nn);
+            skl.nodes.resize(nn);
+            parallel_for(nn, po.nthreads, [&](int64_t v) {
+                skeletonize_prescaled(sp[v], l, eps_hif, shift0, nshift, pre.nodes[v], skl.nodes[v]);
+            });
+            F.steps.push_back(std::move(pre));
+            F.steps.push_back(std::move(skl));
+            std::vector<ActiveP> up(nn / 2);
+            parallel_for(nn / 2, po.nthreads, [&](int64_t p) {
+                up[p] = merge_prescaled(sp[2 * p], sp[2 * p + 1], H.B[l][p], l);
+            });
+            sp.swap(up);
+        }
+        F.root_idx = sp[0].I;
+        if (!F.root_idx.empty()) {
+            const double sh = hpd_inverse_shifted(sp[0].A, F.A0inv, shift0);
+            if (sh < 0) fail(FIO_ERR_NOT_HPD, "top-level block is not HPD");
+            if (sh > 0) nshift.fetch_add(1);
+        }
+        F.shifted = nshift.load();
+        return F;
+    }
     std::vector<Active> st(nleaf);
     for (int64_t b = 0; b < nleaf; ++b) {
         st[b].I.resize(H.mh);

@@ -45,7 +45,8 @@ class fio_problem(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("device", ctypes.c_int), ("nthreads", ctypes.c_int),
                 ("verbose", ctypes.c_int), ("amp_sigma2", ctypes.c_double), ("amp_terms", ctypes.c_int),
                 ("amp_x", ctypes.c_double * FIO_MAX_AMP_TERMS), ("amp_eta", ctypes.c_double * FIO_MAX_AMP_TERMS),
-                ("strict_hpd", ctypes.c_int), ("host_construction", ctypes.c_int)]
+                ("strict_hpd", ctypes.c_int), ("host_construction", ctypes.c_int),
+                ("prescale_skel", ctypes.c_int)]
 
 
 class fio_solve_opts(ctypes.Structure):

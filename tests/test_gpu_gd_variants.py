@@ -71,3 +71,23 @@ def test_variant_out_of_range_is_an_argument_error(tmp_path):
     with pytest.raises(F.FioError) as e:
         F.fio_gd_apply_variant(plan, F.FIO_C128, 5, X, X, 4, 4096, G.stream())
     assert e.value.status == 1
+
+
+def test_prescaled_factors_on_every_kernel(tmp_path):
+    """Cholesky-prescaled skeletonization (1D): its scaling steps (nodes with only
+    redundant DOFs) and skeletonization steps run on every kernel, tightly against the
+    saved factors, and the direct inverse meets 10 eps against the oracle."""
+    eps = 1e-6
+    plan = F.fio_build(F.make_problem(1, 4096, "1d_ex1", eps=eps, device=0, prescale_skel=1))
+    path = str(tmp_path / "pre.fio")
+    F.fio_save(plan, path)
+    f = FF.read(path)
+    x = gaussian_complex((4096, 48), 91)
+    ref = FF.from_tree(f, FF.gd(f, FF.to_tree(f, x)))
+    for variant in (-1, 0, 1, 2, 3, 4):
+        log("prescaled Gd variant %d" % variant)
+        assert O.rel_err(gd_gpu(plan, F.FIO_C128, variant, x), ref).max() < 1e-12
+        assert O.rel_err(gd_gpu(plan, F.FIO_C64, variant, x), ref).max() < 1e-5
+    K = O.dense_K(O.OracleProblem(1, 4096, "1d_ex1", 16.0))
+    u = K @ x[:, :8]
+    assert O.rel_err(G.inverse(plan, F.FIO_C128, u), x[:, :8]).max() < 10 * eps

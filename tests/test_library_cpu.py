@@ -225,3 +225,43 @@ def test_c_example_is_built_and_checks_its_arguments():
     assert os.path.exists(exe)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 2 and "usage" in r.stderr
+
+
+def test_prescaled_skeletonization_matches_the_oracle_and_the_standard_inverse(tmp_path):
+    """Cholesky-prescaled skeletonization (section 4, the alternative to the
+    elimination step): two steps per level, the first a pure scaling (only
+    redundant DOFs, lower-triangular L^{-1}); Gd Hermitian positive; Gd Kd^* u within
+    10 eps of the oracle's LU solve, and within eps of the standard variant's Gd."""
+    eps = 1e-6
+    (tmp_path / "s").mkdir()
+    _, fs, _ = _host_plan(tmp_path / "s", n=1024, eps=eps)
+    _, fp, _ = _host_plan(tmp_path, n=1024, eps=eps, prescale_skel=1)
+    assert len(fp["steps"]) == 2 * len(fs["steps"])
+    for k, nodes in enumerate(fp["steps"]):
+        if k % 2 == 0:  # the scaling step of a level
+            for nd in nodes:
+                assert nd["s"].size == 0
+                assert np.allclose(np.triu(nd["Linv"], 1), 0)
+    x, y = gaussian_complex(1024, 3), gaussian_complex(1024, 4)
+    a, b = np.vdot(y, FF.gd(fp, x)), np.vdot(FF.gd(fp, y), x)
+    assert abs(a - b) < 1e-10 * abs(a) and np.vdot(x, FF.gd(fp, x)).real > 0
+    p = O.OracleProblem(1, 1024, "1d_ex1", 16.0)
+    K = O.dense_K(p)
+    u = K @ gaussian_complex((1024, 3), 1001)
+    ref = O.solve_dense(p, u, K)
+    assert O.rel_err(FF.inverse(fp, u), ref).max() < 10 * eps
+    assert O.rel_err(FF.inverse(fp, u), FF.inverse(fs, u)).max() < eps
+
+
+def test_prescaled_identity_phase_inverse_is_the_dft(tmp_path):
+    """Phi = x.xi: S = N I, so the scaling is N^{-1/2} I and no DOF survives."""
+    _, f, _ = _host_plan(tmp_path, phase="linear", prescale_skel=1)
+    assert f["root"].size == 0
+    u = gaussian_complex(256, 5)
+    assert O.rel_err(FF.inverse(f, u), O.dft(u, 1, 256)).max() < 1e-6
+
+
+def test_prescaled_skeletonization_is_one_dimensional_only():
+    with pytest.raises(F.FioError) as e:
+        F.fio_build(F.make_problem(2, 16, "2d_radon", eps=1e-4, device=-1, prescale_skel=1))
+    assert e.value.status == 1
