@@ -323,7 +323,9 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
 // per workgroup: stage-a blocks, stage-b blocks, then for each stage-b block the
 // workgroup slot of each of its fan_b <= 2 inputs; -1 pads).  Wave w computes
 // stage-a block w of the workgroup into LDS, then stage-b block w from LDS, so
-// the intermediate coefficients never leave the compute unit.
+// the intermediate coefficients never leave the compute unit.  LDS holds only the
+// r_mid valid rows of each block (dynamic size 4 * r_mid * 16*NT entries), which
+// at ranks 22-25 lets three workgroups share a compute unit instead of two.
 template <class R, int MT, int NT>
 __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__ tab, int r_mid,
                                                      int r_in_a, int fan_a,
@@ -336,8 +338,9 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
                                                      int64_t n_wg, int nchunks) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
-    constexpr int ROWS = 16 * MT, COLS = 16 * NT;
-    __shared__ C mid[4][ROWS][COLS];
+    constexpr int COLS = 16 * NT;
+    extern __shared__ char smem_raw[];
+    C *mid = reinterpret_cast<C *>(smem_raw);   // [4][r_mid][COLS]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     int64_t g;
@@ -360,18 +363,20 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+            for (int v = 0; v < 4; ++v) {
+                const int row = mt * 16 + MF<R>::drow(lk, v);
+                if (row >= r_mid) continue;
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    mid[w][mt * 16 + MF<R>::drow(lk, v)][nt * 16 + li] = acc.get(mt, nt, v);
+                for (int nt = 0; nt < NT; ++nt) mid[((int64_t)w * r_mid + row) * COLS + nt * 16 + li] = acc.get(mt, nt, v);
+            }
     }
     __syncthreads();
     const int bb = t[4 + w];
     if (bb < 0) return;  // wave-uniform, after the only barrier
     const int Kb = fan_b * r_mid;
-    const Off4 off{(int64_t)t[8 + 2 * w] * ROWS * COLS, fan_b > 1 ? (int64_t)t[9 + 2 * w] * ROWS * COLS : 0, 0, 0};
+    const Off4 off{(int64_t)t[8 + 2 * w] * r_mid * COLS, fan_b > 1 ? (int64_t)t[9 + 2 * w] * r_mid * COLS : 0, 0, 0};
     mfma_block<R, MT, NT>(acc, A_b + (int64_t)bb * r_out_b * Kb, r_out_b, r_mid, Kb, 0, ncols,
-                          &mid[0][0][0], off, (int64_t)COLS);
+                          mid, off, (int64_t)COLS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -447,7 +452,8 @@ template <class R, int MT, int NT>
 static void launch_pair(const StagePairDev &p, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
     const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
-    hipLaunchKernelGGL((k_stage2_mfma<R, MT, NT>), dim3(xcd_grid(p.n_wg, nch)), dim3(256), 0, st, p.tab,
+    const size_t lds = (size_t)4 * p.a.r_out * 16 * NT * sizeof(C);
+    hipLaunchKernelGGL((k_stage2_mfma<R, MT, NT>), dim3(xcd_grid(p.n_wg, nch)), dim3(256), lds, st, p.tab,
                        p.a.r_out, p.a.r_in, p.a.fan, p.a.idx, (const C *)p.a.A, p.b.r_out, p.b.fan,
                        (const C *)p.b.A, (const C *)x, (C *)y, nrhs, p.n_wg, nch);
 }
