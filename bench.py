@@ -152,6 +152,7 @@ def serve_main(args):
 
 VNAME = {1: (1, 4), 2: (2, 4), 3: (1, 2), 4: (2, 2), 5: (1, 1), 6: (2, 1)}
 PAIR_NT = {1: 1, 2: 2, 3: 4}
+PAIR_STACKED = 4  # fused pair with sibling blocks stacked into one operand
 
 
 def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
@@ -202,7 +203,10 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
         flops = sum(8.0 * io(k)[0]["nnz"] * nrhs for k in ks)
         byts = sum(io(k)[0]["nnz"] * csize + 4 * io(k)[3] for k in ks)
         byts += (io(ks[0])[1] + io(ks[-1])[2]) * nrhs * csize
-        if count == 2:
+        if count == 2 and v == PAIR_STACKED:
+            rmax = max(io(k)[0]["r_out"] if op == F.FIO_OP_K else io(k)[0]["r_in"] for k in ks)
+            name = "k_stage2s_mfma<%s, %d, %d>" % (r, 2 if dtype == F.FIO_C64 else 1, 3 if rmax <= 24 else 4)
+        elif count == 2:
             mt = 2 if max(io(k)[0]["r_out"] if op == F.FIO_OP_K else io(k)[0]["r_in"] for k in ks) > 16 else 1
             name = "k_stage2_mfma<%s, %d, %d>" % (r, mt, PAIR_NT[v])
         elif v == 0:

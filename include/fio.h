@@ -251,6 +251,15 @@ fio_status fio_stage_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype,
 fio_status fio_stage_pair_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x,
                                 void *y, int64_t nrhs, void *hip_stream);
 
+/* The same two stages with one kernel variant forced: 1/2/3 the fused pair with
+ * 16/32/64 columns per wave (3 for FIO_C64 only), 4 the stacked form (two sibling
+ * blocks that read the same inputs computed as one operand of 16-row tiles: three
+ * up to rank 24, four up to rank 32).  For tests and measurement.  Asynchronous.  Errors:
+ * FIO_ERR_ARG (variant or stage out of range), FIO_ERR_UNSUPPORTED (the stages
+ * cannot run fused, or not stacked). */
+fio_status fio_stage_pair_apply_variant(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int variant,
+                                        const void *x, void *y, int64_t nrhs, void *hip_stream);
+
 /* The launches that an apply of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) makes at this
  * dtype and nrhs: launch j runs n_stages[j] (1 or 2) consecutive factors from
  * first_stage[j] with kernel variant variant[j] (single factor: the codes of

@@ -83,10 +83,57 @@ struct DHifStore {
 // groups hold at most fan^2 blocks.  Whole groups are packed into workgroups of at
 // most four stage-a and four stage-b blocks.
 struct DPair {
-    DBuf tab;
-    int64_t n_wg = 0;
+    DBuf tab, tab_s;
+    int64_t n_wg = 0, n_wg_s = 0;
     bool ok = false;
 };
+
+// Table of the stacked variant: one closed group per workgroup, whose stage-a blocks
+// and stage-b blocks each split into two pairs of siblings (equal input lists).
+// Returns false if some group does not.
+bool build_stacked_table(const Stage &a, const Stage &b, const std::vector<int32_t> &tab,
+                         std::vector<int32_t> &out) {
+    out.clear();
+    if (!stage_pair_stackable(a.r_out, b.r_out) || b.fan > 2) return false;
+    auto same_in = [](const Stage &s, int32_t x, int32_t y) {
+        for (int q = 0; q < s.fan; ++q)
+            if (s.in_idx[(int64_t)x * s.fan + q] != s.in_idx[(int64_t)y * s.fan + q]) return false;
+        return true;
+    };
+    // pair up four blocks (p[0..3]) into sibling pairs; false if impossible
+    auto pairs = [&](const Stage &s, const int32_t *p, int32_t *o) {
+        for (int i = 0; i < 4; ++i)
+            if (p[i] < 0) return false;
+        const int other[3][2] = {{2, 3}, {1, 3}, {1, 2}};
+        for (int j = 1; j < 4; ++j) {
+            if (!same_in(s, p[0], p[j])) continue;
+            const int u = other[j - 1][0], v = other[j - 1][1];
+            if (!same_in(s, p[u], p[v])) continue;
+            o[0] = p[0]; o[1] = p[j]; o[2] = p[u]; o[3] = p[v];
+            return true;
+        }
+        return false;
+    };
+    for (size_t g = 0; g < tab.size(); g += 16) {
+        const int32_t *t = tab.data() + g;
+        int32_t w[16];
+        for (int i = 0; i < 16; ++i) w[i] = -1;
+        if (!pairs(a, t, w) || !pairs(b, t + 4, w + 4)) return false;
+        for (int pr = 0; pr < 2; ++pr) {
+            const int32_t o = w[4 + 2 * pr];
+            for (int q = 0; q < b.fan; ++q) {
+                const int32_t m = b.in_idx[(int64_t)o * b.fan + q];
+                int slot = -1;
+                for (int i = 0; i < 4; ++i)
+                    if (w[i] == m) slot = i;
+                if (slot < 0) return false;
+                w[8 + 2 * pr + q] = slot;
+            }
+        }
+        out.insert(out.end(), w, w + 16);
+    }
+    return true;
+}
 
 bool build_pair_table(const Stage &a, const Stage &b, std::vector<int32_t> &tab) {
     tab.clear();
@@ -224,6 +271,11 @@ void upload_pairs(const std::vector<Stage> &st, std::vector<DPair> &d) {
         d[s].tab.upload(tab.data(), tab.size() * sizeof(int32_t));
         d[s].n_wg = (int64_t)tab.size() / 16;
         d[s].ok = true;
+        std::vector<int32_t> ts;
+        if (build_stacked_table(st[s], st[s + 1], tab, ts)) {
+            d[s].tab_s.upload(ts.data(), ts.size() * sizeof(int32_t));
+            d[s].n_wg_s = (int64_t)ts.size() / 16;
+        }
     }
 }
 
@@ -352,6 +404,8 @@ StagePairDev pair_view(fio_plan p, bool fwd, bool dbl, int s) {
     v.b = ds[s + 1].view(dbl, hs[s + 1]);
     v.tab = (const int32_t *)pr[s].tab.p;
     v.n_wg = pr[s].n_wg;
+    v.tab_s = (const int32_t *)pr[s].tab_s.p;
+    v.n_wg_s = pr[s].n_wg_s;
     return v;
 }
 
@@ -636,6 +690,28 @@ fio_status fio_stage_pair_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, 
     });
 }
 
+fio_status fio_stage_pair_apply_variant(fio_plan p, fio_op op, int stage, fio_dtype dt, int variant, const void *x,
+                                        void *y, int64_t nrhs, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, p ? p->host.N : 0, x, y);
+        if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        const bool fwd = op == FIO_OP_K;
+        const bool dbl = dt == FIO_C128;
+        const auto &pr = fwd ? p->pfwd : p->padj;
+        if (stage < 0 || stage >= (int)pr.size()) fail(FIO_ERR_ARG, "stage out of range");
+        if (variant < 1 || (variant > stage_pair_variants(dbl) && variant != STAGE_PAIR_STACKED))
+            fail(FIO_ERR_ARG, "fused pair variant out of range");
+        if (!pr[stage].ok) fail(FIO_ERR_UNSUPPORTED, "these two stages cannot run fused");
+        const StagePairDev pv = pair_view(p, fwd, dbl, stage);
+        if (variant == STAGE_PAIR_STACKED && !(pv.tab_s && stage_pair_stackable(pv.a.r_out, pv.b.r_out)))
+            fail(FIO_ERR_UNSUPPORTED, "these two stages cannot run stacked");
+        if (nrhs == 0) return;
+        HIPC(hipSetDevice(p->device));
+        launch_stage_pair(pv, dbl, variant, x, y, (int)nrhs, (hipStream_t)stream);
+    });
+}
+
 fio_status fio_chain_schedule(fio_plan p, fio_op op, fio_dtype dt, int64_t nrhs, int cap, int *n_launch,
                               int *first_stage, int *n_stages, int *variant) {
     return guard([&] {
@@ -719,7 +795,10 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                 one_ms[s] = best_ms;
                 if (s + 1 < S && pr[s].ok && nr >= 8) {
                     const StagePairDev pv = pair_view(p, fwd, dbl, s);
-                    for (int v = 1; v <= stage_pair_variants(dbl); ++v) {
+                    std::vector<int> vs;
+                    for (int v = 1; v <= stage_pair_variants(dbl); ++v) vs.push_back(v);
+                    if (pv.tab_s && stage_pair_stackable(pv.a.r_out, pv.b.r_out)) vs.push_back(STAGE_PAIR_STACKED);
+                    for (int v : vs) {
                         const float ms = timeit([&] { launch_stage_pair(pv, dbl, v, p->P.p, p->Q.p, nr, st); });
                         progress(vb, "tune %s %s pair (%d,%d) variant %d: %.4f ms", dbl ? "c128" : "c64",
                                  fwd ? "K" : "KH", s, s + 1, v, ms / reps);

@@ -225,35 +225,46 @@ template <class R, int MT, int NT> struct Acc {
     __device__ __forceinline__ C get(int mt, int nt, int v) const { return C{re[mt][nt][v], im[mt][nt][v]}; }
 };
 
+// The product with explicit per-lane row offsets: row tile mt of this lane reads
+// the factor at Ao + rowc[mt] + k * lda (column-major, leading dimension lda).
 template <class R, int MT, int NT, class P>
-__device__ __forceinline__ void mfma_block(Acc<R, MT, NT> &acc, const typename MF<R>::C *__restrict__ Ao, int r_out,
-                                           int r_in, int K, int mrow0, int ncols, const P *__restrict__ xb,
-                                           const Off4 &off, int64_t ld) {
+__device__ __forceinline__ void mfma_rows(Acc<R, MT, NT> &acc, const typename MF<R>::C *__restrict__ Ao, int lda,
+                                          int r_in, int K, const int (&rowc)[MT], int ncols,
+                                          const P *__restrict__ xb, const Off4 &off, int64_t ld) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     acc.zero();
-    int colc[NT], rowc[MT];
+    int colc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) colc[nt] = min(nt * 16 + li, ncols - 1);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) rowc[mt] = min(mrow0 + mt * 16 + li, r_out - 1);
     KWalk<R, P> w;
     w.k = lk;
     w.q = lk / r_in;
     w.e = lk - w.q * r_in;
-    w.ap = Ao + (int64_t)lk * r_out;
+    w.ap = Ao + (int64_t)lk * lda;
     w.xp = xb + off(w.q) + (int64_t)w.e * ld;
     Frag<R, MT, NT> f[STAGE_PF];
 #pragma unroll
-    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, r_out, colc, rowc);
+    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, lda, colc, rowc);
     for (int k0 = 0; k0 < K; k0 += 4 * STAGE_PF) {
 #pragma unroll
         for (int j = 0; j < STAGE_PF; ++j) {
             if (k0 + 4 * j >= K) break;  // wave-uniform
-            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, r_out, colc, rowc);
+            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, lda, colc, rowc);
             acc.mma(f[j]);
         }
     }
+}
+
+template <class R, int MT, int NT, class P>
+__device__ __forceinline__ void mfma_block(Acc<R, MT, NT> &acc, const typename MF<R>::C *__restrict__ Ao, int r_out,
+                                           int r_in, int K, int mrow0, int ncols, const P *__restrict__ xb,
+                                           const Off4 &off, int64_t ld) {
+    const int li = threadIdx.x & 15;
+    int rowc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) rowc[mt] = min(mrow0 + mt * 16 + li, r_out - 1);
+    mfma_rows<R, MT, NT>(acc, Ao, r_out, r_in, K, rowc, ncols, xb, off, ld);
 }
 
 // XCD-aware workgroup order.  Workgroups of a launch are dispatched to the eight
@@ -390,6 +401,96 @@ __global__ void __launch_bounds__(256) k_stage2_mfma(const int32_t *__restrict__
             }
 }
 
+// Stacked variant of the fused pair.  Two sibling blocks of one stage read the same
+// inputs, so their rows are stacked into one 2r-row operand of MTS 16-row tiles
+// (three for r <= 24: at r = 24 no padding, against 2 x 32 rows for the blocks
+// apart, 25% fewer MFMAs; four for r <= 32).  Table (16 int32 per workgroup, one closed group): the
+// two stage-a sibling pairs, the two stage-b sibling pairs, then for each stage-b
+// pair the workgroup slots (0..3, position in the stage-a list) of its fan_b inputs.
+// Wave w takes sibling pair w & 1 and the column half w >> 1 (16*NT columns each).
+template <class R, int NT, int MTS>
+__global__ void __launch_bounds__(256) k_stage2s_mfma(const int32_t *__restrict__ tab, int r_mid,
+                                                      int r_in_a, int fan_a,
+                                                      const int32_t *__restrict__ idx_a,
+                                                      const typename MF<R>::C *__restrict__ A_a,
+                                                      int r_out_b, int fan_b,
+                                                      const typename MF<R>::C *__restrict__ A_b,
+                                                      const typename MF<R>::C *__restrict__ x,
+                                                      typename MF<R>::C *__restrict__ y, int nrhs,
+                                                      int64_t n_wg, int nchunks) {
+    using C = typename MF<R>::C;
+    constexpr int HC = 16 * NT, COLS = 2 * HC;
+    extern __shared__ char smem_raw[];
+    C *mid = reinterpret_cast<C *>(smem_raw);   // [4][r_mid][COLS]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int pr = w & 1, half = w >> 1;
+    int64_t g;
+    int chunk;
+    xcd_order(n_wg, nchunks, g, chunk);
+    if (g >= n_wg) return;  // workgroup-uniform, before the barrier
+    const int32_t *t = tab + g * 16;
+    const int c0 = half * HC;
+    const int n0 = chunk * COLS + c0;
+    const int ncols = nrhs - n0;
+    Acc<R, MTS, NT> acc;
+    const int a0 = t[2 * pr], a1 = t[2 * pr + 1];
+    if (a0 >= 0 && ncols > 0) {  // wave-uniform
+        const int Ka = fan_a * r_in_a;
+        int rowc[MTS];
+#pragma unroll
+        for (int mt = 0; mt < MTS; ++mt) {
+            const int row = min(mt * 16 + li, 2 * r_mid - 1);
+            rowc[mt] = (row < r_mid) ? row : (a1 - a0) * r_mid * Ka + row - r_mid;
+        }
+        const int32_t *io = idx_a + (int64_t)a0 * fan_a;
+        const int64_t bs = (int64_t)r_in_a * nrhs;
+        const Off4 off{io[0] * bs, fan_a > 1 ? io[1] * bs : 0, fan_a > 2 ? io[2] * bs : 0,
+                       fan_a > 3 ? io[3] * bs : 0};
+        mfma_rows<R, MTS, NT>(acc, A_a + (int64_t)a0 * r_mid * Ka, r_mid, r_in_a, Ka, rowc, ncols, x + n0, off,
+                              (int64_t)nrhs);
+#pragma unroll
+        for (int mt = 0; mt < MTS; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = mt * 16 + MF<R>::drow(lk, v);
+                if (row >= 2 * r_mid) continue;
+                const int slot = 2 * pr + (row >= r_mid ? 1 : 0);
+                const int rr = row >= r_mid ? row - r_mid : row;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    mid[((int64_t)slot * r_mid + rr) * COLS + c0 + nt * 16 + li] = acc.get(mt, nt, v);
+            }
+    }
+    __syncthreads();
+    const int b0 = t[4 + 2 * pr], b1 = t[5 + 2 * pr];
+    if (b0 < 0 || ncols <= 0) return;  // wave-uniform, after the only barrier
+    const int Kb = fan_b * r_mid;
+    int rowc[MTS];
+#pragma unroll
+    for (int mt = 0; mt < MTS; ++mt) {
+        const int row = min(mt * 16 + li, 2 * r_out_b - 1);
+        rowc[mt] = (row < r_out_b) ? row : (b1 - b0) * r_out_b * Kb + row - r_out_b;
+    }
+    const Off4 off{(int64_t)t[8 + 2 * pr] * r_mid * COLS, fan_b > 1 ? (int64_t)t[9 + 2 * pr] * r_mid * COLS : 0, 0, 0};
+    mfma_rows<R, MTS, NT>(acc, A_b + (int64_t)b0 * r_out_b * Kb, r_out_b, r_mid, Kb, rowc, ncols, mid + c0, off,
+                          (int64_t)COLS);
+#pragma unroll
+    for (int mt = 0; mt < MTS; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = mt * 16 + MF<R>::drow(lk, v);
+            if (row >= 2 * r_out_b) continue;
+            const int blk = row >= r_out_b ? b1 : b0;
+            const int rr = row >= r_out_b ? row - r_out_b : row;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int col = n0 + nt * 16 + li;
+                if (col < nrhs) y[((int64_t)blk * r_out_b + rr) * nrhs + col] = acc.get(mt, nt, v);
+            }
+        }
+}
+
 template <class R, int MT, int NT>
 static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
@@ -464,11 +565,35 @@ bool stage_pair_fusable(int r_mid, int r_out_b, int fan_b) {
 
 int stage_pair_variants(bool dbl) { return dbl ? 2 : 3; }
 
+bool stage_pair_stackable(int r_mid, int r_out_b) { return r_mid >= 1 && r_mid <= 32 && r_out_b >= 1 && r_out_b <= 32; }
+
+template <class R, int NT, int MTS>
+static void launch_pair_stacked(const StagePairDev &p, const void *x, void *y, int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    constexpr int COLS = 32 * NT;
+    const int nch = (nrhs + COLS - 1) / COLS;
+    const size_t lds = (size_t)4 * p.a.r_out * COLS * sizeof(C);
+    hipLaunchKernelGGL((k_stage2s_mfma<R, NT, MTS>), dim3(xcd_grid(p.n_wg_s, nch)), dim3(256), lds, st, p.tab_s,
+                       p.a.r_out, p.a.r_in, p.a.fan, p.a.idx, (const C *)p.a.A, p.b.r_out, p.b.fan,
+                       (const C *)p.b.A, (const C *)x, (C *)y, nrhs, p.n_wg_s, nch);
+}
+
 void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void *x, void *y, int nrhs,
                        hipStream_t st) {
     if (!stage_pair_fusable(p.a.r_out, p.b.r_out, p.b.fan) || p.b.r_in != p.a.r_out || p.a.fan > 4 ||
         p.a.r_in < 1)
         throw std::runtime_error("stage pair cannot be fused");
+    if (variant == STAGE_PAIR_STACKED) {
+        if (!p.tab_s || !stage_pair_stackable(p.a.r_out, p.b.r_out))
+            throw std::runtime_error("stage pair cannot run stacked");
+        // 64 columns per workgroup for complex64, 32 for complex128 (LDS); three row
+        // tiles per sibling pair up to rank 24, four up to 32
+        const bool m3 = std::max(p.a.r_out, p.b.r_out) <= 24;
+        if (dbl) { if (m3) launch_pair_stacked<double, 1, 3>(p, x, y, nrhs, st); else launch_pair_stacked<double, 1, 4>(p, x, y, nrhs, st); }
+        else { if (m3) launch_pair_stacked<float, 2, 3>(p, x, y, nrhs, st); else launch_pair_stacked<float, 2, 4>(p, x, y, nrhs, st); }
+        check_launch("fused stage pair (stacked)");
+        return;
+    }
     const bool m2 = std::max(p.a.r_out, p.b.r_out) > 16;
     if (variant < 1 || variant > stage_pair_variants(dbl)) variant = 2;
     if (dbl) {

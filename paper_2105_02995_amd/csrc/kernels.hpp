@@ -28,11 +28,19 @@ struct StagePairDev {
     StageDev a, b;
     const int32_t *tab = nullptr;
     int64_t n_wg = 0;
+    // stacked variant: one closed group of two sibling pairs per stage per workgroup
+    // (16 int32: stage-a pairs, stage-b pairs, input slots of each stage-b pair)
+    const int32_t *tab_s = nullptr;
+    int64_t n_wg_s = 0;
 };
 // Whether two stages with these shapes can run fused (ranks <= 32, fan of b <= 2).
 bool stage_pair_fusable(int r_mid, int r_out_b, int fan_b);
 // Fused kernel variants: 1: 16 columns per wave, 2: 32, 3: 64 (complex64 only).
 int stage_pair_variants(bool dbl);
+// Variant number of the stacked fused pair (sibling blocks sharing their inputs
+// stacked into one operand of 16-row tiles; ranks <= 32 and a stacked table).
+constexpr int STAGE_PAIR_STACKED = 4;
+bool stage_pair_stackable(int r_mid, int r_out_b);
 void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void *x, void *y, int nrhs,
                        hipStream_t st);
 

@@ -24,7 +24,7 @@ FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG, FIO_SOLVE_GMRES = 0, 1, 2, 3
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON,
           "1d_ex2": FIO_PHASE_1D_EX2}
 
-EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error"]
@@ -85,6 +85,8 @@ def load_library():
     lib.fio_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_stage_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
     lib.fio_stage_pair_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
+    lib.fio_stage_pair_apply_variant.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP,
+                                                 I64, VP]
     IP = ctypes.POINTER(ctypes.c_int)
     lib.fio_chain_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, I64, ctypes.c_int, IP, IP, IP, IP]
     lib.fio_autotune.argtypes = [P, ctypes.c_int, I64, ctypes.c_int, VP]
@@ -196,6 +198,12 @@ def fio_apply(plan: Plan, op: int, dtype: int, x, y, nrhs: int, ld: int, stream=
 def fio_stage_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
     _check(load_library().fio_stage_apply(plan.handle, op, stage, dtype, _ptr(x), _ptr(y), nrhs,
                                           _stream(stream)))
+
+
+def fio_stage_pair_apply_variant(plan: Plan, op: int, stage: int, dtype: int, variant: int, x, y, nrhs: int,
+                                 stream=None):
+    _check(load_library().fio_stage_pair_apply_variant(plan.handle, op, stage, dtype, variant, _ptr(x), _ptr(y),
+                                                       nrhs, _stream(stream)))
 
 
 def fio_stage_pair_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):

@@ -105,3 +105,42 @@ def test_tuned_schedule_apply_matches_oracle(plan):
     F.fio_autotune(plan, F.FIO_C64, 48, 2, G.stream())
     y = G.apply(plan, F.FIO_OP_K, F.FIO_C64, x)
     assert O.rel_err(y[rows], ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [F.FIO_C64, F.FIO_C128])
+@pytest.mark.parametrize("op", [F.FIO_OP_K, F.FIO_OP_KH])
+@pytest.mark.parametrize("B", [16, 40, 64, 100])
+def test_every_fused_variant_equals_two_single_launches(plan, dtype, op, B):
+    """Each fused-pair kernel variant (16/32/64 columns per wave, and the stacked form
+    where two sibling blocks sharing their inputs form one three-tile operand) equals
+    the two stages launched one by one, full and ragged batches."""
+    S = F.fio_plan_stats(plan)["n_stages"]
+    ct = G.CT[dtype]
+    tol = 1e-5 if dtype == F.FIO_C64 else 1e-13
+    variants = [1, 2, 4] + ([3] if dtype == F.FIO_C64 else [])
+    stacked = 0
+    for s in range(S - 1):
+        n_in, n_mid = _stage_io(plan, op, s)
+        _, n_out = _stage_io(plan, op, s + 1)
+        x = torch.from_numpy(np.ascontiguousarray(gaussian_complex((n_in, B), 70 + s))).to(ct).cuda()
+        mid = torch.zeros((n_mid, B), dtype=ct, device="cuda")
+        ref = torch.zeros((n_out, B), dtype=ct, device="cuda")
+        F.fio_stage_apply(plan, op, s, dtype, x, mid, B, G.stream())
+        F.fio_stage_apply(plan, op, s + 1, dtype, mid, ref, B, G.stream())
+        torch.cuda.synchronize()
+        r = ref.cpu().numpy()
+        for v in variants:
+            out = torch.full((n_out, B), float("nan"), dtype=ct, device="cuda")
+            try:
+                F.fio_stage_pair_apply_variant(plan, op, s, dtype, v, x, out, B, G.stream())
+            except F.FioError as e:
+                assert e.status == 6, e  # not fusable, or not stackable
+                continue
+            torch.cuda.synchronize()
+            a = out.cpu().numpy()
+            err = np.abs(a - r).max() / max(np.abs(r).max(), 1e-300)
+            log("op=%d dtype=%d B=%d pair (%d,%d) variant %d: rel diff %.2e" % (op, dtype, B, s, s + 1, v, err))
+            assert np.isfinite(a).all()
+            assert err < tol
+            stacked += v == 4
+    assert stacked >= 1  # ranks of this plan allow the stacked form somewhere
