@@ -31,14 +31,24 @@ PEAK_HBM_GBS = 8000.0
 # profiles/), valid only for the kernel source and the factor set (its nonzero
 # count) they were measured on.
 TRAFFIC = {
-    "k_stage2_mfma<float, 2, 4>": {
-        "bytes": (113965.40 * 2 + 91136.00) * 1024,
-        "kernels_sha256": "b1d9f0cd23f3016ffdb6d00e4e4499af4c3f5bec29601f708bd25dccbbca6ae3",
+    "k_stage2_mfma<double, 2, 2>": {
+        "bytes": (247082.66 * 2 + 204800.00) * 1024,
+        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
         "bf_nnz": 109109248,
     },
-    "k_stage2_mfma<float, 2, 2>": {
-        "bytes": (119066.29 * 2 + 102400.00) * 1024,
-        "kernels_sha256": "b1d9f0cd23f3016ffdb6d00e4e4499af4c3f5bec29601f708bd25dccbbca6ae3",
+    "k_stage2s_mfma<float, 2, 3>": {
+        "bytes": (108834.59 * 2 + 87381.33) * 1024,
+        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
+        "bf_nnz": 109109248,
+    },
+    "k_stage2_mfma<float, 2, 4>": {
+        "bytes": (132910.16 * 2 + 102400.00) * 1024,
+        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
+        "bf_nnz": 109109248,
+    },
+    "k_stage2s_mfma<double, 1, 3>": {
+        "bytes": (217252.23 * 2 + 174762.67) * 1024,
+        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
         "bf_nnz": 109109248,
     },
 }
