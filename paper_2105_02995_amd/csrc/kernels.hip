@@ -780,8 +780,9 @@ void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, 
 // Every phase reads its factor column-major (the conjugate transposes are stored),
 // so the loads of a tile's rows are coalesced.  Linv is lower triangular: phase 1
 // stops at the tile's last row, phase 4 starts at its first.  The k loop is the
-// pipelined one of the stage kernels, with the gathered row index of the next
-// k-step loaded one step ahead.
+// pipelined one of the stage kernels.  Each wave first copies its tile's gathered
+// row indices to LDS (one coalesced pass), so the loads of the gathered rows in the
+// k loop do not wait on index loads from global memory.
 template <class R, int MT, int NT> struct GWalk {
     const typename MF<R>::C *ap;
     int k, gnext;  // this lane's next k; gathered row of that k (already loaded)
@@ -805,6 +806,11 @@ __device__ __forceinline__ void gfrag_load(Frag<R, MT, NT> &f, GWalk<R, MT, NT> 
     w.gnext = kin[min(w.k, kend - 1)];
 }
 
+// k-steps of loads in flight in the skeletonization GEMMs: their tiles are narrow
+// (few MFMAs per k-step), so more steps are kept in flight than in the stage kernels
+// (measured best: 8 for complex64, 4 for complex128)
+template <class R> struct HgPf { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
+
 template <class R, int PH, int MT, int NT>
 __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
                                                const int32_t *__restrict__ idx,
@@ -813,7 +819,7 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
                                                const typename MF<R>::C *__restrict__ mat,
                                                const typename MF<R>::C *__restrict__ matH,
                                                typename MF<R>::C *__restrict__ x,
-                                               typename MF<R>::C *__restrict__ t, int nrhs, int nchunks) {
+                                               typename MF<R>::C *__restrict__ t, int nrhs, int nchunks, int maxk) {
     using C = typename MF<R>::C;
     const int lane = threadIdx.x & 63;
     int64_t wg;
@@ -833,7 +839,7 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
     const int ld = (PH == 2 || PH == 5) ? ns : nr;
     const int64_t off = (PH == 0 || PH == 5) ? 0 : ((PH == 1 || PH == 4) ? (int64_t)ns * nr : (int64_t)ns * nr + (int64_t)nr * nr);
     const C *S = ((PH == 0 || PH == 3 || PH == 4) ? matH : mat) + mo + off;
-    const int32_t *kin = (PH == 0 || PH == 3) ? is : ir;      // input rows
+    const int32_t *kin = (PH == 0 || PH == 3) ? is : ir;      // input rows (global, then LDS)
     const C *src = (PH == 2 || PH == 4) ? t : x;              // input vector
     const int32_t *oout = (PH == 2 || PH == 5) ? is : ir;     // output rows
     C *dst = (PH == 1 || PH == 3) ? t : x;                    // output vector
@@ -846,6 +852,19 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
     Acc<R, MT, NT> acc;
     acc.zero();
     if (kbeg < kend && m > 0) {  // wave-uniform
+        // this wave's gathered row indices kin[0..kend) in LDS (wave-local: LDS
+        // operations of one wave complete in order, no barrier needed)
+        extern __shared__ int32_t sidx[];
+        int32_t *lidx = sidx + (threadIdx.x >> 6) * maxk;
+        for (int i0 = 0; i0 < kend; i0 += 512) {  // eight loads in flight per lane
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = kin[min(i0 + 64 * u + lane, kend - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + 64 * u + lane < kend) lidx[i0 + 64 * u + lane] = v[u];
+        }
+        kin = lidx;
         int colc[NT], rowc[MT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) colc[nt] = min(nt * 16 + li, ncols - 1);
@@ -856,14 +875,15 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
         w.k = kbeg + lk;
         w.ap = S + (int64_t)w.k * ld;
         w.gnext = kin[min(w.k, kend - 1)];
-        Frag<R, MT, NT> f[STAGE_PF];
+        constexpr int HG_PF = HgPf<R>::value;
+        Frag<R, MT, NT> f[HG_PF];
 #pragma unroll
-        for (int j = 0; j + 1 < STAGE_PF; ++j) gfrag_load(f[j], w, kend, xb, nrhs, kin, ld, colc, rowc);
-        for (int k0 = kbeg; k0 < kend; k0 += 4 * STAGE_PF) {
+        for (int j = 0; j + 1 < HG_PF; ++j) gfrag_load(f[j], w, kend, xb, nrhs, kin, ld, colc, rowc);
+        for (int k0 = kbeg; k0 < kend; k0 += 4 * HG_PF) {
 #pragma unroll
-            for (int j = 0; j < STAGE_PF; ++j) {
+            for (int j = 0; j < HG_PF; ++j) {
                 if (k0 + 4 * j >= kend) break;  // wave-uniform
-                gfrag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, kend, xb, nrhs, kin, ld, colc, rowc);
+                gfrag_load(f[(j + HG_PF - 1) % HG_PF], w, kend, xb, nrhs, kin, ld, colc, rowc);
                 acc.mma(f[j]);
             }
         }
@@ -914,8 +934,19 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
     const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
     const dim3 g(xcd_grid((ntiles + 3) / 4, nch));
     const C *mat = (const C *)h.mat, *matH = (const C *)h.matH;
-#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1, NT>), g, dim3(256), 0, st, h.desc, h.idx, tiles, ntiles, mat, matH, \
-                                 (C *)x, (C *)t, nrhs, nch)
+    const int maxk = std::max(1, std::max(h.max_nr, h.max_ns));
+    const size_t lds = (size_t)4 * maxk * sizeof(int32_t);
+    if ((int64_t)lds > hif_lds_budget()) throw std::runtime_error("hif step: index lists exceed LDS");
+    static bool attr_set[6] = {false, false, false, false, false, false};
+    if (lds > 65536 && !attr_set[ph]) {
+        const void *fn[6] = {(const void *)k_hgemm<R, 0, 1, NT>, (const void *)k_hgemm<R, 1, 1, NT>,
+                             (const void *)k_hgemm<R, 2, 1, NT>, (const void *)k_hgemm<R, 3, 1, NT>,
+                             (const void *)k_hgemm<R, 4, 1, NT>, (const void *)k_hgemm<R, 5, 1, NT>};
+        (void)hipFuncSetAttribute(fn[ph], hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
+        attr_set[ph] = true;
+    }
+#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1, NT>), g, dim3(256), lds, st, h.desc, h.idx, tiles, ntiles, mat, matH, \
+                                 (C *)x, (C *)t, nrhs, nch, maxk)
     switch (ph) {
         case 0: HG(0); break;
         case 1: HG(1); break;
