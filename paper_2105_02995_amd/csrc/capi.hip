@@ -433,23 +433,24 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
 // GEMMs on matrix cores when a node's blocks exceed LDS (large 2D cells and edges),
 // in tiles of 64, 32 or 16 right-hand sides (choices 1, 2, 3), or the fused
 // per-node matrix-core kernel for nodes of at most 64 redundant and 64 skeleton
-// DOFs (choice 4).  `force` overrides the tuned choice where it applies.
-constexpr int HIF_CHOICES = 5;
+// DOFs, 64 or 32 right-hand sides per workgroup (choices 4, 5).  `force` overrides
+// the tuned choice where it applies.
+constexpr int HIF_CHOICES = 6;
 void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int force = -1) {
     const HifStepDev h = p->dhif[k].view(dbl);
     int choice = force;
-    if (choice == 4 && !hif_fused_fits(h)) choice = -1;
+    if ((choice == 4 || choice == 5) && !hif_fused_fits(h)) choice = -1;
     if (choice < 0) {
         const auto *t = p->tuned(dbl, nrhs);
         if (t && k < t->hif.size()) choice = t->hif[k];
     }
     if (choice < 0) {
-        if (nrhs >= 16 && hif_fused_fits(h)) choice = 4;
+        if (nrhs >= 16 && hif_fused_fits(h)) choice = 5;
         else choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
     }
     if (choice >= 1 && choice <= 3 && nrhs < 16) choice = 0;
     if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
-    else if (choice == 4) launch_hif_fused_step(h, dbl, up, x, nrhs, st);
+    else if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
     else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, 64 >> (choice - 1), st);
 }
 
@@ -844,11 +845,14 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                     if (ms < best_ms) { best_ms = ms; best = c; }
                 }
                 if (hif_fused_fits(h)) {
-                    const float ms = timeit([&] {
-                        launch_hif_fused_step(h, dbl, true, p->V2.p, nr, st);
-                        launch_hif_fused_step(h, dbl, false, p->V2.p, nr, st);
-                    });
-                    if (ms < best_ms) { best_ms = ms; best = 4; }
+                    for (int c = 4; c <= 5; ++c) {
+                        const int cw = c == 4 ? 64 : 32;
+                        const float ms = timeit([&] {
+                            launch_hif_fused_step(h, dbl, true, p->V2.p, nr, st, cw);
+                            launch_hif_fused_step(h, dbl, false, p->V2.p, nr, st, cw);
+                        });
+                        if (ms < best_ms) { best_ms = ms; best = c; }
+                    }
                 }
                 progress(vb, "tune %s skeletonization step %zu (%lld nodes): choice %d %.4f ms",
                          dbl ? "c128" : "c64", k, (long long)h.n_nodes, best, best_ms / reps);

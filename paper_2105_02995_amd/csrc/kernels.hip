@@ -1009,7 +1009,6 @@ bool hif_step_fits_lds(const HifStepDev &h, bool dbl) {
 // k-steps in which a triangular factor's tile is zero are skipped.  Staged rows
 // past nr (ns) are zero, so clamped factor entries of k beyond the product's K
 // (finite duplicates) add nothing.
-constexpr int HF_LD = 68;   // LDS row stride, complex entries (64 columns + 4)
 constexpr int HF_PF = 4;    // k-steps of loads in flight (register ring)
 
 template <class R> struct HfFragR {   // row split: one factor entry, four vector entries
@@ -1028,11 +1027,12 @@ __device__ __forceinline__ void cmma(typename MF<R>::V4 &re, typename MF<R>::V4 
     im = MF<R>::mma(a.y, b.x, im);
 }
 
-// Row split: acc[nt] = A(rows 16mt.., :) B(:, 16nt..) for nt < ntl.
-template <class R>
+// Row split: acc[nt] = A(rows 16mt.., :) B(:, 16nt..) for the NTW column tiles of
+// the workgroup (B has row stride ld).
+template <class R, int NTW>
 __device__ __forceinline__ void hf_rows(typename MF<R>::V4 (&re)[4], typename MF<R>::V4 (&im)[4],
                                         const typename MF<R>::C *__restrict__ A, int lda, int rows, int K, int tri,
-                                        const typename MF<R>::C *B, int mt, int ntl) {
+                                        const typename MF<R>::C *B, int ld, int mt) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -1050,7 +1050,7 @@ __device__ __forceinline__ void hf_rows(typename MF<R>::V4 (&re)[4], typename MF
         const int k = 4 * s + lk;
         f.a = arow[(int64_t)min(k, K - 1) * lda];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) f.b[nt] = B[k * HF_LD + 16 * nt + li];
+        for (int nt = 0; nt < NTW; ++nt) f.b[nt] = B[k * ld + 16 * nt + li];
     };
     HfFragR<R> f[HF_PF];
 #pragma unroll
@@ -1061,7 +1061,7 @@ __device__ __forceinline__ void hf_rows(typename MF<R>::V4 (&re)[4], typename MF
             if (s0 + j >= se) break;  // wave-uniform
             load(f[(j + HF_PF - 1) % HF_PF], s0 + j + HF_PF - 1);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) cmma<R>(re[nt], im[nt], f[j].a, f[j].b[nt]);
+            for (int nt = 0; nt < NTW; ++nt) cmma<R>(re[nt], im[nt], f[j].a, f[j].b[nt]);
         }
     }
 }
@@ -1070,7 +1070,7 @@ __device__ __forceinline__ void hf_rows(typename MF<R>::V4 (&re)[4], typename MF
 template <class R>
 __device__ __forceinline__ void hf_cols(typename MF<R>::V4 (&re)[4], typename MF<R>::V4 (&im)[4],
                                         const typename MF<R>::C *__restrict__ A, int lda, int rows, int K,
-                                        const typename MF<R>::C *B, int col0) {
+                                        const typename MF<R>::C *B, int ld, int col0) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -1085,7 +1085,7 @@ __device__ __forceinline__ void hf_cols(typename MF<R>::V4 (&re)[4], typename MF
         const C *acol = A + (int64_t)min(k, K - 1) * lda;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) f.a[mt] = acol[min(16 * mt + li, rows - 1)];
-        f.b = B[k * HF_LD + col0 + li];
+        f.b = B[k * ld + col0 + li];
     };
     HfFragC<R> f[HF_PF];
 #pragma unroll
@@ -1105,7 +1105,7 @@ __device__ __forceinline__ void hf_cols(typename MF<R>::V4 (&re)[4], typename MF
 // Row-split result into Y (SET) or subtracted from it: rows 16mt.., columns 16nt + li.
 template <class R, bool SET>
 __device__ __forceinline__ void hf_store_rows(const typename MF<R>::V4 (&re)[4], const typename MF<R>::V4 (&im)[4],
-                                              typename MF<R>::C *Y, int rows, int mt, int ntl) {
+                                              typename MF<R>::C *Y, int ld, int rows, int mt, int ntl) {
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     if (16 * mt >= rows) return;
 #pragma unroll
@@ -1115,7 +1115,7 @@ __device__ __forceinline__ void hf_store_rows(const typename MF<R>::V4 (&re)[4],
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             if (nt >= ntl) continue;
-            typename MF<R>::C &y = Y[row * HF_LD + 16 * nt + li];
+            typename MF<R>::C &y = Y[row * ld + 16 * nt + li];
             if (SET) y = typename MF<R>::C{re[nt][v], im[nt][v]};
             else y = typename MF<R>::C{y.x - re[nt][v], y.y - im[nt][v]};
         }
@@ -1125,7 +1125,7 @@ __device__ __forceinline__ void hf_store_rows(const typename MF<R>::V4 (&re)[4],
 // Column-split result subtracted from Y: rows 16mt + .., columns col0 + li.
 template <class R>
 __device__ __forceinline__ void hf_sub_cols(const typename MF<R>::V4 (&re)[4], const typename MF<R>::V4 (&im)[4],
-                                            typename MF<R>::C *Y, int rows, int col0) {
+                                            typename MF<R>::C *Y, int ld, int rows, int col0) {
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
@@ -1134,13 +1134,13 @@ __device__ __forceinline__ void hf_sub_cols(const typename MF<R>::V4 (&re)[4], c
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * mt + MF<R>::drow(lk, v);
             if (row >= rows) continue;
-            typename MF<R>::C &y = Y[row * HF_LD + col0 + li];
+            typename MF<R>::C &y = Y[row * ld + col0 + li];
             y = typename MF<R>::C{y.x - re[mt][v], y.y - im[mt][v]};
         }
     }
 }
 
-template <class R, bool UP>
+template <class R, bool UP, int NTW>
 __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
                                                    const typename MF<R>::C *__restrict__ mat,
                                                    const typename MF<R>::C *__restrict__ matH,
@@ -1148,9 +1148,10 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
                                                    int rows_s) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
+    constexpr int CW = 16 * NTW, LD = CW + 4;   // columns per workgroup, LDS row stride
     extern __shared__ char smem_raw[];
-    C *Xr = reinterpret_cast<C *>(smem_raw);   // rows_r x HF_LD
-    C *Xs = Xr + (int64_t)rows_r * HF_LD;      // rows_s x HF_LD
+    C *Xr = reinterpret_cast<C *>(smem_raw);   // rows_r x LD
+    C *Xs = Xr + (int64_t)rows_r * LD;         // rows_s x LD
     const int64_t v = blockIdx.x;
     const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
     const int32_t *ir = idx + desc[4 * v + 2];
@@ -1160,11 +1161,11 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
     const C *TH = matH + mo, *LH = TH + (int64_t)ns * nr, *MH = LH + (int64_t)nr * nr;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int w = threadIdx.x >> 6, col0 = 16 * w;
-    const int b0 = blockIdx.y * 64;
-    const int bc = min(64, nrhs - b0);
+    const int b0 = blockIdx.y * CW;
+    const int bc = min(CW, nrhs - b0);
     const int ntl = (bc + 15) >> 4;   // column tiles holding columns
     // the node's row indices (x_r rows, then x_s rows) in LDS, one load per thread
-    int32_t *gidx = reinterpret_cast<int32_t *>(Xr + (int64_t)(rows_r + rows_s) * HF_LD);
+    int32_t *gidx = reinterpret_cast<int32_t *>(Xr + (int64_t)(rows_r + rows_s) * LD);
     const int32_t g0 = (nr > 0) ? ir[0] : ((ns > 0) ? is[0] : 0);
     for (int i = threadIdx.x; i < rows_r + rows_s; i += blockDim.x) {
         const int ii = (i < rows_r) ? i : i - rows_r;
@@ -1177,7 +1178,7 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
     // entries outside the node or the batch are then replaced by zero
     const bool cv = col0 + li < bc;
     const int64_t cc = b0 + min(col0 + li, bc - 1);
-    for (int i0 = 0; i0 < rows_r + rows_s; i0 += 64) {
+    for (int i0 = 0; w < NTW && i0 < rows_r + rows_s; i0 += 64) {
         C t[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -1188,60 +1189,67 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int i = i0 + 4 * u + lk;
-            if (i < rows_r + rows_s) Xr[i * HF_LD + col0 + li] = (cv && gidx[i] >= 0) ? t[u] : C{0, 0};
+            if (i < rows_r + rows_s) Xr[i * LD + col0 + li] = (cv && gidx[i] >= 0) ? t[u] : C{0, 0};
         }
     }
     __syncthreads();
     V4 re[4], im[4];
     // first product: x_r -= (T^* or M^*) x_s, row split
     if (ns > 0) {
-        hf_rows<R>(re, im, UP ? TH : MH, nr, nr, ns, 0, Xs, w, ntl);
-        hf_store_rows<R, false>(re, im, Xr, nr, w, ntl);
+        hf_rows<R, NTW>(re, im, UP ? TH : MH, nr, nr, ns, 0, Xs, LD, w);
+        hf_store_rows<R, false>(re, im, Xr, LD, nr, w, ntl);
     }
     __syncthreads();
     // x_r <- (Linv or Linv^*) x_r, row split; every wave reads all rows first
-    hf_rows<R>(re, im, UP ? Li : LH, nr, nr, nr, UP ? 1 : 2, Xr, w, ntl);
+    hf_rows<R, NTW>(re, im, UP ? Li : LH, nr, nr, nr, UP ? 1 : 2, Xr, LD, w);
     __syncthreads();
-    hf_store_rows<R, true>(re, im, Xr, nr, w, ntl);
+    hf_store_rows<R, true>(re, im, Xr, LD, nr, w, ntl);
     __syncthreads();
     // x_s -= (M or T) x_r, column split
     if (ns > 0 && col0 < bc) {
-        hf_cols<R>(re, im, UP ? Mm : Tm, ns, ns, nr, Xr, col0);
-        hf_sub_cols<R>(re, im, Xs, ns, col0);
+        hf_cols<R>(re, im, UP ? Mm : Tm, ns, ns, nr, Xr, LD, col0);
+        hf_sub_cols<R>(re, im, Xs, LD, ns, col0);
     }
     // write back this wave's columns (x_s was last written by this wave, x_r before
     // the last barrier)
     if (cv) {
-        for (int i = lk; i < nr; i += 4) x[(int64_t)gidx[i] * nrhs + cc] = Xr[i * HF_LD + col0 + li];
-        for (int i = lk; i < ns; i += 4) x[(int64_t)gidx[rows_r + i] * nrhs + cc] = Xs[i * HF_LD + col0 + li];
+        for (int i = lk; i < nr; i += 4) x[(int64_t)gidx[i] * nrhs + cc] = Xr[i * LD + col0 + li];
+        for (int i = lk; i < ns; i += 4) x[(int64_t)gidx[rows_r + i] * nrhs + cc] = Xs[i * LD + col0 + li];
     }
 }
 
 bool hif_fused_fits(const HifStepDev &h) { return h.max_nr <= 64 && h.max_ns <= 64; }
 
-template <class R, bool UP>
+template <class R, bool UP, int NTW>
 static void hif_fused_go(const HifStepDev &h, int rr, int rs, void *x, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
-    const size_t lds = (size_t)(rr + rs) * HF_LD * sizeof(C) + (size_t)(rr + rs) * sizeof(int32_t);
+    constexpr int CW = 16 * NTW, LD = CW + 4;
+    const size_t lds = (size_t)(rr + rs) * LD * sizeof(C) + (size_t)(rr + rs) * sizeof(int32_t);
     static bool attr_set = false;
     if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_hif_fused<R, UP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void *)k_hif_fused<R, UP, NTW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   hif_lds_budget());
         attr_set = true;
     }
     if ((int64_t)lds > hif_lds_budget()) throw std::runtime_error("fused skeletonization step exceeds LDS");
-    const dim3 g((unsigned)h.n_nodes, (unsigned)((nrhs + 63) / 64));
-    hipLaunchKernelGGL((k_hif_fused<R, UP>), g, dim3(256), lds, st, h.desc, h.idx, (const C *)h.mat,
+    const dim3 g((unsigned)h.n_nodes, (unsigned)((nrhs + CW - 1) / CW));
+    hipLaunchKernelGGL((k_hif_fused<R, UP, NTW>), g, dim3(256), lds, st, h.desc, h.idx, (const C *)h.mat,
                        (const C *)h.matH, (C *)x, nrhs, rr, rs);
 }
 
-void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
+void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int cols) {
     if (h.n_nodes == 0) return;
     if (!hif_fused_fits(h)) throw std::runtime_error("fused skeletonization step needs nr, ns <= 64");
     // staged rows: whole 16-row tiles (the k loops read up to the next multiple of 4)
     const int rr = std::max(16, (h.max_nr + 15) / 16 * 16), rs = std::max(16, (h.max_ns + 15) / 16 * 16);
-    if (dbl) { if (up) hif_fused_go<double, true>(h, rr, rs, x, nrhs, st); else hif_fused_go<double, false>(h, rr, rs, x, nrhs, st); }
-    else { if (up) hif_fused_go<float, true>(h, rr, rs, x, nrhs, st); else hif_fused_go<float, false>(h, rr, rs, x, nrhs, st); }
+    const bool w64 = cols > 32;
+    if (dbl) {
+        if (w64) { if (up) hif_fused_go<double, true, 4>(h, rr, rs, x, nrhs, st); else hif_fused_go<double, false, 4>(h, rr, rs, x, nrhs, st); }
+        else { if (up) hif_fused_go<double, true, 2>(h, rr, rs, x, nrhs, st); else hif_fused_go<double, false, 2>(h, rr, rs, x, nrhs, st); }
+    } else {
+        if (w64) { if (up) hif_fused_go<float, true, 4>(h, rr, rs, x, nrhs, st); else hif_fused_go<float, false, 4>(h, rr, rs, x, nrhs, st); }
+        else { if (up) hif_fused_go<float, true, 2>(h, rr, rs, x, nrhs, st); else hif_fused_go<float, false, 2>(h, rr, rs, x, nrhs, st); }
+    }
     check_launch("hif step (fused)");
 }
 

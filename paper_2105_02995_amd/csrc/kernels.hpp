@@ -74,10 +74,12 @@ void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void 
 // Whether a step's largest node fits the LDS-staged kernel.
 bool hif_step_fits_lds(const HifStepDev &h, bool dbl);
 // One skeletonization step in a single launch for nodes with nr, ns <= 64: per
-// (node, 64 right-hand sides) the node's entries of x are staged in LDS and the
-// step's three products run on matrix cores.
+// (node, 64 or 32 right-hand sides) the node's entries of x are staged in LDS and
+// the step's three products run on matrix cores.
 bool hif_fused_fits(const HifStepDev &h);
-void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st);
+// cols: right-hand sides per workgroup, 64 or 32.
+void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st,
+                           int cols = 64);
 void launch_rows_gather(const void *x, bool xd, const int32_t *idx, int64_t rows, int nrhs, void *out, bool od,
                         hipStream_t st);
 void launch_rows_scatter(const void *in, bool id, const int32_t *idx, int64_t rows, int nrhs, void *x, bool xd,
