@@ -32,23 +32,23 @@ PEAK_HBM_GBS = 8000.0
 # count) they were measured on.
 TRAFFIC = {
     "k_stage2_mfma<double, 2, 2>": {
-        "bytes": (247082.66 * 2 + 204800.00) * 1024,
-        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
+        "bytes": (247081.56 * 2 + 204800.00) * 1024,
+        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
         "bf_nnz": 109109248,
     },
     "k_stage2s_mfma<float, 2, 3>": {
-        "bytes": (108834.59 * 2 + 87381.33) * 1024,
-        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
+        "bytes": (108831.44 * 2 + 87381.33) * 1024,
+        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
         "bf_nnz": 109109248,
     },
     "k_stage2_mfma<float, 2, 4>": {
-        "bytes": (132910.16 * 2 + 102400.00) * 1024,
-        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
+        "bytes": (123726.49 * 2 + 102400.00) * 1024,
+        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
         "bf_nnz": 109109248,
     },
     "k_stage2s_mfma<double, 1, 3>": {
-        "bytes": (217252.23 * 2 + 174762.67) * 1024,
-        "kernels_sha256": "f5768cab5fa03057d1423307fec3dde3f52ab60372b05222127731d7e925544a",
+        "bytes": (217253.39 * 2 + 174762.67) * 1024,
+        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
         "bf_nnz": 109109248,
     },
 }
