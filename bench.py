@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
     ap.add_argument("--no-serve", action="store_true", help="skip the small serving leg")
+    ap.add_argument("--trace", action="store_true",
+                    help="named library ranges (fio_set_trace) during the timed steps, for a marker trace")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in kernel heuristics")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving mix (Poisson arrivals over many keys) instead of the solve bench")
@@ -302,6 +304,8 @@ def main():
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
+    if args.trace:
+        F.fio_set_trace(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         evs[k][0].record(stream)
@@ -309,6 +313,8 @@ def main():
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if args.trace:
+        F.fio_set_trace(False)
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     ms = 1000.0 * elapsed / args.steps
     value = B * N / (elapsed / args.steps)

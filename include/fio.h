@@ -128,6 +128,12 @@ typedef struct {
  * FIO_ERR_DEVICE. */
 fio_status fio_build(const fio_problem *p, fio_plan *out);
 
+/* Tracing: with on != 0 every solve, chain apply, Gd sweep and step, and refinement
+ * or PCG iteration pushes a named range for a profiler's marker trace (roctx; e.g.
+ * rocprofv3 --marker-trace); 0 (the default) switches it off.  Process-wide; host
+ * overhead only (about a microsecond per range) and no effect on results. */
+void fio_set_trace(int on);
+
 /* y = Kd x (op = FIO_OP_K, eq_BFF_fact) or y = Kd^* x (op = FIO_OP_KH).
  * x, y: device buffers of dtype, N x nrhs, leading dimension ld; x and y must
  * not overlap.  Asynchronous on hip_stream. */

@@ -51,7 +51,8 @@ def build(verbose: bool = False) -> str:
                 print(o)
     objs = [os.path.join(OBJ, s + ".o") for s in CXX_SOURCES + HIP_SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
-    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread"])
+    _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread",
+          "-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, LIB)
     # the C ABI from plain C: a file-to-file solve (HIP runtime C API for device memory)
     ex = os.path.join(HERE, "fio_solve_file")

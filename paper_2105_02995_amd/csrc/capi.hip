@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cstdarg>
+#include <cstdio>
 #include <complex>
 #include <cmath>
 #include <map>
@@ -13,6 +16,8 @@
 #include <mutex>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "fio.h"
 #include "kernels.hpp"
@@ -23,6 +28,27 @@ using namespace fio;
 namespace {
 
 thread_local std::string g_err;
+
+// Named ranges of the host-side phases (solve, chains, Gd sweeps and steps,
+// iterations) for a profiler's marker trace, when switched on by fio_set_trace.
+std::atomic<int> g_trace(0);
+struct TraceRange {
+    bool on;
+    explicit TraceRange(const char *fmt, ...) : on(g_trace.load(std::memory_order_relaxed) != 0) {
+        if (!on) return;
+        char buf[96];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        roctxRangePushA(buf);
+    }
+    ~TraceRange() {
+        if (on) roctxRangePop();
+    }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 #define HIPC(x)                                                                          \
     do {                                                                                 \
@@ -411,6 +437,7 @@ StagePairDev pair_view(fio_plan p, bool fwd, bool dbl, int s) {
 
 // Run a stage chain: in (first stage's input) -> out (last stage's output).
 void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nrhs, hipStream_t st) {
+    TraceRange tr("fio %s chain %s B=%d", fwd ? "Kd" : "Kd*", dbl ? "c128" : "c64", nrhs);
     const auto &hs = fwd ? p->host.fwd : p->adj;
     const auto &ds = fwd ? p->dfwd : p->dadj;
     const std::vector<Launch> sched = chain_schedule(p, fwd, dbl, nrhs);
@@ -474,9 +501,19 @@ void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
 }
 
 void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, int force = -1) {
-    for (size_t k = 0; k < p->dhif.size(); ++k) hif_step(p, k, dbl, true, x, nrhs, st, force);
-    root_apply(p, dbl, x, nrhs, st);
-    for (size_t k = p->dhif.size(); k-- > 0;) hif_step(p, k, dbl, false, x, nrhs, st, force);
+    TraceRange tr("fio Gd %s B=%d", dbl ? "c128" : "c64", nrhs);
+    for (size_t k = 0; k < p->dhif.size(); ++k) {
+        TraceRange ts("fio Gd step %zu up", k);
+        hif_step(p, k, dbl, true, x, nrhs, st, force);
+    }
+    {
+        TraceRange tr0("fio Gd root");
+        root_apply(p, dbl, x, nrhs, st);
+    }
+    for (size_t k = p->dhif.size(); k-- > 0;) {
+        TraceRange ts("fio Gd step %zu down", k);
+        hif_step(p, k, dbl, false, x, nrhs, st, force);
+    }
 }
 
 void check_apply_args(fio_plan p, int64_t nrhs, int64_t ld, const void *a, const void *b) {
@@ -544,6 +581,8 @@ PeelApplyFactory gpu_peel_factory(int device) {
 extern "C" {
 
 const char *fio_last_error(void) { return g_err.c_str(); }
+
+void fio_set_trace(int on) { g_trace.store(on ? 1 : 0); }
 
 fio_status fio_build(const fio_problem *prob, fio_plan *out) {
     return guard([&] {
@@ -1099,6 +1138,7 @@ extern "C" {
 fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const void *u, void *out,
                      int64_t nrhs, int64_t ld, fio_solve_info *info, void *stream) {
     return guard([&] {
+        TraceRange tr("fio solve mode %d %s", opts ? (int)opts->mode : -1, dt == FIO_C128 ? "c128" : "c64");
         check_apply_args(p, nrhs, ld, u, out);
         if (!opts) fail(FIO_ERR_ARG, "null options");
         if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
@@ -1165,6 +1205,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             launch_convert(p->V2.p, dbl, p->X.p, true, cnt, st);  // x0 = Gd Kd^* u
             if (opts->mode == FIO_SOLVE_REFINE) {
                 for (int it = 0; it < opts->maxit; ++it) {
+                    TraceRange ti("fio refine iteration %d", it);
                     // r = u - Kd x with complex128 factors and FP64 accumulation
                     run_chain(p, true, true, p->X.p, p->V1.p, nr, st);
                     launch_residual(p->U.p, p->V1.p, p->R.p, true, cnt, st);
@@ -1203,6 +1244,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             HIPC(hipStreamSynchronize(st));
             converged = false;
             for (int it = 0; it < std::max(1, opts->maxit); ++it) {
+                TraceRange ti("fio pcg iteration %d", it);
                 apply_chain(true, p->Pv.p, p->V2.p);
                 apply_chain(false, p->V2.p, p->V1.p);  // Ap (complex128 in V1)
                 launch_coldot(p->Pv.p, p->V1.p, N, nr, (double *)p->red.p, cap, pAp, st);

@@ -27,7 +27,7 @@ PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FI
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
-           "fio_last_error"]
+           "fio_last_error", "fio_set_trace"]
 
 
 class FioError(RuntimeError):
@@ -106,9 +106,11 @@ def load_library():
     lib.fio_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(P)]
     lib.fio_destroy.argtypes = [P]
     lib.fio_destroy.restype = None
+    lib.fio_set_trace.argtypes = [ctypes.c_int]
+    lib.fio_set_trace.restype = None
     lib.fio_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("fio_destroy", "fio_last_error"):
+        if name not in ("fio_destroy", "fio_last_error", "fio_set_trace"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -184,6 +186,11 @@ def fio_load(path: str, device: int = 0) -> Plan:
 
 def fio_save(plan: Plan, path: str):
     _check(load_library().fio_save(plan.handle, path.encode()))
+
+
+def fio_set_trace(on: bool):
+    """Named roctx ranges of the library's phases (for a profiler's marker trace)."""
+    load_library().fio_set_trace(1 if on else 0)
 
 
 def fio_destroy(plan: Plan):

@@ -53,3 +53,19 @@ def test_split_batch_equals_whole_batch(mode, tol, maxit):
     lo, _ = G.solve(p, mode, F.FIO_C64, u[:, :32], tol=tol, maxit=maxit)
     hi, _ = G.solve(p, mode, F.FIO_C64, u[:, 32:], tol=tol, maxit=maxit)
     assert np.array_equal(whole, np.concatenate([lo, hi], axis=1))
+
+
+def test_tracing_does_not_change_results():
+    """fio_set_trace only adds named host ranges: solves with it on equal those with
+    it off, bit for bit."""
+    p = plan()
+    u = gaussian_complex((4096, 24), 79)
+    x0, _ = G.solve(p, F.FIO_SOLVE_REFINE, F.FIO_C64, u, maxit=1)
+    F.fio_set_trace(True)
+    try:
+        x1, _ = G.solve(p, F.FIO_SOLVE_REFINE, F.FIO_C64, u, maxit=1)
+        x2, _ = G.solve(p, F.FIO_SOLVE_PCG, F.FIO_C64, u, tol=1e-8, maxit=50)
+    finally:
+        F.fio_set_trace(False)
+    x3, _ = G.solve(p, F.FIO_SOLVE_PCG, F.FIO_C64, u, tol=1e-8, maxit=50)
+    assert np.array_equal(x0, x1) and np.array_equal(x2, x3)
