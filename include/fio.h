@@ -279,9 +279,11 @@ fio_status fio_chain_schedule(fio_plan plan, fio_op op, fio_dtype dtype, int64_t
 
 /* Autotuner: for this dtype and batch width, time every kernel variant of every
  * butterfly stage (vector kernel; matrix-core tiles of 16 or 32 rows by 16, 32 or
- * 64 columns), of every fusable pair of consecutive stages, per skeletonization
- * step the LDS-staged kernel against the matrix-core GEMM path (16, 32 or 64
- * columns per tile), and the tiling of the FP64 top-level block, with `reps` timed
+ * 64 columns), of every fusable pair of consecutive stages (16, 32 or 64 columns per
+ * wave, and the stacked form of sibling blocks), per skeletonization step the
+ * LDS-staged kernel, the matrix-core GEMM path (16, 32 or 64 columns per tile) and
+ * the fused per-node kernel (64 or 32 columns per workgroup), and the tiling of the
+ * FP64 top-level block, with `reps` timed
  * repetitions each (HIP events on hip_stream); keep the fastest choices in the
  * plan, with the chain split into single and fused launches that minimises the
  * summed time.  Later applies with the same dtype and nrhs use them (other widths
