@@ -217,6 +217,8 @@ typedef struct {
                                       not stored by fio_save)                          */
     double bf_seconds;             /* wall time of the butterfly construction (not stored) */
     int bf_device_levels;          /* butterfly levels decomposed on the device (not stored) */
+    int hif_device_ids;            /* skeletonization IDs (large 2D cells and edges) computed
+                                      on the device (not stored)                       */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

@@ -600,8 +600,12 @@ fio_status fio_build(const fio_problem *prob, fio_plan *out) {
         PeelApplyFactory f;
         BatchedIdFactory ids;
         if (p->device >= 0) f = gpu_peel_factory(p->device);
-        if (p->device >= 0 && !prob->host_construction) ids = device_id_factory(p->device);
-        build_host_factors(*prob, p->host, f, ids);
+        BigIdFn big;
+        if (p->device >= 0 && !prob->host_construction) {
+            ids = device_id_factory(p->device);
+            big = device_big_id(p->device);
+        }
+        build_host_factors(*prob, p->host, f, ids, big);
         for (int s = (int)p->host.fwd.size() - 1; s >= 0; --s) p->adj.push_back(adjoint_stage(p->host.fwd[s]));
         if (p->device >= 0) upload_plan(p.get());
         *out = p.release();
@@ -653,6 +657,7 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
         o->build_seconds = h.build_seconds;
         o->bf_seconds = h.bf_seconds;
         o->bf_device_levels = h.bf_device_levels;
+        o->hif_device_ids = h.hif.device_ids;
     });
 }
 

@@ -12,10 +12,12 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "butterfly.hpp"
+#include "hif.hpp"
 
 namespace fio {
 namespace {
@@ -415,12 +417,232 @@ bool run_batch(const Tables &tb, const IdBatch &bt, const IdSink &sink, int nthr
     return true;
 }
 
+// ---- one large matrix: column-pivoted QR with column-parallel updates ----
+// state[0]: set once the next pivot is below the tolerance; state[1]: pivots done.
+// dstate[0]: absolute tolerance (from the largest initial column norm), dstate[1]:
+// w^* w of the current reflector.  hh[0]: reflector head w_k, hh[1]: R_kk.
+
+// nrm[j] = |A(:, j)|^2, one wave per column.
+__global__ __launch_bounds__(256) void k_lq_norms(const double2 *A, int64_t m, int n, double *nrm) {
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= n) return;  // wave-uniform
+    const double2 *c = A + j * m;
+    double s = 0.0;
+    for (int64_t i = lane; i < m; i += 64) s += cabs2(c[i]);
+    s = wsum(s);
+    if (lane == 0) nrm[j] = s;
+}
+
+// Block-wide sum over 256 threads (the same bits in every thread).
+__device__ double bsum(double v, double *red) {
+    v = wsum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+// Step k, one workgroup: previous R_kk, pivot (largest remaining norm, first among
+// equals), tolerance test, column swap, reflector of column k.
+__global__ __launch_bounds__(256) void k_lq_pivot(double2 *A, int64_t m, int n, int k, double *nrm, int *perm,
+                                                  double tol_rel, int *state, double *dstate, double2 *hh) {
+    __shared__ double red_v[4], red[4];
+    __shared__ int red_i[4];
+    __shared__ int s_p;
+    __shared__ double s_v, s_tol;
+    if (state[0]) return;  // the same value in every thread
+    if (k > 0 && threadIdx.x == 0) A[(int64_t)(k - 1) * m + (k - 1)] = hh[1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double bv = -1.0;
+    int bi = n;
+    for (int j = k + (int)threadIdx.x; j < n; j += 256) {
+        const double v = nrm[j];
+        if (v > bv) { bv = v; bi = j; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wv] = bv; red_i[wv] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = red_v[0];
+        int i = red_i[0];
+        for (int w = 1; w < 4; ++w)
+            if (red_v[w] > v || (red_v[w] == v && red_i[w] < i)) { v = red_v[w]; i = red_i[w]; }
+        s_p = i;
+        s_v = v;
+        if (k == 0) dstate[0] = (tol_rel > 0) ? tol_rel * sqrt(fmax(v, 0.0)) : -1.0;
+        s_tol = dstate[0];
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (sqrt(fmax(s_v, 0.0)) <= s_tol) {
+        if (threadIdx.x == 0) state[0] = 1;
+        return;
+    }
+    if (p != k) {
+        double2 *ck = A + (int64_t)k * m, *cp = A + (int64_t)p * m;
+        for (int64_t i = threadIdx.x; i < m; i += 256) {
+            const double2 t = ck[i];
+            ck[i] = cp[i];
+            cp[i] = t;
+        }
+        if (threadIdx.x == 0) {
+            const double tv = nrm[k]; nrm[k] = nrm[p]; nrm[p] = tv;
+            const int ti = perm[k]; perm[k] = perm[p]; perm[p] = ti;
+        }
+    }
+    __syncthreads();
+    const double2 *ck = A + (int64_t)k * m;
+    double tail = 0.0;
+    for (int64_t i = k + 1 + threadIdx.x; i < m; i += 256) tail += cabs2(ck[i]);
+    tail = bsum(tail, red);
+    if (threadIdx.x == 0) {
+        const double2 x0 = ck[k];
+        const double ax0 = hypot(x0.x, x0.y);
+        const double alpha = sqrt(ax0 * ax0 + tail);
+        const double2 ph = (ax0 > 0) ? make_double2(x0.x / ax0, x0.y / ax0) : make_double2(1.0, 0.0);
+        const double2 w0 = make_double2(x0.x + ph.x * alpha, x0.y + ph.y * alpha);
+        hh[0] = w0;
+        hh[1] = make_double2(-ph.x * alpha, -ph.y * alpha);
+        dstate[1] = cabs2(w0) + tail;
+        state[1] = k + 1;
+    }
+}
+
+// Step k, trailing columns j > k, one wave per column: v -= (2 w^* v / w^* w) w with
+// w = column k below row k - 1 (head hh[0]), then the exact norm of rows > k.
+__global__ __launch_bounds__(256) void k_lq_update(double2 *A, int64_t m, int n, int k, double *nrm,
+                                                   const int *state, const double *dstate, const double2 *hh) {
+    if (state[0]) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const double wn2 = dstate[1];
+    const double2 w0 = hh[0];
+    const double2 *wk = A + (int64_t)k * m;
+    for (int64_t j = k + 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < n; j += nw) {
+        double2 *v = A + j * m;
+        double nn = 0.0;
+        if (wn2 > 0) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t i = k + lane; i < m; i += 64) {
+                const double2 w = (i == k) ? w0 : wk[i];
+                const double2 t = cjmul(w, v[i]);
+                sr += t.x;
+                si += t.y;
+            }
+            sr = wsum(sr);
+            si = wsum(si);
+            const double2 tau = make_double2(2.0 * sr / wn2, 2.0 * si / wn2);
+            for (int64_t i = k + lane; i < m; i += 64) {
+                const double2 w = (i == k) ? w0 : wk[i];
+                const double2 d = cmul(tau, w);
+                double2 x = v[i];
+                x.x -= d.x;
+                x.y -= d.y;
+                v[i] = x;
+                if (i > k) nn += cabs2(x);
+            }
+        } else {
+            for (int64_t i = k + 1 + lane; i < m; i += 64) nn += cabs2(v[i]);
+        }
+        nn = wsum(nn);
+        if (lane == 0) nrm[j] = nn;
+    }
+}
+
+// R_kk of the last step when the loop ended without reaching the tolerance.
+__global__ void k_lq_finish(double2 *A, int64_t m, const int *state, const double2 *hh) {
+    if (threadIdx.x == 0 && state[0] == 0 && state[1] > 0)
+        A[(int64_t)(state[1] - 1) * m + (state[1] - 1)] = hh[1];
+}
+
+bool big_column_id(int device, const Mat &Ah, double tol_rel, ColumnID &out) {
+    const int64_t m = Ah.m;
+    const int n = Ah.n;
+    if (m < 1 || n < 1) return false;
+    CHK(hipSetDevice(device));
+    DevMem A, nrm, perm, st, dst, hh;
+    A.alloc((size_t)m * n * 16);
+    nrm.alloc((size_t)n * 8);
+    perm.alloc((size_t)n * 4);
+    st.alloc(4 * sizeof(int));
+    dst.alloc(4 * sizeof(double));
+    hh.alloc(2 * 16);
+    CHK(hipMemcpy(A.p, Ah.a.data(), (size_t)m * n * 16, hipMemcpyHostToDevice));
+    std::vector<int> order(n);
+    for (int j = 0; j < n; ++j) order[j] = j;
+    CHK(hipMemcpy(perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    const int zero[4] = {0, 0, 0, 0};
+    CHK(hipMemcpy(st.p, zero, sizeof(zero), hipMemcpyHostToDevice));
+    double2 *a = (double2 *)A.p;
+    hipLaunchKernelGGL(k_lq_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, 0, (const double2 *)a, m, n,
+                       (double *)nrm.p);
+    CHK(hipGetLastError());
+    const int kmax = (int)std::min<int64_t>(m, n);
+    int hs[4] = {0, 0, 0, 0};
+    for (int k = 0; k < kmax; ++k) {
+        hipLaunchKernelGGL(k_lq_pivot, dim3(1), dim3(256), 0, 0, a, m, n, k, (double *)nrm.p, (int *)perm.p, tol_rel,
+                           (int *)st.p, (double *)dst.p, (double2 *)hh.p);
+        const int cols = n - k - 1;
+        if (cols > 0) {
+            const unsigned g = (unsigned)std::min<int64_t>((cols + 3) / 4, 4096);
+            hipLaunchKernelGGL(k_lq_update, dim3(g), dim3(256), 0, 0, a, m, n, k, (double *)nrm.p, (const int *)st.p,
+                               (const double *)dst.p, (const double2 *)hh.p);
+        }
+        if ((k & 31) == 31) {  // early exit once the tolerance has been reached
+            CHK(hipMemcpy(hs, st.p, sizeof(hs), hipMemcpyDeviceToHost));
+            if (hs[0]) break;
+        }
+    }
+    hipLaunchKernelGGL(k_lq_finish, dim3(1), dim3(64), 0, 0, a, m, (const int *)st.p, (const double2 *)hh.p);
+    CHK(hipGetLastError());
+    CHK(hipMemcpy(hs, st.p, sizeof(hs), hipMemcpyDeviceToHost));
+    const int k = hs[1];
+    CHK(hipMemcpy(order.data(), perm.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    Mat R(k, n);
+    if (k > 0)
+        CHK(hipMemcpy2D(R.a.data(), (size_t)k * 16, A.p, (size_t)m * 16, (size_t)k * 16, (size_t)n,
+                        hipMemcpyDeviceToHost));
+    out.skel.assign(order.begin(), order.begin() + k);
+    out.redund.assign(order.begin() + k, order.end());
+    out.T = Mat(k, n - k);
+    // T = R11^{-1} R12 by back substitution, column by column
+    par_cols(n - k, (double)k * k * (n - k) / 2.0, [&](int64_t jj) {
+        const int j = (int)jj;
+        cd *t = out.T.col(j);
+        const cd *r12 = R.col(k + j);
+        for (int i = 0; i < k; ++i) t[i] = r12[i];
+        for (int q = k - 1; q >= 0; --q) {
+            const cd d = R(q, q);
+            t[q] = (std::abs(d) > 0) ? t[q] / d : cd(0);
+            const cd tq = t[q];
+            const cd *rq = R.col(q);
+            for (int i = 0; i < q; ++i) t[i] -= rq[i] * tq;
+        }
+    });
+    return true;
+}
+
 }  // namespace
 
 BatchedIdFactory device_id_factory(int device) {
     return [device](const FioKernel &K) -> BatchedId {
         auto tb = std::make_shared<Tables>(device, K);
         return [tb](const IdBatch &bt, const IdSink &sink) { return run_batch(*tb, bt, sink, 0); };
+    };
+}
+
+BigIdFn device_big_id(int device) {
+    auto mu = std::make_shared<std::mutex>();
+    return [device, mu](const Mat &A, double tol_rel, ColumnID &out) {
+        std::lock_guard<std::mutex> lk(*mu);  // one matrix at a time on the device
+        return big_column_id(device, A, tol_rel, out);
     };
 }
 

@@ -39,10 +39,20 @@ struct HifFactors {
     Mat A0inv;                      // inverse of the top-level block on S_0 (FP64)
     int max_rank_h = 0;             // largest off-diagonal rank of Sd
     int shifted = 0;                // pivot blocks (and root) that needed a diagonal shift
+    int device_ids = 0;             // interpolative decompositions done on the device (not stored)
 };
 
 // y = A x for nrhs vectors stored point-major (entry (e, b) at e*nrhs + b).
 using BlockApply = std::function<void(const cd *x, cd *y, int nrhs)>;
+
+// Column ID of one large matrix (tall stacked bases of coarse 2D nodes) on a device;
+// returns false (having done nothing) if it declines the shape.  Same contract as
+// column_id(A, tol_rel, 0, -1).
+using BigIdFn = std::function<bool(const Mat &A, double tol_rel, ColumnID &out)>;
+// The device implementation (column-pivoted Householder QR, one launch for the pivot
+// and reflector and one for the trailing columns per step; serialised across host
+// threads).
+BigIdFn device_big_id(int device);
 
 struct PeelOptions {
     double eps = 1e-6;      // relative tolerance (to ||S||_2) of the low-rank blocks
@@ -63,6 +73,8 @@ struct PeelOptions {
     // remains acts on I + T^* T.  Each level then has two steps: the scaling (a node
     // with only redundant DOFs and Linv = L^{-1}) and the skeletonization.
     bool prescale = false;
+    // 2D: large column IDs of the skeletonization on a device (empty: host).
+    BigIdFn big_id;
 };
 
 // 1D HODLR peeling of a Hermitian operator given only by products (section 3),

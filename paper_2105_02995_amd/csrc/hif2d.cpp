@@ -385,8 +385,11 @@ struct NodeOut {
 
 // Skeletonize the DOFs I given the stacked row block Ubar and the current
 // diagonal block A_II; same algebra as the 1D case (eq_sk, eq_sk_3).
+// Large IDs (coarse cells and edges) go to the device when the plan has one.
+constexpr int64_t BIG_ID_ENTRIES = 1 << 19;
+
 NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, double eps, double shift0,
-               std::atomic<int> &nshift) {
+               std::atomic<int> &nshift, const BigIdFn &big_id, std::atomic<int> &ndev) {
     NodeOut out;
     const int n = (int)I.size();
     std::vector<int> sk, rd;
@@ -395,7 +398,11 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         for (int i = 0; i < n; ++i) rd.push_back(i);
         T = Mat(0, n);
     } else {
-        ColumnID id = column_id(Ubar, eps, 0, -1);
+        ColumnID id;
+        if (big_id && (int64_t)Ubar.m * Ubar.n >= BIG_ID_ENTRIES && big_id(Ubar, eps, id))
+            ndev.fetch_add(1);
+        else
+            id = column_id(Ubar, eps, 0, -1);
         sk = id.skel;
         rd = id.redund;
         T = std::move(id.T);
@@ -464,7 +471,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
     const double normS = power_norm(A, g.N, 12, po.seed ^ 0x5EEDULL);
     Hmat2D H = peel_2d(A, g, po, normS);
     const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
-    std::atomic<int> nshift(0);
+    std::atomic<int> nshift(0), ndev(0);
     F.max_rank_h = H.max_rank;
     Active2D act(H);
     // active DOFs per cell at the current level
@@ -486,7 +493,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                 if (!Bnear.empty()) blocks.push_back(act.sub(Bnear, I));
                 far_rows(H, l, c, I, blocks);
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift);
+                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po.big_id, ndev);
             });
             HifStep step;
             for (int64_t c = 0; c < ncell; ++c) {
@@ -565,7 +572,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                     if (c1 == c2) break;
                 }
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift);
+                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po.big_id, ndev);
             });
             HifStep step;
             std::vector<std::vector<int>> remain(ncell);
@@ -606,6 +613,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
         if (sh > 0) nshift.fetch_add(1);
     }
     F.shifted = nshift.load();
+    F.device_ids = ndev.load();
     return F;
 }
 

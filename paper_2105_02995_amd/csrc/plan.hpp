@@ -24,11 +24,11 @@ struct HostFactors {
 
 // Builds the factors; `gpu` (may be empty) replaces the host product Kd^* Kd of the
 // peeling step, `ids` (may be empty) the host interpolative decompositions of the
-// butterfly.
+// butterfly, `big_id` (may be empty) the large IDs of the 2D skeletonization.
 using PeelApplyFactory = std::function<BlockApply(const std::vector<Stage> &fwd,
                                                   const std::vector<Stage> &adj)>;
 void build_host_factors(const fio_problem &p, HostFactors &out, const PeelApplyFactory &gpu,
-                        const BatchedIdFactory &ids);
+                        const BatchedIdFactory &ids, const BigIdFn &big_id = BigIdFn());
 
 void save_factors(const HostFactors &f, const std::string &path);
 void load_factors(const std::string &path, HostFactors &f);

@@ -66,7 +66,8 @@ class fio_plan_stats_t(ctypes.Structure):
                 ("root_size", ctypes.c_int), ("max_rank_h", ctypes.c_int),
                 ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("hif_shifted", ctypes.c_int),
-                ("bf_seconds", ctypes.c_double), ("bf_device_levels", ctypes.c_int)]
+                ("bf_seconds", ctypes.c_double), ("bf_device_levels", ctypes.c_int),
+                ("hif_device_ids", ctypes.c_int)]
 
 
 _lib = None

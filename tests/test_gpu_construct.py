@@ -60,6 +60,14 @@ def test_every_level_decomposed_on_the_device(d, n, phase, eps):
     assert abs(sd["bf_nnz"] - sh["bf_nnz"]) <= 0.05 * sh["bf_nnz"]
     log("bf %.2fs device vs %.2fs host; max rank %d vs %d" % (sd["bf_seconds"], sh["bf_seconds"],
                                                               sd["max_rank_bf"], sh["max_rank_bf"]))
+    assert sh["hif_device_ids"] == 0
+    if d == 2:
+        # the large IDs of the coarse 2D skeletonization ran on the device too, with
+        # the same rank criterion (skeleton sizes agree up to near-ties)
+        assert sd["hif_device_ids"] > 0
+        assert abs(sd["root_size"] - sh["root_size"]) <= 0.02 * sh["root_size"]
+        log("2D skeletonization: %d IDs on the device; root %d vs %d" % (sd["hif_device_ids"], sd["root_size"],
+                                                                          sh["root_size"]))
 
 
 @pytest.mark.parametrize("d,n,phase,eps", CASES)
