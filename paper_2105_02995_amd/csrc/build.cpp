@@ -85,13 +85,14 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     out.d = p.d; out.n = p.n; out.N = B.N; out.L = B.L; out.Lm = B.Lm; out.m = B.m;
     out.perm = K.to_nat;
     out.prob = p;
+    // Peeling needs products with A = Kd^* Kd (section 5): on the GPU when available
+    // (which forms the adjoint stages itself), else on the host.
     std::vector<Stage> adj;
-    for (int s = (int)B.fwd.size() - 1; s >= 0; --s) adj.push_back(adjoint_stage(B.fwd[s]));
-    // Peeling needs products with A = Kd^* Kd (section 5): on the GPU when available.
     BlockApply A;
     if (gpu) {
-        A = gpu(B.fwd, adj);
+        A = gpu(B.fwd);
     } else {
+        for (int s = (int)B.fwd.size() - 1; s >= 0; --s) adj.push_back(adjoint_stage(B.fwd[s]));
         const int64_t N = B.N;
         const int nt = p.nthreads;
         // N and nt by value: the product outlives this block

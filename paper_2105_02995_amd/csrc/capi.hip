@@ -222,14 +222,51 @@ bool build_pair_table(const Stage &a, const Stage &b, std::vector<int32_t> &tab)
     return true;
 }
 
-void upload_complex(DBuf &b64, DBuf &b128, const std::vector<cd> &a) {
-    std::vector<float> f(2 * a.size());
-    for (size_t i = 0; i < a.size(); ++i) {
-        f[2 * i] = (float)a[i].real();
-        f[2 * i + 1] = (float)a[i].imag();
+// b = a rounded to complex FP32 (round to nearest, as the host conversion).
+__global__ __launch_bounds__(256) void k_to_c64(const double2 *a, float2 *b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double2 v = a[i];
+        b[i] = make_float2((float)v.x, (float)v.y);
     }
-    b64.upload(f.data(), f.size() * sizeof(float));
+}
+
+unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16)); }
+
+// Complex FP32 copy of a complex FP64 device array (synchronous).
+void to_c64(const DBuf &b128, DBuf &b64) {
+    const int64_t n = (int64_t)(b128.bytes / sizeof(cd));
+    b64.alloc((size_t)n * 8);
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_to_c64, dim3(grid_for(n)), dim3(256), 0, 0, (const double2 *)b128.p, (float2 *)b64.p, n);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(0));
+}
+
+// FP64 array to the device, with its complex FP32 copy formed there.
+void upload_complex(DBuf &b64, DBuf &b128, const std::vector<cd> &a) {
     b128.upload(a.data(), a.size() * sizeof(cd));
+    to_c64(b128, b64);
+}
+
+// Blocks of the adjoint stage (see adjoint_index): element (b, sl*r_out_s + a) of
+// target block `in` is conj of element (a, q*r_in_s + b) of source block o, where
+// src_of[in*fan_t + sl] = o*fan_s + q.  One thread per target element.
+__global__ __launch_bounds__(256) void k_adjoint_blocks(const double2 *src, double2 *dst, const int64_t *src_of,
+                                                        int64_t n_tgt, int fan_t, int r_out_s, int r_in_s,
+                                                        int fan_s) {
+    const int64_t cols = (int64_t)fan_t * r_out_s, per = cols * r_in_s, total = n_tgt * per;
+    const int64_t blk_s = (int64_t)r_out_s * fan_s * r_in_s;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t in = e / per, rem = e - in * per;
+        const int64_t c = rem / r_in_s;
+        const int b = (int)(rem - c * r_in_s);
+        const int sl = (int)(c / r_out_s), a = (int)(c - (int64_t)sl * r_out_s);
+        const int64_t oq = src_of[in * fan_t + sl];
+        const int64_t o = oq / fan_s;
+        const int q = (int)(oq - o * fan_s);
+        const double2 v = src[o * blk_s + a + ((int64_t)q * r_in_s + b) * r_out_s];
+        dst[e] = make_double2(v.x, -v.y);
+    }
 }
 
 }  // namespace
@@ -289,6 +326,56 @@ void upload_stages(const std::vector<Stage> &st, std::vector<DStageStore<int>> &
     }
 }
 
+// The adjoint chain formed on the device from the forward one: host index parts
+// (sizes and in_idx, no blocks) in `adj`, device blocks in `dadj` (adj[k] is the
+// adjoint of fwd[S-1-k]).
+void device_adjoints(const std::vector<Stage> &fwd, const std::vector<DStageStore<int>> &dfwd,
+                     std::vector<Stage> &adj, std::vector<DStageStore<int>> &dadj) {
+    const size_t S = fwd.size();
+    adj.assign(S, Stage());
+    dadj.resize(S);
+    std::vector<int64_t> src_of;
+    for (size_t k = 0; k < S; ++k) {
+        const Stage &f = fwd[S - 1 - k];
+        Stage &t = adj[k];
+        t = adjoint_index(f, src_of);
+        DStageStore<int> &d = dadj[k];
+        d.idx.upload(t.in_idx.data(), t.in_idx.size() * sizeof(int32_t));
+        DBuf so;
+        so.upload(src_of.data(), src_of.size() * sizeof(int64_t));
+        const int64_t total = t.nnz();
+        d.A128.alloc((size_t)total * sizeof(cd));
+        if (total > 0) {
+            hipLaunchKernelGGL(k_adjoint_blocks, dim3(grid_for(total)), dim3(256), 0, 0,
+                               (const double2 *)dfwd[S - 1 - k].A128.p, (double2 *)d.A128.p,
+                               (const int64_t *)so.p, t.n_out, t.fan, f.r_out, f.r_in, f.fan);
+            HIPC(hipGetLastError());
+            HIPC(hipStreamSynchronize(0));
+        }
+        to_c64(d.A128, d.A64);
+    }
+}
+
+// Host index parts of the adjoint chain (a plan without a device, or one whose
+// device chains are formed later).
+std::vector<Stage> adjoint_indexes(const std::vector<Stage> &fwd) {
+    std::vector<Stage> adj;
+    std::vector<int64_t> src_of;
+    for (int s = (int)fwd.size() - 1; s >= 0; --s) adj.push_back(adjoint_index(fwd[s], src_of));
+    return adj;
+}
+
+// Both chains on the device (the plan's images, also used by the peeling products).
+struct DeviceChains {
+    std::vector<Stage> adj;                   // index parts of the adjoint stages
+    std::vector<DStageStore<int>> dfwd, dadj;
+};
+
+void upload_chains(const std::vector<Stage> &fwd, DeviceChains &c) {
+    upload_stages(fwd, c.dfwd);
+    device_adjoints(fwd, c.dfwd, c.adj, c.dadj);
+}
+
 void upload_pairs(const std::vector<Stage> &st, std::vector<DPair> &d) {
     d.assign(st.empty() ? 0 : st.size() - 1, DPair());
     std::vector<int32_t> tab;
@@ -308,8 +395,13 @@ void upload_pairs(const std::vector<Stage> &st, std::vector<DPair> &d) {
 void upload_plan(fio_plan p) {
     HIPC(hipSetDevice(p->device));
     const HostFactors &h = p->host;
-    upload_stages(h.fwd, p->dfwd);
-    upload_stages(p->adj, p->dadj);
+    if (p->dfwd.empty()) {  // not formed by the build already
+        DeviceChains c;
+        upload_chains(h.fwd, c);
+        p->adj.swap(c.adj);
+        p->dfwd.swap(c.dfwd);
+        p->dadj.swap(c.dadj);
+    }
     upload_pairs(h.fwd, p->pfwd);
     upload_pairs(p->adj, p->padj);
     p->max_coef = h.N;
@@ -541,17 +633,15 @@ template <class F> fio_status guard(F &&f) {
 }
 
 // Builder hook: products with Kd^* Kd for the peeling step on the plan's GPU (FP64).
-PeelApplyFactory gpu_peel_factory(int device) {
-    return [device](const std::vector<Stage> &fwd, const std::vector<Stage> &adj) -> BlockApply {
-        auto df = std::make_shared<std::vector<DStageStore<int>>>();
-        auto da = std::make_shared<std::vector<DStageStore<int>>>();
+// The device chains it forms are kept in `c` for the plan.
+PeelApplyFactory gpu_peel_factory(int device, std::shared_ptr<DeviceChains> c) {
+    return [device, c](const std::vector<Stage> &fwd) -> BlockApply {
         HIPC(hipSetDevice(device));
-        upload_stages(fwd, *df);
-        upload_stages(adj, *da);
+        if (c->dfwd.empty()) upload_chains(fwd, *c);
         int64_t maxc = 0;
         for (auto &s : fwd) maxc = std::max<int64_t>(maxc, std::max(s.n_out * s.r_out, s.n_in * s.r_in));
         const int64_t N = fwd.front().n_in * fwd.front().r_in;
-        return [df, da, maxc, N, device, &fwd, &adj](const cd *x, cd *y, int nr) {
+        return [c, maxc, N, device, &fwd](const cd *x, cd *y, int nr) {
             HIPC(hipSetDevice(device));
             DBuf in, out, P, Q;
             in.alloc((size_t)N * nr * 16);
@@ -568,8 +658,8 @@ PeelApplyFactory gpu_peel_factory(int device) {
                     cur = t;
                 }
             };
-            chain(fwd, *df, in.p, out.p);
-            chain(adj, *da, out.p, in.p);
+            chain(fwd, c->dfwd, in.p, out.p);
+            chain(c->adj, c->dadj, out.p, in.p);
             HIPC(hipMemcpy(y, in.p, (size_t)N * nr * 16, hipMemcpyDeviceToHost));
         };
     };
@@ -599,14 +689,22 @@ fio_status fio_build(const fio_problem *prob, fio_plan *out) {
         // Peeling products on the GPU when the plan has one (host otherwise).
         PeelApplyFactory f;
         BatchedIdFactory ids;
-        if (p->device >= 0) f = gpu_peel_factory(p->device);
+        auto chains = std::make_shared<DeviceChains>();
+        if (p->device >= 0) f = gpu_peel_factory(p->device, chains);
         BigIdFn big;
         if (p->device >= 0 && !prob->host_construction) {
             ids = device_id_factory(p->device);
             big = device_big_id(p->device);
         }
         build_host_factors(*prob, p->host, f, ids, big);
-        for (int s = (int)p->host.fwd.size() - 1; s >= 0; --s) p->adj.push_back(adjoint_stage(p->host.fwd[s]));
+        f = nullptr;
+        if (!chains->dfwd.empty()) {  // the chains the peeling products used
+            p->adj.swap(chains->adj);
+            p->dfwd.swap(chains->dfwd);
+            p->dadj.swap(chains->dadj);
+        } else if (p->device < 0) {
+            p->adj = adjoint_indexes(p->host.fwd);
+        }
         if (p->device >= 0) upload_plan(p.get());
         *out = p.release();
     });
@@ -620,8 +718,8 @@ fio_status fio_load(const char *path, int device, fio_plan *out) {
         load_factors(path, p->host);
         p->host.prob.device = device;
         p->device = device;
-        for (int s = (int)p->host.fwd.size() - 1; s >= 0; --s) p->adj.push_back(adjoint_stage(p->host.fwd[s]));
         if (device >= 0) upload_plan(p.get());
+        else p->adj = adjoint_indexes(p->host.fwd);
         *out = p.release();
     });
 }

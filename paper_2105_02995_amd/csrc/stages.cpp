@@ -4,7 +4,7 @@
 
 namespace fio {
 
-Stage adjoint_stage(const Stage &s) {
+Stage adjoint_index(const Stage &s, std::vector<int64_t> &src_of) {
     Stage t;
     t.n_out = s.n_in;
     t.n_in = s.n_out;
@@ -19,25 +19,43 @@ Stage adjoint_stage(const Stage &s) {
         if (c != fan) fail(FIO_ERR_ARG, "adjoint_stage: non-uniform fan-out");
     t.fan = fan;
     t.in_idx.assign((size_t)t.n_out * fan, -1);
-    t.A.assign((size_t)t.n_out * t.r_out * fan * t.r_in, cd(0));
+    // Slot sl of target block `in` takes the uses of `in` in source order.
+    src_of.assign((size_t)t.n_out * fan, -1);
     std::vector<int32_t> slot(s.n_in, 0);
+    for (int64_t o = 0; o < s.n_out; ++o)
+        for (int q = 0; q < s.fan; ++q) {
+            const int32_t in = s.in_idx[o * s.fan + q];
+            const int sl = slot[in]++;
+            t.in_idx[(size_t)in * fan + sl] = (int32_t)o;
+            src_of[(size_t)in * fan + sl] = o * s.fan + q;
+        }
+    return t;
+}
+
+Stage adjoint_stage(const Stage &s) {
+    std::vector<int64_t> src_of;
+    Stage t = adjoint_index(s, src_of);
+    const int fan = t.fan;
+    t.A.resize((size_t)t.n_out * t.r_out * fan * t.r_in);
     const int64_t ldA = s.r_out;                   // leading dim of a source block
     const int64_t ldT = t.r_out;                   // leading dim of a target block
-    for (int64_t o = 0; o < s.n_out; ++o) {
-        const cd *src = s.A.data() + (size_t)o * s.block_elems();
-        for (int q = 0; q < s.fan; ++q) {
-            int32_t in = s.in_idx[o * s.fan + q];
-            int sl = slot[in]++;
-            t.in_idx[(size_t)in * fan + sl] = (int32_t)o;
-            cd *dst = t.A.data() + (size_t)in * t.block_elems();
+    // target blocks are disjoint: one task per block
+    parallel_for(t.n_out, 0, [&](int64_t in) {
+        cd *dst = t.A.data() + (size_t)in * t.block_elems();
+        for (int sl = 0; sl < fan; ++sl) {
+            const int64_t oq = src_of[(size_t)in * fan + sl];
+            const int64_t o = oq / s.fan;
+            const int q = (int)(oq - o * s.fan);
+            const cd *src = s.A.data() + (size_t)o * s.block_elems();
             // target block (r_in x r_out) at column offset sl*r_out = conj transpose of
             // source block columns [q*r_in, (q+1)*r_in)
-            for (int a = 0; a < s.r_out; ++a)
-                for (int b = 0; b < s.r_in; ++b)
-                    dst[b + (int64_t)(sl * s.r_out + a) * ldT] =
-                        std::conj(src[a + (int64_t)(q * s.r_in + b) * ldA]);
+            for (int a = 0; a < s.r_out; ++a) {
+                cd *d = dst + (int64_t)(sl * s.r_out + a) * ldT;
+                const cd *sa = src + a + (int64_t)q * s.r_in * ldA;
+                for (int b = 0; b < s.r_in; ++b) d[b] = std::conj(sa[(int64_t)b * ldA]);
+            }
         }
-    }
+    });
     return t;
 }
 

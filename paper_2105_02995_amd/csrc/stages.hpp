@@ -26,6 +26,10 @@ struct Stage {
 // Adjoint stage: maps y (n_out blocks) back to x (n_in blocks) with blocks A^*.
 // Every input block must be used by the same number of outputs.
 Stage adjoint_stage(const Stage &s);
+// Its index part only (sizes and in_idx; A left empty).  src_of[in*fan + sl] =
+// o*s.fan + q: target slot sl of block `in` is the conjugate transpose of column
+// group q of source block o.
+Stage adjoint_index(const Stage &s, std::vector<int64_t> &src_of);
 
 // Host product of a stage chain on nrhs vectors stored point-major
 // (entry (e, b) of a vector block at e*nrhs + b).  Used by the factor
