@@ -219,6 +219,9 @@ typedef struct {
     int bf_device_levels;          /* butterfly levels decomposed on the device (not stored) */
     int hif_device_ids;            /* skeletonization IDs (large 2D cells and edges) computed
                                       on the device (not stored)                       */
+    int hif_device_nodes;          /* skeletonization nodes (large 2D cells and edges) whose
+                                      Schur update, Cholesky factor and L^{-1}, M blocks
+                                      were formed on the device (not stored)           */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

@@ -23,6 +23,7 @@ CXX_SOURCES = ["la.cpp", "stages.cpp", "butterfly.cpp", "hif1d.cpp", "hif2d.cpp"
 HIP_SOURCES = ["kernels.hip", "construct.hip", "capi.hip"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+HOST_FLAGS = ["-fcomplex-arithmetic=improved"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops"]
 
@@ -38,7 +39,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     jobs = []
     for s in CXX_SOURCES:
-        jobs.append([CLANGXX, *COMMON, "-c", os.path.join(CSRC, s),
+        jobs.append([CLANGXX, *COMMON, *HOST_FLAGS, "-c", os.path.join(CSRC, s),
                      "-o", os.path.join(OBJ, s + ".o")])
     for s in HIP_SOURCES:
         jobs.append([HIPCC, *COMMON, *HIP_FLAGS, "-c", os.path.join(CSRC, s),
@@ -52,7 +53,7 @@ def build(verbose: bool = False) -> str:
     objs = [os.path.join(OBJ, s + ".o") for s in CXX_SOURCES + HIP_SOURCES]
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lpthread",
-          "-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+          "-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-lrocsolver", "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, LIB)
     # the C ABI from plain C: a file-to-file solve (HIP runtime C API for device memory)
     ex = os.path.join(HERE, "fio_solve_file")

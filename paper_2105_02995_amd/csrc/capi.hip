@@ -692,11 +692,14 @@ fio_status fio_build(const fio_problem *prob, fio_plan *out) {
         auto chains = std::make_shared<DeviceChains>();
         if (p->device >= 0) f = gpu_peel_factory(p->device, chains);
         BigIdFn big;
+        BigNodeFn node;
         if (p->device >= 0 && !prob->host_construction) {
             ids = device_id_factory(p->device);
             big = device_big_id(p->device);
+            node = device_big_node(p->device);
         }
-        build_host_factors(*prob, p->host, f, ids, big);
+        build_host_factors(*prob, p->host, f, ids, big, node);
+        node = nullptr;
         f = nullptr;
         if (!chains->dfwd.empty()) {  // the chains the peeling products used
             p->adj.swap(chains->adj);
@@ -756,6 +759,7 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
         o->bf_seconds = h.bf_seconds;
         o->bf_device_levels = h.bf_device_levels;
         o->hif_device_ids = h.hif.device_ids;
+        o->hif_device_nodes = h.hif.device_nodes;
     });
 }
 

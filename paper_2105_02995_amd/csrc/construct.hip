@@ -16,6 +16,9 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "butterfly.hpp"
 #include "hif.hpp"
 
@@ -629,6 +632,111 @@ bool big_column_id(int device, const Mat &Ah, double tol_rel, ColumnID &out) {
     return true;
 }
 
+// ---- dense algebra of one large skeletonization node ----
+
+// Lower triangle of A (n x n, leading dimension n) := Hermitian part (A + A^*)/2.
+__global__ __launch_bounds__(256) void k_herm_lower(double2 *A, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t j = e / n;
+        const int64_t i = e - j * n;
+        if (i <= j) continue;
+        const double2 l = A[e], u = A[i * n + j];
+        A[e] = make_double2(0.5 * (l.x + u.x), 0.5 * (l.y - u.y));
+    }
+}
+
+// Strict upper triangle of A (n x n) := 0.
+__global__ __launch_bounds__(256) void k_zero_upper(double2 *A, int n) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t j = e / n;
+        if (e - j * n < j) A[e] = make_double2(0.0, 0.0);
+    }
+}
+
+#define RB(x)                                                                                 \
+    do {                                                                                      \
+        rocblas_status s_ = (x);                                                              \
+        if (s_ != rocblas_status_success)                                                     \
+            fail(FIO_ERR_DEVICE, std::string(#x) + ": " + rocblas_status_to_string(s_));      \
+    } while (0)
+
+struct NodeEngine {
+    int device = 0;
+    rocblas_handle h = nullptr;
+    std::mutex mu;
+    ~NodeEngine() {
+        if (h) {
+            (void)hipSetDevice(device);
+            (void)rocblas_destroy_handle(h);
+        }
+    }
+};
+
+unsigned grid256(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16)); }
+
+bool big_node_device(NodeEngine &E, const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M,
+                     Mat &delta) {
+    const int nr = Arr.m, ns = Ass.m;
+    if (nr < 1 || ns < 1 || Arr.n != nr || Asr.m != ns || Asr.n != nr || Ass.n != ns || T.m != ns || T.n != nr)
+        return false;
+    std::lock_guard<std::mutex> lk(E.mu);  // one node at a time on the device
+    CHK(hipSetDevice(E.device));
+    if (!E.h) RB(rocblas_create_handle(&E.h));
+    RB(rocblas_set_stream(E.h, 0));
+    RB(rocblas_set_pointer_mode(E.h, rocblas_pointer_mode_host));
+    DevMem dA, dS, dQ, dT, dU, dM, dD, dinfo;
+    const size_t bR = (size_t)nr * nr * 16, bSR = (size_t)ns * nr * 16, bS = (size_t)ns * ns * 16;
+    dA.alloc(bR);   // Arr -> Atr -> L -> L^{-1}
+    dS.alloc(bSR);  // Asr -> Ats = Asr - Ass T
+    dQ.alloc(bS);   // Ass
+    dT.alloc(bSR);  // T
+    dU.alloc(bSR);  // Ass T
+    dM.alloc(bSR);
+    dD.alloc(bS);
+    dinfo.alloc(sizeof(rocblas_int));
+    CHK(hipMemcpy(dA.p, Arr.a.data(), bR, hipMemcpyHostToDevice));
+    CHK(hipMemcpy(dS.p, Asr.a.data(), bSR, hipMemcpyHostToDevice));
+    CHK(hipMemcpy(dQ.p, Ass.a.data(), bS, hipMemcpyHostToDevice));
+    CHK(hipMemcpy(dT.p, T.a.data(), bSR, hipMemcpyHostToDevice));
+    auto A = (rocblas_double_complex *)dA.p, S = (rocblas_double_complex *)dS.p, Q = (rocblas_double_complex *)dQ.p,
+         Tm = (rocblas_double_complex *)dT.p, U = (rocblas_double_complex *)dU.p, Mm = (rocblas_double_complex *)dM.p,
+         D = (rocblas_double_complex *)dD.p;
+    const rocblas_double_complex one(1.0, 0.0), mone(-1.0, 0.0), zero(0.0, 0.0);
+    const auto N = rocblas_operation_none, C = rocblas_operation_conjugate_transpose;
+    // U = Ass T; Atr = Arr - T^* Asr - Asr^* T + T^* U
+    RB(rocblas_zgemm(E.h, N, N, ns, nr, ns, &one, Q, ns, Tm, ns, &zero, U, ns));
+    RB(rocblas_zgemm(E.h, C, N, nr, nr, ns, &mone, Tm, ns, S, ns, &one, A, nr));
+    RB(rocblas_zgemm(E.h, C, N, nr, nr, ns, &mone, S, ns, Tm, ns, &one, A, nr));
+    RB(rocblas_zgemm(E.h, C, N, nr, nr, ns, &one, Tm, ns, U, ns, &one, A, nr));
+    hipLaunchKernelGGL(k_herm_lower, dim3(grid256((int64_t)nr * nr)), dim3(256), 0, 0, (double2 *)A, nr);
+    CHK(hipGetLastError());
+    // Ats = Asr - Ass T (in place of Asr, whose uses are done)
+    RB(rocblas_zgemm(E.h, N, N, ns, nr, ns, &mone, Q, ns, Tm, ns, &one, S, ns));
+    // L L^* = Atr, then L^{-1}
+    rocblas_int info = 0;
+    RB(rocsolver_zpotrf(E.h, rocblas_fill_lower, nr, A, nr, (rocblas_int *)dinfo.p));
+    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    if (info != 0) return false;  // not numerically HPD: the host path decides
+    RB(rocsolver_ztrtri(E.h, rocblas_fill_lower, rocblas_diagonal_non_unit, nr, A, nr, (rocblas_int *)dinfo.p));
+    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    if (info != 0) return false;
+    hipLaunchKernelGGL(k_zero_upper, dim3(grid256((int64_t)nr * nr)), dim3(256), 0, 0, (double2 *)A, nr);
+    CHK(hipGetLastError());
+    // M = Ats L^{-*}; delta = -M M^*
+    RB(rocblas_zgemm(E.h, N, C, ns, nr, nr, &one, S, ns, A, nr, &zero, Mm, ns));
+    RB(rocblas_zgemm(E.h, N, C, ns, ns, nr, &mone, Mm, ns, Mm, ns, &zero, D, ns));
+    Mat L(nr, nr), Mo(ns, nr), Do(ns, ns);
+    CHK(hipMemcpy(L.a.data(), dA.p, bR, hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(Mo.a.data(), dM.p, bSR, hipMemcpyDeviceToHost));
+    CHK(hipMemcpy(Do.a.data(), dD.p, bS, hipMemcpyDeviceToHost));
+    Linv = std::move(L);
+    M = std::move(Mo);
+    delta = std::move(Do);
+    return true;
+}
+
 }  // namespace
 
 BatchedIdFactory device_id_factory(int device) {
@@ -643,6 +751,14 @@ BigIdFn device_big_id(int device) {
     return [device, mu](const Mat &A, double tol_rel, ColumnID &out) {
         std::lock_guard<std::mutex> lk(*mu);  // one matrix at a time on the device
         return big_column_id(device, A, tol_rel, out);
+    };
+}
+
+BigNodeFn device_big_node(int device) {
+    auto e = std::make_shared<NodeEngine>();
+    e->device = device;
+    return [e](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M, Mat &delta) {
+        return big_node_device(*e, Arr, Asr, Ass, T, Linv, M, delta);
     };
 }
 

@@ -40,6 +40,7 @@ struct HifFactors {
     int max_rank_h = 0;             // largest off-diagonal rank of Sd
     int shifted = 0;                // pivot blocks (and root) that needed a diagonal shift
     int device_ids = 0;             // interpolative decompositions done on the device (not stored)
+    int device_nodes = 0;           // node factorizations done on the device (not stored)
 };
 
 // y = A x for nrhs vectors stored point-major (entry (e, b) at e*nrhs + b).
@@ -53,6 +54,18 @@ using BigIdFn = std::function<bool(const Mat &A, double tol_rel, ColumnID &out)>
 // and reflector and one for the trailing columns per step; serialised across host
 // threads).
 BigIdFn device_big_id(int device);
+
+// Dense algebra of one large skeletonization node (eq_sk, eq_sk_3): from the blocks
+// Arr, Asr, Ass of A_II on the redundant (r) and skeleton (s) DOFs and the ID's T,
+// forms Atr = Arr - T^* Asr - Asr^* T + T^* Ass T (made Hermitian), its Cholesky
+// factor L, Linv = L^{-1}, M = (Asr - Ass T) Linv^* and delta = -M M^*.  Returns
+// false (outputs untouched) if it declines or Atr is not numerically HPD, so that the
+// host path, which may shift the diagonal, takes the node.
+using BigNodeFn = std::function<bool(const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv,
+                                     Mat &M, Mat &delta)>;
+// The device implementation (rocBLAS GEMMs, rocSOLVER Cholesky and triangular
+// inverse, FP64; serialised across host threads).
+BigNodeFn device_big_node(int device);
 
 struct PeelOptions {
     double eps = 1e-6;      // relative tolerance (to ||S||_2) of the low-rank blocks
@@ -75,6 +88,8 @@ struct PeelOptions {
     bool prescale = false;
     // 2D: large column IDs of the skeletonization on a device (empty: host).
     BigIdFn big_id;
+    // 2D: dense algebra of large nodes on a device (empty: host).
+    BigNodeFn big_node;
 };
 
 // 1D HODLR peeling of a Hermitian operator given only by products (section 3),

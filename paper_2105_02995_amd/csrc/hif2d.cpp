@@ -387,9 +387,13 @@ struct NodeOut {
 // diagonal block A_II; same algebra as the 1D case (eq_sk, eq_sk_3).
 // Large IDs (coarse cells and edges) go to the device when the plan has one.
 constexpr int64_t BIG_ID_ENTRIES = 1 << 19;
+// ... and so does the dense algebra of nodes with at least this many multiply-adds
+// (nr^2 (nr + ns), the Schur update and Cholesky scale).
+constexpr double BIG_NODE_WORK = 1 << 26;
 
 NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, double eps, double shift0,
-               std::atomic<int> &nshift, const BigIdFn &big_id, std::atomic<int> &ndev) {
+               std::atomic<int> &nshift, const PeelOptions &po, std::atomic<int> &ndev,
+               std::atomic<int> &nnode) {
     NodeOut out;
     const int n = (int)I.size();
     std::vector<int> sk, rd;
@@ -399,7 +403,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         T = Mat(0, n);
     } else {
         ColumnID id;
-        if (big_id && (int64_t)Ubar.m * Ubar.n >= BIG_ID_ENTRIES && big_id(Ubar, eps, id))
+        if (po.big_id && (int64_t)Ubar.m * Ubar.n >= BIG_ID_ENTRIES && po.big_id(Ubar, eps, id))
             ndev.fetch_add(1);
         else
             id = column_id(Ubar, eps, 0, -1);
@@ -415,6 +419,17 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
     }
     for (int j = 0; j < ns; ++j)
         for (int i = 0; i < ns; ++i) Ass(i, j) = AII(sk[i], sk[j]);
+    const auto finish = [&]() {
+        out.nd.T = std::move(T);
+        for (int i : rd) out.nd.idx_r.push_back(I[i]);
+        for (int i : sk) out.nd.idx_s.push_back(I[i]);
+    };
+    if (po.big_node && nr > 0 && ns > 0 && (double)nr * nr * (nr + ns) >= BIG_NODE_WORK &&
+        po.big_node(Arr, Asr, Ass, T, out.nd.Linv, out.nd.M, out.delta)) {
+        nnode.fetch_add(1);
+        finish();
+        return out;
+    }
     Mat AssT = matmul(Ass, T);
     Mat Atr = Arr;
     gemm_acc(Atr, T, Asr, -1.0, 'C', 'N');
@@ -436,9 +451,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
     out.nd.M = matmul(Ats, out.nd.Linv, 'N', 'C');
     out.delta = Mat(ns, ns);
     gemm_acc(out.delta, out.nd.M, out.nd.M, -1.0, 'N', 'C');
-    out.nd.T = std::move(T);
-    for (int i : rd) out.nd.idx_r.push_back(I[i]);
-    for (int i : sk) out.nd.idx_s.push_back(I[i]);
+    finish();
     return out;
 }
 
@@ -471,7 +484,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
     const double normS = power_norm(A, g.N, 12, po.seed ^ 0x5EEDULL);
     Hmat2D H = peel_2d(A, g, po, normS);
     const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
-    std::atomic<int> nshift(0), ndev(0);
+    std::atomic<int> nshift(0), ndev(0), nnode(0);
     F.max_rank_h = H.max_rank;
     Active2D act(H);
     // active DOFs per cell at the current level
@@ -493,7 +506,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                 if (!Bnear.empty()) blocks.push_back(act.sub(Bnear, I));
                 far_rows(H, l, c, I, blocks);
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po.big_id, ndev);
+                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po, ndev, nnode);
             });
             HifStep step;
             for (int64_t c = 0; c < ncell; ++c) {
@@ -572,7 +585,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                     if (c1 == c2) break;
                 }
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po.big_id, ndev);
+                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po, ndev, nnode);
             });
             HifStep step;
             std::vector<std::vector<int>> remain(ncell);
@@ -614,6 +627,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
     }
     F.shifted = nshift.load();
     F.device_ids = ndev.load();
+    F.device_nodes = nnode.load();
     return F;
 }
 

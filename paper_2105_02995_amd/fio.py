@@ -67,7 +67,7 @@ class fio_plan_stats_t(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("hif_shifted", ctypes.c_int),
                 ("bf_seconds", ctypes.c_double), ("bf_device_levels", ctypes.c_int),
-                ("hif_device_ids", ctypes.c_int)]
+                ("hif_device_ids", ctypes.c_int), ("hif_device_nodes", ctypes.c_int)]
 
 
 _lib = None

@@ -64,10 +64,11 @@ def test_every_level_decomposed_on_the_device(d, n, phase, eps):
     if d == 2:
         # the large IDs of the coarse 2D skeletonization ran on the device too, with
         # the same rank criterion (skeleton sizes agree up to near-ties)
-        assert sd["hif_device_ids"] > 0
+        assert sd["hif_device_ids"] > 0 and sd["hif_device_nodes"] > 0
+        assert sh["hif_device_nodes"] == 0
         assert abs(sd["root_size"] - sh["root_size"]) <= 0.02 * sh["root_size"]
-        log("2D skeletonization: %d IDs on the device; root %d vs %d" % (sd["hif_device_ids"], sd["root_size"],
-                                                                          sh["root_size"]))
+        log("2D skeletonization: %d IDs and %d nodes on the device; root %d vs %d" % (
+            sd["hif_device_ids"], sd["hif_device_nodes"], sd["root_size"], sh["root_size"]))
 
 
 @pytest.mark.parametrize("d,n,phase,eps", CASES)
