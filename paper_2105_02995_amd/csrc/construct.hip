@@ -7,6 +7,11 @@
 //                per matrix, until the rank criterion or the fixed rank is reached,
 //   k_id_solve   the interpolation matrix T = R11^{-1} R12 by back substitution.
 // The host keeps the bookkeeping (candidates, samples, assembly of the stages).
+//
+// Also the large dense work of the 2D skeletonization (section 4): the column ID of
+// one tall stacked basis (k_lq_* kernels, one pivot step at a time, columns in
+// parallel) and the Schur update, Cholesky factor and inverse of one large node
+// (rocBLAS and rocSOLVER).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
