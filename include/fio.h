@@ -219,9 +219,9 @@ typedef struct {
     int bf_device_levels;          /* butterfly levels decomposed on the device (not stored) */
     int hif_device_ids;            /* skeletonization IDs (large 2D cells and edges) computed
                                       on the device (not stored)                       */
-    int hif_device_nodes;          /* skeletonization nodes (large 2D cells and edges) whose
-                                      Schur update, Cholesky factor and L^{-1}, M blocks
-                                      were formed on the device (not stored)           */
+    int hif_device_nodes;          /* large 2D skeletonization nodes whose Schur update,
+                                      Cholesky factor, L^{-1} and M were formed on the
+                                      device, plus 1 if A_0^{-1} was (not stored)      */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

@@ -62,7 +62,7 @@ fio_problem normalized_problem(const fio_problem &in) {
 }
 
 void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu,
-                        const BatchedIdFactory &ids, const BigIdFn &big_id, const BigNodeFn &big_node) {
+                        const BatchedIdFactory &ids, const SkelHooks &skel) {
     auto t0 = std::chrono::steady_clock::now();
     fio_problem p = normalized_problem(pin);
     FioKernel K;
@@ -111,8 +111,7 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     po.verbose = vb;
     po.allow_shift = p.strict_hpd == 0;
     po.prescale = p.prescale_skel != 0;
-    po.big_id = big_id;
-    po.big_node = big_node;
+    po.dev = skel;
     out.hif = (p.d == 1) ? build_hif_1d(A, B.N, po, p.eps_hif) : build_hif_2d(A, p.n, po, p.eps_hif);
     progress(vb,
              "inverse factors done: %zu steps, root %zu, %d shifted pivot blocks, %d IDs and %d nodes on the device "

@@ -691,15 +691,13 @@ fio_status fio_build(const fio_problem *prob, fio_plan *out) {
         BatchedIdFactory ids;
         auto chains = std::make_shared<DeviceChains>();
         if (p->device >= 0) f = gpu_peel_factory(p->device, chains);
-        BigIdFn big;
-        BigNodeFn node;
+        SkelHooks skel;
         if (p->device >= 0 && !prob->host_construction) {
             ids = device_id_factory(p->device);
-            big = device_big_id(p->device);
-            node = device_big_node(p->device);
+            skel = device_skel_hooks(p->device);
         }
-        build_host_factors(*prob, p->host, f, ids, big, node);
-        node = nullptr;
+        build_host_factors(*prob, p->host, f, ids, skel);
+        skel = SkelHooks();
         f = nullptr;
         if (!chains->dfwd.empty()) {  // the chains the peeling products used
             p->adj.swap(chains->adj);

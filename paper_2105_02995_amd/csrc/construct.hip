@@ -742,6 +742,40 @@ bool big_node_device(NodeEngine &E, const Mat &Arr, const Mat &Asr, const Mat &A
     return true;
 }
 
+bool hpd_inverse_device(NodeEngine &E, const Mat &Ah, Mat &inv) {
+    const int n = Ah.n;
+    if (n < 1 || Ah.m != n) return false;
+    std::lock_guard<std::mutex> lk(E.mu);
+    CHK(hipSetDevice(E.device));
+    if (!E.h) RB(rocblas_create_handle(&E.h));
+    RB(rocblas_set_stream(E.h, 0));
+    RB(rocblas_set_pointer_mode(E.h, rocblas_pointer_mode_host));
+    const size_t b = (size_t)n * n * 16;
+    DevMem dA, dX, dinfo;
+    dA.alloc(b);
+    dX.alloc(b);
+    dinfo.alloc(sizeof(rocblas_int));
+    CHK(hipMemcpy(dA.p, Ah.a.data(), b, hipMemcpyHostToDevice));
+    auto A = (rocblas_double_complex *)dA.p, X = (rocblas_double_complex *)dX.p;
+    rocblas_int info = 0;
+    RB(rocsolver_zpotrf(E.h, rocblas_fill_lower, n, A, n, (rocblas_int *)dinfo.p));
+    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    if (info != 0) return false;
+    RB(rocsolver_ztrtri(E.h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, A, n, (rocblas_int *)dinfo.p));
+    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    if (info != 0) return false;
+    hipLaunchKernelGGL(k_zero_upper, dim3(grid256((int64_t)n * n)), dim3(256), 0, 0, (double2 *)A, n);
+    CHK(hipGetLastError());
+    const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+    // A^{-1} = L^{-*} L^{-1}
+    RB(rocblas_zgemm(E.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, n, n, &one, A, n, A, n,
+                     &zero, X, n));
+    Mat out(n, n);
+    CHK(hipMemcpy(out.a.data(), dX.p, b, hipMemcpyDeviceToHost));
+    inv = std::move(out);
+    return true;
+}
+
 }  // namespace
 
 BatchedIdFactory device_id_factory(int device) {
@@ -751,20 +785,20 @@ BatchedIdFactory device_id_factory(int device) {
     };
 }
 
-BigIdFn device_big_id(int device) {
+SkelHooks device_skel_hooks(int device) {
+    SkelHooks h;
     auto mu = std::make_shared<std::mutex>();
-    return [device, mu](const Mat &A, double tol_rel, ColumnID &out) {
+    h.big_id = [device, mu](const Mat &A, double tol_rel, ColumnID &out) {
         std::lock_guard<std::mutex> lk(*mu);  // one matrix at a time on the device
         return big_column_id(device, A, tol_rel, out);
     };
-}
-
-BigNodeFn device_big_node(int device) {
     auto e = std::make_shared<NodeEngine>();
     e->device = device;
-    return [e](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M, Mat &delta) {
+    h.big_node = [e](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M, Mat &delta) {
         return big_node_device(*e, Arr, Asr, Ass, T, Linv, M, delta);
     };
+    h.hpd_inverse = [e](const Mat &A, Mat &inv) { return hpd_inverse_device(*e, A, inv); };
+    return h;
 }
 
 }  // namespace fio

@@ -40,7 +40,7 @@ struct HifFactors {
     int max_rank_h = 0;             // largest off-diagonal rank of Sd
     int shifted = 0;                // pivot blocks (and root) that needed a diagonal shift
     int device_ids = 0;             // interpolative decompositions done on the device (not stored)
-    int device_nodes = 0;           // node factorizations done on the device (not stored)
+    int device_nodes = 0;           // node factorizations (and root inverse) done on the device (not stored)
 };
 
 // y = A x for nrhs vectors stored point-major (entry (e, b) at e*nrhs + b).
@@ -53,7 +53,6 @@ using BigIdFn = std::function<bool(const Mat &A, double tol_rel, ColumnID &out)>
 // The device implementation (column-pivoted Householder QR, one launch for the pivot
 // and reflector and one for the trailing columns per step; serialised across host
 // threads).
-BigIdFn device_big_id(int device);
 
 // Dense algebra of one large skeletonization node (eq_sk, eq_sk_3): from the blocks
 // Arr, Asr, Ass of A_II on the redundant (r) and skeleton (s) DOFs and the ID's T,
@@ -63,9 +62,20 @@ BigIdFn device_big_id(int device);
 // host path, which may shift the diagonal, takes the node.
 using BigNodeFn = std::function<bool(const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv,
                                      Mat &M, Mat &delta)>;
-// The device implementation (rocBLAS GEMMs, rocSOLVER Cholesky and triangular
+// Inverse of one large Hermitian matrix (the top-level block A_0) by Cholesky:
+// A^{-1} = L^{-*} L^{-1}.  Returns false (inv untouched) if it declines or A is not
+// numerically HPD (the host path may then shift the diagonal).
+using HpdInverseFn = std::function<bool(const Mat &A, Mat &inv)>;
+
+// Device hooks of the 2D skeletonization (each may be empty: host).
+struct SkelHooks {
+    BigIdFn big_id;
+    BigNodeFn big_node;
+    HpdInverseFn hpd_inverse;
+};
+// The device implementations (rocBLAS GEMMs, rocSOLVER Cholesky and triangular
 // inverse, FP64; serialised across host threads).
-BigNodeFn device_big_node(int device);
+SkelHooks device_skel_hooks(int device);
 
 struct PeelOptions {
     double eps = 1e-6;      // relative tolerance (to ||S||_2) of the low-rank blocks
@@ -86,10 +96,9 @@ struct PeelOptions {
     // remains acts on I + T^* T.  Each level then has two steps: the scaling (a node
     // with only redundant DOFs and Linv = L^{-1}) and the skeletonization.
     bool prescale = false;
-    // 2D: large column IDs of the skeletonization on a device (empty: host).
-    BigIdFn big_id;
-    // 2D: dense algebra of large nodes on a device (empty: host).
-    BigNodeFn big_node;
+    // 2D: large column IDs, dense algebra of large nodes and the root inverse on a
+    // device (empty hooks: host).
+    SkelHooks dev;
 };
 
 // 1D HODLR peeling of a Hermitian operator given only by products (section 3),

@@ -403,7 +403,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         T = Mat(0, n);
     } else {
         ColumnID id;
-        if (po.big_id && (int64_t)Ubar.m * Ubar.n >= BIG_ID_ENTRIES && po.big_id(Ubar, eps, id))
+        if (po.dev.big_id && (int64_t)Ubar.m * Ubar.n >= BIG_ID_ENTRIES && po.dev.big_id(Ubar, eps, id))
             ndev.fetch_add(1);
         else
             id = column_id(Ubar, eps, 0, -1);
@@ -424,8 +424,8 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         for (int i : rd) out.nd.idx_r.push_back(I[i]);
         for (int i : sk) out.nd.idx_s.push_back(I[i]);
     };
-    if (po.big_node && nr > 0 && ns > 0 && (double)nr * nr * (nr + ns) >= BIG_NODE_WORK &&
-        po.big_node(Arr, Asr, Ass, T, out.nd.Linv, out.nd.M, out.delta)) {
+    if (po.dev.big_node && nr > 0 && ns > 0 && (double)nr * nr * (nr + ns) >= BIG_NODE_WORK &&
+        po.dev.big_node(Arr, Asr, Ass, T, out.nd.Linv, out.nd.M, out.delta)) {
         nnode.fetch_add(1);
         finish();
         return out;
@@ -621,9 +621,13 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                 A0(i, j) = v;
                 A0(j, i) = std::conj(v);
             }
-        const double sh = hpd_inverse_shifted(A0, F.A0inv, shift0);
-        if (sh < 0) fail(FIO_ERR_NOT_HPD, "2D top-level block is not HPD");
-        if (sh > 0) nshift.fetch_add(1);
+        if (po.dev.hpd_inverse && (double)A0.n * A0.n * A0.n >= BIG_NODE_WORK && po.dev.hpd_inverse(A0, F.A0inv)) {
+            nnode.fetch_add(1);
+        } else {
+            const double sh = hpd_inverse_shifted(A0, F.A0inv, shift0);
+            if (sh < 0) fail(FIO_ERR_NOT_HPD, "2D top-level block is not HPD");
+            if (sh > 0) nshift.fetch_add(1);
+        }
     }
     F.shifted = nshift.load();
     F.device_ids = ndev.load();

@@ -24,12 +24,10 @@ struct HostFactors {
 
 // Builds the factors; `gpu` (may be empty) replaces the host product Kd^* Kd of the
 // peeling step, `ids` (may be empty) the host interpolative decompositions of the
-// butterfly, `big_id` and `big_node` (may be empty) the large IDs and the dense
-// algebra of large nodes of the 2D skeletonization.
+// butterfly, `skel` (may be empty) the large dense work of the 2D skeletonization.
 using PeelApplyFactory = std::function<BlockApply(const std::vector<Stage> &fwd)>;
 void build_host_factors(const fio_problem &p, HostFactors &out, const PeelApplyFactory &gpu,
-                        const BatchedIdFactory &ids, const BigIdFn &big_id = BigIdFn(),
-                        const BigNodeFn &big_node = BigNodeFn());
+                        const BatchedIdFactory &ids, const SkelHooks &skel = SkelHooks());
 
 void save_factors(const HostFactors &f, const std::string &path);
 void load_factors(const std::string &path, HostFactors &f);
