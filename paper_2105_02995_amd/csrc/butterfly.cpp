@@ -115,6 +115,7 @@ static int level_ids(const FioKernel &K, const ButterflyOptions &opt, bool cand_
         r = *std::max_element(ranks.begin(), ranks.end());
     }
     r = std::min(ncand, std::max(1, r));
+    progress(opt.verbose, "  rank probe: %zu pairs, %d candidates, %d samples, rank %d", probe.size(), ncand, ns, r);
     on_rank(r);
     if (*dev) {
         IdBatch bt;
@@ -129,6 +130,7 @@ static int level_ids(const FioKernel &K, const ButterflyOptions &opt, bool cand_
             std::copy(T, T + (size_t)k * (ncand - k), id.T.a.begin());
             sink(pr, id);
         });
+        progress(opt.verbose, "  IDs of %lld pairs done", (long long)npairs);
         if (*dev) return r;
     }
     parallel_for(npairs, nt, [&](int64_t pr) {
