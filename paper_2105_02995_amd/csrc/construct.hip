@@ -425,6 +425,27 @@ bool run_batch(const Tables &tb, const IdBatch &bt, const IdSink &sink, int nthr
     return true;
 }
 
+#define RB(x)                                                                                 \
+    do {                                                                                      \
+        rocblas_status s_ = (x);                                                              \
+        if (s_ != rocblas_status_success)                                                     \
+            fail(FIO_ERR_DEVICE, std::string(#x) + ": " + rocblas_status_to_string(s_));      \
+    } while (0)
+
+struct NodeEngine {
+    int device = 0;
+    rocblas_handle h = nullptr;
+    std::mutex mu;
+    ~NodeEngine() {
+        if (h) {
+            (void)hipSetDevice(device);
+            (void)rocblas_destroy_handle(h);
+        }
+    }
+};
+
+unsigned grid256(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16)); }
+
 // ---- one large matrix: column-pivoted QR with column-parallel updates ----
 // state[0]: set once the next pivot is below the tolerance; state[1]: pivots done.
 // dstate[0]: absolute tolerance (from the largest initial column norm), dstate[1]:
@@ -570,57 +591,140 @@ __global__ void k_lq_finish(double2 *A, int64_t m, const int *state, const doubl
         A[(int64_t)(state[1] - 1) * m + (state[1] - 1)] = hh[1];
 }
 
-bool big_column_id(int device, const Mat &Ah, double tol_rel, ColumnID &out) {
-    const int64_t m = Ah.m;
-    const int n = Ah.n;
-    if (m < 1 || n < 1) return false;
-    CHK(hipSetDevice(device));
-    DevMem A, nrm, perm, st, dst, hh;
-    A.alloc((size_t)m * n * 16);
+// R (n x n, zero below the diagonal) from the upper triangle of A (lda rows).
+__global__ __launch_bounds__(256) void k_upper_copy(const double2 *A, int64_t lda, int n, double2 *R) {
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t j = e / n, i = e - j * n;
+        R[e] = (i <= j) ? A[j * lda + i] : make_double2(0.0, 0.0);
+    }
+}
+
+// flags[b] = 1 if block b saw a non-finite entry of A (total entries).
+__global__ __launch_bounds__(256) void k_nonfinite(const double2 *A, int64_t total, int *flags) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const double2 v = A[e];
+        bad |= !(isfinite(v.x) && isfinite(v.y));
+    }
+    if (bad) any = 1;  // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) flags[blockIdx.x] = any;
+}
+
+// Pivoted QR steps on the device (a: mrows x n, column-major, overwritten): rank k,
+// the pivot order and the top k rows of R (k x n).
+void device_cpqr_steps(double2 *a, int64_t mrows, int n, double tol_rel, int &k, std::vector<int> &order, Mat &R) {
+    DevMem nrm, perm, st, dst, hh;
     nrm.alloc((size_t)n * 8);
     perm.alloc((size_t)n * 4);
     st.alloc(4 * sizeof(int));
     dst.alloc(4 * sizeof(double));
     hh.alloc(2 * 16);
-    CHK(hipMemcpy(A.p, Ah.a.data(), (size_t)m * n * 16, hipMemcpyHostToDevice));
-    std::vector<int> order(n);
+    order.resize(n);
     for (int j = 0; j < n; ++j) order[j] = j;
     CHK(hipMemcpy(perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice));
     const int zero[4] = {0, 0, 0, 0};
     CHK(hipMemcpy(st.p, zero, sizeof(zero), hipMemcpyHostToDevice));
-    double2 *a = (double2 *)A.p;
-    hipLaunchKernelGGL(k_lq_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, 0, (const double2 *)a, m, n,
+    hipLaunchKernelGGL(k_lq_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, 0, (const double2 *)a, mrows, n,
                        (double *)nrm.p);
     CHK(hipGetLastError());
-    const int kmax = (int)std::min<int64_t>(m, n);
+    const int kmax = (int)std::min<int64_t>(mrows, n);
     int hs[4] = {0, 0, 0, 0};
-    for (int k = 0; k < kmax; ++k) {
-        hipLaunchKernelGGL(k_lq_pivot, dim3(1), dim3(256), 0, 0, a, m, n, k, (double *)nrm.p, (int *)perm.p, tol_rel,
-                           (int *)st.p, (double *)dst.p, (double2 *)hh.p);
-        const int cols = n - k - 1;
+    for (int s = 0; s < kmax; ++s) {
+        hipLaunchKernelGGL(k_lq_pivot, dim3(1), dim3(256), 0, 0, a, mrows, n, s, (double *)nrm.p, (int *)perm.p,
+                           tol_rel, (int *)st.p, (double *)dst.p, (double2 *)hh.p);
+        const int cols = n - s - 1;
         if (cols > 0) {
             const unsigned g = (unsigned)std::min<int64_t>((cols + 3) / 4, 4096);
-            hipLaunchKernelGGL(k_lq_update, dim3(g), dim3(256), 0, 0, a, m, n, k, (double *)nrm.p, (const int *)st.p,
-                               (const double *)dst.p, (const double2 *)hh.p);
+            hipLaunchKernelGGL(k_lq_update, dim3(g), dim3(256), 0, 0, a, mrows, n, s, (double *)nrm.p,
+                               (const int *)st.p, (const double *)dst.p, (const double2 *)hh.p);
         }
-        if ((k & 31) == 31) {  // early exit once the tolerance has been reached
+        if ((s & 31) == 31) {  // early exit once the tolerance has been reached
             CHK(hipMemcpy(hs, st.p, sizeof(hs), hipMemcpyDeviceToHost));
             if (hs[0]) break;
         }
     }
-    hipLaunchKernelGGL(k_lq_finish, dim3(1), dim3(64), 0, 0, a, m, (const int *)st.p, (const double2 *)hh.p);
+    hipLaunchKernelGGL(k_lq_finish, dim3(1), dim3(64), 0, 0, a, mrows, (const int *)st.p, (const double2 *)hh.p);
     CHK(hipGetLastError());
     CHK(hipMemcpy(hs, st.p, sizeof(hs), hipMemcpyDeviceToHost));
-    const int k = hs[1];
+    k = hs[1];
     CHK(hipMemcpy(order.data(), perm.p, (size_t)n * 4, hipMemcpyDeviceToHost));
-    Mat R(k, n);
+    R = Mat(k, n);
     if (k > 0)
-        CHK(hipMemcpy2D(R.a.data(), (size_t)k * 16, A.p, (size_t)m * 16, (size_t)k * 16, (size_t)n,
+        CHK(hipMemcpy2D(R.a.data(), (size_t)k * 16, a, (size_t)mrows * 16, (size_t)k * 16, (size_t)n,
                         hipMemcpyDeviceToHost));
-    out.skel.assign(order.begin(), order.begin() + k);
-    out.redund.assign(order.begin() + k, order.end());
-    out.T = Mat(k, n - k);
-    // T = R11^{-1} R12 by back substitution, column by column
+}
+
+bool big_column_id(NodeEngine &E, const Mat &Ah, double tol_rel, ColumnID &out) {
+    const int64_t m0 = Ah.m;
+    const int n0 = Ah.n;
+    if (m0 < 1 || n0 < 1 || m0 > INT32_MAX) return false;
+    // Exactly zero columns are redundant with zero interpolation coefficients; they
+    // are left out of the factorization (the library QR turns them into NaNs).
+    std::vector<int> nz, zc;
+    for (int j = 0; j < n0; ++j) {
+        const cd *c = Ah.col(j);
+        bool any = false;
+        for (int64_t i = 0; i < m0 && !any; ++i) any = c[i] != cd(0);
+        (any ? nz : zc).push_back(j);
+    }
+    const int n = (int)nz.size();
+    int k = 0;
+    std::vector<int> order;
+    Mat R;
+    if (n > 0) {
+        const Mat Ac = zc.empty() ? Mat() : cols_of(Ah, nz);
+        const Mat &A = zc.empty() ? Ah : Ac;
+        std::lock_guard<std::mutex> lk(E.mu);  // one matrix at a time on the device
+        CHK(hipSetDevice(E.device));
+        DevMem A0, Rt, tau, flags;
+        A0.alloc((size_t)m0 * n * 16);
+        CHK(hipMemcpy(A0.p, A.a.data(), (size_t)m0 * n * 16, hipMemcpyHostToDevice));
+        // A tall matrix is first reduced to its triangular factor R (A = QR, Householder,
+        // rocSOLVER): Q has orthonormal columns, so every column norm of every trailing
+        // block, hence every pivot and R11^{-1} R12, is that of A, and the pivoted
+        // steps touch n rows instead of m.  If that R holds a non-finite value the
+        // steps run on A itself.
+        bool qr = false;
+        if (m0 > n) {
+            if (!E.h) RB(rocblas_create_handle(&E.h));
+            RB(rocblas_set_stream(E.h, 0));
+            tau.alloc((size_t)n * 16);
+            RB(rocsolver_zgeqrf(E.h, (rocblas_int)m0, n, (rocblas_double_complex *)A0.p, (rocblas_int)m0,
+                                (rocblas_double_complex *)tau.p));
+            Rt.alloc((size_t)n * n * 16);
+            const int64_t nn = (int64_t)n * n;
+            hipLaunchKernelGGL(k_upper_copy, dim3(grid256(nn)), dim3(256), 0, 0, (const double2 *)A0.p, m0, n,
+                               (double2 *)Rt.p);
+            CHK(hipGetLastError());
+            const unsigned G = std::min(grid256(nn), 1024u);
+            flags.alloc((size_t)G * sizeof(int));
+            hipLaunchKernelGGL(k_nonfinite, dim3(G), dim3(256), 0, 0, (const double2 *)Rt.p, nn, (int *)flags.p);
+            CHK(hipGetLastError());
+            std::vector<int> fl(G);
+            CHK(hipMemcpy(fl.data(), flags.p, (size_t)G * sizeof(int), hipMemcpyDeviceToHost));
+            qr = std::find(fl.begin(), fl.end(), 1) == fl.end();
+            if (!qr) CHK(hipMemcpy(A0.p, A.a.data(), (size_t)m0 * n * 16, hipMemcpyHostToDevice));
+        }
+        if (qr) {
+            A0.alloc(0);
+            device_cpqr_steps((double2 *)Rt.p, n, n, tol_rel, k, order, R);
+        } else {
+            device_cpqr_steps((double2 *)A0.p, m0, n, tol_rel, k, order, R);
+        }
+    }
+    // map back to the columns of Ah; zero columns close the redundant set
+    out.skel.resize(k);
+    out.redund.clear();
+    for (int q = 0; q < k; ++q) out.skel[q] = nz[order[q]];
+    for (int q = k; q < n; ++q) out.redund.push_back(nz[order[q]]);
+    out.redund.insert(out.redund.end(), zc.begin(), zc.end());
+    out.T = Mat(k, n0 - k);
+    // T = R11^{-1} R12 by back substitution, column by column (host)
     par_cols(n - k, (double)k * k * (n - k) / 2.0, [&](int64_t jj) {
         const int j = (int)jj;
         cd *t = out.T.col(j);
@@ -659,27 +763,6 @@ __global__ __launch_bounds__(256) void k_zero_upper(double2 *A, int n) {
         if (e - j * n < j) A[e] = make_double2(0.0, 0.0);
     }
 }
-
-#define RB(x)                                                                                 \
-    do {                                                                                      \
-        rocblas_status s_ = (x);                                                              \
-        if (s_ != rocblas_status_success)                                                     \
-            fail(FIO_ERR_DEVICE, std::string(#x) + ": " + rocblas_status_to_string(s_));      \
-    } while (0)
-
-struct NodeEngine {
-    int device = 0;
-    rocblas_handle h = nullptr;
-    std::mutex mu;
-    ~NodeEngine() {
-        if (h) {
-            (void)hipSetDevice(device);
-            (void)rocblas_destroy_handle(h);
-        }
-    }
-};
-
-unsigned grid256(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16)); }
 
 bool big_node_device(NodeEngine &E, const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M,
                      Mat &delta) {
@@ -787,13 +870,11 @@ BatchedIdFactory device_id_factory(int device) {
 
 SkelHooks device_skel_hooks(int device) {
     SkelHooks h;
-    auto mu = std::make_shared<std::mutex>();
-    h.big_id = [device, mu](const Mat &A, double tol_rel, ColumnID &out) {
-        std::lock_guard<std::mutex> lk(*mu);  // one matrix at a time on the device
-        return big_column_id(device, A, tol_rel, out);
-    };
+    // one engine (one library handle, one lock) for all three: no two host threads
+    // drive the device at once
     auto e = std::make_shared<NodeEngine>();
     e->device = device;
+    h.big_id = [e](const Mat &A, double tol_rel, ColumnID &out) { return big_column_id(*e, A, tol_rel, out); };
     h.big_node = [e](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M, Mat &delta) {
         return big_node_device(*e, Arr, Asr, Ass, T, Linv, M, delta);
     };

@@ -6,6 +6,7 @@
 // level l is a contiguous range and its Morton index is the prefix of the DOF index.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -378,6 +379,26 @@ void far_rows(const Hmat2D &H, int l, int64_t c, const std::vector<int> &D, std:
     }
 }
 
+// Wall time per phase of a skeletonization level, summed over the node loop's threads
+// (verbose builds report it).
+struct PhaseTimes {
+    std::atomic<int64_t> ns[8] = {};
+    static int64_t now() {
+        return std::chrono::duration_cast<std::chrono::nanoseconds>(
+                   std::chrono::steady_clock::now().time_since_epoch())
+            .count();
+    }
+    void add(int k, int64_t t0) { ns[k].fetch_add(now() - t0); }
+    void report(bool on, const char *what, int l) {
+        progress(on,
+                 "  %s level %d thread-seconds: near %.2f far %.2f stack %.2f diag %.2f node %.2f (ID %.2f, "
+                 "elimination %.2f); merge %.2f",
+                 what, l, ns[0] * 1e-9, ns[1] * 1e-9, ns[2] * 1e-9, ns[3] * 1e-9, ns[4] * 1e-9, ns[6] * 1e-9,
+                 ns[7] * 1e-9, ns[5] * 1e-9);
+        for (auto &v : ns) v.store(0);
+    }
+};
+
 struct NodeOut {
     HifNode nd;
     Mat delta;  // Schur update on the skeleton DOFs (added to the active matrix)
@@ -393,7 +414,7 @@ constexpr double BIG_NODE_WORK = 1 << 26;
 
 NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, double eps, double shift0,
                std::atomic<int> &nshift, const PeelOptions &po, std::atomic<int> &ndev,
-               std::atomic<int> &nnode) {
+               std::atomic<int> &nnode, PhaseTimes &pt) {
     NodeOut out;
     const int n = (int)I.size();
     std::vector<int> sk, rd;
@@ -402,6 +423,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         for (int i = 0; i < n; ++i) rd.push_back(i);
         T = Mat(0, n);
     } else {
+        const int64_t t0 = PhaseTimes::now();
         ColumnID id;
         if (po.dev.big_id && (int64_t)Ubar.m * Ubar.n >= BIG_ID_ENTRIES && po.dev.big_id(Ubar, eps, id))
             ndev.fetch_add(1);
@@ -410,7 +432,9 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         sk = id.skel;
         rd = id.redund;
         T = std::move(id.T);
+        pt.add(6, t0);
     }
+    const int64_t t1 = PhaseTimes::now();
     const int ns = (int)sk.size(), nr = (int)rd.size();
     Mat Arr(nr, nr), Asr(ns, nr), Ass(ns, ns);
     for (int j = 0; j < nr; ++j) {
@@ -428,6 +452,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         po.dev.big_node(Arr, Asr, Ass, T, out.nd.Linv, out.nd.M, out.delta)) {
         nnode.fetch_add(1);
         finish();
+        pt.add(7, t1);
         return out;
     }
     Mat AssT = matmul(Ass, T);
@@ -452,6 +477,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
     out.delta = Mat(ns, ns);
     gemm_acc(out.delta, out.nd.M, out.nd.M, -1.0, 'N', 'C');
     finish();
+    pt.add(7, t1);
     return out;
 }
 
@@ -485,6 +511,7 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
     Hmat2D H = peel_2d(A, g, po, normS);
     const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
     std::atomic<int> nshift(0), ndev(0), nnode(0);
+    PhaseTimes pt;
     F.max_rank_h = H.max_rank;
     Active2D act(H);
     // active DOFs per cell at the current level
@@ -503,18 +530,32 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                 for (int64_t J : g.NL(l, c))
                     if (J != c) Bnear.insert(Bnear.end(), cells[J].begin(), cells[J].end());
                 std::vector<Mat> blocks;
+                int64_t t0 = PhaseTimes::now();
                 if (!Bnear.empty()) blocks.push_back(act.sub(Bnear, I));
+                pt.add(0, t0);
+                t0 = PhaseTimes::now();
                 far_rows(H, l, c, I, blocks);
+                pt.add(1, t0);
+                t0 = PhaseTimes::now();
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[c] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po, ndev, nnode);
+                pt.add(2, t0);
+                t0 = PhaseTimes::now();
+                Mat AII = act.sub(I, I);
+                pt.add(3, t0);
+                t0 = PhaseTimes::now();
+                res[c] = skel2d(I, Ubar, AII, eps_hif, shift0, nshift, po, ndev, nnode, pt);
+                pt.add(4, t0);
             });
             HifStep step;
+            const int64_t tm = PhaseTimes::now();
             for (int64_t c = 0; c < ncell; ++c) {
                 act.add(res[c].nd.idx_s, res[c].delta);
                 cells[c] = res[c].nd.idx_s;
                 step.nodes.push_back(std::move(res[c].nd));
             }
+            pt.add(5, tm);
             F.steps.push_back(std::move(step));
+            pt.report(po.verbose, "cells", l);
             progress(po.verbose, "cell skeletonization level %d done", l);
         }
         // ---- edge skeletonization (ID_2d_bases, eq_edge_sk_2d) ----
@@ -564,7 +605,10 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                     for (int d : cells[J])
                         if (!inE.count(d)) Bnear.push_back(d);
                 std::vector<Mat> blocks;
+                int64_t t0 = PhaseTimes::now();
                 if (!Bnear.empty()) blocks.push_back(act.sub(Bnear, I));
+                pt.add(0, t0);
+                t0 = PhaseTimes::now();
                 // far-field bases of each side, placed in the columns of that side
                 for (int64_t side_cell : {c1, c2}) {
                     std::vector<int> D, pos;
@@ -584,17 +628,28 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
                     }
                     if (c1 == c2) break;
                 }
+                pt.add(1, t0);
+                t0 = PhaseTimes::now();
                 Mat Ubar = stack_rows(blocks, (int)I.size());
-                res[e] = skel2d(I, Ubar, act.sub(I, I), eps_hif, shift0, nshift, po, ndev, nnode);
+                pt.add(2, t0);
+                t0 = PhaseTimes::now();
+                Mat AII = act.sub(I, I);
+                pt.add(3, t0);
+                t0 = PhaseTimes::now();
+                res[e] = skel2d(I, Ubar, AII, eps_hif, shift0, nshift, po, ndev, nnode, pt);
+                pt.add(4, t0);
             });
             HifStep step;
             std::vector<std::vector<int>> remain(ncell);
+            const int64_t tm = PhaseTimes::now();
             for (int64_t e = 0; e < 2 * ncell; ++e) {
                 if (!used[e]) continue;
                 act.add(res[e].nd.idx_s, res[e].delta);
                 for (int d : res[e].nd.idx_s) remain[g.cell_of(d, l)].push_back(d);
                 step.nodes.push_back(std::move(res[e].nd));
             }
+            pt.add(5, tm);
+            pt.report(po.verbose, "edges", l);
             F.steps.push_back(std::move(step));
             // merge child cells into their parents (level l-1)
             const int64_t npar = ncell / 4;
