@@ -272,6 +272,23 @@ fio_status fio_stage_pair_apply(fio_plan plan, fio_op op, int stage, fio_dtype d
 fio_status fio_stage_pair_apply_variant(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int variant,
                                         const void *x, void *y, int64_t nrhs, void *hip_stream);
 
+/* Column interpolative decomposition of one dense matrix on a device: the routine
+ * the 2D skeletonization runs for its large stacked bases (section 4, the ID of
+ * eq. ID_2d_bases), exposed for tests and measurement.  A(:, redund) ~= A(:, skel) T
+ * where skel are the first rank pivots of a column-pivoted Householder QR that stops
+ * before the first pivot whose trailing column norm is at most tol_rel times the
+ * largest column norm of A (pivot: largest trailing norm, first among equals; a tall
+ * A is first reduced to its triangular factor, which leaves every pivot unchanged;
+ * exactly zero columns are redundant with zero coefficients).  A: host, complex128,
+ * column-major m x n, leading dimension lda >= m, not modified.  Outputs, host: *rank;
+ * perm[n] with skel = perm[0..rank) and redund = perm[rank..n); T complex128,
+ * rank x (n - rank), column-major with leading dimension rank, in a buffer of t_cap
+ * elements.  Synchronous.  Errors: FIO_ERR_ARG (sizes, null pointers, device
+ * ordinal, t_cap < rank*(n - rank), with *rank set), FIO_ERR_UNSUPPORTED (m above
+ * 2^31 - 1), FIO_ERR_DEVICE, FIO_ERR_NOMEM. */
+fio_status fio_column_id(int device, int64_t m, int64_t n, const void *A, int64_t lda, double tol_rel, int *rank,
+                         int *perm, void *T, int64_t t_cap);
+
 /* The launches that an apply of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) makes at this
  * dtype and nrhs: launch j runs n_stages[j] (1 or 2) consecutive factors from
  * first_stage[j] with kernel variant variant[j] (single factor: the codes of

@@ -857,6 +857,30 @@ fio_status fio_stage_pair_apply_variant(fio_plan p, fio_op op, int stage, fio_dt
     });
 }
 
+fio_status fio_column_id(int device, int64_t m, int64_t n, const void *A, int64_t lda, double tol_rel, int *rank,
+                         int *perm, void *T, int64_t t_cap) {
+    return guard([&] {
+        if (!A || !rank || !perm || !T) fail(FIO_ERR_ARG, "null argument");
+        if (m < 1 || n < 1 || n > INT32_MAX || lda < m) fail(FIO_ERR_ARG, "bad matrix shape");
+        if (!(tol_rel >= 0)) fail(FIO_ERR_ARG, "tol_rel must be non-negative");
+        int cnt = 0;
+        HIPC(hipGetDeviceCount(&cnt));
+        if (device < 0 || device >= cnt) fail(FIO_ERR_ARG, "device ordinal out of range");
+        if (m > INT32_MAX) fail(FIO_ERR_UNSUPPORTED, "more than 2^31 - 1 rows");
+        Mat Ah((int)m, (int)n);
+        const cd *a = (const cd *)A;
+        for (int64_t j = 0; j < n; ++j) std::copy(a + j * lda, a + j * lda + m, Ah.col((int)j));
+        ColumnID id;
+        if (!device_skel_hooks(device).big_id(Ah, tol_rel, id)) fail(FIO_ERR_UNSUPPORTED, "matrix declined");
+        const int k = (int)id.skel.size();
+        *rank = k;
+        if ((int64_t)k * (n - k) > t_cap) fail(FIO_ERR_ARG, "T buffer too small for the rank");
+        for (int q = 0; q < k; ++q) perm[q] = id.skel[q];
+        for (int64_t q = k; q < n; ++q) perm[q] = id.redund[q - k];
+        std::copy(id.T.a.begin(), id.T.a.end(), (cd *)T);
+    });
+}
+
 fio_status fio_chain_schedule(fio_plan p, fio_op op, fio_dtype dt, int64_t nrhs, int cap, int *n_launch,
                               int *first_stage, int *n_stages, int *variant) {
     return guard([&] {

@@ -27,7 +27,7 @@ PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FI
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
-           "fio_last_error", "fio_set_trace"]
+           "fio_last_error", "fio_set_trace", "fio_column_id"]
 
 
 class FioError(RuntimeError):
@@ -86,6 +86,8 @@ def load_library():
     lib.fio_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_stage_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
     lib.fio_stage_pair_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
+    lib.fio_column_id.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, VP, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.POINTER(ctypes.c_int), VP, VP, ctypes.c_int64]
     lib.fio_stage_pair_apply_variant.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP,
                                                  I64, VP]
     IP = ctypes.POINTER(ctypes.c_int)
@@ -212,6 +214,22 @@ def fio_stage_pair_apply_variant(plan: Plan, op: int, stage: int, dtype: int, va
                                  stream=None):
     _check(load_library().fio_stage_pair_apply_variant(plan.handle, op, stage, dtype, variant, _ptr(x), _ptr(y),
                                                        nrhs, _stream(stream)))
+
+
+def fio_column_id(A, tol_rel: float, device: int = 0):
+    """Device column ID of a host complex128 matrix: (skel, redund, T) with
+    A[:, redund] ~= A[:, skel] @ T."""
+    import numpy as np
+    A = np.asfortranarray(np.asarray(A, dtype=np.complex128))
+    m, n = A.shape
+    rank = ctypes.c_int()
+    perm = np.zeros(n, dtype=np.int32)
+    T = np.zeros(max(1, (n * n) // 4 + n), dtype=np.complex128)
+    _check(load_library().fio_column_id(device, m, n, A.ctypes.data, m, tol_rel, ctypes.byref(rank),
+                                        perm.ctypes.data, T.ctypes.data, T.size))
+    k = rank.value
+    return perm[:k].copy(), perm[k:].copy(), T[:k * (n - k)].reshape(n - k, k).T.copy() if k * (n - k) else \
+        np.zeros((k, n - k), dtype=np.complex128)
 
 
 def fio_stage_pair_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
