@@ -432,16 +432,67 @@ bool run_batch(const Tables &tb, const IdBatch &bt, const IdSink &sink, int nthr
             fail(FIO_ERR_DEVICE, std::string(#x) + ": " + rocblas_status_to_string(s_));      \
     } while (0)
 
+// One lane of device work for the skeletonization hooks: its own stream, library
+// handle and grow-only buffers (no frees between calls, so lanes do not wait on each
+// other), used by one host thread at a time.
 struct NodeEngine {
     int device = 0;
+    hipStream_t st = nullptr;
     rocblas_handle h = nullptr;
     std::mutex mu;
+    struct Buf {
+        void *p = nullptr;
+        size_t cap = 0;
+    };
+    Buf buf[10];
     ~NodeEngine() {
-        if (h) {
-            (void)hipSetDevice(device);
-            (void)rocblas_destroy_handle(h);
+        (void)hipSetDevice(device);
+        if (h) (void)rocblas_destroy_handle(h);
+        for (Buf &b : buf)
+            if (b.p) (void)hipFree(b.p);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    // Called with mu held: current device, stream and handle ready.
+    void begin() {
+        CHK(hipSetDevice(device));
+        if (!st) CHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        if (!h) {
+            RB(rocblas_create_handle(&h));
+            RB(rocblas_set_stream(h, st));
+        }
+        RB(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+    }
+    void *get(int slot, size_t bytes) {
+        Buf &b = buf[slot];
+        if (b.cap < bytes) {
+            CHK(hipStreamSynchronize(st));
+            if (b.p) CHK(hipFree(b.p));
+            b.p = nullptr;
+            b.cap = 0;
+            CHK(hipMalloc(&b.p, std::max<size_t>(bytes, 256)));
+            b.cap = std::max<size_t>(bytes, 256);
+        }
+        return b.p;
+    }
+    // Copies ordered on the lane's stream, complete on return.
+    void copy(void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+        if (bytes == 0) return;
+        CHK(hipMemcpyAsync(dst, src, bytes, kind, st));
+        CHK(hipStreamSynchronize(st));
+    }
+};
+
+// A few lanes, handed out round robin.
+struct EnginePool {
+    std::vector<std::unique_ptr<NodeEngine>> lanes;
+    std::atomic<unsigned> next{0};
+    EnginePool(int device, int n) {
+        for (int i = 0; i < n; ++i) {
+            lanes.emplace_back(new NodeEngine());
+            lanes.back()->device = device;
         }
     }
+    NodeEngine &pick() { return *lanes[next.fetch_add(1) % lanes.size()]; }
 };
 
 unsigned grid256(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16)); }
@@ -617,46 +668,47 @@ __global__ __launch_bounds__(256) void k_nonfinite(const double2 *A, int64_t tot
 
 // Pivoted QR steps on the device (a: mrows x n, column-major, overwritten): rank k,
 // the pivot order and the top k rows of R (k x n).
-void device_cpqr_steps(double2 *a, int64_t mrows, int n, double tol_rel, int &k, std::vector<int> &order, Mat &R) {
-    DevMem nrm, perm, st, dst, hh;
-    nrm.alloc((size_t)n * 8);
-    perm.alloc((size_t)n * 4);
-    st.alloc(4 * sizeof(int));
-    dst.alloc(4 * sizeof(double));
-    hh.alloc(2 * 16);
+void device_cpqr_steps(NodeEngine &E, double2 *a, int64_t mrows, int n, double tol_rel, int &k,
+                       std::vector<int> &order, Mat &R) {
+    double *nrm = (double *)E.get(4, (size_t)n * 8);
+    int *perm = (int *)E.get(5, (size_t)n * 4);
+    int *st = (int *)E.get(6, 4 * sizeof(int));
+    double *dst = (double *)E.get(7, 4 * sizeof(double));
+    double2 *hh = (double2 *)E.get(8, 2 * 16);
     order.resize(n);
     for (int j = 0; j < n; ++j) order[j] = j;
-    CHK(hipMemcpy(perm.p, order.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    E.copy(perm, order.data(), (size_t)n * 4, hipMemcpyHostToDevice);
     const int zero[4] = {0, 0, 0, 0};
-    CHK(hipMemcpy(st.p, zero, sizeof(zero), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_lq_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, 0, (const double2 *)a, mrows, n,
-                       (double *)nrm.p);
+    E.copy(st, zero, sizeof(zero), hipMemcpyHostToDevice);
+    hipLaunchKernelGGL(k_lq_norms, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, E.st, (const double2 *)a, mrows, n,
+                       nrm);
     CHK(hipGetLastError());
     const int kmax = (int)std::min<int64_t>(mrows, n);
     int hs[4] = {0, 0, 0, 0};
     for (int s = 0; s < kmax; ++s) {
-        hipLaunchKernelGGL(k_lq_pivot, dim3(1), dim3(256), 0, 0, a, mrows, n, s, (double *)nrm.p, (int *)perm.p,
-                           tol_rel, (int *)st.p, (double *)dst.p, (double2 *)hh.p);
+        hipLaunchKernelGGL(k_lq_pivot, dim3(1), dim3(256), 0, E.st, a, mrows, n, s, nrm, perm, tol_rel, st, dst, hh);
         const int cols = n - s - 1;
         if (cols > 0) {
             const unsigned g = (unsigned)std::min<int64_t>((cols + 3) / 4, 4096);
-            hipLaunchKernelGGL(k_lq_update, dim3(g), dim3(256), 0, 0, a, mrows, n, s, (double *)nrm.p,
-                               (const int *)st.p, (const double *)dst.p, (const double2 *)hh.p);
+            hipLaunchKernelGGL(k_lq_update, dim3(g), dim3(256), 0, E.st, a, mrows, n, s, nrm, (const int *)st,
+                               (const double *)dst, (const double2 *)hh);
         }
         if ((s & 31) == 31) {  // early exit once the tolerance has been reached
-            CHK(hipMemcpy(hs, st.p, sizeof(hs), hipMemcpyDeviceToHost));
+            E.copy(hs, st, sizeof(hs), hipMemcpyDeviceToHost);
             if (hs[0]) break;
         }
     }
-    hipLaunchKernelGGL(k_lq_finish, dim3(1), dim3(64), 0, 0, a, mrows, (const int *)st.p, (const double2 *)hh.p);
+    hipLaunchKernelGGL(k_lq_finish, dim3(1), dim3(64), 0, E.st, a, mrows, (const int *)st, (const double2 *)hh);
     CHK(hipGetLastError());
-    CHK(hipMemcpy(hs, st.p, sizeof(hs), hipMemcpyDeviceToHost));
+    E.copy(hs, st, sizeof(hs), hipMemcpyDeviceToHost);
     k = hs[1];
-    CHK(hipMemcpy(order.data(), perm.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    E.copy(order.data(), perm, (size_t)n * 4, hipMemcpyDeviceToHost);
     R = Mat(k, n);
-    if (k > 0)
-        CHK(hipMemcpy2D(R.a.data(), (size_t)k * 16, a, (size_t)mrows * 16, (size_t)k * 16, (size_t)n,
-                        hipMemcpyDeviceToHost));
+    if (k > 0) {
+        CHK(hipMemcpy2DAsync(R.a.data(), (size_t)k * 16, a, (size_t)mrows * 16, (size_t)k * 16, (size_t)n,
+                             hipMemcpyDeviceToHost, E.st));
+        CHK(hipStreamSynchronize(E.st));
+    }
 }
 
 bool big_column_id(NodeEngine &E, const Mat &Ah, double tol_rel, ColumnID &out) {
@@ -679,42 +731,38 @@ bool big_column_id(NodeEngine &E, const Mat &Ah, double tol_rel, ColumnID &out) 
     if (n > 0) {
         const Mat Ac = zc.empty() ? Mat() : cols_of(Ah, nz);
         const Mat &A = zc.empty() ? Ah : Ac;
-        std::lock_guard<std::mutex> lk(E.mu);  // one matrix at a time on the device
-        CHK(hipSetDevice(E.device));
-        DevMem A0, Rt, tau, flags;
-        A0.alloc((size_t)m0 * n * 16);
-        CHK(hipMemcpy(A0.p, A.a.data(), (size_t)m0 * n * 16, hipMemcpyHostToDevice));
+        std::lock_guard<std::mutex> lk(E.mu);  // one host thread per lane
+        E.begin();
+        double2 *A0 = (double2 *)E.get(0, (size_t)m0 * n * 16);
+        E.copy(A0, A.a.data(), (size_t)m0 * n * 16, hipMemcpyHostToDevice);
         // A tall matrix is first reduced to its triangular factor R (A = QR, Householder,
         // rocSOLVER): Q has orthonormal columns, so every column norm of every trailing
         // block, hence every pivot and R11^{-1} R12, is that of A, and the pivoted
         // steps touch n rows instead of m.  If that R holds a non-finite value the
         // steps run on A itself.
         bool qr = false;
+        double2 *Rt = nullptr;
         if (m0 > n) {
-            if (!E.h) RB(rocblas_create_handle(&E.h));
-            RB(rocblas_set_stream(E.h, 0));
-            tau.alloc((size_t)n * 16);
-            RB(rocsolver_zgeqrf(E.h, (rocblas_int)m0, n, (rocblas_double_complex *)A0.p, (rocblas_int)m0,
-                                (rocblas_double_complex *)tau.p));
-            Rt.alloc((size_t)n * n * 16);
+            double2 *tau = (double2 *)E.get(2, (size_t)n * 16);
+            RB(rocsolver_zgeqrf(E.h, (rocblas_int)m0, n, (rocblas_double_complex *)A0, (rocblas_int)m0,
+                                (rocblas_double_complex *)tau));
             const int64_t nn = (int64_t)n * n;
-            hipLaunchKernelGGL(k_upper_copy, dim3(grid256(nn)), dim3(256), 0, 0, (const double2 *)A0.p, m0, n,
-                               (double2 *)Rt.p);
+            Rt = (double2 *)E.get(1, (size_t)nn * 16);
+            hipLaunchKernelGGL(k_upper_copy, dim3(grid256(nn)), dim3(256), 0, E.st, (const double2 *)A0, m0, n, Rt);
             CHK(hipGetLastError());
             const unsigned G = std::min(grid256(nn), 1024u);
-            flags.alloc((size_t)G * sizeof(int));
-            hipLaunchKernelGGL(k_nonfinite, dim3(G), dim3(256), 0, 0, (const double2 *)Rt.p, nn, (int *)flags.p);
+            int *flags = (int *)E.get(3, (size_t)G * sizeof(int));
+            hipLaunchKernelGGL(k_nonfinite, dim3(G), dim3(256), 0, E.st, (const double2 *)Rt, nn, flags);
             CHK(hipGetLastError());
             std::vector<int> fl(G);
-            CHK(hipMemcpy(fl.data(), flags.p, (size_t)G * sizeof(int), hipMemcpyDeviceToHost));
+            E.copy(fl.data(), flags, (size_t)G * sizeof(int), hipMemcpyDeviceToHost);
             qr = std::find(fl.begin(), fl.end(), 1) == fl.end();
-            if (!qr) CHK(hipMemcpy(A0.p, A.a.data(), (size_t)m0 * n * 16, hipMemcpyHostToDevice));
+            if (!qr) E.copy(A0, A.a.data(), (size_t)m0 * n * 16, hipMemcpyHostToDevice);
         }
         if (qr) {
-            A0.alloc(0);
-            device_cpqr_steps((double2 *)Rt.p, n, n, tol_rel, k, order, R);
+            device_cpqr_steps(E, Rt, n, n, tol_rel, k, order, R);
         } else {
-            device_cpqr_steps((double2 *)A0.p, m0, n, tol_rel, k, order, R);
+            device_cpqr_steps(E, A0, m0, n, tol_rel, k, order, R);
         }
     }
     // map back to the columns of Ah; zero columns close the redundant set
@@ -769,28 +817,21 @@ bool big_node_device(NodeEngine &E, const Mat &Arr, const Mat &Asr, const Mat &A
     const int nr = Arr.m, ns = Ass.m;
     if (nr < 1 || ns < 1 || Arr.n != nr || Asr.m != ns || Asr.n != nr || Ass.n != ns || T.m != ns || T.n != nr)
         return false;
-    std::lock_guard<std::mutex> lk(E.mu);  // one node at a time on the device
-    CHK(hipSetDevice(E.device));
-    if (!E.h) RB(rocblas_create_handle(&E.h));
-    RB(rocblas_set_stream(E.h, 0));
-    RB(rocblas_set_pointer_mode(E.h, rocblas_pointer_mode_host));
-    DevMem dA, dS, dQ, dT, dU, dM, dD, dinfo;
+    std::lock_guard<std::mutex> lk(E.mu);  // one host thread per lane
+    E.begin();
     const size_t bR = (size_t)nr * nr * 16, bSR = (size_t)ns * nr * 16, bS = (size_t)ns * ns * 16;
-    dA.alloc(bR);   // Arr -> Atr -> L -> L^{-1}
-    dS.alloc(bSR);  // Asr -> Ats = Asr - Ass T
-    dQ.alloc(bS);   // Ass
-    dT.alloc(bSR);  // T
-    dU.alloc(bSR);  // Ass T
-    dM.alloc(bSR);
-    dD.alloc(bS);
-    dinfo.alloc(sizeof(rocblas_int));
-    CHK(hipMemcpy(dA.p, Arr.a.data(), bR, hipMemcpyHostToDevice));
-    CHK(hipMemcpy(dS.p, Asr.a.data(), bSR, hipMemcpyHostToDevice));
-    CHK(hipMemcpy(dQ.p, Ass.a.data(), bS, hipMemcpyHostToDevice));
-    CHK(hipMemcpy(dT.p, T.a.data(), bSR, hipMemcpyHostToDevice));
-    auto A = (rocblas_double_complex *)dA.p, S = (rocblas_double_complex *)dS.p, Q = (rocblas_double_complex *)dQ.p,
-         Tm = (rocblas_double_complex *)dT.p, U = (rocblas_double_complex *)dU.p, Mm = (rocblas_double_complex *)dM.p,
-         D = (rocblas_double_complex *)dD.p;
+    auto A = (rocblas_double_complex *)E.get(0, bR);   // Arr -> Atr -> L -> L^{-1}
+    auto S = (rocblas_double_complex *)E.get(1, bSR);  // Asr -> Ats = Asr - Ass T
+    auto Q = (rocblas_double_complex *)E.get(2, bS);   // Ass
+    auto Tm = (rocblas_double_complex *)E.get(3, bSR); // T
+    auto U = (rocblas_double_complex *)E.get(4, bSR);  // Ass T
+    auto Mm = (rocblas_double_complex *)E.get(5, bSR);
+    auto D = (rocblas_double_complex *)E.get(6, bS);
+    auto dinfo = (rocblas_int *)E.get(7, sizeof(rocblas_int));
+    E.copy(A, Arr.a.data(), bR, hipMemcpyHostToDevice);
+    E.copy(S, Asr.a.data(), bSR, hipMemcpyHostToDevice);
+    E.copy(Q, Ass.a.data(), bS, hipMemcpyHostToDevice);
+    E.copy(Tm, T.a.data(), bSR, hipMemcpyHostToDevice);
     const rocblas_double_complex one(1.0, 0.0), mone(-1.0, 0.0), zero(0.0, 0.0);
     const auto N = rocblas_operation_none, C = rocblas_operation_conjugate_transpose;
     // U = Ass T; Atr = Arr - T^* Asr - Asr^* T + T^* U
@@ -798,27 +839,27 @@ bool big_node_device(NodeEngine &E, const Mat &Arr, const Mat &Asr, const Mat &A
     RB(rocblas_zgemm(E.h, C, N, nr, nr, ns, &mone, Tm, ns, S, ns, &one, A, nr));
     RB(rocblas_zgemm(E.h, C, N, nr, nr, ns, &mone, S, ns, Tm, ns, &one, A, nr));
     RB(rocblas_zgemm(E.h, C, N, nr, nr, ns, &one, Tm, ns, U, ns, &one, A, nr));
-    hipLaunchKernelGGL(k_herm_lower, dim3(grid256((int64_t)nr * nr)), dim3(256), 0, 0, (double2 *)A, nr);
+    hipLaunchKernelGGL(k_herm_lower, dim3(grid256((int64_t)nr * nr)), dim3(256), 0, E.st, (double2 *)A, nr);
     CHK(hipGetLastError());
     // Ats = Asr - Ass T (in place of Asr, whose uses are done)
     RB(rocblas_zgemm(E.h, N, N, ns, nr, ns, &mone, Q, ns, Tm, ns, &one, S, ns));
     // L L^* = Atr, then L^{-1}
     rocblas_int info = 0;
-    RB(rocsolver_zpotrf(E.h, rocblas_fill_lower, nr, A, nr, (rocblas_int *)dinfo.p));
-    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    RB(rocsolver_zpotrf(E.h, rocblas_fill_lower, nr, A, nr, dinfo));
+    E.copy(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost);
     if (info != 0) return false;  // not numerically HPD: the host path decides
-    RB(rocsolver_ztrtri(E.h, rocblas_fill_lower, rocblas_diagonal_non_unit, nr, A, nr, (rocblas_int *)dinfo.p));
-    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    RB(rocsolver_ztrtri(E.h, rocblas_fill_lower, rocblas_diagonal_non_unit, nr, A, nr, dinfo));
+    E.copy(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost);
     if (info != 0) return false;
-    hipLaunchKernelGGL(k_zero_upper, dim3(grid256((int64_t)nr * nr)), dim3(256), 0, 0, (double2 *)A, nr);
+    hipLaunchKernelGGL(k_zero_upper, dim3(grid256((int64_t)nr * nr)), dim3(256), 0, E.st, (double2 *)A, nr);
     CHK(hipGetLastError());
     // M = Ats L^{-*}; delta = -M M^*
     RB(rocblas_zgemm(E.h, N, C, ns, nr, nr, &one, S, ns, A, nr, &zero, Mm, ns));
     RB(rocblas_zgemm(E.h, N, C, ns, ns, nr, &mone, Mm, ns, Mm, ns, &zero, D, ns));
     Mat L(nr, nr), Mo(ns, nr), Do(ns, ns);
-    CHK(hipMemcpy(L.a.data(), dA.p, bR, hipMemcpyDeviceToHost));
-    CHK(hipMemcpy(Mo.a.data(), dM.p, bSR, hipMemcpyDeviceToHost));
-    CHK(hipMemcpy(Do.a.data(), dD.p, bS, hipMemcpyDeviceToHost));
+    E.copy(L.a.data(), A, bR, hipMemcpyDeviceToHost);
+    E.copy(Mo.a.data(), Mm, bSR, hipMemcpyDeviceToHost);
+    E.copy(Do.a.data(), D, bS, hipMemcpyDeviceToHost);
     Linv = std::move(L);
     M = std::move(Mo);
     delta = std::move(Do);
@@ -828,33 +869,28 @@ bool big_node_device(NodeEngine &E, const Mat &Arr, const Mat &Asr, const Mat &A
 bool hpd_inverse_device(NodeEngine &E, const Mat &Ah, Mat &inv) {
     const int n = Ah.n;
     if (n < 1 || Ah.m != n) return false;
-    std::lock_guard<std::mutex> lk(E.mu);
-    CHK(hipSetDevice(E.device));
-    if (!E.h) RB(rocblas_create_handle(&E.h));
-    RB(rocblas_set_stream(E.h, 0));
-    RB(rocblas_set_pointer_mode(E.h, rocblas_pointer_mode_host));
+    std::lock_guard<std::mutex> lk(E.mu);  // one host thread per lane
+    E.begin();
     const size_t b = (size_t)n * n * 16;
-    DevMem dA, dX, dinfo;
-    dA.alloc(b);
-    dX.alloc(b);
-    dinfo.alloc(sizeof(rocblas_int));
-    CHK(hipMemcpy(dA.p, Ah.a.data(), b, hipMemcpyHostToDevice));
-    auto A = (rocblas_double_complex *)dA.p, X = (rocblas_double_complex *)dX.p;
+    auto A = (rocblas_double_complex *)E.get(0, b);
+    auto X = (rocblas_double_complex *)E.get(1, b);
+    auto dinfo = (rocblas_int *)E.get(2, sizeof(rocblas_int));
+    E.copy(A, Ah.a.data(), b, hipMemcpyHostToDevice);
     rocblas_int info = 0;
-    RB(rocsolver_zpotrf(E.h, rocblas_fill_lower, n, A, n, (rocblas_int *)dinfo.p));
-    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    RB(rocsolver_zpotrf(E.h, rocblas_fill_lower, n, A, n, dinfo));
+    E.copy(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost);
     if (info != 0) return false;
-    RB(rocsolver_ztrtri(E.h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, A, n, (rocblas_int *)dinfo.p));
-    CHK(hipMemcpy(&info, dinfo.p, sizeof(info), hipMemcpyDeviceToHost));
+    RB(rocsolver_ztrtri(E.h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, A, n, dinfo));
+    E.copy(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost);
     if (info != 0) return false;
-    hipLaunchKernelGGL(k_zero_upper, dim3(grid256((int64_t)n * n)), dim3(256), 0, 0, (double2 *)A, n);
+    hipLaunchKernelGGL(k_zero_upper, dim3(grid256((int64_t)n * n)), dim3(256), 0, E.st, (double2 *)A, n);
     CHK(hipGetLastError());
     const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
     // A^{-1} = L^{-*} L^{-1}
     RB(rocblas_zgemm(E.h, rocblas_operation_conjugate_transpose, rocblas_operation_none, n, n, n, &one, A, n, A, n,
                      &zero, X, n));
     Mat out(n, n);
-    CHK(hipMemcpy(out.a.data(), dX.p, b, hipMemcpyDeviceToHost));
+    E.copy(out.a.data(), X, b, hipMemcpyDeviceToHost);
     inv = std::move(out);
     return true;
 }
@@ -870,15 +906,14 @@ BatchedIdFactory device_id_factory(int device) {
 
 SkelHooks device_skel_hooks(int device) {
     SkelHooks h;
-    // one engine (one library handle, one lock) for all three: no two host threads
-    // drive the device at once
-    auto e = std::make_shared<NodeEngine>();
-    e->device = device;
-    h.big_id = [e](const Mat &A, double tol_rel, ColumnID &out) { return big_column_id(*e, A, tol_rel, out); };
-    h.big_node = [e](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M, Mat &delta) {
-        return big_node_device(*e, Arr, Asr, Ass, T, Linv, M, delta);
+    // four lanes (streams) shared by the node loop's host threads
+    auto pool = std::make_shared<EnginePool>(device, 4);
+    h.big_id = [pool](const Mat &A, double tol_rel, ColumnID &out) {
+        return big_column_id(pool->pick(), A, tol_rel, out);
     };
-    h.hpd_inverse = [e](const Mat &A, Mat &inv) { return hpd_inverse_device(*e, A, inv); };
+    h.big_node = [pool](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M,
+                        Mat &delta) { return big_node_device(pool->pick(), Arr, Asr, Ass, T, Linv, M, delta); };
+    h.hpd_inverse = [pool](const Mat &A, Mat &inv) { return hpd_inverse_device(pool->pick(), A, inv); };
     return h;
 }
 
