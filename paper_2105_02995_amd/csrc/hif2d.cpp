@@ -205,7 +205,7 @@ Hmat2D peel_2d(const BlockApply &A, const Geo &g, const PeelOptions &po, double 
             std::map<std::pair<int64_t, int64_t>, Mat> Ysamp;
             std::vector<Mat> Rcell(ncell);
             const uint64_t sd = po.seed ^ splitmix64(0x2D00 + 64 * l + attempt);
-            for (int64_t I = 0; I < ncell; ++I) {
+            parallel_for(ncell, po.nthreads, [&](int64_t I) {
                 Mat R((int)csz, s);
                 for (int64_t i = 0; i < csz; ++i)
                     for (int q = 0; q < s; ++q) {
@@ -213,7 +213,7 @@ Hmat2D peel_2d(const BlockApply &A, const Geo &g, const PeelOptions &po, double 
                         R((int)i, q) = cd(gauss(sd, ctr), gauss(sd, ctr + 1));
                     }
                 Rcell[I] = std::move(R);
-            }
+            });
             // classes batched into applies of at most ~512 columns
             std::vector<std::pair<int, int>> classes;
             for (int p = 0; p < stride; ++p)
@@ -224,21 +224,33 @@ Hmat2D peel_2d(const BlockApply &A, const Geo &g, const PeelOptions &po, double 
                 const int S = nclass * s;
                 std::vector<cd> R((size_t)N * S, cd(0)), Y((size_t)N * S);
                 std::vector<std::vector<int64_t>> members(nclass);
+                std::vector<std::pair<int, int64_t>> tI;  // (class, cell) pairs of this apply
                 for (int t = 0; t < nclass; ++t) {
                     auto [p, q] = classes[c0 + t];
                     for (int ci = p; ci < side; ci += stride)
                         for (int cj = q; cj < side; cj += stride) {
-                            const int64_t I = g.cell_id(l, ci, cj);
-                            members[t].push_back(I);
-                            for (int64_t i = 0; i < csz; ++i)
-                                for (int u = 0; u < s; ++u) R[(I * csz + i) * S + t * s + u] = Rcell[I]((int)i, u);
+                            members[t].push_back(g.cell_id(l, ci, cj));
+                            tI.push_back({t, members[t].back()});
                         }
                 }
+                // the cells of one apply are distinct: disjoint rows of R
+                parallel_for((int64_t)tI.size(), po.nthreads, [&](int64_t x) {
+                    const int t = tI[x].first;
+                    const int64_t I = tI[x].second;
+                    for (int64_t i = 0; i < csz; ++i)
+                        for (int u = 0; u < s; ++u) R[(I * csz + i) * S + t * s + u] = Rcell[I]((int)i, u);
+                });
                 A(R.data(), Y.data(), S);
                 subtract_lr(H, l, R, Y, S, po.nthreads);
+                std::vector<std::pair<std::pair<int64_t, int64_t>, std::pair<int, int64_t>>> want;  // (I,J) <- (t, J)
                 for (int t = 0; t < nclass; ++t)
                     for (int64_t I : members[t])
-                        for (int64_t J : g.IL(l, I)) Ysamp[{I, J}] = take(Y, S, J * csz, csz, t * s, s);
+                        for (int64_t J : g.IL(l, I)) want.push_back({{I, J}, {t, J}});
+                std::vector<Mat> got(want.size());
+                parallel_for((int64_t)want.size(), po.nthreads, [&](int64_t x) {
+                    got[x] = take(Y, S, want[x].second.second * csz, csz, want[x].second.first * s, s);
+                });
+                for (size_t x = 0; x < want.size(); ++x) Ysamp[want[x].first] = std::move(got[x]);
             }
             const double tol = po.eps * normS * std::sqrt(2.0 * s);
             std::atomic<bool> saturated(false);
@@ -297,9 +309,15 @@ Hmat2D peel_2d(const BlockApply &A, const Geo &g, const PeelOptions &po, double 
             }
             A(R.data(), Y.data(), S);
             subtract_lr(H, L + 1, R, Y, S, po.nthreads);
+            std::vector<std::pair<std::pair<int64_t, int64_t>, int>> want;  // (J, I) <- class t
             for (int t = 0; t < nclass; ++t)
                 for (int64_t I : members[t])
-                    for (int64_t J : g.NL(L, I)) H.near[{J, I}] = take(Y, S, J * csz, csz, t * m, m);
+                    for (int64_t J : g.NL(L, I)) want.push_back({{J, I}, t});
+            std::vector<Mat> got(want.size());
+            parallel_for((int64_t)want.size(), po.nthreads, [&](int64_t x) {
+                got[x] = take(Y, S, want[x].first.first * csz, csz, want[x].second * m, m);
+            });
+            for (size_t x = 0; x < want.size(); ++x) H.near[want[x].first] = std::move(got[x]);
         }
         // Hermitian symmetrisation of the near field
         for (auto &kv : H.near) {
