@@ -278,7 +278,8 @@ fio_status fio_stage_pair_apply_variant(fio_plan plan, fio_op op, int stage, fio
  * where skel are the first rank pivots of a column-pivoted Householder QR that stops
  * before the first pivot whose trailing column norm is at most tol_rel times the
  * largest column norm of A (pivot: largest trailing norm, first among equals; a tall
- * A is first reduced to its triangular factor, which leaves every pivot unchanged;
+ * A is first reduced to its triangular factor, which leaves every pivot unchanged up
+ * to rounding;
  * exactly zero columns are redundant with zero coefficients).  A: host, complex128,
  * column-major m x n, leading dimension lda >= m, not modified.  Outputs, host: *rank;
  * perm[n] with skel = perm[0..rank) and redund = perm[rank..n); T complex128,
