@@ -906,8 +906,8 @@ BatchedIdFactory device_id_factory(int device) {
 
 SkelHooks device_skel_hooks(int device) {
     SkelHooks h;
-    // four lanes (streams) shared by the node loop's host threads
-    auto pool = std::make_shared<EnginePool>(device, 4);
+    // eight lanes (streams) shared by the node loop's host threads
+    auto pool = std::make_shared<EnginePool>(device, 8);
     h.big_id = [pool](const Mat &A, double tol_rel, ColumnID &out) {
         return big_column_id(pool->pick(), A, tol_rel, out);
     };

@@ -425,10 +425,10 @@ struct NodeOut {
 // Skeletonize the DOFs I given the stacked row block Ubar and the current
 // diagonal block A_II; same algebra as the 1D case (eq_sk, eq_sk_3).
 // Large IDs (coarse cells and edges) go to the device when the plan has one.
-constexpr int64_t BIG_ID_ENTRIES = 1 << 19;
+constexpr int64_t BIG_ID_ENTRIES = 1 << 18;
 // ... and so does the dense algebra of nodes with at least this many multiply-adds
 // (nr^2 (nr + ns), the Schur update and Cholesky scale).
-constexpr double BIG_NODE_WORK = 1 << 26;
+constexpr double BIG_NODE_WORK = 1 << 25;
 
 NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, double eps, double shift0,
                std::atomic<int> &nshift, const PeelOptions &po, std::atomic<int> &ndev,
