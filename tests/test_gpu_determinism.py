@@ -69,3 +69,23 @@ def test_tracing_does_not_change_results():
         F.fio_set_trace(False)
     x3, _ = G.solve(p, F.FIO_SOLVE_PCG, F.FIO_C64, u, tol=1e-8, maxit=50)
     assert np.array_equal(x0, x1) and np.array_equal(x2, x3)
+
+
+@pytest.mark.parametrize("d,n,phase,eps", [(1, 4096, "1d_ex1", 1e-6), (2, 32, "2d_radon", 1e-4)])
+def test_loaded_plan_equals_built_plan(tmp_path, d, n, phase, eps):
+    """A plan saved and loaded onto the device forms its complex64 copies and the
+    adjoint chain again on the device (from the stored forward chain): applies of
+    Kd, Kd^* and solves equal those of the plan that was built, bit for bit."""
+    built = plan() if d == 1 else F.fio_build(F.make_problem(d, n, phase, eps=eps, device=0))
+    path = str(tmp_path / "p.fio")
+    F.fio_save(built, path)
+    loaded = F.fio_load(path, device=0)
+    N = n ** d
+    x = gaussian_complex((N, 12), 79)
+    for op in (F.FIO_OP_K, F.FIO_OP_KH):
+        for dt in (F.FIO_C64, F.FIO_C128):
+            assert np.array_equal(G.apply(built, op, dt, x), G.apply(loaded, op, dt, x))
+    for mode, tol, maxit in MODES[:2]:
+        a, _ = G.solve(built, mode, F.FIO_C64, x, tol=tol, maxit=maxit)
+        b, _ = G.solve(loaded, mode, F.FIO_C64, x, tol=tol, maxit=maxit)
+        assert np.array_equal(a, b)
