@@ -286,7 +286,7 @@ fio_status fio_stage_pair_apply_variant(fio_plan plan, fio_op op, int stage, fio
  * rank x (n - rank), column-major with leading dimension rank, in a buffer of t_cap
  * elements.  Synchronous.  Errors: FIO_ERR_ARG (sizes, null pointers, device
  * ordinal, t_cap < rank*(n - rank), with *rank set), FIO_ERR_UNSUPPORTED (m above
- * 2^31 - 1), FIO_ERR_DEVICE, FIO_ERR_NOMEM. */
+ * 2^31 - 1, or not enough device memory for A), FIO_ERR_DEVICE. */
 fio_status fio_column_id(int device, int64_t m, int64_t n, const void *A, int64_t lda, double tol_rel, int *rank,
                          int *perm, void *T, int64_t t_cap);
 

@@ -871,7 +871,7 @@ fio_status fio_column_id(int device, int64_t m, int64_t n, const void *A, int64_
         const cd *a = (const cd *)A;
         for (int64_t j = 0; j < n; ++j) std::copy(a + j * lda, a + j * lda + m, Ah.col((int)j));
         ColumnID id;
-        if (!device_skel_hooks(device).big_id(Ah, tol_rel, id)) fail(FIO_ERR_UNSUPPORTED, "matrix declined");
+        if (!device_skel_hooks(device).big_id(Ah, tol_rel, id)) fail(FIO_ERR_UNSUPPORTED, "matrix declined (not enough device memory)");
         const int k = (int)id.skel.size();
         *rank = k;
         if ((int64_t)k * (n - k) > t_cap) fail(FIO_ERR_ARG, "T buffer too small for the rank");

@@ -904,16 +904,32 @@ BatchedIdFactory device_id_factory(int device) {
     };
 }
 
+// Runs a hook; when the device is out of memory the hook declines and the host path
+// takes the node (the runtime's last-error state is cleared first).
+template <class Fn> bool or_host(Fn &&fn) {
+    try {
+        return fn();
+    } catch (const Error &e) {
+        if (e.status != FIO_ERR_NOMEM) throw;
+        (void)hipGetLastError();
+        return false;
+    }
+}
+
 SkelHooks device_skel_hooks(int device) {
     SkelHooks h;
     // eight lanes (streams) shared by the node loop's host threads
     auto pool = std::make_shared<EnginePool>(device, 8);
     h.big_id = [pool](const Mat &A, double tol_rel, ColumnID &out) {
-        return big_column_id(pool->pick(), A, tol_rel, out);
+        return or_host([&] { return big_column_id(pool->pick(), A, tol_rel, out); });
     };
     h.big_node = [pool](const Mat &Arr, const Mat &Asr, const Mat &Ass, const Mat &T, Mat &Linv, Mat &M,
-                        Mat &delta) { return big_node_device(pool->pick(), Arr, Asr, Ass, T, Linv, M, delta); };
-    h.hpd_inverse = [pool](const Mat &A, Mat &inv) { return hpd_inverse_device(pool->pick(), A, inv); };
+                        Mat &delta) {
+        return or_host([&] { return big_node_device(pool->pick(), Arr, Asr, Ass, T, Linv, M, delta); });
+    };
+    h.hpd_inverse = [pool](const Mat &A, Mat &inv) {
+        return or_host([&] { return hpd_inverse_device(pool->pick(), A, inv); });
+    };
     return h;
 }
 

@@ -49,10 +49,10 @@ using BlockApply = std::function<void(const cd *x, cd *y, int nrhs)>;
 // Column ID of one large matrix (tall stacked bases of coarse 2D nodes) on a device;
 // returns false (having done nothing) if it declines the shape.  Same contract as
 // column_id(A, tol_rel, 0, -1).
+// The device implementation reduces a tall A to its triangular factor first (which
+// keeps every pivot), then runs the pivoted Householder steps, one launch for pivot
+// and reflector and one for the trailing columns per step.
 using BigIdFn = std::function<bool(const Mat &A, double tol_rel, ColumnID &out)>;
-// The device implementation (column-pivoted Householder QR, one launch for the pivot
-// and reflector and one for the trailing columns per step; serialised across host
-// threads).
 
 // Dense algebra of one large skeletonization node (eq_sk, eq_sk_3): from the blocks
 // Arr, Asr, Ass of A_II on the redundant (r) and skeleton (s) DOFs and the ID's T,
@@ -73,8 +73,9 @@ struct SkelHooks {
     BigNodeFn big_node;
     HpdInverseFn hpd_inverse;
 };
-// The device implementations (rocBLAS GEMMs, rocSOLVER Cholesky and triangular
-// inverse, FP64; serialised across host threads).
+// The device implementations (rocBLAS GEMMs, rocSOLVER QR, Cholesky and triangular
+// inverse, FP64; eight device lanes shared by the host threads; a hook that runs out of
+// device memory declines, and the host path takes the node).
 SkelHooks device_skel_hooks(int device);
 
 struct PeelOptions {
