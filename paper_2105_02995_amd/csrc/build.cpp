@@ -129,7 +129,7 @@ const char MAGIC[8] = {'F', 'I', 'O', 'P', 'L', 'A', 'N', '1'};
 struct W {
     std::ofstream f;
     template <class T> void v(const T &x) { f.write((const char *)&x, sizeof(T)); }
-    template <class T> void arr(const std::vector<T> &a) {
+    template <class T, class Al> void arr(const std::vector<T, Al> &a) {
         int64_t n = (int64_t)a.size();
         v(n);
         if (n) f.write((const char *)a.data(), sizeof(T) * n);
@@ -145,7 +145,7 @@ struct R {
         f.read((char *)&x, sizeof(T));
         if (!f) fail(FIO_ERR_IO, "truncated plan file");
     }
-    template <class T> void arr(std::vector<T> &a) {
+    template <class T, class Al> void arr(std::vector<T, Al> &a) {
         int64_t n = 0;
         v(n);
         if (n < 0 || n > (int64_t)1 << 40) fail(FIO_ERR_IO, "corrupt plan file");

@@ -218,10 +218,10 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
             st.r_out = (int)szX; st.r_in = r; st.fan = 1;
             st.in_idx.resize(npairs);
             st.A.resize((size_t)npairs * szX * r);
-            for (int64_t i = 0; i < npairs; ++i) {
+            parallel_for(npairs, nt, [&](int64_t i) {
                 st.in_idx[i] = (int32_t)i;
                 std::copy(Q[i].a.begin(), Q[i].a.end(), st.A.begin() + (size_t)i * szX * r);
-            }
+            });
             B.fwd[L + 2] = std::move(st);
         } else {
             // C_l: pair (ih, jh) at level l+1 <- pairs (ih/F, F jh + q) at level l.
@@ -229,7 +229,7 @@ Butterfly build_butterfly(const FioKernel &K, const ButterflyOptions &opt) {
             st.n_out = npairs; st.n_in = npairs;
             st.r_out = rnext; st.r_in = r; st.fan = F;
             st.in_idx.resize(npairs * F);
-            st.A.assign((size_t)npairs * rnext * F * r, cd(0));
+            st.A.resize((size_t)npairs * rnext * F * r);  // every entry written below
             parallel_for(npairs, nt, [&](int64_t o) {
                 int64_t ih = o / nOmN, jh = o % nOmN;
                 int64_t i = ih / F, c = ih % F;

@@ -243,7 +243,7 @@ void to_c64(const DBuf &b128, DBuf &b64) {
 }
 
 // FP64 array to the device, with its complex FP32 copy formed there.
-void upload_complex(DBuf &b64, DBuf &b128, const std::vector<cd> &a) {
+template <class Al> void upload_complex(DBuf &b64, DBuf &b128, const std::vector<cd, Al> &a) {
     b128.upload(a.data(), a.size() * sizeof(cd));
     to_c64(b128, b64);
 }

@@ -8,17 +8,36 @@
 // r_out x (fan*r_in) matrix, at offset o*r_out*fan*r_in of A.
 #pragma once
 
+#include <new>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
 
 namespace fio {
 
+// Allocator whose resize() leaves new elements unwritten: the stage arrays (up to
+// several GB) are then first written by the parallel loops that fill them, instead
+// of being zeroed on one thread beforehand.  Only for element types that every
+// filler overwrites completely (complex entries of the factor blocks).
+template <class T> struct FillLaterAlloc : std::allocator<T> {
+    template <class U> struct rebind {
+        using other = FillLaterAlloc<U>;
+    };
+    FillLaterAlloc() = default;
+    template <class U> FillLaterAlloc(const FillLaterAlloc<U> &) noexcept {}
+    template <class U> void construct(U *) noexcept {}
+    template <class U, class... Args> void construct(U *p, Args &&...args) {
+        ::new ((void *)p) U(std::forward<Args>(args)...);
+    }
+};
+using CVec = std::vector<cd, FillLaterAlloc<cd>>;
+
 struct Stage {
     int64_t n_out = 0, n_in = 0;
     int r_out = 0, r_in = 0, fan = 0;
     std::vector<int32_t> in_idx;  // n_out * fan
-    std::vector<cd> A;            // n_out * r_out * fan * r_in
+    CVec A;                       // n_out * r_out * fan * r_in (resize leaves it unwritten)
     size_t block_elems() const { return (size_t)r_out * fan * r_in; }
     int64_t nnz() const { return (int64_t)n_out * r_out * fan * r_in; }
 };
