@@ -265,3 +265,24 @@ def test_prescaled_skeletonization_is_one_dimensional_only():
     with pytest.raises(F.FioError) as e:
         F.fio_build(F.make_problem(2, 16, "2d_radon", eps=1e-4, device=-1, prescale_skel=1))
     assert e.value.status == 1
+
+
+def test_column_id_checks_its_arguments():
+    """fio_column_id refuses bad shapes, tolerances and null pointers with a status,
+    and reports a device error (not a crash) where there is no GPU."""
+    import ctypes
+    import numpy as np
+    lib = F.load_library()
+    A = np.zeros((8, 4), dtype=np.complex128, order="F")
+    rank = ctypes.c_int()
+    perm = np.zeros(4, dtype=np.int32)
+    T = np.zeros(16, dtype=np.complex128)
+    args = lambda m, n, lda, tol, a=A.ctypes.data: (0, m, n, a, lda, tol, ctypes.byref(rank), perm.ctypes.data,
+                                                     T.ctypes.data, 16)
+    assert lib.fio_column_id(*args(8, 4, 4, 1e-6)) == 1        # lda < m
+    assert lib.fio_column_id(*args(0, 4, 8, 1e-6)) == 1        # empty
+    assert lib.fio_column_id(*args(8, 4, 8, -1.0)) == 1        # negative tolerance
+    assert lib.fio_column_id(*args(8, 4, 8, 1e-6, None)) == 1  # null matrix
+    with pytest.raises(F.FioError) as e:
+        F.fio_column_id(A, 1e-6, device=0)
+    assert e.value.status in (1, 3)  # no device here: ordinal out of range or HIP error
