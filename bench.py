@@ -54,19 +54,46 @@ TRAFFIC = {
 }
 
 
-def traffic_for(name, bf_nnz):
-    """HBM bytes per launch from the committed counter runs, or None if the kernel
-    source or the factors (their nonzero count) differ from the ones profiled."""
+# Matrix-core counters per launch (rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 and
+# SQ_VALU_MFMA_BUSY_CYCLES; summary under profiles/), under the same validity rule.
+MFMA_COUNTERS = {
+    "k_stage2_mfma<double, 2, 2>": {
+        "executed_flop": 2.5585254e7 * 512,
+        "busy": 0.774,
+        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
+        "bf_nnz": 109109248,
+    },
+}
+
+
+def counted(table, name, bf_nnz):
+    """The entry of a counter table for this kernel, or None if the kernel source or
+    the factors (their nonzero count) differ from the ones profiled."""
     import hashlib
-    key = name.split(" (")[0]
-    t = TRAFFIC.get(key)
+    t = table.get(name.split(" (")[0])
     if not t or t.get("bf_nnz") != bf_nnz:
         return None
     src = os.path.join(ROOT, "paper_2105_02995_amd", "csrc", "kernels.hip")
     with open(src, "rb") as fh:
         if hashlib.sha256(fh.read()).hexdigest() != t["kernels_sha256"]:
             return None
-    return t["bytes"]
+    return t
+
+
+def mfma_counters_for(name, bf_nnz, avg_launch_ms, peak):
+    t = counted(MFMA_COUNTERS, name, bf_nnz)
+    if t is None:
+        return None
+    ex = t["executed_flop"] / (avg_launch_ms * 1e-3) / 1e12
+    return {"executed_flop_per_launch": t["executed_flop"], "executed_tflops": round(ex, 3),
+            "executed_frac": round(ex / peak, 4), "mfma_busy": t["busy"]}
+
+
+def traffic_for(name, bf_nnz):
+    """HBM bytes per launch from the committed counter runs, or None if the kernel
+    source or the factors (their nonzero count) differ from the ones profiled."""
+    t = counted(TRAFFIC, name, bf_nnz)
+    return None if t is None else t["bytes"]
 
 
 def log(msg):
@@ -363,6 +390,7 @@ def main():
             "unit": "GB/s" if hbm_bound else "TFLOP/s",
             "frac": round((gbs / PEAK_HBM_GBS) if hbm_bound else (tf / pk), 4),
             "traffic": traffic_for(best, stats["bf_nnz"]), "kernel": best,
+            "mfma_counters": mfma_counters_for(best, stats["bf_nnz"], float(tms.mean()), pk),
             "launches_per_chain": len(e["l"]),
             "avg_launch_ms": round(float(tms.mean()), 5),
             "flops_per_launch": float(fl.mean()), "bytes_per_launch": float(by.mean()),
