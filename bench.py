@@ -5,6 +5,12 @@ layout in, Kd^* (butterfly adjoint, complex64), Gd (skeletonization sweeps and
 the FP64 top-level block), one FP64 refinement step r = u - Kd x (complex128
 factors) followed by the complex64 correction Gd Kd^* r, and layout out.
 
+The default workload is the largest one-GPU configuration: the 2D generalized
+Radon FIO (section 6, Example 3) at n = 256 (N = 65536) with 256 right-hand
+sides, eps = 1e-4.  Every run also solves, untimed, a batch whose known-truth
+columns come from the oracle's direct summation (u = K fhat), and prints no
+value if their error exceeds 10 eps.
+
 Prints one JSON line (see the keys below).  Inputs are synthetic (seeded
 Gaussian right-hand sides) and resident in HBM before timing starts.
 """
@@ -105,7 +111,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="1d_n65536", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="2d_n256", choices=sorted(WORKLOADS))
     ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
@@ -120,7 +126,7 @@ def parse():
 
 
 SERVE_KEYS_FULL = ([(1, n, "1d_ex1", e) for n in (1024, 2048, 4096, 8192, 16384, 32768, 65536)
-                    for e in (1e-4, 1e-6)] + [(2, n, "2d_radon", 1e-4) for n in (32, 64, 128)])
+                    for e in (1e-4, 1e-6)] + [(2, n, "2d_radon", 1e-4) for n in (32, 64, 128, 256)])
 SERVE_KEYS_SMALL = [(1, 4096, "1d_ex1", 1e-6), (1, 65536, "1d_ex1", 1e-6), (2, 64, "2d_radon", 1e-4)]
 
 
@@ -183,7 +189,7 @@ def serve_main(args):
            "value": head["rhs_n_per_s"], "unit": "RHS*N/s", "n_gpus": 1,
            "higher_is_better": True, "data": "synthetic",
            "config": {"workload": "Poisson arrivals over %d resident keys (1D N=1024..65536 at eps 1e-4/1e-6, "
-                                  "2D n=32,64,128 at eps 1e-4), 1-32 RHS per request, complex64 + 1 FP64 "
+                                  "2D n=32,64,128,256 at eps 1e-4), 1-32 RHS per request, complex64 + 1 FP64 "
                                   "refinement step, HIP-graph replay" % len(SERVE_KEYS_FULL)},
            "serving": res}
     print(json.dumps(out), flush=True)
@@ -199,20 +205,22 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
     (single stages and fused stage pairs), timed with HIP events on the launch
     stream.  Returns one dict per launch: kernel instance name, average ms,
     algorithmic flops (8 per complex multiply-add of the block products) and
-    algorithmic HBM bytes (factor blocks and input indices read once, the
-    launch's input coefficients read once, its output written once)."""
+    algorithmic HBM bytes: the factor entries of the launch's stages read once,
+    plus the chain's input vector (first launch) and output vector (last launch);
+    the coefficient vectors passed between launches are an implementation cost,
+    not algorithmic work."""
     st = F.fio_plan_stats(plan)
     S = st["n_stages"]
     N = st["n"] ** st["d"]
     fwd_info = [F.fio_stage_info(plan, s) for s in range(S)]
-    # stage k of the chain of op: its factor, input and output entry counts
+
     def io(k):
+        """stage k of the chain of op: its factor info, input and output entry counts"""
         f = k if op == F.FIO_OP_K else S - 1 - k
         i = fwd_info[f]
         rows_o = i["n_out"] * i["r_out"]
         rows_i = N if f == 0 else fwd_info[f - 1]["n_out"] * fwd_info[f - 1]["r_out"]
-        nb_idx = i["n_out"] * i["fan"]
-        return (i, rows_i, rows_o, nb_idx) if op == F.FIO_OP_K else (i, rows_o, rows_i, nb_idx)
+        return (i, rows_i, rows_o) if op == F.FIO_OP_K else (i, rows_o, rows_i)
     csize = 8 if dtype == F.FIO_C64 else 16
     r = "float" if dtype == F.FIO_C64 else "double"
     sched = F.fio_chain_schedule(plan, op, dtype, nrhs)
@@ -240,8 +248,13 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
     for j, (first, count, v) in enumerate(sched):
         ks = list(range(first, first + count))
         flops = sum(8.0 * io(k)[0]["nnz"] * nrhs for k in ks)
-        byts = sum(io(k)[0]["nnz"] * csize + 4 * io(k)[3] for k in ks)
-        byts += (io(ks[0])[1] + io(ks[-1])[2]) * nrhs * csize
+        byts = sum(io(k)[0]["nnz"] * csize for k in ks)
+        if j == 0:
+            byts += N * nrhs * csize
+        if j == len(sched) - 1:
+            byts += N * nrhs * csize
+        moved = sum(io(k)[0]["nnz"] * csize + 4 * io(k)[0]["n_out"] * io(k)[0]["fan"] for k in ks)
+        moved += (io(ks[0])[1] + io(ks[-1])[2]) * nrhs * csize
         if count == 2 and v == PAIR_STACKED:
             rmax = max(io(k)[0]["r_out"] if op == F.FIO_OP_K else io(k)[0]["r_in"] for k in ks)
             name = "k_stage2s_mfma<%s, %d, %d>" % (r, 2 if dtype == F.FIO_C64 else 1, 3 if rmax <= 24 else 4)
@@ -253,38 +266,167 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
         else:
             name = "k_stage_mfma<%s, %d, %d>" % ((r,) + VNAME[v])
         out.append({"name": name, "ms": float(tot[j]), "flops": flops, "bytes": float(byts),
-                    "stages": ks})
+                    "launch_io_bytes": float(moved), "stages": ks})
     return out
 
 
-def cpu_baseline(wl, x_gpu, u):
-    """The FP64 oracle on a bounded sample of the same workload (CPU, all cores):
-    its solve is CG on K^*K x = K^*u with direct-summation products (section 6,
-    eq_NR_1).  Timed: one K^*K product on one right-hand side at full N; the
-    iteration count comes from the oracle's own CG at N = 4096 (same phase).
-    Also checks the GPU solution's residual on sampled rows."""
+def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
+    """The FP64 oracle on a bounded sample of the workload (CPU, all cores).
+
+    1. Known truth: fhat for `ncol` columns (seeded Gaussian) and u = K fhat by the
+       oracle's direct summation (section 1, eq6) at full N; this product is timed.
+    2. The GPU solves (untimed) a full batch whose columns spread over it carry
+       these u; the max relative error against fhat is rel_err_vs_oracle.
+    3. CPU baseline: the oracle's solve at this N is CG on K^*K with
+       direct-summation products (section 6, eq_NR_1), 2 products per iteration
+       plus K^* u.  Its rate is extrapolated from the timed product and the
+       oracle's own CG count at the small size of the same example (dense K).
+       A dense LU solve of the small size (K formation, LU, all right-hand
+       sides) is timed as a measured point.
+    """
     import oracle as O
-    p_small = O.OracleProblem(wl.d, 4096 if wl.d == 1 else 64, wl.phase, wl.c_div)
-    K = O.dense_K(p_small)
-    _, iters = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v,
-                           gaussian_complex(4096, 99), tol=1e-8)
-    del K
+    N, B = wl.N, wl.nrhs
     p = O.OracleProblem(wl.d, wl.n, wl.phase, wl.c_div)
-    v = gaussian_complex(wl.N, 98)
+    fh = gaussian_complex((N, ncol), wl.seed + 100)
+    log("oracle: direct summation u = K fhat, N=%d, %d columns ..." % (N, ncol))
     t0 = time.perf_counter()
-    w = O.apply_direct(p, v)
-    O.apply_direct(p, w, adjoint=True)
-    t_pair = time.perf_counter() - t0
-    per_rhs = (iters + 0.5) * t_pair          # iterations plus the initial K^* u
+    u_true = O.apply_direct(p, fh)
+    t_prod = time.perf_counter() - t0
+    log("oracle: %.1f s" % t_prod)
+    u = gaussian_complex((N, B), wl.seed + 101)
+    cols = np.unique(np.linspace(0, B - 1, ncol).round().astype(np.int64))
+    u[:, cols] = u_true
+    U = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()
+    X = torch.zeros_like(U)
+    F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0, maxit=refine, stream=stream,
+                want_info=False)
+    torch.cuda.synchronize()
+    x = X.cpu().numpy().T
+    finite = bool(np.isfinite(x).all())
+    err = O.rel_err(x[:, cols], fh) if finite else np.full(len(cols), np.inf)
+    # the oracle's CG count and a measured dense solve at the small size
+    small_n = 4096 if wl.d == 1 else 64
+    ps = O.OracleProblem(wl.d, small_n, wl.phase, wl.c_div)
+    Ns = ps.N
+    t0 = time.perf_counter()
+    K = O.dense_K(ps)
+    us = gaussian_complex((Ns, B), wl.seed + 102)
+    O.solve_dense(ps, us, K)
+    t_lu = time.perf_counter() - t0
+    _, iters = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, gaussian_complex(Ns, 99), tol=1e-8)
+    del K
+    per_solve = (2 * iters + 1) * t_prod          # ncol right-hand sides
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rows = uniform_indices(32, wl.N, 7)
-    cols = np.array([0, wl.nrhs - 1])
-    r = O.apply_direct(p, x_gpu[:, cols], out_idx=rows) - u[rows][:, cols]
-    resid = float((np.linalg.norm(r, axis=0) / np.linalg.norm(u[rows][:, cols], axis=0)).max())
-    return {"value": wl.N / per_rhs, "unit": "RHS*N/s", "cores": cores, "kind": "oracle",
-            "sample": "one K^*K product by direct summation on 1 RHS at N=%d (%.1f s), "
-                      "times %d CG iterations (oracle CG count at N=4096) + 0.5" % (wl.N, t_pair, iters),
-            "oracle_residual_sampled_rows": resid}
+    base = {"value": ncol * N / per_solve, "unit": "RHS*N/s", "cores": cores, "kind": "oracle, extrapolated",
+            "sample": "one direct-summation product K fhat on %d RHS at N=%d (%.1f s, timed), times %d products "
+                      "of the oracle's CG on K^*K (%d iterations: the oracle's CG count at %s, same phase, "
+                      "to 1e-8)" % (ncol, N, t_prod, 2 * iters + 1, iters,
+                                    "N=%d" % small_n if wl.d == 1 else "n=%d" % small_n),
+            "measured_small": {"value": B * Ns / t_lu, "unit": "RHS*N/s", "seconds": t_lu,
+                               "sample": "dense LU oracle solve at %s (N=%d): K formation, LU, %d RHS"
+                                         % ("N=%d" % small_n if wl.d == 1 else "2D n=%d" % small_n, Ns, B)}}
+    check = {"rel_err_vs_oracle": float(err.max()), "rel_err_median": float(np.median(err)),
+             "columns": [int(c) for c in cols], "bound": 10 * wl.eps, "finite": finite}
+    return base, check
+
+
+def measure_serving(F, wl, plan, args):
+    """Small serving leg: Poisson arrivals over a few resident keys including the
+    workload's own plan, at 0.8 of the measured saturation rate."""
+    key = (wl.d, wl.n, wl.phase, wl.eps)
+    keys = list(SERVE_KEYS_SMALL)
+    if key not in keys:
+        keys.append(key)
+    plans = build_plans(F, keys, {key: plan})
+    try:
+        return serving_run(F, plans, keys, 100, (0.8,), 2000)
+    finally:
+        for k, pl in plans.items():
+            if pl is not plan:
+                pl.close()
+
+
+def roofline_of(F, torch, plan, stats, B, refine):
+    """Dominant butterfly kernel instance of the step and its roofline figures.
+    The complex64 adjoint chain runs twice per step, the complex128 forward chain
+    once per refinement step.  The bound is the roof the instance reaches first:
+    HBM if its algorithmic bytes take longer at 8 TB/s than its flops at the
+    matrix-core peak of its precision."""
+    l64 = chain_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
+    l128 = chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
+    inst = {}
+    for launches, weight, pk in ((l64, 2, PEAK_TFLOPS["c64"]), (l128, refine, PEAK_TFLOPS["c128"])):
+        for ln in launches:
+            e = inst.setdefault(ln["name"], {"l": [], "w": weight, "pk": pk})
+            e["l"].append(ln)
+    best = max(inst, key=lambda n: inst[n]["w"] * sum(x["ms"] for x in inst[n]["l"]))
+    e = inst[best]
+    tms = np.array([x["ms"] for x in e["l"]])
+    fl = np.array([x["flops"] for x in e["l"]])
+    by = np.array([x["bytes"] for x in e["l"]])
+    pk = e["pk"]
+    tf = fl.sum() / (tms.sum() * 1e-3) / 1e12
+    gbs = by.sum() / (tms.sum() * 1e-3) / 1e9
+    hbm_bound = by.sum() / (PEAK_HBM_GBS * 1e9) >= fl.sum() / (pk * 1e12)
+    traffic = traffic_for(best, stats["bf_nnz"])
+    roof = {"bound": "hbm" if hbm_bound else "mfma",
+            "achieved": round(gbs if hbm_bound else tf, 3),
+            "peak": PEAK_HBM_GBS if hbm_bound else pk,
+            "unit": "GB/s" if hbm_bound else "TFLOP/s",
+            "frac": round((gbs / PEAK_HBM_GBS) if hbm_bound else (tf / pk), 4),
+            "traffic": traffic, "kernel": best,
+            "traffic_over_algorithmic": round(traffic / float(by.mean()), 3) if traffic else None,
+            "mfma_counters": mfma_counters_for(best, stats["bf_nnz"], float(tms.mean()), pk),
+            "launches_per_chain": len(e["l"]),
+            "avg_launch_ms": round(float(tms.mean()), 5),
+            "flops_per_launch": float(fl.mean()), "bytes_per_launch": float(by.mean()),
+            "intensity_flop_per_byte": round(float(fl.sum() / by.sum()), 2),
+            "other_roof": {"mfma_tflops": round(tf, 3), "mfma_frac": round(tf / pk, 4),
+                           "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)},
+            "chain_ms": {"c64_KH": round(sum(x["ms"] for x in l64), 4),
+                         "c128_K": round(sum(x["ms"] for x in l128), 4)},
+            "chain_tflops": {"c64_KH": round(sum(x["flops"] for x in l64) / (sum(x["ms"] for x in l64) * 1e9), 2),
+                             "c128_K": round(sum(x["flops"] for x in l128) / (sum(x["ms"] for x in l128) * 1e9), 2)},
+            "chain_bytes": {"c64_KH": {"algorithmic": sum(x["bytes"] for x in l64),
+                                       "launch_io": sum(x["launch_io_bytes"] for x in l64)},
+                            "c128_K": {"algorithmic": sum(x["bytes"] for x in l128),
+                                       "launch_io": sum(x["launch_io_bytes"] for x in l128)}},
+            "instances": {n: {"launches": len(v["l"]), "ms_per_chain": round(sum(x["ms"] for x in v["l"]), 4)}
+                          for n, v in inst.items()}}
+    log("roofline: %s avg %.4f ms/launch over %d launches: %.2f TFLOP/s (%.1f%% of %.1f), "
+        "%.0f GB/s (%.1f%% of HBM), bound %s" % (best, tms.mean(), len(e["l"]), tf, 100 * tf / pk, pk,
+                                                 gbs, 100 * gbs / PEAK_HBM_GBS, roof["bound"]))
+    log("chains: c64 KH %.4f ms (%.1f TFLOP/s), c128 K %.4f ms (%.1f TFLOP/s)" % (
+        roof["chain_ms"]["c64_KH"], roof["chain_tflops"]["c64_KH"], roof["chain_ms"]["c128_K"],
+        roof["chain_tflops"]["c128_K"]))
+    return roof
+
+
+def plain_fp64(F, torch, plan, U, N, stream, ncols=16):
+    """Plain FP64 path: complex128 factors, one right-hand side per call, direct
+    solve (Gd Kd^* u)."""
+    Uc = [U[j:j + 1].contiguous() for j in range(ncols)]
+    Xc = [torch.zeros_like(Uc[0]) for _ in range(ncols)]
+    for j in range(2):
+        F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream, want_info=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(ncols):
+        F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream, want_info=False)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    st = F.fio_plan_stats(plan)
+    # algorithmic bytes of one complex128 direct solve: the Kd^* factors, the Gd
+    # factors (T, L^-1, M), the root block, and u in / fhat out
+    byts = (st["bf_nnz"] + st["hif_nnz"] + st["root_size"] ** 2 + 2 * N) * 16
+    gbs = byts / (tp / ncols) / 1e9
+    out = {"value": ncols * N / tp, "ms_per_rhs": 1000 * tp / ncols, "dtype": "c128", "nrhs_per_call": 1,
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_rhs": byts,
+                        "what": "whole direct solve (every launch of Kd^*, Gd and layout)"}}
+    log("plain FP64 single-RHS: %.3f ms/RHS, %.3e RHS*N/s, %.0f GB/s of factor bytes" % (
+        1000 * tp / ncols, out["value"], gbs))
+    return out
 
 
 def main():
@@ -302,7 +444,7 @@ def main():
     N, B = wl.N, wl.nrhs
     log("workload %s: d=%d n=%d N=%d nrhs=%d eps=%g" % (wl.name, wl.d, wl.n, N, B, wl.eps))
     t0 = time.perf_counter()
-    # large 2D builds take minutes on the host: print their progress
+    # large 2D builds take a while: print their progress
     plan = F.fio_build(F.make_problem(wl.d, wl.n, wl.phase, eps=wl.eps, c_div=wl.c_div, device=0,
                                       verbose=1 if wl.N * wl.d >= 2 * 65536 else 0))
     build_s = time.perf_counter() - t0
@@ -348,7 +490,6 @@ def main():
     log("timed %d steps: %.3f ms/step, %.3e RHS*N/s" % (args.steps, ms, value))
     its, corr = F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0,
                             maxit=args.refine, stream=stream)
-    x = X.cpu().numpy().T
 
     # optional spatial output f = n^d F* fhat of the batch (not part of the step)
     Fs = torch.empty_like(X)
@@ -363,86 +504,21 @@ def main():
     del Fs
     log("spatial output (inverse DFT of the batch): %.4f ms" % spatial_ms)
 
-    # Dominant kernel: the butterfly kernel instance (template instantiation, chosen
-    # per launch by the autotuner) with the largest time per step.  The complex64
-    # adjoint chain runs twice per step, the complex128 forward chain once per
-    # refinement step.  Its bound is the roof it would reach first: HBM if its
-    # algorithmic bytes take longer at 8 TB/s than its flops at the MFMA peak.
-    l64 = chain_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
-    l128 = chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
-    inst = {}
-    for launches, weight, pk in ((l64, 2, PEAK_TFLOPS["c64"]), (l128, args.refine, PEAK_TFLOPS["c128"])):
-        for ln in launches:
-            e = inst.setdefault(ln["name"], {"l": [], "w": weight, "pk": pk})
-            e["l"].append(ln)
-    best = max(inst, key=lambda n: inst[n]["w"] * sum(x["ms"] for x in inst[n]["l"]))
-    e = inst[best]
-    tms = np.array([x["ms"] for x in e["l"]])
-    fl = np.array([x["flops"] for x in e["l"]])
-    by = np.array([x["bytes"] for x in e["l"]])
-    pk = e["pk"]
-    tf = fl.sum() / (tms.sum() * 1e-3) / 1e12
-    gbs = by.sum() / (tms.sum() * 1e-3) / 1e9
-    hbm_bound = by.sum() / (PEAK_HBM_GBS * 1e9) >= fl.sum() / (pk * 1e12)
-    roof = {"bound": "hbm" if hbm_bound else "mfma",
-            "achieved": round(gbs if hbm_bound else tf, 3),
-            "peak": PEAK_HBM_GBS if hbm_bound else pk,
-            "unit": "GB/s" if hbm_bound else "TFLOP/s",
-            "frac": round((gbs / PEAK_HBM_GBS) if hbm_bound else (tf / pk), 4),
-            "traffic": traffic_for(best, stats["bf_nnz"]), "kernel": best,
-            "mfma_counters": mfma_counters_for(best, stats["bf_nnz"], float(tms.mean()), pk),
-            "launches_per_chain": len(e["l"]),
-            "avg_launch_ms": round(float(tms.mean()), 5),
-            "flops_per_launch": float(fl.mean()), "bytes_per_launch": float(by.mean()),
-            "intensity_flop_per_byte": round(float(fl.sum() / by.sum()), 2),
-            "other_roof": {"mfma_tflops": round(tf, 3), "mfma_frac": round(tf / pk, 4),
-                           "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)},
-            "chain_ms": {"c64_KH": round(sum(x["ms"] for x in l64), 4),
-                         "c128_K": round(sum(x["ms"] for x in l128), 4)},
-            "instances": {n: {"launches": len(v["l"]), "ms_per_chain": round(sum(x["ms"] for x in v["l"]), 4)}
-                          for n, v in inst.items()}}
-    log("roofline: %s avg %.4f ms/launch over %d launches: %.2f TFLOP/s (%.1f%% of %.1f), "
-        "%.0f GB/s (%.1f%% of HBM), bound %s" % (best, tms.mean(), len(e["l"]), tf, 100 * tf / pk, pk,
-                                                 gbs, 100 * gbs / PEAK_HBM_GBS, roof["bound"]))
-    log("chains: c64 KH %.4f ms, c128 K %.4f ms" % (roof["chain_ms"]["c64_KH"], roof["chain_ms"]["c128_K"]))
+    roof = roofline_of(F, torch, plan, stats, B, args.refine)
+    plain = None if args.no_plain else plain_fp64(F, torch, plan, U, N, stream)
+    del X
+    serving = None if args.no_serve else measure_serving(F, wl, plan, args)
 
-    plain = None
-    if not args.no_plain:
-        # plain FP64 path: complex128 factors, one right-hand side per call, direct solve
-        ncols = 16
-        Uc = [U[j:j + 1].contiguous() for j in range(ncols)]
-        Xc = [torch.zeros_like(Uc[0]) for _ in range(ncols)]
-        for j in range(2):
-            F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream,
-                        want_info=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for j in range(ncols):
-            F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream,
-                        want_info=False)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t0
-        plain = {"value": ncols * N / tp, "ms_per_rhs": 1000 * tp / ncols, "dtype": "c128",
-                 "nrhs_per_call": 1}
-        log("plain FP64 single-RHS: %.3f ms/RHS, %.3e RHS*N/s" % (1000 * tp / ncols, plain["value"]))
-
-    serving = None
-    if not args.no_serve and wl.d == 1 and wl.n == 65536:
-        plans = build_plans(F, SERVE_KEYS_SMALL, {SERVE_KEYS_SMALL[1]: plan})
-        serving = serving_run(F, plans, SERVE_KEYS_SMALL, 100, (0.8,), 2000)
-        for k, pl in plans.items():
-            if pl is not plan:
-                pl.close()
-
-    cpu = None
+    cpu, check = None, None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(wl, x, u)
-        log("cpu baseline: %.3e RHS*N/s on %d cores" % (cpu["value"], cpu["cores"]))
+        cpu, check = oracle_leg(F, torch, plan, wl, stream, args.refine)
+        log("oracle check: max rel err %.3e over columns %s (bound %.1e); cpu baseline %.3e RHS*N/s on %d cores"
+            % (check["rel_err_vs_oracle"], check["columns"], check["bound"], cpu["value"], cpu["cores"]))
 
+    ok = check is None or (check["finite"] and check["rel_err_vs_oracle"] <= check["bound"])
     out = {
         "metric": "RHS*N/s of factored FIO inverse solve at rel err <= 10 eps; p50/p99 latency",
-        "value": value, "unit": "RHS*N/s", "n_gpus": 1, "steps": args.steps,
+        "value": value if ok else None, "unit": "RHS*N/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
         "config": {"workload": "%s: %s, N=%d, %d RHS, eps=%g, complex64 applies + %d FP64 "
@@ -451,8 +527,9 @@ def main():
                                   "2D FIO Example 3 (generalized Radon phase), n=%d" % wl.n,
                                   N, B, wl.eps, args.refine),
                    "N": N, "nrhs": B, "eps": wl.eps},
+        "rel_err_vs_oracle": check,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "per-step (64-RHS batch) latency, HIP events"},
+                       "what": "per-step (%d-RHS batch) latency, HIP events" % B},
         "serving": serving,
         "last_correction_rel": corr,
         "spatial_output_ms": spatial_ms,
@@ -466,6 +543,10 @@ def main():
     }
     print(json.dumps(out), flush=True)
     plan.close()
+    if not ok:
+        log("rel_err_vs_oracle %.3e exceeds 10 eps = %.1e: no value reported"
+            % (check["rel_err_vs_oracle"], check["bound"]))
+        sys.exit(1)
 
 
 if __name__ == "__main__":

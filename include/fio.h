@@ -26,6 +26,11 @@
  *    asynchronous on that stream; they may use library-owned device workspace
  *    that is sized for the largest nrhs seen (grown on demand), so calls on one
  *    plan must not run concurrently on different streams.
+ *  - Graph capture: a call made while hip_stream is being captured records the
+ *    plan's workspace addresses into the graph.  From then on the workspace of
+ *    that plan never moves: a later call (captured or not) that needs more
+ *    columns than the workspace holds fails with FIO_ERR_ARG.  Make the widest
+ *    call once, eagerly, before capturing.
  *  - Every call returns an fio_status; nothing throws across the ABI.  On error
  *    the outputs are unspecified, fio_last_error() gives a message (thread
  *    local), and the plan stays valid unless the status is FIO_ERR_DEVICE.
@@ -65,11 +70,29 @@ typedef enum {
     FIO_PHASE_2D_RADON = 2, /* Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2),          (Ex. 3)
                                c1 = (2 + sin 2pi x1 sin 2pi x2)/c_div,
                                c2 = (2 + cos 2pi x1 cos 2pi x2)/c_div                     */
-    FIO_PHASE_1D_EX2 = 3    /* Example 1's phase with the variable amplitude of Ex. 2:
+    FIO_PHASE_1D_EX2 = 3,   /* Example 1's phase with the variable amplitude of Ex. 2:
                                a(x, xi) = sum_k exp(-(d(x, x_k)^2 + (xi/n - eta_k)^2)/sigma2),
                                d the distance on the unit circle (periodic in x); the
                                centres come from amp_x/amp_eta (see fio_problem)          */
+    FIO_PHASE_CALLBACK = 4  /* any FIO of section 1 (eq3, eq6): the phase Phi(x, xi) and
+                               the amplitude a(x, xi) come from the caller's functions
+                               phi and amp of fio_problem                                 */
 } fio_phase_id;
+
+/* Phase of a caller-defined FIO (FIO_PHASE_CALLBACK): returns Phi(x, xi) in cycles,
+ * so that K_ij = a(x_i, xi_j) exp(2 pi i Phi(x_i, xi_j)) (section 1, eq6).  x holds the
+ * d coordinates of a point of X (each k/n in [0, 1)), xi the d frequencies of a point
+ * of Omega (integers -n/2 .. n/2 - 1, as doubles).  The whole phase is returned,
+ * including the linear part x.xi; the library reduces it mod 1 in FP64 (so the phase
+ * must be accurate to a small fraction of a cycle, far below eps, at |xi| up to n/2).
+ * Called on the host during fio_build only, concurrently from several threads, so it
+ * must be thread-safe; user is fio_problem.user. */
+typedef double (*fio_phase_fn)(const double *x, const double *xi, int d, void *user);
+
+/* Amplitude a(x, xi) of a caller-defined FIO: writes its real and imaginary parts to
+ * re_im[0], re_im[1].  Same arguments and rules as fio_phase_fn.  a must be smooth in
+ * both variables (the butterfly compresses K; section 1 assumes a symbol). */
+typedef void (*fio_amp_fn)(const double *x, const double *xi, int d, void *user, double re_im[2]);
 
 #define FIO_MAX_AMP_TERMS 8
 
@@ -119,6 +142,14 @@ typedef struct {
      * node with redundant DOFs only, then the skeletonization).  Not stored by
      * fio_save (the factors are).                                                  */
     int prescale_skel;
+    /* FIO_PHASE_CALLBACK only (ignored otherwise): the caller's phase (required) and
+     * amplitude (NULL means a = 1), both evaluated on the host during fio_build, and the
+     * pointer passed to them.  The butterfly then samples K on the host and hands the
+     * samples to the device decompositions.  Neither function is stored by fio_save:
+     * a saved plan holds the factors, which is all an apply needs.                  */
+    fio_phase_fn phi;
+    fio_amp_fn amp;
+    void *user;
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",
@@ -188,6 +219,14 @@ typedef struct {
 typedef struct {
     int iters;              /* iterations performed                                    */
     double rel_resid;       /* max over columns of the last relative residual/correction */
+    double est_rel_err;     /* estimate of max over columns of ||x - K^{-1}u|| / ||K^{-1}u||,
+                               the error against the exact solve (the method's error, not
+                               only the iteration's): from the plan's estimates e_a, e_s
+                               and cond(Kd) (fio_plan_stats_t) and this solve's rel_resid:
+                                 DIRECT  e_s + cond e_a (+ the FP32 rounding for FIO_C64)
+                                 REFINE  e_s rel_resid + cond e_a (+ FP64 rounding)
+                                 PCG     cond^2 rel_resid + cond e_a
+                                 GMRES   cond rel_resid + cond e_a                        */
 } fio_solve_info;
 
 /* Solve K fhat = u for nrhs columns.  u and out are complex128 device buffers
@@ -222,6 +261,15 @@ typedef struct {
     int hif_device_nodes;          /* large 2D skeletonization nodes whose Schur update,
                                       Cholesky factor, L^{-1} and M were formed on the
                                       device, plus 1 if A_0^{-1} was (not stored)      */
+    /* Error estimates, measured on the device when the plan is built (and stored in
+     * the plan file); 0 for a host-only plan.  The paper's e_a and e_s (section 6): */
+    double e_a_est;                /* butterfly error ||K - Kd|| / ||K||: relative error of
+                                      Kd v against K v (K summed directly from its entries)
+                                      on 64 sampled rows, max over 4 Gaussian vectors       */
+    double e_s_est;                /* inverse error: spectral radius of I - Gd Kd^* Kd by 12
+                                      power iterations (4 Gaussian start vectors, FP64)     */
+    double cond_est;               /* cond(Kd) = sqrt(lambda_max(Kd^* Kd) lambda_max(Gd)),
+                                      each by 12 power iterations (Gd ~ (Kd^* Kd)^{-1})     */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

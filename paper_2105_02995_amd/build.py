@@ -60,7 +60,7 @@ def build(verbose: bool = False) -> str:
     _run(["gcc", "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
           "-I" + os.path.join(ROCM, "include"), os.path.join(HERE, "examples", "solve_file.c"),
           "-L" + HERE, "-lfio", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
-          "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", ex + ".tmp"])
+          "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lm", "-o", ex + ".tmp"])
     os.replace(ex + ".tmp", ex)
     # measurement aid (copy kernel of known size, MFMA rates)
     cal = os.path.join(HERE, "fio_calibrate")

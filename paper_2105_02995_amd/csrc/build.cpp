@@ -1,4 +1,5 @@
 // Host construction of all factors (Algorithm "alg", section 5) and their file format.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -34,7 +35,13 @@ fio_problem normalized_problem(const fio_problem &in) {
     if (p.phase == FIO_PHASE_1D_EX1 && p.d != 1) fail(FIO_ERR_ARG, "phase 1D_EX1 needs d = 1");
     if (p.phase == FIO_PHASE_2D_RADON && p.d != 2) fail(FIO_ERR_ARG, "phase 2D_RADON needs d = 2");
     if (p.phase == FIO_PHASE_1D_EX2 && p.d != 1) fail(FIO_ERR_ARG, "phase 1D_EX2 needs d = 1");
-    if (p.phase < FIO_PHASE_LINEAR || p.phase > FIO_PHASE_1D_EX2) fail(FIO_ERR_ARG, "unknown phase");
+    if (p.phase < FIO_PHASE_LINEAR || p.phase > FIO_PHASE_CALLBACK) fail(FIO_ERR_ARG, "unknown phase");
+    if (p.phase == FIO_PHASE_CALLBACK && !p.phi) fail(FIO_ERR_ARG, "FIO_PHASE_CALLBACK needs a phase function phi");
+    if (p.phase != FIO_PHASE_CALLBACK) {  // the callbacks belong to FIO_PHASE_CALLBACK only
+        p.phi = nullptr;
+        p.amp = nullptr;
+        p.user = nullptr;
+    }
     if (p.amp_terms < 0 || p.amp_terms > FIO_MAX_AMP_TERMS) fail(FIO_ERR_ARG, "amp_terms out of range");
     if (p.amp_sigma2 == 0) p.amp_sigma2 = 0.1;
     if (!(p.amp_sigma2 > 0)) fail(FIO_ERR_ARG, "amp_sigma2 must be positive");
@@ -85,6 +92,31 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     out.d = p.d; out.n = p.n; out.N = B.N; out.L = B.L; out.Lm = B.Lm; out.m = B.m;
     out.perm = K.to_nat;
     out.prob = p;
+    // e_a probe: K v on sampled rows, from the entries of K (the phase is only at hand
+    // here for a caller-defined FIO)
+    {
+        const int64_t N = B.N;
+        const int nr = (int)std::min<int64_t>(EA_ROWS, N);
+        std::vector<int> rows;
+        for (uint64_t t = 0; (int)rows.size() < nr; ++t) {
+            const int r = (int)(splitmix64(p.seed ^ 0xEA0ULL ^ splitmix64(t)) % (uint64_t)N);
+            if (std::find(rows.begin(), rows.end(), r) == rows.end()) rows.push_back(r);
+        }
+        std::sort(rows.begin(), rows.end());
+        out.ea_rows = rows;
+        out.ea_vecs.resize((size_t)N * EA_VECS);
+        for (int64_t i = 0; i < N * EA_VECS; ++i)
+            out.ea_vecs[i] = cd(gauss(p.seed ^ 0xEA1ULL, 2 * (uint64_t)i), gauss(p.seed ^ 0xEA1ULL, 2 * (uint64_t)i + 1));
+        out.ea_ref.assign((size_t)nr * EA_VECS, cd(0));
+        parallel_for(nr, p.nthreads, [&](int64_t i) {
+            cd acc[EA_VECS] = {};
+            for (int64_t q = 0; q < N; ++q) {
+                const cd k = K.entry(rows[i], q);
+                for (int v = 0; v < EA_VECS; ++v) acc[v] += k * out.ea_vecs[(size_t)v * N + q];
+            }
+            for (int v = 0; v < EA_VECS; ++v) out.ea_ref[(size_t)v * nr + i] = acc[v];
+        });
+    }
     // Peeling needs products with A = Kd^* Kd (section 5): on the GPU when available
     // (which forms the adjoint stages itself), else on the host.
     std::vector<Stage> adj;
@@ -125,6 +157,7 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
 // ---------------------------------------------------------------- file format
 namespace {
 const char MAGIC[8] = {'F', 'I', 'O', 'P', 'L', 'A', 'N', '1'};
+const char EST_TAG[4] = {'E', 'S', 'T', '1'};
 
 struct W {
     std::ofstream f;
@@ -194,6 +227,10 @@ void save_factors(const HostFactors &h, const std::string &path) {
     w.mat(h.hif.A0inv);
     w.v(h.hif.max_rank_h);
     w.v(h.build_seconds);
+    // trailer (absent in files written before it): error estimates and the e_a probe
+    w.f.write(EST_TAG, 4);
+    w.v(h.e_a_est); w.v(h.e_s_est); w.v(h.cond_est);
+    w.arr(h.ea_rows); w.arr(h.ea_vecs); w.arr(h.ea_ref);
     if (!w.f) fail(FIO_ERR_IO, "write failed: " + path);
 }
 
@@ -254,6 +291,16 @@ void load_factors(const std::string &path, HostFactors &h) {
     if (h.hif.A0inv.m != (int)h.hif.root_idx.size()) fail(FIO_ERR_IO, "corrupt plan file (root)");
     r.v(h.hif.max_rank_h);
     r.v(h.build_seconds);
+    char tag[4];
+    r.f.read(tag, 4);
+    if (r.f.gcount() == 0 && r.f.eof()) return;  // no trailer
+    if (r.f.gcount() != 4 || std::memcmp(tag, EST_TAG, 4) != 0) fail(FIO_ERR_IO, "corrupt plan file (trailer)");
+    r.v(h.e_a_est); r.v(h.e_s_est); r.v(h.cond_est);
+    r.arr(h.ea_rows); r.arr(h.ea_vecs); r.arr(h.ea_ref);
+    for (int v : h.ea_rows) if (v < 0 || v >= h.N) fail(FIO_ERR_IO, "corrupt plan file (probe rows)");
+    if ((int64_t)h.ea_vecs.size() != (h.ea_rows.empty() ? 0 : h.N * EA_VECS) ||
+        h.ea_ref.size() != h.ea_rows.size() * EA_VECS)
+        fail(FIO_ERR_IO, "corrupt plan file (probe sizes)");
 }
 
 }  // namespace fio

@@ -284,6 +284,7 @@ struct fio_plan_s {
     int64_t device_bytes = 0;
     // workspace (grown on demand)
     int ws_nrhs = 0;
+    bool ws_captured = false;                 // a call ran under stream capture
     DBuf P, Q, V1, V2, V3, W, U, X, R, Z, Pv, red, scal, HT, RI, RO;
     DBuf GV, GH;                              // GMRES basis ((m+1) vectors) and Hessenberg entries
     int64_t gv_vecs = 0, gv_cnt = 0;
@@ -466,8 +467,18 @@ void upload_plan(fio_plan p) {
     count_bytes(p);
 }
 
-void ensure_ws(fio_plan p, int nrhs) {
+// Workspace for nrhs columns.  A graph captured from a call keeps the workspace's
+// addresses, so once any call has run under stream capture the workspace never
+// moves again: a later call that would need more fails instead.
+void ensure_ws(fio_plan p, int nrhs, hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (st) HIPC(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) p->ws_captured = true;
     if (nrhs <= p->ws_nrhs) return;
+    if (p->ws_captured)
+        fail(FIO_ERR_ARG, "nrhs = " + std::to_string(nrhs) + " needs a larger workspace than the " +
+                              std::to_string(p->ws_nrhs) + " columns a captured graph of this plan uses; "
+                              "make the widest call before capturing");
     const size_t coef = (size_t)p->max_coef * nrhs * 16;
     const size_t vec = (size_t)p->host.N * nrhs * 16;
     p->P.alloc(coef); p->Q.alloc(coef);
@@ -608,6 +619,103 @@ void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, int for
     }
 }
 
+// worst = max(worst, v), where a NaN v (a non-finite column) wins, so that the
+// convergence tests below fail for it instead of skipping it.
+inline void worse(double &worst, double v) {
+    if (!(v <= worst)) worst = v;
+}
+
+// Error estimates of a device plan (section 6's e_a and e_s, and cond(Kd)), in FP64
+// on EA_VECS columns in the library's internal layout:
+//   e_a   relative error of Kd v against K v on the probe rows the build summed;
+//   e_s   spectral radius of E = I - Gd Kd^* Kd by power iteration (E is similar
+//         to the Hermitian I - Sd^{1/2} Gd Sd^{1/2}, so the iteration converges to it);
+//   cond  sqrt(lambda_max(Sd) lambda_max(Gd)), with Gd ~ Sd^{-1}.
+// Skipped where the plan already carries them (a loaded plan file).
+void estimate_errors(fio_plan p) {
+    HostFactors &h = p->host;
+    if (h.e_s_est > 0 || h.cond_est > 0) return;
+    const int nr = EA_VECS;
+    const int64_t N = h.N, cnt = N * nr;
+    hipStream_t st = 0;
+    ensure_ws(p, nr, st);
+    double *scal = (double *)p->scal.p, *red = (double *)p->red.p;
+    const int64_t cap = reduce_partial_cap(N, nr);
+    std::vector<cd> pm((size_t)cnt);
+    std::vector<double> nrm(nr);
+    auto norms = [&](const void *v) {  // squared column norms to the host
+        launch_colnorm2(v, N, nr, red, cap, scal, st);
+        HIPC(hipMemcpyAsync(nrm.data(), scal, nr * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPC(hipStreamSynchronize(st));
+    };
+    auto start = [&](uint64_t salt) {  // Gaussian unit columns in X
+        for (int64_t i = 0; i < cnt; ++i)
+            pm[i] = cd(gauss(0xE57ULL ^ salt, 2 * (uint64_t)i), gauss(0xE57ULL ^ salt, 2 * (uint64_t)i + 1));
+        HIPC(hipMemcpy(p->X.p, pm.data(), (size_t)cnt * 16, hipMemcpyHostToDevice));
+        launch_colnorm2(p->X.p, N, nr, red, cap, scal, st);
+        launch_col_unit(p->X.p, p->X.p, scal, N, nr, st);
+    };
+    auto sd = [&](const void *in, void *out) {  // out = Kd^* Kd in
+        run_chain(p, true, true, in, p->V1.p, nr, st);
+        run_chain(p, false, true, p->V1.p, out, nr, st);
+    };
+    auto gd = [&](const void *in, void *out) {  // out = Gd in
+        HIPC(hipMemcpyAsync(out, in, (size_t)cnt * 16, hipMemcpyDeviceToDevice, st));
+        gd_inplace(p, true, out, nr, st);
+    };
+    constexpr int ITS = 12;
+    // e_a on the probe rows
+    if (!h.ea_rows.empty() && h.e_a_est == 0) {
+        const int rows = (int)h.ea_rows.size();
+        for (int64_t q = 0; q < N; ++q)
+            for (int v = 0; v < nr; ++v) pm[q * nr + v] = h.ea_vecs[(size_t)v * N + q];
+        HIPC(hipMemcpy(p->X.p, pm.data(), (size_t)cnt * 16, hipMemcpyHostToDevice));
+        run_chain(p, true, true, p->X.p, p->V2.p, nr, st);
+        HIPC(hipMemcpy(pm.data(), p->V2.p, (size_t)cnt * 16, hipMemcpyDeviceToHost));
+        double worst = 0;
+        for (int v = 0; v < nr; ++v) {
+            double num = 0, den = 0;
+            for (int i = 0; i < rows; ++i) {
+                const cd ref = h.ea_ref[(size_t)v * rows + i];
+                num += std::norm(pm[(size_t)h.ea_rows[i] * nr + v] - ref);
+                den += std::norm(ref);
+            }
+            worse(worst, std::sqrt(num / std::max(den, 1e-300)));
+        }
+        h.e_a_est = worst;
+    }
+    // e_s: power iteration on I - Gd Sd
+    start(1);
+    double es = 0;
+    for (int it = 0; it < ITS; ++it) {
+        sd(p->X.p, p->V2.p);
+        gd(p->V2.p, p->V3.p);
+        launch_residual(p->X.p, p->V3.p, p->R.p, true, cnt, st);  // R = (I - Gd Sd) x, ||x|| = 1
+        norms(p->R.p);
+        es = 0;
+        for (int b = 0; b < nr; ++b) worse(es, std::sqrt(nrm[b]));
+        launch_col_unit(p->X.p, p->R.p, scal, N, nr, st);
+    }
+    // lambda_max of Sd and of Gd
+    auto lmax = [&](bool of_sd, uint64_t salt) {
+        start(salt);
+        double l = 0;
+        for (int it = 0; it < ITS; ++it) {
+            if (of_sd) sd(p->X.p, p->V2.p);
+            else gd(p->X.p, p->V2.p);
+            norms(p->V2.p);
+            l = 0;
+            for (int b = 0; b < nr; ++b) worse(l, std::sqrt(nrm[b]));
+            launch_col_unit(p->X.p, p->V2.p, scal, N, nr, st);
+        }
+        return l;
+    };
+    const double ls = lmax(true, 2), lg = lmax(false, 3);
+    HIPC(hipStreamSynchronize(st));
+    h.e_s_est = es;
+    h.cond_est = std::sqrt(std::max(ls * lg, 1.0));
+}
+
 void check_apply_args(fio_plan p, int64_t nrhs, int64_t ld, const void *a, const void *b) {
     if (!p) fail(FIO_ERR_ARG, "null plan");
     if (p->device < 0) fail(FIO_ERR_UNSUPPORTED, "plan is host-only (built or loaded with device = -1)");
@@ -706,7 +814,10 @@ fio_status fio_build(const fio_problem *prob, fio_plan *out) {
         } else if (p->device < 0) {
             p->adj = adjoint_indexes(p->host.fwd);
         }
-        if (p->device >= 0) upload_plan(p.get());
+        if (p->device >= 0) {
+            upload_plan(p.get());
+            estimate_errors(p.get());
+        }
         *out = p.release();
     });
 }
@@ -719,8 +830,12 @@ fio_status fio_load(const char *path, int device, fio_plan *out) {
         load_factors(path, p->host);
         p->host.prob.device = device;
         p->device = device;
-        if (device >= 0) upload_plan(p.get());
-        else p->adj = adjoint_indexes(p->host.fwd);
+        if (device >= 0) {
+            upload_plan(p.get());
+            estimate_errors(p.get());
+        } else {
+            p->adj = adjoint_indexes(p->host.fwd);
+        }
         *out = p.release();
     });
 }
@@ -758,6 +873,9 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
         o->bf_device_levels = h.bf_device_levels;
         o->hif_device_ids = h.hif.device_ids;
         o->hif_device_nodes = h.hif.device_nodes;
+        o->e_a_est = h.e_a_est;
+        o->e_s_est = h.e_s_est;
+        o->cond_est = h.cond_est;
     });
 }
 
@@ -786,7 +904,7 @@ fio_status fio_apply(fio_plan p, fio_op op, fio_dtype dt, const void *x, void *y
         hipStream_t st = (hipStream_t)stream;
         const bool dbl = dt == FIO_C128;
         const int nr = (int)nrhs;
-        ensure_ws(p, nr);
+        ensure_ws(p, nr, st);
         const int32_t *perm = (const int32_t *)p->perm.p;
         const int64_t N = p->host.N;
         launch_gather(x, dbl, ld, perm, p->V1.p, dbl, N, nr, st);
@@ -921,7 +1039,7 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
         hipStream_t st = (hipStream_t)stream;
         const bool dbl = dt == FIO_C128;
         const int nr = (int)nrhs;
-        ensure_ws(p, nr);
+        ensure_ws(p, nr, st);
         launch_scale_zero(p->P.p, p->max_coef * nr, st);
         launch_scale_zero(p->Q.p, p->max_coef * nr, st);
         launch_scale_zero(p->V2.p, p->host.N * nr, st);
@@ -1080,7 +1198,7 @@ fio_status fio_gd_apply_variant(fio_plan p, fio_dtype dt, int variant, const voi
         hipStream_t st = (hipStream_t)stream;
         const bool dbl = dt == FIO_C128;
         const int nr = (int)nrhs;
-        ensure_ws(p, nr);
+        ensure_ws(p, nr, st);
         const int32_t *perm = (const int32_t *)p->perm.p;
         launch_gather(x, dbl, ld, perm, p->V2.p, dbl, p->host.N, nr, st);
         gd_inplace(p, dbl, p->V2.p, nr, st, variant);
@@ -1099,7 +1217,7 @@ fio_status fio_inverse_apply(fio_plan p, fio_dtype dt, const void *u, void *fh, 
         hipStream_t st = (hipStream_t)stream;
         const bool dbl = dt == FIO_C128;
         const int nr = (int)nrhs;
-        ensure_ws(p, nr);
+        ensure_ws(p, nr, st);
         const int32_t *perm = (const int32_t *)p->perm.p;
         const int64_t N = p->host.N;
         launch_gather(u, dbl, ld, perm, p->V1.p, dbl, N, nr, st);
@@ -1175,7 +1293,7 @@ int gmres(fio_plan p, const fio_solve_opts *opts, int nr, AC &apply_chain, GD &g
         worst = 0;
         for (int b = 0; b < nr; ++b) {
             beta[b] = std::sqrt(h2[b]);
-            worst = std::max(worst, beta[b] / unorm[b]);
+            worse(worst, beta[b] / unorm[b]);
         }
         if (opts->tol > 0 && worst <= opts->tol) { converged = true; break; }
         std::fill(g.begin(), g.end(), cdd(0));
@@ -1225,7 +1343,7 @@ int gmres(fio_plan p, const fio_solve_opts *opts, int nr, AC &apply_chain, GD &g
                 const cdd gj = g[(size_t)j * nr + b];
                 g[(size_t)j * nr + b] = c * gj;
                 g[(size_t)(j + 1) * nr + b] = -std::conj(s) * gj;
-                worst = std::max(worst, std::abs(g[(size_t)(j + 1) * nr + b]) / unorm[b]);
+                worse(worst, std::abs(g[(size_t)(j + 1) * nr + b]) / unorm[b]);
             }
             if (opts->tol > 0 && worst <= opts->tol) { ++j; break; }
         }
@@ -1280,7 +1398,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
         hipStream_t st = (hipStream_t)stream;
         const bool dbl = dt == FIO_C128;
         const int nr = (int)nrhs;
-        ensure_ws(p, nr);
+        ensure_ws(p, nr, st);
         const int32_t *perm = (const int32_t *)p->perm.p;
         const int64_t N = p->host.N;
         const int64_t cnt = N * nr;
@@ -1351,7 +1469,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
                         HIPC(hipStreamSynchronize(st));
                         worst = 0;
                         for (int b = 0; b < nr; ++b)
-                            worst = std::max(worst, std::sqrt(hs[b] / std::max(hs[nr + b], 1e-300)));
+                            worse(worst, std::sqrt(hs[b] / std::max(hs[nr + b], 1e-300)));
                         if (opts->tol > 0 && worst <= opts->tol) break;
                     }
                 }
@@ -1383,7 +1501,7 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
                 HIPC(hipMemcpyAsync(hs.data(), nrm, nr * sizeof(double), hipMemcpyDeviceToHost, st));
                 HIPC(hipStreamSynchronize(st));
                 worst = 0;
-                for (int b = 0; b < nr; ++b) worst = std::max(worst, std::sqrt(hs[b] / std::max(bnorm[b], 1e-300)));
+                for (int b = 0; b < nr; ++b) worse(worst, std::sqrt(hs[b] / std::max(bnorm[b], 1e-300)));
                 if (opts->tol > 0 && worst <= opts->tol) { converged = true; break; }
                 if (opts->tol == 0 && it + 1 == opts->maxit) { converged = true; break; }
                 precond(p->R.p, p->Z.p);
@@ -1399,8 +1517,27 @@ fio_status fio_solve(fio_plan p, const fio_solve_opts *opts, fio_dtype dt, const
             HIPC(hipStreamSynchronize(st));
             info->iters = iters;
             info->rel_resid = worst;
+            // error against the exact solve: the iteration's part, plus cond e_a for the
+            // fixed point Kd^{-1} u (or the normal-equation solution) against K^{-1} u
+            const HostFactors &h = p->host;
+            const double kap = std::max(1.0, h.cond_est), fixed = kap * h.e_a_est;
+            const bool direct = opts->mode == FIO_SOLVE_DIRECT || (opts->mode == FIO_SOLVE_REFINE && iters == 0);
+            double est;
+            if (direct) {
+                // FP32 applies add rounding of about 2^-24 per factor, compounded over the steps
+                const double steps = (double)(h.fwd.size() + 2 * h.hif.steps.size() + 1);
+                est = h.e_s_est + fixed + (dbl ? 0.0 : kap * 6e-8 * std::sqrt(steps));
+            } else if (opts->mode == FIO_SOLVE_REFINE) {
+                est = h.e_s_est * worst + fixed + kap * 1e-15;
+            } else if (opts->mode == FIO_SOLVE_PCG) {
+                est = kap * kap * worst + fixed;
+            } else {
+                est = kap * worst + fixed;
+            }
+            info->est_rel_err = est;
         }
         if (!converged) fail(FIO_ERR_NOT_CONVERGED, "tolerance not reached within maxit");
+        if (std::isnan(worst)) fail(FIO_ERR_NOT_CONVERGED, "a column of the iteration is not finite");
     });
 }
 
@@ -1410,7 +1547,7 @@ fio_status fio_inverse_dft(fio_plan p, const void *fhat, void *f, int64_t nrhs, 
         if (nrhs == 0) return;
         std::lock_guard<std::mutex> lk(p->mu);
         HIPC(hipSetDevice(p->device));
-        ensure_ws(p, (int)nrhs);
+        ensure_ws(p, (int)nrhs, (hipStream_t)stream);
         launch_inverse_dft(fhat, ld, f, p->host.d, p->host.n, (int)nrhs, p->V1.p, p->V2.p, (hipStream_t)stream);
     });
 }

@@ -322,12 +322,21 @@ struct DevMem {
 };
 
 // Device copies of the kernel tables, alive as long as the engine.
+// A caller-defined FIO (FIO_PHASE_CALLBACK) has no device image: its entries are
+// evaluated on the host (host points at the builder's kernel table, which outlives
+// the engine) and copied to the device for the decompositions.
 struct Tables {
     int device = 0;
     KTab view;
     DevMem k1, k2, j1, j2, c1, c2, gx, hq;
+    const FioKernel *host = nullptr;
     Tables(int dev, const FioKernel &K) : device(dev) {
         CHK(hipSetDevice(dev));
+        if (K.phi_fn) {
+            host = &K;
+            view.N = K.N;
+            return;
+        }
         auto up = [](DevMem &m, const void *src, size_t bytes) {
             m.alloc(bytes);
             if (bytes) CHK(hipMemcpy(m.p, src, bytes, hipMemcpyHostToDevice));
@@ -387,10 +396,28 @@ bool run_batch(const Tables &tb, const IdBatch &bt, const IdSink &sink, int nthr
         CHK(hipMemcpy(S.p, bt.samp.data() + b0 * ns, (size_t)nbc * ns * 4, hipMemcpyHostToDevice));
         CHK(hipMemcpy(C.p, bt.cand.data() + b0 * nc, (size_t)nbc * nc * 4, hipMemcpyHostToDevice));
         const int64_t total = nbc * ns * nc;
-        const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
-        hipLaunchKernelGGL(k_id_sample, dim3(grid), dim3(256), 0, 0, tb.view, (const int *)S.p, (const int *)C.p,
-                           ns, nc, nbc, bt.cand_is_x ? 1 : 0, (double2 *)W.p);
-        CHK(hipGetLastError());
+        if (tb.host) {
+            // caller's phase and amplitude: sample on the host, then upload
+            std::vector<cd> Wh((size_t)total);
+            const int *sp = bt.samp.data() + b0 * ns, *cp = bt.cand.data() + b0 * nc;
+            const bool cx = bt.cand_is_x;
+            parallel_for(nbc * nc, nthreads, [&](int64_t bc) {
+                const int64_t b = bc / nc;
+                const int c = (int)(bc - b * nc);
+                const int pc = cp[b * nc + c];
+                cd *col = Wh.data() + (size_t)bc * ns;
+                for (int s2 = 0; s2 < ns; ++s2) {
+                    const int ps = sp[b * ns + s2];
+                    col[s2] = cx ? tb.host->entry(pc, ps) : tb.host->entry(ps, pc);
+                }
+            });
+            CHK(hipMemcpy(W.p, Wh.data(), (size_t)total * 16, hipMemcpyHostToDevice));
+        } else {
+            const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+            hipLaunchKernelGGL(k_id_sample, dim3(grid), dim3(256), 0, 0, tb.view, (const int *)S.p,
+                               (const int *)C.p, ns, nc, nbc, bt.cand_is_x ? 1 : 0, (double2 *)W.p);
+            CHK(hipGetLastError());
+        }
         double2 *w = (double2 *)W.p;
         const double tol = fixed ? 0.0 : bt.tol_rel;
         int *rp = (int *)R.p, *pp = (int *)P.p;

@@ -34,9 +34,19 @@ struct FioKernel {
     // Example 2's amplitude: each Gaussian term factors into g_k(x) h_k(xi), so
     // a(x_p, xi_q) = sum_k gx[k][p] hq[k][q] (tree order).
     std::vector<std::vector<double>> gx, hq;
+    // A caller-defined FIO (FIO_PHASE_CALLBACK): the whole phase and the amplitude.
+    fio_phase_fn phi_fn = nullptr;
+    fio_amp_fn amp_fn = nullptr;
+    void *user = nullptr;
 
     void init(const fio_problem &pr) {
         init(pr.d, pr.n, pr.phase, pr.c_div);
+        if (pr.phase == FIO_PHASE_CALLBACK) {
+            phi_fn = pr.phi;
+            amp_fn = pr.amp;
+            user = pr.user;
+            return;
+        }
         if (pr.phase != FIO_PHASE_1D_EX2) return;
         gx.assign(pr.amp_terms, std::vector<double>(N));
         hq.assign(pr.amp_terms, std::vector<double>(N));
@@ -104,7 +114,27 @@ struct FioKernel {
         return a;
     }
 
+    // K(x_p, xi_q) from the caller's functions: x = k/n, xi as given; the phase is
+    // reduced mod 1 before the exponential.
+    cd callback_entry(int64_t p, int64_t q) const {
+        const double x[2] = {(double)k1[p] / n, (double)k2[p] / n};
+        const double xi[2] = {(double)j1[q], (double)j2[q]};
+        const double ph = phi_fn(x, xi, d, user);
+        if (!std::isfinite(ph)) fail(FIO_ERR_ARG, "the phase callback returned a non-finite value");
+        const double t = 6.283185307179586476925286766559 * (ph - std::floor(ph));
+        cd e(std::cos(t), std::sin(t));
+        if (amp_fn) {
+            double ri[2] = {1.0, 0.0};
+            amp_fn(x, xi, d, user, ri);
+            if (!std::isfinite(ri[0]) || !std::isfinite(ri[1]))
+                fail(FIO_ERR_ARG, "the amplitude callback returned a non-finite value");
+            e *= cd(ri[0], ri[1]);
+        }
+        return e;
+    }
+
     cd entry(int64_t p, int64_t q) const {
+        if (phi_fn) return callback_entry(p, q);
         double t = 6.283185307179586476925286766559 * phase_mod1(p, q);
         return amplitude(p, q) * cd(std::cos(t), std::sin(t));
     }

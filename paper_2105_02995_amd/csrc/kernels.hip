@@ -4,6 +4,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -720,26 +721,24 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
 // LDS one workgroup may use: the device's opt-in limit (160 KiB per CU on
 // gfx950), capped with a margin; 64 KiB if the runtime does not report it.
 static int hif_lds_budget() {
-    static int budget = -1;
-    if (budget < 0) {
+    static const int budget = [] {  // initialised once, thread-safe
         int dev = 0, v = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0)
             v = 64 * 1024;
-        budget = std::min(v, 144 * 1024);
         (void)hipGetLastError();
-    }
+        return std::min(v, 144 * 1024);
+    }();
     return budget;
 }
 
 template <class T, bool UP, bool ST>
 static void hif_go(const HifStepDev &h, size_t lds, void *x, int nrhs, int bchunk, hipStream_t st) {
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;  // plans may be used from several host threads
+    std::call_once(attr_once, [] {
         (void)hipFuncSetAttribute((const void *)k_hif<T, UP, ST>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
-        attr_set = true;
-    }
+    });
     const unsigned nch = (unsigned)((nrhs + bchunk - 1) / bchunk);
     hipLaunchKernelGGL((k_hif<T, UP, ST>), dim3((unsigned)h.n_nodes, nch), dim3(256), lds, st, h.desc,
                        h.idx, (const T *)h.mat, (T *)x, nrhs, bchunk);
@@ -937,13 +936,14 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
     const int maxk = std::max(1, std::max(h.max_nr, h.max_ns));
     const size_t lds = (size_t)4 * maxk * sizeof(int32_t);
     if ((int64_t)lds > hif_lds_budget()) throw std::runtime_error("hif step: index lists exceed LDS");
-    static bool attr_set[6] = {false, false, false, false, false, false};
-    if (lds > 65536 && !attr_set[ph]) {
-        const void *fn[6] = {(const void *)k_hgemm<R, 0, 1, NT>, (const void *)k_hgemm<R, 1, 1, NT>,
-                             (const void *)k_hgemm<R, 2, 1, NT>, (const void *)k_hgemm<R, 3, 1, NT>,
-                             (const void *)k_hgemm<R, 4, 1, NT>, (const void *)k_hgemm<R, 5, 1, NT>};
-        (void)hipFuncSetAttribute(fn[ph], hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
-        attr_set[ph] = true;
+    static std::once_flag attr_once[6];  // plans may be used from several host threads
+    if (lds > 65536) {
+        std::call_once(attr_once[ph], [ph] {
+            const void *fn[6] = {(const void *)k_hgemm<R, 0, 1, NT>, (const void *)k_hgemm<R, 1, 1, NT>,
+                                 (const void *)k_hgemm<R, 2, 1, NT>, (const void *)k_hgemm<R, 3, 1, NT>,
+                                 (const void *)k_hgemm<R, 4, 1, NT>, (const void *)k_hgemm<R, 5, 1, NT>};
+            (void)hipFuncSetAttribute(fn[ph], hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
+        });
     }
 #define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1, NT>), g, dim3(256), lds, st, h.desc, h.idx, tiles, ntiles, mat, matH, \
                                  (C *)x, (C *)t, nrhs, nch, maxk)
@@ -1225,12 +1225,11 @@ static void hif_fused_go(const HifStepDev &h, int rr, int rs, void *x, int nrhs,
     using C = typename MF<R>::C;
     constexpr int CW = 16 * NTW, LD = CW + 4;
     const size_t lds = (size_t)(rr + rs) * LD * sizeof(C) + (size_t)(rr + rs) * sizeof(int32_t);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_once;  // plans may be used from several host threads
+    std::call_once(attr_once, [] {
         (void)hipFuncSetAttribute((const void *)k_hif_fused<R, UP, NTW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   hif_lds_budget());
-        attr_set = true;
-    }
+    });
     if ((int64_t)lds > hif_lds_budget()) throw std::runtime_error("fused skeletonization step exceeds LDS");
     const dim3 g((unsigned)h.n_nodes, (unsigned)((nrhs + CW - 1) / CW));
     hipLaunchKernelGGL((k_hif_fused<R, UP, NTW>), g, dim3(256), lds, st, h.desc, h.idx, (const C *)h.mat,
@@ -1499,8 +1498,11 @@ void launch_coldot(const void *a, const void *c, int64_t n, int nrhs, double *pa
     colred(true, a, c, n, nrhs, partial, cap, out, st);
 }
 
+// a / b, and 0 where b is 0: a column whose right-hand side is zero has r = p = 0,
+// so both PCG ratios are 0/0 there; a zero step keeps its exact solution x = 0.
 __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
     const double den = b.x * b.x + b.y * b.y;
+    if (!(den > 0.0)) return make_double2(0.0, 0.0);
     return make_double2((a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den);
 }
 

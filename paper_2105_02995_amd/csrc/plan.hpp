@@ -20,7 +20,16 @@ struct HostFactors {
     double build_seconds = 0;
     double bf_seconds = 0;          // butterfly construction (not stored in files)
     int bf_device_levels = 0;       // butterfly levels decomposed on the device
+    // Probe of the butterfly error e_a: EA_VECS Gaussian vectors (Omega tree order,
+    // column-major N x EA_VECS), EA_ROWS sampled X tree positions, and K v on those
+    // rows summed from the entries of K in FP64.  Formed by the build (where the
+    // phase is at hand) and compared with Kd v on the device.
+    std::vector<int> ea_rows;
+    std::vector<cd> ea_vecs, ea_ref;
+    // Error estimates (0 until measured; see fio_plan_stats_t).
+    double e_a_est = 0, e_s_est = 0, cond_est = 0;
 };
+constexpr int EA_ROWS = 64, EA_VECS = 4;
 
 // Builds the factors; `gpu` (may be empty) replaces the host product Kd^* Kd of the
 // peeling step, `ids` (may be empty) the host interpolative decompositions of the

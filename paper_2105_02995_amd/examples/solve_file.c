@@ -3,18 +3,62 @@
  *
  *   fio_solve_file d n phase eps nrhs mode u.bin out.bin
  *
- * Builds the factors of the discrete FIO (phase: 1 = 1D Example 1, 2 = 2D Example 3,
- * c/16), reads u (complex128, column-major N x nrhs, interleaved re/im) from u.bin,
- * runs fio_solve on device 0 (mode 0 direct, 1 refinement with one FP64 step, 2 PCG,
- * 3 GMRES; complex64 applies) and writes fhat to out.bin in the same layout.  Device
- * memory comes from the HIP runtime's C API.  Exit status 0 on success.
+ * Builds the factors of the discrete FIO, reads u (complex128, column-major N x nrhs,
+ * interleaved re/im) from u.bin, runs fio_solve on device 0 (mode 0 direct, 1
+ * refinement with one FP64 step, 2 PCG, 3 GMRES; complex64 applies) and writes fhat to
+ * out.bin in the same layout.  Device memory comes from the HIP runtime's C API.  Exit
+ * status 0 on success.
+ *
+ * phase: 1 = 1D Example 1, 2 = 2D Example 3 (the library's built-in phases, c/16), or a
+ * FIO this program defines itself through FIO_PHASE_CALLBACK (section 1, eq6: any
+ * amplitude and phase):
+ *   101  Phi = x xi + c(x)|xi|, c = (2 + sin 2 pi x)/16             (Example 1)
+ *   102  Phi = x.xi + sqrt(c1^2 xi1^2 + c2^2 xi2^2)                  (Example 3)
+ *   103  101's phase with a Gaussian-mixture amplitude a(x, xi)      (Example 2 shape:
+ *        three terms at (x, xi/n) = (0.2, -0.2), (0.5, 0.2), (0.8, 0.0), sigma^2 = 0.1,
+ *        x periodic)
  */
 #include <hip/hip_runtime_api.h>
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include "fio.h"
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+/* fio_phase_fn: the whole phase in cycles (the library reduces it mod 1). */
+static double phase_ex1(const double *x, const double *xi, int d, void *user) {
+    (void)d;
+    (void)user;
+    const double c = (2.0 + sin(TWO_PI * x[0])) / 16.0;
+    return x[0] * xi[0] + c * fabs(xi[0]);
+}
+
+static double phase_radon(const double *x, const double *xi, int d, void *user) {
+    (void)d;
+    (void)user;
+    const double c1 = (2.0 + sin(TWO_PI * x[0]) * sin(TWO_PI * x[1])) / 16.0;
+    const double c2 = (2.0 + cos(TWO_PI * x[0]) * cos(TWO_PI * x[1])) / 16.0;
+    return x[0] * xi[0] + x[1] * xi[1] + sqrt(c1 * c1 * xi[0] * xi[0] + c2 * c2 * xi[1] * xi[1]);
+}
+
+/* fio_amp_fn: user points at n (frequencies are scaled to xi/n). */
+static void amp_mixture(const double *x, const double *xi, int d, void *user, double re_im[2]) {
+    (void)d;
+    static const double cx[3] = {0.2, 0.5, 0.8}, ce[3] = {-0.2, 0.2, 0.0};
+    const double nu = xi[0] / (double)*(const int *)user;
+    double a = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double dx = fabs(x[0] - cx[k]);
+        if (dx > 0.5) dx = 1.0 - dx;
+        const double de = nu - ce[k];
+        a += exp(-(dx * dx + de * de) / 0.1);
+    }
+    re_im[0] = a;
+    re_im[1] = 0.0;
+}
 
 #define CHECK_FIO(call)                                                                    \
     do {                                                                                   \
@@ -42,7 +86,14 @@ int main(int argc, char **argv) {
     memset(&p, 0, sizeof(p));
     p.d = atoi(argv[1]);
     p.n = atoi(argv[2]);
-    p.phase = (fio_phase_id)atoi(argv[3]);
+    const int phase = atoi(argv[3]);
+    p.phase = (fio_phase_id)phase;
+    if (phase > 100) {
+        p.phase = FIO_PHASE_CALLBACK;
+        p.phi = phase == 102 ? phase_radon : phase_ex1;
+        p.amp = phase == 103 ? amp_mixture : NULL;
+        p.user = &p.n;
+    }
     p.eps = atof(argv[4]);
     p.device = 0;
     const int64_t nrhs = atoll(argv[5]);
@@ -74,8 +125,8 @@ int main(int argc, char **argv) {
     fio_solve_info info;
     CHECK_FIO(fio_solve(plan, &o, FIO_C64, du, dx, nrhs, N, &info, NULL));
     CHECK_HIP(hipMemcpy(host, dx, bytes, hipMemcpyDeviceToHost));
-    printf("solved N=%lld nrhs=%lld mode=%d: %d iterations, residual %.3e\n", (long long)N,
-           (long long)nrhs, mode, info.iters, info.rel_resid);
+    printf("solved N=%lld nrhs=%lld mode=%d: %d iterations, residual %.3e, estimated error %.3e\n",
+           (long long)N, (long long)nrhs, mode, info.iters, info.rel_resid, info.est_rel_err);
 
     f = fopen(argv[8], "wb");
     if (!f || fwrite(host, 1, bytes, f) != bytes) {

@@ -19,10 +19,17 @@ STATUS = {0: "FIO_OK", 1: "FIO_ERR_ARG", 2: "FIO_ERR_NOMEM", 3: "FIO_ERR_DEVICE"
 FIO_C64, FIO_C128 = 0, 1
 FIO_OP_K, FIO_OP_KH = 0, 1
 FIO_PHASE_LINEAR, FIO_PHASE_1D_EX1, FIO_PHASE_2D_RADON, FIO_PHASE_1D_EX2 = 0, 1, 2, 3
+FIO_PHASE_CALLBACK = 4
 FIO_MAX_AMP_TERMS = 8
 FIO_SOLVE_DIRECT, FIO_SOLVE_REFINE, FIO_SOLVE_PCG, FIO_SOLVE_GMRES = 0, 1, 2, 3
 PHASES = {"linear": FIO_PHASE_LINEAR, "1d_ex1": FIO_PHASE_1D_EX1, "2d_radon": FIO_PHASE_2D_RADON,
-          "1d_ex2": FIO_PHASE_1D_EX2}
+          "1d_ex2": FIO_PHASE_1D_EX2, "callback": FIO_PHASE_CALLBACK}
+
+# fio_phase_fn and fio_amp_fn of fio.h
+PHASE_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                            ctypes.c_int, ctypes.c_void_p)
+AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
@@ -46,7 +53,8 @@ class fio_problem(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("amp_sigma2", ctypes.c_double), ("amp_terms", ctypes.c_int),
                 ("amp_x", ctypes.c_double * FIO_MAX_AMP_TERMS), ("amp_eta", ctypes.c_double * FIO_MAX_AMP_TERMS),
                 ("strict_hpd", ctypes.c_int), ("host_construction", ctypes.c_int),
-                ("prescale_skel", ctypes.c_int)]
+                ("prescale_skel", ctypes.c_int), ("phi", PHASE_FN), ("amp_fn", AMP_FN),
+                ("user", ctypes.c_void_p)]
 
 
 class fio_solve_opts(ctypes.Structure):
@@ -55,7 +63,7 @@ class fio_solve_opts(ctypes.Structure):
 
 
 class fio_solve_info(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int), ("rel_resid", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int), ("rel_resid", ctypes.c_double), ("est_rel_err", ctypes.c_double)]
 
 
 class fio_plan_stats_t(ctypes.Structure):
@@ -67,7 +75,8 @@ class fio_plan_stats_t(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("hif_shifted", ctypes.c_int),
                 ("bf_seconds", ctypes.c_double), ("bf_device_levels", ctypes.c_int),
-                ("hif_device_ids", ctypes.c_int), ("hif_device_nodes", ctypes.c_int)]
+                ("hif_device_ids", ctypes.c_int), ("hif_device_nodes", ctypes.c_int),
+                ("e_a_est", ctypes.c_double), ("e_s_est", ctypes.c_double), ("cond_est", ctypes.c_double)]
 
 
 _lib = None
@@ -170,8 +179,22 @@ def make_problem(d, n, phase="1d_ex1", eps=1e-6, c_div=16.0, device=0, **kw) -> 
         p.amp_terms = len(amp)
         for k, (x, e) in enumerate(amp):
             p.amp_x[k], p.amp_eta[k] = x, e
+    # FIO_PHASE_CALLBACK: the caller's phase and amplitude, as C function addresses
+    # (ints, e.g. from a compiled library) or Python callables with the signatures of
+    # fio_phase_fn / fio_amp_fn (correct but slow: every entry of K the build samples
+    # is one Python call).  The wrappers stay alive with the problem.
+    phi_fn = kw.pop("phi_fn", None)
+    amp_fn = kw.pop("amp_fn", None)
+    keep = []
+    if phi_fn is not None:
+        p.phi = ctypes.cast(phi_fn, PHASE_FN) if isinstance(phi_fn, int) else PHASE_FN(phi_fn)
+        keep.append(p.phi)
+    if amp_fn is not None:
+        p.amp_fn = ctypes.cast(amp_fn, AMP_FN) if isinstance(amp_fn, int) else AMP_FN(amp_fn)
+        keep.append(p.amp_fn)
     for k, v in kw.items():
         setattr(p, k, v)
+    p._keep = keep
     return p
 
 
@@ -278,12 +301,16 @@ def fio_gd_apply_variant(plan: Plan, dtype: int, variant: int, x, y, nrhs: int, 
 
 def fio_solve(plan: Plan, mode: int, dtype: int, u, out, nrhs: int, ld: int, tol: float = 0.0,
               maxit: int = 0, precondition: int = 1, stream=None, want_info: bool = True,
-              spatial: int = 0, restart: int = 0):
+              spatial: int = 0, restart: int = 0, with_estimate: bool = False):
+    """Returns (iters, rel_resid), or (iters, rel_resid, est_rel_err) with
+    with_estimate, or None without want_info (no synchronisation)."""
     o = fio_solve_opts(mode, tol, maxit, precondition, spatial, restart)
     info = fio_solve_info()
     _check(load_library().fio_solve(plan.handle, ctypes.byref(o), dtype, _ptr(u), _ptr(out), nrhs,
-                                    ld, ctypes.byref(info) if want_info else None,
+                                    ld, ctypes.byref(info) if (want_info or with_estimate) else None,
                                     _stream(stream)))
+    if with_estimate:
+        return info.iters, info.rel_resid, info.est_rel_err
     return (info.iters, info.rel_resid) if want_info else None
 
 

@@ -61,7 +61,8 @@ class Scheduler:
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_batch_rhs = max_batch_rhs
-        self.max_inflight = max_inflight
+        # never more batches in flight than the executor can run side by side
+        self.max_inflight = min(max_inflight, getattr(executor, "max_concurrent", max_inflight))
         self.queues = collections.defaultdict(collections.deque)
         self.running = {}           # key -> Batch
         self.resident = 0           # bytes of resident factors and workspaces
@@ -83,23 +84,34 @@ class Scheduler:
         return True
 
     # ---------------------------------------------------------------- loop
+    def check(self, req: ServeRequest):
+        """A request wider than max_batch_rhs columns could never be batched (the
+        executor's buffers and graphs stop there): it is refused, as is an empty one."""
+        if req.nrhs > self.max_batch_rhs:
+            raise ValueError("request %s has %d right-hand sides, more than max_batch_rhs = %d"
+                             % (req.rid, req.nrhs, self.max_batch_rhs))
+        if req.nrhs < 1:
+            raise ValueError("request %s has no right-hand side" % (req.rid,))
+
     def submit(self, req: ServeRequest):
+        self.check(req)
         self.queues[req.key].append(req)
 
     def _form_batch(self, key):
         q = self.queues[key]
         reqs, cols = [], 0
-        while q and (cols + q[0].nrhs <= self.max_batch_rhs or not reqs):
+        while q and cols + q[0].nrhs <= self.max_batch_rhs:
             r = q.popleft()
             reqs.append(r)
             cols += r.nrhs
         return Batch(key, reqs, cols, self.ex.footprint(key, cols))
 
     def step(self, now: float):
-        """Start every admissible batch, then collect the finished ones."""
-        for key in list(self.queues):
-            if not self.queues[key] or key in self.running:
-                continue
+        """Start every admissible batch, oldest waiting request first, then collect
+        the finished ones."""
+        ready = [k for k, q in self.queues.items() if q and k not in self.running]
+        ready.sort(key=lambda k: self.queues[k][0].arrival)
+        for key in ready:
             if len(self.running) >= self.max_inflight:
                 break
             b = self._form_batch(key)
@@ -134,6 +146,8 @@ class Scheduler:
     def run(self, requests, time_scale: float = 1.0, timeout: float = 600.0):
         """Replay requests at their arrival times (seconds * time_scale) until all finish."""
         pending = sorted(requests, key=lambda r: r.arrival)
+        for r in pending:  # refuse a bad request before anything starts
+            self.check(r)
         t0 = self.ex.clock()
         i = 0
         while True:
@@ -221,7 +235,7 @@ class GpuExecutor:
 
     BUCKETS = (16, 32, 64, 128, 256, 512, 1024)
 
-    def __init__(self, plans: dict, max_batch_rhs: int = 256, refine: int = 1, nstreams: int = 4,
+    def __init__(self, plans: dict, max_batch_rhs: int = 256, refine: int = 1, nstreams: int = 8,
                  use_graphs: bool = False):
         import torch
         from . import fio as F
@@ -230,6 +244,7 @@ class GpuExecutor:
         self.max_batch_rhs = max_batch_rhs
         self.refine = refine
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.max_concurrent = nstreams  # one batch per stream
         self.busy = {}
         self.stats = {k: F.fio_plan_stats(p) for k, p in plans.items()}
         self.use_graphs = use_graphs
@@ -299,7 +314,7 @@ class GpuExecutor:
         for s in self.streams:
             if id(s) not in used:
                 return s
-        return self.streams[0]
+        raise RuntimeError("every stream is busy: the scheduler started more batches than streams")
 
     def start(self, batch, now):
         torch = self.torch

@@ -109,3 +109,37 @@ def test_2d_n128_batch256_sampled_columns():
     err = O.rel_err(x[:, cols], fh)
     log("2D n=128 refine rel err %s" % err)
     assert err.max() < 10 * EPS
+
+
+def test_2d_n256_batch256_sampled_columns_and_rows():
+    """n=256 (N=65536), 256 right-hand sides, complex64 applies + one FP64
+    refinement step (section 6, Example 3, Table 2d_FIO's 256^2 row): four
+    columns carry u = K fhat from the oracle's direct summation and must give
+    fhat back within 10 eps.  Kd and Kd^* on sampled output rows must match
+    the direct sums within eps (the butterfly error e_a of section 2)."""
+    n, B = 256, 256
+    N = n * n
+    plan = plan2d(n)
+    st = F.fio_plan_stats(plan)
+    log("2D n=256 plan: bf_nnz=%d root=%d max_rank_bf=%d" % (st["bf_nnz"], st["root_size"],
+                                                             st["max_rank_bf"]))
+    p = O.OracleProblem(2, n, "2d_radon", 16.0)
+    fh = gaussian_complex((N, 4), 3005)
+    log("oracle direct summation n=256, 4 columns")
+    u = gaussian_complex((N, B), 3006)
+    cols = np.array([0, 85, 170, 255])
+    u[:, cols] = O.apply_direct(p, fh)
+    x, (its, rr) = G.solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, u, maxit=1)
+    err = O.rel_err(x[:, cols], fh)
+    log("2D n=256 refine rel err %s" % err)
+    assert np.isfinite(x).all()
+    assert err.max() < 10 * EPS
+    # sampled rows of Kd v and Kd^* v (complex128 applies) against the direct sums
+    rows = np.sort(np.random.default_rng(11).choice(N, size=48, replace=False))
+    v = gaussian_complex((N, 2), 3007)
+    for op, adj in ((F.FIO_OP_K, False), (F.FIO_OP_KH, True)):
+        y = G.apply(plan, op, F.FIO_C128, v)
+        ref = O.apply_direct(p, v, adjoint=adj, out_idx=rows)
+        e = O.rel_err(y[rows], ref)
+        log("2D n=256 %s sampled-row rel err %s" % ("Kd" if not adj else "Kd*", e))
+        assert e.max() < EPS

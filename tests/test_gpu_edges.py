@@ -113,3 +113,56 @@ def test_argument_errors():
         with pytest.raises(F.FioError) as e:
             call()
         assert e.value.status == 1  # FIO_ERR_ARG
+
+
+@pytest.mark.parametrize("mode,kw", [
+    (F.FIO_SOLVE_PCG, {"tol": 1e-8, "maxit": 50}),
+    (F.FIO_SOLVE_REFINE, {"maxit": 2}),
+    (F.FIO_SOLVE_GMRES, {"tol": 1e-10, "maxit": 30})])
+def test_zero_column_among_gaussian_ones(mode, kw):
+    """A zero right-hand side has the exact solution 0: every mode must return 0
+    for it (no 0/0 in the per-column scalars) and solve the other columns."""
+    n, eps = 1024, 1e-6
+    plan, op, K = setup(1, n, eps)
+    fh = gaussian_complex((n, 5), 806)
+    fh[:, 2] = 0
+    u = K @ fh
+    x, (its, rr) = G.solve(plan, mode, F.FIO_C128, u, **kw)
+    log("mode %d with a zero column: its %d, rel resid %.2e" % (mode, its, rr))
+    assert np.isfinite(x).all()
+    assert np.abs(x[:, 2]).max() == 0.0
+    assert np.isfinite(rr)
+    keep = [0, 1, 3, 4]
+    assert O.rel_err(x[:, keep], O.solve_dense(op, u[:, keep], K)).max() < 10 * eps
+
+
+def test_captured_plan_refuses_a_wider_call():
+    """A graph captured from a solve keeps the plan's workspace addresses: after
+    the capture a wider call must fail (FIO_ERR_ARG) instead of moving the
+    workspace, and replays keep matching the eager result."""
+    n, eps = 256, 1e-6
+    plan = F.fio_build(F.make_problem(1, n, "1d_ex1", eps=eps, device=0))
+    try:
+        s = torch.cuda.Stream()
+        U = torch.from_numpy(np.ascontiguousarray(gaussian_complex((n, 16), 807).T)).cuda()
+        X = torch.zeros_like(U)
+        with torch.cuda.stream(s):
+            F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, 16, n, maxit=1, stream=s, want_info=False)
+        s.synchronize()
+        eager = X.cpu().clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, 16, n, maxit=1, stream=s, want_info=False)
+        U2 = torch.zeros((32, n), dtype=torch.complex128, device="cuda")
+        X2 = torch.zeros_like(U2)
+        with pytest.raises(F.FioError) as e:
+            F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C64, U2, X2, 32, n, want_info=False)
+        assert e.value.status == 1
+        for _ in range(3):
+            X.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(X.cpu(), eager)
+        del g
+    finally:
+        plan.close()

@@ -51,7 +51,7 @@ def test_requests_arriving_during_a_batch_are_merged_into_the_next():
     assert len(s.finished) == 100
 
 
-def test_batch_never_exceeds_max_columns_unless_a_single_request_does():
+def test_batch_never_exceeds_max_columns():
     sizes = []
 
     class Ex(MockExecutor):
@@ -62,10 +62,11 @@ def test_batch_never_exceeds_max_columns_unless_a_single_request_does():
     ex = Ex(cost=lambda key, nr: 0.01)
     s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=10)
     s.register(_key(0))
-    reqs = [ServeRequest(j, _key(0), 0.0, gaussian_complex((4, 3 if j != 5 else 25), j)) for j in range(12)]
-    s.run(reqs)
-    assert all(n <= 10 or k == 1 for n, k in sizes)
-    assert any(n == 25 for n, _ in sizes)
+    reqs = [ServeRequest(j, _key(0), 0.0, gaussian_complex((4, 3 if j != 5 else 10), j)) for j in range(12)]
+    done = s.run(reqs)
+    assert len(done) == 12
+    assert all(n <= 10 for n, k in sizes)
+    assert any(n == 10 and k == 1 for n, k in sizes)
 
 
 def test_hbm_admission_bounds_inflight_bytes_and_refuses_oversized_keys():
@@ -109,3 +110,52 @@ def test_serving_mix_generator_shapes():
     assert {m.d for m in mix} <= {1, 2}
     arr = [m.arrival for m in mix]
     assert arr == sorted(arr)
+
+
+def test_oldest_request_first_with_more_keys_than_slots():
+    """Twelve keys share four slots: dispatch goes by the arrival of each queue's
+    head, so no key starves behind keys that were submitted first, and the oldest
+    request never waits longer than a few batch durations."""
+    cost = 0.01
+    ex = MockExecutor(cost=lambda key, nr: cost)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=8, max_inflight=4)
+    keys = [(1, 1024 * (i + 1), "1d_ex1", 1e-6) for i in range(12)]
+    for k in keys:
+        assert s.register(k)
+    rng = np.random.default_rng(3)
+    reqs = []
+    t = 0.0
+    for j in range(600):  # offered load just under the four slots' capacity
+        t += rng.exponential(cost / 3.6)
+        reqs.append(ServeRequest(j, keys[j % 12], t, np.zeros((4, 8))))
+    done = s.run(reqs)
+    assert len(done) == 600
+    waits = np.array([r.start - r.arrival for r in done])
+    # a request waits at most for the batches ahead of it in arrival order: with
+    # 12 keys over 4 slots that is about 3 rounds of batches
+    assert waits.max() < 6 * cost, waits.max()
+    assert s.peak_inflight <= 4
+
+
+def test_scheduler_never_exceeds_executor_concurrency():
+    ex = MockExecutor(cost=lambda key, nr: 0.01)
+    ex.max_concurrent = 2
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=8, max_inflight=8)
+    assert s.max_inflight == 2
+    for i in range(5):
+        assert s.register(_key(i))
+    done = s.run(_requests(50, rate=1e4, keys=5, max_rhs=4))
+    assert len(done) == 50 and s.peak_inflight <= 2
+
+
+def test_oversized_request_is_refused_before_anything_runs():
+    ex = MockExecutor(cost=lambda key, nr: 0.01)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=16)
+    assert s.register(_key(0))
+    ok = ServeRequest(0, _key(0), 0.0, np.zeros((4, 3)))
+    big = ServeRequest(1, _key(0), 0.0, np.zeros((4, 17)))
+    with pytest.raises(ValueError):
+        s.run([ok, big])
+    assert s.batches_started == 0
+    with pytest.raises(ValueError):
+        s.submit(ServeRequest(2, _key(0), 0.0, np.zeros((4, 0))))
