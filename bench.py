@@ -116,12 +116,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
     ap.add_argument("--no-serve", action="store_true", help="skip the small serving leg")
+    ap.add_argument("--plan-file", default=None,
+                    help="load the factors from this plan file if it exists, else build them and save them there")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="run only the FP64 single-RHS comparator (for profiling its kernels)")
     ap.add_argument("--trace", action="store_true",
                     help="named library ranges (fio_set_trace) during the timed steps, for a marker trace")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in kernel heuristics")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving mix (Poisson arrivals over many keys) instead of the solve bench")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-multi", action="store_true",
+                    help="serving: run every batch on its own (no multi-instance solves)")
     return ap.parse_args()
 
 
@@ -130,17 +136,19 @@ SERVE_KEYS_FULL = ([(1, n, "1d_ex1", e) for n in (1024, 2048, 4096, 8192, 16384,
 SERVE_KEYS_SMALL = [(1, 4096, "1d_ex1", 1e-6), (1, 65536, "1d_ex1", 1e-6), (2, 64, "2d_radon", 1e-4)]
 
 
-def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True):
+def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True, multi=True):
     """Poisson arrivals (seeded) of solves over the given resident keys, 1..32
     right-hand sides each; the rate is a fraction of the measured saturation rate
-    (all requests at t=0).  Returns p50/p99 latency and RHS*N/s per rate."""
+    (all requests at t=0).  Batches of different keys admitted together run as one
+    multi-instance solve (multi).  Returns p50/p99 latency and RHS*N/s per rate."""
     from paper_2105_02995_amd.serve import (GpuExecutor, Scheduler, ServeRequest, latency_stats,
                                             throughput)
     rng = np.random.default_rng(seed)
     pools = {k: gaussian_complex((k[1] ** k[0], 32), 7000 + i) for i, k in enumerate(keys)}
     kidx = rng.integers(len(keys), size=nreq)
     nrhs = rng.integers(1, 33, size=nreq)
-    ex = GpuExecutor({k: plans[k] for k in keys}, max_batch_rhs=max_batch, refine=1, use_graphs=graphs)
+    ex = GpuExecutor({k: plans[k] for k in keys}, max_batch_rhs=max_batch, refine=1, use_graphs=graphs,
+                     use_multi=multi)
 
     def make(times):
         return [ServeRequest(j, keys[kidx[j]], float(times[j]), pools[keys[kidx[j]]][:, :nrhs[j]])
@@ -154,14 +162,17 @@ def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True):
     t0 = time.perf_counter()
     sch.run(make(np.zeros(nreq)))
     sat = nreq / (time.perf_counter() - t0)
-    out = {"saturation_req_per_s": sat, "keys": len(keys), "requests": nreq, "graphs": graphs, "rates": []}
+    out = {"saturation_req_per_s": sat, "keys": len(keys), "requests": nreq, "graphs": graphs, "multi": multi,
+           "rates": []}
     for frac in fracs:
         sch.finished = []
+        sch.batches_started = sch.groups_started = 0
         times = np.cumsum(rng.exponential(1.0 / (frac * sat), nreq))
         done = sch.run(make(times))
         st = latency_stats(done)
         rec = {"rate_frac": frac, "req_per_s": frac * sat, "p50_ms": st["p50_ms"],
-               "p99_ms": st["p99_ms"], "rhs_n_per_s": throughput(done)}
+               "p99_ms": st["p99_ms"], "rhs_n_per_s": throughput(done),
+               "batches": sch.batches_started, "multi_groups": sch.groups_started}
         log("serving at %.2f x saturation: p50 %.2f ms, p99 %.2f ms, %.3e RHS*N/s" % (
             frac, st["p50_ms"], st["p99_ms"], rec["rhs_n_per_s"]))
         out["rates"].append(rec)
@@ -183,7 +194,8 @@ def serve_main(args):
     import torch  # noqa: F401
     from paper_2105_02995_amd import fio as F
     plans = build_plans(F, SERVE_KEYS_FULL)
-    res = serving_run(F, plans, SERVE_KEYS_FULL, args.serve_requests, (0.5, 0.8, 0.95), 2000)
+    res = serving_run(F, plans, SERVE_KEYS_FULL, args.serve_requests, (0.5, 0.8, 0.95), 2000,
+                      multi=not args.no_multi)
     head = res["rates"][1]
     out = {"metric": "serving mix: p50/p99 latency and RHS*N/s of factored FIO solves",
            "value": head["rhs_n_per_s"], "unit": "RHS*N/s", "n_gpus": 1,
@@ -339,7 +351,7 @@ def measure_serving(F, wl, plan, args):
         keys.append(key)
     plans = build_plans(F, keys, {key: plan})
     try:
-        return serving_run(F, plans, keys, 100, (0.8,), 2000)
+        return serving_run(F, plans, keys, 100, (0.8,), 2000, multi=not args.no_multi)
     finally:
         for k, pl in plans.items():
             if pl is not plan:
@@ -444,9 +456,16 @@ def main():
     N, B = wl.N, wl.nrhs
     log("workload %s: d=%d n=%d N=%d nrhs=%d eps=%g" % (wl.name, wl.d, wl.n, N, B, wl.eps))
     t0 = time.perf_counter()
-    # large 2D builds take a while: print their progress
-    plan = F.fio_build(F.make_problem(wl.d, wl.n, wl.phase, eps=wl.eps, c_div=wl.c_div, device=0,
-                                      verbose=1 if wl.N * wl.d >= 2 * 65536 else 0))
+    if args.plan_file and os.path.exists(args.plan_file):
+        plan = F.fio_load(args.plan_file, 0)
+        log("loaded %s in %.1f s" % (args.plan_file, time.perf_counter() - t0))
+    else:
+        # large 2D builds take a while: print their progress
+        plan = F.fio_build(F.make_problem(wl.d, wl.n, wl.phase, eps=wl.eps, c_div=wl.c_div, device=0,
+                                          verbose=1 if wl.N * wl.d >= 2 * 65536 else 0))
+        if args.plan_file:
+            F.fio_save(plan, args.plan_file)
+            log("saved the factors to %s" % args.plan_file)
     build_s = time.perf_counter() - t0
     stats = F.fio_plan_stats(plan)
     log("built in %.1f s: bf_nnz=%d hif_nnz=%d root=%d device_bytes=%.2f GB" % (
@@ -456,6 +475,11 @@ def main():
     U = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()
     X = torch.zeros_like(U)
     stream = torch.cuda.current_stream()
+    if args.plain_only:
+        print(json.dumps({"workload": wl.name, "plain_fp64_single_rhs": plain_fp64(F, torch, plan, U, N, stream)}),
+              flush=True)
+        plan.close()
+        return
 
     if not args.no_tune:
         t0 = time.perf_counter()

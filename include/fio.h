@@ -240,6 +240,38 @@ fio_status fio_solve(fio_plan plan, const fio_solve_opts *opts, fio_dtype dtype,
                      const void *u, void *out, int64_t nrhs, int64_t ld,
                      fio_solve_info *info, void *hip_stream);
 
+/* Several independent solves in one pass: instance i solves K_i fhat = u_i with
+ * plans[i] (plans of any size, dimension and ranks) for nrhs[i] columns; u[i] and
+ * out[i] are complex128 device buffers, column-major N_i x nrhs[i] with leading
+ * dimension ld[i], as for fio_solve.  Every factor level runs as ONE launch for all
+ * instances (section 7: the nodes of a tree level are independent, and so are the
+ * instances): butterfly stage s of every instance's chain, skeletonization step k
+ * of every instance's Gd sweep (counted from the finest level), the top-level
+ * blocks; instances without that level sit it out.  Matrix-core tiles and
+ * persistent-grid caps per level come from fio_multi_autotune for this group (plans
+ * and batch widths), else from heuristics.  The results equal fio_solve's to
+ * rounding (single-stage launches; no fused stage pairs).
+ * opts: FIO_SOLVE_DIRECT, or FIO_SOLVE_REFINE with tol = 0 (maxit steps, no
+ * synchronisation); spatial = 0.  1 <= n_inst <= 8; the plans must be distinct
+ * (each instance uses its plan's workspace) and on one device.  Asynchronous; takes
+ * every plan's lock for the call; capturable in a HIP graph (no allocation when
+ * the workspaces are already sized, see the graph-capture rule above).
+ * Errors: FIO_ERR_ARG, FIO_ERR_UNSUPPORTED (other modes or options). */
+fio_status fio_solve_multi(int n_inst, const fio_plan *plans, const fio_solve_opts *opts, fio_dtype dtype,
+                           const void *const *u, void *const *out, const int64_t *nrhs, const int64_t *ld,
+                           void *hip_stream);
+
+/* Autotuner of a multi-instance group (the plans and batch widths of a
+ * fio_solve_multi call): per butterfly level of Kd^* (dtype) and Kd (complex128) the
+ * matrix-core tiling and the grid (full, or persistent with 1024/2048/4096
+ * workgroups), per skeletonization step the node kernel (fused with 64 or 32
+ * columns, or LDS-staged) and the grid, each timed with HIP events (reps
+ * repetitions) on hip_stream.  Later fio_solve_multi calls with the same plans (in
+ * the same order), widths and dtype use the choices.  Synchronous; uses the plans'
+ * workspaces as scratch.  Errors as fio_solve_multi. */
+fio_status fio_multi_autotune(int n_inst, const fio_plan *plans, fio_dtype dtype, const int64_t *nrhs, int reps,
+                              void *hip_stream);
+
 typedef struct {
     int d, n, L, L_mid;            /* butterfly depth and middle level                 */
     int n_stages;                  /* butterfly stages of one apply (L + 3)            */
@@ -366,7 +398,8 @@ fio_status fio_autotune(fio_plan plan, fio_dtype dtype, int64_t nrhs, int reps, 
 /* Kernel variant used for stage `stage` of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) at
  * this dtype and nrhs: 0 vector kernel, 1..6 matrix-core tilings (16*MT rows x
  * 16*NT columns per wave: 1 MT1xNT4, 2 MT2xNT4, 3 MT1xNT2, 4 MT2xNT2, 5 MT1xNT1,
- * 6 MT2xNT1). */
+ * 6 MT2xNT1), 7 the small-batch kernel (fewer than 16 columns: 64 rows per
+ * workgroup, the k range split over its four waves). */
 fio_status fio_tune_query(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int64_t nrhs,
                           int *variant);
 

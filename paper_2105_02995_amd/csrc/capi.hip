@@ -28,6 +28,7 @@ using namespace fio;
 namespace {
 
 thread_local std::string g_err;
+void forget_multi_tunes(fio_plan p);  // drops the multi-instance tunes that name a plan
 
 // Named ranges of the host-side phases (solve, chains, Gd sweeps and steps,
 // iterations) for a profiler's marker trace, when switched on by fio_set_trace.
@@ -538,15 +539,28 @@ StagePairDev pair_view(fio_plan p, bool fwd, bool dbl, int s) {
     return v;
 }
 
+// Device temporaries of the chain and Gd drivers: the stage ping-pong buffers P, Q
+// (max_coef x nrhs), the GEMM path's temporary HT (N x nrhs) and the FP64 root's
+// gathered rows RI, RO (s0 x nrhs).  The plan's own workspace by default; the
+// no-allocation entry point passes parts of its static scratch array instead.
+struct Ws {
+    void *P, *Q, *HT, *RI, *RO;
+};
+Ws plan_ws(fio_plan p) { return Ws{p->P.p, p->Q.p, p->HT.p, p->RI.p, p->RO.p}; }
+void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nrhs, hipStream_t st, const Ws &ws);
+
 // Run a stage chain: in (first stage's input) -> out (last stage's output).
 void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nrhs, hipStream_t st) {
+    run_chain(p, fwd, dbl, in, out, nrhs, st, plan_ws(p));
+}
+void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nrhs, hipStream_t st, const Ws &ws) {
     TraceRange tr("fio %s chain %s B=%d", fwd ? "Kd" : "Kd*", dbl ? "c128" : "c64", nrhs);
     const auto &hs = fwd ? p->host.fwd : p->adj;
     const auto &ds = fwd ? p->dfwd : p->dadj;
     const std::vector<Launch> sched = chain_schedule(p, fwd, dbl, nrhs);
     const void *cur = in;
     for (size_t j = 0; j < sched.size(); ++j) {
-        void *dst = (j + 1 == sched.size()) ? out : ((j % 2 == 0) ? p->P.p : p->Q.p);
+        void *dst = (j + 1 == sched.size()) ? out : ((j % 2 == 0) ? ws.P : ws.Q);
         const Launch &l = sched[j];
         if (l.count == 2) {
             launch_stage_pair(pair_view(p, fwd, dbl, l.first), dbl, l.variant, cur, dst, nrhs, st);
@@ -566,7 +580,8 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
 // DOFs, 64 or 32 right-hand sides per workgroup (choices 4, 5).  `force` overrides
 // the tuned choice where it applies.
 constexpr int HIF_CHOICES = 6;
-void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int force = -1) {
+void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, const Ws &ws,
+              int force = -1) {
     const HifStepDev h = p->dhif[k].view(dbl);
     int choice = force;
     if ((choice == 4 || choice == 5) && !hif_fused_fits(h)) choice = -1;
@@ -578,45 +593,47 @@ void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStr
         if (nrhs >= 16 && hif_fused_fits(h)) choice = 5;
         else choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
     }
-    if (choice >= 1 && choice <= 3 && nrhs < 16) choice = 0;
     if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
     else if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
-    else launch_hif_gemm_step(h, dbl, up, x, p->HT.p, nrhs, 64 >> (choice - 1), st);
+    else launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, 64 >> (choice - 1), st);
 }
 
 // A_0^{-1} on the remaining DOFs, always in FP64: as a one-block FP64 stage on
 // matrix cores for batches, else the direct kernel.
-void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st) {
+void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, const Ws &ws) {
     if (p->s0 == 0) return;
     if (nrhs < 16 || p->s0 < 64) {
         launch_root((const int32_t *)p->root_idx.p, p->A0inv.p, p->s0, dbl, x, nrhs, st);
         return;
     }
-    launch_rows_gather(x, dbl, (const int32_t *)p->root_idx.p, p->s0, nrhs, p->RI.p, true, st);
+    launch_rows_gather(x, dbl, (const int32_t *)p->root_idx.p, p->s0, nrhs, ws.RI, true, st);
     StageDev s;
     s.n_out = 1; s.n_in = 1; s.r_out = p->s0; s.r_in = p->s0; s.fan = 1;
     s.idx = (const int32_t *)p->root_stage_idx.p;
     s.A = p->A0inv.p;
     const auto *t = p->tuned(dbl, nrhs);
     if (t) s.variant = t->root;
-    launch_stage(s, true, p->RI.p, p->RO.p, nrhs, st);
-    launch_rows_scatter(p->RO.p, true, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
+    launch_stage(s, true, ws.RI, ws.RO, nrhs, st);
+    launch_rows_scatter(ws.RO, true, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
 }
 
-void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, int force = -1) {
+void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, const Ws &ws, int force = -1) {
     TraceRange tr("fio Gd %s B=%d", dbl ? "c128" : "c64", nrhs);
     for (size_t k = 0; k < p->dhif.size(); ++k) {
         TraceRange ts("fio Gd step %zu up", k);
-        hif_step(p, k, dbl, true, x, nrhs, st, force);
+        hif_step(p, k, dbl, true, x, nrhs, st, ws, force);
     }
     {
         TraceRange tr0("fio Gd root");
-        root_apply(p, dbl, x, nrhs, st);
+        root_apply(p, dbl, x, nrhs, st, ws);
     }
     for (size_t k = p->dhif.size(); k-- > 0;) {
         TraceRange ts("fio Gd step %zu down", k);
-        hif_step(p, k, dbl, false, x, nrhs, st, force);
+        hif_step(p, k, dbl, false, x, nrhs, st, ws, force);
     }
+}
+void gd_inplace(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, int force = -1) {
+    gd_inplace(p, dbl, x, nrhs, st, plan_ws(p), force);
 }
 
 // worst = max(worst, v), where a NaN v (a non-finite column) wins, so that the
@@ -847,7 +864,11 @@ fio_status fio_save(fio_plan p, const char *path) {
     });
 }
 
-void fio_destroy(fio_plan p) { delete p; }
+void fio_destroy(fio_plan p) {
+    if (!p) return;
+    forget_multi_tunes(p);
+    delete p;
+}
 
 fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
     return guard([&] {
@@ -1072,7 +1093,8 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                 int best = -1;
                 float best_ms = 1e30f;
                 for (int v = 0; v < STAGE_VARIANTS; ++v) {
-                    if (v > 0 && nr < 8) continue;  // matrix cores need a few columns
+                    if (v > 0 && v != STAGE_SMALL_BATCH && nr < 8) continue;  // matrix cores need a few columns
+                    if (v == STAGE_SMALL_BATCH && nr >= 16) continue;         // for small batches only
                     StageDev sd = ds[s].view(dbl, hs[s]);
                     sd.variant = v;
                     const float ms = timeit([&] { launch_stage(sd, dbl, p->P.p, p->Q.p, nr, st); });
@@ -1115,15 +1137,16 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
         for (size_t k = 0; k < p->dhif.size(); ++k) {
             const HifStepDev h = p->dhif[k].view(dbl);
             int best = 0;
-            if (nr >= 16) {
+            {
                 float best_ms = 1e30f;
-                if (hif_step_fits_lds(h, dbl)) {
+                if (hif_step_fits_lds(h, dbl) || nr < 16) {
                     best_ms = timeit([&] {
                         launch_hif_step(h, dbl, true, p->V2.p, nr, st);
                         launch_hif_step(h, dbl, false, p->V2.p, nr, st);
                     });
                 }
                 for (int c = 1; c <= 3; ++c) {
+                    if (nr <= 16 && c < 3) continue;  // one 16-column tile covers the batch
                     const float ms = timeit([&] {
                         launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, 64 >> (c - 1), st);
                         launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, 64 >> (c - 1), st);
@@ -1152,7 +1175,7 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             sr.A = p->A0inv.p;
             float best_ms = 1e30f;
             launch_scale_zero(p->RI.p, (int64_t)p->s0 * nr, st);
-            for (int v = 1; v < STAGE_VARIANTS; ++v) {
+            for (int v = 1; v < STAGE_SMALL_BATCH; ++v) {
                 sr.variant = v;
                 const float ms = timeit([&] { launch_stage(sr, true, p->RI.p, p->RO.p, nr, st); });
                 if (ms < best_ms) { best_ms = ms; t.root = v; }
@@ -1379,6 +1402,349 @@ int gmres(fio_plan p, const fio_solve_opts *opts, int nr, AC &apply_chain, GD &g
 }
 
 }  // namespace
+
+// ============================================================ multi-instance solves
+namespace {
+
+// One instance of a multi-instance solve: its plan, batch width and user buffers.
+struct Inst {
+    fio_plan p;
+    int nr;
+    const void *u;
+    void *out;
+    int64_t ld;
+};
+
+// Per-level launch choices of a group of instances (autotuned, else heuristic):
+// chain levels of Kd^* (in the solve's dtype) and Kd (complex128), and Gd steps.
+// variant: stage kernel variant (0 vector, 1..6 matrix cores); kind: 0 LDS node
+// kernel, 4/5 fused node kernel; cap: persistent grid cap (0 = full grid).
+struct LevelChoice {
+    int variant = -1, cap = 0;
+};
+struct MultiTune {
+    std::vector<LevelChoice> adj, fwd, hif;
+};
+std::mutex g_multi_mu;
+std::map<std::vector<int64_t>, MultiTune> g_multi_tune;  // key: dtype, (plan id, nrhs)...
+
+std::vector<int64_t> multi_key(const std::vector<Inst> &I, bool dbl) {
+    std::vector<int64_t> k{dbl ? 1 : 0};
+    for (const Inst &i : I) {
+        k.push_back((int64_t)(intptr_t)i.p);
+        k.push_back(i.nr);
+    }
+    return k;
+}
+
+const MultiTune *multi_tuned(const std::vector<Inst> &I, bool dbl) {
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    auto it = g_multi_tune.find(multi_key(I, dbl));
+    return it == g_multi_tune.end() ? nullptr : &it->second;
+}
+
+void forget_multi_tunes(fio_plan p) {
+    std::lock_guard<std::mutex> lk(g_multi_mu);
+    for (auto it = g_multi_tune.begin(); it != g_multi_tune.end();) {
+        bool has = false;
+        for (size_t j = 1; j < it->first.size(); j += 2) has |= it->first[j] == (int64_t)(intptr_t)p;
+        it = has ? g_multi_tune.erase(it) : std::next(it);
+    }
+}
+
+// Stage level j of every instance's chain (Kd if fwd, else Kd^*): one launch for the
+// instances with at least 16 columns (matrix cores), one for the others (vector
+// kernel).  in[i] / out[i]: the chain's input and output of instance i; the
+// instance's own P/Q buffers carry the levels in between.
+void multi_chain(const std::vector<Inst> &I, bool fwd, bool dbl, const std::vector<const void *> &in,
+                 const std::vector<void *> &out, const std::vector<LevelChoice> *tune, hipStream_t st) {
+    int S = 0;
+    for (const Inst &i : I) S = std::max(S, (int)(fwd ? i.p->dfwd : i.p->dadj).size());
+    for (int j = 0; j < S; ++j) {
+        StageDev sv[MULTI_MAX], sm[MULTI_MAX];
+        const void *xv[MULTI_MAX], *xm[MULTI_MAX];
+        void *yv[MULTI_MAX], *ym[MULTI_MAX];
+        int nv[MULTI_MAX], nm[MULTI_MAX], cv = 0, cm = 0;
+        for (size_t k = 0; k < I.size(); ++k) {
+            fio_plan p = I[k].p;
+            const auto &hs = fwd ? p->host.fwd : p->adj;
+            const auto &ds = fwd ? p->dfwd : p->dadj;
+            const int Si = (int)ds.size();
+            if (j >= Si) continue;
+            const void *src = j == 0 ? in[k] : ((j - 1) % 2 == 0 ? p->P.p : p->Q.p);
+            void *dst = j == Si - 1 ? out[k] : (j % 2 == 0 ? p->P.p : p->Q.p);
+            const StageDev v = ds[j].view(dbl, hs[j]);
+            if (I[k].nr >= 16 && v.fan <= 4) { sm[cm] = v; xm[cm] = src; ym[cm] = dst; nm[cm++] = I[k].nr; }
+            else { sv[cv] = v; xv[cv] = src; yv[cv] = dst; nv[cv++] = I[k].nr; }
+        }
+        LevelChoice c;
+        if (tune && j < (int)tune->size()) c = (*tune)[j];
+        if (cm > 0) launch_stage_multi(sm, xm, ym, nm, cm, dbl, c.variant > 0 ? c.variant : (dbl ? 1 : 2), c.cap, st);
+        if (cv > 0) launch_stage_multi(sv, xv, yv, nv, cv, dbl, 0, 0, st);
+    }
+}
+
+// Gd in place on x[i] for every instance: step k of all instances whose sweep has a
+// step k (counted from the finest level) in one launch per node kernel (the fused
+// matrix-core kernel where every node fits it and the instance has 16 or more
+// columns, else the LDS kernel; the gathered-GEMM path, for nodes that fit neither,
+// runs per instance), then the top-level blocks, then the downward steps.
+void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x, const std::vector<LevelChoice> *tune,
+              hipStream_t st) {
+    int K = 0;
+    for (const Inst &i : I) K = std::max(K, (int)i.p->dhif.size());
+    auto step = [&](int k, bool up) {
+        HifStepDev hf[MULTI_MAX], hl[MULTI_MAX];
+        void *xf[MULTI_MAX], *xl[MULTI_MAX];
+        int nf[MULTI_MAX], nl[MULTI_MAX], cf = 0, cl = 0;
+        LevelChoice c;
+        if (tune && k < (int)tune->size()) c = (*tune)[k];
+        const int fkind = c.variant == 4 ? 4 : 5;
+        for (size_t i = 0; i < I.size(); ++i) {
+            fio_plan p = I[i].p;
+            if (k >= (int)p->dhif.size()) continue;
+            const HifStepDev h = p->dhif[k].view(dbl);
+            if (h.n_nodes == 0) continue;
+            const bool fused_ok = I[i].nr >= 16 && hif_fused_fits(h) && c.variant != 0;
+            if (fused_ok) {
+                hf[cf] = h; xf[cf] = x[i]; nf[cf++] = I[i].nr;
+            } else if (hif_step_fits_lds(h, dbl)) {
+                hl[cl] = h; xl[cl] = x[i]; nl[cl++] = I[i].nr;
+            } else if (I[i].nr >= 16) {  // large nodes: the instance's own gathered-GEMM launches
+                const auto *tn = p->tuned(dbl, I[i].nr);
+                const int ch = (tn && k < (int)tn->hif.size() && tn->hif[k] >= 1 && tn->hif[k] <= 3) ? tn->hif[k] : 1;
+                launch_hif_gemm_step(h, dbl, up, x[i], p->HT.p, I[i].nr, 64 >> (ch - 1), st);
+            } else {
+                launch_hif_step(h, dbl, up, x[i], I[i].nr, st);  // node blocks read from memory
+            }
+        }
+        if (cf > 0) launch_hif_multi(hf, xf, nf, cf, dbl, up, fkind, c.cap, st);
+        if (cl > 0) launch_hif_multi(hl, xl, nl, cl, dbl, up, 0, c.cap, st);
+    };
+    for (int k = 0; k < K; ++k) step(k, true);
+    // top-level blocks: the one-block matrix-core stage for wide batches of large
+    // blocks (per instance), the direct kernel for the others (one launch)
+    const int32_t *ri[MULTI_MAX];
+    const void *ra[MULTI_MAX];
+    int rs[MULTI_MAX], rn[MULTI_MAX], cr = 0;
+    void *rx[MULTI_MAX];
+    for (size_t i = 0; i < I.size(); ++i) {
+        fio_plan p = I[i].p;
+        if (p->s0 == 0) continue;
+        if (I[i].nr >= 16 && p->s0 >= 64) {
+            root_apply(p, dbl, x[i], I[i].nr, st, plan_ws(p));
+        } else {
+            ri[cr] = (const int32_t *)p->root_idx.p; ra[cr] = p->A0inv.p; rs[cr] = p->s0; rx[cr] = x[i];
+            rn[cr++] = I[i].nr;
+        }
+    }
+    if (cr > 0) launch_root_multi(ri, ra, rs, rx, rn, cr, dbl, st);
+    for (int k = K - 1; k >= 0; --k) step(k, false);
+}
+
+// The direct or refined solve of every instance, level by level (see fio_solve).
+void multi_solve(const std::vector<Inst> &I, bool dbl, int refine, hipStream_t st) {
+    const size_t n = I.size();
+    const MultiTune *t = multi_tuned(I, dbl);
+    std::vector<const void *> in(n);
+    std::vector<void *> outv(n), xv(n);
+    for (size_t i = 0; i < n; ++i) {
+        fio_plan p = I[i].p;
+        const int32_t *perm = (const int32_t *)p->perm.p;
+        launch_gather(I[i].u, true, I[i].ld, perm, p->U.p, true, p->host.N, I[i].nr, st);
+    }
+    // d = Gd Kd^* r for r (complex128) in `src` of each instance, into V2 (dtype)
+    auto gd_kh = [&](DBuf fio_plan_s::*src) {
+        for (size_t i = 0; i < n; ++i) {
+            fio_plan p = I[i].p;
+            const int64_t cnt = p->host.N * I[i].nr;
+            if (!dbl) launch_convert((p->*src).p, true, p->V3.p, false, cnt, st);
+            in[i] = dbl ? (p->*src).p : p->V3.p;
+            outv[i] = p->V2.p;
+        }
+        multi_chain(I, false, dbl, in, outv, t ? &t->adj : nullptr, st);
+        multi_gd(I, dbl, outv, t ? &t->hif : nullptr, st);
+    };
+    gd_kh(&fio_plan_s::U);
+    for (size_t i = 0; i < n; ++i)
+        launch_convert(I[i].p->V2.p, dbl, I[i].p->X.p, true, I[i].p->host.N * I[i].nr, st);  // x0
+    for (int it = 0; it < refine; ++it) {
+        for (size_t i = 0; i < n; ++i) {
+            in[i] = I[i].p->X.p;
+            xv[i] = I[i].p->V1.p;
+        }
+        multi_chain(I, true, true, in, xv, t ? &t->fwd : nullptr, st);  // Kd x, FP64
+        for (size_t i = 0; i < n; ++i)
+            launch_residual(I[i].p->U.p, I[i].p->V1.p, I[i].p->R.p, true, I[i].p->host.N * I[i].nr, st);
+        gd_kh(&fio_plan_s::R);
+        for (size_t i = 0; i < n; ++i)
+            launch_axpy_update(I[i].p->X.p, I[i].p->V2.p, dbl, I[i].p->host.N * I[i].nr, st);
+    }
+    for (size_t i = 0; i < n; ++i) {
+        fio_plan p = I[i].p;
+        launch_scatter(p->X.p, true, (const int32_t *)p->perm.p, I[i].out, true, I[i].ld, p->host.N, I[i].nr, st);
+    }
+}
+
+// Validates a multi-instance call, takes every plan's lock (in address order) and
+// sizes the workspaces.
+struct MultiLock {
+    std::vector<std::unique_lock<std::mutex>> locks;
+};
+std::vector<Inst> multi_setup(int n_inst, const fio_plan *plans, const void *const *u, void *const *out,
+                              const int64_t *nrhs, const int64_t *ld, hipStream_t st, MultiLock &ml) {
+    if (n_inst < 1 || n_inst > MULTI_MAX) fail(FIO_ERR_ARG, "n_inst must be 1.." + std::to_string(MULTI_MAX));
+    if (!plans || !nrhs || !ld || (u == nullptr) != (out == nullptr)) fail(FIO_ERR_ARG, "null argument");
+    std::vector<Inst> I;
+    for (int i = 0; i < n_inst; ++i) {
+        fio_plan p = plans[i];
+        check_apply_args(p, nrhs[i], ld[i], u ? u[i] : (const void *)1, out ? out[i] : (void *)1);
+        if (nrhs[i] < 1) fail(FIO_ERR_ARG, "every instance needs at least one column");
+        if (p->device != plans[0]->device) fail(FIO_ERR_ARG, "all plans must be on one device");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == p) fail(FIO_ERR_ARG, "a plan appears twice (each instance uses its plan's workspace)");
+        I.push_back(Inst{p, (int)nrhs[i], u ? u[i] : nullptr, out ? out[i] : nullptr, ld[i]});
+    }
+    std::vector<fio_plan> order(plans, plans + n_inst);
+    std::sort(order.begin(), order.end());
+    for (fio_plan p : order) ml.locks.emplace_back(p->mu);
+    HIPC(hipSetDevice(plans[0]->device));
+    for (const Inst &i : I) ensure_ws(i.p, i.nr, st);
+    return I;
+}
+
+}  // namespace
+
+extern "C" {
+
+fio_status fio_solve_multi(int n_inst, const fio_plan *plans, const fio_solve_opts *opts, fio_dtype dt,
+                           const void *const *u, void *const *out, const int64_t *nrhs, const int64_t *ld,
+                           void *stream) {
+    return guard([&] {
+        TraceRange tr("fio solve multi %d", n_inst);
+        if (!opts || !u || !out) fail(FIO_ERR_ARG, "null argument");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (opts->mode != FIO_SOLVE_DIRECT && opts->mode != FIO_SOLVE_REFINE)
+            fail(FIO_ERR_UNSUPPORTED, "multi-instance solves run DIRECT or REFINE");
+        if (opts->tol != 0 || opts->spatial)
+            fail(FIO_ERR_UNSUPPORTED, "multi-instance solves run a fixed number of steps (tol = 0), fhat output");
+        if (opts->maxit < 0) fail(FIO_ERR_ARG, "bad iteration settings");
+        hipStream_t st = (hipStream_t)stream;
+        MultiLock ml;
+        const std::vector<Inst> I = multi_setup(n_inst, plans, u, out, nrhs, ld, st, ml);
+        multi_solve(I, dt == FIO_C128, opts->mode == FIO_SOLVE_REFINE ? opts->maxit : 0, st);
+    });
+}
+
+fio_status fio_multi_autotune(int n_inst, const fio_plan *plans, fio_dtype dt, const int64_t *nrhs, int reps,
+                              void *stream) {
+    return guard([&] {
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (reps < 1) reps = 3;
+        hipStream_t st = (hipStream_t)stream;
+        std::vector<int64_t> ld(n_inst > 0 ? n_inst : 1);
+        for (int i = 0; i < n_inst && plans; ++i) ld[i] = plans[i] ? plans[i]->host.N : 0;
+        MultiLock ml;
+        const std::vector<Inst> I = multi_setup(n_inst, plans, nullptr, nullptr, nrhs, ld.data(), st, ml);
+        const bool dbl = dt == FIO_C128;
+        const bool vb = I[0].p->host.prob.verbose != 0;
+        for (const Inst &i : I) {  // defined inputs for the timed launches
+            launch_scale_zero(i.p->P.p, i.p->max_coef * i.nr, st);
+            launch_scale_zero(i.p->Q.p, i.p->max_coef * i.nr, st);
+            launch_scale_zero(i.p->V2.p, i.p->host.N * i.nr, st);
+            launch_scale_zero(i.p->X.p, i.p->host.N * i.nr, st);
+        }
+        hipEvent_t e0, e1;
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        auto timeit = [&](auto &&fn) {
+            fn();
+            HIPC(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) fn();
+            HIPC(hipEventRecord(e1, st));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            return ms;
+        };
+        const int caps[] = {0, 4096, 2048, 1024};
+        MultiTune t;
+        // chain levels: every matrix-core tiling and grid cap, one level at a time
+        for (int chain = 0; chain < 2; ++chain) {
+            const bool fwd = chain == 0;
+            const bool cdbl = fwd ? true : dbl;  // Kd runs in FP64 (the residual), Kd^* in dtype
+            std::vector<LevelChoice> &out = fwd ? t.fwd : t.adj;
+            int S = 0;
+            for (const Inst &i : I) S = std::max(S, (int)(fwd ? i.p->dfwd : i.p->dadj).size());
+            std::vector<const void *> in(I.size());
+            std::vector<void *> ov(I.size());
+            for (int j = 0; j < S; ++j) {
+                LevelChoice best;
+                float best_ms = 1e30f;
+                for (int v = 1; v < STAGE_SMALL_BATCH; ++v)
+                    for (int cap : caps) {
+                        std::vector<LevelChoice> one(S);
+                        one[j] = LevelChoice{v, cap};
+                        // the level alone: instances whose chain has it, P -> Q
+                        const float ms = timeit([&] {
+                            StageDev sm[MULTI_MAX];
+                            const void *xm[MULTI_MAX];
+                            void *ym[MULTI_MAX];
+                            int nm[MULTI_MAX], cm = 0;
+                            for (const Inst &i : I) {
+                                const auto &hs = fwd ? i.p->host.fwd : i.p->adj;
+                                const auto &ds = fwd ? i.p->dfwd : i.p->dadj;
+                                if (j >= (int)ds.size() || i.nr < 16) continue;
+                                sm[cm] = ds[j].view(cdbl, hs[j]);
+                                xm[cm] = i.p->P.p; ym[cm] = i.p->Q.p; nm[cm++] = i.nr;
+                            }
+                            if (cm > 0) launch_stage_multi(sm, xm, ym, nm, cm, cdbl, v, cap, st);
+                        });
+                        if (ms < best_ms) { best_ms = ms; best = LevelChoice{v, cap}; }
+                    }
+                out.push_back(best);
+                progress(vb, "multi tune %s level %d: variant %d cap %d %.4f ms", fwd ? "Kd c128" : "Kd^*", j,
+                         best.variant, best.cap, best_ms / reps);
+            }
+        }
+        // Gd steps: the fused kernel (64 or 32 columns) or the LDS kernel, grid caps
+        int K = 0;
+        for (const Inst &i : I) K = std::max(K, (int)i.p->dhif.size());
+        for (int k = 0; k < K; ++k) {
+            LevelChoice best{5, 0};
+            float best_ms = 1e30f;
+            for (int kind : {4, 5, 0})
+                for (int cap : caps) {
+                    HifStepDev hs[MULTI_MAX];
+                    void *xs[MULTI_MAX];
+                    int ns[MULTI_MAX], c = 0;
+                    bool ok = true;
+                    for (const Inst &i : I) {
+                        if (k >= (int)i.p->dhif.size() || i.p->dhif[k].base.n_nodes == 0) continue;
+                        hs[c] = i.p->dhif[k].view(dbl);
+                        if (kind != 0 && (i.nr < 16 || !hif_fused_fits(hs[c]))) { ok = false; break; }
+                        if (kind == 0 && !hif_step_fits_lds(hs[c], dbl)) { ok = false; break; }
+                        xs[c] = i.p->V2.p; ns[c++] = i.nr;
+                    }
+                    if (!ok || c == 0) continue;
+                    const float ms = timeit([&] {
+                        launch_hif_multi(hs, xs, ns, c, dbl, true, kind, cap, st);
+                        launch_hif_multi(hs, xs, ns, c, dbl, false, kind, cap, st);
+                    });
+                    if (ms < best_ms) { best_ms = ms; best = LevelChoice{kind, cap}; }
+                }
+            t.hif.push_back(best);
+            progress(vb, "multi tune Gd step %d: kind %d cap %d %.4f ms", k, best.variant, best.cap,
+                     best_ms < 1e29f ? best_ms / reps : 0.f);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        std::lock_guard<std::mutex> lk(g_multi_mu);
+        g_multi_tune[multi_key(I, dbl)] = std::move(t);
+    });
+}
+
+}  // extern "C"
 
 extern "C" {
 

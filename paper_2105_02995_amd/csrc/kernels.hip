@@ -73,26 +73,120 @@ static unsigned grid_for(int64_t work, int block) {
 // One thread per output entry (o, a, b), b fastest: the factor entry is shared by
 // the nrhs lanes of one row and the gathered input is read coalesced across b.
 template <class T>
+__device__ __forceinline__ T stage_entry(int r_out, int r_in, int fan, const int32_t *__restrict__ idx,
+                                         const T *__restrict__ A, const T *__restrict__ x, int nrhs, int64_t t) {
+    const int b = (int)(t % nrhs);
+    const int64_t t2 = t / nrhs;
+    const int a = (int)(t2 % r_out);
+    const int64_t o = t2 / r_out;
+    const T *Ao = A + o * (int64_t)r_out * fan * r_in + a;
+    T acc = cz(T());
+    for (int q = 0; q < fan; ++q) {
+        const T *xin = x + (int64_t)idx[o * fan + q] * r_in * nrhs + b;
+        const T *Aq = Ao + (int64_t)q * r_in * r_out;
+        for (int e = 0; e < r_in; ++e) acc = cfma(acc, Aq[(int64_t)e * r_out], xin[(int64_t)e * nrhs]);
+    }
+    return acc;
+}
+
+template <class T>
 __global__ void __launch_bounds__(256) k_stage(int64_t n_out, int r_out, int r_in, int fan,
                                                const int32_t *__restrict__ idx,
                                                const T *__restrict__ A, const T *__restrict__ x,
                                                T *__restrict__ y, int nrhs) {
     const int64_t total = n_out * r_out * (int64_t)nrhs;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int b = (int)(t % nrhs);
-        const int64_t t2 = t / nrhs;
-        const int a = (int)(t2 % r_out);
-        const int64_t o = t2 / r_out;
-        const T *Ao = A + o * (int64_t)r_out * fan * r_in + a;
-        T acc = cz(T());
-        for (int q = 0; q < fan; ++q) {
-            const T *xin = x + (int64_t)idx[o * fan + q] * r_in * nrhs + b;
-            const T *Aq = Ao + (int64_t)q * r_in * r_out;
-            for (int e = 0; e < r_in; ++e) acc = cfma(acc, Aq[(int64_t)e * r_out], xin[(int64_t)e * nrhs]);
+         t += (int64_t)gridDim.x * blockDim.x)
+        y[t] = stage_entry(r_out, r_in, fan, idx, A, x, nrhs, t);
+}
+
+// Small batches (fewer than 16 right-hand sides), bound by the factor bytes: a
+// workgroup takes 64 rows of one output block (one row per lane) and NB right-hand
+// sides; its four waves split the block's k range in four, so every wave streams a
+// quarter of the block's columns with coalesced 64-row loads, U k-steps of loads
+// issued before their products (the gathered input entries are the same for all
+// lanes: one broadcast load each), and the four partial sums meet in LDS.
+template <class T, int NB>
+__global__ void __launch_bounds__(256) k_stage_nb(int64_t n_out, int r_out, int r_in, int fan,
+                                                  const int32_t *__restrict__ idx, const T *__restrict__ A,
+                                                  const T *__restrict__ x, T *__restrict__ y, int nrhs,
+                                                  int rchunks) {
+    constexpr int U = NB <= 2 ? 8 : (NB == 4 ? 4 : 2);
+    __shared__ T red[3 * 64 * NB];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t o = blockIdx.x / rchunks;
+    const int a = (int)(blockIdx.x - o * rchunks) * 64 + lane;
+    const int ac = min(a, r_out - 1);
+    const int c0 = blockIdx.y * NB;
+    const int K = fan * r_in;
+    const int kb = (K * w) >> 2, ke = (K * (w + 1)) >> 2;
+    int cj[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) cj[j] = min(c0 + j, nrhs - 1);
+    T acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = cz(T());
+    const T *Ao = A + o * (int64_t)r_out * K + ac;
+    for (int k = kb; k < ke;) {
+        const int q = k / r_in;
+        const int kq = min(ke, (q + 1) * r_in);   // end of input block q in this wave's range
+        // row of x for column k of the block: idx[q] * r_in + (k - q * r_in)
+        const T *xr = x + ((int64_t)idx[o * fan + q] * r_in - (int64_t)q * r_in) * nrhs;
+        for (; k + U <= kq; k += U) {
+            T av[U], xv[U][NB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) av[u] = Ao[(int64_t)(k + u) * r_out];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) xv[u][j] = xr[(int64_t)(k + u) * nrhs + cj[j]];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = cfma(acc[j], av[u], xv[u][j]);
         }
-        y[t] = acc;
+        for (; k < kq; ++k) {
+            const T av = Ao[(int64_t)k * r_out];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = cfma(acc[j], av, xr[(int64_t)k * nrhs + cj[j]]);
+        }
     }
+    if (w > 0) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) red[((w - 1) * 64 + lane) * NB + j] = acc[j];
+    }
+    __syncthreads();
+    if (w == 0 && a < r_out) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            T s = acc[j];
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const T t = red[(v * 64 + lane) * NB + j];
+                s.x += t.x;
+                s.y += t.y;
+            }
+            if (c0 + j < nrhs) y[(o * r_out + a) * (int64_t)nrhs + c0 + j] = s;
+        }
+    }
+}
+
+template <class T, int NB>
+static void stage_nb_go(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+    const int rchunks = (s.r_out + 63) / 64;
+    const int64_t nb = s.n_out * rchunks;
+    if (nb >= ((int64_t)1 << 31)) throw std::runtime_error("stage launch exceeds the grid limit");
+    const dim3 g((unsigned)nb, (unsigned)((nrhs + NB - 1) / NB));
+    hipLaunchKernelGGL((k_stage_nb<T, NB>), g, dim3(256), 0, st, s.n_out, s.r_out, s.r_in, s.fan, s.idx,
+                       (const T *)s.A, (const T *)x, (T *)y, nrhs, rchunks);
+}
+
+template <class T>
+static void launch_stage_nb(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+    if (nrhs <= 1) stage_nb_go<T, 1>(s, x, y, nrhs, st);
+    else if (nrhs <= 2) stage_nb_go<T, 2>(s, x, y, nrhs, st);
+    else if (nrhs <= 4) stage_nb_go<T, 4>(s, x, y, nrhs, st);
+    else stage_nb_go<T, 8>(s, x, y, nrhs, st);
 }
 
 // Batched stage on matrix cores.  One wave computes 16*MT rows of one output
@@ -289,19 +383,19 @@ static unsigned xcd_grid(int64_t nb, int nch) {
     return (unsigned)(per * N_XCD);
 }
 
+// One workgroup's work of a stage launch: workgroup wg of the (output block, row
+// chunk) waves, column chunk `chunk`.  Shared by the single-instance kernel and the
+// multi-instance one.
 template <class R, int MT, int NT>
-__global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
-                                                    const int32_t *__restrict__ idx,
-                                                    const typename MF<R>::C *__restrict__ A,
-                                                    const typename MF<R>::C *__restrict__ x,
-                                                    typename MF<R>::C *__restrict__ y, int nrhs,
-                                                    int mchunks, int nchunks) {
+__device__ __forceinline__ void stage_mfma_wg(int64_t n_out, int r_out, int r_in, int fan,
+                                              const int32_t *__restrict__ idx,
+                                              const typename MF<R>::C *__restrict__ A,
+                                              const typename MF<R>::C *__restrict__ x,
+                                              typename MF<R>::C *__restrict__ y, int nrhs, int mchunks,
+                                              int64_t wg, int chunk) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
     const int lane = threadIdx.x & 63;
-    int64_t wg;
-    int chunk;
-    xcd_order((n_out * mchunks + 3) / 4, nchunks, wg, chunk);
     const int64_t wave = wg * 4 + (threadIdx.x >> 6);
     if (wave >= n_out * mchunks) return;  // wave-uniform
     const int64_t o = wave / mchunks;
@@ -326,6 +420,19 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
                 if (row < r_out && col < nrhs)
                     y[(o * r_out + row) * (int64_t)nrhs + col] = acc.get(mt, nt, v);
             }
+}
+
+template <class R, int MT, int NT>
+__global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
+                                                    const int32_t *__restrict__ idx,
+                                                    const typename MF<R>::C *__restrict__ A,
+                                                    const typename MF<R>::C *__restrict__ x,
+                                                    typename MF<R>::C *__restrict__ y, int nrhs,
+                                                    int mchunks, int nchunks) {
+    int64_t wg;
+    int chunk;
+    xcd_order((n_out * mchunks + 3) / 4, nchunks, wg, chunk);
+    stage_mfma_wg<R, MT, NT>(n_out, r_out, r_in, fan, idx, A, x, y, nrhs, mchunks, wg, chunk);
 }
 
 // Two consecutive stages a, b in one launch.  The blocks of two consecutive
@@ -510,7 +617,7 @@ static const int MFMA_MIN_RHS = 16;
 //   0 vector kernel; 1..6 matrix cores with MT row tiles and NT 16-column tiles
 //   (1: MT1 NT4, 2: MT2 NT4, 3: MT1 NT2, 4: MT2 NT2, 5: MT1 NT1, 6: MT2 NT1).
 int stage_default_variant(const StageDev &s, bool dbl, int nrhs) {
-    if (nrhs < MFMA_MIN_RHS) return 0;
+    if (nrhs < MFMA_MIN_RHS) return s.r_out >= 48 ? STAGE_SMALL_BATCH : 0;
     const int mtiles = (s.r_out + 15) / 16;
     if (dbl || mtiles < 2) return 1;
     return 2;
@@ -532,7 +639,14 @@ static void launch_variant(int v, const StageDev &s, const void *x, void *y, int
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st) {
     int v = (s.variant >= 0) ? s.variant : stage_default_variant(s, dbl, nrhs);
     // the matrix-core kernels walk at most four input blocks of at least one row
-    if (s.fan > 4 || s.r_in < 1 || s.r_out < 1) v = 0;
+    if ((s.fan > 4 || s.r_in < 1 || s.r_out < 1) && v != STAGE_SMALL_BATCH) v = 0;
+    if (s.r_in < 1 || s.r_out < 1) v = 0;
+    if (v == STAGE_SMALL_BATCH) {
+        if (dbl) launch_stage_nb<double2>(s, x, y, nrhs, st);
+        else launch_stage_nb<float2>(s, x, y, nrhs, st);
+        check_launch("stage (small batch)");
+        return;
+    }
     if (v > 0) {
         if (dbl) launch_variant<double>(v, s, x, y, nrhs, st);
         else launch_variant<float>(v, s, x, y, nrhs, st);
@@ -616,13 +730,11 @@ void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void 
 // transformed, and scattered back.  Nodes of one step own disjoint index sets,
 // so workgroups never touch the same entries of x.
 template <class T, bool UP, bool STAGED>
-__global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
-                                             const int32_t *__restrict__ idx,
-                                             const T *__restrict__ mat, T *__restrict__ x,
-                                             int nrhs, int bchunk) {
+__device__ __forceinline__ void hif_node(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                         const T *__restrict__ mat, T *__restrict__ x, int nrhs, int bchunk,
+                                         int64_t v, int ychunk) {
     extern __shared__ char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
-    const int64_t v = blockIdx.x;
     const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
     const int32_t *ir = idx + desc[4 * v + 2];
     const int32_t *is = ir + nr;
@@ -641,7 +753,7 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
     Li = Tm + (int64_t)ns * nr;  // nr x nr (lower)
     Mm = Li + (int64_t)nr * nr;  // ns x nr
     {
-        const int b0 = blockIdx.y * bchunk;
+        const int b0 = ychunk * bchunk;
         const int bc = min(bchunk, nrhs - b0);
         T *xr = work, *xs = work + nr * bc, *y = xs + ns * bc;
         for (int e = threadIdx.x; e < (nr + ns) * bc; e += blockDim.x) {
@@ -716,6 +828,14 @@ __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
         }
         __syncthreads();
     }
+}
+
+template <class T, bool UP, bool STAGED>
+__global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
+                                             const int32_t *__restrict__ idx,
+                                             const T *__restrict__ mat, T *__restrict__ x,
+                                             int nrhs, int bchunk) {
+    hif_node<T, UP, STAGED>(desc, idx, mat, x, nrhs, bchunk, blockIdx.x, blockIdx.y);
 }
 
 // LDS one workgroup may use: the device's opt-in limit (160 KiB per CU on
@@ -1141,18 +1261,17 @@ __device__ __forceinline__ void hf_sub_cols(const typename MF<R>::V4 (&re)[4], c
 }
 
 template <class R, bool UP, int NTW>
-__global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
-                                                   const typename MF<R>::C *__restrict__ mat,
-                                                   const typename MF<R>::C *__restrict__ matH,
-                                                   typename MF<R>::C *__restrict__ x, int nrhs, int rows_r,
-                                                   int rows_s) {
+__device__ __forceinline__ void hif_fused_node(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                               const typename MF<R>::C *__restrict__ mat,
+                                               const typename MF<R>::C *__restrict__ matH,
+                                               typename MF<R>::C *__restrict__ x, int nrhs, int rows_r, int rows_s,
+                                               int64_t v, int ychunk) {
     using C = typename MF<R>::C;
     using V4 = typename MF<R>::V4;
     constexpr int CW = 16 * NTW, LD = CW + 4;   // columns per workgroup, LDS row stride
     extern __shared__ char smem_raw[];
     C *Xr = reinterpret_cast<C *>(smem_raw);   // rows_r x LD
     C *Xs = Xr + (int64_t)rows_r * LD;         // rows_s x LD
-    const int64_t v = blockIdx.x;
     const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
     const int32_t *ir = idx + desc[4 * v + 2];
     const int32_t *is = ir + nr;
@@ -1161,7 +1280,7 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
     const C *TH = matH + mo, *LH = TH + (int64_t)ns * nr, *MH = LH + (int64_t)nr * nr;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int w = threadIdx.x >> 6, col0 = 16 * w;
-    const int b0 = blockIdx.y * CW;
+    const int b0 = ychunk * CW;
     const int bc = min(CW, nrhs - b0);
     const int ntl = (bc + 15) >> 4;   // column tiles holding columns
     // the node's row indices (x_r rows, then x_s rows) in LDS, one load per thread
@@ -1216,6 +1335,15 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
         for (int i = lk; i < nr; i += 4) x[(int64_t)gidx[i] * nrhs + cc] = Xr[i * LD + col0 + li];
         for (int i = lk; i < ns; i += 4) x[(int64_t)gidx[rows_r + i] * nrhs + cc] = Xs[i * LD + col0 + li];
     }
+}
+
+template <class R, bool UP, int NTW>
+__global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                                   const typename MF<R>::C *__restrict__ mat,
+                                                   const typename MF<R>::C *__restrict__ matH,
+                                                   typename MF<R>::C *__restrict__ x, int nrhs, int rows_r,
+                                                   int rows_s) {
+    hif_fused_node<R, UP, NTW>(desc, idx, mat, matH, x, nrhs, rows_r, rows_s, blockIdx.x, blockIdx.y);
 }
 
 bool hif_fused_fits(const HifStepDev &h) { return h.max_nr <= 64 && h.max_ns <= 64; }
@@ -1708,6 +1836,280 @@ void launch_inverse_dft(const void *fhat, int64_t ld, void *f, int d, int n, int
         check_launch("inverse DFT pass");
     }
     launch_scatter(a, true, nullptr, f, true, ld, N, nrhs, st);
+}
+
+
+// ------------------------------------------------------------------ multi-instance launches
+// One launch runs the same factor level of several instances (plans of different
+// sizes, ranks and batch widths): stage s of each instance's chain, or step k of
+// each instance's Gd sweep.  The instances travel by value in the kernel arguments;
+// a workgroup finds its instance from the prefix of workgroup counts (`wg0`).  With
+// a grid cap the launch is persistent: a fixed grid (a multiple of the eight XCDs)
+// walks the whole work list, each workgroup staying on its XCD.
+//
+// Instance fields are read with compile-time indices (a select over the unrolled
+// list), so the argument block is never copied to private memory.
+template <class A> __device__ __forceinline__ A pick_inst(const A (&in)[MULTI_MAX], int n, int64_t lid) {
+    A r = in[0];
+#pragma unroll
+    for (int j = 1; j < MULTI_MAX; ++j)
+        if (j < n && lid >= in[j].wg0) r = in[j];
+    return r;
+}
+
+// Logical workgroup ids of a (possibly persistent) launch over `total` workgroups,
+// in the XCD-contiguous order of xcd_order: the loop visits this workgroup's ids.
+#define FOR_EACH_WG(total, lid)                                                            \
+    for (int64_t id_ = blockIdx.x, per_ = ((total) + N_XCD - 1) / N_XCD; id_ < per_ * N_XCD; \
+         id_ += gridDim.x)                                                                 \
+        for (int64_t lid = (id_ % N_XCD) * per_ + id_ / N_XCD; lid < (total); lid = (total))
+
+template <class R, int MT, int NT>
+__global__ void __launch_bounds__(256) k_stage_mfma_multi(const StageMultiArgs a) {
+    using C = typename MF<R>::C;
+    FOR_EACH_WG(a.total, lid) {
+        const StageInstDev s = pick_inst(a.in, a.n, lid);
+        const int64_t l = lid - s.wg0;
+        stage_mfma_wg<R, MT, NT>(s.n_out, s.r_out, s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)s.x,
+                                 (C *)s.y, s.nrhs, s.mchunks, l / s.nch, (int)(l % s.nch));
+    }
+}
+
+// Vector kernel: wg0 counts output entries (n_out * r_out * nrhs per instance).
+template <class T>
+__global__ void __launch_bounds__(256) k_stage_vec_multi(const StageMultiArgs a) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < a.total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const StageInstDev s = pick_inst(a.in, a.n, t);
+        const int64_t l = t - s.wg0;
+        ((T *)s.y)[l] = stage_entry(s.r_out, s.r_in, s.fan, s.idx, (const T *)s.A, (const T *)s.x, s.nrhs, l);
+    }
+}
+
+template <class T, bool UP, bool STAGED>
+__global__ void __launch_bounds__(256) k_hif_multi(const HifMultiArgs a) {
+    FOR_EACH_WG(a.total, lid) {
+        const HifInstDev s = pick_inst(a.in, a.n, lid);
+        const int64_t l = lid - s.wg0;
+        hif_node<T, UP, STAGED>(s.desc, s.idx, (const T *)s.mat, (T *)s.x, s.nrhs, s.bchunk, l / s.nch,
+                                (int)(l % s.nch));  // ends with a barrier
+    }
+}
+
+template <class R, bool UP, int NTW>
+__global__ void __launch_bounds__(256) k_hif_fused_multi(const HifMultiArgs a) {
+    using C = typename MF<R>::C;
+    FOR_EACH_WG(a.total, lid) {
+        const HifInstDev s = pick_inst(a.in, a.n, lid);
+        const int64_t l = lid - s.wg0;
+        hif_fused_node<R, UP, NTW>(s.desc, s.idx, (const C *)s.mat, (const C *)s.matH, (C *)s.x, s.nrhs, s.rows_r,
+                                   s.rows_s, l / s.nch, (int)(l % s.nch));
+        __syncthreads();  // the next node's staging overwrites this one's LDS
+    }
+}
+
+// Top-level blocks: one workgroup per (instance, right-hand side), as k_root.
+template <class T>
+__global__ void __launch_bounds__(256) k_root_multi(const RootMultiArgs a) {
+    extern __shared__ char smem_raw[];
+    double2 *v = reinterpret_cast<double2 *>(smem_raw);
+    for (int64_t lid = blockIdx.x; lid < a.total; lid += gridDim.x) {
+        const RootInstDev s = pick_inst(a.in, a.n, lid);
+        const int b = (int)(lid - s.wg0);
+        T *x = (T *)s.x;
+        for (int i = threadIdx.x; i < s.s0; i += blockDim.x) v[i] = cvt<double2, T>(x[(int64_t)s.idx[i] * s.nrhs + b]);
+        __syncthreads();
+        for (int i = threadIdx.x; i < s.s0; i += blockDim.x) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int k = 0; k < s.s0; ++k) acc = cfma(acc, s.A[i + (int64_t)k * s.s0], v[k]);
+            x[(int64_t)s.idx[i] * s.nrhs + b] = cvt<T, double2>(acc);
+        }
+        __syncthreads();
+    }
+}
+
+static unsigned multi_grid(int64_t total, int grid_cap) {
+    const int64_t per = (total + N_XCD - 1) / N_XCD;
+    int64_t g = per * N_XCD;
+    if (grid_cap > 0) g = std::min<int64_t>(g, std::max(N_XCD, grid_cap / N_XCD * N_XCD));
+    if (g >= ((int64_t)1 << 31)) throw std::runtime_error("multi-instance launch exceeds the grid limit");
+    return (unsigned)std::max<int64_t>(1, g);
+}
+
+template <class R, int MT, int NT>
+static void stage_multi_go(StageMultiArgs &a, const StageDev *s, int grid_cap, hipStream_t st) {
+    int64_t wg = 0;
+    for (int i = 0; i < a.n; ++i) {
+        StageInstDev &d = a.in[i];
+        d.mchunks = ((s[i].r_out + 15) / 16 + MT - 1) / MT;
+        d.nch = (d.nrhs + 16 * NT - 1) / (16 * NT);
+        d.wg0 = wg;
+        wg += (d.n_out * d.mchunks + 3) / 4 * d.nch;
+    }
+    a.total = wg;
+    hipLaunchKernelGGL((k_stage_mfma_multi<R, MT, NT>), dim3(multi_grid(wg, grid_cap)), dim3(256), 0, st, a);
+}
+
+template <class R>
+static void stage_multi_variant(int v, StageMultiArgs &a, const StageDev *s, int cap, hipStream_t st) {
+    switch (v) {
+        case 1: stage_multi_go<R, 1, 4>(a, s, cap, st); break;
+        case 2: stage_multi_go<R, 2, 4>(a, s, cap, st); break;
+        case 3: stage_multi_go<R, 1, 2>(a, s, cap, st); break;
+        case 4: stage_multi_go<R, 2, 2>(a, s, cap, st); break;
+        case 5: stage_multi_go<R, 1, 1>(a, s, cap, st); break;
+        default: stage_multi_go<R, 2, 1>(a, s, cap, st); break;
+    }
+}
+
+void launch_stage_multi(const StageDev *s, const void *const *x, void *const *y, const int *nrhs, int n, bool dbl,
+                        int variant, int grid_cap, hipStream_t st) {
+    if (n < 1 || n > MULTI_MAX) throw std::runtime_error("multi-instance stage: 1..MULTI_MAX instances");
+    StageMultiArgs a{};
+    a.n = n;
+    bool mfma_ok = variant > 0;
+    for (int i = 0; i < n; ++i) {
+        StageInstDev &d = a.in[i];
+        d.idx = s[i].idx; d.A = s[i].A; d.x = x[i]; d.y = y[i];
+        d.n_out = s[i].n_out; d.r_out = s[i].r_out; d.r_in = s[i].r_in; d.fan = s[i].fan; d.nrhs = nrhs[i];
+        if (s[i].fan > 4 || s[i].r_in < 1 || s[i].r_out < 1) mfma_ok = false;
+    }
+    if (mfma_ok) {
+        if (dbl) stage_multi_variant<double>(variant, a, s, grid_cap, st);
+        else stage_multi_variant<float>(variant, a, s, grid_cap, st);
+        check_launch("multi-instance stage (matrix cores)");
+        return;
+    }
+    int64_t e = 0;
+    for (int i = 0; i < n; ++i) {
+        a.in[i].wg0 = e;
+        e += s[i].n_out * s[i].r_out * (int64_t)nrhs[i];
+    }
+    a.total = e;
+    const unsigned g = grid_for(e, 256);
+    if (dbl) hipLaunchKernelGGL(k_stage_vec_multi<double2>, dim3(g), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(k_stage_vec_multi<float2>, dim3(g), dim3(256), 0, st, a);
+    check_launch("multi-instance stage");
+}
+
+template <class T, bool UP, bool ST>
+static void hif_multi_go(const HifMultiArgs &a, size_t lds, int grid_cap, hipStream_t st) {
+    static std::once_flag attr_once;  // plans may be used from several host threads
+    std::call_once(attr_once, [] {
+        (void)hipFuncSetAttribute((const void *)k_hif_multi<T, UP, ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  hif_lds_budget());
+    });
+    hipLaunchKernelGGL((k_hif_multi<T, UP, ST>), dim3(multi_grid(a.total, grid_cap)), dim3(256), lds, st, a);
+}
+
+template <class R, bool UP, int NTW>
+static void hif_fused_multi_go(const HifMultiArgs &a, size_t lds, int grid_cap, hipStream_t st) {
+    static std::once_flag attr_once;  // plans may be used from several host threads
+    std::call_once(attr_once, [] {
+        (void)hipFuncSetAttribute((const void *)k_hif_fused_multi<R, UP, NTW>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
+    });
+    hipLaunchKernelGGL((k_hif_fused_multi<R, UP, NTW>), dim3(multi_grid(a.total, grid_cap)), dim3(256), lds, st, a);
+}
+
+bool hif_multi_fits(const HifStepDev *h, int n, bool dbl, int kind) {
+    for (int i = 0; i < n; ++i) {
+        if (h[i].n_nodes == 0) continue;
+        if (kind == 0 ? !hif_step_fits_lds(h[i], dbl) : !hif_fused_fits(h[i])) return false;
+    }
+    return true;
+}
+
+void launch_hif_multi(const HifStepDev *h, void *const *x, const int *nrhs, int n, bool dbl, bool up, int kind,
+                      int grid_cap, hipStream_t st) {
+    if (n < 1 || n > MULTI_MAX) throw std::runtime_error("multi-instance step: 1..MULTI_MAX instances");
+    if (!hif_multi_fits(h, n, dbl, kind)) throw std::runtime_error("multi-instance step: a node does not fit");
+    HifMultiArgs a{};
+    a.n = n;
+    const int elt = dbl ? 16 : 8;
+    const int64_t HIF_LDS = hif_lds_budget();
+    int64_t wg = 0;
+    size_t lds = 0;
+    if (kind == 0) {
+        // LDS kernel: staged factor blocks only if every instance's fit beside one column
+        bool staged = true;
+        for (int i = 0; i < n; ++i)
+            if ((int64_t)h[i].max_mat * elt + (int64_t)std::max(1, h[i].max_vec) * elt > HIF_LDS) staged = false;
+        for (int i = 0; i < n; ++i) {
+            HifInstDev &d = a.in[i];
+            const int per = std::max(1, h[i].max_vec);
+            const int64_t matb = staged ? (int64_t)h[i].max_mat * elt : 0;
+            int bchunk = (int)std::max<int64_t>(1, std::min<int64_t>(nrhs[i], (HIF_LDS - matb) / ((int64_t)per * elt)));
+            if (bchunk >= 64) bchunk = (bchunk / 64) * 64;
+            const int64_t want = (int64_t)nrhs[i] * h[i].n_nodes / 1024;
+            if (want < bchunk) bchunk = (int)std::max<int64_t>(std::min<int64_t>(16, bchunk), want);
+            d.desc = h[i].desc; d.idx = h[i].idx; d.mat = h[i].mat; d.matH = h[i].matH; d.x = x[i];
+            d.nrhs = nrhs[i]; d.bchunk = bchunk;
+            d.nch = (nrhs[i] + bchunk - 1) / bchunk;
+            d.wg0 = wg;
+            wg += h[i].n_nodes * d.nch;
+            lds = std::max(lds, (size_t)matb + (size_t)per * elt * bchunk);
+        }
+        a.total = wg;
+        if ((int64_t)lds > HIF_LDS) throw std::runtime_error("multi-instance step exceeds LDS");
+        if (dbl) {
+            if (staged) { if (up) hif_multi_go<double2, true, true>(a, lds, grid_cap, st); else hif_multi_go<double2, false, true>(a, lds, grid_cap, st); }
+            else { if (up) hif_multi_go<double2, true, false>(a, lds, grid_cap, st); else hif_multi_go<double2, false, false>(a, lds, grid_cap, st); }
+        } else {
+            if (staged) { if (up) hif_multi_go<float2, true, true>(a, lds, grid_cap, st); else hif_multi_go<float2, false, true>(a, lds, grid_cap, st); }
+            else { if (up) hif_multi_go<float2, true, false>(a, lds, grid_cap, st); else hif_multi_go<float2, false, false>(a, lds, grid_cap, st); }
+        }
+        check_launch("multi-instance hif step");
+        return;
+    }
+    // fused kernel, 64 (kind 4) or 32 (kind 5) right-hand sides per workgroup
+    const int CW = kind == 4 ? 64 : 32, LD = CW + 4;
+    const size_t celt = dbl ? sizeof(double2) : sizeof(float2);
+    for (int i = 0; i < n; ++i) {
+        HifInstDev &d = a.in[i];
+        d.desc = h[i].desc; d.idx = h[i].idx; d.mat = h[i].mat; d.matH = h[i].matH; d.x = x[i];
+        d.nrhs = nrhs[i];
+        d.rows_r = std::max(16, (h[i].max_nr + 15) / 16 * 16);
+        d.rows_s = std::max(16, (h[i].max_ns + 15) / 16 * 16);
+        d.nch = (nrhs[i] + CW - 1) / CW;
+        d.wg0 = wg;
+        wg += h[i].n_nodes * d.nch;
+        lds = std::max(lds, (size_t)(d.rows_r + d.rows_s) * LD * celt + (size_t)(d.rows_r + d.rows_s) * sizeof(int32_t));
+    }
+    a.total = wg;
+    if ((int64_t)lds > HIF_LDS) throw std::runtime_error("multi-instance fused step exceeds LDS");
+    if (dbl) {
+        if (CW == 64) { if (up) hif_fused_multi_go<double, true, 4>(a, lds, grid_cap, st); else hif_fused_multi_go<double, false, 4>(a, lds, grid_cap, st); }
+        else { if (up) hif_fused_multi_go<double, true, 2>(a, lds, grid_cap, st); else hif_fused_multi_go<double, false, 2>(a, lds, grid_cap, st); }
+    } else {
+        if (CW == 64) { if (up) hif_fused_multi_go<float, true, 4>(a, lds, grid_cap, st); else hif_fused_multi_go<float, false, 4>(a, lds, grid_cap, st); }
+        else { if (up) hif_fused_multi_go<float, true, 2>(a, lds, grid_cap, st); else hif_fused_multi_go<float, false, 2>(a, lds, grid_cap, st); }
+    }
+    check_launch("multi-instance hif step (fused)");
+}
+
+void launch_root_multi(const int32_t *const *idx, const void *const *A0inv, const int *s0, void *const *x,
+                       const int *nrhs, int n, bool dbl, hipStream_t st) {
+    if (n < 1 || n > MULTI_MAX) throw std::runtime_error("multi-instance root: 1..MULTI_MAX instances");
+    RootMultiArgs a{};
+    a.n = n;
+    int64_t wg = 0;
+    int smax = 0;
+    for (int i = 0; i < n; ++i) {
+        RootInstDev &d = a.in[i];
+        d.idx = idx[i]; d.A = (const double2 *)A0inv[i]; d.x = x[i]; d.s0 = s0[i]; d.nrhs = nrhs[i];
+        d.wg0 = wg;
+        wg += s0[i] > 0 ? nrhs[i] : 0;
+        smax = std::max(smax, s0[i]);
+    }
+    a.total = wg;
+    if (wg == 0) return;
+    if ((size_t)smax * 16 > 64 * 1024) throw std::runtime_error("top-level block exceeds LDS");
+    const size_t lds = (size_t)smax * 16;
+    const unsigned g = (unsigned)std::min<int64_t>(wg, 1 << 20);
+    if (dbl) hipLaunchKernelGGL(k_root_multi<double2>, dim3(g), dim3(256), lds, st, a);
+    else hipLaunchKernelGGL(k_root_multi<float2>, dim3(g), dim3(256), lds, st, a);
+    check_launch("multi-instance root");
 }
 
 }  // namespace fio

@@ -17,8 +17,11 @@ struct StageDev {
     int variant = -1;          // kernel variant (see stage_default_variant); -1: heuristic
 };
 
-// Number of stage kernel variants and the heuristic choice for a launch.
-constexpr int STAGE_VARIANTS = 7;
+// Number of stage kernel variants and the heuristic choice for a launch: 0 the
+// vector kernel (one thread per output entry), 1..6 matrix-core tilings, 7 the
+// small-batch kernel (64 rows x 4 k-slices per workgroup, for fewer than 16 columns).
+constexpr int STAGE_VARIANTS = 8;
+constexpr int STAGE_SMALL_BATCH = 7;
 int stage_default_variant(const StageDev &s, bool dbl, int nrhs);
 
 // Two consecutive stages a, b fused in one launch (the intermediate stays in LDS).
@@ -124,5 +127,64 @@ void launch_inverse_dft(const void *fhat, int64_t ld, void *f, int d, int n, int
                         hipStream_t st);
 // x = 0 (complex128), by a fill kernel (no memset node if the stream is captured).
 void launch_scale_zero(void *x, int64_t count, hipStream_t st);
+
+// ------------------------------------------------------------------ multi-instance launches
+// One launch for the same factor level of up to MULTI_MAX instances (different
+// plans, sizes and batch widths).  The instance lists travel by value as kernel
+// arguments (no device memory, nothing to copy: a captured graph keeps them).
+constexpr int MULTI_MAX = 8;
+struct StageInstDev {
+    const int32_t *idx;
+    const void *A, *x;
+    void *y;
+    int64_t n_out, wg0;
+    int r_out, r_in, fan, nrhs, mchunks, nch;
+};
+struct StageMultiArgs {
+    StageInstDev in[MULTI_MAX];
+    int n;
+    int64_t total;
+};
+struct HifInstDev {
+    const int64_t *desc;
+    const int32_t *idx;
+    const void *mat, *matH;
+    void *x;
+    int64_t wg0;
+    int nrhs, bchunk, nch, rows_r, rows_s;
+};
+struct HifMultiArgs {
+    HifInstDev in[MULTI_MAX];
+    int n;
+    int64_t total;
+};
+struct RootInstDev {
+    const int32_t *idx;
+    const double2 *A;
+    void *x;
+    int64_t wg0;
+    int s0, nrhs;
+};
+struct RootMultiArgs {
+    RootInstDev in[MULTI_MAX];
+    int n;
+    int64_t total;
+};
+// Stage s[i] of instance i applied to x[i] (nrhs[i] columns) into y[i], all in one
+// launch: matrix cores with the variant's tiles (1..6 as launch_stage) when every
+// instance allows them (fan <= 4), else the vector kernel.  grid_cap > 0: persistent
+// grid of at most grid_cap workgroups (rounded to the eight XCDs).
+void launch_stage_multi(const StageDev *s, const void *const *x, void *const *y, const int *nrhs, int n, bool dbl,
+                        int variant, int grid_cap, hipStream_t st);
+// Whether every instance's step fits kind 0 (LDS kernel) or 4/5 (fused kernel).
+bool hif_multi_fits(const HifStepDev *h, int n, bool dbl, int kind);
+// Skeletonization step h[i] of every instance on x[i], in one launch: kind 0 the
+// LDS-staged node kernel, 4/5 the fused matrix-core node kernel with 64/32 columns
+// per workgroup.
+void launch_hif_multi(const HifStepDev *h, void *const *x, const int *nrhs, int n, bool dbl, bool up, int kind,
+                      int grid_cap, hipStream_t st);
+// Top-level blocks A0inv[i] (FP64, s0[i] x s0[i]) on the rows idx[i] of x[i], one launch.
+void launch_root_multi(const int32_t *const *idx, const void *const *A0inv, const int *s0, void *const *x,
+                       const int *nrhs, int n, bool dbl, hipStream_t st);
 
 }  // namespace fio

@@ -31,7 +31,7 @@ PHASE_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ct
 AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
-EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error", "fio_set_trace", "fio_column_id"]
@@ -105,6 +105,11 @@ def load_library():
     lib.fio_tune_query.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64,
                                    ctypes.POINTER(ctypes.c_int)]
     lib.fio_inverse_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_solve_multi.argtypes = [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(fio_solve_opts), ctypes.c_int,
+                                    ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(I64),
+                                    ctypes.POINTER(I64), VP]
+    lib.fio_multi_autotune.argtypes = [ctypes.c_int, ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(I64),
+                                       ctypes.c_int, VP]
     lib.fio_gd_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_gd_apply_variant.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_inverse_dft.argtypes = [P, VP, VP, I64, I64, VP]
@@ -312,6 +317,25 @@ def fio_solve(plan: Plan, mode: int, dtype: int, u, out, nrhs: int, ld: int, tol
     if with_estimate:
         return info.iters, info.rel_resid, info.est_rel_err
     return (info.iters, info.rel_resid) if want_info else None
+
+
+def fio_solve_multi(plans, mode: int, dtype: int, us, outs, nrhs, lds, maxit: int = 0, stream=None):
+    """One pass over several independent solves (one launch per factor level)."""
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    U = (ctypes.c_void_p * n)(*[_ptr(u) for u in us])
+    O = (ctypes.c_void_p * n)(*[_ptr(o) for o in outs])
+    B = (ctypes.c_int64 * n)(*nrhs)
+    L = (ctypes.c_int64 * n)(*lds)
+    o = fio_solve_opts(mode, 0.0, maxit, 1, 0, 0)
+    _check(load_library().fio_solve_multi(n, P, ctypes.byref(o), dtype, U, O, B, L, _stream(stream)))
+
+
+def fio_multi_autotune(plans, dtype: int, nrhs, reps: int = 3, stream=None):
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    B = (ctypes.c_int64 * n)(*nrhs)
+    _check(load_library().fio_multi_autotune(n, P, dtype, B, reps, _stream(stream)))
 
 
 def fio_plan_stats(plan: Plan) -> dict:

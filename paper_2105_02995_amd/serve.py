@@ -69,6 +69,7 @@ class Scheduler:
         self.inflight_bytes = 0
         self.finished = []
         self.batches_started = 0
+        self.groups_started = 0      # multi-instance launches of several batches
         self.peak_inflight = 0
         self.rejected_keys = []
 
@@ -108,11 +109,13 @@ class Scheduler:
 
     def step(self, now: float):
         """Start every admissible batch, oldest waiting request first, then collect
-        the finished ones."""
+        the finished ones.  Batches admitted in the same step go to the executor
+        together (``start_group``) when it can run them as one multi-instance solve."""
         ready = [k for k, q in self.queues.items() if q and k not in self.running]
         ready.sort(key=lambda k: self.queues[k][0].arrival)
+        admitted = []
         for key in ready:
-            if len(self.running) >= self.max_inflight:
+            if len(self.running) + len(admitted) >= self.max_inflight:
                 break
             b = self._form_batch(key)
             if self.resident + self.inflight_bytes + b.bytes > self.budget:
@@ -121,10 +124,18 @@ class Scheduler:
                 continue
             for r in b.requests:
                 r.start = now
-            b.handle = self.ex.start(b, now)
-            self.running[key] = b
             self.inflight_bytes += b.bytes
-            self.batches_started += 1
+            admitted.append(b)
+        if admitted:
+            if len(admitted) > 1 and hasattr(self.ex, "start_group"):
+                handles = self.ex.start_group(admitted, now)
+                self.groups_started += 1
+            else:
+                handles = [self.ex.start(b, now) for b in admitted]
+            for b, h in zip(admitted, handles):
+                b.handle = h
+                self.running[b.key] = b
+                self.batches_started += 1
             self.peak_inflight = max(self.peak_inflight, len(self.running))
         for key, b in list(self.running.items()):
             res = self.ex.poll(b.handle, now)
@@ -231,12 +242,19 @@ class GpuExecutor:
     bucket (a HIP graph of all its kernel launches, on static device buffers) and
     replayed; a batch is padded up to its bucket.  Columns are independent, so
     padding does not change the results.
+
+    With ``use_multi``, batches of different keys admitted together run as one
+    multi-instance solve (``fio_solve_multi``: one launch per factor level for all
+    of them, on one stream); with graphs, each group (its keys and buckets) is
+    captured once and replayed.
     """
 
     BUCKETS = (16, 32, 64, 128, 256, 512, 1024)
 
+    MULTI_MAX = 8  # instances per multi-instance solve (fio.h)
+
     def __init__(self, plans: dict, max_batch_rhs: int = 256, refine: int = 1, nstreams: int = 8,
-                 use_graphs: bool = False):
+                 use_graphs: bool = False, use_multi: bool = False):
         import torch
         from . import fio as F
         self.torch, self.F = torch, F
@@ -250,6 +268,8 @@ class GpuExecutor:
         self.use_graphs = use_graphs
         self.graphs = {}              # (key, bucket) -> (graph, U, X)
         self.stage = {}               # key -> (pinned u, pinned x)
+        self.use_multi = use_multi
+        self.group_graphs = {}        # ((key, bucket), ...) -> graph of the multi-instance solve
 
     def clock(self):
         return time.perf_counter()
@@ -345,6 +365,71 @@ class GpuExecutor:
             ev.record(s)
         self.busy[id(batch)] = s
         return (batch, ev, B, keep)
+
+    def _multi(self, members, s):
+        """fio_solve_multi over members [(key, U, X, columns)] on stream s."""
+        F = self.F
+        F.fio_solve_multi([self.plans[k] for k, _, _, _ in members], F.FIO_SOLVE_REFINE, F.FIO_C64,
+                          [U for _, U, _, _ in members], [X for _, _, X, _ in members],
+                          [b for _, _, _, b in members], [self._N(k) for k, _, _, _ in members],
+                          maxit=self.refine, stream=s)
+
+    def start_group(self, batches, now):
+        """Several batches of different keys as multi-instance solves (groups of up
+        to MULTI_MAX, one stream each); returns one handle per batch."""
+        if not self.use_multi:
+            return [self.start(b, now) for b in batches]
+        torch = self.torch
+        handles = [None] * len(batches)
+        order = sorted(range(len(batches)), key=lambda i: batches[i].key)
+        for g0 in range(0, len(order), self.MULTI_MAX):
+            idx = order[g0:g0 + self.MULTI_MAX]
+            if len(idx) == 1:
+                handles[idx[0]] = self.start(batches[idx[0]], now)
+                continue
+            s = self._stream()
+            members, keep = [], []
+            for i in idx:
+                b = batches[i]
+                hu = self.stage[b.key][0]
+                c0 = 0
+                for r in b.requests:
+                    hu[c0:c0 + r.nrhs].copy_(torch.from_numpy(np.ascontiguousarray(r.u.T)))
+                    c0 += r.nrhs
+            with torch.cuda.stream(s):
+                for i in idx:
+                    b = batches[i]
+                    if self.use_graphs:
+                        _, U, X = self.graphs[(b.key, self._bucket(b.nrhs))]
+                        members.append((b.key, U, X, self._bucket(b.nrhs)))
+                    else:
+                        U = torch.empty((b.nrhs, self._N(b.key)), dtype=torch.complex128, device="cuda")
+                        X = torch.empty_like(U)
+                        members.append((b.key, U, X, b.nrhs))
+                        keep.append((U, X))
+                    U[:b.nrhs].copy_(self.stage[b.key][0][:b.nrhs], non_blocking=True)
+                if self.use_graphs:
+                    sig = tuple((k, cols) for k, _, _, cols in members)
+                    g = self.group_graphs.get(sig)
+                    if g is None:
+                        self._multi(members, s)  # eager first run (also outside the capture)
+                        s.synchronize()
+                        g = torch.cuda.CUDAGraph()
+                        with torch.cuda.graph(g, stream=s):
+                            self._multi(members, s)
+                        self.group_graphs[sig] = g
+                    g.replay()
+                else:
+                    self._multi(members, s)
+                for i, (_, _, X, _) in zip(idx, members):
+                    b = batches[i]
+                    self.stage[b.key][1][:b.nrhs].copy_(X[:b.nrhs], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(s)
+            for i in idx:
+                self.busy[id(batches[i])] = s
+                handles[i] = (batches[i], ev, batches[i].nrhs, keep)
+        return handles
 
     def poll(self, handle, now):
         batch, ev, B, keep = handle

@@ -22,11 +22,20 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EXE = os.path.join(ROOT, "paper_2105_02995_amd", "fio_solve_file")
 
 
+MIX = ((0.2, -0.2), (0.5, 0.2), (0.8, 0.0))
+
+
+# pid 1, 2: the library's built-in phases; 101-103: FIOs the C program defines itself
+# through FIO_PHASE_CALLBACK (Example 1's phase, Example 3's phase, Example 1's phase
+# with Example 2's amplitude)
 @pytest.mark.parametrize("d,n,phase,pid,eps,mode", [(1, 1024, "1d_ex1", 1, 1e-6, 1), (1, 1024, "1d_ex1", 1, 1e-6, 2),
-                                                     (1, 1024, "1d_ex1", 1, 1e-6, 3), (2, 32, "2d_radon", 2, 1e-4, 1)])
+                                                     (1, 1024, "1d_ex1", 1, 1e-6, 3), (2, 32, "2d_radon", 2, 1e-4, 1),
+                                                     (1, 1024, "1d_ex1", 101, 1e-6, 1),
+                                                     (2, 32, "2d_radon", 102, 1e-4, 1),
+                                                     (1, 1024, "1d_ex2", 103, 1e-5, 2)])
 def test_c_program_solves_from_file(tmp_path, d, n, phase, pid, eps, mode):
     B = 3
-    op = O.OracleProblem(d, n, phase, 16.0)
+    op = O.OracleProblem(d, n, phase, 16.0, amp=MIX, sigma2=0.1)
     K = O.dense_K(op)
     fh = gaussian_complex((n ** d, B), 1100 + mode)
     u = K @ fh

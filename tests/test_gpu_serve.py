@@ -139,3 +139,31 @@ def test_serving_with_graphs_matches_eager_serving(plans):
         out.append({r.rid: r for r in done})
     for rid, r in out[0].items():
         assert O.rel_err(out[1][rid].result, r.result).max() < 10 * r.key[3]
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_multi_instance_serving_alone_equals_mix(plans, graphs):
+    """Batches of different keys admitted together run as one multi-instance solve
+    (one launch per factor level for all of them); each request's result must be
+    the same as when it is served alone (within the stated tolerance), and correct."""
+    ex = GpuExecutor(plans, max_batch_rhs=64, refine=1, use_graphs=graphs, use_multi=True)
+    sched = Scheduler(ex, hbm_budget=64 << 30, max_batch_rhs=64)
+    for k in KEYS:
+        assert sched.register(k)
+    reqs = _mix(60, rate=3000.0, seed=13)
+    done = sched.run(reqs)
+    assert len(done) == 60
+    log("multi serving graphs=%s: %d batches in %d multi-instance groups" % (graphs, sched.batches_started,
+                                                                             sched.groups_started))
+    assert sched.groups_started >= 1
+    worst = 0.0
+    for r in sorted(done, key=lambda r: r.rid)[:12]:
+        ex1 = GpuExecutor({r.key: plans[r.key]}, max_batch_rhs=64, refine=1)
+        s1 = Scheduler(ex1, hbm_budget=64 << 30, max_batch_rhs=64)
+        assert s1.register(r.key)
+        alone = ServeRequest(r.rid, r.key, 0.0, r.u)
+        s1.run([alone])
+        rel = O.rel_err(alone.result, r.result).max()
+        worst = max(worst, rel)
+        assert rel < 10 * r.key[3], (r.key, rel)
+    log("alone vs multi-instance mix: worst relative difference %.2e" % worst)

@@ -211,6 +211,60 @@ def test_cg_count_distinguishes_config_phase():
     assert its < 20
 
 
+def _ex1_c8(n=256):
+    p = O.OracleProblem(1, n, "1d_ex1", 8.0)
+    return O.dense_K(p)
+
+
+def test_pcg_with_exact_inverse_stops_after_one_iteration():
+    """Preconditioned branch of cg_normal (section 5): with M = (K^*K)^{-1} the
+    first search direction is the exact solution, so one iteration solves K^*K x =
+    K^*b to rounding and the iteration stops there."""
+    K = _ex1_c8()
+    S = K.conj().T @ K
+    Sinv = np.linalg.inv(S)
+    b = gaussian_complex(K.shape[0], 40)
+    x, its = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, b, tol=1e-8,
+                         precond=lambda r: Sinv @ r)
+    assert its == 1
+    assert O.rel_err(x, np.linalg.solve(K, b)).max() < 1e-10
+
+
+def test_pcg_with_scaled_identity_has_the_iterates_of_cg():
+    """M = c I changes neither the step lengths nor the directions of CG: the
+    preconditioned branch with c = 7.5 returns the iterate of the plain branch
+    after the same number of iterations (and for a fixed iteration cap)."""
+    K = _ex1_c8()
+    b = gaussian_complex(K.shape[0], 41)
+    aK, aKH = (lambda v: K @ v), (lambda v: K.conj().T @ v)
+    for cap, tol in ((5, 0.0), (1000, 1e-8)):
+        x0, i0 = O.cg_normal(aK, aKH, b, tol=tol, maxit=cap)
+        x1, i1 = O.cg_normal(aK, aKH, b, tol=tol, maxit=cap, precond=lambda r: 7.5 * r)
+        assert i0 == i1
+        assert O.rel_err(x1, x0).max() < 1e-10
+
+
+def test_pcg_equals_cg_on_the_split_preconditioned_system():
+    """PCG with M = D^2 (D diagonal, positive) is CG on (K D)^*(K D) y = (K D)^* b
+    with x = D y, a textbook identity of split preconditioning: the preconditioned
+    branch must reproduce, iterate by iterate, the plain branch (pinned by the
+    paper's counts) run on the transformed operator."""
+    K = _ex1_c8()
+    n = K.shape[0]
+    rng = np.random.default_rng(42)
+    dg = np.exp(rng.uniform(-1.0, 1.0, n))
+    b = gaussian_complex(n, 43)
+    for cap in (1, 2, 3, 6):
+        x, i = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, b, tol=0.0, maxit=cap,
+                           precond=lambda r: dg ** 2 * r)
+        y, j = O.cg_normal(lambda v: K @ (dg * v), lambda v: dg * (K.conj().T @ v), b, tol=0.0, maxit=cap)
+        assert i == j == cap
+        assert O.rel_err(x, dg * y).max() < 1e-9
+    x, i = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, b, tol=1e-8,
+                       precond=lambda r: dg ** 2 * r)
+    assert O.rel_err(x, np.linalg.solve(K, b)).max() < 1e-6
+
+
 def test_example2_single_term_is_separable():
     """One Gaussian term factors, a(x, xi) = g(x) h(xi), so K = diag(g) K_1 diag(h)
     with K_1 Example 1's operator: rows reduce to the FFT closed form.  Pins the

@@ -75,7 +75,7 @@ def test_hbm_admission_bounds_inflight_bytes_and_refuses_oversized_keys():
 
     class Ex(MockExecutor):
         def start(self, batch, now):
-            inflight.append(sched.inflight_bytes + batch.bytes)
+            inflight.append(sched.inflight_bytes)  # counts every batch admitted so far, this one included
             return super().start(batch, now)
 
     ex = Ex(cost=lambda key, nr: 0.02, factor_bytes=lambda key: 100_000 if key[0] == 2 else 10_000,
