@@ -178,6 +178,26 @@ fio_status fio_apply(fio_plan plan, fio_op op, fio_dtype dtype, const void *x, v
 fio_status fio_inverse_apply(fio_plan plan, fio_dtype dtype, const void *u, void *fhat,
                              int64_t nrhs, int64_t ld, void *hip_stream);
 
+/* fhat = Gd Kd^* u as fio_inverse_apply (same kernels, same launches, the same
+ * result bit for bit), for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  The call
+ * allocates nothing (no hipMalloc or hipFree, no allocating library routine): its
+ * temporaries live in one static device array of 256 MiB per GPU, reserved when the
+ * library's code object is loaded on that GPU and held until the process ends.  The
+ * plan's factors were allocated by fio_build; the caller passes u and fhat as for
+ * fio_inverse_apply.  The temporaries need
+ *   (3 N + 2 C) nrhs e + 2 s0 nrhs 16 bytes (each part rounded up to 256 bytes),
+ * e = 8 (FIO_C64) or 16 (FIO_C128), C the longest coefficient vector between butterfly
+ * stages, s0 the top-level block (fio_plan_stats_t.root_size); e.g. 1D N = 65536 takes
+ * about 5 MB per complex64 right-hand side.  Errors: FIO_ERR_ARG when nrhs needs more
+ * than 256 MiB (the message states the bytes), as fio_inverse_apply otherwise.
+ * Every call on one GPU uses that GPU's one array, for every plan: calls that overlap
+ * on one GPU (different streams or host threads) race and give wrong results; the
+ * array keeps the last call's contents, and no part of it has to start at zero.
+ * Asynchronous. */
+fio_status fio_inverse_apply_noalloc(fio_plan plan, fio_dtype dtype, const void *u, void *fhat,
+                                     int64_t nrhs, int64_t ld, void *hip_stream);
+
 /* y = Gd x, the approximate inverse of Kd^* Kd alone (section 4). */
 fio_status fio_gd_apply(fio_plan plan, fio_dtype dtype, const void *x, void *y,
                         int64_t nrhs, int64_t ld, void *hip_stream);

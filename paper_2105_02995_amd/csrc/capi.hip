@@ -792,6 +792,59 @@ PeelApplyFactory gpu_peel_factory(int device, std::shared_ptr<DeviceChains> c) {
 
 }  // namespace
 
+// ------------------------------------------------- static scratch (no-allocation path)
+// Device memory of fio_inverse_apply_noalloc: one file-scope array per device (every
+// device that loads this code object holds its own copy until the process ends).
+// In host code `scratch` names a host-side stand-in, not device memory: its device
+// address comes from hipGetSymbolAddress, once per device, and only that address is
+// ever handed to kernels or copies.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // device ordinal -> address of that device's scratch
+
+// Address of the current device's scratch array (dev must be current).
+void *scratch_on(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPC(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) fail(FIO_ERR_DEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Bytes of scratch an inverse apply of nrhs columns needs: the gathered input and
+// the chain output (N x nrhs), the stage ping-pong buffers (max_coef x nrhs) and the
+// GEMM path's temporary (N x nrhs), all of the working precision, and the FP64 root
+// rows (s0 x nrhs, twice); each part starts on a 256-byte boundary.
+struct ScratchLayout {
+    size_t v1, v2, p, q, ht, ri, ro, total;
+};
+ScratchLayout scratch_layout(fio_plan p, bool dbl, int64_t nrhs) {
+    const size_t elt = dbl ? 16 : 8;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t vec = up((size_t)p->host.N * nrhs * elt), coef = up((size_t)p->max_coef * nrhs * elt);
+    const size_t root = up((size_t)std::max(1, p->s0) * nrhs * 16);
+    ScratchLayout L;
+    L.v1 = 0;
+    L.v2 = L.v1 + vec;
+    L.p = L.v2 + vec;
+    L.q = L.p + coef;
+    L.ht = L.q + coef;
+    L.ri = L.ht + vec;
+    L.ro = L.ri + root;
+    L.total = L.ro + root;
+    return L;
+}
+
+}  // namespace
+
 // ============================================================================ C ABI
 extern "C" {
 
@@ -1226,6 +1279,33 @@ fio_status fio_gd_apply_variant(fio_plan p, fio_dtype dt, int variant, const voi
         launch_gather(x, dbl, ld, perm, p->V2.p, dbl, p->host.N, nr, st);
         gd_inplace(p, dbl, p->V2.p, nr, st, variant);
         launch_scatter(p->V2.p, dbl, perm, y, dbl, ld, p->host.N, nr, st);
+    });
+}
+
+fio_status fio_inverse_apply_noalloc(fio_plan p, fio_dtype dt, const void *u, void *fh, int64_t nrhs,
+                                     int64_t ld, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, ld, u, fh);
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (nrhs == 0) return;
+        const bool dbl = dt == FIO_C128;
+        const ScratchLayout L = scratch_layout(p, dbl, nrhs);
+        if (L.total > NOALLOC_SCRATCH_BYTES)
+            fail(FIO_ERR_ARG, "nrhs = " + std::to_string(nrhs) + " needs " + std::to_string(L.total) +
+                                  " bytes of scratch; the no-allocation path has " +
+                                  std::to_string(NOALLOC_SCRATCH_BYTES));
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        char *base = (char *)scratch_on(p->device);
+        hipStream_t st = (hipStream_t)stream;
+        const int nr = (int)nrhs;
+        const Ws ws{base + L.p, base + L.q, base + L.ht, base + L.ri, base + L.ro};
+        void *v1 = base + L.v1, *v2 = base + L.v2;
+        const int32_t *perm = (const int32_t *)p->perm.p;
+        launch_gather(u, dbl, ld, perm, v1, dbl, p->host.N, nr, st);
+        run_chain(p, false, dbl, v1, v2, nr, st, ws);
+        gd_inplace(p, dbl, v2, nr, st, ws);
+        launch_scatter(v2, dbl, perm, fh, dbl, ld, p->host.N, nr, st);
     });
 }
 

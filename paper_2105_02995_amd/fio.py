@@ -31,7 +31,7 @@ PHASE_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ct
 AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
-EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error", "fio_set_trace", "fio_column_id"]
@@ -105,6 +105,7 @@ def load_library():
     lib.fio_tune_query.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64,
                                    ctypes.POINTER(ctypes.c_int)]
     lib.fio_inverse_apply.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
+    lib.fio_inverse_apply_noalloc.argtypes = [P, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_solve_multi.argtypes = [ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(fio_solve_opts), ctypes.c_int,
                                     ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(I64),
                                     ctypes.POINTER(I64), VP]
@@ -288,6 +289,12 @@ def fio_tune_query(plan: Plan, op: int, stage: int, dtype: int, nrhs: int) -> in
 def fio_inverse_apply(plan: Plan, dtype: int, u, fhat, nrhs: int, ld: int, stream=None):
     _check(load_library().fio_inverse_apply(plan.handle, dtype, _ptr(u), _ptr(fhat), nrhs, ld,
                                             _stream(stream)))
+
+
+def fio_inverse_apply_noalloc(plan: Plan, dtype: int, u, fhat, nrhs: int, ld: int, stream=None):
+    """fio_inverse_apply with its temporaries in the library's static scratch array."""
+    _check(load_library().fio_inverse_apply_noalloc(plan.handle, dtype, _ptr(u), _ptr(fhat), nrhs, ld,
+                                                    _stream(stream)))
 
 
 def fio_inverse_dft(plan: Plan, fhat, f, nrhs: int, ld: int, stream=None):
