@@ -207,7 +207,7 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
-VNAME = {1: (1, 4), 2: (2, 4), 3: (1, 2), 4: (2, 2), 5: (1, 1), 6: (2, 1)}
+VNAME = {1: (1, 4), 2: (2, 4), 3: (1, 2), 4: (2, 2), 5: (1, 1), 6: (2, 1), 8: (4, 4), 9: (4, 2)}
 PAIR_NT = {1: 1, 2: 2, 3: 4}
 PAIR_STACKED = 4  # fused pair with sibling blocks stacked into one operand
 
@@ -275,6 +275,11 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
             name = "k_stage2_mfma<%s, %d, %d>" % (r, mt, PAIR_NT[v])
         elif v == 0:
             name = "k_stage<%s2>" % r
+        elif v == 7:
+            name = "k_stage_nb<%s2>" % r
+        elif v in (10, 11):
+            ro = io(ks[0])[0]["r_out"] if op == F.FIO_OP_K else io(ks[0])[0]["r_in"]
+            name = "k_stage_lds<%s, %d, %d>" % (r, 1 if ro <= 64 else (2 if ro <= 128 else 3), 4 if v == 10 else 2)
         else:
             name = "k_stage_mfma<%s, %d, %d>" % ((r,) + VNAME[v])
         out.append({"name": name, "ms": float(tot[j]), "flops": flops, "bytes": float(byts),
@@ -416,7 +421,11 @@ def roofline_of(F, torch, plan, stats, B, refine):
 
 def plain_fp64(F, torch, plan, U, N, stream, ncols=16):
     """Plain FP64 path: complex128 factors, one right-hand side per call, direct
-    solve (Gd Kd^* u)."""
+    solve (Gd Kd^* u), with the kernels autotuned for that width as the batched
+    path is for its own."""
+    t0 = time.perf_counter()
+    F.fio_autotune(plan, F.FIO_C128, 1, 3, stream)
+    log("autotuned the single-RHS FP64 path in %.1f s" % (time.perf_counter() - t0))
     Uc = [U[j:j + 1].contiguous() for j in range(ncols)]
     Xc = [torch.zeros_like(Uc[0]) for _ in range(ncols)]
     for j in range(2):

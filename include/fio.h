@@ -351,6 +351,14 @@ fio_status fio_stage_info(fio_plan plan, int stage, int64_t *nnz, int64_t *n_out
 fio_status fio_stage_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x,
                            void *y, int64_t nrhs, void *hip_stream);
 
+/* fio_stage_apply with one kernel variant forced (the codes of fio_tune_query;
+ * -1: the tuned or default choice).  For tests and measurement: every variant
+ * computes the same product (to rounding).  A matrix-core variant on a factor
+ * whose blocks read more than four input blocks runs the vector kernel.
+ * Asynchronous.  Errors: FIO_ERR_ARG (variant, stage or op out of range). */
+fio_status fio_stage_apply_variant(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int variant,
+                                   const void *x, void *y, int64_t nrhs, void *hip_stream);
+
 /* Apply the factors `stage` and `stage + 1` of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH)
  * in one fused launch: consecutive butterfly factors of eq_BFF_fact couple closed
  * groups of at most fan^2 blocks, so one workgroup computes a group's
@@ -418,8 +426,10 @@ fio_status fio_autotune(fio_plan plan, fio_dtype dtype, int64_t nrhs, int reps, 
 /* Kernel variant used for stage `stage` of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) at
  * this dtype and nrhs: 0 vector kernel, 1..6 matrix-core tilings (16*MT rows x
  * 16*NT columns per wave: 1 MT1xNT4, 2 MT2xNT4, 3 MT1xNT2, 4 MT2xNT2, 5 MT1xNT1,
- * 6 MT2xNT1), 7 the small-batch kernel (fewer than 16 columns: 64 rows per
- * workgroup, the k range split over its four waves). */
+ * 6 MT2xNT1, 8 MT4xNT4, 9 MT4xNT2), 7 the small-batch kernel (fewer than 16
+ * columns: 64 rows per workgroup, the k range split over its four waves), 10/11
+ * matrix cores with the gathered input staged in LDS and shared by a workgroup's
+ * four waves (one output block of up to 192 rows per workgroup, 64/32 columns). */
 fio_status fio_tune_query(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int64_t nrhs,
                           int *variant);
 

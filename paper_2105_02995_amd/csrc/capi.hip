@@ -591,18 +591,20 @@ void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStr
     }
     if (choice < 0) {
         if (nrhs >= 16 && hif_fused_fits(h)) choice = 5;
-        else choice = (hif_step_fits_lds(h, dbl) || nrhs < 16) ? 0 : 1;
+        else if (hif_step_fits_lds(h, dbl)) choice = 0;
+        else choice = nrhs >= 64 ? 1 : 3;  // large nodes: gathered GEMMs over all nodes' row tiles
     }
     if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
     else if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
     else launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, 64 >> (choice - 1), st);
 }
 
-// A_0^{-1} on the remaining DOFs, always in FP64: as a one-block FP64 stage on
-// matrix cores for batches, else the direct kernel.
+// A_0^{-1} on the remaining DOFs, always in FP64: a block of 64 or more DOFs as a
+// one-block FP64 stage (matrix cores for batches, the small-batch kernel for fewer
+// than 16 columns), a smaller one with the direct kernel.
 void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, const Ws &ws) {
     if (p->s0 == 0) return;
-    if (nrhs < 16 || p->s0 < 64) {
+    if (p->s0 < 64) {
         launch_root((const int32_t *)p->root_idx.p, p->A0inv.p, p->s0, dbl, x, nrhs, st);
         return;
     }
@@ -988,12 +990,13 @@ fio_status fio_apply(fio_plan p, fio_op op, fio_dtype dt, const void *x, void *y
     });
 }
 
-fio_status fio_stage_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const void *x, void *y,
-                           int64_t nrhs, void *stream) {
+fio_status fio_stage_apply_variant(fio_plan p, fio_op op, int stage, fio_dtype dt, int variant, const void *x,
+                                   void *y, int64_t nrhs, void *stream) {
     return guard([&] {
         check_apply_args(p, nrhs, p ? p->host.N : 0, x, y);
         if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
         if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        if (variant < -1 || variant >= STAGE_VARIANTS) fail(FIO_ERR_ARG, "stage kernel variant out of range");
         const auto &hs = (op == FIO_OP_K) ? p->host.fwd : p->adj;
         const auto &ds = (op == FIO_OP_K) ? p->dfwd : p->dadj;
         if (stage < 0 || stage >= (int)hs.size()) fail(FIO_ERR_ARG, "stage out of range");
@@ -1001,10 +1004,19 @@ fio_status fio_stage_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const
         HIPC(hipSetDevice(p->device));
         const bool dbl = dt == FIO_C128;
         StageDev v = ds[stage].view(dbl, hs[stage]);
-        const auto *t = p->tuned(dbl, (int)nrhs);
-        if (t) v.variant = (op == FIO_OP_K) ? t->fwd[stage] : t->adj[stage];
+        if (variant >= 0) {
+            v.variant = variant;
+        } else {
+            const auto *t = p->tuned(dbl, (int)nrhs);
+            if (t) v.variant = (op == FIO_OP_K) ? t->fwd[stage] : t->adj[stage];
+        }
         launch_stage(v, dbl, x, y, (int)nrhs, (hipStream_t)stream);
     });
+}
+
+fio_status fio_stage_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const void *x, void *y,
+                           int64_t nrhs, void *stream) {
+    return fio_stage_apply_variant(p, op, stage, dt, -1, x, y, nrhs, stream);
 }
 
 fio_status fio_stage_pair_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const void *x, void *y,
@@ -1221,14 +1233,16 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             }
             t.hif.push_back(best);
         }
-        if (nr >= 16 && p->s0 >= 64) {
+        if (p->s0 >= 64) {
             StageDev sr;
             sr.n_out = 1; sr.n_in = 1; sr.r_out = p->s0; sr.r_in = p->s0; sr.fan = 1;
             sr.idx = (const int32_t *)p->root_stage_idx.p;
             sr.A = p->A0inv.p;
             float best_ms = 1e30f;
             launch_scale_zero(p->RI.p, (int64_t)p->s0 * nr, st);
-            for (int v = 1; v < STAGE_SMALL_BATCH; ++v) {
+            for (int v = 1; v < STAGE_VARIANTS; ++v) {
+                if ((v == STAGE_SMALL_BATCH) != (nr < 16)) continue;  // matrix cores from 16 columns
+                if (v == STAGE_LDS4 || v == STAGE_LDS2) continue;      // blocks of up to 192 rows only
                 sr.variant = v;
                 const float ms = timeit([&] { launch_stage(sr, true, p->RI.p, p->RO.p, nr, st); });
                 if (ms < best_ms) { best_ms = ms; t.root = v; }
@@ -1602,8 +1616,8 @@ void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x
         if (cl > 0) launch_hif_multi(hl, xl, nl, cl, dbl, up, 0, c.cap, st);
     };
     for (int k = 0; k < K; ++k) step(k, true);
-    // top-level blocks: the one-block matrix-core stage for wide batches of large
-    // blocks (per instance), the direct kernel for the others (one launch)
+    // top-level blocks: large ones as one-block FP64 stages (per instance), the small
+    // ones with the direct kernel (one launch)
     const int32_t *ri[MULTI_MAX];
     const void *ra[MULTI_MAX];
     int rs[MULTI_MAX], rn[MULTI_MAX], cr = 0;
@@ -1611,7 +1625,7 @@ void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x
     for (size_t i = 0; i < I.size(); ++i) {
         fio_plan p = I[i].p;
         if (p->s0 == 0) continue;
-        if (I[i].nr >= 16 && p->s0 >= 64) {
+        if (p->s0 >= 64) {
             root_apply(p, dbl, x[i], I[i].nr, st, plan_ws(p));
         } else {
             ri[cr] = (const int32_t *)p->root_idx.p; ra[cr] = p->A0inv.p; rs[cr] = p->s0; rx[cr] = x[i];
@@ -1761,8 +1775,10 @@ fio_status fio_multi_autotune(int n_inst, const fio_plan *plans, fio_dtype dt, c
             for (int j = 0; j < S; ++j) {
                 LevelChoice best;
                 float best_ms = 1e30f;
-                for (int v = 1; v < STAGE_SMALL_BATCH; ++v)
+                for (int v = 1; v < STAGE_VARIANTS; ++v)
                     for (int cap : caps) {
+                        // the multi-instance kernel has the register-tiled variants only
+                        if (v == STAGE_SMALL_BATCH || v == STAGE_LDS4 || v == STAGE_LDS2) continue;
                         std::vector<LevelChoice> one(S);
                         one[j] = LevelChoice{v, cap};
                         // the level alone: instances whose chain has it, P -> Q

@@ -72,9 +72,13 @@ static unsigned grid_for(int64_t work, int block) {
 // ------------------------------------------------------------------ butterfly stage
 // One thread per output entry (o, a, b), b fastest: the factor entry is shared by
 // the nrhs lanes of one row and the gathered input is read coalesced across b.
+// Entry t = (o, a, b) of a stage's output.  Eight k-steps of loads are issued before
+// their products, so a thread keeps eight loads in flight instead of waiting for
+// each one (the loads do not depend on the accumulator).
 template <class T>
 __device__ __forceinline__ T stage_entry(int r_out, int r_in, int fan, const int32_t *__restrict__ idx,
                                          const T *__restrict__ A, const T *__restrict__ x, int nrhs, int64_t t) {
+    constexpr int U = 8;
     const int b = (int)(t % nrhs);
     const int64_t t2 = t / nrhs;
     const int a = (int)(t2 % r_out);
@@ -84,7 +88,18 @@ __device__ __forceinline__ T stage_entry(int r_out, int r_in, int fan, const int
     for (int q = 0; q < fan; ++q) {
         const T *xin = x + (int64_t)idx[o * fan + q] * r_in * nrhs + b;
         const T *Aq = Ao + (int64_t)q * r_in * r_out;
-        for (int e = 0; e < r_in; ++e) acc = cfma(acc, Aq[(int64_t)e * r_out], xin[(int64_t)e * nrhs]);
+        int e = 0;
+        for (; e + U <= r_in; e += U) {
+            T av[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                av[u] = Aq[(int64_t)(e + u) * r_out];
+                xv[u] = xin[(int64_t)(e + u) * nrhs];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = cfma(acc, av[u], xv[u]);
+        }
+        for (; e < r_in; ++e) acc = cfma(acc, Aq[(int64_t)e * r_out], xin[(int64_t)e * nrhs]);
     }
     return acc;
 }
@@ -610,6 +625,137 @@ static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hip
                        s.r_out, s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks, nch);
 }
 
+// Stage with the gathered input staged in LDS: one workgroup per (output block,
+// column chunk of 16*NT right-hand sides); its four waves split the block's rows
+// (16*MT each, so 64*MT >= r_out) and share the input, which is brought into LDS
+// in chunks of LDS_KC k-rows, double buffered: the next chunk's global loads are in
+// flight while the current chunk's products run, and every input entry is read
+// from L2 once per workgroup instead of once per wave.  The factor rows stream
+// from memory per wave with the same register prefetch as k_stage_mfma (past the
+// last k the factor operand is zero).
+constexpr int LDS_KC = 32;
+template <class R, int NT> struct LdsTile {
+    static constexpr int CW = 16 * NT, LDX = CW + 2;
+    static constexpr int LPT = LDS_KC * CW / 256;  // staged entries per thread per chunk
+};
+
+template <class R, int MT, int NT>
+__global__ void __launch_bounds__(256) k_stage_lds(int64_t n_out, int r_out, int r_in, int fan,
+                                                   const int32_t *__restrict__ idx,
+                                                   const typename MF<R>::C *__restrict__ A,
+                                                   const typename MF<R>::C *__restrict__ x,
+                                                   typename MF<R>::C *__restrict__ y, int nrhs, int nch) {
+    using C = typename MF<R>::C;
+    using T = LdsTile<R, NT>;
+    constexpr int CW = T::CW, LDX = T::LDX, LPT = T::LPT, RSTEP = 256 / CW;
+    extern __shared__ char smem_raw[];
+    C *Xs = reinterpret_cast<C *>(smem_raw);  // 2 buffers of LDS_KC x LDX
+    int64_t o;
+    int chunk;
+    xcd_order(n_out, nch, o, chunk);
+    if (o >= n_out) return;  // workgroup-uniform
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int K = fan * r_in;
+    const int n0 = chunk * CW;
+    const int ncols = nrhs - n0;
+    const int32_t *io = idx + o * fan;
+    // staging: thread t loads column t % CW of rows t / CW + j * RSTEP of each chunk
+    const int lcol = threadIdx.x % CW, lrow = threadIdx.x / CW;
+    const C *xg = x + n0 + min(lcol, ncols - 1);
+    R xre[LPT], xim[LPT];  // real and imaginary parts kept apart: plain registers
+    // global loads of the chunk starting at k-row kc0 (past K: a valid row, which
+    // meets a zero factor entry)
+#define LDS_GLOAD(kc0)                                                                   \
+    _Pragma("unroll") for (int j = 0; j < LPT; ++j) {                                    \
+        const int k_ = min((kc0) + lrow + j * RSTEP, K - 1);                             \
+        const int q_ = k_ / r_in;                                                        \
+        const C v_ = xg[((int64_t)io[q_] * r_in + (k_ - q_ * r_in)) * nrhs];             \
+        xre[j] = v_.x;                                                                   \
+        xim[j] = v_.y;                                                                   \
+    }
+#define LDS_STORE(buf)                                                                   \
+    _Pragma("unroll") for (int j = 0; j < LPT; ++j)                                      \
+        Xs[((buf) * LDS_KC + lrow + j * RSTEP) * LDX + lcol] = C{xre[j], xim[j]};
+    // this lane's factor rows; k-step s reads column k = 4 s + lk (zero past K)
+    int rowc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) rowc[mt] = min(w * 16 * MT + mt * 16 + li, r_out - 1);
+    const C *Ao = A + o * (int64_t)r_out * K;
+#define LDS_ALOAD(slot, step)                                                            \
+    {                                                                                    \
+        const int k_ = 4 * (step) + lk;                                                  \
+        const bool kv_ = k_ < K;                                                         \
+        const C *acol_ = kv_ ? Ao + (int64_t)k_ * r_out : reinterpret_cast<const C *>(g_zero_rows); \
+        _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) ar[slot][mt] = acol_[kv_ ? rowc[mt] : mt * 16 + li]; \
+    }
+    Acc<R, MT, NT> acc;
+    acc.zero();
+    LDS_GLOAD(0)
+    LDS_STORE(0)
+    C ar[STAGE_PF][MT];
+#pragma unroll
+    for (int j = 0; j + 1 < STAGE_PF; ++j) LDS_ALOAD(j, j)
+    __syncthreads();
+    const int nchunks = (K + LDS_KC - 1) / LDS_KC;
+    static_assert((LDS_KC / 4) % STAGE_PF == 0, "ring index must be a compile-time constant");
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        const bool more = c + 1 < nchunks;
+        if (more) { LDS_GLOAD((c + 1) * LDS_KC) }  // in flight during this chunk's products
+        const C *Xb = Xs + buf * LDS_KC * LDX;
+        const int step0 = c * (LDS_KC / 4);
+        // every chunk runs all its k-steps: past K the factor operand is zero, so the
+        // last chunk's extra steps add nothing, and the loop has no exit to unroll around
+#pragma unroll
+        for (int ks = 0; ks < LDS_KC / 4; ++ks) {
+            // step0 is a multiple of STAGE_PF, so the ring slots are compile-time indices
+            LDS_ALOAD((ks + STAGE_PF - 1) % STAGE_PF, step0 + ks + STAGE_PF - 1)
+            Frag<R, MT, NT> f;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) f.a[mt] = ar[ks % STAGE_PF][mt];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) f.x[nt] = Xb[(4 * ks + lk) * LDX + nt * 16 + li];
+            acc.mma(f);
+        }
+        if (more) { LDS_STORE(buf ^ 1) }  // that buffer was last read before the previous barrier
+        __syncthreads();
+    }
+#undef LDS_GLOAD
+#undef LDS_STORE
+#undef LDS_ALOAD
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = w * 16 * MT + mt * 16 + MF<R>::drow(lk, v);
+                const int col = n0 + nt * 16 + li;
+                if (row < r_out && col < nrhs) y[(o * r_out + row) * (int64_t)nrhs + col] = acc.get(mt, nt, v);
+            }
+}
+
+template <class R, int MT, int NT>
+static void lds_go(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    using T = LdsTile<R, NT>;
+    const int nch = (nrhs + T::CW - 1) / T::CW;
+    const size_t lds = (size_t)2 * LDS_KC * T::LDX * sizeof(C);
+    hipLaunchKernelGGL((k_stage_lds<R, MT, NT>), dim3(xcd_grid(s.n_out, nch)), dim3(256), lds, st, s.n_out, s.r_out,
+                       s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, nch);
+}
+
+// Whether the LDS-staged kernel applies: blocks of at most 192 rows (four waves of
+// up to three 16-row tiles), at most four input blocks.
+bool stage_lds_fits(const StageDev &s) { return s.r_out <= 192 && s.fan <= 4 && s.r_in >= 1 && s.r_out >= 1; }
+
+template <class R, int NT>
+static void launch_lds(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+    if (s.r_out <= 64) lds_go<R, 1, NT>(s, x, y, nrhs, st);
+    else if (s.r_out <= 128) lds_go<R, 2, NT>(s, x, y, nrhs, st);
+    else lds_go<R, 3, NT>(s, x, y, nrhs, st);
+}
+
 // Right-hand-side counts from which the matrix-core path is used by default.
 static const int MFMA_MIN_RHS = 16;
 
@@ -631,6 +777,8 @@ static void launch_variant(int v, const StageDev &s, const void *x, void *y, int
         case 3: launch_mfma<R, 1, 2>(s, x, y, nrhs, st); break;
         case 4: launch_mfma<R, 2, 2>(s, x, y, nrhs, st); break;
         case 5: launch_mfma<R, 1, 1>(s, x, y, nrhs, st); break;
+        case 8: launch_mfma<R, 4, 4>(s, x, y, nrhs, st); break;
+        case 9: launch_mfma<R, 4, 2>(s, x, y, nrhs, st); break;
         default: launch_mfma<R, 2, 1>(s, x, y, nrhs, st); break;
     }
 }
@@ -646,6 +794,15 @@ void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs,
         else launch_stage_nb<float2>(s, x, y, nrhs, st);
         check_launch("stage (small batch)");
         return;
+    }
+    if (v == STAGE_LDS4 || v == STAGE_LDS2) {
+        if (!stage_lds_fits(s)) v = 0;
+        else {
+            if (dbl) { if (v == STAGE_LDS4) launch_lds<double, 4>(s, x, y, nrhs, st); else launch_lds<double, 2>(s, x, y, nrhs, st); }
+            else { if (v == STAGE_LDS4) launch_lds<float, 4>(s, x, y, nrhs, st); else launch_lds<float, 2>(s, x, y, nrhs, st); }
+            check_launch("stage (LDS-staged input)");
+            return;
+        }
     }
     if (v > 0) {
         if (dbl) launch_variant<double>(v, s, x, y, nrhs, st);
@@ -1958,6 +2115,8 @@ static void stage_multi_variant(int v, StageMultiArgs &a, const StageDev *s, int
         case 3: stage_multi_go<R, 1, 2>(a, s, cap, st); break;
         case 4: stage_multi_go<R, 2, 2>(a, s, cap, st); break;
         case 5: stage_multi_go<R, 1, 1>(a, s, cap, st); break;
+        case 8: stage_multi_go<R, 4, 4>(a, s, cap, st); break;
+        case 9: stage_multi_go<R, 4, 2>(a, s, cap, st); break;
         default: stage_multi_go<R, 2, 1>(a, s, cap, st); break;
     }
 }

@@ -18,10 +18,15 @@ struct StageDev {
 };
 
 // Number of stage kernel variants and the heuristic choice for a launch: 0 the
-// vector kernel (one thread per output entry), 1..6 matrix-core tilings, 7 the
-// small-batch kernel (64 rows x 4 k-slices per workgroup, for fewer than 16 columns).
-constexpr int STAGE_VARIANTS = 8;
+// vector kernel (one thread per output entry), 1..6 and 8, 9 matrix-core tilings
+// (16*MT rows x 16*NT columns per wave: 1 MT1 NT4, 2 MT2 NT4, 3 MT1 NT2, 4 MT2 NT2,
+// 5 MT1 NT1, 6 MT2 NT1, 8 MT4 NT4, 9 MT4 NT2), 7 the small-batch kernel (64 rows x 4
+// k-slices per workgroup, for fewer than 16 columns), 10 and 11 the matrix-core
+// kernel with the input staged in LDS and shared by a workgroup's four waves (one
+// block of up to 192 rows per workgroup, 64 or 32 columns).
+constexpr int STAGE_VARIANTS = 12;
 constexpr int STAGE_SMALL_BATCH = 7;
+constexpr int STAGE_LDS4 = 10, STAGE_LDS2 = 11;
 int stage_default_variant(const StageDev &s, bool dbl, int nrhs);
 
 // Two consecutive stages a, b fused in one launch (the intermediate stays in LDS).

@@ -31,7 +31,7 @@ PHASE_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ct
 AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
-EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_stage_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error", "fio_set_trace", "fio_column_id"]
@@ -94,6 +94,8 @@ def load_library():
     lib.fio_build.argtypes = [ctypes.POINTER(fio_problem), ctypes.POINTER(P)]
     lib.fio_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, VP, VP, I64, I64, VP]
     lib.fio_stage_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
+    lib.fio_stage_apply_variant.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64,
+                                            VP]
     lib.fio_stage_pair_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
     lib.fio_column_id.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, VP, ctypes.c_int64, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_int), VP, VP, ctypes.c_int64]
@@ -237,6 +239,12 @@ def fio_apply(plan: Plan, op: int, dtype: int, x, y, nrhs: int, ld: int, stream=
 def fio_stage_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
     _check(load_library().fio_stage_apply(plan.handle, op, stage, dtype, _ptr(x), _ptr(y), nrhs,
                                           _stream(stream)))
+
+
+def fio_stage_apply_variant(plan: Plan, op: int, stage: int, dtype: int, variant: int, x, y, nrhs: int,
+                            stream=None):
+    _check(load_library().fio_stage_apply_variant(plan.handle, op, stage, dtype, variant, _ptr(x), _ptr(y), nrhs,
+                                                  _stream(stream)))
 
 
 def fio_stage_pair_apply_variant(plan: Plan, op: int, stage: int, dtype: int, variant: int, x, y, nrhs: int,

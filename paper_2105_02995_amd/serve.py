@@ -374,16 +374,36 @@ class GpuExecutor:
                           [b for _, _, _, b in members], [self._N(k) for k, _, _, _ in members],
                           maxit=self.refine, stream=s)
 
+    GROUP_SPREAD = 4.0  # batches of one group differ in estimated work by at most this factor
+
+    def _work(self, batch):
+        """Estimated work of a batch: butterfly nonzeros times padded columns."""
+        return float(self.stats[batch.key]["bf_nnz"]) * self._bucket(batch.nrhs)
+
+    def _groups(self, batches):
+        """Index groups of batches of similar work (a small solve grouped with a large
+        one would wait for it), at most MULTI_MAX each, keys in a fixed order."""
+        order = sorted(range(len(batches)), key=lambda i: self._work(batches[i]))
+        groups, cur = [], []
+        for i in order:
+            if cur and (len(cur) == self.MULTI_MAX or
+                        self._work(batches[i]) > self.GROUP_SPREAD * self._work(batches[cur[0]])):
+                groups.append(cur)
+                cur = []
+            cur.append(i)
+        if cur:
+            groups.append(cur)
+        return [sorted(g, key=lambda i: batches[i].key) for g in groups]
+
     def start_group(self, batches, now):
-        """Several batches of different keys as multi-instance solves (groups of up
-        to MULTI_MAX, one stream each); returns one handle per batch."""
+        """Several batches of different keys as multi-instance solves (groups of
+        similar work, up to MULTI_MAX, one stream each; a batch left alone runs its
+        own solve); returns one handle per batch."""
         if not self.use_multi:
             return [self.start(b, now) for b in batches]
         torch = self.torch
         handles = [None] * len(batches)
-        order = sorted(range(len(batches)), key=lambda i: batches[i].key)
-        for g0 in range(0, len(order), self.MULTI_MAX):
-            idx = order[g0:g0 + self.MULTI_MAX]
+        for idx in self._groups(batches):
             if len(idx) == 1:
                 handles[idx[0]] = self.start(batches[idx[0]], now)
                 continue

@@ -159,3 +159,29 @@ def test_oversized_request_is_refused_before_anything_runs():
     assert s.batches_started == 0
     with pytest.raises(ValueError):
         s.submit(ServeRequest(2, _key(0), 0.0, np.zeros((4, 0))))
+
+
+def test_multi_instance_groups_hold_batches_of_similar_work():
+    """The GPU executor groups batches admitted together into multi-instance solves
+    only when their estimated work (butterfly nonzeros x padded columns) is within a
+    factor GROUP_SPREAD; a much larger batch runs on its own, and no group exceeds
+    MULTI_MAX instances."""
+    from paper_2105_02995_amd.serve import Batch, GpuExecutor
+
+    class Fake(GpuExecutor):
+        def __init__(self, stats):  # no device: only the grouping logic
+            self.stats = stats
+            self.max_batch_rhs = 256
+
+    nnz = {("k%d" % i,): 1e6 * (1 + i % 3) for i in range(10)}
+    nnz[("big",)] = 1e9
+    ex = Fake({k: {"bf_nnz": v} for k, v in nnz.items()})
+    batches = [Batch(k, [], 16, 0) for k in nnz]
+    groups = ex._groups(batches)
+    assert sorted(i for g in groups for i in g) == list(range(len(batches)))
+    for g in groups:
+        assert len(g) <= ex.MULTI_MAX
+        w = [ex._work(batches[i]) for i in g]
+        assert max(w) <= ex.GROUP_SPREAD * min(w)
+    big = [g for g in groups if any(batches[i].key == ("big",) for i in g)]
+    assert len(big) == 1 and len(big[0]) == 1
