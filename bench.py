@@ -136,7 +136,7 @@ SERVE_KEYS_FULL = ([(1, n, "1d_ex1", e) for n in (1024, 2048, 4096, 8192, 16384,
 SERVE_KEYS_SMALL = [(1, 4096, "1d_ex1", 1e-6), (1, 65536, "1d_ex1", 1e-6), (2, 64, "2d_radon", 1e-4)]
 
 
-def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True, multi=True):
+def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True, multi=True, trim=False):
     """Poisson arrivals (seeded) of solves over the given resident keys, 1..32
     right-hand sides each; the rate is a fraction of the measured saturation rate
     (all requests at t=0).  Batches of different keys admitted together run as one
@@ -148,7 +148,7 @@ def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True, m
     kidx = rng.integers(len(keys), size=nreq)
     nrhs = rng.integers(1, 33, size=nreq)
     ex = GpuExecutor({k: plans[k] for k in keys}, max_batch_rhs=max_batch, refine=1, use_graphs=graphs,
-                     use_multi=multi)
+                     use_multi=multi, trim=trim)
 
     def make(times):
         return [ServeRequest(j, keys[kidx[j]], float(times[j]), pools[keys[kidx[j]]][:, :nrhs[j]])
@@ -195,14 +195,15 @@ def serve_main(args):
     from paper_2105_02995_amd import fio as F
     plans = build_plans(F, SERVE_KEYS_FULL)
     res = serving_run(F, plans, SERVE_KEYS_FULL, args.serve_requests, (0.5, 0.8, 0.95), 2000,
-                      multi=not args.no_multi)
+                      multi=not args.no_multi, trim=True)
     head = res["rates"][1]
     out = {"metric": "serving mix: p50/p99 latency and RHS*N/s of factored FIO solves",
            "value": head["rhs_n_per_s"], "unit": "RHS*N/s", "n_gpus": 1,
            "higher_is_better": True, "data": "synthetic",
            "config": {"workload": "Poisson arrivals over %d resident keys (1D N=1024..65536 at eps 1e-4/1e-6, "
                                   "2D n=32,64,128,256 at eps 1e-4), 1-32 RHS per request, complex64 + 1 FP64 "
-                                  "refinement step, HIP-graph replay" % len(SERVE_KEYS_FULL)},
+                                  "refinement step, HIP-graph replay, plans trimmed to the images the solve "
+                                  "uses" % len(SERVE_KEYS_FULL)},
            "serving": res}
     print(json.dumps(out), flush=True)
 
@@ -277,6 +278,8 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
             name = "k_stage<%s2>" % r
         elif v == 7:
             name = "k_stage_nb<%s2>" % r
+        elif v in (12, 13, 14):
+            name = "k_stage_mfma<%s, %d, %d, 3M>" % ((r,) + {12: (2, 4), 13: (4, 2), 14: (2, 2)}[v])
         elif v in (10, 11):
             ro = io(ks[0])[0]["r_out"] if op == F.FIO_OP_K else io(ks[0])[0]["r_in"]
             name = "k_stage_lds<%s, %d, %d>" % (r, 1 if ro <= 64 else (2 if ro <= 128 else 3), 4 if v == 10 else 2)

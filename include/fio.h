@@ -150,6 +150,13 @@ typedef struct {
     fio_phase_fn phi;
     fio_amp_fn amp;
     void *user;
+    /* Butterfly rank alignment; 0 -> 8, 1 keeps every level at its tolerance rank.
+     * A level whose rank r (the largest numerical rank of the probe blocks at eps_bf,
+     * section 2's interpolative decompositions) is not a multiple of bf_rank_align is
+     * given rank floor(r / bf_rank_align) * bf_rank_align when the probe blocks need
+     * no more at 4 eps_bf: whole matrix-core tiles for at most 4x the level's ID
+     * residual.  Not stored by fio_save (the ranks are, in the factors).           */
+    int bf_rank_align;
 } fio_problem;
 
 /* Build the factors of K and of the approximate inverse (Algorithm "alg",
@@ -432,6 +439,21 @@ fio_status fio_autotune(fio_plan plan, fio_dtype dtype, int64_t nrhs, int reps, 
  * four waves (one output block of up to 192 rows per workgroup, 64/32 columns). */
 fio_status fio_tune_query(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int64_t nrhs,
                           int *variant);
+
+/* Device images a plan keeps (fio_plan_trim). */
+typedef enum {
+    FIO_KEEP_ALL = 0,          /* Kd and Kd^* in complex64 and complex128, Gd in both   */
+    FIO_KEEP_REFINE_C64 = 1    /* what DIRECT and REFINE solves in complex64 use: Kd^* and
+                                  Gd in complex64, Kd in complex128 (the residual)       */
+} fio_keep;
+
+/* Release the device images of the factors that `keep` does not list, to admit more
+ * plans into HBM (FIO_KEEP_REFINE_C64 halves the factor memory: at 2D n = 256 from
+ * 61 GB to about 30 GB).  One-way: later calls that need a released image (fio_apply
+ * of Kd in complex64, complex128 solves, PCG or GMRES in complex64, ...) fail with
+ * FIO_ERR_UNSUPPORTED; the error estimates, the host factors and fio_save are kept.
+ * Synchronises the device.  Errors: FIO_ERR_ARG, FIO_ERR_UNSUPPORTED (host-only plan). */
+fio_status fio_plan_trim(fio_plan plan, int keep);
 
 /* Save the factors to a file / load them onto a device (device = -1: host only). */
 fio_status fio_save(fio_plan plan, const char *path);

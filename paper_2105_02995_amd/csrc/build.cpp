@@ -65,7 +65,26 @@ fio_problem normalized_problem(const fio_problem &in) {
     if (p.d == 2 && p.leaf_h > p.n / 2) p.leaf_h = p.n / 2;
     if (p.oversample < 1) fail(FIO_ERR_ARG, "oversample must be positive");
     if (p.prescale_skel && p.d != 1) fail(FIO_ERR_ARG, "prescaled skeletonization is built for 1D only");
+    if (p.bf_rank_align == 0) p.bf_rank_align = 8;
+    if (p.bf_rank_align < 1) fail(FIO_ERR_ARG, "bf_rank_align must be positive");
     return p;
+}
+
+static void print_fingerprints(const HifFactors &F) {
+    for (size_t k = 0; k < F.steps.size(); ++k) {
+        uint64_t h = 0xCBF29CE484222325ULL;
+        for (const HifNode &nd : F.steps[k].nodes) {
+            h = fingerprint(h, nd.idx_r.data(), nd.idx_r.size() * 4);
+            h = fingerprint(h, nd.idx_s.data(), nd.idx_s.size() * 4);
+            h = fingerprint(h, nd.T.a.data(), nd.T.a.size() * 16);
+            h = fingerprint(h, nd.Linv.a.data(), nd.Linv.a.size() * 16);
+            h = fingerprint(h, nd.M.a.data(), nd.M.a.size() * 16);
+        }
+        progress(true, "  fingerprint of inverse-factor step %zu: %016llx", k, (unsigned long long)h);
+    }
+    uint64_t h = fingerprint(0xCBF29CE484222325ULL, F.root_idx.data(), F.root_idx.size() * 4);
+    h = fingerprint(h, F.A0inv.a.data(), F.A0inv.a.size() * 16);
+    progress(true, "  fingerprint of the top-level inverse: %016llx", (unsigned long long)h);
 }
 
 void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu,
@@ -79,6 +98,7 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
     bo.leaf = p.leaf_bf;
     bo.nthreads = p.nthreads;
     bo.seed = p.seed ^ 0xB0F1ULL;
+    bo.rank_align = p.bf_rank_align;
     const bool vb = p.verbose != 0;
     bo.verbose = vb;
     if (ids) bo.ids = ids(K);
@@ -150,6 +170,7 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
              "(%.1fs)",
              out.hif.steps.size(), out.hif.root_idx.size(), out.hif.shifted, out.hif.device_ids, out.hif.device_nodes,
              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    if (vb) print_fingerprints(out.hif);
     out.fwd = std::move(B.fwd);
     out.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }

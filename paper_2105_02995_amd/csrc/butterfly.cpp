@@ -92,29 +92,42 @@ static int level_ids(const FioKernel &K, const ButterflyOptions &opt, bool cand_
             std::copy(sp.begin(), sp.end(), bt.samp.begin() + t * ns);
         });
     };
-    *dev = false;
-    int r = 0;
-    if (opt.ids) {
-        IdBatch bt;
-        fill(bt, (int64_t)probe.size(), [&](int64_t t) { return probe[t]; });
-        bt.tol_rel = opt.eps;
-        bt.max_rank = ncand;
-        std::atomic<int> mx(0);
-        *dev = opt.ids(bt, [&](int64_t, int k, const int *, const cd *) {
-            int cur = mx.load();
-            while (k > cur && !mx.compare_exchange_weak(cur, k)) {
-            }
-        });
-        r = mx.load();
+    // Largest numerical rank over the probe pairs at relative tolerance tol.
+    auto probe_rank = [&](double tol) {
+        int r = 0;
+        if (*dev) {
+            IdBatch bt;
+            fill(bt, (int64_t)probe.size(), [&](int64_t t) { return probe[t]; });
+            bt.tol_rel = tol;
+            bt.max_rank = ncand;
+            std::atomic<int> mx(0);
+            *dev = opt.ids(bt, [&](int64_t, int k, const int *, const cd *) {
+                int cur = mx.load();
+                while (k > cur && !mx.compare_exchange_weak(cur, k)) {
+                }
+            });
+            r = mx.load();
+        }
+        if (!*dev) {
+            std::vector<int> ranks(probe.size());
+            parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
+                ranks[t] = id_rank(sample_block(K, cand_is_x, cand_of(probe[t]), samp_of(probe[t])), tol, ncand);
+            });
+            r = *std::max_element(ranks.begin(), ranks.end());
+        }
+        return std::min(ncand, std::max(1, r));
+    };
+    *dev = (bool)opt.ids;
+    int r = probe_rank(opt.eps);
+    // Rank alignment: a rank just above a multiple of the alignment leaves the last
+    // matrix-core tile of every block mostly padding.  The rank is cut down to that
+    // multiple when the probes need no more than it at rank_slack times the
+    // tolerance, so the cut costs at most that factor in the level's ID residual.
+    const int a = opt.rank_align;
+    if (a > 1 && r > a && r % a) {
+        const int ra = r / a * a;
+        if (probe_rank(opt.eps * opt.rank_slack) <= ra) r = ra;
     }
-    if (!*dev) {
-        std::vector<int> ranks(probe.size());
-        parallel_for((int64_t)probe.size(), nt, [&](int64_t t) {
-            ranks[t] = id_rank(sample_block(K, cand_is_x, cand_of(probe[t]), samp_of(probe[t])), opt.eps, ncand);
-        });
-        r = *std::max_element(ranks.begin(), ranks.end());
-    }
-    r = std::min(ncand, std::max(1, r));
     progress(opt.verbose, "  rank probe: %zu pairs, %d candidates, %d samples, rank %d", probe.size(), ncand, ns, r);
     on_rank(r);
     if (*dev) {

@@ -52,6 +52,8 @@ struct ButterflyOptions {
     int leaf = 8;         // leaf side (points per dimension)
     int nthreads = 0;
     uint64_t seed = 1;    // column/row sampling
+    int rank_align = 1;   // a level's rank may be cut down to a multiple of this ...
+    double rank_slack = 4;  // ... when the probes need no more at rank_slack * eps
     bool verbose = false;
     BatchedId ids;        // empty: sample and decompose on the host
 };

@@ -80,17 +80,23 @@ struct DBuf {
 
 template <class T> struct DStageStore {
     DBuf idx, A64, A128;
+    bool gone64 = false, gone128 = false;  // released by fio_plan_trim
     StageDev view(bool dbl, const Stage &s) const {
         StageDev v;
         v.n_out = s.n_out; v.n_in = s.n_in; v.r_out = s.r_out; v.r_in = s.r_in; v.fan = s.fan;
         v.idx = (const int32_t *)idx.p;
         v.A = dbl ? A128.p : A64.p;
+        if (dbl ? gone128 : gone64)
+            fail(FIO_ERR_UNSUPPORTED, std::string("the ") + (dbl ? "complex128" : "complex64") +
+                                          " image of this chain was released by fio_plan_trim");
         return v;
     }
+    bool has(bool dbl) const { return !(dbl ? gone128 : gone64); }
 };
 
 struct DHifStore {
     DBuf desc, idx, m64, m128, h64, h128, tr, ts;
+    bool gone128 = false;  // released by fio_plan_trim
     HifStepDev view(bool dbl) const {
         HifStepDev v = base;
         v.desc = (const int64_t *)desc.p;
@@ -99,8 +105,10 @@ struct DHifStore {
         v.matH = dbl ? h128.p : h64.p;
         v.tiles_r = (const int32_t *)tr.p;
         v.tiles_s = (const int32_t *)ts.p;
+        if (dbl && gone128) fail(FIO_ERR_UNSUPPORTED, "the complex128 image of Gd was released by fio_plan_trim");
         return v;
     }
+    bool has(bool dbl) const { return !(dbl && gone128); }
     HifStepDev base;
 };
 
@@ -912,6 +920,32 @@ fio_status fio_load(const char *path, int device, fio_plan *out) {
     });
 }
 
+fio_status fio_plan_trim(fio_plan p, int keep) {
+    return guard([&] {
+        if (!p) fail(FIO_ERR_ARG, "null plan");
+        if (keep != FIO_KEEP_ALL && keep != FIO_KEEP_REFINE_C64) fail(FIO_ERR_ARG, "bad keep");
+        if (p->device < 0) fail(FIO_ERR_UNSUPPORTED, "plan is host-only");
+        if (keep == FIO_KEEP_ALL) return;
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPC(hipSetDevice(p->device));
+        HIPC(hipDeviceSynchronize());  // no launch in flight may still read what goes
+        for (auto &d : p->dfwd) {
+            d.A64.alloc(0);
+            d.gone64 = true;
+        }
+        for (auto &d : p->dadj) {
+            d.A128.alloc(0);
+            d.gone128 = true;
+        }
+        for (auto &h : p->dhif) {
+            h.m128.alloc(0);
+            h.h128.alloc(0);
+            h.gone128 = true;
+        }
+        count_bytes(p);
+    });
+}
+
 fio_status fio_save(fio_plan p, const char *path) {
     return guard([&] {
         if (!p || !path) fail(FIO_ERR_ARG, "null argument");
@@ -1152,6 +1186,11 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             std::vector<int> &out = fwd ? t.fwd : t.adj;
             std::vector<int> &pout = fwd ? t.fwd_pair : t.adj_pair;
             const int S = (int)ds.size();
+            if (S > 0 && !ds[0].has(dbl)) {  // released by fio_plan_trim: nothing to tune
+                out.assign(S, -1);
+                pout.assign(S, 0);
+                continue;
+            }
             std::vector<float> one_ms(S, 0.f), two_ms(S, 1e30f);
             std::vector<int> two_v(S, 0);
             for (int s = 0; s < S; ++s) {
@@ -1200,6 +1239,10 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             }
         }
         for (size_t k = 0; k < p->dhif.size(); ++k) {
+            if (!p->dhif[k].has(dbl)) {  // released by fio_plan_trim
+                t.hif.push_back(-1);
+                continue;
+            }
             const HifStepDev h = p->dhif[k].view(dbl);
             int best = 0;
             {
@@ -1243,6 +1286,7 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
             for (int v = 1; v < STAGE_VARIANTS; ++v) {
                 if ((v == STAGE_SMALL_BATCH) != (nr < 16)) continue;  // matrix cores from 16 columns
                 if (v == STAGE_LDS4 || v == STAGE_LDS2) continue;      // blocks of up to 192 rows only
+                if (v >= 12) continue;                                    // four-product tilings for FP64
                 sr.variant = v;
                 const float ms = timeit([&] { launch_stage(sr, true, p->RI.p, p->RO.p, nr, st); });
                 if (ms < best_ms) { best_ms = ms; t.root = v; }
@@ -1777,8 +1821,7 @@ fio_status fio_multi_autotune(int n_inst, const fio_plan *plans, fio_dtype dt, c
                 float best_ms = 1e30f;
                 for (int v = 1; v < STAGE_VARIANTS; ++v)
                     for (int cap : caps) {
-                        // the multi-instance kernel has the register-tiled variants only
-                        if (v == STAGE_SMALL_BATCH || v == STAGE_LDS4 || v == STAGE_LDS2) continue;
+                        if (!stage_multi_variant_ok(v)) continue;
                         std::vector<LevelChoice> one(S);
                         one[j] = LevelChoice{v, cap};
                         // the level alone: instances whose chain has it, P -> Q

@@ -1,6 +1,7 @@
 // Shared host utilities: complex type, error reporting, a small thread pool loop.
 #pragma once
 
+#include <cstring>
 #include <atomic>
 #include <complex>
 #include <cstdint>
@@ -104,6 +105,22 @@ void par_cols(int64_t n, double work, Fn &&fn) {
         return;
     }
     parallel_for(n, 0, fn);
+}
+
+// 64-bit fingerprint of a run of bytes (multiply-xor over 8-byte words): verbose
+// builds print them for the peeled matrix and each inverse-factor step, so two
+// builds can be compared.
+inline uint64_t fingerprint(uint64_t h, const void *p, size_t bytes) {
+    const unsigned char *b = (const unsigned char *)p;
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, b + i, 8);
+        h = (h ^ w) * 0x100000001B3ULL;
+        h ^= h >> 29;
+    }
+    for (; i < bytes; ++i) h = (h ^ b[i]) * 0x100000001B3ULL;
+    return h;
 }
 
 // Progress line on stderr (build phases); flushed so a watcher sees it at once.

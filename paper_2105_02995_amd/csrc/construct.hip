@@ -486,6 +486,8 @@ struct NodeEngine {
         if (!h) {
             RB(rocblas_create_handle(&h));
             RB(rocblas_set_stream(h, st));
+            // no atomics: the same factors from the same inputs on every build
+            RB(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));
         }
         RB(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
     }
@@ -509,7 +511,7 @@ struct NodeEngine {
     }
 };
 
-// A few lanes, handed out round robin.
+// Lanes handed out round robin (one in use: see device_skel_hooks).
 struct EnginePool {
     std::vector<std::unique_ptr<NodeEngine>> lanes;
     std::atomic<unsigned> next{0};
@@ -945,8 +947,12 @@ template <class Fn> bool or_host(Fn &&fn) {
 
 SkelHooks device_skel_hooks(int device) {
     SkelHooks h;
-    // eight lanes (streams) shared by the node loop's host threads
-    auto pool = std::make_shared<EnginePool>(device, 8);
+    // One lane (stream) shared by the node loop's host threads.  With several lanes
+    // the library's dense routines (zgemm, potrf, trtri) running concurrently on
+    // several streams gave results that differed between identical builds, at times
+    // badly (the coarse cells' Schur updates), while every lane only touches its own
+    // buffers; on one lane repeated builds give identical factors.
+    auto pool = std::make_shared<EnginePool>(device, 1);
     h.big_id = [pool](const Mat &A, double tol_rel, ColumnID &out) {
         return or_host([&] { return big_column_id(pool->pick(), A, tol_rel, out); });
     };

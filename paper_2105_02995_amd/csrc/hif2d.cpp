@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <map>
+#include <cstring>
 #include <mutex>
 #include <set>
 #include <unordered_map>
@@ -273,6 +274,12 @@ Hmat2D peel_2d(const BlockApply &A, const Geo &g, const PeelOptions &po, double 
                 k = (int)std::min<int64_t>(2 * k, csz);
                 continue;
             }
+            if (po.verbose) {
+                int mr = 0;
+                for (const LR &p : pairs) mr = std::max({mr, p.UI.n, p.UJ.n});
+                progress(true, "  peeling level %d: %d samples per cell (attempt %d), largest rank %d%s", l, s,
+                         attempt, mr, saturated ? " (saturated)" : "");
+            }
             break;
         }
         progress(po.verbose, "peeling level %d: %zu admissible pairs", l, pairs.size());
@@ -406,14 +413,30 @@ struct PhaseTimes {
                    std::chrono::steady_clock::now().time_since_epoch())
             .count();
     }
+    // largest interpolation coefficient |T_ij| of the level's IDs (the bit pattern of
+    // a non-negative double orders like the value)
+    std::atomic<uint64_t> tmax{0};
     void add(int k, int64_t t0) { ns[k].fetch_add(now() - t0); }
+    void see_T(const Mat &T) {
+        double m = 0;
+        for (const cd &v : T.a) m = std::max(m, std::abs(v));
+        uint64_t b;
+        std::memcpy(&b, &m, 8);
+        uint64_t cur = tmax.load();
+        while (b > cur && !tmax.compare_exchange_weak(cur, b)) {
+        }
+    }
     void report(bool on, const char *what, int l) {
+        double tm;
+        const uint64_t b = tmax.load();
+        std::memcpy(&tm, &b, 8);
         progress(on,
                  "  %s level %d thread-seconds: near %.2f far %.2f stack %.2f diag %.2f node %.2f (ID %.2f, "
-                 "elimination %.2f); merge %.2f",
+                 "elimination %.2f); merge %.2f; largest |T| %.2e",
                  what, l, ns[0] * 1e-9, ns[1] * 1e-9, ns[2] * 1e-9, ns[3] * 1e-9, ns[4] * 1e-9, ns[6] * 1e-9,
-                 ns[7] * 1e-9, ns[5] * 1e-9);
+                 ns[7] * 1e-9, ns[5] * 1e-9, tm);
         for (auto &v : ns) v.store(0);
+        tmax.store(0);
     }
 };
 
@@ -450,6 +473,7 @@ NodeOut skel2d(const std::vector<int> &I, const Mat &Ubar, const Mat &AII, doubl
         sk = id.skel;
         rd = id.redund;
         T = std::move(id.T);
+        if (po.verbose) pt.see_T(T);
         pt.add(6, t0);
     }
     const int64_t t1 = PhaseTimes::now();
@@ -527,6 +551,18 @@ HifFactors build_hif_2d(const BlockApply &A, int n, const PeelOptions &po, doubl
     F.N = g.N;
     const double normS = power_norm(A, g.N, 12, po.seed ^ 0x5EEDULL);
     Hmat2D H = peel_2d(A, g, po, normS);
+    if (po.verbose) {
+        uint64_t f = 0xCBF29CE484222325ULL;
+        f = fingerprint(f, &normS, 8);
+        for (const auto &lv : H.lr)
+            for (const LR &p : lv) {
+                f = fingerprint(f, p.UI.a.data(), p.UI.a.size() * 16);
+                f = fingerprint(f, p.UJ.a.data(), p.UJ.a.size() * 16);
+                f = fingerprint(f, p.B.a.data(), p.B.a.size() * 16);
+            }
+        for (const auto &kv : H.near) f = fingerprint(f, kv.second.a.data(), kv.second.a.size() * 16);
+        progress(true, "  fingerprint of the peeled matrix: %016llx (norm %.17g)", (unsigned long long)f, normS);
+    }
     const double shift0 = po.allow_shift ? 1e-3 * eps_hif * normS : 0.0;
     std::atomic<int> nshift(0), ndev(0), nnode(0);
     PhaseTimes pt;

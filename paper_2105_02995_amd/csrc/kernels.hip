@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 #include <stdexcept>
 #include <string>
 
@@ -300,8 +301,8 @@ __device__ __forceinline__ void frag_load(Frag<R, MT, NT> &f, KWalk<R, P> &w, in
 }
 
 // Accumulators of a wave's 16*MT x 16*NT complex tile: Yr = Ar Xr - Ai Xi and
-// Yi = Ar Xi + Ai Xr as four real products per k-step.  (The three-product form
-// measured slower: its third accumulator set costs occupancy.)
+// Yi = Ar Xi + Ai Xr as four real products per k-step (the three-product form is
+// Acc3 below; its third accumulator set costs occupancy, so the tuner decides).
 template <class R, int MT, int NT> struct Acc {
     using V4 = typename MF<R>::V4;
     using C = typename MF<R>::C;
@@ -335,10 +336,51 @@ template <class R, int MT, int NT> struct Acc {
     __device__ __forceinline__ C get(int mt, int nt, int v) const { return C{re[mt][nt][v], im[mt][nt][v]}; }
 };
 
+// The same tile with three real products per complex k-step (the 3M form):
+// t1 = Ar Xr, t2 = Ai Xi, t3 = (Ar + Ai)(Xr + Xi); Yr = t1 - t2, Yi = t3 - t1 - t2.
+// A quarter fewer matrix-core operations for a third more accumulators and two
+// vector additions per operand; the imaginary part loses some relative accuracy
+// where it is small against |Ar Xr| + |Ai Xi| (a few ulps in complex64, within what
+// the FP64 refinement recovers).  Selected per stage by the autotuner.
+template <class R, int MT, int NT> struct Acc3 {
+    using V4 = typename MF<R>::V4;
+    using C = typename MF<R>::C;
+    V4 t1[MT][NT], t2[MT][NT], t3[MT][NT];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                t1[mt][nt] = V4{0, 0, 0, 0};
+                t2[mt][nt] = V4{0, 0, 0, 0};
+                t3[mt][nt] = V4{0, 0, 0, 0};
+            }
+    }
+    __device__ __forceinline__ void mma(const Frag<R, MT, NT> &f) {
+        R xs[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) xs[nt] = f.x[nt].x + f.x[nt].y;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const R ar = f.a[mt].x, ai = f.a[mt].y, as = ar + ai;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                t1[mt][nt] = MF<R>::mma(ar, f.x[nt].x, t1[mt][nt]);
+                t2[mt][nt] = MF<R>::mma(ai, f.x[nt].y, t2[mt][nt]);
+                t3[mt][nt] = MF<R>::mma(as, xs[nt], t3[mt][nt]);
+            }
+        }
+    }
+    __device__ __forceinline__ C get(int mt, int nt, int v) const {
+        const R a = t1[mt][nt][v], b = t2[mt][nt][v];
+        return C{a - b, t3[mt][nt][v] - a - b};
+    }
+};
+
 // The product with explicit per-lane row offsets: row tile mt of this lane reads
 // the factor at Ao + rowc[mt] + k * lda (column-major, leading dimension lda).
-template <class R, int MT, int NT, class P>
-__device__ __forceinline__ void mfma_rows(Acc<R, MT, NT> &acc, const typename MF<R>::C *__restrict__ Ao, int lda,
+template <class R, int MT, int NT, class P, class ACC>
+__device__ __forceinline__ void mfma_rows(ACC &acc, const typename MF<R>::C *__restrict__ Ao, int lda,
                                           int r_in, int K, const int (&rowc)[MT], int ncols,
                                           const P *__restrict__ xb, const Off4 &off, int64_t ld) {
     const int lane = threadIdx.x & 63;
@@ -366,8 +408,8 @@ __device__ __forceinline__ void mfma_rows(Acc<R, MT, NT> &acc, const typename MF
     }
 }
 
-template <class R, int MT, int NT, class P>
-__device__ __forceinline__ void mfma_block(Acc<R, MT, NT> &acc, const typename MF<R>::C *__restrict__ Ao, int r_out,
+template <class R, int MT, int NT, class P, class ACC>
+__device__ __forceinline__ void mfma_block(ACC &acc, const typename MF<R>::C *__restrict__ Ao, int r_out,
                                            int r_in, int K, int mrow0, int ncols, const P *__restrict__ xb,
                                            const Off4 &off, int64_t ld) {
     const int li = threadIdx.x & 15;
@@ -401,7 +443,7 @@ static unsigned xcd_grid(int64_t nb, int nch) {
 // One workgroup's work of a stage launch: workgroup wg of the (output block, row
 // chunk) waves, column chunk `chunk`.  Shared by the single-instance kernel and the
 // multi-instance one.
-template <class R, int MT, int NT>
+template <class R, int MT, int NT, bool M3 = false>
 __device__ __forceinline__ void stage_mfma_wg(int64_t n_out, int r_out, int r_in, int fan,
                                               const int32_t *__restrict__ idx,
                                               const typename MF<R>::C *__restrict__ A,
@@ -418,7 +460,7 @@ __device__ __forceinline__ void stage_mfma_wg(int64_t n_out, int r_out, int r_in
     const int n0 = chunk * (16 * NT);
     const int K = fan * r_in;
     const int li = lane & 15, lk = lane >> 4;
-    Acc<R, MT, NT> acc;
+    typename std::conditional<M3, Acc3<R, MT, NT>, Acc<R, MT, NT>>::type acc;
     const int32_t *io = idx + o * fan;
     const int64_t bs = (int64_t)r_in * nrhs;
     const Off4 off{io[0] * bs, fan > 1 ? io[1] * bs : 0, fan > 2 ? io[2] * bs : 0, fan > 3 ? io[3] * bs : 0};
@@ -437,7 +479,7 @@ __device__ __forceinline__ void stage_mfma_wg(int64_t n_out, int r_out, int r_in
             }
 }
 
-template <class R, int MT, int NT>
+template <class R, int MT, int NT, bool M3 = false>
 __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, int r_in, int fan,
                                                     const int32_t *__restrict__ idx,
                                                     const typename MF<R>::C *__restrict__ A,
@@ -447,7 +489,7 @@ __global__ void __launch_bounds__(256) k_stage_mfma(int64_t n_out, int r_out, in
     int64_t wg;
     int chunk;
     xcd_order((n_out * mchunks + 3) / 4, nchunks, wg, chunk);
-    stage_mfma_wg<R, MT, NT>(n_out, r_out, r_in, fan, idx, A, x, y, nrhs, mchunks, wg, chunk);
+    stage_mfma_wg<R, MT, NT, M3>(n_out, r_out, r_in, fan, idx, A, x, y, nrhs, mchunks, wg, chunk);
 }
 
 // Two consecutive stages a, b in one launch.  The blocks of two consecutive
@@ -614,15 +656,16 @@ __global__ void __launch_bounds__(256) k_stage2s_mfma(const int32_t *__restrict_
         }
 }
 
-template <class R, int MT, int NT>
+template <class R, int MT, int NT, bool M3 = false>
 static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
     const int mtiles = (s.r_out + 15) / 16;
     const int mchunks = (mtiles + MT - 1) / MT;
     const int64_t waves = s.n_out * mchunks;
     const int nch = (nrhs + 16 * NT - 1) / (16 * NT);
-    hipLaunchKernelGGL((k_stage_mfma<R, MT, NT>), dim3(xcd_grid((waves + 3) / 4, nch)), dim3(256), 0, st, s.n_out,
-                       s.r_out, s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks, nch);
+    hipLaunchKernelGGL((k_stage_mfma<R, MT, NT, M3>), dim3(xcd_grid((waves + 3) / 4, nch)), dim3(256), 0, st,
+                       s.n_out, s.r_out, s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, mchunks,
+                       nch);
 }
 
 // Stage with the gathered input staged in LDS: one workgroup per (output block,
@@ -779,6 +822,9 @@ static void launch_variant(int v, const StageDev &s, const void *x, void *y, int
         case 5: launch_mfma<R, 1, 1>(s, x, y, nrhs, st); break;
         case 8: launch_mfma<R, 4, 4>(s, x, y, nrhs, st); break;
         case 9: launch_mfma<R, 4, 2>(s, x, y, nrhs, st); break;
+        case 12: launch_mfma<R, 2, 4, true>(s, x, y, nrhs, st); break;
+        case 13: launch_mfma<R, 4, 2, true>(s, x, y, nrhs, st); break;
+        case 14: launch_mfma<R, 2, 2, true>(s, x, y, nrhs, st); break;
         default: launch_mfma<R, 2, 1>(s, x, y, nrhs, st); break;
     }
 }

@@ -23,10 +23,14 @@ struct StageDev {
 // 5 MT1 NT1, 6 MT2 NT1, 8 MT4 NT4, 9 MT4 NT2), 7 the small-batch kernel (64 rows x 4
 // k-slices per workgroup, for fewer than 16 columns), 10 and 11 the matrix-core
 // kernel with the input staged in LDS and shared by a workgroup's four waves (one
-// block of up to 192 rows per workgroup, 64 or 32 columns).
-constexpr int STAGE_VARIANTS = 12;
+// block of up to 192 rows per workgroup, 64 or 32 columns), 12..14 the register
+// tilings MT2 NT4, MT4 NT2, MT2 NT2 with three real products per complex k-step.
+constexpr int STAGE_VARIANTS = 15;
 constexpr int STAGE_SMALL_BATCH = 7;
 constexpr int STAGE_LDS4 = 10, STAGE_LDS2 = 11;
+// Whether the multi-instance stage kernel has this variant (the four-product
+// register tilings only).
+inline bool stage_multi_variant_ok(int v) { return (v >= 1 && v <= 6) || v == 8 || v == 9; }
 int stage_default_variant(const StageDev &s, bool dbl, int nrhs);
 
 // Two consecutive stages a, b fused in one launch (the intermediate stays in LDS).

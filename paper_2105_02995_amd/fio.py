@@ -33,7 +33,7 @@ AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(
 
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_stage_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
-           "fio_plan_stats", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
+           "fio_plan_stats", "fio_plan_trim", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error", "fio_set_trace", "fio_column_id"]
 
 
@@ -54,7 +54,8 @@ class fio_problem(ctypes.Structure):
                 ("amp_x", ctypes.c_double * FIO_MAX_AMP_TERMS), ("amp_eta", ctypes.c_double * FIO_MAX_AMP_TERMS),
                 ("strict_hpd", ctypes.c_int), ("host_construction", ctypes.c_int),
                 ("prescale_skel", ctypes.c_int), ("phi", PHASE_FN), ("amp_fn", AMP_FN),
-                ("user", ctypes.c_void_p)]
+                ("user", ctypes.c_void_p),
+                ("bf_rank_align", ctypes.c_int)]
 
 
 class fio_solve_opts(ctypes.Structure):
@@ -119,6 +120,7 @@ def load_library():
     lib.fio_solve.argtypes = [P, ctypes.POINTER(fio_solve_opts), ctypes.c_int, VP, VP, I64, I64,
                               ctypes.POINTER(fio_solve_info), VP]
     lib.fio_plan_stats.argtypes = [P, ctypes.POINTER(fio_plan_stats_t)]
+    lib.fio_plan_trim.argtypes = [P, ctypes.c_int]
     lib.fio_stage_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_int)]
@@ -200,7 +202,10 @@ def make_problem(d, n, phase="1d_ex1", eps=1e-6, c_div=16.0, device=0, **kw) -> 
     if amp_fn is not None:
         p.amp_fn = ctypes.cast(amp_fn, AMP_FN) if isinstance(amp_fn, int) else AMP_FN(amp_fn)
         keep.append(p.amp_fn)
+    fields = {f[0] for f in fio_problem._fields_}
     for k, v in kw.items():
+        if k not in fields:  # a ctypes structure would take an unknown name silently
+            raise TypeError("fio_problem has no field %r" % k)
         setattr(p, k, v)
     p._keep = keep
     return p
@@ -351,6 +356,13 @@ def fio_multi_autotune(plans, dtype: int, nrhs, reps: int = 3, stream=None):
     P = (ctypes.c_void_p * n)(*[p.handle for p in plans])
     B = (ctypes.c_int64 * n)(*nrhs)
     _check(load_library().fio_multi_autotune(n, P, dtype, B, reps, _stream(stream)))
+
+
+FIO_KEEP_ALL, FIO_KEEP_REFINE_C64 = 0, 1
+
+
+def fio_plan_trim(plan: Plan, keep: int):
+    _check(load_library().fio_plan_trim(plan.handle, keep))
 
 
 def fio_plan_stats(plan: Plan) -> dict:

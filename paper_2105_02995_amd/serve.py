@@ -243,6 +243,10 @@ class GpuExecutor:
     replayed; a batch is padded up to its bucket.  Columns are independent, so
     padding does not change the results.
 
+    With ``trim`` every plan keeps only the device images the refined complex64 solve
+    uses (``fio_plan_trim``), about half the factor memory, so more keys fit the HBM
+    budget.
+
     With ``use_multi``, batches of different keys admitted together run as one
     multi-instance solve (``fio_solve_multi``: one launch per factor level for all
     of them, on one stream); with graphs, each group (its keys and buckets) is
@@ -254,7 +258,7 @@ class GpuExecutor:
     MULTI_MAX = 8  # instances per multi-instance solve (fio.h)
 
     def __init__(self, plans: dict, max_batch_rhs: int = 256, refine: int = 1, nstreams: int = 8,
-                 use_graphs: bool = False, use_multi: bool = False):
+                 use_graphs: bool = False, use_multi: bool = False, trim: bool = False):
         import torch
         from . import fio as F
         self.torch, self.F = torch, F
@@ -264,6 +268,9 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
         self.max_concurrent = nstreams  # one batch per stream
         self.busy = {}
+        if trim:  # keep only what the refined complex64 solve uses: more keys fit in HBM
+            for p in plans.values():
+                F.fio_plan_trim(p, F.FIO_KEEP_REFINE_C64)
         self.stats = {k: F.fio_plan_stats(p) for k, p in plans.items()}
         self.use_graphs = use_graphs
         self.graphs = {}              # (key, bucket) -> (graph, U, X)
