@@ -32,42 +32,28 @@ from fio_synth import WORKLOADS, gaussian_complex, uniform_indices  # noqa: E402
 PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}   # MI355X dense MFMA FP32 / FP64
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of a stage-kernel instance on this workload, from rocprofv3
-# FETCH_SIZE (x2) and WRITE_SIZE (x1) scaled by a 1 GiB copy kernel (summaries under
-# profiles/), valid only for the kernel source and the factor set (its nonzero
-# count) they were measured on.
+# HBM bytes per launch of a stage-kernel instance on the measured workload, from
+# rocprofv3 FETCH_SIZE (x2) and WRITE_SIZE (x1) scaled by a 1 GiB copy kernel
+# (summaries under profiles/), valid only for the kernel source and the factor set
+# (its nonzero count) they were measured on.
 TRAFFIC = {
-    "k_stage2_mfma<double, 2, 2>": {
-        "bytes": (247081.56 * 2 + 204800.00) * 1024,
-        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
-        "bf_nnz": 109109248,
-    },
-    "k_stage2s_mfma<float, 2, 3>": {
-        "bytes": (108831.44 * 2 + 87381.33) * 1024,
-        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
-        "bf_nnz": 109109248,
-    },
-    "k_stage2_mfma<float, 2, 4>": {
-        "bytes": (123726.49 * 2 + 102400.00) * 1024,
-        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
-        "bf_nnz": 109109248,
-    },
-    "k_stage2s_mfma<double, 1, 3>": {
-        "bytes": (217253.39 * 2 + 174762.67) * 1024,
-        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
-        "bf_nnz": 109109248,
+    # 2D Example 3, n=256, 256 RHS (profiles/k_stage_mfma_f32_3m_2d_n256_traffic.md)
+    "k_stage_mfma<float, 2, 4, 3M>": {
+        "bytes": 4.1531e9,
+        "kernels_sha256": "7f7380b9efbce115cb4d74a07375f4a30aa6541ec47d713dad90a4aa4bd18d94",
+        "bf_nnz": 1138753536,
     },
 }
 
 
-# Matrix-core counters per launch (rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 and
+# Matrix-core counters per launch (rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 and
 # SQ_VALU_MFMA_BUSY_CYCLES; summary under profiles/), under the same validity rule.
 MFMA_COUNTERS = {
-    "k_stage2_mfma<double, 2, 2>": {
-        "executed_flop": 2.5585254e7 * 512,
-        "busy": 0.774,
-        "kernels_sha256": "0963792c43c62a1024fa5dffbe1c3757f7a2427ce96b7620d825ceefebccdd11",
-        "bf_nnz": 109109248,
+    "k_stage_mfma<float, 2, 4, 3M>": {
+        "executed_flop": 3.4403e11,
+        "busy": 0.587,
+        "kernels_sha256": "7f7380b9efbce115cb4d74a07375f4a30aa6541ec47d713dad90a4aa4bd18d94",
+        "bf_nnz": 1138753536,
     },
 }
 
