@@ -95,7 +95,7 @@ template <class T> struct DStageStore {
 };
 
 struct DHifStore {
-    DBuf desc, idx, m64, m128, h64, h128, tr, ts;
+    DBuf desc, idx, m64, m128, h64, h128, tr, ts, tr2, ts2, tr4, ts4;
     bool gone128 = false;  // released by fio_plan_trim
     HifStepDev view(bool dbl) const {
         HifStepDev v = base;
@@ -105,6 +105,10 @@ struct DHifStore {
         v.matH = dbl ? h128.p : h64.p;
         v.tiles_r = (const int32_t *)tr.p;
         v.tiles_s = (const int32_t *)ts.p;
+        v.tiles_r2 = (const int32_t *)tr2.p;
+        v.tiles_s2 = (const int32_t *)ts2.p;
+        v.tiles_r4 = (const int32_t *)tr4.p;
+        v.tiles_s4 = (const int32_t *)ts4.p;
         if (dbl && gone128) fail(FIO_ERR_UNSUPPORTED, "the complex128 image of Gd was released by fio_plan_trim");
         return v;
     }
@@ -426,11 +430,16 @@ void upload_plan(fio_plan p) {
         std::vector<int32_t> idx;
         std::vector<cd> mat, matH;
         int mr = 0, ms = 0, mv = 0, mm = 0;
-        std::vector<int32_t> tr, ts;
+        // row tiles of 16, 32 and 64 rows: pairs (node, first row)
+        std::vector<int32_t> tr, ts, tr2, ts2, tr4, ts4;
         for (size_t v = 0; v < st.nodes.size(); ++v) {
             const int nr = (int)st.nodes[v].idx_r.size(), ns = (int)st.nodes[v].idx_s.size();
-            for (int r0 = 0; r0 < nr; r0 += 16) { tr.push_back((int32_t)v); tr.push_back(r0); }
-            for (int r0 = 0; r0 < ns; r0 += 16) { ts.push_back((int32_t)v); ts.push_back(r0); }
+            for (int w : {16, 32, 64}) {
+                auto &lr = w == 16 ? tr : (w == 32 ? tr2 : tr4);
+                auto &ls = w == 16 ? ts : (w == 32 ? ts2 : ts4);
+                for (int r0 = 0; r0 < nr; r0 += w) { lr.push_back((int32_t)v); lr.push_back(r0); }
+                for (int r0 = 0; r0 < ns; r0 += w) { ls.push_back((int32_t)v); ls.push_back(r0); }
+            }
         }
         for (const HifNode &nd : st.nodes) {
             const int nr = (int)nd.idx_r.size(), ns = (int)nd.idx_s.size();
@@ -460,8 +469,16 @@ void upload_plan(fio_plan p) {
         d.base.max_mat = mm;
         d.tr.upload(tr.data(), tr.size() * sizeof(int32_t));
         d.ts.upload(ts.data(), ts.size() * sizeof(int32_t));
+        d.tr2.upload(tr2.data(), tr2.size() * sizeof(int32_t));
+        d.ts2.upload(ts2.data(), ts2.size() * sizeof(int32_t));
+        d.tr4.upload(tr4.data(), tr4.size() * sizeof(int32_t));
+        d.ts4.upload(ts4.data(), ts4.size() * sizeof(int32_t));
         d.base.n_tiles_r = (int64_t)tr.size() / 2;
         d.base.n_tiles_s = (int64_t)ts.size() / 2;
+        d.base.n_tiles_r2 = (int64_t)tr2.size() / 2;
+        d.base.n_tiles_s2 = (int64_t)ts2.size() / 2;
+        d.base.n_tiles_r4 = (int64_t)tr4.size() / 2;
+        d.base.n_tiles_s4 = (int64_t)ts4.size() / 2;
         d.desc.upload(desc.data(), desc.size() * sizeof(int64_t));
         d.idx.upload(idx.data(), idx.size() * sizeof(int32_t));
         upload_complex(d.m64, d.m128, mat);
@@ -583,14 +600,28 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
 
 // One skeletonization step: LDS-staged kernel for small nodes (choice 0), gathered
 // GEMMs on matrix cores when a node's blocks exceed LDS (large 2D cells and edges),
-// in tiles of 64, 32 or 16 right-hand sides (choices 1, 2, 3), or the fused
-// per-node matrix-core kernel for nodes of at most 64 redundant and 64 skeleton
-// DOFs, 64 or 32 right-hand sides per workgroup (choices 4, 5).  `force` overrides
-// the tuned choice where it applies.
-constexpr int HIF_CHOICES = 6;
+// in tiles of 16 rows by 64, 32 or 16 right-hand sides (choices 1, 2, 3) or of 32
+// rows by 32 (6) and 64 rows by 16 or 32 (7, 8), or the fused per-node matrix-core
+// kernel for nodes of at most 64 redundant and 64 skeleton DOFs, 64 or 32
+// right-hand sides per workgroup (choices 4, 5).  `force` overrides the tuned
+// choice where it applies.
+constexpr int HIF_CHOICES = 9;
+// Tiling of a gathered-GEMM choice: rows per wave in 16-row tiles, columns per wave.
+bool hif_gemm_tiling(int choice, int &mt, int &cols) {
+    switch (choice) {
+        case 1: mt = 1; cols = 64; return true;
+        case 2: mt = 1; cols = 32; return true;
+        case 3: mt = 1; cols = 16; return true;
+        case 6: mt = 2; cols = 32; return true;
+        case 7: mt = 4; cols = 16; return true;
+        case 8: mt = 4; cols = 32; return true;
+        default: return false;
+    }
+}
 void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStream_t st, const Ws &ws,
               int force = -1) {
     const HifStepDev h = p->dhif[k].view(dbl);
+    if (h.max_nr == 0) return;  // no redundant DOFs in any node: the step is the identity
     int choice = force;
     if ((choice == 4 || choice == 5) && !hif_fused_fits(h)) choice = -1;
     if (choice < 0) {
@@ -602,9 +633,10 @@ void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStr
         else if (hif_step_fits_lds(h, dbl)) choice = 0;
         else choice = nrhs >= 64 ? 1 : 3;  // large nodes: gathered GEMMs over all nodes' row tiles
     }
-    if (choice == 0) launch_hif_step(h, dbl, up, x, nrhs, st);
-    else if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
-    else launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, 64 >> (choice - 1), st);
+    int mt = 1, cols = 16;
+    if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
+    else if (hif_gemm_tiling(choice, mt, cols)) launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, cols, st, mt);
+    else launch_hif_step(h, dbl, up, x, nrhs, st);
 }
 
 // A_0^{-1} on the remaining DOFs, always in FP64: a block of 64 or more DOFs as a
@@ -1253,11 +1285,14 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                         launch_hif_step(h, dbl, false, p->V2.p, nr, st);
                     });
                 }
-                for (int c = 1; c <= 3; ++c) {
-                    if (nr <= 16 && c < 3) continue;  // one 16-column tile covers the batch
+                for (int c : {1, 2, 3, 6, 7, 8}) {
+                    int mt = 1, cols = 16;
+                    hif_gemm_tiling(c, mt, cols);
+                    if (nr <= 16 && cols > 16) continue;  // one 16-column tile covers the batch
+                    if (mt > 1 && std::max(h.max_nr, h.max_ns) < 16 * mt) continue;  // rows would be padding
                     const float ms = timeit([&] {
-                        launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, 64 >> (c - 1), st);
-                        launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, 64 >> (c - 1), st);
+                        launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, cols, st, mt);
+                        launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, cols, st, mt);
                     });
                     if (ms < best_ms) { best_ms = ms; best = c; }
                 }
@@ -1271,8 +1306,24 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                         if (ms < best_ms) { best_ms = ms; best = c; }
                     }
                 }
-                progress(vb, "tune %s skeletonization step %zu (%lld nodes): choice %d %.4f ms",
-                         dbl ? "c128" : "c64", k, (long long)h.n_nodes, best, best_ms / reps);
+                if (vb) {
+                    // complex multiply-adds of the step's up and down sweeps per column:
+                    // T and M products (ns nr each) and the triangular L^-1 (nr (nr+1)/2)
+                    double macs = 0;
+                    int mr = 0, ms = 0;
+                    for (const HifNode &nd : p->host.hif.steps[k].nodes) {
+                        const double r = (double)nd.idx_r.size(), q = (double)nd.idx_s.size();
+                        macs += 2.0 * (2.0 * q * r + r * (r + 1) / 2);
+                        mr = std::max(mr, (int)nd.idx_r.size());
+                        ms = std::max(ms, (int)nd.idx_s.size());
+                    }
+                    const double sec = best_ms / reps * 1e-3;
+                    progress(true,
+                             "tune %s skeletonization step %zu (%lld nodes, largest nr %d ns %d): choice %d %.4f ms, "
+                             "%.1f TFLOP/s",
+                             dbl ? "c128" : "c64", k, (long long)h.n_nodes, mr, ms, best, best_ms / reps,
+                             8.0 * macs * nr / sec / 1e12);
+                }
             }
             t.hif.push_back(best);
         }
@@ -1642,7 +1693,7 @@ void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x
             fio_plan p = I[i].p;
             if (k >= (int)p->dhif.size()) continue;
             const HifStepDev h = p->dhif[k].view(dbl);
-            if (h.n_nodes == 0) continue;
+            if (h.n_nodes == 0 || h.max_nr == 0) continue;  // empty or identity step
             const bool fused_ok = I[i].nr >= 16 && hif_fused_fits(h) && c.variant != 0;
             if (fused_ok) {
                 hf[cf] = h; xf[cf] = x[i]; nf[cf++] = I[i].nr;
@@ -1650,8 +1701,9 @@ void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x
                 hl[cl] = h; xl[cl] = x[i]; nl[cl++] = I[i].nr;
             } else if (I[i].nr >= 16) {  // large nodes: the instance's own gathered-GEMM launches
                 const auto *tn = p->tuned(dbl, I[i].nr);
-                const int ch = (tn && k < (int)tn->hif.size() && tn->hif[k] >= 1 && tn->hif[k] <= 3) ? tn->hif[k] : 1;
-                launch_hif_gemm_step(h, dbl, up, x[i], p->HT.p, I[i].nr, 64 >> (ch - 1), st);
+                int mt = 1, cols = 64;
+                if (tn && k < (int)tn->hif.size()) hif_gemm_tiling(tn->hif[k], mt, cols);
+                launch_hif_gemm_step(h, dbl, up, x[i], p->HT.p, I[i].nr, cols, st, mt);
             } else {
                 launch_hif_step(h, dbl, up, x[i], I[i].nr, st);  // node blocks read from memory
             }

@@ -1248,7 +1248,7 @@ __global__ void __launch_bounds__(256) k_hcopy(const int64_t *__restrict__ desc,
     }
 }
 
-template <class R, int NT>
+template <class R, int MT, int NT>
 static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, void *x, void *t,
                         int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
@@ -1262,14 +1262,14 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
     static std::once_flag attr_once[6];  // plans may be used from several host threads
     if (lds > 65536) {
         std::call_once(attr_once[ph], [ph] {
-            const void *fn[6] = {(const void *)k_hgemm<R, 0, 1, NT>, (const void *)k_hgemm<R, 1, 1, NT>,
-                                 (const void *)k_hgemm<R, 2, 1, NT>, (const void *)k_hgemm<R, 3, 1, NT>,
-                                 (const void *)k_hgemm<R, 4, 1, NT>, (const void *)k_hgemm<R, 5, 1, NT>};
+            const void *fn[6] = {(const void *)k_hgemm<R, 0, MT, NT>, (const void *)k_hgemm<R, 1, MT, NT>,
+                                 (const void *)k_hgemm<R, 2, MT, NT>, (const void *)k_hgemm<R, 3, MT, NT>,
+                                 (const void *)k_hgemm<R, 4, MT, NT>, (const void *)k_hgemm<R, 5, MT, NT>};
             (void)hipFuncSetAttribute(fn[ph], hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
         });
     }
-#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, 1, NT>), g, dim3(256), lds, st, h.desc, h.idx, tiles, ntiles, mat, matH, \
-                                 (C *)x, (C *)t, nrhs, nch, maxk)
+#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, MT, NT>), g, dim3(256), lds, st, h.desc, h.idx, tiles, ntiles, mat, \
+                                 matH, (C *)x, (C *)t, nrhs, nch, maxk)
     switch (ph) {
         case 0: HG(0); break;
         case 1: HG(1); break;
@@ -1281,27 +1281,42 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
 #undef HG
 }
 
+// The register tilings of the gathered GEMMs: 16*MT rows x 16*NT columns per wave.
 template <class R>
-static void hgemm_phase_nt(int nt, int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, void *x,
-                           void *t, int nrhs, hipStream_t st) {
-    if (nt == 1) hgemm_phase<R, 1>(ph, h, tiles, ntiles, x, t, nrhs, st);
-    else if (nt == 2) hgemm_phase<R, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
-    else hgemm_phase<R, 4>(ph, h, tiles, ntiles, x, t, nrhs, st);
+static void hgemm_phase_tile(int mt, int nt, int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles,
+                             void *x, void *t, int nrhs, hipStream_t st) {
+    if (mt == 4) {
+        if (nt == 1) hgemm_phase<R, 4, 1>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else hgemm_phase<R, 4, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
+    } else if (mt == 2) {
+        hgemm_phase<R, 2, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
+    } else {
+        if (nt == 1) hgemm_phase<R, 1, 1>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else if (nt == 2) hgemm_phase<R, 1, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else hgemm_phase<R, 1, 4>(ph, h, tiles, ntiles, x, t, nrhs, st);
+    }
 }
 
 void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
-                          hipStream_t st) {
+                          hipStream_t st, int mt) {
     if (h.n_nodes == 0) return;
     const int nt = cols <= 16 ? 1 : (cols <= 32 ? 2 : 4);
+    if (mt != 1 && mt != 2 && mt != 4) throw std::runtime_error("hif step: 1, 2 or 4 row tiles per wave");
+    if ((mt == 4 && nt > 2) || (mt == 2 && nt != 2)) throw std::runtime_error("hif step: tiling not built");
     const int p0 = up ? 0 : 3;
     for (int k = 0; k < 3; ++k) {
         const int ph = p0 + k;
         // phases 2 and 5 produce the skeleton rows (ns), the others the redundant rows (nr)
         const bool srows = (ph == 2 || ph == 5);
-        const int32_t *tiles = srows ? h.tiles_s : h.tiles_r;
-        const int64_t ntl = srows ? h.n_tiles_s : h.n_tiles_r;
-        if (dbl) hgemm_phase_nt<double>(nt, ph, h, tiles, ntl, x, t, nrhs, st);
-        else hgemm_phase_nt<float>(nt, ph, h, tiles, ntl, x, t, nrhs, st);
+        const int32_t *tiles = mt == 4 ? (srows ? h.tiles_s4 : h.tiles_r4)
+                             : mt == 2 ? (srows ? h.tiles_s2 : h.tiles_r2)
+                                       : (srows ? h.tiles_s : h.tiles_r);
+        const int64_t ntl = mt == 4 ? (srows ? h.n_tiles_s4 : h.n_tiles_r4)
+                          : mt == 2 ? (srows ? h.n_tiles_s2 : h.n_tiles_r2)
+                                    : (srows ? h.n_tiles_s : h.n_tiles_r);
+        if (ntl > 0 && !tiles) throw std::runtime_error("hif step: tile list missing");
+        if (dbl) hgemm_phase_tile<double>(mt, nt, ph, h, tiles, ntl, x, t, nrhs, st);
+        else hgemm_phase_tile<float>(mt, nt, ph, h, tiles, ntl, x, t, nrhs, st);
         check_launch("hif step (matrix cores)");
     }
     if (up && h.n_tiles_r > 0) {

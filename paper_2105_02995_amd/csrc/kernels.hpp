@@ -68,6 +68,10 @@ struct HifStepDev {
     // over the redundant rows (nr) and over the skeleton rows (ns).
     const int32_t *tiles_r = nullptr, *tiles_s = nullptr;
     int64_t n_tiles_r = 0, n_tiles_s = 0;
+    // The same over tiles of 32 and of 64 rows (two and four matrix-core row tiles
+    // per wave, for large nodes: each gathered input row then serves more rows).
+    const int32_t *tiles_r2 = nullptr, *tiles_s2 = nullptr, *tiles_r4 = nullptr, *tiles_s4 = nullptr;
+    int64_t n_tiles_r2 = 0, n_tiles_s2 = 0, n_tiles_r4 = 0, n_tiles_s4 = 0;
     const int64_t *desc = nullptr;
     const int32_t *idx = nullptr;
     const void *mat = nullptr;
@@ -79,10 +83,10 @@ struct HifStepDev {
 void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, hipStream_t st);
 void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st);
 // Large-node variant of launch_hif_step (gathered GEMMs on matrix cores, tiles of
-// 16 rows by `cols` = 16, 32 or 64 right-hand sides); t is an N x nrhs temporary of
-// the same dtype.
+// 16*mt rows by `cols` right-hand sides: mt 1 with cols 16, 32 or 64, mt 2 with 32,
+// mt 4 with 16 or 32); t is an N x nrhs temporary of the same dtype.
 void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
-                          hipStream_t st);
+                          hipStream_t st, int mt = 1);
 // Whether a step's largest node fits the LDS-staged kernel.
 bool hif_step_fits_lds(const HifStepDev &h, bool dbl);
 // One skeletonization step in a single launch for nodes with nr, ns <= 64: per
