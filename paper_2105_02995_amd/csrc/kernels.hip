@@ -377,6 +377,13 @@ template <class R, int MT, int NT> struct Acc3 {
     }
 };
 
+// k-steps of loads in flight for an accumulator form: STAGE_PF, except for the
+// complex64 three-product tiles, which measured fastest with 4 (2D n = 256 complex64
+// chain 18.4 against 19.4 ms); deeper rings cost the FP64 and four-product tilings
+// occupancy.
+template <class ACC> struct PfOf { static constexpr int value = STAGE_PF; };
+template <int MT, int NT> struct PfOf<Acc3<float, MT, NT>> { static constexpr int value = 4; };
+
 // The product with explicit per-lane row offsets: row tile mt of this lane reads
 // the factor at Ao + rowc[mt] + k * lda (column-major, leading dimension lda).
 template <class R, int MT, int NT, class P, class ACC>
@@ -395,14 +402,15 @@ __device__ __forceinline__ void mfma_rows(ACC &acc, const typename MF<R>::C *__r
     w.e = lk - w.q * r_in;
     w.ap = Ao + (int64_t)lk * lda;
     w.xp = xb + off(w.q) + (int64_t)w.e * ld;
-    Frag<R, MT, NT> f[STAGE_PF];
+    constexpr int PF = PfOf<ACC>::value;
+    Frag<R, MT, NT> f[PF];
 #pragma unroll
-    for (int j = 0; j + 1 < STAGE_PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, lda, colc, rowc);
-    for (int k0 = 0; k0 < K; k0 += 4 * STAGE_PF) {
+    for (int j = 0; j + 1 < PF; ++j) frag_load(f[j], w, K, r_in, xb, off, ld, lda, colc, rowc);
+    for (int k0 = 0; k0 < K; k0 += 4 * PF) {
 #pragma unroll
-        for (int j = 0; j < STAGE_PF; ++j) {
+        for (int j = 0; j < PF; ++j) {
             if (k0 + 4 * j >= K) break;  // wave-uniform
-            frag_load(f[(j + STAGE_PF - 1) % STAGE_PF], w, K, r_in, xb, off, ld, lda, colc, rowc);
+            frag_load(f[(j + PF - 1) % PF], w, K, r_in, xb, off, ld, lda, colc, rowc);
             acc.mma(f[j]);
         }
     }

@@ -34,6 +34,7 @@ class ServeRequest:
     result: np.ndarray | None = None
     start: float | None = None
     done: float | None = None
+    error: str | None = None   # set when the request was cancelled or its batch failed
 
     @property
     def nrhs(self) -> int:
@@ -72,6 +73,9 @@ class Scheduler:
         self.groups_started = 0      # multi-instance launches of several batches
         self.peak_inflight = 0
         self.rejected_keys = []
+        self.failed = []             # requests whose batch the executor could not run
+        self.cancelled = []          # requests withdrawn by cancel()
+        self._cancel_ids = set()     # cancelled while their batch runs
 
     # ---------------------------------------------------------------- keys
     def register(self, key) -> bool:
@@ -97,6 +101,35 @@ class Scheduler:
     def submit(self, req: ServeRequest):
         self.check(req)
         self.queues[req.key].append(req)
+
+    def cancel(self, rid) -> bool:
+        """Withdraw a request.  A queued one leaves its queue at once; one whose batch
+        already runs is dropped when the batch completes (the other requests of the
+        batch are unaffected).  Returns False if the request is unknown or done."""
+        for q in self.queues.values():
+            for r in q:
+                if r.rid == rid:
+                    q.remove(r)
+                    self._withdraw(r, "cancelled")
+                    return True
+        for b in self.running.values():
+            if any(r.rid == rid for r in b.requests):
+                self._cancel_ids.add(rid)
+                return True
+        return False
+
+    def _withdraw(self, r, why):
+        r.error = why
+        r.done = self.ex.clock()
+        (self.cancelled if why == "cancelled" else self.failed).append(r)
+
+    def _fail_batch(self, b, exc):
+        """The executor raised for batch b: its requests fail with the error and its
+        memory is released; the loop goes on with the other keys."""
+        for r in b.requests:
+            self._cancel_ids.discard(r.rid)
+            self._withdraw(r, "%s: %s" % (type(exc).__name__, exc))
+        self.inflight_bytes -= b.bytes
 
     def _form_batch(self, key):
         q = self.queues[key]
@@ -128,26 +161,46 @@ class Scheduler:
             admitted.append(b)
         if admitted:
             if len(admitted) > 1 and hasattr(self.ex, "start_group"):
-                handles = self.ex.start_group(admitted, now)
-                self.groups_started += 1
+                try:
+                    handles = self.ex.start_group(admitted, now)
+                    self.groups_started += 1
+                except Exception as exc:  # noqa: BLE001 - the group's batches fail, the loop goes on
+                    for b in admitted:
+                        self._fail_batch(b, exc)
+                    admitted, handles = [], []
             else:
-                handles = [self.ex.start(b, now) for b in admitted]
+                handles = []
+                for b in list(admitted):
+                    try:
+                        handles.append(self.ex.start(b, now))
+                    except Exception as exc:  # noqa: BLE001 - the batch fails, the loop goes on
+                        self._fail_batch(b, exc)
+                        admitted.remove(b)
             for b, h in zip(admitted, handles):
                 b.handle = h
                 self.running[b.key] = b
                 self.batches_started += 1
             self.peak_inflight = max(self.peak_inflight, len(self.running))
         for key, b in list(self.running.items()):
-            res = self.ex.poll(b.handle, now)
+            try:
+                res = self.ex.poll(b.handle, now)
+            except Exception as exc:  # noqa: BLE001
+                del self.running[key]
+                self._fail_batch(b, exc)
+                continue
             if res is None:
                 continue
             t = self.ex.clock()
             c0 = 0
             for r in b.requests:
-                r.result = res[:, c0:c0 + r.nrhs]
-                r.done = t
+                if r.rid in self._cancel_ids:  # withdrawn while running: result dropped
+                    self._cancel_ids.discard(r.rid)
+                    self._withdraw(r, "cancelled")
+                else:
+                    r.result = res[:, c0:c0 + r.nrhs]
+                    r.done = t
+                    self.finished.append(r)
                 c0 += r.nrhs
-                self.finished.append(r)
             del self.running[key]
             self.inflight_bytes -= b.bytes
 
@@ -196,11 +249,13 @@ class MockExecutor:
     """CPU stand-in: a batch takes ``cost(key, nrhs)`` seconds of modelled time and
     returns ``transform(key, u)``; clock and waiting are virtual."""
 
-    def __init__(self, cost, transform=None, factor_bytes=None, ws_bytes_per_rhs=None):
+    def __init__(self, cost, transform=None, factor_bytes=None, ws_bytes_per_rhs=None, fail_starts=()):
         self.cost = cost
         self.transform = transform or (lambda key, u: u.copy())
         self.factor_bytes = factor_bytes or (lambda key: 0)
         self.ws_bytes_per_rhs = ws_bytes_per_rhs or (lambda key: 0)
+        self.fail_starts = set(fail_starts)  # 0-based start() calls that raise (out of memory)
+        self.starts = 0
         self.t = 0.0
         self.events = []
         self.loaded = []
@@ -221,6 +276,10 @@ class MockExecutor:
         return self.ws_bytes_per_rhs(key) * nrhs
 
     def start(self, batch, now):
+        k = self.starts
+        self.starts += 1
+        if k in self.fail_starts:
+            raise MemoryError("device allocation failed (modelled, start call %d)" % k)
         u = np.concatenate([r.u for r in batch.requests], axis=1)
         return (self.t + self.cost(batch.key, batch.nrhs), self.transform(batch.key, u))
 
@@ -277,6 +336,7 @@ class GpuExecutor:
         self.stage = {}               # key -> (pinned u, pinned x)
         self.use_multi = use_multi
         self.group_graphs = {}        # ((key, bucket), ...) -> graph of the multi-instance solve
+        self.group_seen = {}          # group signature -> times started
 
     def clock(self):
         return time.perf_counter()
@@ -382,6 +442,7 @@ class GpuExecutor:
                           maxit=self.refine, stream=s)
 
     GROUP_SPREAD = 4.0  # batches of one group differ in estimated work by at most this factor
+    GROUP_CAPTURE_AFTER = 3  # a group (keys and column buckets) is captured on its third start
 
     def _work(self, batch):
         """Estimated work of a batch: butterfly nonzeros times padded columns."""
@@ -435,16 +496,19 @@ class GpuExecutor:
                         members.append((b.key, U, X, b.nrhs))
                         keep.append((U, X))
                     U[:b.nrhs].copy_(self.stage[b.key][0][:b.nrhs], non_blocking=True)
-                if self.use_graphs:
-                    sig = tuple((k, cols) for k, _, _, cols in members)
-                    g = self.group_graphs.get(sig)
-                    if g is None:
-                        self._multi(members, s)  # eager first run (also outside the capture)
-                        s.synchronize()
-                        g = torch.cuda.CUDAGraph()
-                        with torch.cuda.graph(g, stream=s):
-                            self._multi(members, s)
-                        self.group_graphs[sig] = g
+                sig = tuple((k, cols) for k, _, _, cols in members)
+                g = self.group_graphs.get(sig)
+                seen = self.group_seen.get(sig, 0) + 1
+                self.group_seen[sig] = seen
+                if g is None and self.use_graphs and seen >= self.GROUP_CAPTURE_AFTER:
+                    # a recurring group: capture it once (a capture waits for the whole
+                    # device, so rare groups run eagerly instead)
+                    s.synchronize()
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=s):
+                        self._multi(members, s)
+                    self.group_graphs[sig] = g
+                if g is not None:
                     g.replay()
                 else:
                     self._multi(members, s)

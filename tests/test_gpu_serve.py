@@ -141,20 +141,25 @@ def test_serving_with_graphs_matches_eager_serving(plans):
         assert O.rel_err(out[1][rid].result, r.result).max() < 10 * r.key[3]
 
 
-@pytest.mark.parametrize("graphs", [False, True])
-def test_multi_instance_serving_alone_equals_mix(plans, graphs):
+@pytest.mark.parametrize("graphs,capture_after", [(False, 3), (True, 3), (True, 1)])
+def test_multi_instance_serving_alone_equals_mix(plans, graphs, capture_after):
     """Batches of different keys admitted together run as one multi-instance solve
     (one launch per factor level for all of them); each request's result must be
-    the same as when it is served alone (within the stated tolerance), and correct."""
+    the same as when it is served alone (within the stated tolerance), and correct.
+    With graphs, a group is captured on its capture_after-th start (1: every group
+    runs from its graph)."""
     ex = GpuExecutor(plans, max_batch_rhs=64, refine=1, use_graphs=graphs, use_multi=True)
+    ex.GROUP_CAPTURE_AFTER = capture_after
     sched = Scheduler(ex, hbm_budget=64 << 30, max_batch_rhs=64)
     for k in KEYS:
         assert sched.register(k)
     reqs = _mix(60, rate=3000.0, seed=13)
     done = sched.run(reqs)
     assert len(done) == 60
-    log("multi serving graphs=%s: %d batches in %d multi-instance groups" % (graphs, sched.batches_started,
-                                                                             sched.groups_started))
+    log("multi serving graphs=%s: %d batches in %d multi-instance groups, %d captured" % (
+        graphs, sched.batches_started, sched.groups_started, len(ex.group_graphs)))
+    if graphs and capture_after == 1:
+        assert len(ex.group_graphs) >= 1
     assert sched.groups_started >= 1
     worst = 0.0
     for r in sorted(done, key=lambda r: r.rid)[:12]:

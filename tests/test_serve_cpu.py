@@ -185,3 +185,50 @@ def test_multi_instance_groups_hold_batches_of_similar_work():
         assert max(w) <= ex.GROUP_SPREAD * min(w)
     big = [g for g in groups if any(batches[i].key == ("big",) for i in g)]
     assert len(big) == 1 and len(big[0]) == 1
+
+
+def test_cancel_withdraws_queued_and_running_requests():
+    """A queued request leaves its queue at once; a running one is dropped when its
+    batch completes; the other requests are served as usual."""
+    ex = MockExecutor(cost=lambda key, nr: 0.05, transform=_transform)
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=64)
+    k = _key(0)
+    s.register(k)
+    r = [ServeRequest(j, k, 0.0, gaussian_complex((16, 2), 500 + j)) for j in range(4)]
+    s.submit(r[0])
+    s.step(ex.clock())                 # r0 runs
+    for q in r[1:]:
+        s.submit(q)                    # r1..r3 wait for the key's slot
+    assert s.cancel(1)                 # queued
+    assert s.cancel(0)                 # running
+    assert not s.cancel(99)
+    while not s.idle():
+        ex.wait()
+        s.step(ex.clock())
+    assert sorted(q.rid for q in s.finished) == [2, 3]
+    assert sorted(q.rid for q in s.cancelled) == [0, 1]
+    for q in s.cancelled:
+        assert q.result is None and q.error == "cancelled"
+    for q in s.finished:
+        np.testing.assert_array_equal(q.result, _transform(k, q.u))
+    assert not s.cancel(2)             # done: nothing to withdraw
+    assert s.inflight_bytes == 0
+
+
+def test_executor_failure_fails_only_that_batch():
+    """The executor raising for one batch (a modelled allocation failure on its
+    second start) fails that batch's requests with the error; the loop serves every
+    other request and releases the batch's memory."""
+    ex = MockExecutor(cost=lambda key, nr: 0.01, transform=_transform, ws_bytes_per_rhs=lambda key: 1000,
+                      fail_starts={1})
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=32)
+    for k in {_key(i) for i in range(3)}:
+        s.register(k)
+    reqs = _requests(60, rate=2000.0, seed=3)
+    s.run(reqs)
+    assert len(s.finished) + len(s.failed) == 60
+    assert s.failed and all("MemoryError" in q.error and q.result is None for q in s.failed)
+    assert len({q.key for q in s.failed}) == 1       # one batch: one key
+    for q in s.finished:
+        np.testing.assert_array_equal(q.result, _transform(q.key, q.u))
+    assert s.inflight_bytes == 0 and not s.running
