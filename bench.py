@@ -38,9 +38,9 @@ PEAK_HBM_GBS = 8000.0
 # (its nonzero count) they were measured on.
 TRAFFIC = {
     # 2D Example 3, n=256, 256 RHS (profiles/k_stage_mfma_f32_3m_2d_n256_traffic.md)
-    "k_stage_mfma<float, 2, 4, 3M>": {
-        "bytes": 4.1531e9,
-        "kernels_sha256": "7f7380b9efbce115cb4d74a07375f4a30aa6541ec47d713dad90a4aa4bd18d94",
+    "k_stage_mfma<float, 2, 2, 3M>": {
+        "bytes": 4.1726e9,
+        "kernels_sha256": "7d4610cabe2589ea3958dea624d95927099889958aa4dbef2223154f83bdfadd",
         "bf_nnz": 1138753536,
     },
 }
@@ -49,10 +49,10 @@ TRAFFIC = {
 # Matrix-core counters per launch (rocprofv3 SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 and
 # SQ_VALU_MFMA_BUSY_CYCLES; summary under profiles/), under the same validity rule.
 MFMA_COUNTERS = {
-    "k_stage_mfma<float, 2, 4, 3M>": {
+    "k_stage_mfma<float, 2, 2, 3M>": {
         "executed_flop": 3.4403e11,
-        "busy": 0.587,
-        "kernels_sha256": "7f7380b9efbce115cb4d74a07375f4a30aa6541ec47d713dad90a4aa4bd18d94",
+        "busy": 0.629,
+        "kernels_sha256": "7d4610cabe2589ea3958dea624d95927099889958aa4dbef2223154f83bdfadd",
         "bf_nnz": 1138753536,
     },
 }
