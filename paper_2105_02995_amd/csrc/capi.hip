@@ -63,6 +63,23 @@ struct TraceRange {
 struct DBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;  // owns its device memory: moved, never copied
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), bytes(o.bytes) {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) {
+            if (p) (void)hipFree(p);
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
     ~DBuf() {
         if (p) (void)hipFree(p);
     }
@@ -327,7 +344,7 @@ void count_bytes(fio_plan p) {
     for (auto &q : p->pfwd) b += q.tab.bytes;
     for (auto &q : p->padj) b += q.tab.bytes;
     for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes + h.h64.bytes + h.h128.bytes +
-                                   h.tr.bytes + h.ts.bytes;
+                                   h.tr.bytes + h.ts.bytes + h.tr2.bytes + h.ts2.bytes + h.tr4.bytes + h.ts4.bytes;
     b += p->root_idx.bytes + p->A0inv.bytes + p->perm.bytes;
     p->device_bytes = b;
 }
@@ -391,7 +408,8 @@ void upload_chains(const std::vector<Stage> &fwd, DeviceChains &c) {
 }
 
 void upload_pairs(const std::vector<Stage> &st, std::vector<DPair> &d) {
-    d.assign(st.empty() ? 0 : st.size() - 1, DPair());
+    d.clear();  // default-constructed entries: DBuf is not copied
+    d.resize(st.empty() ? 0 : st.size() - 1);
     std::vector<int32_t> tab;
     for (size_t s = 0; s + 1 < st.size(); ++s) {
         if (!build_pair_table(st[s], st[s + 1], tab)) continue;
