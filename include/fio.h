@@ -456,6 +456,18 @@ typedef enum {
  * Synchronises the device.  Errors: FIO_ERR_ARG, FIO_ERR_UNSUPPORTED (host-only plan). */
 fio_status fio_plan_trim(fio_plan plan, int keep);
 
+/* 64-bit fingerprints of the plan's factors (its host copy, the source of every
+ * device image and of fio_save): fp[0] the butterfly Kd (tree permutation and every
+ * stage's sizes, indices and blocks, section 2), fp[1..K] the K skeletonization steps
+ * of Gd (each node's index sets, T, L^-1 and M, section 4), fp[K+1] the top-level
+ * block's indices and inverse.  Up to cap values are written; *count receives K + 2.
+ * Builds are deterministic: the same problem built again on the same device gives
+ * the same fingerprints, and a fingerprint that differs names the part of the
+ * factors that does.
+ * Synchronous, host only.  Errors: FIO_ERR_ARG (null plan or count, fp NULL with
+ * cap > 0). */
+fio_status fio_plan_fingerprints(fio_plan plan, uint64_t *fp, int cap, int *count);
+
 /* Save the factors to a file / load them onto a device (device = -1: host only). */
 fio_status fio_save(fio_plan plan, const char *path);
 fio_status fio_load(const char *path, int device, fio_plan *out);

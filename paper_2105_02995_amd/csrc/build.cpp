@@ -70,21 +70,30 @@ fio_problem normalized_problem(const fio_problem &in) {
     return p;
 }
 
-static void print_fingerprints(const HifFactors &F) {
-    for (size_t k = 0; k < F.steps.size(); ++k) {
-        uint64_t h = 0xCBF29CE484222325ULL;
-        for (const HifNode &nd : F.steps[k].nodes) {
+std::vector<uint64_t> factor_fingerprints(const HostFactors &f) {
+    std::vector<uint64_t> out;
+    uint64_t h = fingerprint(0xCBF29CE484222325ULL, f.perm.data(), f.perm.size() * 4);
+    for (const Stage &s : f.fwd) {
+        const int64_t dims[5] = {s.n_out, s.n_in, s.r_out, s.r_in, s.fan};
+        h = fingerprint(h, dims, sizeof(dims));
+        h = fingerprint(h, s.in_idx.data(), s.in_idx.size() * 4);
+        h = fingerprint(h, s.A.data(), s.A.size() * sizeof(cd));
+    }
+    out.push_back(h);
+    for (const HifStep &st : f.hif.steps) {
+        h = 0xCBF29CE484222325ULL;
+        for (const HifNode &nd : st.nodes) {
             h = fingerprint(h, nd.idx_r.data(), nd.idx_r.size() * 4);
             h = fingerprint(h, nd.idx_s.data(), nd.idx_s.size() * 4);
             h = fingerprint(h, nd.T.a.data(), nd.T.a.size() * 16);
             h = fingerprint(h, nd.Linv.a.data(), nd.Linv.a.size() * 16);
             h = fingerprint(h, nd.M.a.data(), nd.M.a.size() * 16);
         }
-        progress(true, "  fingerprint of inverse-factor step %zu: %016llx", k, (unsigned long long)h);
+        out.push_back(h);
     }
-    uint64_t h = fingerprint(0xCBF29CE484222325ULL, F.root_idx.data(), F.root_idx.size() * 4);
-    h = fingerprint(h, F.A0inv.a.data(), F.A0inv.a.size() * 16);
-    progress(true, "  fingerprint of the top-level inverse: %016llx", (unsigned long long)h);
+    h = fingerprint(0xCBF29CE484222325ULL, f.hif.root_idx.data(), f.hif.root_idx.size() * 4);
+    out.push_back(fingerprint(h, f.hif.A0inv.a.data(), f.hif.A0inv.a.size() * 16));
+    return out;
 }
 
 void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelApplyFactory &gpu,
@@ -170,9 +179,15 @@ void build_host_factors(const fio_problem &pin, HostFactors &out, const PeelAppl
              "(%.1fs)",
              out.hif.steps.size(), out.hif.root_idx.size(), out.hif.shifted, out.hif.device_ids, out.hif.device_nodes,
              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-    if (vb) print_fingerprints(out.hif);
     out.fwd = std::move(B.fwd);
     out.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (vb) {
+        const std::vector<uint64_t> fp = factor_fingerprints(out);
+        progress(true, "  fingerprint of the butterfly: %016llx", (unsigned long long)fp.front());
+        for (size_t k = 1; k + 1 < fp.size(); ++k)
+            progress(true, "  fingerprint of inverse-factor step %zu: %016llx", k - 1, (unsigned long long)fp[k]);
+        progress(true, "  fingerprint of the top-level inverse: %016llx", (unsigned long long)fp.back());
+    }
 }
 
 // ---------------------------------------------------------------- file format

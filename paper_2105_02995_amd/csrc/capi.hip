@@ -1409,6 +1409,15 @@ fio_status fio_gd_apply_variant(fio_plan p, fio_dtype dt, int variant, const voi
     });
 }
 
+fio_status fio_plan_fingerprints(fio_plan p, uint64_t *fp, int cap, int *count) {
+    return guard([&] {
+        if (!p || !count || (cap > 0 && !fp)) fail(FIO_ERR_ARG, "null argument");
+        const std::vector<uint64_t> f = factor_fingerprints(p->host);
+        for (int i = 0; i < cap && i < (int)f.size(); ++i) fp[i] = f[i];
+        *count = (int)f.size();
+    });
+}
+
 fio_status fio_inverse_apply_noalloc(fio_plan p, fio_dtype dt, const void *u, void *fh, int64_t nrhs,
                                      int64_t ld, void *stream) {
     return guard([&] {

@@ -38,6 +38,10 @@ using PeelApplyFactory = std::function<BlockApply(const std::vector<Stage> &fwd)
 void build_host_factors(const fio_problem &p, HostFactors &out, const PeelApplyFactory &gpu,
                         const BatchedIdFactory &ids, const SkelHooks &skel = SkelHooks());
 
+// 64-bit fingerprints of the factors: the butterfly (permutation and every stage),
+// each inverse-factor step, and the top-level inverse; equal for bit-identical factors.
+std::vector<uint64_t> factor_fingerprints(const HostFactors &f);
+
 void save_factors(const HostFactors &f, const std::string &path);
 void load_factors(const std::string &path, HostFactors &f);
 

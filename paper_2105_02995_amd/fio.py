@@ -33,7 +33,7 @@ AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(
 
 EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_stage_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
-           "fio_plan_stats", "fio_plan_trim", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
+           "fio_plan_stats", "fio_plan_fingerprints", "fio_plan_trim", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error", "fio_set_trace", "fio_column_id"]
 
 
@@ -121,6 +121,8 @@ def load_library():
                               ctypes.POINTER(fio_solve_info), VP]
     lib.fio_plan_stats.argtypes = [P, ctypes.POINTER(fio_plan_stats_t)]
     lib.fio_plan_trim.argtypes = [P, ctypes.c_int]
+    lib.fio_plan_fingerprints.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]
     lib.fio_stage_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(I64), ctypes.POINTER(I64),
                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_int)]
@@ -359,6 +361,15 @@ def fio_multi_autotune(plans, dtype: int, nrhs, reps: int = 3, stream=None):
 
 
 FIO_KEEP_ALL, FIO_KEEP_REFINE_C64 = 0, 1
+
+
+def fio_plan_fingerprints(plan: Plan) -> list:
+    lib = load_library()
+    n = ctypes.c_int()
+    _check(lib.fio_plan_fingerprints(plan.handle, None, 0, ctypes.byref(n)))
+    out = (ctypes.c_uint64 * max(n.value, 1))()
+    _check(lib.fio_plan_fingerprints(plan.handle, out, n.value, ctypes.byref(n)))
+    return list(out[:n.value])
 
 
 def fio_plan_trim(plan: Plan, keep: int):

@@ -89,3 +89,22 @@ def test_loaded_plan_equals_built_plan(tmp_path, d, n, phase, eps):
         a, _ = G.solve(built, mode, F.FIO_C64, x, tol=tol, maxit=maxit)
         b, _ = G.solve(loaded, mode, F.FIO_C64, x, tol=tol, maxit=maxit)
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_builds_give_identical_factors_2d(n):
+    """Two builds of the same 2D problem give bit-identical factors: the fingerprints
+    of the butterfly, of every skeletonization step and of the top-level inverse
+    agree.  The large skeletonization nodes, their IDs and the top-level inverse run
+    through the device's dense routines here (n = 256: 664 device IDs, 89 device
+    node factorizations), where concurrent streams once made builds differ."""
+    fps = []
+    for rep in range(2):
+        p = F.fio_build(F.make_problem(2, n, "2d_radon", eps=1e-4, device=0))
+        fps.append(F.fio_plan_fingerprints(p))
+        st = F.fio_plan_stats(p)
+        print("2D n=%d build %d: root %d, %d fingerprints, first %016x" % (n, rep, st["root_size"], len(fps[-1]),
+                                                                          fps[-1][0]), flush=True)
+        p.close()
+    assert len(fps[0]) == st["hif_levels"] + 2
+    assert fps[0] == fps[1], [i for i, (a, b) in enumerate(zip(*fps)) if a != b]

@@ -2,6 +2,7 @@
 factor construction (plans built with device = -1 are never applied on the CPU;
 their saved factors are multiplied out with NumPy here).
 """
+import ctypes
 import os
 import re
 
@@ -288,3 +289,23 @@ def test_column_id_checks_its_arguments():
         assert len(skel) == 0 and len(red) == 4
     except F.FioError as e:
         assert e.status in (1, 3)  # ordinal out of range or HIP error
+
+
+def test_fingerprints_identify_identical_factors(tmp_path):
+    """Host builds of one problem give equal fingerprints (butterfly, every
+    skeletonization step, top-level inverse); a saved and reloaded plan keeps them;
+    another tolerance changes them."""
+    def build(eps):
+        return F.fio_build(F.make_problem(1, 1024, "1d_ex1", eps=eps, device=-1))
+    a, b = build(1e-6), build(1e-6)
+    fa = F.fio_plan_fingerprints(a)
+    assert len(fa) == F.fio_plan_stats(a)["hif_levels"] + 2
+    assert fa == F.fio_plan_fingerprints(b)
+    path = str(tmp_path / "f.fio")
+    F.fio_save(a, path)
+    assert F.fio_plan_fingerprints(F.fio_load(path, -1)) == fa
+    fc = F.fio_plan_fingerprints(build(1e-4))
+    assert fc[0] != fa[0] and fc[-1] != fa[-1]
+    n = ctypes.c_int()
+    assert F.load_library().fio_plan_fingerprints(a.handle, None, 1, n) == 1   # FIO_ERR_ARG: no array
+    assert F.load_library().fio_plan_fingerprints(a.handle, None, 0, None) == 1  # nor count
