@@ -212,7 +212,8 @@ fio_status fio_gd_apply(fio_plan plan, fio_dtype dtype, const void *x, void *y,
 /* y = Gd x as fio_gd_apply, with every skeletonization step on one kernel:
  * 0 the LDS-staged per-node kernel, 1/2/3 gathered GEMMs on matrix cores in tiles of
  * 16 rows by 64/32/16 right-hand sides, 6 the same in tiles of 32 rows by 32, 7/8 of
- * 64 rows by 16/32, 4/5 the fused per-node matrix-core kernel with 64/32
+ * 64 rows by 16/32, 9/10/11 as 1/2/6 with three real products per complex
+ * multiply-add instead of four, 4/5 the fused per-node matrix-core kernel with 64/32
  * right-hand sides per workgroup (a step whose nodes exceed 64 redundant or 64
  * skeleton DOFs keeps its tuned choice), -1 the
  * tuned (else default) choice per step, which is what fio_gd_apply runs.  For tests

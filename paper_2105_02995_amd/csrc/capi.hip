@@ -623,9 +623,11 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
 // kernel for nodes of at most 64 redundant and 64 skeleton DOFs, 64 or 32
 // right-hand sides per workgroup (choices 4, 5).  `force` overrides the tuned
 // choice where it applies.
-constexpr int HIF_CHOICES = 9;
-// Tiling of a gathered-GEMM choice: rows per wave in 16-row tiles, columns per wave.
-bool hif_gemm_tiling(int choice, int &mt, int &cols) {
+constexpr int HIF_CHOICES = 12;
+// Tiling of a gathered-GEMM choice: rows per wave in 16-row tiles, columns per wave,
+// and whether a complex k-step takes three real products instead of four (9-11).
+bool hif_gemm_tiling(int choice, int &mt, int &cols, bool &m3) {
+    m3 = choice >= 9;
     switch (choice) {
         case 1: mt = 1; cols = 64; return true;
         case 2: mt = 1; cols = 32; return true;
@@ -633,6 +635,9 @@ bool hif_gemm_tiling(int choice, int &mt, int &cols) {
         case 6: mt = 2; cols = 32; return true;
         case 7: mt = 4; cols = 16; return true;
         case 8: mt = 4; cols = 32; return true;
+        case 9: mt = 1; cols = 64; return true;
+        case 10: mt = 1; cols = 32; return true;
+        case 11: mt = 2; cols = 32; return true;
         default: return false;
     }
 }
@@ -652,8 +657,9 @@ void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStr
         else choice = nrhs >= 64 ? 1 : 3;  // large nodes: gathered GEMMs over all nodes' row tiles
     }
     int mt = 1, cols = 16;
+    bool m3 = false;
     if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
-    else if (hif_gemm_tiling(choice, mt, cols)) launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, cols, st, mt);
+    else if (hif_gemm_tiling(choice, mt, cols, m3)) launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, cols, st, mt, m3);
     else launch_hif_step(h, dbl, up, x, nrhs, st);
 }
 
@@ -1303,14 +1309,15 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                         launch_hif_step(h, dbl, false, p->V2.p, nr, st);
                     });
                 }
-                for (int c : {1, 2, 3, 6, 7, 8}) {
+                for (int c : {1, 2, 3, 6, 7, 8, 9, 10, 11}) {
                     int mt = 1, cols = 16;
-                    hif_gemm_tiling(c, mt, cols);
+                    bool m3 = false;
+                    hif_gemm_tiling(c, mt, cols, m3);
                     if (nr <= 16 && cols > 16) continue;  // one 16-column tile covers the batch
                     if (mt > 1 && std::max(h.max_nr, h.max_ns) < 16 * mt) continue;  // rows would be padding
                     const float ms = timeit([&] {
-                        launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, cols, st, mt);
-                        launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, cols, st, mt);
+                        launch_hif_gemm_step(h, dbl, true, p->V2.p, p->HT.p, nr, cols, st, mt, m3);
+                        launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, cols, st, mt, m3);
                     });
                     if (ms < best_ms) { best_ms = ms; best = c; }
                 }
@@ -1729,8 +1736,13 @@ void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x
             } else if (I[i].nr >= 16) {  // large nodes: the instance's own gathered-GEMM launches
                 const auto *tn = p->tuned(dbl, I[i].nr);
                 int mt = 1, cols = 64;
-                if (tn && k < (int)tn->hif.size()) hif_gemm_tiling(tn->hif[k], mt, cols);
-                launch_hif_gemm_step(h, dbl, up, x[i], p->HT.p, I[i].nr, cols, st, mt);
+                bool m3 = false;
+                if (!(tn && k < (int)tn->hif.size() && hif_gemm_tiling(tn->hif[k], mt, cols, m3))) {
+                    mt = 1;
+                    cols = 64;
+                    m3 = false;
+                }
+                launch_hif_gemm_step(h, dbl, up, x[i], p->HT.p, I[i].nr, cols, st, mt, m3);
             } else {
                 launch_hif_step(h, dbl, up, x[i], I[i].nr, st);  // node blocks read from memory
             }

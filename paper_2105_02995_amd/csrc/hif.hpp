@@ -74,8 +74,9 @@ struct SkelHooks {
     HpdInverseFn hpd_inverse;
 };
 // The device implementations (rocBLAS GEMMs, rocSOLVER QR, Cholesky and triangular
-// inverse, FP64; eight device lanes shared by the host threads; a hook that runs out of
-// device memory declines, and the host path takes the node).
+// inverse, FP64; one device lane, a stream shared by the host threads one call at a
+// time, so that builds are deterministic; a hook that runs out of device memory
+// declines, and the host path takes the node).
 SkelHooks device_skel_hooks(int device);
 
 struct PeelOptions {

@@ -1141,7 +1141,7 @@ __device__ __forceinline__ void gfrag_load(Frag<R, MT, NT> &f, GWalk<R, MT, NT> 
 // (measured best: 8 for complex64, 4 for complex128)
 template <class R> struct HgPf { static constexpr int value = sizeof(R) == 4 ? 8 : 4; };
 
-template <class R, int PH, int MT, int NT>
+template <class R, int PH, int MT, int NT, bool M3 = false>
 __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
                                                const int32_t *__restrict__ idx,
                                                const int32_t *__restrict__ tiles,
@@ -1179,7 +1179,7 @@ __global__ void __launch_bounds__(256) k_hgemm(const int64_t *__restrict__ desc,
     const int n0 = chunk * (16 * NT);
     const int ncols = nrhs - n0;
     const int li = lane & 15, lk = lane >> 4;
-    Acc<R, MT, NT> acc;
+    typename std::conditional<M3, Acc3<R, MT, NT>, Acc<R, MT, NT>>::type acc;
     acc.zero();
     if (kbeg < kend && m > 0) {  // wave-uniform
         // this wave's gathered row indices kin[0..kend) in LDS (wave-local: LDS
@@ -1256,7 +1256,7 @@ __global__ void __launch_bounds__(256) k_hcopy(const int64_t *__restrict__ desc,
     }
 }
 
-template <class R, int MT, int NT>
+template <class R, int MT, int NT, bool M3>
 static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, void *x, void *t,
                         int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
@@ -1270,13 +1270,13 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
     static std::once_flag attr_once[6];  // plans may be used from several host threads
     if (lds > 65536) {
         std::call_once(attr_once[ph], [ph] {
-            const void *fn[6] = {(const void *)k_hgemm<R, 0, MT, NT>, (const void *)k_hgemm<R, 1, MT, NT>,
-                                 (const void *)k_hgemm<R, 2, MT, NT>, (const void *)k_hgemm<R, 3, MT, NT>,
-                                 (const void *)k_hgemm<R, 4, MT, NT>, (const void *)k_hgemm<R, 5, MT, NT>};
+            const void *fn[6] = {(const void *)k_hgemm<R, 0, MT, NT, M3>, (const void *)k_hgemm<R, 1, MT, NT, M3>,
+                                 (const void *)k_hgemm<R, 2, MT, NT, M3>, (const void *)k_hgemm<R, 3, MT, NT, M3>,
+                                 (const void *)k_hgemm<R, 4, MT, NT, M3>, (const void *)k_hgemm<R, 5, MT, NT, M3>};
             (void)hipFuncSetAttribute(fn[ph], hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
         });
     }
-#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, MT, NT>), g, dim3(256), lds, st, h.desc, h.idx, tiles, ntiles, mat, \
+#define HG(P) hipLaunchKernelGGL((k_hgemm<R, P, MT, NT, M3>), g, dim3(256), lds, st, h.desc, h.idx, tiles, ntiles, mat, \
                                  matH, (C *)x, (C *)t, nrhs, nch, maxk)
     switch (ph) {
         case 0: HG(0); break;
@@ -1289,28 +1289,34 @@ static void hgemm_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64
 #undef HG
 }
 
-// The register tilings of the gathered GEMMs: 16*MT rows x 16*NT columns per wave.
+// The register tilings of the gathered GEMMs: 16*MT rows x 16*NT columns per wave,
+// four or three (m3) real products per complex k-step.
 template <class R>
-static void hgemm_phase_tile(int mt, int nt, int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles,
-                             void *x, void *t, int nrhs, hipStream_t st) {
-    if (mt == 4) {
-        if (nt == 1) hgemm_phase<R, 4, 1>(ph, h, tiles, ntiles, x, t, nrhs, st);
-        else hgemm_phase<R, 4, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
+static void hgemm_phase_tile(int mt, int nt, bool m3, int ph, const HifStepDev &h, const int32_t *tiles,
+                             int64_t ntiles, void *x, void *t, int nrhs, hipStream_t st) {
+    if (m3) {
+        if (mt == 2) hgemm_phase<R, 2, 2, true>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else if (nt == 2) hgemm_phase<R, 1, 2, true>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else hgemm_phase<R, 1, 4, true>(ph, h, tiles, ntiles, x, t, nrhs, st);
+    } else if (mt == 4) {
+        if (nt == 1) hgemm_phase<R, 4, 1, false>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else hgemm_phase<R, 4, 2, false>(ph, h, tiles, ntiles, x, t, nrhs, st);
     } else if (mt == 2) {
-        hgemm_phase<R, 2, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        hgemm_phase<R, 2, 2, false>(ph, h, tiles, ntiles, x, t, nrhs, st);
     } else {
-        if (nt == 1) hgemm_phase<R, 1, 1>(ph, h, tiles, ntiles, x, t, nrhs, st);
-        else if (nt == 2) hgemm_phase<R, 1, 2>(ph, h, tiles, ntiles, x, t, nrhs, st);
-        else hgemm_phase<R, 1, 4>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        if (nt == 1) hgemm_phase<R, 1, 1, false>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else if (nt == 2) hgemm_phase<R, 1, 2, false>(ph, h, tiles, ntiles, x, t, nrhs, st);
+        else hgemm_phase<R, 1, 4, false>(ph, h, tiles, ntiles, x, t, nrhs, st);
     }
 }
 
 void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
-                          hipStream_t st, int mt) {
+                          hipStream_t st, int mt, bool m3) {
     if (h.n_nodes == 0) return;
     const int nt = cols <= 16 ? 1 : (cols <= 32 ? 2 : 4);
     if (mt != 1 && mt != 2 && mt != 4) throw std::runtime_error("hif step: 1, 2 or 4 row tiles per wave");
-    if ((mt == 4 && nt > 2) || (mt == 2 && nt != 2)) throw std::runtime_error("hif step: tiling not built");
+    if ((mt == 4 && nt > 2) || (mt == 2 && nt != 2) || (m3 && (mt == 4 || nt == 1)))
+        throw std::runtime_error("hif step: tiling not built");
     const int p0 = up ? 0 : 3;
     for (int k = 0; k < 3; ++k) {
         const int ph = p0 + k;
@@ -1323,8 +1329,8 @@ void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void 
                           : mt == 2 ? (srows ? h.n_tiles_s2 : h.n_tiles_r2)
                                     : (srows ? h.n_tiles_s : h.n_tiles_r);
         if (ntl > 0 && !tiles) throw std::runtime_error("hif step: tile list missing");
-        if (dbl) hgemm_phase_tile<double>(mt, nt, ph, h, tiles, ntl, x, t, nrhs, st);
-        else hgemm_phase_tile<float>(mt, nt, ph, h, tiles, ntl, x, t, nrhs, st);
+        if (dbl) hgemm_phase_tile<double>(mt, nt, m3, ph, h, tiles, ntl, x, t, nrhs, st);
+        else hgemm_phase_tile<float>(mt, nt, m3, ph, h, tiles, ntl, x, t, nrhs, st);
         check_launch("hif step (matrix cores)");
     }
     if (up && h.n_tiles_r > 0) {

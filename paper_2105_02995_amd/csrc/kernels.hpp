@@ -84,9 +84,10 @@ void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs,
 void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st);
 // Large-node variant of launch_hif_step (gathered GEMMs on matrix cores, tiles of
 // 16*mt rows by `cols` right-hand sides: mt 1 with cols 16, 32 or 64, mt 2 with 32,
-// mt 4 with 16 or 32); t is an N x nrhs temporary of the same dtype.
+// mt 4 with 16 or 32; m3: three real products per complex k-step, mt 1 with 32 or 64
+// columns or mt 2 with 32); t is an N x nrhs temporary of the same dtype.
 void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
-                          hipStream_t st, int mt = 1);
+                          hipStream_t st, int mt = 1, bool m3 = false);
 // Whether a step's largest node fits the LDS-staged kernel.
 bool hif_step_fits_lds(const HifStepDev &h, bool dbl);
 // One skeletonization step in a single launch for nodes with nr, ns <= 64: per
