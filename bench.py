@@ -106,6 +106,9 @@ def parse():
                     help="load the factors from this plan file if it exists, else build them and save them there")
     ap.add_argument("--plain-only", action="store_true",
                     help="run only the FP64 single-RHS comparator (for profiling its kernels)")
+    ap.add_argument("--plain-untuned", action="store_true",
+                    help="FP64 single-RHS comparator on the default kernel choices (no autotuning: "
+                         "profiled runs then launch the same kernels, whatever the profiler does to timings)")
     ap.add_argument("--trace", action="store_true",
                     help="named library ranges (fio_set_trace) during the timed steps, for a marker trace")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in kernel heuristics")
@@ -408,13 +411,14 @@ def roofline_of(F, torch, plan, stats, B, refine):
     return roof
 
 
-def plain_fp64(F, torch, plan, U, N, stream, ncols=16):
+def plain_fp64(F, torch, plan, U, N, stream, ncols=16, tune=True):
     """Plain FP64 path: complex128 factors, one right-hand side per call, direct
     solve (Gd Kd^* u), with the kernels autotuned for that width as the batched
-    path is for its own."""
-    t0 = time.perf_counter()
-    F.fio_autotune(plan, F.FIO_C128, 1, 3, stream)
-    log("autotuned the single-RHS FP64 path in %.1f s" % (time.perf_counter() - t0))
+    path is for its own (tune=False: the library's default choices)."""
+    if tune:
+        t0 = time.perf_counter()
+        F.fio_autotune(plan, F.FIO_C128, 1, 3, stream)
+        log("autotuned the single-RHS FP64 path in %.1f s" % (time.perf_counter() - t0))
     Uc = [U[j:j + 1].contiguous() for j in range(ncols)]
     Xc = [torch.zeros_like(Uc[0]) for _ in range(ncols)]
     for j in range(2):
@@ -427,8 +431,9 @@ def plain_fp64(F, torch, plan, U, N, stream, ncols=16):
     tp = time.perf_counter() - t0
     st = F.fio_plan_stats(plan)
     # algorithmic bytes of one complex128 direct solve: the Kd^* factors, the Gd
-    # factors (T, L^-1, M), the root block, and u in / fhat out
-    byts = (st["bf_nnz"] + st["hif_nnz"] + st["root_size"] ** 2 + 2 * N) * 16
+    # factors twice (the up sweep reads T^*, L^-1, M and the down sweep M^*, L^-*, T;
+    # the triangle of L^-1 only), the root block, and u in / fhat out
+    byts = (st["bf_nnz"] + 2 * st["hif_sweep_nnz"] + st["root_size"] ** 2 + 2 * N) * 16
     gbs = byts / (tp / ncols) / 1e9
     out = {"value": ncols * N / tp, "ms_per_rhs": 1000 * tp / ncols, "dtype": "c128", "nrhs_per_call": 1,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -474,7 +479,8 @@ def main():
     X = torch.zeros_like(U)
     stream = torch.cuda.current_stream()
     if args.plain_only:
-        print(json.dumps({"workload": wl.name, "plain_fp64_single_rhs": plain_fp64(F, torch, plan, U, N, stream)}),
+        print(json.dumps({"workload": wl.name, "plain_fp64_single_rhs": plain_fp64(F, torch, plan, U, N, stream,
+                                                                                tune=not args.plain_untuned)}),
               flush=True)
         plan.close()
         return
@@ -527,7 +533,7 @@ def main():
     log("spatial output (inverse DFT of the batch): %.4f ms" % spatial_ms)
 
     roof = roofline_of(F, torch, plan, stats, B, args.refine)
-    plain = None if args.no_plain else plain_fp64(F, torch, plan, U, N, stream)
+    plain = None if args.no_plain else plain_fp64(F, torch, plan, U, N, stream, tune=not args.plain_untuned)
     del X
     serving = None if args.no_serve else measure_serving(F, wl, plan, args)
 

@@ -215,7 +215,8 @@ fio_status fio_gd_apply(fio_plan plan, fio_dtype dtype, const void *x, void *y,
  * 64 rows by 16/32, 9/10/11 as 1/2/6 with three real products per complex
  * multiply-add instead of four, 4/5 the fused per-node matrix-core kernel with 64/32
  * right-hand sides per workgroup (a step whose nodes exceed 64 redundant or 64
- * skeleton DOFs keeps its tuned choice), -1 the
+ * skeleton DOFs keeps its tuned choice), 12 gathered matrix-vector products for
+ * small batches (64 rows per workgroup, any nrhs; the factor bytes bound it), -1 the
  * tuned (else default) choice per step, which is what fio_gd_apply runs.  For tests
  * and measurement: all variants agree to rounding.  Asynchronous.  Errors:
  * FIO_ERR_ARG (variant out of range, as fio_gd_apply otherwise). */
@@ -331,6 +332,10 @@ typedef struct {
                                       power iterations (4 Gaussian start vectors, FP64)     */
     double cond_est;               /* cond(Kd) = sqrt(lambda_max(Kd^* Kd) lambda_max(Gd)),
                                       each by 12 power iterations (Gd ~ (Kd^* Kd)^{-1})     */
+    int64_t hif_sweep_nnz;         /* entries one sweep of Gd reads: T, M and the lower
+                                      triangle of L^{-1} of every node (an apply of Gd makes
+                                      two sweeps, up with T^*, L^{-1}, M and down with M^*,
+                                      L^{-*}, T)                                          */
 } fio_plan_stats_t;
 
 fio_status fio_plan_stats(fio_plan plan, fio_plan_stats_t *out);

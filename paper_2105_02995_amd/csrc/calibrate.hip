@@ -1,7 +1,10 @@
 // fio_calibrate: measurement aid for the roofline figures of the library.
 //   fio_calibrate copy   1 GiB device-to-device copy kernel (known bytes), used to
 //                        scale the FETCH_SIZE / WRITE_SIZE counters of rocprofv3;
-//   fio_calibrate mfma   sustained 16x16x4 FP32 and FP64 MFMA rates (registers only).
+//   fio_calibrate mfma   sustained 16x16x4 FP32 and FP64 MFMA rates (registers only);
+//   fio_calibrate read   streaming read of 4 GiB (16-byte loads, eight in flight per
+//                        lane, one partial sum written per workgroup): the HBM read
+//                        rate a bandwidth-bound kernel can reach in practice.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -12,6 +15,28 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) calib_copy(const float4 *__restrict__ a, float4 *__restrict__ b, long n) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(256) calib_read(const float4 *__restrict__ a, float *__restrict__ out, long n) {
+    float4 s = {0.f, 0.f, 0.f, 0.f};
+    const long stride = (long)gridDim.x * blockDim.x;
+    long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    for (; i + 7 * stride < n; i += 8 * stride) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { s.x += v[u].x; s.y += v[u].y; s.z += v[u].z; s.w += v[u].w; }
+    }
+    for (; i < n; i += stride) { const float4 v = a[i]; s.x += v.x; s.y += v.y; s.z += v.z; s.w += v.w; }
+    __shared__ float red[256];
+    red[threadIdx.x] = s.x + s.y + s.z + s.w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < 256; ++k) t += red[k];
+        out[blockIdx.x] = t;
+    }
 }
 
 template <int NACC>
@@ -65,6 +90,26 @@ int main(int argc, char **argv) {
         printf("copy: 1 GiB read + 1 GiB write per dispatch, %.2f TB/s\n", 2.0 * n * 16 * reps / ms / 1e9);
         CK(hipFree(a));
         CK(hipFree(b));
+    } else if (!strcmp(mode, "read")) {
+        const long n = 1L << 28;  // float4 elements: 4 GiB
+        float4 *a;
+        float *o;
+        CK(hipMalloc(&a, n * 16));
+        CK(hipMalloc(&o, 65536 * sizeof(float)));
+        CK(hipMemset(a, 0, n * 16));
+        for (int blocks : {4096, 16384, 65536}) {
+            hipLaunchKernelGGL(calib_read, dim3(blocks), dim3(256), 0, 0, a, o, n);
+            CK(hipDeviceSynchronize());
+            const int reps = 5;
+            CK(hipEventRecord(e0));
+            for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(calib_read, dim3(blocks), dim3(256), 0, 0, a, o, n);
+            CK(hipEventRecord(e1));
+            CK(hipEventSynchronize(e1));
+            CK(hipEventElapsedTime(&ms, e0, e1));
+            printf("read: 4 GiB per dispatch, %d workgroups, %.2f TB/s\n", blocks, 1.0 * n * 16 * reps / ms / 1e9);
+        }
+        CK(hipFree(a));
+        CK(hipFree(o));
     } else {
         float *o;
         double *od;

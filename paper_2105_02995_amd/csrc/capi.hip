@@ -621,9 +621,10 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
 // in tiles of 16 rows by 64, 32 or 16 right-hand sides (choices 1, 2, 3) or of 32
 // rows by 32 (6) and 64 rows by 16 or 32 (7, 8), or the fused per-node matrix-core
 // kernel for nodes of at most 64 redundant and 64 skeleton DOFs, 64 or 32
-// right-hand sides per workgroup (choices 4, 5).  `force` overrides the tuned
-// choice where it applies.
-constexpr int HIF_CHOICES = 12;
+// right-hand sides per workgroup (choices 4, 5), or gathered matrix-vector products
+// for small batches (choice 12).  `force` overrides the tuned choice where it applies.
+constexpr int HIF_CHOICES = 13;
+constexpr int HIF_GEMV = 12;
 // Tiling of a gathered-GEMM choice: rows per wave in 16-row tiles, columns per wave,
 // and whether a complex k-step takes three real products instead of four (9-11).
 bool hif_gemm_tiling(int choice, int &mt, int &cols, bool &m3) {
@@ -654,11 +655,14 @@ void hif_step(fio_plan p, size_t k, bool dbl, bool up, void *x, int nrhs, hipStr
     if (choice < 0) {
         if (nrhs >= 16 && hif_fused_fits(h)) choice = 5;
         else if (hif_step_fits_lds(h, dbl)) choice = 0;
+        else if (nrhs < 16) choice = HIF_GEMV;  // large nodes, small batches: matrix-vector products
         else choice = nrhs >= 64 ? 1 : 3;  // large nodes: gathered GEMMs over all nodes' row tiles
     }
     int mt = 1, cols = 16;
     bool m3 = false;
     if (choice == 4 || choice == 5) launch_hif_fused_step(h, dbl, up, x, nrhs, st, choice == 4 ? 64 : 32);
+    else if (choice == HIF_GEMV)  // partial sums in the chain buffer P (idle during Gd)
+        launch_hif_gemv_step(h, dbl, up, x, ws.HT, nrhs, ws.P, (size_t)p->max_coef * nrhs * (dbl ? 16 : 8), st);
     else if (hif_gemm_tiling(choice, mt, cols, m3)) launch_hif_gemm_step(h, dbl, up, x, ws.HT, nrhs, cols, st, mt, m3);
     else launch_hif_step(h, dbl, up, x, nrhs, st);
 }
@@ -679,6 +683,19 @@ void root_apply(fio_plan p, bool dbl, void *x, int nrhs, hipStream_t st, const W
     s.A = p->A0inv.p;
     const auto *t = p->tuned(dbl, nrhs);
     if (t) s.variant = t->root;
+    if (nrhs < 16 && (s.variant < 0 || s.variant == STAGE_SMALL_BATCH)) {
+        // one block of s0/64 row chunks leaves most of the device idle: split its k range
+        // too (at least 64 columns per wave), partial sums in the GEMM temporary
+        // (N x nrhs of the working precision), added by the scatter
+        const int64_t rch = (p->s0 + 63) / 64, cch = (nrhs + 7) / 8;
+        const int64_t cap = p->host.N * (dbl ? 16 : 8) / (16 * (int64_t)p->s0);
+        const int ks = (int)std::min<int64_t>({16, std::max<int64_t>(1, 1024 / (rch * cch)), p->s0 / 256, cap});
+        if (ks >= 2) {
+            launch_stage_nb_split(s, true, ws.RI, ws.HT, nrhs, ks, st);
+            launch_rows_scatter_sum(ws.HT, ks, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
+            return;
+        }
+    }
     launch_stage(s, true, ws.RI, ws.RO, nrhs, st);
     launch_rows_scatter(ws.RO, true, (const int32_t *)p->root_idx.p, p->s0, nrhs, x, dbl, st);
 }
@@ -1028,7 +1045,11 @@ fio_status fio_plan_stats(fio_plan p, fio_plan_stats_t *o) {
         }
         o->hif_levels = (int)h.hif.steps.size();
         for (auto &st : h.hif.steps)
-            for (auto &nd : st.nodes) o->hif_nnz += (int64_t)nd.T.a.size() + nd.Linv.a.size() + nd.M.a.size();
+            for (auto &nd : st.nodes) {
+                const int64_t r = (int64_t)nd.idx_r.size();
+                o->hif_nnz += (int64_t)nd.T.a.size() + nd.Linv.a.size() + nd.M.a.size();
+                o->hif_sweep_nnz += (int64_t)nd.T.a.size() + nd.M.a.size() + r * (r + 1) / 2;
+            }
         o->root_size = (int)h.hif.root_idx.size();
         o->max_rank_h = h.hif.max_rank_h;
         o->hif_shifted = h.hif.shifted;
@@ -1320,6 +1341,14 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                         launch_hif_gemm_step(h, dbl, false, p->V2.p, p->HT.p, nr, cols, st, mt, m3);
                     });
                     if (ms < best_ms) { best_ms = ms; best = c; }
+                }
+                if (nr < 16) {
+                    const size_t pbytes = (size_t)p->max_coef * nr * (dbl ? 16 : 8);
+                    const float ms = timeit([&] {
+                        launch_hif_gemv_step(h, dbl, true, p->V2.p, p->HT.p, nr, p->P.p, pbytes, st);
+                        launch_hif_gemv_step(h, dbl, false, p->V2.p, p->HT.p, nr, p->P.p, pbytes, st);
+                    });
+                    if (ms < best_ms) { best_ms = ms; best = HIF_GEMV; }
                 }
                 if (hif_fused_fits(h)) {
                     for (int c = 4; c <= 5; ++c) {
@@ -1743,8 +1772,9 @@ void multi_gd(const std::vector<Inst> &I, bool dbl, const std::vector<void *> &x
                     m3 = false;
                 }
                 launch_hif_gemm_step(h, dbl, up, x[i], p->HT.p, I[i].nr, cols, st, mt, m3);
-            } else {
-                launch_hif_step(h, dbl, up, x[i], I[i].nr, st);  // node blocks read from memory
+            } else {  // large nodes, small batches: matrix-vector products
+                launch_hif_gemv_step(h, dbl, up, x[i], p->HT.p, I[i].nr, p->P.p,
+                                     (size_t)p->max_coef * I[i].nr * (dbl ? 16 : 8), st);
             }
         }
         if (cf > 0) launch_hif_multi(hf, xf, nf, cf, dbl, up, fkind, c.cap, st);

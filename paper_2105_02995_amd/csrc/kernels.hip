@@ -121,12 +121,15 @@ __global__ void __launch_bounds__(256) k_stage(int64_t n_out, int r_out, int r_i
 // sides; its four waves split the block's k range in four, so every wave streams a
 // quarter of the block's columns with coalesced 64-row loads, U k-steps of loads
 // issued before their products (the gathered input entries are the same for all
-// lanes: one broadcast load each), and the four partial sums meet in LDS.
+// lanes: one broadcast load each), and the four partial sums meet in LDS.  With
+// ksplit > 1 (few output blocks, e.g. the one dense top-level block) the k range is
+// also split over gridDim.z workgroups, each writing its partial sum to its own
+// slice y + z * zstride, for the caller to add.
 template <class T, int NB>
 __global__ void __launch_bounds__(256) k_stage_nb(int64_t n_out, int r_out, int r_in, int fan,
                                                   const int32_t *__restrict__ idx, const T *__restrict__ A,
                                                   const T *__restrict__ x, T *__restrict__ y, int nrhs,
-                                                  int rchunks) {
+                                                  int rchunks, int ksplit, int64_t zstride) {
     constexpr int U = NB <= 2 ? 8 : (NB == 4 ? 4 : 2);
     __shared__ T red[3 * 64 * NB];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -135,7 +138,9 @@ __global__ void __launch_bounds__(256) k_stage_nb(int64_t n_out, int r_out, int 
     const int ac = min(a, r_out - 1);
     const int c0 = blockIdx.y * NB;
     const int K = fan * r_in;
-    const int kb = (K * w) >> 2, ke = (K * (w + 1)) >> 2;
+    const int ka = (int)((int64_t)K * blockIdx.z / ksplit), kz = (int)((int64_t)K * (blockIdx.z + 1) / ksplit);
+    const int kb = ka + (((kz - ka) * w) >> 2), ke = ka + (((kz - ka) * (w + 1)) >> 2);
+    y += blockIdx.z * zstride;
     int cj[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) cj[j] = min(c0 + j, nrhs - 1);
@@ -188,21 +193,31 @@ __global__ void __launch_bounds__(256) k_stage_nb(int64_t n_out, int r_out, int 
 }
 
 template <class T, int NB>
-static void stage_nb_go(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
+static void stage_nb_go(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st, int ksplit) {
     const int rchunks = (s.r_out + 63) / 64;
     const int64_t nb = s.n_out * rchunks;
     if (nb >= ((int64_t)1 << 31)) throw std::runtime_error("stage launch exceeds the grid limit");
-    const dim3 g((unsigned)nb, (unsigned)((nrhs + NB - 1) / NB));
+    const dim3 g((unsigned)nb, (unsigned)((nrhs + NB - 1) / NB), (unsigned)ksplit);
     hipLaunchKernelGGL((k_stage_nb<T, NB>), g, dim3(256), 0, st, s.n_out, s.r_out, s.r_in, s.fan, s.idx,
-                       (const T *)s.A, (const T *)x, (T *)y, nrhs, rchunks);
+                       (const T *)s.A, (const T *)x, (T *)y, nrhs, rchunks, ksplit,
+                       s.n_out * (int64_t)s.r_out * nrhs);
 }
 
 template <class T>
-static void launch_stage_nb(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
-    if (nrhs <= 1) stage_nb_go<T, 1>(s, x, y, nrhs, st);
-    else if (nrhs <= 2) stage_nb_go<T, 2>(s, x, y, nrhs, st);
-    else if (nrhs <= 4) stage_nb_go<T, 4>(s, x, y, nrhs, st);
-    else stage_nb_go<T, 8>(s, x, y, nrhs, st);
+static void launch_stage_nb(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st, int ksplit = 1) {
+    if (nrhs <= 1) stage_nb_go<T, 1>(s, x, y, nrhs, st, ksplit);
+    else if (nrhs <= 2) stage_nb_go<T, 2>(s, x, y, nrhs, st, ksplit);
+    else if (nrhs <= 4) stage_nb_go<T, 4>(s, x, y, nrhs, st, ksplit);
+    else stage_nb_go<T, 8>(s, x, y, nrhs, st, ksplit);
+}
+
+void launch_stage_nb_split(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, int ksplit,
+                           hipStream_t st) {
+    if (ksplit < 1 || ksplit > 65535 || ksplit > s.fan * s.r_in)
+        throw std::runtime_error("stage: k split out of range");
+    if (dbl) launch_stage_nb<double2>(s, x, y, nrhs, st, ksplit);
+    else launch_stage_nb<float2>(s, x, y, nrhs, st, ksplit);
+    check_launch("stage (small batch, split k)");
 }
 
 // Batched stage on matrix cores.  One wave computes 16*MT rows of one output
@@ -1341,6 +1356,269 @@ void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void 
     }
 }
 
+// ------------------------------------------------------------------ skeletonization, small batches
+// Fewer than 16 right-hand sides: the six phases above as gathered matrix-vector
+// products, bound by the factor bytes.  A workgroup takes 64 output rows of one node
+// (one row per lane; the 64-row tile lists) and NB right-hand sides; its W waves
+// split the phase's k range and stream their share of the factor's columns with
+// coalesced 64-row loads (every phase reads a column-major factor), U k-steps of
+// loads issued before their products.  The gathered input entry of a k-step is the
+// same for all lanes of a wave (its row index a wave-uniform load, the entry one
+// broadcast load); the W partial sums meet in LDS.  Phases with few tiles take 16
+// waves per workgroup, so that the device holds enough loads in flight; phases whose
+// tiles have long k ranges (nodes of thousands of DOFs: one workgroup would stream
+// megabytes alone) also split each tile's k range over gridDim.z workgroups, which
+// write their partial sums to `part` for k_hgemv_sum to add in a fixed order.  The
+// launch of phase 2 also carries the end of the up sweep, x_r = t_r, in extra
+// workgroups over the 64-row tiles of the redundant rows (phase 2 reads t_r and
+// writes x_s only).
+template <class T, int PH, int NB, int W>
+__global__ void __launch_bounds__(64 * W) k_hgemv(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                                  const int32_t *__restrict__ tiles, int64_t ntiles,
+                                                  const int32_t *__restrict__ ctiles, const T *__restrict__ mat,
+                                                  const T *__restrict__ matH, T *__restrict__ x, T *__restrict__ t,
+                                                  int nrhs, T *__restrict__ part) {
+    constexpr int U = NB <= 2 ? 8 : (NB == 4 ? 4 : 2);
+    __shared__ T red[(W - 1) * 64 * NB];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = blockIdx.y * NB;
+    if (PH == 2 && (int64_t)blockIdx.x >= ntiles) {  // workgroup-uniform: x_r = t_r
+        if (blockIdx.z != 0) return;
+        const int64_t ct = blockIdx.x - ntiles;
+        const int v = ctiles[2 * ct], row0 = ctiles[2 * ct + 1];
+        const int nr = (int)desc[4 * v];
+        const int32_t *ir = idx + desc[4 * v + 2];
+        for (int e = threadIdx.x; e < 64 * NB; e += 64 * W) {
+            const int row = row0 + e / NB, col = c0 + e % NB;
+            if (row < nr && col < nrhs) {
+                const int64_t g = (int64_t)ir[row] * nrhs + col;
+                x[g] = t[g];
+            }
+        }
+        return;
+    }
+    const int64_t tile = blockIdx.x;
+    const int v = tiles[2 * tile], row0 = tiles[2 * tile + 1];
+    const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
+    const int32_t *ir = idx + desc[4 * v + 2];
+    const int32_t *is = ir + nr;
+    const int64_t mo = desc[4 * v + 3];
+    constexpr bool SUB = (PH == 0 || PH == 2 || PH == 3 || PH == 5);
+    const int m = (PH == 2 || PH == 5) ? ns : nr;
+    const int K = (PH == 0 || PH == 3) ? ns : nr;
+    const int ld = m;
+    const int64_t off = (PH == 0 || PH == 5) ? 0 : ((PH == 1 || PH == 4) ? (int64_t)ns * nr : (int64_t)ns * nr + (int64_t)nr * nr);
+    const T *S = ((PH == 0 || PH == 3 || PH == 4) ? matH : mat) + mo + off;
+    const int32_t *kin = (PH == 0 || PH == 3) ? is : ir;
+    const T *src = (PH == 2 || PH == 4) ? t : x;
+    const int32_t *oout = (PH == 2 || PH == 5) ? is : ir;
+    T *dst = (PH == 1 || PH == 3) ? t : x;
+    const T *yin = (PH == 3) ? x : dst;
+    // L^-1 is lower triangular: phase 1 stops at the tile's last row, phase 4 starts at its first
+    const int kbeg = (PH == 4) ? row0 : 0;
+    const int kend = (PH == 1) ? min(K, row0 + 64) : K;
+    const int span = max(kend - kbeg, 0);
+    const int za = kbeg + (int)((int64_t)span * blockIdx.z / gridDim.z);
+    const int zspan = kbeg + (int)((int64_t)span * (blockIdx.z + 1) / gridDim.z) - za;
+    const int kb = za + (zspan * w) / W, ke = za + (zspan * (w + 1)) / W;
+    const int row = row0 + lane;
+    const T *Sp = S + min(row, m - 1);
+    int cj[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) cj[j] = min(c0 + j, nrhs - 1);
+    T acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = cz(T());
+    int k = kb;
+    for (; k + U <= ke; k += U) {
+        T av[U], xv[U][NB];
+#pragma unroll
+        for (int u = 0; u < U; ++u) av[u] = Sp[(int64_t)(k + u) * ld];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T *xr = src + (int64_t)kin[k + u] * nrhs;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) xv[u][j] = xr[cj[j]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = cfma(acc[j], av[u], xv[u][j]);
+    }
+    for (; k < ke; ++k) {
+        const T av = Sp[(int64_t)k * ld];
+        const T *xr = src + (int64_t)kin[k] * nrhs;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j] = cfma(acc[j], av, xr[cj[j]]);
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) red[((w - 1) * 64 + lane) * NB + j] = acc[j];
+    }
+    __syncthreads();
+    if (w == 0 && gridDim.z > 1) {  // partial sum of this k slice
+        T *pp = part + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * ntiles + tile) * 64 * NB;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            T s = acc[j];
+#pragma unroll
+            for (int q = 0; q < W - 1; ++q) {
+                const T r = red[(q * 64 + lane) * NB + j];
+                s.x += r.x;
+                s.y += r.y;
+            }
+            pp[lane * NB + j] = s;
+        }
+    } else if (w == 0 && row < m) {
+        const int64_t orow = (int64_t)oout[row] * nrhs;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            T s = acc[j];
+#pragma unroll
+            for (int q = 0; q < W - 1; ++q) {
+                const T r = red[(q * 64 + lane) * NB + j];
+                s.x += r.x;
+                s.y += r.y;
+            }
+            if (c0 + j >= nrhs) continue;
+            if (SUB) {
+                const T b = yin[orow + c0 + j];
+                s = T{b.x - s.x, b.y - s.y};
+            }
+            dst[orow + c0 + j] = s;
+        }
+    }
+}
+
+// Output of a split phase: the gridDim.z partial sums of each tile row, added in
+// slice order, then stored (or subtracted) as k_hgemv stores its sums.
+template <class T, int PH, int NB>
+__global__ void __launch_bounds__(64) k_hgemv_sum(const int64_t *__restrict__ desc, const int32_t *__restrict__ idx,
+                                                  const int32_t *__restrict__ tiles, int64_t ntiles, int ks,
+                                                  const T *__restrict__ part, T *__restrict__ x, T *__restrict__ t,
+                                                  int nrhs) {
+    const int64_t tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int v = tiles[2 * tile], row0 = tiles[2 * tile + 1];
+    const int nr = (int)desc[4 * v], ns = (int)desc[4 * v + 1];
+    const int32_t *ir = idx + desc[4 * v + 2];
+    const int32_t *is = ir + nr;
+    constexpr bool SUB = (PH == 0 || PH == 2 || PH == 3 || PH == 5);
+    const int m = (PH == 2 || PH == 5) ? ns : nr;
+    const int32_t *oout = (PH == 2 || PH == 5) ? is : ir;
+    T *dst = (PH == 1 || PH == 3) ? t : x;
+    const T *yin = (PH == 3) ? x : dst;
+    const int row = row0 + lane;
+    if (row >= m) return;
+    const int c0 = blockIdx.y * NB;
+    const int64_t orow = (int64_t)oout[row] * nrhs;
+    const int64_t zs = (int64_t)gridDim.y * ntiles * 64 * NB;
+    const T *pp = part + ((int64_t)blockIdx.y * ntiles + tile) * 64 * NB + lane * NB;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if (c0 + j >= nrhs) continue;
+        T r[16];  // ks <= 16: every load issued before the first sum
+#pragma unroll
+        for (int z = 0; z < 16; ++z)
+            if (z < ks) r[z] = pp[z * zs + j];
+        T s = r[0];
+#pragma unroll
+        for (int z = 1; z < 16; ++z)
+            if (z < ks) {
+                s.x += r[z].x;
+                s.y += r[z].y;
+            }
+        if (SUB) {
+            const T b = yin[orow + c0 + j];
+            s = T{b.x - s.x, b.y - s.y};
+        }
+        dst[orow + c0 + j] = s;
+    }
+}
+
+template <class T, int NB, int W>
+static void hgemv_phase_w(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, int64_t ncopy,
+                          int ks, void *part, void *x, void *t, int nrhs, hipStream_t st) {
+    const dim3 g((unsigned)(ntiles + ncopy), (unsigned)((nrhs + NB - 1) / NB), (unsigned)ks);
+    const dim3 gs((unsigned)ntiles, g.y);
+#define HV(P) hipLaunchKernelGGL((k_hgemv<T, P, NB, W>), g, dim3(64 * W), 0, st, h.desc, h.idx, tiles, ntiles, \
+                                 h.tiles_r4, (const T *)h.mat, (const T *)h.matH, (T *)x, (T *)t, nrhs, (T *)part)
+#define HS(P) hipLaunchKernelGGL((k_hgemv_sum<T, P, NB>), gs, dim3(64), 0, st, h.desc, h.idx, tiles, ntiles, ks, \
+                                 (const T *)part, (T *)x, (T *)t, nrhs)
+    switch (ph) {
+        case 0: HV(0); break;
+        case 1: HV(1); break;
+        case 2: HV(2); break;
+        case 3: HV(3); break;
+        case 4: HV(4); break;
+        default: HV(5); break;
+    }
+    if (ks > 1 && ntiles > 0) {
+        switch (ph) {
+            case 0: HS(0); break;
+            case 1: HS(1); break;
+            case 2: HS(2); break;
+            case 3: HS(3); break;
+            case 4: HS(4); break;
+            default: HS(5); break;
+        }
+    }
+#undef HS
+#undef HV
+}
+
+// Launch shape of a phase: with fewer tiles than compute units and long k ranges
+// (K >= 512), the k range of each tile is split into ks slices (at most K / 256, 16,
+// about 1024 workgroups in all, and as many as `part` holds) on workgroups of 4
+// waves; else, with fewer tiles than four per compute unit, whole tiles on
+// workgroups of 16 waves (NB <= 2, so that the LDS of the partial sums stays small);
+// otherwise 4 waves.
+template <class T, int NB>
+static void hgemv_phase(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, int64_t ncopy,
+                        void *part, size_t part_bytes, void *x, void *t, int nrhs, hipStream_t st) {
+    if (ntiles + ncopy == 0) return;
+    if (ntiles + ncopy >= ((int64_t)1 << 31)) throw std::runtime_error("hif step: tile count exceeds the grid limit");
+    const int K = (ph == 0 || ph == 3) ? h.max_ns : h.max_nr;
+    int ks = 1;
+    if (ntiles > 0 && ntiles < 256 && part) {
+        const int64_t slice = (int64_t)((nrhs + NB - 1) / NB) * ntiles * 64 * NB * sizeof(T);
+        ks = (int)std::min<int64_t>({16, K / 256, (1024 + ntiles - 1) / ntiles,
+                                     (int64_t)(part_bytes / std::max<int64_t>(1, slice))});
+        ks = std::max(ks, 1);
+    }
+    if (ks > 1) hgemv_phase_w<T, NB, 4>(ph, h, tiles, ntiles, ncopy, ks, part, x, t, nrhs, st);
+    else if (NB <= 2 && ntiles < 1024) hgemv_phase_w<T, NB, (NB <= 2 ? 16 : 4)>(ph, h, tiles, ntiles, ncopy, 1, part, x, t, nrhs, st);
+    else hgemv_phase_w<T, NB, 4>(ph, h, tiles, ntiles, ncopy, 1, part, x, t, nrhs, st);
+}
+
+template <class T>
+static void hgemv_phase_nb(int ph, const HifStepDev &h, const int32_t *tiles, int64_t ntiles, int64_t ncopy,
+                           void *part, size_t part_bytes, void *x, void *t, int nrhs, hipStream_t st) {
+    if (nrhs <= 1) hgemv_phase<T, 1>(ph, h, tiles, ntiles, ncopy, part, part_bytes, x, t, nrhs, st);
+    else if (nrhs <= 2) hgemv_phase<T, 2>(ph, h, tiles, ntiles, ncopy, part, part_bytes, x, t, nrhs, st);
+    else if (nrhs <= 4) hgemv_phase<T, 4>(ph, h, tiles, ntiles, ncopy, part, part_bytes, x, t, nrhs, st);
+    else hgemv_phase<T, 8>(ph, h, tiles, ntiles, ncopy, part, part_bytes, x, t, nrhs, st);
+}
+
+void launch_hif_gemv_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, void *part,
+                          size_t part_bytes, hipStream_t st) {
+    if (h.n_nodes == 0) return;
+    if (h.n_tiles_r4 > 0 && !h.tiles_r4) throw std::runtime_error("hif step: tile list missing");
+    const int p0 = up ? 0 : 3;
+    for (int k = 0; k < 3; ++k) {
+        const int ph = p0 + k;
+        const bool srows = (ph == 2 || ph == 5);
+        const int32_t *tiles = srows ? h.tiles_s4 : h.tiles_r4;
+        const int64_t ntl = srows ? h.n_tiles_s4 : h.n_tiles_r4;
+        const int64_t ncopy = (ph == 2) ? h.n_tiles_r4 : 0;  // x_r = t_r with phase 2
+        if (ntl > 0 && !tiles) throw std::runtime_error("hif step: tile list missing");
+        if (dbl) hgemv_phase_nb<double2>(ph, h, tiles, ntl, ncopy, part, part_bytes, x, t, nrhs, st);
+        else hgemv_phase_nb<float2>(ph, h, tiles, ntl, ncopy, part, part_bytes, x, t, nrhs, st);
+        check_launch("hif step (small batch)");
+    }
+}
+
 bool hif_step_fits_lds(const HifStepDev &h, bool dbl) {
     const int elt = dbl ? 16 : 8;
     const int64_t budget = hif_lds_budget();
@@ -1624,6 +1902,38 @@ __global__ void __launch_bounds__(256) k_rows_scatter(const Ti *__restrict__ in,
                                                       int64_t rows, int nrhs, To *__restrict__ x) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * nrhs; e += (int64_t)gridDim.x * blockDim.x)
         x[(int64_t)idx[e / nrhs] * nrhs + e % nrhs] = cvt<To, Ti>(in[e]);
+}
+
+// x[idx[r] * nrhs + b] = sum over z < parts of in[z * rows * nrhs + r * nrhs + b]
+// (complex128 partial sums, summed in order), with conversion.
+template <class To>
+__global__ void __launch_bounds__(256) k_rows_scatter_sum(const double2 *__restrict__ in, int parts,
+                                                          const int32_t *__restrict__ idx, int64_t rows, int nrhs,
+                                                          To *__restrict__ x) {
+    const int64_t n = rows * nrhs;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double2 v[16];  // parts <= 16: every load issued before the first sum
+#pragma unroll
+        for (int z = 0; z < 16; ++z)
+            if (z < parts) v[z] = in[z * n + e];
+        double2 s = v[0];
+#pragma unroll
+        for (int z = 1; z < 16; ++z)
+            if (z < parts) {
+                s.x += v[z].x;
+                s.y += v[z].y;
+            }
+        x[(int64_t)idx[e / nrhs] * nrhs + e % nrhs] = cvt<To, double2>(s);
+    }
+}
+
+void launch_rows_scatter_sum(const void *in, int parts, const int32_t *idx, int64_t rows, int nrhs, void *x,
+                             bool xd, hipStream_t st) {
+    if (parts < 1 || parts > 16) throw std::runtime_error("rows scatter: 1 to 16 parts");
+    const unsigned g = grid_for(rows * nrhs, 256);
+    if (xd) hipLaunchKernelGGL(k_rows_scatter_sum<double2>, dim3(g), dim3(256), 0, st, (const double2 *)in, parts, idx, rows, nrhs, (double2 *)x);
+    else hipLaunchKernelGGL(k_rows_scatter_sum<float2>, dim3(g), dim3(256), 0, st, (const double2 *)in, parts, idx, rows, nrhs, (float2 *)x);
+    check_launch("rows scatter (sum of parts)");
 }
 
 void launch_rows_gather(const void *x, bool xd, const int32_t *idx, int64_t rows, int nrhs, void *out, bool od,

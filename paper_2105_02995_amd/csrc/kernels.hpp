@@ -88,6 +88,12 @@ void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, 
 // columns or mt 2 with 32); t is an N x nrhs temporary of the same dtype.
 void launch_hif_gemm_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, int cols,
                           hipStream_t st, int mt = 1, bool m3 = false);
+// Small-batch variant (fewer than 16 right-hand sides): each phase as gathered
+// matrix-vector products over the 64-row tiles, bound by the factor bytes; t as above;
+// part (part_bytes, may be null) holds the partial sums of phases whose k ranges are
+// split over workgroups (fewer slices, or none, where it is too small).
+void launch_hif_gemv_step(const HifStepDev &h, bool dbl, bool up, void *x, void *t, int nrhs, void *part,
+                          size_t part_bytes, hipStream_t st);
 // Whether a step's largest node fits the LDS-staged kernel.
 bool hif_step_fits_lds(const HifStepDev &h, bool dbl);
 // One skeletonization step in a single launch for nodes with nr, ns <= 64: per
@@ -99,6 +105,14 @@ void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int 
                            int cols = 64);
 void launch_rows_gather(const void *x, bool xd, const int32_t *idx, int64_t rows, int nrhs, void *out, bool od,
                         hipStream_t st);
+// The small-batch stage kernel with its k range split over ksplit workgroups: y
+// receives ksplit partial results, slice z at y + z * n_out * r_out * nrhs.
+void launch_stage_nb_split(const StageDev &s, bool dbl, const void *x, void *y, int nrhs, int ksplit,
+                           hipStream_t st);
+// x[idx[r] * nrhs + b] = sum over z < parts of in[(z * rows + r) * nrhs + b] (in
+// complex128), converted to x's dtype.
+void launch_rows_scatter_sum(const void *in, int parts, const int32_t *idx, int64_t rows, int nrhs, void *x,
+                             bool xd, hipStream_t st);
 void launch_rows_scatter(const void *in, bool id, const int32_t *idx, int64_t rows, int nrhs, void *x, bool xd,
                          hipStream_t st);
 void launch_root(const int32_t *idx, const void *A0inv, int s0, bool dbl, void *x, int nrhs,

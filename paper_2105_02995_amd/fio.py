@@ -77,7 +77,8 @@ class fio_plan_stats_t(ctypes.Structure):
                 ("build_seconds", ctypes.c_double), ("hif_shifted", ctypes.c_int),
                 ("bf_seconds", ctypes.c_double), ("bf_device_levels", ctypes.c_int),
                 ("hif_device_ids", ctypes.c_int), ("hif_device_nodes", ctypes.c_int),
-                ("e_a_est", ctypes.c_double), ("e_s_est", ctypes.c_double), ("cond_est", ctypes.c_double)]
+                ("e_a_est", ctypes.c_double), ("e_s_est", ctypes.c_double), ("cond_est", ctypes.c_double),
+                ("hif_sweep_nnz", ctypes.c_int64)]
 
 
 _lib = None

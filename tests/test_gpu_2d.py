@@ -134,6 +134,17 @@ def test_2d_n256_batch256_sampled_columns_and_rows():
     log("2D n=256 refine rel err %s" % err)
     assert np.isfinite(x).all()
     assert err.max() < 10 * EPS
+    # small batches (Gd's matrix-vector kernels over nodes of up to 2098 redundant
+    # DOFs, the top-level block with its k range split over workgroups): one column
+    # as the plain FP64 direct solve (tuned for one column), three in complex64 with
+    # one refinement step (default kernel choices)
+    F.fio_autotune(plan, F.FIO_C128, 1, 2, G.stream())
+    for dtype, mode, b in ((F.FIO_C128, F.FIO_SOLVE_DIRECT, 1), (F.FIO_C64, F.FIO_SOLVE_REFINE, 3)):
+        xs, _ = G.solve(plan, mode, dtype, u[:, cols[:b]], maxit=1)
+        e = O.rel_err(xs, fh[:, :b])
+        log("2D n=256 %d column(s), dtype %d, mode %d: rel err %s" % (b, dtype, mode, e))
+        assert np.isfinite(xs).all()
+        assert e.max() < 10 * EPS
     # sampled rows of Kd v and Kd^* v (complex128 applies) against the direct sums
     rows = np.sort(np.random.default_rng(11).choice(N, size=48, replace=False))
     v = gaussian_complex((N, 2), 3007)

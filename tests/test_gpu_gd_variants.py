@@ -51,12 +51,12 @@ def gd_gpu(plan, dtype, variant, x):
 
 
 @pytest.mark.parametrize("d,n,phase,eps", [(1, 4096, "1d_ex1", 1e-6), (2, 64, "2d_radon", 1e-4)])
-@pytest.mark.parametrize("B", [64, 37, 8])
+@pytest.mark.parametrize("B", [64, 37, 8, 3, 1])
 def test_every_skeletonization_kernel_matches_saved_factors(tmp_path, d, n, phase, eps, B):
     plan, f = plan_and_factors(d, n, phase, eps, tmp_path)
     x = gaussian_complex((n ** d, B), 60 + B)
     ref = FF.from_tree(f, FF.gd(f, FF.to_tree(f, x)))
-    for variant in range(-1, 12):
+    for variant in range(-1, 13):
         log("Gd d=%d n=%d B=%d variant %d" % (d, n, B, variant))
         e128 = O.rel_err(gd_gpu(plan, F.FIO_C128, variant, x), ref).max()
         e64 = O.rel_err(gd_gpu(plan, F.FIO_C64, variant, x), ref).max()
@@ -69,7 +69,7 @@ def test_variant_out_of_range_is_an_argument_error(tmp_path):
     plan, _ = plan_and_factors(1, 4096, "1d_ex1", 1e-6, tmp_path)
     X = G.empty(4096, 4)
     with pytest.raises(F.FioError) as e:
-        F.fio_gd_apply_variant(plan, F.FIO_C128, 12, X, X, 4, 4096, G.stream())
+        F.fio_gd_apply_variant(plan, F.FIO_C128, 13, X, X, 4, 4096, G.stream())
     assert e.value.status == 1
 
 
@@ -84,10 +84,27 @@ def test_prescaled_factors_on_every_kernel(tmp_path):
     f = FF.read(path)
     x = gaussian_complex((4096, 48), 91)
     ref = FF.from_tree(f, FF.gd(f, FF.to_tree(f, x)))
-    for variant in range(-1, 12):
+    for variant in range(-1, 13):
         log("prescaled Gd variant %d" % variant)
         assert O.rel_err(gd_gpu(plan, F.FIO_C128, variant, x), ref).max() < 1e-12
         assert O.rel_err(gd_gpu(plan, F.FIO_C64, variant, x), ref).max() < 1e-5
     K = O.dense_K(O.OracleProblem(1, 4096, "1d_ex1", 16.0))
     u = K @ x[:, :8]
     assert O.rel_err(G.inverse(plan, F.FIO_C128, u), x[:, :8]).max() < 10 * eps
+
+
+@pytest.mark.parametrize("B", [1, 2, 5])
+def test_small_batch_kernel_2d_n128(tmp_path, B):
+    """The small-batch skeletonization kernel on the large nodes of 2D n=128 (phases
+    with few tiles and long k ranges run split over workgroups, their partial sums
+    added by a second launch; the others on 16-wave or 4-wave workgroups), against
+    the host product of the saved factors."""
+    plan, f = plan_and_factors(2, 128, "2d_radon", 1e-4, tmp_path)
+    x = gaussian_complex((128 * 128, B), 70 + B)
+    ref = FF.from_tree(f, FF.gd(f, FF.to_tree(f, x)))
+    for variant in (-1, 12):
+        e128 = O.rel_err(gd_gpu(plan, F.FIO_C128, variant, x), ref).max()
+        e64 = O.rel_err(gd_gpu(plan, F.FIO_C64, variant, x), ref).max()
+        log("Gd 2D n=128 B=%d variant %d: c128 %.2e  c64 %.2e" % (B, variant, e128, e64))
+        assert e128 < 1e-12
+        assert e64 < 1e-5
