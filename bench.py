@@ -58,6 +58,17 @@ MFMA_COUNTERS = {
 }
 
 
+# HBM bytes per plain FP64 single-RHS solve (every launch), the same counters and
+# calibration, default kernel choices (profiles/plain_fp64_2d_n256_traffic.md).
+PLAIN_TRAFFIC = {
+    "plain_fp64": {
+        "bytes": 2.1873e10,
+        "kernels_sha256": "7adada25df8b60eb8dfd955bedda8c1e5b1e41a43606c27eaec59418979fb264",
+        "bf_nnz": 1138753536,
+    },
+}
+
+
 def counted(table, name, bf_nnz):
     """The entry of a counter table for this kernel, or None if the kernel source or
     the factors (their nonzero count) differ from the ones profiled."""
@@ -434,10 +445,14 @@ def plain_fp64(F, torch, plan, U, N, stream, ncols=16, tune=True):
     # factors twice (the up sweep reads T^*, L^-1, M and the down sweep M^*, L^-*, T;
     # the triangle of L^-1 only), the root block, and u in / fhat out
     byts = (st["bf_nnz"] + 2 * st["hif_sweep_nnz"] + st["root_size"] ** 2 + 2 * N) * 16
+    tp_entry = counted(PLAIN_TRAFFIC, "plain_fp64", st["bf_nnz"])
+    traffic_plain = None if tp_entry is None else tp_entry["bytes"]
     gbs = byts / (tp / ncols) / 1e9
     out = {"value": ncols * N / tp, "ms_per_rhs": 1000 * tp / ncols, "dtype": "c128", "nrhs_per_call": 1,
            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_rhs": byts,
+                        "traffic": traffic_plain, "traffic_over_algorithmic":
+                            None if traffic_plain is None else round(traffic_plain / byts, 3),
                         "what": "whole direct solve (every launch of Kd^*, Gd and layout)"}}
     log("plain FP64 single-RHS: %.3f ms/RHS, %.3e RHS*N/s, %.0f GB/s of factor bytes" % (
         1000 * tp / ncols, out["value"], gbs))
