@@ -309,3 +309,24 @@ def test_fingerprints_identify_identical_factors(tmp_path):
     n = ctypes.c_int()
     assert F.load_library().fio_plan_fingerprints(a.handle, None, 1, n) == 1   # FIO_ERR_ARG: no array
     assert F.load_library().fio_plan_fingerprints(a.handle, None, 0, None) == 1  # nor count
+
+
+def test_plan_stats_count_the_factor_entries(tmp_path):
+    """fio_plan_stats against the saved factors (section 4): hif_nnz counts every
+    entry of T, L^-1 and M; hif_sweep_nnz the entries one sweep of Gd reads, T, M
+    and the lower triangle of L^-1 (whose upper part is zero); bf_nnz every entry of
+    the butterfly stages (section 2); the root block is square."""
+    plan, f, _ = _host_plan(tmp_path)
+    st = F.fio_plan_stats(plan)
+    full = sweep = 0
+    for nodes in f["steps"]:
+        for nd in nodes:
+            r = nd["Linv"].shape[0]
+            assert np.allclose(np.triu(nd["Linv"], 1), 0)
+            full += nd["T"].size + nd["Linv"].size + nd["M"].size
+            sweep += nd["T"].size + nd["M"].size + r * (r + 1) // 2
+    assert st["hif_nnz"] == full
+    assert st["hif_sweep_nnz"] == sweep
+    assert 0 < sweep < full
+    assert st["bf_nnz"] == sum(s["A"].size for s in f["stages"])
+    assert st["root_size"] ** 2 == f["A0inv"].size
