@@ -324,15 +324,28 @@ def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
     x = X.cpu().numpy().T
     finite = bool(np.isfinite(x).all())
     err = O.rel_err(x[:, cols], fh) if finite else np.full(len(cols), np.inf)
-    # the oracle's CG count and a measured dense solve at the small size
+    # the oracle's CG count and a measured dense solve at the small size: K formation,
+    # LU and the solves, median of 3 with the BLAS on all its threads, and once with
+    # one thread
     small_n = 4096 if wl.d == 1 else 64
     ps = O.OracleProblem(wl.d, small_n, wl.phase, wl.c_div)
     Ns = ps.N
-    t0 = time.perf_counter()
-    K = O.dense_K(ps)
     us = gaussian_complex((Ns, B), wl.seed + 102)
-    O.solve_dense(ps, us, K)
-    t_lu = time.perf_counter() - t0
+
+    def dense_solve():
+        t0 = time.perf_counter()
+        Kd = O.dense_K(ps)
+        O.solve_dense(ps, us, Kd)
+        return time.perf_counter() - t0, Kd
+
+    from threadpoolctl import threadpool_info, threadpool_limits
+    blas_threads = max([i.get("num_threads", 0) for i in threadpool_info()] or [0])
+    runs = [dense_solve() for _ in range(3)]
+    t_lu = float(np.median([r[0] for r in runs]))
+    K = runs[0][1]
+    del runs
+    with threadpool_limits(limits=1):
+        t_lu1, _ = dense_solve()
     _, iters = O.cg_normal(lambda v: K @ v, lambda v: K.conj().T @ v, gaussian_complex(Ns, 99), tol=1e-8)
     del K
     per_solve = (2 * iters + 1) * t_prod          # ncol right-hand sides
@@ -343,8 +356,12 @@ def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
                       "to 1e-8)" % (ncol, N, t_prod, 2 * iters + 1, iters,
                                     "N=%d" % small_n if wl.d == 1 else "n=%d" % small_n),
             "measured_small": {"value": B * Ns / t_lu, "unit": "RHS*N/s", "seconds": t_lu,
-                               "sample": "dense LU oracle solve at %s (N=%d): K formation, LU, %d RHS"
-                                         % ("N=%d" % small_n if wl.d == 1 else "2D n=%d" % small_n, Ns, B)}}
+                               "blas_threads": blas_threads, "os_cpu_count": os.cpu_count(),
+                               "sample": "dense LU oracle solve at %s (N=%d): K formation, LU, %d RHS; "
+                                         "median of 3" % ("N=%d" % small_n if wl.d == 1 else "2D n=%d" % small_n,
+                                                          Ns, B)},
+            "measured_small_1thread": {"value": B * Ns / t_lu1, "unit": "RHS*N/s", "seconds": t_lu1,
+                                       "blas_threads": 1, "sample": "the same solve, BLAS limited to one thread"}}
     check = {"rel_err_vs_oracle": float(err.max()), "rel_err_median": float(np.median(err)),
              "columns": [int(c) for c in cols], "bound": 10 * wl.eps, "finite": finite}
     return base, check
