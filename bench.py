@@ -111,6 +111,8 @@ def parse():
     ap.add_argument("--workload", default="2d_n256", choices=sorted(WORKLOADS))
     ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-calibration", action="store_true",
+                    help="skip the measured device ceilings (streaming read, matrix-core loop)")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 single-RHS comparator")
     ap.add_argument("--no-serve", action="store_true", help="skip the small serving leg")
     ap.add_argument("--plan-file", default=None,
@@ -172,7 +174,13 @@ def serving_run(F, plans, keys, nreq, fracs, seed, max_batch=256, graphs=True, m
         st = latency_stats(done)
         rec = {"rate_frac": frac, "req_per_s": frac * sat, "p50_ms": st["p50_ms"],
                "p99_ms": st["p99_ms"], "rhs_n_per_s": throughput(done),
-               "batches": sch.batches_started, "multi_groups": sch.groups_started}
+               "batches": sch.batches_started, "multi_groups": sch.groups_started, "per_key": {}}
+        for k in keys:  # the tail by key: large keys' batches run longest
+            dk = [r for r in done if r.key == k]
+            if dk:
+                sk = latency_stats(dk)
+                rec["per_key"]["%dd_n%d_eps%g" % (k[0], k[1], k[3])] = {
+                    "requests": len(dk), "p50_ms": round(sk["p50_ms"], 3), "p99_ms": round(sk["p99_ms"], 3)}
         log("serving at %.2f x saturation: p50 %.2f ms, p99 %.2f ms, %.3e RHS*N/s" % (
             frac, st["p50_ms"], st["p99_ms"], rec["rhs_n_per_s"]))
         out["rates"].append(rec)
@@ -290,6 +298,34 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
     return out
 
 
+def calibration():
+    """Measured ceilings of the device (paper_2105_02995_amd/fio_calibrate, a child
+    process): streaming read rate and register-only FP32/FP64 matrix-core loop rates,
+    beside the published peaks the roofline fractions use."""
+    import re
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2105_02995_amd", "fio_calibrate")
+    out = {}
+    for mode in ("read", "mfma"):
+        try:
+            r = subprocess.run([exe, mode], capture_output=True, text=True, timeout=120)
+        except (OSError, subprocess.TimeoutExpired) as exc:
+            log("calibration %s: %s" % (mode, exc))
+            return None
+        if r.returncode != 0:
+            log("calibration %s failed: %s" % (mode, r.stderr.strip()))
+            return None
+        for line in r.stdout.splitlines():
+            m = re.match(r"read: .* (\d+) workgroups, ([0-9.]+) TB/s", line)
+            if m:
+                out["read_tbs"] = max(out.get("read_tbs", 0.0), float(m.group(2)))
+            m = re.match(r"mfma (f32|f64) 16x16x4: ([0-9.]+) TFLOP/s", line)
+            if m:
+                out["mfma_loop_%s_tflops" % m.group(1)] = float(m.group(2))
+    log("calibration: %s" % out)
+    return out
+
+
 def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
     """The FP64 oracle on a bounded sample of the workload (CPU, all cores).
 
@@ -376,7 +412,7 @@ def measure_serving(F, wl, plan, args):
         keys.append(key)
     plans = build_plans(F, keys, {key: plan})
     try:
-        return serving_run(F, plans, keys, 100, (0.8,), 2000, multi=not args.no_multi)
+        return serving_run(F, plans, keys, 400, (0.8,), 2000, multi=not args.no_multi)
     finally:
         for k, pl in plans.items():
             if pl is not plan:
@@ -569,6 +605,7 @@ def main():
     del X
     serving = None if args.no_serve else measure_serving(F, wl, plan, args)
 
+    calib = None if args.no_calibration else calibration()
     cpu, check = None, None
     if not args.no_cpu_baseline:
         cpu, check = oracle_leg(F, torch, plan, wl, stream, args.refine)
@@ -597,6 +634,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fp64_single_rhs": plain,
         "speedup_vs_plain": (value / plain["value"]) if plain else None,
+        "calibration": calib,
         "build_seconds": build_s,
         "plan": {k: stats[k] for k in ("bf_nnz", "hif_nnz", "root_size", "max_rank_bf",
                                        "max_rank_h", "device_bytes", "L")},

@@ -1,7 +1,10 @@
 // fio_calibrate: measurement aid for the roofline figures of the library.
 //   fio_calibrate copy   1 GiB device-to-device copy kernel (known bytes), used to
 //                        scale the FETCH_SIZE / WRITE_SIZE counters of rocprofv3;
-//   fio_calibrate mfma   sustained 16x16x4 FP32 and FP64 MFMA rates (registers only);
+//   fio_calibrate mfma   sustained 16x16x4 FP32 and FP64 MFMA rates (registers only;
+//                        16 and 8 independent accumulators per wave: the FP64 loop
+//                        is slower with 16, and below what the FP64 stage kernels
+//                        reach, so it bounds the FP64 rate from below only);
 //   fio_calibrate read   streaming read of 4 GiB (16-byte loads, eight in flight per
 //                        lane, one partial sum written per workgroup): the HBM read
 //                        rate a bandwidth-bound kernel can reach in practice.
@@ -116,14 +119,14 @@ int main(int argc, char **argv) {
         CK(hipMalloc(&o, 4096));
         CK(hipMalloc(&od, 8192));
         const int iters = 2000, blocks = 2048;
-        hipLaunchKernelGGL(calib_mfma32<8>, dim3(blocks), dim3(256), 0, 0, o, 10, 1.0f);
+        hipLaunchKernelGGL(calib_mfma32<16>, dim3(blocks), dim3(256), 0, 0, o, 10, 1.0f);
         CK(hipDeviceSynchronize());
         CK(hipEventRecord(e0));
-        hipLaunchKernelGGL(calib_mfma32<8>, dim3(blocks), dim3(256), 0, 0, o, iters, 1.0f);
+        hipLaunchKernelGGL(calib_mfma32<16>, dim3(blocks), dim3(256), 0, 0, o, iters, 1.0f);
         CK(hipEventRecord(e1));
         CK(hipEventSynchronize(e1));
         CK(hipEventElapsedTime(&ms, e0, e1));
-        printf("mfma f32 16x16x4: %.1f TFLOP/s\n", 2048.0 * 8 * iters * blocks * 4 / ms / 1e9);
+        printf("mfma f32 16x16x4: %.1f TFLOP/s\n", 2048.0 * 16 * iters * blocks * 4 / ms / 1e9);
         hipLaunchKernelGGL(calib_mfma64<8>, dim3(blocks), dim3(256), 0, 0, od, 10, 1.0);
         CK(hipDeviceSynchronize());
         CK(hipEventRecord(e0));

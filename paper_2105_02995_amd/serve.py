@@ -132,9 +132,17 @@ class Scheduler:
         self.inflight_bytes -= b.bytes
 
     def _form_batch(self, key):
+        """The key's queued requests in arrival order, up to the executor's column cap
+        for the key (``batch_cap``, a bound on one batch's device time, so that a large
+        key's batches do not hold the device, and the requests behind them, for long)
+        and ``max_batch_rhs``; the first request is always taken."""
         q = self.queues[key]
-        reqs, cols = [], 0
-        while q and cols + q[0].nrhs <= self.max_batch_rhs:
+        cap = self.max_batch_rhs
+        if hasattr(self.ex, "batch_cap"):
+            cap = min(cap, self.ex.batch_cap(key))
+        first = q.popleft()
+        reqs, cols = [first], first.nrhs
+        while q and cols + q[0].nrhs <= cap:
             r = q.popleft()
             reqs.append(r)
             cols += r.nrhs
@@ -249,8 +257,11 @@ class MockExecutor:
     """CPU stand-in: a batch takes ``cost(key, nrhs)`` seconds of modelled time and
     returns ``transform(key, u)``; clock and waiting are virtual."""
 
-    def __init__(self, cost, transform=None, factor_bytes=None, ws_bytes_per_rhs=None, fail_starts=()):
+    def __init__(self, cost, transform=None, factor_bytes=None, ws_bytes_per_rhs=None, fail_starts=(),
+                 batch_caps=None):
         self.cost = cost
+        if batch_caps is not None:  # per-key column caps, as GpuExecutor.batch_cap
+            self.batch_cap = lambda key: batch_caps.get(key, 1 << 30)
         self.transform = transform or (lambda key, u: u.copy())
         self.factor_bytes = factor_bytes or (lambda key: 0)
         self.ws_bytes_per_rhs = ws_bytes_per_rhs or (lambda key: 0)
@@ -317,7 +328,7 @@ class GpuExecutor:
     MULTI_MAX = 8  # instances per multi-instance solve (fio.h)
 
     def __init__(self, plans: dict, max_batch_rhs: int = 256, refine: int = 1, nstreams: int = 8,
-                 use_graphs: bool = False, use_multi: bool = False, trim: bool = False):
+                 use_graphs: bool = False, use_multi: bool = False, trim: bool = False, autotune: bool = True):
         import torch
         from . import fio as F
         self.torch, self.F = torch, F
@@ -331,6 +342,7 @@ class GpuExecutor:
             for p in plans.values():
                 F.fio_plan_trim(p, F.FIO_KEEP_REFINE_C64)
         self.stats = {k: F.fio_plan_stats(p) for k, p in plans.items()}
+        self.autotune = autotune      # tune each key's kernels at its bucket widths on load
         self.use_graphs = use_graphs
         self.graphs = {}              # (key, bucket) -> (graph, U, X)
         self.stage = {}               # key -> (pinned u, pinned x)
@@ -373,6 +385,20 @@ class GpuExecutor:
         X = torch.zeros_like(U)
         self._solve(key, U, X, top, torch.cuda.current_stream())  # sizes the plan's workspace
         torch.cuda.synchronize()
+        if self.autotune:
+            # kernel choices per batch width (the library looks them up by exact width):
+            # the widths batches run at, up to the key's cap, for the complex64 applies and
+            # the complex128 residual; before any graph captures the choices
+            F = self.F
+            cap = min(top, self.batch_cap(key))
+            st = torch.cuda.current_stream()
+            for b in self.BUCKETS:
+                if b > cap:
+                    break
+                F.fio_autotune(self.plans[key], F.FIO_C64, b, 2, st)
+                if self.refine > 0:
+                    F.fio_autotune(self.plans[key], F.FIO_C128, b, 2, st)
+            torch.cuda.synchronize()
         self.stage[key] = (torch.empty((top, N), dtype=torch.complex128).pin_memory(),
                            torch.empty((top, N), dtype=torch.complex128).pin_memory())
         if self.use_graphs:
@@ -447,6 +473,23 @@ class GpuExecutor:
     def _work(self, batch):
         """Estimated work of a batch: butterfly nonzeros times padded columns."""
         return float(self.stats[batch.key]["bf_nnz"]) * self._bucket(batch.nrhs)
+
+    BATCH_TARGET_MS = 24.0   # device time one batch may take, estimated
+    EST_TFLOPS = 110.0       # rate of the estimate (the batched applies run at 100-130)
+
+    def batch_cap(self, key):
+        """Columns per batch of this key: the largest bucket whose estimated solve
+        time stays within BATCH_TARGET_MS (a direct complex64 apply of Kd^* and Gd, and
+        per refinement step a complex128 Kd at half the rate and another complex64
+        apply: 8 flop per butterfly nonzero and column each, Gd neglected), at least
+        the smallest bucket.  Only the largest keys are capped (2D n = 256: 64 columns,
+        about 20 ms)."""
+        per_col = 8.0 * self.stats[key]["bf_nnz"] * (2 + 2 * self.refine) / (self.EST_TFLOPS * 1e12) * 1e3
+        cap = self.BUCKETS[0]
+        for b in self.BUCKETS:
+            if b <= self.max_batch_rhs and b * per_col <= self.BATCH_TARGET_MS:
+                cap = b
+        return cap
 
     def _groups(self, batches):
         """Index groups of batches of similar work (a small solve grouped with a large

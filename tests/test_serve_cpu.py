@@ -232,3 +232,29 @@ def test_executor_failure_fails_only_that_batch():
     for q in s.finished:
         np.testing.assert_array_equal(q.result, _transform(q.key, q.u))
     assert s.inflight_bytes == 0 and not s.running
+
+
+def test_per_key_batch_cap_bounds_large_keys_only():
+    """The executor's per-key column cap (a bound on one batch's device time): the
+    capped key's batches stay within it, a request wider than the cap still runs
+    (alone), the other key batches up to max_batch_rhs, and every request is served."""
+    sizes = {}
+    big, small = _key(0), _key(1)
+
+    class Ex(MockExecutor):
+        def start(self, batch, now):
+            sizes.setdefault(batch.key, []).append((batch.nrhs, len(batch.requests)))
+            return super().start(batch, now)
+
+    ex = Ex(cost=lambda key, nr: 0.02, transform=_transform, batch_caps={big: 8})
+    s = Scheduler(ex, hbm_budget=1 << 40, max_batch_rhs=64)
+    assert s.register(big) and s.register(small)
+    reqs = [ServeRequest(j, big if j % 2 == 0 else small, 0.0,
+                         gaussian_complex((4, 12 if j == 4 else 3), 500 + j)) for j in range(40)]
+    done = s.run(reqs)
+    assert len(done) == 40
+    for r in done:
+        np.testing.assert_array_equal(r.result, _transform(r.key, r.u))
+    assert all(n <= 8 or k == 1 for n, k in sizes[big])
+    assert any(n == 12 and k == 1 for n, k in sizes[big])
+    assert max(n for n, _ in sizes[small]) > 8
