@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC = {
     # 2D Example 3, n=256, 256 RHS (profiles/k_stage_mfma_f32_3m_2d_n256_traffic.md)
     "k_stage_mfma<float, 2, 2, 3M>": {
-        "bytes": 4.1725e9,
-        "kernels_sha256": "3c64deb3e47da4e0e4e6165a79a1ddd04d1449e140c839a3d59764e92429d1b1",
+        "bytes": 4.1730e9,
+        "kernels_sha256": "7adada25df8b60eb8dfd955bedda8c1e5b1e41a43606c27eaec59418979fb264",
         "bf_nnz": 1138753536,
     },
 }
@@ -51,8 +51,8 @@ TRAFFIC = {
 MFMA_COUNTERS = {
     "k_stage_mfma<float, 2, 2, 3M>": {
         "executed_flop": 3.4403e11,
-        "busy": 0.6285,
-        "kernels_sha256": "3c64deb3e47da4e0e4e6165a79a1ddd04d1449e140c839a3d59764e92429d1b1",
+        "busy": 0.6259,
+        "kernels_sha256": "7adada25df8b60eb8dfd955bedda8c1e5b1e41a43606c27eaec59418979fb264",
         "bf_nnz": 1138753536,
     },
 }
