@@ -516,7 +516,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the factored solve is measured on a single "
-              "MI355X (multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "MI355X (sharding over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         return serve_main(args)

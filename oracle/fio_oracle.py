@@ -38,7 +38,7 @@ class OracleProblem:
             a(x, xi) = sum_k exp(-(d(x, x_k)^2 + (xi/n - eta_k)^2) / sigma2),
             d the distance on the unit circle, amp = ((x_k, eta_k), ...).  The
             paper gives neither the centres nor their number; these defaults are
-            this build's choice.  a = 1 for the other phases.
+            a choice made here.  a = 1 for the other phases.
     """
     d: int
     n: int

@@ -1,7 +1,7 @@
 """Address- and undefined-behaviour-sanitizer build of the host construction code
 (butterfly factorization, peeling, skeletonization, the plan file format), run on
 small problems of every phase: no memory error, leak or undefined behaviour may be
-reported.  GPU code is not part of this build (host sources with g++ only)."""
+reported.  GPU code is not part of this sanitizer build (host sources with g++ only)."""
 import os
 import shutil
 import subprocess
