@@ -110,6 +110,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="2d_n256", choices=sorted(WORKLOADS))
     ap.add_argument("--refine", type=int, default=1, help="FP64 refinement steps per solve")
+    ap.add_argument("--mode", choices=("refine", "pcg"), default="refine",
+                    help="refine: complex64 applies + FP64 refinement; pcg: CG on Kd^*Kd preconditioned "
+                         "by Gd (complex128 applies) to a relative residual of 1e-8, the 2D n=64 configuration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-calibration", action="store_true",
                     help="skip the measured device ceilings (streaming read, matrix-core loop)")
@@ -326,7 +329,7 @@ def calibration():
     return out
 
 
-def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
+def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4, mode="refine"):
     """The FP64 oracle on a bounded sample of the workload (CPU, all cores).
 
     1. Known truth: fhat for `ncol` columns (seeded Gaussian) and u = K fhat by the
@@ -342,6 +345,7 @@ def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
     """
     import oracle as O
     N, B = wl.N, wl.nrhs
+    ncol = min(ncol, B)
     p = O.OracleProblem(wl.d, wl.n, wl.phase, wl.c_div)
     fh = gaussian_complex((N, ncol), wl.seed + 100)
     log("oracle: direct summation u = K fhat, N=%d, %d columns ..." % (N, ncol))
@@ -354,8 +358,12 @@ def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
     u[:, cols] = u_true
     U = torch.from_numpy(np.ascontiguousarray(u.T)).cuda()
     X = torch.zeros_like(U)
-    F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0, maxit=refine, stream=stream,
-                want_info=False)
+    if mode == "pcg":
+        F.fio_solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, U, X, B, N, tol=1e-8, maxit=200, precondition=1,
+                    stream=stream)
+    else:
+        F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0, maxit=refine, stream=stream,
+                    want_info=False)
     torch.cuda.synchronize()
     x = X.cpu().numpy().T
     finite = bool(np.isfinite(x).all())
@@ -363,7 +371,7 @@ def oracle_leg(F, torch, plan, wl, stream, refine, ncol=4):
     # the oracle's CG count and a measured dense solve at the small size: K formation,
     # LU and the solves, median of 3 with the BLAS on all its threads, and once with
     # one thread
-    small_n = 4096 if wl.d == 1 else 64
+    small_n = min(wl.n, 4096 if wl.d == 1 else 64)
     ps = O.OracleProblem(wl.d, small_n, wl.phase, wl.c_div)
     Ns = ps.N
     us = gaussian_complex((Ns, B), wl.seed + 102)
@@ -419,16 +427,22 @@ def measure_serving(F, wl, plan, args):
                 pl.close()
 
 
-def roofline_of(F, torch, plan, stats, B, refine):
+def roofline_of(F, torch, plan, stats, B, refine, mode="refine"):
     """Dominant butterfly kernel instance of the step and its roofline figures.
     The complex64 adjoint chain runs twice per step, the complex128 forward chain
     once per refinement step.  The bound is the roof the instance reaches first:
     HBM if its algorithmic bytes take longer at 8 TB/s than its flops at the
     matrix-core peak of its precision."""
-    l64 = chain_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B)
-    l128 = chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B)
+    if mode == "pcg":  # every iteration applies Kd and Kd^* in complex128
+        legs = ((chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_KH, B), 1, PEAK_TFLOPS["c128"]),
+                (chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B), 1, PEAK_TFLOPS["c128"]))
+    else:
+        legs = ((chain_timing(F, plan, torch, F.FIO_C64, F.FIO_OP_KH, B), 2, PEAK_TFLOPS["c64"]),
+                (chain_timing(F, plan, torch, F.FIO_C128, F.FIO_OP_K, B), refine, PEAK_TFLOPS["c128"]))
+    l64, l128 = legs[0][0], legs[1][0]
+    n64, n128 = ("c128_KH", "c128_K") if mode == "pcg" else ("c64_KH", "c128_K")
     inst = {}
-    for launches, weight, pk in ((l64, 2, PEAK_TFLOPS["c64"]), (l128, refine, PEAK_TFLOPS["c128"])):
+    for launches, weight, pk in legs:
         for ln in launches:
             e = inst.setdefault(ln["name"], {"l": [], "w": weight, "pk": pk})
             e["l"].append(ln)
@@ -456,22 +470,22 @@ def roofline_of(F, torch, plan, stats, B, refine):
             "intensity_flop_per_byte": round(float(fl.sum() / by.sum()), 2),
             "other_roof": {"mfma_tflops": round(tf, 3), "mfma_frac": round(tf / pk, 4),
                            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)},
-            "chain_ms": {"c64_KH": round(sum(x["ms"] for x in l64), 4),
-                         "c128_K": round(sum(x["ms"] for x in l128), 4)},
-            "chain_tflops": {"c64_KH": round(sum(x["flops"] for x in l64) / (sum(x["ms"] for x in l64) * 1e9), 2),
-                             "c128_K": round(sum(x["flops"] for x in l128) / (sum(x["ms"] for x in l128) * 1e9), 2)},
-            "chain_bytes": {"c64_KH": {"algorithmic": sum(x["bytes"] for x in l64),
-                                       "launch_io": sum(x["launch_io_bytes"] for x in l64)},
-                            "c128_K": {"algorithmic": sum(x["bytes"] for x in l128),
-                                       "launch_io": sum(x["launch_io_bytes"] for x in l128)}},
+            "chain_ms": {n64: round(sum(x["ms"] for x in l64), 4),
+                         n128: round(sum(x["ms"] for x in l128), 4)},
+            "chain_tflops": {n64: round(sum(x["flops"] for x in l64) / (sum(x["ms"] for x in l64) * 1e9), 2),
+                             n128: round(sum(x["flops"] for x in l128) / (sum(x["ms"] for x in l128) * 1e9), 2)},
+            "chain_bytes": {n64: {"algorithmic": sum(x["bytes"] for x in l64),
+                                  "launch_io": sum(x["launch_io_bytes"] for x in l64)},
+                            n128: {"algorithmic": sum(x["bytes"] for x in l128),
+                                   "launch_io": sum(x["launch_io_bytes"] for x in l128)}},
             "instances": {n: {"launches": len(v["l"]), "ms_per_chain": round(sum(x["ms"] for x in v["l"]), 4)}
                           for n, v in inst.items()}}
     log("roofline: %s avg %.4f ms/launch over %d launches: %.2f TFLOP/s (%.1f%% of %.1f), "
         "%.0f GB/s (%.1f%% of HBM), bound %s" % (best, tms.mean(), len(e["l"]), tf, 100 * tf / pk, pk,
                                                  gbs, 100 * gbs / PEAK_HBM_GBS, roof["bound"]))
-    log("chains: c64 KH %.4f ms (%.1f TFLOP/s), c128 K %.4f ms (%.1f TFLOP/s)" % (
-        roof["chain_ms"]["c64_KH"], roof["chain_tflops"]["c64_KH"], roof["chain_ms"]["c128_K"],
-        roof["chain_tflops"]["c128_K"]))
+    log("chains: %s %.4f ms (%.1f TFLOP/s), %s %.4f ms (%.1f TFLOP/s)" % (
+        n64, roof["chain_ms"][n64], roof["chain_tflops"][n64], n128, roof["chain_ms"][n128],
+        roof["chain_tflops"][n128]))
     return roof
 
 
@@ -483,7 +497,7 @@ def plain_fp64(F, torch, plan, U, N, stream, ncols=16, tune=True):
         t0 = time.perf_counter()
         F.fio_autotune(plan, F.FIO_C128, 1, 3, stream)
         log("autotuned the single-RHS FP64 path in %.1f s" % (time.perf_counter() - t0))
-    Uc = [U[j:j + 1].contiguous() for j in range(ncols)]
+    Uc = [U[j % U.shape[0]:j % U.shape[0] + 1].contiguous() for j in range(ncols)]  # workloads of < ncols RHS cycle
     Xc = [torch.zeros_like(Uc[0]) for _ in range(ncols)]
     for j in range(2):
         F.fio_solve(plan, F.FIO_SOLVE_DIRECT, F.FIO_C128, Uc[j], Xc[j], 1, N, stream=stream, want_info=False)
@@ -559,9 +573,15 @@ def main():
         F.fio_autotune(plan, F.FIO_C128, B, 3, stream)
         log("autotuned stage kernels for %d RHS in %.1f s" % (B, time.perf_counter() - t0))
 
+    def solve(Uin, Xout):
+        if args.mode == "pcg":
+            return F.fio_solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, Uin, Xout, B, N, tol=1e-8, maxit=200,
+                               precondition=1, stream=stream)
+        return F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, Uin, Xout, B, N, tol=0.0, maxit=args.refine,
+                           stream=stream, want_info=False)
+
     def step():
-        F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0, maxit=args.refine,
-                    stream=stream, want_info=False)
+        solve(U, X)
 
     for _ in range(args.warmup):
         step()
@@ -586,6 +606,23 @@ def main():
     log("timed %d steps: %.3f ms/step, %.3e RHS*N/s" % (args.steps, ms, value))
     its, corr = F.fio_solve(plan, F.FIO_SOLVE_REFINE, F.FIO_C64, U, X, B, N, tol=0.0,
                             maxit=args.refine, stream=stream)
+    pcg = None
+    if args.mode == "pcg":
+        # iterations with Gd, and the same solve with Kd^* alone (no preconditioner)
+        its_g, res_g = F.fio_solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, U, X, B, N, tol=1e-8, maxit=200,
+                                   precondition=1, stream=stream)
+        X0 = torch.zeros_like(U)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its_0, res_0 = F.fio_solve(plan, F.FIO_SOLVE_PCG, F.FIO_C128, U, X0, B, N, tol=1e-8, maxit=200,
+                                   precondition=0, stream=stream)
+        torch.cuda.synchronize()
+        t_0 = time.perf_counter() - t1
+        pcg = {"tol": 1e-8, "iters_with_gd": its_g, "rel_resid_with_gd": res_g, "iters_kd_only": its_0,
+               "rel_resid_kd_only": res_0, "ms_kd_only": 1000 * t_0}
+        log("pcg: %d iterations with Gd (rel resid %.2e), %d with Kd^* alone (%.1f ms)"
+            % (its_g, res_g, its_0, 1000 * t_0))
+        del X0
 
     # optional spatial output f = n^d F* fhat of the batch (not part of the step)
     Fs = torch.empty_like(X)
@@ -600,7 +637,7 @@ def main():
     del Fs
     log("spatial output (inverse DFT of the batch): %.4f ms" % spatial_ms)
 
-    roof = roofline_of(F, torch, plan, stats, B, args.refine)
+    roof = roofline_of(F, torch, plan, stats, B, args.refine, args.mode)
     plain = None if args.no_plain else plain_fp64(F, torch, plan, U, N, stream, tune=not args.plain_untuned)
     del X
     serving = None if args.no_serve else measure_serving(F, wl, plan, args)
@@ -608,7 +645,7 @@ def main():
     calib = None if args.no_calibration else calibration()
     cpu, check = None, None
     if not args.no_cpu_baseline:
-        cpu, check = oracle_leg(F, torch, plan, wl, stream, args.refine)
+        cpu, check = oracle_leg(F, torch, plan, wl, stream, args.refine, mode=args.mode)
         log("oracle check: max rel err %.3e over columns %s (bound %.1e); cpu baseline %.3e RHS*N/s on %d cores"
             % (check["rel_err_vs_oracle"], check["columns"], check["bound"], cpu["value"], cpu["cores"]))
 
@@ -617,18 +654,21 @@ def main():
         "metric": "RHS*N/s of factored FIO inverse solve at rel err <= 10 eps; p50/p99 latency",
         "value": value if ok else None, "unit": "RHS*N/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64+f64", "data": "synthetic",
-        "config": {"workload": "%s: %s, N=%d, %d RHS, eps=%g, complex64 applies + %d FP64 "
-                               "refinement step(s)"
+        "vs_baseline": None, "dtype": "c128" if args.mode == "pcg" else "c64+f64", "data": "synthetic",
+        "config": {"workload": "%s: %s, N=%d, %d RHS, eps=%g, %s"
                                % (wl.name, "1D FIO Example 1 phase c(x)=(2+sin 2pi x)/16" if wl.d == 1 else
                                   "2D FIO Example 3 (generalized Radon phase), n=%d" % wl.n,
-                                  N, B, wl.eps, args.refine),
-                   "N": N, "nrhs": B, "eps": wl.eps},
+                                  N, B, wl.eps,
+                                  "CG on Kd^*Kd preconditioned by Gd to 1e-8, complex128 applies"
+                                  if args.mode == "pcg" else
+                                  "complex64 applies + %d FP64 refinement step(s)" % args.refine),
+                   "N": N, "nrhs": B, "eps": wl.eps, "mode": args.mode},
         "rel_err_vs_oracle": check,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "per-step (%d-RHS batch) latency, HIP events" % B},
         "serving": serving,
         "last_correction_rel": corr,
+        "pcg": pcg,
         "spatial_output_ms": spatial_ms,
         "roofline": roof,
         "cpu_baseline": cpu,
