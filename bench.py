@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC = {
     # 2D Example 3, n=256, 256 RHS (profiles/k_stage_mfma_f32_3m_2d_n256_traffic.md)
     "k_stage_mfma<float, 2, 2, 3M>": {
-        "bytes": 3.9389e9,
-        "kernels_sha256": "ae7aa8f3d43213b161076a5bb45921a1a35be16ef1e8761b9e92a545e1dc324f",
+        "bytes": 4.1730e9,
+        "kernels_sha256": "7adada25df8b60eb8dfd955bedda8c1e5b1e41a43606c27eaec59418979fb264",
         "bf_nnz": 1138753536,
     },
 }
@@ -50,9 +50,9 @@ TRAFFIC = {
 # SQ_VALU_MFMA_BUSY_CYCLES; summary under profiles/), under the same validity rule.
 MFMA_COUNTERS = {
     "k_stage_mfma<float, 2, 2, 3M>": {
-        "executed_flop": 3.0118e11,
-        "busy": 0.6234,
-        "kernels_sha256": "ae7aa8f3d43213b161076a5bb45921a1a35be16ef1e8761b9e92a545e1dc324f",
+        "executed_flop": 3.4403e11,
+        "busy": 0.6259,
+        "kernels_sha256": "7adada25df8b60eb8dfd955bedda8c1e5b1e41a43606c27eaec59418979fb264",
         "bf_nnz": 1138753536,
     },
 }
@@ -63,7 +63,7 @@ MFMA_COUNTERS = {
 PLAIN_TRAFFIC = {
     "plain_fp64": {
         "bytes": 2.1873e10,
-        "kernels_sha256": "ae7aa8f3d43213b161076a5bb45921a1a35be16ef1e8761b9e92a545e1dc324f",
+        "kernels_sha256": "7adada25df8b60eb8dfd955bedda8c1e5b1e41a43606c27eaec59418979fb264",
         "bf_nnz": 1138753536,
     },
 }
