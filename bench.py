@@ -291,10 +291,9 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
             name = "k_stage_nb<%s2>" % r
         elif v in (12, 13, 14):
             name = "k_stage_mfma<%s, %d, %d, 3M>" % ((r,) + {12: (2, 4), 13: (4, 2), 14: (2, 2)}[v])
-        elif v in (10, 11, 15, 16):
+        elif v in (10, 11):
             ro = io(ks[0])[0]["r_out"] if op == F.FIO_OP_K else io(ks[0])[0]["r_in"]
-            name = "k_stage_lds<%s, %d, %d%s>" % (r, 1 if ro <= 64 else (2 if ro <= 128 else 3),
-                                                  4 if v in (10, 15) else 2, ", 3M" if v >= 15 else "")
+            name = "k_stage_lds<%s, %d, %d>" % (r, 1 if ro <= 64 else (2 if ro <= 128 else 3), 4 if v == 10 else 2)
         else:
             name = "k_stage_mfma<%s, %d, %d>" % ((r,) + VNAME[v])
         out.append({"name": name, "ms": float(tot[j]), "flops": flops, "bytes": float(byts),

@@ -705,7 +705,7 @@ template <class R, int NT> struct LdsTile {
     static constexpr int LPT = LDS_KC * CW / 256;  // staged entries per thread per chunk
 };
 
-template <class R, int MT, int NT, bool M3 = false>
+template <class R, int MT, int NT>
 __global__ void __launch_bounds__(256) k_stage_lds(int64_t n_out, int r_out, int r_in, int fan,
                                                    const int32_t *__restrict__ idx,
                                                    const typename MF<R>::C *__restrict__ A,
@@ -754,7 +754,7 @@ __global__ void __launch_bounds__(256) k_stage_lds(int64_t n_out, int r_out, int
         const C *acol_ = kv_ ? Ao + (int64_t)k_ * r_out : reinterpret_cast<const C *>(g_zero_rows); \
         _Pragma("unroll") for (int mt = 0; mt < MT; ++mt) ar[slot][mt] = acol_[kv_ ? rowc[mt] : mt * 16 + li]; \
     }
-    typename std::conditional<M3, Acc3<R, MT, NT>, Acc<R, MT, NT>>::type acc;
+    Acc<R, MT, NT> acc;
     acc.zero();
     LDS_GLOAD(0)
     LDS_STORE(0)
@@ -801,13 +801,13 @@ __global__ void __launch_bounds__(256) k_stage_lds(int64_t n_out, int r_out, int
             }
 }
 
-template <class R, int MT, int NT, bool M3>
+template <class R, int MT, int NT>
 static void lds_go(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;
     using T = LdsTile<R, NT>;
     const int nch = (nrhs + T::CW - 1) / T::CW;
     const size_t lds = (size_t)2 * LDS_KC * T::LDX * sizeof(C);
-    hipLaunchKernelGGL((k_stage_lds<R, MT, NT, M3>), dim3(xcd_grid(s.n_out, nch)), dim3(256), lds, st, s.n_out, s.r_out,
+    hipLaunchKernelGGL((k_stage_lds<R, MT, NT>), dim3(xcd_grid(s.n_out, nch)), dim3(256), lds, st, s.n_out, s.r_out,
                        s.r_in, s.fan, s.idx, (const C *)s.A, (const C *)x, (C *)y, nrhs, nch);
 }
 
@@ -815,11 +815,11 @@ static void lds_go(const StageDev &s, const void *x, void *y, int nrhs, hipStrea
 // up to three 16-row tiles), at most four input blocks.
 bool stage_lds_fits(const StageDev &s) { return s.r_out <= 192 && s.fan <= 4 && s.r_in >= 1 && s.r_out >= 1; }
 
-template <class R, int NT, bool M3 = false>
+template <class R, int NT>
 static void launch_lds(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
-    if (s.r_out <= 64) lds_go<R, 1, NT, M3>(s, x, y, nrhs, st);
-    else if (s.r_out <= 128) lds_go<R, 2, NT, M3>(s, x, y, nrhs, st);
-    else lds_go<R, 3, NT, M3>(s, x, y, nrhs, st);
+    if (s.r_out <= 64) lds_go<R, 1, NT>(s, x, y, nrhs, st);
+    else if (s.r_out <= 128) lds_go<R, 2, NT>(s, x, y, nrhs, st);
+    else lds_go<R, 3, NT>(s, x, y, nrhs, st);
 }
 
 // Right-hand-side counts from which the matrix-core path is used by default.
@@ -864,17 +864,11 @@ void launch_stage(const StageDev &s, bool dbl, const void *x, void *y, int nrhs,
         check_launch("stage (small batch)");
         return;
     }
-    if (v == STAGE_LDS4 || v == STAGE_LDS2 || v == STAGE_LDS4_3M || v == STAGE_LDS2_3M) {
+    if (v == STAGE_LDS4 || v == STAGE_LDS2) {
         if (!stage_lds_fits(s)) v = 0;
         else {
-            switch (v) {
-                case STAGE_LDS4: if (dbl) launch_lds<double, 4>(s, x, y, nrhs, st); else launch_lds<float, 4>(s, x, y, nrhs, st); break;
-                case STAGE_LDS2: if (dbl) launch_lds<double, 2>(s, x, y, nrhs, st); else launch_lds<float, 2>(s, x, y, nrhs, st); break;
-                // three products in FP64 need more registers than a lane has (spills): the
-                // complex128 path keeps four products
-                case STAGE_LDS4_3M: if (dbl) launch_lds<double, 4>(s, x, y, nrhs, st); else launch_lds<float, 4, true>(s, x, y, nrhs, st); break;
-                default: if (dbl) launch_lds<double, 2>(s, x, y, nrhs, st); else launch_lds<float, 2, true>(s, x, y, nrhs, st); break;
-            }
+            if (dbl) { if (v == STAGE_LDS4) launch_lds<double, 4>(s, x, y, nrhs, st); else launch_lds<double, 2>(s, x, y, nrhs, st); }
+            else { if (v == STAGE_LDS4) launch_lds<float, 4>(s, x, y, nrhs, st); else launch_lds<float, 2>(s, x, y, nrhs, st); }
             check_launch("stage (LDS-staged input)");
             return;
         }

@@ -24,12 +24,10 @@ struct StageDev {
 // k-slices per workgroup, for fewer than 16 columns), 10 and 11 the matrix-core
 // kernel with the input staged in LDS and shared by a workgroup's four waves (one
 // block of up to 192 rows per workgroup, 64 or 32 columns), 12..14 the register
-// tilings MT2 NT4, MT4 NT2, MT2 NT2 with three real products per complex k-step,
-// 15 and 16 the LDS-staged kernel of 10 and 11 with three real products (complex64;
-// complex128 runs 10 and 11).
-constexpr int STAGE_VARIANTS = 17;
+// tilings MT2 NT4, MT4 NT2, MT2 NT2 with three real products per complex k-step.
+constexpr int STAGE_VARIANTS = 15;
 constexpr int STAGE_SMALL_BATCH = 7;
-constexpr int STAGE_LDS4 = 10, STAGE_LDS2 = 11, STAGE_LDS4_3M = 15, STAGE_LDS2_3M = 16;
+constexpr int STAGE_LDS4 = 10, STAGE_LDS2 = 11;
 // Whether the multi-instance stage kernel has this variant (the four-product
 // register tilings only).
 inline bool stage_multi_variant_ok(int v) { return (v >= 1 && v <= 6) || v == 8 || v == 9; }

@@ -23,7 +23,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 
 from . import gpu_util as G  # noqa: E402
 
-VARIANTS = range(17)
+VARIANTS = range(15)
 _cache = {}
 
 
@@ -69,12 +69,12 @@ def test_every_stage_variant_matches_the_host_product(tmp_path_factory, d, n, ep
                     worst = max(worst, e)
                     assert np.isfinite(y).all(), (op, k, B, v)
                     assert e < tol, (op, k, B, v, e)
-    log("d=%d n=%d dtype %d: worst stage-variant error %.2e over variants 0-16" % (d, n, dtype, worst))
+    log("d=%d n=%d dtype %d: worst stage-variant error %.2e over variants 0-14" % (d, n, dtype, worst))
 
 
 def test_stage_variant_out_of_range_is_an_argument_error(tmp_path_factory):
     plan, f = setup(1, 4096, 1e-6, tmp_path_factory)
     X = torch.zeros(64, dtype=torch.complex64, device="cuda")
     with pytest.raises(F.FioError) as e:
-        F.fio_stage_apply_variant(plan, F.FIO_OP_K, 0, F.FIO_C64, 17, X, X, 1, G.stream())
+        F.fio_stage_apply_variant(plan, F.FIO_OP_K, 0, F.FIO_C64, 15, X, X, 1, G.stream())
     assert e.value.status == 1
