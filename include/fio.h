@@ -443,7 +443,9 @@ fio_status fio_autotune(fio_plan plan, fio_dtype dtype, int64_t nrhs, int reps, 
  * 6 MT2xNT1, 8 MT4xNT4, 9 MT4xNT2), 7 the small-batch kernel (fewer than 16
  * columns: 64 rows per workgroup, the k range split over its four waves), 10/11
  * matrix cores with the gathered input staged in LDS and shared by a workgroup's
- * four waves (one output block of up to 192 rows per workgroup, 64/32 columns). */
+ * four waves (one output block of up to 192 rows per workgroup, 64/32 columns),
+ * 12/13/14 the tilings MT2xNT4, MT4xNT2, MT2xNT2 with three real products per
+ * complex multiply-add instead of four. */
 fio_status fio_tune_query(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int64_t nrhs,
                           int *variant);
 
