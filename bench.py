@@ -258,7 +258,9 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
     for rep in range(reps):
         for j, (first, count, v) in enumerate(sched):
             ev[j][0].record(stream)
-            if count == 2:
+            if count == 3:
+                F.fio_stage_triple_apply(plan, op, first, dtype, a, b, nrhs, stream)
+            elif count == 2:
                 F.fio_stage_pair_apply(plan, op, first, dtype, a, b, nrhs, stream)
             else:
                 F.fio_stage_apply(plan, op, first, dtype, a, b, nrhs, stream)
@@ -279,7 +281,11 @@ def chain_timing(F, plan, torch, dtype, op, nrhs, reps=5):
             byts += N * nrhs * csize
         moved = sum(io(k)[0]["nnz"] * csize + 4 * io(k)[0]["n_out"] * io(k)[0]["fan"] for k in ks)
         moved += (io(ks[0])[1] + io(ks[-1])[2]) * nrhs * csize
-        if count == 2 and v == PAIR_STACKED:
+        if count == 3:
+            name = "k_stage3s_mfma<%s, %d, %d>" % (r, 2 if dtype == F.FIO_C64 else 1,
+                                                   3 if max(io(k)[0]["r_out"] if op == F.FIO_OP_K else io(k)[0]["r_in"]
+                                                            for k in ks) <= 24 else 4)
+        elif count == 2 and v == PAIR_STACKED:
             rmax = max(io(k)[0]["r_out"] if op == F.FIO_OP_K else io(k)[0]["r_in"] for k in ks)
             name = "k_stage2s_mfma<%s, %d, %d>" % (r, 2 if dtype == F.FIO_C64 else 1, 3 if rmax <= 24 else 4)
         elif count == 2:

@@ -394,6 +394,19 @@ fio_status fio_stage_pair_apply(fio_plan plan, fio_op op, int stage, fio_dtype d
 fio_status fio_stage_pair_apply_variant(fio_plan plan, fio_op op, int stage, fio_dtype dtype, int variant,
                                         const void *x, void *y, int64_t nrhs, void *hip_stream);
 
+/* Apply the factors `stage`, `stage + 1` and `stage + 2` of Kd (FIO_OP_K) or Kd^*
+ * (FIO_OP_KH) in one fused launch: three consecutive butterfly factors of eq_BFF_fact
+ * (1D) couple closed groups of four blocks per factor; one workgroup computes a group's
+ * two intermediate coefficient sets in LDS, the later two factors two sibling blocks
+ * (equal input lists) at a time as one matrix-core operand.  x is stage `stage`'s input and y stage
+ * `stage + 2`'s output, in the layout of fio_stage_apply.  For tests and
+ * measurement; the autotuner uses it where it is faster.  Asynchronous.  Errors:
+ * FIO_ERR_ARG (stage or op out of range), FIO_ERR_UNSUPPORTED (ranks above 32, a fan
+ * of the later factors above 2, or groups that are not four blocks per factor with
+ * two sibling pairs in the later two). */
+fio_status fio_stage_triple_apply(fio_plan plan, fio_op op, int stage, fio_dtype dtype, const void *x, void *y,
+                                  int64_t nrhs, void *hip_stream);
+
 /* Column interpolative decomposition of one dense matrix on a device: the routine
  * the 2D skeletonization runs for its large stacked bases (section 4, the ID of
  * eq. ID_2d_bases), exposed for tests and measurement.  A(:, redund) ~= A(:, skel) T
@@ -413,9 +426,10 @@ fio_status fio_column_id(int device, int64_t m, int64_t n, const void *A, int64_
                          int *perm, void *T, int64_t t_cap);
 
 /* The launches that an apply of Kd (FIO_OP_K) or Kd^* (FIO_OP_KH) makes at this
- * dtype and nrhs: launch j runs n_stages[j] (1 or 2) consecutive factors from
+ * dtype and nrhs: launch j runs n_stages[j] (1, 2 or 3) consecutive factors from
  * first_stage[j] with kernel variant variant[j] (single factor: the codes of
- * fio_tune_query; fused pair: 1, 2, 3 for 16, 32, 64 columns per wave).
+ * fio_tune_query; fused pair: 1, 2, 3 for 16, 32, 64 columns per wave, 4 the stacked
+ * form; three fused factors: 1).
  * *n_launch is always set; with cap = 0 only the count is returned, otherwise
  * the arrays (cap entries each, host memory) are filled.  Errors: FIO_ERR_ARG
  * (cap too small, null pointers). */

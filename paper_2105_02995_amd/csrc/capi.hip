@@ -142,6 +142,8 @@ struct DPair {
     DBuf tab, tab_s;
     int64_t n_wg = 0, n_wg_s = 0;
     bool ok = false;
+    DBuf tab3;           // stages (s, s+1, s+2) fused (StageTripleDev), if they form stacked groups
+    int64_t n_wg3 = 0;
 };
 
 // Table of the stacked variant: one closed group per workgroup, whose stage-a blocks
@@ -252,6 +254,87 @@ bool build_pair_table(const Stage &a, const Stage &b, std::vector<int32_t> &tab)
     return true;
 }
 
+// Table of three consecutive stages a, b, c fused (StageTripleDev): the closed groups
+// of the three stages (stage-c outputs read only stage-b outputs of the group, which
+// read only its stage-a outputs), each of exactly four blocks per stage, whose
+// stage-b and stage-c blocks split into two sibling pairs (equal input lists).
+// Returns false if some group does not.
+bool build_triple_table(const Stage &a, const Stage &b, const Stage &c, std::vector<int32_t> &out) {
+    out.clear();
+    if (b.n_in != a.n_out || c.n_in != b.n_out || b.r_in != a.r_out || c.r_in != b.r_out) return false;
+    if (std::max({a.r_out, b.r_out, c.r_out}) > 32 || a.r_out < 1 || b.r_out < 1 || c.r_out < 1 || a.r_in < 1)
+        return false;
+    if (a.fan < 1 || a.fan > 4 || b.fan < 1 || b.fan > 2 || c.fan < 1 || c.fan > 2) return false;
+    const int64_t na = a.n_out, nb = b.n_out, nc = c.n_out;
+    std::vector<int64_t> par(na + nb + nc);
+    for (size_t i = 0; i < par.size(); ++i) par[i] = (int64_t)i;
+    auto find = [&](int64_t x) {
+        while (par[x] != x) { par[x] = par[par[x]]; x = par[x]; }
+        return x;
+    };
+    auto unite = [&](int64_t x, int64_t y) { x = find(x); y = find(y); if (x != y) par[x] = y; };
+    for (int64_t m = 0; m < nb; ++m)
+        for (int q = 0; q < b.fan; ++q) unite(na + m, b.in_idx[m * b.fan + q]);
+    for (int64_t o = 0; o < nc; ++o)
+        for (int q = 0; q < c.fan; ++q) unite(na + nb + o, na + c.in_idx[o * c.fan + q]);
+    struct Group {
+        std::vector<int32_t> a, b, c;
+    };
+    std::map<int64_t, Group> groups;
+    for (int64_t i = 0; i < na; ++i) groups[find(i)].a.push_back((int32_t)i);
+    for (int64_t i = 0; i < nb; ++i) groups[find(na + i)].b.push_back((int32_t)i);
+    for (int64_t i = 0; i < nc; ++i) groups[find(na + nb + i)].c.push_back((int32_t)i);
+    auto same_in = [](const Stage &st, int32_t x, int32_t y) {
+        for (int q = 0; q < st.fan; ++q)
+            if (st.in_idx[(int64_t)x * st.fan + q] != st.in_idx[(int64_t)y * st.fan + q]) return false;
+        return true;
+    };
+    // four blocks into two sibling pairs, adjacent in the returned order
+    auto pairs = [&](const Stage &st, const std::vector<int32_t> &v, std::vector<int32_t> &o) {
+        o.clear();
+        for (size_t j = 1; j < 4; ++j) {
+            if (!same_in(st, v[0], v[j])) continue;
+            const size_t u = j == 1 ? 2 : 1, w = j == 3 ? 2 : 3;
+            if (!same_in(st, v[u], v[w])) continue;
+            o = {v[0], v[j], v[u], v[w]};
+            return true;
+        }
+        return false;
+    };
+    // slots of each pair's inputs (positions in the previous stage's list)
+    auto slots = [](const Stage &st, const std::vector<int32_t> &blocks, const std::vector<int32_t> &prev,
+                    int32_t *w) {
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) {
+                w[2 * p + q] = -1;
+                if (q >= st.fan) continue;
+                const int32_t m = st.in_idx[(int64_t)blocks[2 * p] * st.fan + q];
+                const auto it = std::find(prev.begin(), prev.end(), m);
+                if (it == prev.end()) return false;
+                w[2 * p + q] = (int32_t)(it - prev.begin());
+            }
+        return true;
+    };
+    std::vector<std::pair<int32_t, std::vector<int32_t>>> rows;
+    for (auto &kv : groups) {
+        const Group &gr = kv.second;
+        if (gr.a.size() != 4 || gr.b.size() != 4 || gr.c.size() != 4) return false;
+        std::vector<int32_t> pa, pb, pc;
+        pa = gr.a;  // the stage-a blocks run one by one
+        if (!pairs(b, gr.b, pb) || !pairs(c, gr.c, pc)) return false;
+        std::vector<int32_t> w(STAGE_TRIPLE_TAB, -1);
+        std::copy(pa.begin(), pa.end(), w.begin());
+        std::copy(pb.begin(), pb.end(), w.begin() + 4);
+        if (!slots(b, pb, pa, w.data() + 8)) return false;
+        std::copy(pc.begin(), pc.end(), w.begin() + 12);
+        if (!slots(c, pc, pb, w.data() + 16)) return false;
+        rows.push_back({pa[0], std::move(w)});
+    }
+    std::sort(rows.begin(), rows.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+    for (auto &r : rows) out.insert(out.end(), r.second.begin(), r.second.end());
+    return true;
+}
+
 // b = a rounded to complex FP32 (round to nearest, as the host conversion).
 __global__ __launch_bounds__(256) void k_to_c64(const double2 *a, float2 *b, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -322,10 +405,11 @@ struct fio_plan_s {
     // Autotuned choices keyed by (dtype, nrhs): stage kernel variant per stage of the
     // forward and adjoint chains, which consecutive stages run fused, and per
     // skeletonization step 0 = LDS kernel, 1 = matrix-core GEMMs.
-    // fwd_pair/adj_pair[s] > 0: stages s and s+1 run fused with that variant; hif[k]:
-    // the choice of hif_step.
+    // fwd_pair/adj_pair[s] > 0: stages s and s+1 run fused with that variant;
+    // fwd_triple/adj_triple[s] > 0: stages s, s+1 and s+2 run fused; hif[k]: the
+    // choice of hif_step.
     struct Tune {
-        std::vector<int> fwd, adj, hif, fwd_pair, adj_pair;
+        std::vector<int> fwd, adj, hif, fwd_pair, adj_pair, fwd_triple, adj_triple;
         int root = -1;  // stage variant of the FP64 top-level block
     };
     std::map<std::pair<int, int>, Tune> tune;
@@ -341,8 +425,8 @@ void count_bytes(fio_plan p) {
     int64_t b = 0;
     for (auto &s : p->dfwd) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
     for (auto &s : p->dadj) b += s.idx.bytes + s.A64.bytes + s.A128.bytes;
-    for (auto &q : p->pfwd) b += q.tab.bytes;
-    for (auto &q : p->padj) b += q.tab.bytes;
+    for (auto &q : p->pfwd) b += q.tab.bytes + q.tab_s.bytes + q.tab3.bytes;
+    for (auto &q : p->padj) b += q.tab.bytes + q.tab_s.bytes + q.tab3.bytes;
     for (auto &h : p->dhif) b += h.desc.bytes + h.idx.bytes + h.m64.bytes + h.m128.bytes + h.h64.bytes + h.h128.bytes +
                                    h.tr.bytes + h.ts.bytes + h.tr2.bytes + h.ts2.bytes + h.tr4.bytes + h.ts4.bytes;
     b += p->root_idx.bytes + p->A0inv.bytes + p->perm.bytes;
@@ -421,6 +505,12 @@ void upload_pairs(const std::vector<Stage> &st, std::vector<DPair> &d) {
             d[s].tab_s.upload(ts.data(), ts.size() * sizeof(int32_t));
             d[s].n_wg_s = (int64_t)ts.size() / 16;
         }
+    }
+    std::vector<int32_t> t3;
+    for (size_t s = 0; s + 2 < st.size(); ++s) {
+        if (!build_triple_table(st[s], st[s + 1], st[s + 2], t3)) continue;
+        d[s].tab3.upload(t3.data(), t3.size() * sizeof(int32_t));
+        d[s].n_wg3 = (int64_t)t3.size() / STAGE_TRIPLE_TAB;
     }
 }
 
@@ -549,9 +639,15 @@ std::vector<Launch> chain_schedule(fio_plan p, bool fwd, bool dbl, int nrhs) {
     const auto *t = p->tuned(dbl, nrhs);
     const std::vector<int> *var = t ? (fwd ? &t->fwd : &t->adj) : nullptr;
     const std::vector<int> *pv = t ? (fwd ? &t->fwd_pair : &t->adj_pair) : nullptr;
+    const std::vector<int> *tv = t ? (fwd ? &t->fwd_triple : &t->adj_triple) : nullptr;
     std::vector<Launch> out;
     const int S = (int)ds.size();
     for (int s = 0; s < S;) {
+        if (tv && (size_t)s < tv->size() && (*tv)[s] > 0 && s + 2 < S && pr[s].n_wg3 > 0) {
+            out.push_back({s, 3, (*tv)[s]});
+            s += 3;
+            continue;
+        }
         int fuse = 0;
         if (s + 1 < S && pr[s].ok) {
             if (pv && (size_t)s < pv->size()) fuse = (*pv)[s];
@@ -582,6 +678,19 @@ StagePairDev pair_view(fio_plan p, bool fwd, bool dbl, int s) {
     return v;
 }
 
+StageTripleDev triple_view(fio_plan p, bool fwd, bool dbl, int s) {
+    const auto &hs = fwd ? p->host.fwd : p->adj;
+    const auto &ds = fwd ? p->dfwd : p->dadj;
+    const auto &pr = fwd ? p->pfwd : p->padj;
+    StageTripleDev v;
+    v.a = ds[s].view(dbl, hs[s]);
+    v.b = ds[s + 1].view(dbl, hs[s + 1]);
+    v.c = ds[s + 2].view(dbl, hs[s + 2]);
+    v.tab = (const int32_t *)pr[s].tab3.p;
+    v.n_wg = pr[s].n_wg3;
+    return v;
+}
+
 // Device temporaries of the chain and Gd drivers: the stage ping-pong buffers P, Q
 // (max_coef x nrhs), the GEMM path's temporary HT (N x nrhs) and the FP64 root's
 // gathered rows RI, RO (s0 x nrhs).  The plan's own workspace by default; the
@@ -605,7 +714,9 @@ void run_chain(fio_plan p, bool fwd, bool dbl, const void *in, void *out, int nr
     for (size_t j = 0; j < sched.size(); ++j) {
         void *dst = (j + 1 == sched.size()) ? out : ((j % 2 == 0) ? ws.P : ws.Q);
         const Launch &l = sched[j];
-        if (l.count == 2) {
+        if (l.count == 3) {
+            launch_stage_triple(triple_view(p, fwd, dbl, l.first), dbl, cur, dst, nrhs, st);
+        } else if (l.count == 2) {
             launch_stage_pair(pair_view(p, fwd, dbl, l.first), dbl, l.variant, cur, dst, nrhs, st);
         } else {
             StageDev v = ds[l.first].view(dbl, hs[l.first]);
@@ -1172,6 +1283,25 @@ fio_status fio_stage_pair_apply_variant(fio_plan p, fio_op op, int stage, fio_dt
     });
 }
 
+fio_status fio_stage_triple_apply(fio_plan p, fio_op op, int stage, fio_dtype dt, const void *x, void *y,
+                                  int64_t nrhs, void *stream) {
+    return guard([&] {
+        check_apply_args(p, nrhs, p ? p->host.N : 0, x, y);
+        if (op != FIO_OP_K && op != FIO_OP_KH) fail(FIO_ERR_ARG, "bad op");
+        if (dt != FIO_C64 && dt != FIO_C128) fail(FIO_ERR_ARG, "bad dtype");
+        const bool fwd = op == FIO_OP_K;
+        const bool dbl = dt == FIO_C128;
+        const auto &pr = fwd ? p->pfwd : p->padj;
+        const int S = (int)(fwd ? p->dfwd : p->dadj).size();
+        if (stage < 0 || stage + 2 >= S) fail(FIO_ERR_ARG, "stage out of range");
+        if (pr[stage].n_wg3 <= 0) fail(FIO_ERR_UNSUPPORTED, "these three stages cannot run fused");
+        if (!(fwd ? p->dfwd : p->dadj)[stage].has(dbl)) fail(FIO_ERR_UNSUPPORTED, "factor image released");
+        if (nrhs == 0) return;
+        HIPC(hipSetDevice(p->device));
+        launch_stage_triple(triple_view(p, fwd, dbl, stage), dbl, x, y, (int)nrhs, (hipStream_t)stream);
+    });
+}
+
 fio_status fio_column_id(int device, int64_t m, int64_t n, const void *A, int64_t lda, double tol_rel, int *rank,
                          int *perm, void *T, int64_t t_cap) {
     return guard([&] {
@@ -1268,8 +1398,9 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                 pout.assign(S, 0);
                 continue;
             }
-            std::vector<float> one_ms(S, 0.f), two_ms(S, 1e30f);
+            std::vector<float> one_ms(S, 0.f), two_ms(S, 1e30f), three_ms(S, 1e30f);
             std::vector<int> two_v(S, 0);
+            std::vector<int> &tout = fwd ? t.fwd_triple : t.adj_triple;
             for (int s = 0; s < S; ++s) {
                 int best = -1;
                 float best_ms = 1e30f;
@@ -1299,6 +1430,14 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                          dbl ? "c128" : "c64", fwd ? "K" : "KH", s, hs[s].r_out, hs[s].r_in, hs[s].fan,
                          best, best_ms / reps);
             }
+            // three consecutive stages in one launch, where they form stacked groups
+            for (int s = 0; s + 2 < S && nr >= 8; ++s) {
+                if (pr[s].n_wg3 <= 0) continue;
+                const StageTripleDev tv = triple_view(p, fwd, dbl, s);
+                three_ms[s] = timeit([&] { launch_stage_triple(tv, dbl, p->P.p, p->Q.p, nr, st); });
+                progress(vb, "tune %s %s triple (%d,%d,%d): %.4f ms", dbl ? "c128" : "c64", fwd ? "K" : "KH", s,
+                         s + 1, s + 2, three_ms[s] / reps);
+            }
             // fastest split of the chain into single and fused launches
             std::vector<float> best(S + 1, 0.f);
             std::vector<int> take(S, 1);
@@ -1308,10 +1447,16 @@ fio_status fio_autotune(fio_plan p, fio_dtype dt, int64_t nrhs, int reps, void *
                     best[s] = two_ms[s] + best[s + 2];
                     take[s] = 2;
                 }
+                if (s + 2 < S && three_ms[s] < 1e29f && three_ms[s] + best[s + 3] < best[s]) {
+                    best[s] = three_ms[s] + best[s + 3];
+                    take[s] = 3;
+                }
             }
             pout.assign(S, 0);
+            tout.assign(S, 0);
             for (int s = 0; s < S;) {
-                if (take[s] == 2) { pout[s] = two_v[s]; s += 2; }
+                if (take[s] == 3) { tout[s] = 1; s += 3; }
+                else if (take[s] == 2) { pout[s] = two_v[s]; s += 2; }
                 else s += 1;
             }
         }

@@ -679,6 +679,155 @@ __global__ void __launch_bounds__(256) k_stage2s_mfma(const int32_t *__restrict_
         }
 }
 
+// Three consecutive stages in one launch (the stacked form of k_stage2s_mfma carried
+// one stage further).  In the 1D butterfly three consecutive stages still fall into
+// closed groups of four blocks per stage; those of the second and third stage form
+// two sibling pairs (blocks with equal input lists), the first stage's four read four
+// different input pairs.  Wave w computes, on the column half w >> 1 (16*NT columns
+// each), stage-a blocks 2 (w & 1) and 2 (w & 1) + 1 in 16-row tiles, then sibling
+// pair w & 1 of stages b and c as one operand of MTS 16-row tiles.  The stage-a and
+// stage-b outputs of the group stay in one LDS buffer of four block slots: stage b
+// reads it, every wave passes a barrier, then stage b's results replace it.  Waves
+// whose column half lies past the batch compute nothing but pass every barrier.
+// Table: STAGE_TRIPLE_TAB int32 per workgroup (see StageTripleDev).
+template <class R, int NT, int MTS>
+__global__ void __launch_bounds__(256) k_stage3s_mfma(const int32_t *__restrict__ tab, int r_a, int r_in_a,
+                                                      int fan_a, const int32_t *__restrict__ idx_a,
+                                                      const typename MF<R>::C *__restrict__ A_a, int r_b, int fan_b,
+                                                      const typename MF<R>::C *__restrict__ A_b, int r_c, int fan_c,
+                                                      const typename MF<R>::C *__restrict__ A_c,
+                                                      const typename MF<R>::C *__restrict__ x,
+                                                      typename MF<R>::C *__restrict__ y, int nrhs, int64_t n_wg,
+                                                      int nchunks) {
+    using C = typename MF<R>::C;
+    constexpr int HC = 16 * NT, COLS = 2 * HC;
+    extern __shared__ char smem_raw[];
+    C *mid = reinterpret_cast<C *>(smem_raw);   // [4][max(r_a, r_b)][COLS]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int pr = w & 1, half = w >> 1;
+    int64_t g;
+    int chunk;
+    xcd_order(n_wg, nchunks, g, chunk);
+    if (g >= n_wg) return;  // workgroup-uniform, before the barriers
+    const int32_t *t = tab + g * STAGE_TRIPLE_TAB;
+    const int c0 = half * HC;
+    const int n0 = chunk * COLS + c0;
+    const int ncols = nrhs - n0;
+    const bool live = ncols > 0;  // wave-uniform
+    Acc<R, MTS, NT> acc;
+    int rowc[MTS];
+    // stage a: blocks 2 pr and 2 pr + 1 of the group, one after the other (their input
+    // lists differ, so they do not stack), from the gathered global input
+    if (live) {
+        const int Ka = fan_a * r_in_a;
+        const int64_t bs = (int64_t)r_in_a * nrhs;
+        int rowa[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) rowa[mt] = min(mt * 16 + li, r_a - 1);
+        for (int j = 0; j < 2; ++j) {
+            const int slot = 2 * pr + j;
+            const int ab = t[slot];
+            const int32_t *io = idx_a + (int64_t)ab * fan_a;
+            const Off4 off{io[0] * bs, fan_a > 1 ? io[1] * bs : 0, fan_a > 2 ? io[2] * bs : 0,
+                           fan_a > 3 ? io[3] * bs : 0};
+            Acc<R, 2, NT> acca;
+            mfma_rows<R, 2, NT>(acca, A_a + (int64_t)ab * r_a * Ka, r_a, r_in_a, Ka, rowa, ncols, x + n0, off,
+                                (int64_t)nrhs);
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = mt * 16 + MF<R>::drow(lk, v);
+                    if (row >= r_a) continue;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        mid[((int64_t)slot * r_a + row) * COLS + c0 + nt * 16 + li] = acca.get(mt, nt, v);
+                }
+        }
+    }
+    __syncthreads();
+    // stage b: sibling pair pr from the stage-a slots
+    if (live) {
+        const int b0 = t[4 + 2 * pr], b1 = t[5 + 2 * pr];
+        const int Kb = fan_b * r_a;
+#pragma unroll
+        for (int mt = 0; mt < MTS; ++mt) {
+            const int row = min(mt * 16 + li, 2 * r_b - 1);
+            rowc[mt] = (row < r_b) ? row : (b1 - b0) * r_b * Kb + row - r_b;
+        }
+        const Off4 off{(int64_t)t[8 + 2 * pr] * r_a * COLS, fan_b > 1 ? (int64_t)t[9 + 2 * pr] * r_a * COLS : 0, 0, 0};
+        mfma_rows<R, MTS, NT>(acc, A_b + (int64_t)b0 * r_b * Kb, r_b, r_a, Kb, rowc, ncols, mid + c0, off,
+                              (int64_t)COLS);
+    }
+    __syncthreads();  // every wave has read its stage-b inputs: the slots can be replaced
+    if (live) {
+#pragma unroll
+        for (int mt = 0; mt < MTS; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = mt * 16 + MF<R>::drow(lk, v);
+                if (row >= 2 * r_b) continue;
+                const int slot = 2 * pr + (row >= r_b ? 1 : 0);
+                const int rr = row >= r_b ? row - r_b : row;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    mid[((int64_t)slot * r_b + rr) * COLS + c0 + nt * 16 + li] = acc.get(mt, nt, v);
+            }
+    }
+    __syncthreads();
+    if (!live) return;  // after the last barrier
+    // stage c: sibling pair pr from the stage-b slots, to global memory
+    const int cb0 = t[12 + 2 * pr], cb1 = t[13 + 2 * pr];
+    const int Kc = fan_c * r_b;
+#pragma unroll
+    for (int mt = 0; mt < MTS; ++mt) {
+        const int row = min(mt * 16 + li, 2 * r_c - 1);
+        rowc[mt] = (row < r_c) ? row : (cb1 - cb0) * r_c * Kc + row - r_c;
+    }
+    const Off4 off{(int64_t)t[16 + 2 * pr] * r_b * COLS, fan_c > 1 ? (int64_t)t[17 + 2 * pr] * r_b * COLS : 0, 0, 0};
+    mfma_rows<R, MTS, NT>(acc, A_c + (int64_t)cb0 * r_c * Kc, r_c, r_b, Kc, rowc, ncols, mid + c0, off,
+                          (int64_t)COLS);
+#pragma unroll
+    for (int mt = 0; mt < MTS; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = mt * 16 + MF<R>::drow(lk, v);
+            if (row >= 2 * r_c) continue;
+            const int blk = row >= r_c ? cb1 : cb0;
+            const int rr = row >= r_c ? row - r_c : row;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int col = n0 + nt * 16 + li;
+                if (col < nrhs) y[((int64_t)blk * r_c + rr) * nrhs + col] = acc.get(mt, nt, v);
+            }
+        }
+}
+
+template <class R, int NT, int MTS>
+static void launch_triple_go(const StageTripleDev &t, const void *x, void *y, int nrhs, hipStream_t st) {
+    using C = typename MF<R>::C;
+    constexpr int COLS = 32 * NT;
+    const int nch = (nrhs + COLS - 1) / COLS;
+    const size_t lds = (size_t)4 * std::max(t.a.r_out, t.b.r_out) * COLS * sizeof(C);
+    hipLaunchKernelGGL((k_stage3s_mfma<R, NT, MTS>), dim3(xcd_grid(t.n_wg, nch)), dim3(256), lds, st, t.tab,
+                       t.a.r_out, t.a.r_in, t.a.fan, t.a.idx, (const C *)t.a.A, t.b.r_out, t.b.fan, (const C *)t.b.A,
+                       t.c.r_out, t.c.fan, (const C *)t.c.A, (const C *)x, (C *)y, nrhs, t.n_wg, nch);
+}
+
+// 64 columns per workgroup for complex64, 32 for complex128 (one LDS buffer of four
+// slots: 48 KiB at rank 24); three row tiles per sibling pair up to rank 24, four up
+// to 32.
+void launch_stage_triple(const StageTripleDev &t, bool dbl, const void *x, void *y, int nrhs, hipStream_t st) {
+    const int rmax = std::max({t.a.r_out, t.b.r_out, t.c.r_out});
+    if (!t.tab || t.n_wg <= 0 || rmax > 32 || t.a.fan > 4 || t.b.fan > 2 || t.c.fan > 2 || t.a.r_in < 1 ||
+        t.b.r_in != t.a.r_out || t.c.r_in != t.b.r_out)
+        throw std::runtime_error("stage triple cannot be fused");
+    if (dbl) { if (rmax <= 24) launch_triple_go<double, 1, 3>(t, x, y, nrhs, st); else launch_triple_go<double, 1, 4>(t, x, y, nrhs, st); }
+    else { if (rmax <= 24) launch_triple_go<float, 2, 3>(t, x, y, nrhs, st); else launch_triple_go<float, 2, 4>(t, x, y, nrhs, st); }
+    check_launch("fused stage triple");
+}
+
 template <class R, int MT, int NT, bool M3 = false>
 static void launch_mfma(const StageDev &s, const void *x, void *y, int nrhs, hipStream_t st) {
     using C = typename MF<R>::C;

@@ -56,6 +56,21 @@ bool stage_pair_stackable(int r_mid, int r_out_b);
 void launch_stage_pair(const StagePairDev &p, bool dbl, int variant, const void *x, void *y, int nrhs,
                        hipStream_t st);
 
+// Three consecutive stages a, b, c in one launch: closed groups of four blocks per
+// stage; the stage-b and stage-c blocks of a group split into two sibling pairs
+// (blocks with equal input lists).  tab: 20 int32 per workgroup: the four stage-a
+// blocks, the four stage-b blocks (sibling pairs adjacent), for each stage-b pair the
+// workgroup slots (0..3, position in the stage-a list) of its fan_b <= 2 inputs (-1
+// pads), the four stage-c blocks and the slots (positions in the stage-b list) of each
+// stage-c pair's inputs.  Ranks up to 32, fan_a <= 4.
+struct StageTripleDev {
+    StageDev a, b, c;
+    const int32_t *tab = nullptr;
+    int64_t n_wg = 0;
+};
+constexpr int STAGE_TRIPLE_TAB = 20;
+void launch_stage_triple(const StageTripleDev &t, bool dbl, const void *x, void *y, int nrhs, hipStream_t st);
+
 // Node factor table of one skeletonization step: per node
 // {nr, ns, idx_off, mat_off}; idx holds idx_r then idx_s; mat holds T (ns x nr),
 // Linv (nr x nr), M (ns x nr), column-major, one after the other.

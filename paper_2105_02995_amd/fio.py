@@ -31,7 +31,7 @@ PHASE_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.POINTER(ctypes.c_double), ct
 AMP_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                           ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
-EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_stage_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
+EXPORTS = ["fio_build", "fio_apply", "fio_inverse_dft", "fio_stage_apply", "fio_stage_pair_apply", "fio_stage_pair_apply_variant", "fio_stage_triple_apply", "fio_stage_apply_variant", "fio_chain_schedule", "fio_inverse_apply", "fio_inverse_apply_noalloc", "fio_solve_multi", "fio_multi_autotune", "fio_gd_apply", "fio_gd_apply_variant", "fio_solve",
            "fio_autotune", "fio_tune_query",
            "fio_plan_stats", "fio_plan_fingerprints", "fio_plan_trim", "fio_stage_info", "fio_save", "fio_load", "fio_destroy",
            "fio_last_error", "fio_set_trace", "fio_column_id"]
@@ -103,6 +103,7 @@ def load_library():
                                   ctypes.POINTER(ctypes.c_int), VP, VP, ctypes.c_int64]
     lib.fio_stage_pair_apply_variant.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP,
                                                  I64, VP]
+    lib.fio_stage_triple_apply.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, VP, VP, I64, VP]
     IP = ctypes.POINTER(ctypes.c_int)
     lib.fio_chain_schedule.argtypes = [P, ctypes.c_int, ctypes.c_int, I64, ctypes.c_int, IP, IP, IP, IP]
     lib.fio_autotune.argtypes = [P, ctypes.c_int, I64, ctypes.c_int, VP]
@@ -259,6 +260,11 @@ def fio_stage_pair_apply_variant(plan: Plan, op: int, stage: int, dtype: int, va
                                  stream=None):
     _check(load_library().fio_stage_pair_apply_variant(plan.handle, op, stage, dtype, variant, _ptr(x), _ptr(y),
                                                        nrhs, _stream(stream)))
+
+
+def fio_stage_triple_apply(plan: Plan, op: int, stage: int, dtype: int, x, y, nrhs: int, stream=None):
+    _check(load_library().fio_stage_triple_apply(plan.handle, op, stage, dtype, _ptr(x), _ptr(y), nrhs,
+                                                 _stream(stream)))
 
 
 def fio_column_id(A, tol_rel: float, device: int = 0):
