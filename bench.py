@@ -311,7 +311,6 @@ def calibration():
     """Measured ceilings of the device (paper_2105_02995_amd/fio_calibrate, a child
     process): streaming read rate and register-only FP32/FP64 matrix-core loop rates,
     beside the published peaks the roofline fractions use."""
-    import re
     import subprocess
     exe = os.path.join(ROOT, "paper_2105_02995_amd", "fio_calibrate")
     out = {}
@@ -324,14 +323,23 @@ def calibration():
         if r.returncode != 0:
             log("calibration %s failed: %s" % (mode, r.stderr.strip()))
             return None
-        for line in r.stdout.splitlines():
-            m = re.match(r"read: .* (\d+) workgroups, ([0-9.]+) TB/s", line)
-            if m:
-                out["read_tbs"] = max(out.get("read_tbs", 0.0), float(m.group(2)))
-            m = re.match(r"mfma (f32|f64) 16x16x4: ([0-9.]+) TFLOP/s", line)
-            if m:
-                out["mfma_loop_%s_tflops" % m.group(1)] = float(m.group(2))
+        parse_calibration(r.stdout.splitlines(), out)
     log("calibration: %s" % out)
+    return out
+
+
+def parse_calibration(lines, out=None):
+    """The figures of fio_calibrate's output lines: the best streaming-read rate over
+    its launch shapes (TB/s) and the matrix-core loop rates (TFLOP/s)."""
+    import re
+    out = {} if out is None else out
+    for line in lines:
+        m = re.match(r"read: .* (\d+) workgroups, ([0-9.]+) TB/s", line)
+        if m:
+            out["read_tbs"] = max(out.get("read_tbs", 0.0), float(m.group(2)))
+        m = re.match(r"mfma (f32|f64) 16x16x4: ([0-9.]+) TFLOP/s", line)
+        if m:
+            out["mfma_loop_%s_tflops" % m.group(1)] = float(m.group(2))
     return out
 
 
