@@ -385,10 +385,11 @@ class GpuExecutor:
         X = torch.zeros_like(U)
         self._solve(key, U, X, top, torch.cuda.current_stream())  # sizes the plan's workspace
         torch.cuda.synchronize()
-        if self.autotune:
+        if self.autotune and self.use_graphs:
             # kernel choices per batch width (the library looks them up by exact width):
-            # the widths batches run at, up to the key's cap, for the complex64 applies and
-            # the complex128 residual; before any graph captures the choices
+            # with graphs batches run at the bucket widths, up to the key's cap; tuned for
+            # the complex64 applies and the complex128 residual before any graph captures
+            # the choices (eager batches run at their own widths, so they are not tuned)
             F = self.F
             cap = min(top, self.batch_cap(key))
             st = torch.cuda.current_stream()
