@@ -1209,8 +1209,12 @@ template <class T, bool UP, bool STAGED>
 __global__ void __launch_bounds__(256) k_hif(const int64_t *__restrict__ desc,
                                              const int32_t *__restrict__ idx,
                                              const T *__restrict__ mat, T *__restrict__ x,
-                                             int nrhs, int bchunk) {
-    hif_node<T, UP, STAGED>(desc, idx, mat, x, nrhs, bchunk, blockIdx.x, blockIdx.y);
+                                             int nrhs, int bchunk, int64_t n_nodes, int nch) {
+    int64_t v;
+    int c;
+    xcd_order(n_nodes, nch, v, c);   // the chunks of one node on one XCD, one after the other
+    if (v >= n_nodes) return;
+    hif_node<T, UP, STAGED>(desc, idx, mat, x, nrhs, bchunk, v, c);
 }
 
 // LDS one workgroup may use: the device's opt-in limit (160 KiB per CU on
@@ -1235,8 +1239,8 @@ static void hif_go(const HifStepDev &h, size_t lds, void *x, int nrhs, int bchun
                                   hipFuncAttributeMaxDynamicSharedMemorySize, hif_lds_budget());
     });
     const unsigned nch = (unsigned)((nrhs + bchunk - 1) / bchunk);
-    hipLaunchKernelGGL((k_hif<T, UP, ST>), dim3((unsigned)h.n_nodes, nch), dim3(256), lds, st, h.desc,
-                       h.idx, (const T *)h.mat, (T *)x, nrhs, bchunk);
+    hipLaunchKernelGGL((k_hif<T, UP, ST>), dim3(xcd_grid(h.n_nodes, (int)nch)), dim3(256), lds, st, h.desc,
+                       h.idx, (const T *)h.mat, (T *)x, nrhs, bchunk, h.n_nodes, (int)nch);
 }
 
 void launch_hif_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st) {
@@ -2001,8 +2005,12 @@ __global__ void __launch_bounds__(256) k_hif_fused(const int64_t *__restrict__ d
                                                    const typename MF<R>::C *__restrict__ mat,
                                                    const typename MF<R>::C *__restrict__ matH,
                                                    typename MF<R>::C *__restrict__ x, int nrhs, int rows_r,
-                                                   int rows_s) {
-    hif_fused_node<R, UP, NTW>(desc, idx, mat, matH, x, nrhs, rows_r, rows_s, blockIdx.x, blockIdx.y);
+                                                   int rows_s, int64_t n_nodes, int nch) {
+    int64_t v;
+    int c;
+    xcd_order(n_nodes, nch, v, c);   // the column chunks of one node share its factors in one L2
+    if (v >= n_nodes) return;
+    hif_fused_node<R, UP, NTW>(desc, idx, mat, matH, x, nrhs, rows_r, rows_s, v, c);
 }
 
 bool hif_fused_fits(const HifStepDev &h) { return h.max_nr <= 64 && h.max_ns <= 64; }
@@ -2018,9 +2026,9 @@ static void hif_fused_go(const HifStepDev &h, int rr, int rs, void *x, int nrhs,
                                   hif_lds_budget());
     });
     if ((int64_t)lds > hif_lds_budget()) throw std::runtime_error("fused skeletonization step exceeds LDS");
-    const dim3 g((unsigned)h.n_nodes, (unsigned)((nrhs + CW - 1) / CW));
-    hipLaunchKernelGGL((k_hif_fused<R, UP, NTW>), g, dim3(256), lds, st, h.desc, h.idx, (const C *)h.mat,
-                       (const C *)h.matH, (C *)x, nrhs, rr, rs);
+    const int nch = (nrhs + CW - 1) / CW;
+    hipLaunchKernelGGL((k_hif_fused<R, UP, NTW>), dim3(xcd_grid(h.n_nodes, nch)), dim3(256), lds, st, h.desc,
+                       h.idx, (const C *)h.mat, (const C *)h.matH, (C *)x, nrhs, rr, rs, h.n_nodes, nch);
 }
 
 void launch_hif_fused_step(const HifStepDev &h, bool dbl, bool up, void *x, int nrhs, hipStream_t st, int cols) {
