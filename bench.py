@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC = {
     # 2D Example 3, n=256, 256 RHS (profiles/k_stage_mfma_f32_3m_2d_n256_traffic.md)
     "k_stage_mfma<float, 2, 2, 3M>": {
-        "bytes": 4.1744e9,
-        "kernels_sha256": "c0eee713498bdf6fc4c64454d3fba78a970a1e6f8b08d08808b2327a3c56efb7",
+        "bytes": 4.1708e9,
+        "kernels_sha256": "0dbfb62eb9d369702b13a55035612be69e056af0e78babd229ec27fcf0557140",
         "bf_nnz": 1138753536,
     },
 }
@@ -51,8 +51,8 @@ TRAFFIC = {
 MFMA_COUNTERS = {
     "k_stage_mfma<float, 2, 2, 3M>": {
         "executed_flop": 3.4403e11,
-        "busy": 0.6284,
-        "kernels_sha256": "c0eee713498bdf6fc4c64454d3fba78a970a1e6f8b08d08808b2327a3c56efb7",
+        "busy": 0.6285,
+        "kernels_sha256": "0dbfb62eb9d369702b13a55035612be69e056af0e78babd229ec27fcf0557140",
         "bf_nnz": 1138753536,
     },
 }
@@ -63,7 +63,7 @@ MFMA_COUNTERS = {
 PLAIN_TRAFFIC = {
     "plain_fp64": {
         "bytes": 2.1873e10,
-        "kernels_sha256": "c0eee713498bdf6fc4c64454d3fba78a970a1e6f8b08d08808b2327a3c56efb7",
+        "kernels_sha256": "0dbfb62eb9d369702b13a55035612be69e056af0e78babd229ec27fcf0557140",
         "bf_nnz": 1138753536,
     },
 }
